@@ -1,0 +1,472 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test names the passage or the mathematical fact it checks.  None of them
+re-types an oracle formula: they compare oracle outputs with printed values,
+closed forms, invariants, symmetry, convergence order or an independent
+brute-force evaluation.
+"""
+import dataclasses
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_10114_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_cfg(nx, ny, nz, degree=3, seed=7, hmax=2000.0):
+    return dataclasses.replace(synth.CONFIGS["c1"], nx=nx, ny=ny, nz=nz, degree=degree, seed=seed, hmax=hmax)
+
+
+def rest_state(o, ps_val=1e5):
+    st = o.zeros()
+    st["ps"][:] = ps_val
+    return st
+
+
+# ----------------------------------------------------------------------------- geometry (P1, P2)
+def test_table2_zonal_spacing():
+    """Sec. III-B Table 2: zonal spacing at the equator and the rows nearest the poles."""
+    g = json.load(open(os.path.join(GOLD, "table2_zonal_spacing.json")))
+    for row in g["rows"]:
+        res = row["res_deg"]
+        nx, ny = int(round(360 / res)), int(round(180 / res))
+        o = oracle.Oracle(nx, ny, 2)
+        d, dv = o.zonal_spacing()
+        got = [d[ny // 2] / 1e3, d[1] / 1e3, dv[0] / 1e3]
+        want = [row["dx_equator"], row["dx_pole_u"], row["dx_pole_v"]]
+        for gv, wv, dig in zip(got, want, row["digits"]):
+            if dig < 0:   # printed entry beyond a sin(theta) dlam's digit (see note)
+                assert abs(gv - wv) <= 0.01, (res, gv, wv)
+            else:
+                assert round(gv, dig) == pytest.approx(wv, abs=1e-9), (res, gv, wv)
+
+
+def test_eq8_leap_counts():
+    """Sec. III-B eq. 8: 82/41 at 0.5 deg and 173/87 at 0.25 deg on the two rows nearest the pole."""
+    g = json.load(open(os.path.join(GOLD, "eq8_leap_counts.json")))
+    for c in g["cases"]:
+        o = oracle.Oracle(c["nx"], c["ny"], 2)
+        m, mv, r, rv = o.leap_table()
+        assert math.ceil(r[1]) == c["row1"]
+        assert math.ceil(r[2]) == c["row2"]
+        assert math.ceil(r[c["ny"] - 1]) == c["row1"]        # symmetric south
+        assert m[1] % 2 == 1 and m[1] >= c["row1"]             # span made odd (Sec. III-B)
+
+
+def test_leap_table_properties():
+    """eq. 8: spans are odd, 1 equatorward of 45 deg (the reference spacing), and M*dx >= dx45."""
+    for nx, ny in [(128, 64), (256, 128), (720, 360), (1440, 720)]:
+        o = oracle.Oracle(nx, ny, 2)
+        m, mv, r, rv = o.leap_table()
+        d, dv = o.zonal_spacing()
+        dx45 = o.constants()["a"] * math.cos(math.pi / 4) * 2 * math.pi / nx
+        th = np.arange(ny + 1) * math.pi / ny
+        for j in range(1, ny):
+            assert m[j] % 2 == 1
+            if abs(math.pi / 2 - th[j]) < math.pi / 4 - 1e-12:
+                assert m[j] == 1
+            assert m[j] * d[j] >= dx45 * (1 - 1e-6) or m[j] == 1
+        assert np.all(mv % 2 == 1)
+        assert np.array_equal(m[1:ny], m[1:ny][::-1]) and np.array_equal(mv, mv[::-1])
+    # the largest spans at the four grids
+    want = {(128, 64): (15, 29), (256, 128): (29, 59), (720, 360): (83, 163), (1440, 720): (163, 325)}
+    for (nx, ny), (mu, mvv) in want.items():
+        m, mv, _, _ = oracle.Oracle(nx, ny, 2).leap_table()
+        assert (m.max(), mv.max()) == (mu, mvv)
+
+
+def test_substep_rule():
+    """3M adaptation calls per step (Sec. III-D): the sub-step count follows the CFL bound."""
+    for key, want in [("c1", 2), ("c2", 2), ("c3", 4), ("c4", 4)]:
+        c = synth.CONFIGS[key]
+        assert oracle.Oracle(c.nx, c.ny, 2).substeps(c.dt) == want
+
+
+# ----------------------------------------------------------------------------- operator symbols (P4)
+def _row_theta(ny, j):
+    return j * math.pi / ny
+
+
+@pytest.mark.parametrize("nx,ny,j,m", [(64, 32, 2, 3), (64, 32, 5, 2), (128, 64, 4, 7), (96, 48, 16, 4)])
+def test_delta_minus_symbol(nx, ny, j, m):
+    """eq. 7 / Table 6 (x,x-1)->(x+N-1,x-N): leaped divergence of a zonal wave of U, closed form."""
+    o = oracle.Oracle(nx, ny, 2)
+    M = o.leap_table()[0][j]
+    c = o.constants()
+    st = rest_state(o)
+    lam_u = (np.arange(nx) + 0.5) * 2 * math.pi / nx
+    st["U"][j, :, :] = np.cos(m * lam_u)
+    D = o.column_diag(st)["D"][j, 0]
+    lam = np.arange(nx) * 2 * math.pi / nx
+    dx = M * c["a"] * math.sin(_row_theta(ny, j)) * 2 * math.pi / nx
+    want = -2.0 * math.sin(m * M * math.pi / nx) * np.sin(m * lam) / dx
+    np.testing.assert_allclose(D, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("nx,ny,j,m", [(64, 32, 2, 3), (128, 64, 4, 7), (96, 48, 16, 4)])
+def test_delta_plus_symbol(nx, ny, j, m):
+    """Table 6 (x+1,x)->(x+N,x-N+1): the linearised pressure-gradient of a zonal p_s wave at rest."""
+    o = oracle.Oracle(nx, ny, 2)
+    M = o.leap_table()[0][j]
+    c = o.constants()
+    st = rest_state(o)
+    d = o.zeros()
+    lam = np.arange(nx) * 2 * math.pi / nx
+    d["ps"][j, :] = np.cos(m * lam)
+    t = o.tl_tendency(st, d, "A")["U"][j, 0]
+    dx = M * c["a"] * math.sin(_row_theta(ny, j)) * 2 * math.pi / nx
+    lam_u = lam + math.pi / nx
+    want = -c["rd"] * c["t0"] / c["p0"] * (-2.0 * np.sin(m * lam_u) * math.sin(m * M * math.pi / nx)) / dx
+    np.testing.assert_allclose(t, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("nx,ny,j,m", [(64, 32, 2, 3), (128, 64, 4, 7), (96, 48, 30, 5)])
+def test_delta_zero_symbol(nx, ny, j, m):
+    """Table 6 (x+1,x-1)->(x+2N-1,x-2N+1): advection of a zonal wave of Phi by a uniform u."""
+    o = oracle.Oracle(nx, ny, 2)
+    M = o.leap_table()[0][j]
+    c = o.constants()
+    st = rest_state(o)
+    u0 = 10.0
+    st["U"][1:ny] = u0
+    lam = np.arange(nx) * 2 * math.pi / nx
+    st["Phi"][j, :, :] = np.cos(m * lam)
+    t = o.tendency(st, "L")["Phi"][j, 0]
+    dx = M * c["a"] * math.sin(_row_theta(ny, j)) * 2 * math.pi / nx
+    want = u0 * np.sin(m * lam) * math.sin(m * M * 2 * math.pi / nx) / dx
+    np.testing.assert_allclose(t, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_leap_convergence_order():
+    """At a fixed colatitude the span M is fixed, so the leaped zonal derivative converges at order 2."""
+    errs = []
+    for nx in (128, 256, 512):
+        ny = nx // 2
+        j = ny // 16                      # colatitude 11.25 deg on every grid
+        o = oracle.Oracle(nx, ny, 2)
+        c = o.constants()
+        st = rest_state(o)
+        u0 = 10.0
+        st["U"][1:ny] = u0
+        lam = np.arange(nx) * 2 * math.pi / nx
+        m = 3
+        st["Phi"][j, :, :] = np.cos(m * lam)
+        t = o.tendency(st, "L")["Phi"][j, 0]
+        exact = u0 * m * np.sin(m * lam) / (c["a"] * math.sin(_row_theta(ny, j)))
+        errs.append(np.abs(t - exact).max())
+        assert o.leap_table()[0][j] > 1
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.9 < r < 2.1 for r in rates), rates
+
+
+def test_meridional_divergence_convergence():
+    """Divergence of a zonally uniform meridional flow converges at order 2 to (1/(a sin)) d(v sin)/dtheta."""
+    errs = []
+    for ny in (32, 64, 128):
+        nx = 2 * ny
+        o = oracle.Oracle(nx, ny, 1)
+        a = o.constants()["a"]
+        st = rest_state(o)
+        thv = (np.arange(ny) + 0.5) * math.pi / ny
+        st["V"][:, 0, :] = np.sin(2 * thv)[:, None]
+        D = o.column_diag(st)["D"][:, 0, 0]
+        th = np.arange(ny + 1) * math.pi / ny
+        j = np.arange(1, ny)
+        exact = (2 * np.cos(2 * th[j]) * np.sin(th[j]) + np.sin(2 * th[j]) * np.cos(th[j])) / (a * np.sin(th[j]))
+        errs.append(np.abs(D[j] - exact).max() / np.abs(exact).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(r > 1.8 for r in rates), rates
+
+
+# ----------------------------------------------------------------------------- column diagnostics
+def test_hydrostatic_closed_form():
+    """Isothermal deviation: phi'(sigma_k) = -R T' ln(sigma_k) exactly (integral of R T' dln sigma)."""
+    o = oracle.Oracle(16, 8, 6)
+    st = rest_state(o)
+    c = o.constants()
+    P = np.sqrt(st["ps"] / c["p0"])
+    Tp = 2.5
+    st["Phi"][:] = P[:, None, :] * c["rd"] * Tp / c["b"]
+    phi = o.column_diag(st)["phi"]
+    sig = (np.arange(6) + 0.5) / 6
+    want = -c["rd"] * Tp * np.log(sig)
+    np.testing.assert_allclose(phi[3, :, 5], want, rtol=1e-14)
+
+
+def test_sigma_dot_zero_for_uniform_divergence():
+    """Alg. 1/2: if every layer has the same divergence, the surface tendency absorbs it and sigma-dot = 0."""
+    o = oracle.Oracle(16, 8, 5)
+    D = np.full(5, 3.7e-6)
+    S, psd = o.scan_alg1(D)
+    np.testing.assert_allclose(psd, 0.0, atol=1e-20)
+    assert S[-1] == pytest.approx(3.7e-6, rel=1e-15)
+
+
+@pytest.mark.parametrize("nblocks", [1, 2, 3, 4, 7, 30])
+def test_alg1_equals_alg2(nblocks):
+    """Alg. 1 (gathered column) and Alg. 2 (local scans + Allreduce + Exscan) give the same sigma-dot."""
+    o = oracle.Oracle(16, 8, 30)
+    rng = np.random.default_rng(3)
+    D = rng.standard_normal(30) * 1e-5
+    S1, p1 = o.scan_alg1(D)
+    S2, p2 = o.scan_alg2(D, nblocks)
+    np.testing.assert_allclose(S2, S1, rtol=0, atol=1e-19)
+    np.testing.assert_allclose(p2, p1, rtol=0, atol=1e-19)
+    assert p1[0] == 0.0 and abs(p1[-1]) < 1e-20
+
+
+# ----------------------------------------------------------------------------- invariants (P6-P11)
+def test_rest_state_bitwise_zero():
+    """eq. 1 at rest: U = V = Phi = 0, p_s = p0, flat terrain give exactly zero tendencies."""
+    o = oracle.Oracle(32, 16, 4)
+    st = rest_state(o)
+    for which in "AL":
+        t = o.tendency(st, which)
+        for k in t:
+            assert np.all(t[k] == 0.0), (which, k)
+
+
+def test_rest_state_with_terrain():
+    """Terrain in hydrostatic balance (p_s = p0 exp(-phis/RT0)) at rest: tendencies vanish to rounding."""
+    cfg = small_cfg(32, 16, 4)
+    s = synth.make_state(cfg)
+    o = oracle.Oracle(32, 16, 4, phis=s["phis"])
+    c = o.constants()
+    st = rest_state(o)
+    st["ps"] = c["p0"] * np.exp(-s["phis"] / (c["rd"] * c["t0"]))
+    t = o.tendency(st, "A")
+    # scale: the terrain pressure-gradient term that cancels
+    scale = c["rd"] * c["t0"] * np.abs(np.diff(s["phis"][5])).max() / (c["rd"] * c["t0"]) / 1e5
+    assert np.abs(t["U"]).max() < 1e-11 * max(scale, 1.0)
+    assert np.abs(t["V"]).max() < 1e-11 * max(scale, 1.0)
+    assert np.abs(t["Phi"]).max() < 1e-20 and np.abs(t["ps"]).max() < 1e-20
+
+
+def test_mass_conservation_c1():
+    """Telescoping flux-form continuity + linear RK: global mass drift <= 1e-13 over C1's 20 steps."""
+    cfg = synth.CONFIGS["c1"]
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    m0, _ = o.diagnostics(st)
+    s = o.step(st, cfg.steps, cfg.dt)
+    m1, _ = o.diagnostics(s)
+    assert abs(m1 - m0) / m0 <= 1e-13
+    for k in s:
+        assert np.all(np.isfinite(s[k]))
+
+
+def test_mass_tendency_sums_to_zero():
+    """The area-weighted p_s tendency (incl. the polar caps) telescopes to zero."""
+    cfg = small_cfg(64, 32, 5, degree=6)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(64, 32, 5, phis=st["phis"])
+    t = o.tendency(st, "A")
+    c = o.constants()
+    th = np.arange(33) * math.pi / 32
+    w = c["a"] ** 2 * np.sin(th) * (math.pi / 32) * (2 * math.pi / 64)
+    tot = (w[1:32, None] * t["ps"][1:32]).sum() + c["acap"] * (t["ps"][0, 0] + t["ps"][32, 0])
+    scale = (w[1:32, None] * np.abs(t["ps"][1:32])).sum()
+    assert abs(tot) < 1e-14 * scale
+
+
+def test_advection_skew_symmetry():
+    """IAP skew form: sum w dsig F L(F) = 0 for F = U, V, Phi and any winds (energy property)."""
+    cfg = small_cfg(64, 32, 6, degree=8)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(64, 32, 6, phis=st["phis"])
+    c = o.constants()
+    t = o.tendency(st, "L")
+    ny = 32
+    th = np.arange(ny + 1) * math.pi / ny
+    thv = (np.arange(ny) + 0.5) * math.pi / ny
+    w = c["a"] ** 2 * np.sin(th) * (math.pi / ny) * (2 * math.pi / 64)
+    wv = c["a"] ** 2 * np.sin(thv) * (math.pi / ny) * (2 * math.pi / 64)
+    ds = 1.0 / 6
+    for key, wt, rows in [("U", w, slice(1, ny)), ("V", wv, slice(0, ny)), ("Phi", w, slice(1, ny))]:
+        prod = wt[rows, None, None] * ds * st[key][rows] * t[key][rows]
+        tot = prod.sum()
+        scale = np.abs(prod).sum()
+        if key == "Phi":
+            for p in (0, ny):
+                tot += c["acap"] * ds * (st["Phi"][p, :, 0] * t["Phi"][p, :, 0]).sum()
+        assert abs(tot) < 1e-13 * scale, (key, tot, scale)
+
+
+def test_periodicity():
+    """Rolling every input by s columns rolls every tendency by s columns."""
+    cfg = small_cfg(48, 24, 4, degree=6)
+    st = synth.make_state(cfg)
+    s = 7
+    rolled = {k: np.roll(v, s, axis=-1) for k, v in st.items()}
+    o1 = oracle.Oracle(48, 24, 4, phis=st["phis"])
+    o2 = oracle.Oracle(48, 24, 4, phis=rolled["phis"])
+    for which in "AL":
+        t1 = o1.tendency(st, which)
+        t2 = o2.tendency(rolled, which)
+        for k in t1:
+            want = np.roll(t1[k], s, axis=-1)
+            np.testing.assert_allclose(t2[k], want, rtol=0, atol=1e-12 * np.abs(want).max())
+            if k in ("U", "V"):   # rows away from the poles see no pole mean: bitwise
+                assert np.array_equal(t2[k][3:-3], want[3:-3])
+
+
+def test_equatorial_mirror():
+    """j -> ny - j with V -> -V (southward positive) mirrors the tendencies (f flips with cos theta)."""
+    cfg = small_cfg(32, 16, 4, degree=6)
+    st = synth.make_state(cfg)
+    mir = {"U": st["U"][::-1].copy(), "V": -st["V"][::-1].copy(), "Phi": st["Phi"][::-1].copy(),
+           "ps": st["ps"][::-1].copy(), "phis": st["phis"][::-1].copy()}
+    o1 = oracle.Oracle(32, 16, 4, phis=st["phis"])
+    o2 = oracle.Oracle(32, 16, 4, phis=mir["phis"])
+    for which in "AL":
+        t1 = o1.tendency(st, which)
+        t2 = o2.tendency(mir, which)
+        for k, sgn in [("U", 1), ("V", -1), ("Phi", 1), ("ps", 1)]:
+            want = sgn * t1[k][::-1]
+            np.testing.assert_allclose(t2[k], want, rtol=0, atol=1e-12 * max(np.abs(want).max(), 1e-30))
+
+
+def test_solid_body_balance_order2():
+    """Solid-body wind u = u0 sin(theta) with the gradient-wind p_s: zonal terms vanish exactly and the
+    meridional imbalance of the V tendency is O(dtheta^2)."""
+    res = []
+    for ny in (32, 64, 128):
+        nx = 2 * ny
+        o = oracle.Oracle(nx, ny, 2)
+        c = o.constants()
+        u0 = 20.0
+        th = np.arange(ny + 1) * math.pi / ny
+        lb = (c["a"] * c["omega"] * u0 + 0.5 * u0 ** 2) * np.sin(th) ** 2 / (c["rd"] * c["t0"])
+        st = o.zeros()
+        st["ps"][:] = c["p0"] * np.exp(lb)[:, None]
+        P = np.sqrt(st["ps"] / c["p0"])
+        PU = 0.5 * (P + np.roll(P, -1, axis=1))
+        st["U"][1:ny] = (PU[1:ny] * u0 * np.sin(th[1:ny])[:, None])[:, None, :]
+        t = o.tendency(st, "A")
+        assert np.all(t["U"] == 0.0)
+        tl = o.tendency(st, "L")
+        assert np.abs(tl["U"]).max() == 0.0 and np.abs(tl["V"]).max() == 0.0
+        scale = 2 * c["omega"] * u0
+        res.append(np.abs(t["V"]).max() / scale)
+    rates = [math.log2(res[i] / res[i + 1]) for i in range(2)]
+    assert all(r > 1.8 for r in rates), (res, rates)
+
+
+# ----------------------------------------------------------------------------- adjoint (P14)
+def _tiny():
+    cfg = small_cfg(16, 8, 3)
+    st = synth.make_state(cfg)
+    return cfg, st, oracle.Oracle(16, 8, 3, phis=st["phis"])
+
+
+@pytest.mark.parametrize("which", ["A", "L"])
+def test_adjoint_dot_tendency(which):
+    """<J x, y> = <x, J^T y>: hand-written adjoint against the complex-step tangent-linear."""
+    cfg, st, o = _tiny()
+    x = synth.random_like(st, 11)
+    y = synth.random_like(st, 12)
+    a = oracle.dot(o.tl_tendency(st, x, which), y)
+    b = oracle.dot(x, o.adj_tendency(st, y, which))
+    assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_adjoint_dot_step_c1_grid():
+    """Dot test of the whole step (3M adaptation + 3 advection stages) on the C1 grid."""
+    cfg = synth.CONFIGS["c1"]
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    x = synth.random_like(st, 1031)
+    y = synth.random_like(st, 1032)
+    a = oracle.dot(o.tl_step(st, x, cfg.dt), y)
+    b = oracle.dot(x, o.adj_step(st, y, cfg.dt))
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_adjoint_full_jacobian_tiny():
+    """Brute force on a tiny grid: every TL column of the tendency Jacobian equals the adjoint row."""
+    cfg = small_cfg(16, 8, 2)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(16, 8, 2, phis=st["phis"])
+    keys = ["U", "V", "Phi", "ps"]
+    shapes = {k: st[k].shape for k in keys}
+    sizes = [int(np.prod(shapes[k])) for k in keys]
+    n = sum(sizes)
+    rng = np.random.default_rng(5)
+    cols = rng.choice(n, 60, replace=False)
+
+    def unit(idx):
+        d = {k: np.zeros(shapes[k]) for k in keys}
+        off = 0
+        for k, sz in zip(keys, sizes):
+            if idx < off + sz:
+                d[k].reshape(-1)[idx - off] = 1.0
+                return d
+            off += sz
+
+    def flat(d):
+        return np.concatenate([d[k].reshape(-1) for k in keys])
+
+    for which in "AL":
+        for c in cols:
+            col = flat(o.tl_tendency(st, unit(c), which))
+            for r in rng.choice(n, 8, replace=False):
+                row = flat(o.adj_tendency(st, unit(r), which))
+                assert abs(col[r] - row[c]) <= 1e-12 * max(abs(col[r]), 1e-300) + 1e-300
+
+
+def test_adjoint_central_fd():
+    """Central finite differences of the step (eps = 1e-6 relative) against J^T at sampled points."""
+    cfg = small_cfg(32, 16, 4, degree=5)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(32, 16, 4, phis=st["phis"])
+    dt = 600.0
+    rng = np.random.default_rng(1033)
+    for trial in range(4):
+        key = ["U", "V", "Phi", "ps"][trial]
+        shp = st[key].shape
+        idx = tuple(rng.integers(1 if (key == "U" and d == 0) else 0, s - (1 if (key == "U" and d == 0) else 0))
+                    for d, s in enumerate(shp))
+        if key == "ps" and idx[0] in (0, shp[0] - 1):
+            idx = (idx[0] + (1 if idx[0] == 0 else -1),) + idx[1:]
+        okey = ["Phi", "U", "ps", "V"][trial]
+        oshp = st[okey].shape
+        oidx = tuple(rng.integers(1, s - 1) if d == 0 else rng.integers(0, s) for d, s in enumerate(oshp))
+        y = {k: np.zeros_like(v) for k, v in st.items() if k != "phis"}
+        y[okey][oidx] = 1.0
+        g = o.adj_step(st, y, dt)[key][idx]
+        rms = np.sqrt(np.mean(st[key] ** 2))
+        eps = 1e-6 * rms
+        sp = {k: v.copy() for k, v in st.items() if k != "phis"}
+        sm = {k: v.copy() for k, v in st.items() if k != "phis"}
+        sp[key][idx] += eps
+        sm[key][idx] -= eps
+        fd = (o.step(sp, 1, dt)[okey][oidx] - o.step(sm, 1, dt)[okey][oidx]) / (2 * eps)
+        assert abs(fd - g) <= 1e-6 * max(abs(g), abs(fd)) + 1e-10 * abs(o.adj_step(st, y, dt)[key]).max(), \
+            (key, okey, fd, g)
+
+
+# ----------------------------------------------------------------------------- brute force (P15)
+@pytest.mark.parametrize("nx,ny,nz", [(16, 8, 3), (32, 16, 4)])
+@pytest.mark.parametrize("which", ["A", "L"])
+def test_numpy_brute_force(nx, ny, nz, which):
+    """An independent vectorised NumPy evaluation of both tendencies equals the C++ oracle."""
+    from tests import brute_numpy as bn
+    cfg = small_cfg(nx, ny, nz, degree=4, seed=nx + nz)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(nx, ny, nz, phis=st["phis"])
+    m, mv, _, _ = o.leap_table()
+    g = bn.geometry(nx, ny, nz)
+    assert np.array_equal(g["M"][1:ny], m[1:ny]) and np.array_equal(g["Mv"], mv)
+    assert m.max() > 1 and mv.max() > 1            # the leap is active on this grid
+    t = o.tendency(st, which)
+    f = bn.tend_A if which == "A" else bn.tend_L
+    b = f(g, st, st["phis"])
+    for k in ("U", "V", "Phi", "ps"):
+        scale = max(np.abs(t[k]).max(), 1e-300)
+        np.testing.assert_allclose(b[k], t[k], rtol=0, atol=1e-12 * scale, err_msg=f"{which} {k}")
