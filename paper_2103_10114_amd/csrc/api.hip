@@ -1,0 +1,600 @@
+// C ABI of libdycore: handle life cycle, step sequencing, diagnostics, batches.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dycore.h"
+#include "dycore_internal.h"
+
+using namespace dyc;
+
+namespace {
+
+constexpr int kPoleSlots = 8;
+
+struct DeviceBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct dycore_s {
+  int nx, ny, nz, prec, msub, block;
+  unsigned flags;
+  double dt;
+  int device;
+  GeoDev g;
+  std::vector<int> M, Mv;
+  size_t nU, nV, nF, nP;        // element counts of each field
+  size_t elem;                  // 4 or 8
+  size_t state_bytes;           // bytes of one packed state (U|V|F|P, 256-aligned parts)
+  void* geo = nullptr;          // tables
+  void* scratch = nullptr;      // forward scratch: y1, y2
+  double* pole = nullptr;       // kPoleSlots x 2 x (nz+1)
+  double* diag = nullptr;       // 3*(ny+1) partials
+  unsigned long long* count = nullptr;
+  void* adj = nullptr;          // adjoint workspace
+  size_t adj_bytes = 0;
+  size_t bytes = 0;
+};
+
+size_t dyc_adjoint_workspace_bytes(const dycore_s* h);
+
+struct dycore_batch_s {
+  int n, prec, block, grid, max_nx, nstage_max;
+  std::vector<dycore_t> hs;
+  void* d_args = nullptr;       // nstage_max x n StageArgs
+  int2* d_items = nullptr;
+  int nitems = 0;
+  void* d_prep = nullptr;       // per member prep descriptors
+  std::vector<void*> U, V, F, P;
+};
+
+namespace {
+
+template <typename T>
+struct Packed {
+  T* U; T* V; T* F; T* P;
+};
+
+template <typename T>
+Packed<T> unpack(const dycore_s* h, void* base) {
+  char* c = static_cast<char*>(base);
+  Packed<T> s;
+  s.U = reinterpret_cast<T*>(c);
+  c += align256(h->nU * sizeof(T));
+  s.V = reinterpret_cast<T*>(c);
+  c += align256(h->nV * sizeof(T));
+  s.F = reinterpret_cast<T*>(c);
+  c += align256(h->nF * sizeof(T));
+  s.P = reinterpret_cast<T*>(c);
+  return s;
+}
+
+double* pole_slot(const dycore_s* h, int s) { return h->pole + (size_t)s * 2 * (h->nz + 1); }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int hip_status(hipError_t e) { return e == hipSuccess ? DYCORE_OK : DYCORE_EHIP; }
+
+int leap_span(double sin_theta, double dlam, int nx) {
+  // eq. 8 with res = dlam, cos(90 deg - theta) = sin(theta); ceiling, then odd (Sec. III-B), then < nx/2
+  const double r = std::asin(std::cos(M_PI / 4.0) * std::sin(dlam)) / std::asin(sin_theta * std::sin(dlam));
+  int m = (int)std::ceil(r - 1e-9);
+  if (m < 1) m = 1;
+  if ((m & 1) == 0) ++m;
+  int cap = (nx - 1) / 2;
+  if ((cap & 1) == 0) --cap;
+  if (cap < 1) cap = 1;
+  return std::min(m, cap);
+}
+
+int default_block(int nx, int prec) {
+  (void)prec;
+  // one column per thread up to 256 threads, then several columns per thread
+  if (nx <= 64) return 64;
+  if (nx <= 128) return 128;
+  if (nx <= 256) return 256;
+  return 256;
+}
+
+template <typename T>
+StageArgs<T> make_args(const dycore_s* h, int process, double ch, const T* inU, const T* inV, const T* inF,
+                       const T* inP, const T* bU, const T* bV, const T* bF, const T* bP, T* oU, T* oV, T* oF,
+                       T* oP, const double* pin, const double* pbase, double* pout) {
+  StageArgs<T> a;
+  a.g = h->g;
+  a.inU = inU; a.inV = inV; a.inF = inF; a.inP = inP;
+  a.bU = bU; a.bV = bV; a.bF = bF; a.bP = bP;
+  a.oU = oU; a.oV = oV; a.oF = oF; a.oP = oP;
+  a.pin = pin; a.pbase = pbase; a.pout = pout;
+  a.ch = ch;
+  a.process = process;
+  a.pad = 0;
+  return a;
+}
+
+// Pole-value slots of one outer step.  Slot 0 holds the pole values of the
+// step's start state and is written only by the last stage of the step, so the
+// next step (or the next replay of a batch) finds its start values there.  RK
+// step rk has base slot b; its stages write s1 (y1), s2 (y2) and then the next
+// base, which reuses s1.
+struct Slots { int pin, pbase, pout; };
+
+Slots stage_slots(int rk, int nrk, int r) {
+  int b = 0;
+  for (int q = 0; q < rk; ++q) b = (b == 0) ? 1 : (b % 3) + 1;
+  const int s1 = (b == 0) ? 1 : (b % 3) + 1;
+  const int s2 = (s1 % 3) + 1;
+  if (r == 0) return {b, b, s1};
+  if (r == 1) return {s1, b, s2};
+  return {s2, b, (rk == nrk - 1) ? 0 : s1};
+}
+
+// Arguments of stage r (0..2) of RK step rk of one outer step: y1 = y + h/3 T(y),
+// y2 = y + h/2 T(y1), y <- y + h T(y2), with T the adaptation for the first msub
+// RK steps (h = dt/msub) and the advection for the last (h = dt).
+template <typename T>
+StageArgs<T> step_stage_args(const dycore_s* h, int rk, int r, T* U, T* V, T* F, T* P) {
+  Packed<T> y1 = unpack<T>(h, h->scratch);
+  Packed<T> y2 = unpack<T>(h, static_cast<char*>(h->scratch) + h->state_bytes);
+  const int nrk = h->msub + 1;
+  const int proc = (rk < h->msub) ? 0 : 1;
+  const double hs = proc == 0 ? h->dt / h->msub : h->dt;
+  const Slots sl = stage_slots(rk, nrk, r);
+  const double* pin = pole_slot(h, sl.pin);
+  const double* pb = pole_slot(h, sl.pbase);
+  double* po = pole_slot(h, sl.pout);
+  if (r == 0)
+    return make_args<T>(h, proc, hs / 3.0, U, V, F, P, U, V, F, P, y1.U, y1.V, y1.F, y1.P, pin, pb, po);
+  if (r == 1)
+    return make_args<T>(h, proc, hs / 2.0, y1.U, y1.V, y1.F, y1.P, U, V, F, P, y2.U, y2.V, y2.F, y2.P, pin, pb, po);
+  return make_args<T>(h, proc, hs, y2.U, y2.V, y2.F, y2.P, U, V, F, P, U, V, F, P, pin, pb, po);
+}
+
+template <typename T>
+int step_impl(dycore_s* h, T* U, T* V, T* F, T* P, int nsteps, hipStream_t s) {
+  if (nsteps == 0) return DYCORE_OK;
+  hipError_t e = launch_pole_prep<T>(h->g, F, P, pole_slot(h, 0), s);
+  if (e != hipSuccess) return DYCORE_EHIP;
+  const int nrk = h->msub + 1;
+  for (int n = 0; n < nsteps; ++n)
+    for (int rk = 0; rk < nrk; ++rk)
+      for (int r = 0; r < 3; ++r) {
+        e = launch_stage<T>(step_stage_args<T>(h, rk, r, U, V, F, P), h->block, s);
+        if (e != hipSuccess) return DYCORE_EHIP;
+      }
+  return DYCORE_OK;
+}
+
+template <typename T>
+int stage_impl(dycore_s* h, int process, double ch, const T* bU, const T* bV, const T* bF, const T* bP,
+               const T* U, const T* V, const T* F, const T* P, T* oU, T* oV, T* oF, T* oP, hipStream_t s) {
+  hipError_t e = launch_pole_prep<T>(h->g, F, P, pole_slot(h, 0), s);
+  if (e == hipSuccess) e = launch_pole_prep<T>(h->g, bF, bP, pole_slot(h, 1), s);
+  if (e == hipSuccess)
+    e = launch_stage<T>(make_args<T>(h, process, ch, U, V, F, P, bU, bV, bF, bP, oU, oV, oF, oP, pole_slot(h, 0),
+                                     pole_slot(h, 1), pole_slot(h, 2)), h->block, s);
+  return hip_status(e);
+}
+
+int validate_cfg(const dycore_config* c) {
+  if (!c) return DYCORE_EINVAL;
+  if (c->nx < 8 || c->nx > 4096 || c->ny < 4 || c->ny > 8192 || c->nz < 1 || c->nz > 128) return DYCORE_EINVAL;
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return DYCORE_EINVAL;
+  if (c->n_adapt_substeps < 0) return DYCORE_EINVAL;
+  if (c->prec != DYCORE_FP32 && c->prec != DYCORE_FP64) return DYCORE_EINVAL;
+  if (c->block != 0 && (c->block < 64 || c->block > 1024 || (c->block % 64) != 0)) return DYCORE_EINVAL;
+  if (c->sigma_half) {
+    if (c->sigma_half[0] != 0.0 || c->sigma_half[c->nz] != 1.0) return DYCORE_EINVAL;
+    for (int k = 0; k < c->nz; ++k)
+      if (!(c->sigma_half[k + 1] > c->sigma_half[k])) return DYCORE_EINVAL;
+  }
+  return DYCORE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dycore_strerror(int status) {
+  switch (status) {
+    case DYCORE_OK: return "ok";
+    case DYCORE_EINVAL: return "invalid argument";
+    case DYCORE_ENOMEM: return "device allocation failed";
+    case DYCORE_EHIP: return "HIP runtime error";
+    case DYCORE_ENONFINITE: return "non-finite value in a field";
+    case DYCORE_EUNSUPPORTED: return "grid exceeds a kernel tile limit";
+    default: return "unknown status";
+  }
+}
+
+int dycore_create(const dycore_config* cfg, dycore_t* out) {
+  if (!out) return DYCORE_EINVAL;
+  *out = nullptr;
+  int st = validate_cfg(cfg);
+  if (st != DYCORE_OK) return st;
+  dycore_s* h = new (std::nothrow) dycore_s();
+  if (!h) return DYCORE_ENOMEM;
+  h->nx = cfg->nx; h->ny = cfg->ny; h->nz = cfg->nz; h->prec = cfg->prec; h->dt = cfg->dt; h->flags = cfg->flags;
+  h->elem = (h->prec == DYCORE_FP32) ? 4 : 8;
+  h->block = cfg->block ? cfg->block : default_block(h->nx, h->prec);
+  if (columns_per_thread(h->nx, h->block) > 8) { delete h; return DYCORE_EUNSUPPORTED; }
+  const size_t lds = std::max(stage_lds_bytes(0, h->nx, (int)h->elem), stage_lds_bytes(1, h->nx, (int)h->elem));
+  if (lds > 160 * 1024) { delete h; return DYCORE_EUNSUPPORTED; }
+  (void)hipGetDevice(&h->device);
+
+  const int nx = h->nx, ny = h->ny, nz = h->nz;
+  GeoDev& g = h->g;
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  const double defs[7] = {6.371e6, 7.292e-5, 9.80616, 287.04, 1004.64, 1.0e5, 300.0};
+  const double given[7] = {cfg->a, cfg->omega, cfg->g, cfg->rd, cfg->cp, cfg->p0, cfg->t0};
+  double cst[7];
+  for (int i = 0; i < 7; ++i) cst[i] = given[i] != 0.0 ? given[i] : defs[i];
+  g.a = cst[0]; g.omega = cst[1]; g.g = cst[2]; g.rd = cst[3]; g.cp = cst[4]; g.p0 = cst[5]; g.t0 = cst[6];
+  g.kappa = g.rd / g.cp;
+  g.b = std::sqrt(g.kappa * g.rd * g.t0);
+  g.RT0 = g.rd * g.t0;
+  g.dlam = 2.0 * M_PI / nx;
+  g.dth = M_PI / ny;
+  g.acap = 2.0 * M_PI * g.a * g.a * (1.0 - std::cos(0.5 * g.dth));
+
+  // host tables
+  std::vector<double> s(ny + 1, 0.0), cot(ny + 1, 0.0), f(ny + 1, 0.0);
+  std::vector<double> sv(ny), cotv(ny), fv(ny);
+  h->M.assign(ny + 1, 1);
+  h->Mv.assign(ny, 1);
+  for (int j = 1; j < ny; ++j) {
+    const double th = j * g.dth;
+    s[j] = std::sin(th);
+    cot[j] = std::cos(th) / std::sin(th);
+    f[j] = 2.0 * g.omega * std::cos(th);
+    h->M[j] = leap_span(s[j], g.dlam, nx);
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double th = (j + 0.5) * g.dth;
+    sv[j] = std::sin(th);
+    cotv[j] = std::cos(th) / std::sin(th);
+    fv[j] = 2.0 * g.omega * std::cos(th);
+    h->Mv[j] = leap_span(sv[j], g.dlam, nx);
+  }
+  std::vector<double> sigh(nz + 1), sig(nz), dsig(nz), cl(nz), cpk(nz);
+  for (int k = 0; k <= nz; ++k) sigh[k] = cfg->sigma_half ? cfg->sigma_half[k] : double(k) / nz;
+  for (int k = 0; k < nz; ++k) {
+    sig[k] = 0.5 * (sigh[k] + sigh[k + 1]);
+    dsig[k] = sigh[k + 1] - sigh[k];
+    cl[k] = k >= 1 ? std::log(sigh[k + 1] / sigh[k]) : 0.0;
+    cpk[k] = std::log(sigh[k + 1] / sig[k]);
+  }
+  std::vector<double> phis((size_t)(ny + 1) * nx, 0.0);
+  if (cfg->phis) std::memcpy(phis.data(), cfg->phis, sizeof(double) * phis.size());
+  for (int p : {0, ny}) {
+    double m = 0;
+    for (int i = 0; i < nx; ++i) m += phis[(size_t)p * nx + i];
+    m /= nx;
+    for (int i = 0; i < nx; ++i) phis[(size_t)p * nx + i] = m;
+  }
+  if (cfg->n_adapt_substeps > 0) {
+    h->msub = cfg->n_adapt_substeps;
+  } else {
+    const double dx45 = g.a * std::cos(M_PI / 4.0) * g.dlam, dy = g.a * g.dth;
+    const double wmax = 2.0 * 350.0 * std::sqrt(1.0 / (dx45 * dx45) + 1.0 / (dy * dy));
+    h->msub = std::max(1, (int)std::ceil(wmax * h->dt / (0.8 * std::sqrt(3.0))));
+  }
+
+  // one device block for the tables
+  std::vector<std::pair<const void*, size_t>> parts = {
+      {s.data(), s.size() * 8},       {cot.data(), cot.size() * 8},   {f.data(), f.size() * 8},
+      {h->M.data(), h->M.size() * 4}, {sv.data(), sv.size() * 8},     {cotv.data(), cotv.size() * 8},
+      {fv.data(), fv.size() * 8},     {h->Mv.data(), h->Mv.size() * 4}, {sigh.data(), sigh.size() * 8},
+      {sig.data(), sig.size() * 8},   {dsig.data(), dsig.size() * 8}, {cl.data(), cl.size() * 8},
+      {cpk.data(), cpk.size() * 8},   {phis.data(), phis.size() * 8}};
+  size_t gbytes = 0;
+  for (auto& pr : parts) gbytes += align256(pr.second);
+  if (hipMalloc(&h->geo, gbytes) != hipSuccess) { delete h; return DYCORE_ENOMEM; }
+  std::vector<char> host(gbytes, 0);
+  std::vector<size_t> off;
+  size_t o = 0;
+  for (auto& pr : parts) {
+    std::memcpy(host.data() + o, pr.first, pr.second);
+    off.push_back(o);
+    o += align256(pr.second);
+  }
+  if (hipMemcpy(h->geo, host.data(), gbytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(h->geo); delete h; return DYCORE_EHIP;
+  }
+  char* gb = static_cast<char*>(h->geo);
+  g.s = (const double*)(gb + off[0]); g.cot = (const double*)(gb + off[1]); g.f = (const double*)(gb + off[2]);
+  g.M = (const int*)(gb + off[3]); g.sv = (const double*)(gb + off[4]); g.cotv = (const double*)(gb + off[5]);
+  g.fv = (const double*)(gb + off[6]); g.Mv = (const int*)(gb + off[7]); g.sigh = (const double*)(gb + off[8]);
+  g.sig = (const double*)(gb + off[9]); g.dsig = (const double*)(gb + off[10]); g.cl = (const double*)(gb + off[11]);
+  g.cpk = (const double*)(gb + off[12]); g.phis = (const double*)(gb + off[13]);
+
+  h->nU = (size_t)(ny + 1) * nz * nx;
+  h->nV = (size_t)ny * nz * nx;
+  h->nF = h->nU;
+  h->nP = (size_t)(ny + 1) * nx;
+  h->state_bytes = align256(h->nU * h->elem) + align256(h->nV * h->elem) + align256(h->nF * h->elem) +
+                   align256(h->nP * h->elem);
+  h->bytes = gbytes;
+  bool ok = hipMalloc(&h->scratch, 2 * h->state_bytes) == hipSuccess;
+  ok = ok && hipMalloc((void**)&h->pole, sizeof(double) * kPoleSlots * 2 * (nz + 1)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&h->diag, sizeof(double) * 3 * (ny + 1)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&h->count, sizeof(unsigned long long)) == hipSuccess;
+  if (ok && !(h->flags & DYCORE_FORWARD_ONLY)) {
+    h->adj_bytes = dyc_adjoint_workspace_bytes(h);
+    ok = hipMalloc(&h->adj, h->adj_bytes) == hipSuccess;
+  }
+  if (!ok) { dycore_destroy(h); return DYCORE_ENOMEM; }
+  h->bytes += 2 * h->state_bytes + sizeof(double) * (kPoleSlots * 2 * (nz + 1) + 3 * (ny + 1)) + 8 + h->adj_bytes;
+  *out = h;
+  return DYCORE_OK;
+}
+
+int dycore_destroy(dycore_t h) {
+  if (!h) return DYCORE_EINVAL;
+  (void)hipDeviceSynchronize();
+  if (h->geo) (void)hipFree(h->geo);
+  if (h->scratch) (void)hipFree(h->scratch);
+  if (h->pole) (void)hipFree(h->pole);
+  if (h->diag) (void)hipFree(h->diag);
+  if (h->count) (void)hipFree(h->count);
+  if (h->adj) (void)hipFree(h->adj);
+  delete h;
+  return DYCORE_OK;
+}
+
+int dycore_step(dycore_t h, void* U, void* V, void* Phi, void* ps, int nsteps, void* stream) {
+  if (!h || !U || !V || !Phi || !ps || nsteps < 0) return DYCORE_EINVAL;
+  if (!aligned16(U) || !aligned16(V) || !aligned16(Phi) || !aligned16(ps)) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->prec == DYCORE_FP32)
+    return step_impl<float>(h, (float*)U, (float*)V, (float*)Phi, (float*)ps, nsteps, s);
+  return step_impl<double>(h, (double*)U, (double*)V, (double*)Phi, (double*)ps, nsteps, s);
+}
+
+int dycore_stage(dycore_t h, int process, double ch, const void* bU, const void* bV, const void* bPhi,
+                 const void* bps, const void* U, const void* V, const void* Phi, const void* ps, void* oU, void* oV,
+                 void* oPhi, void* ops, void* stream) {
+  if (!h || (process != 0 && process != 1)) return DYCORE_EINVAL;
+  const void* ptrs[12] = {bU, bV, bPhi, bps, U, V, Phi, ps, oU, oV, oPhi, ops};
+  for (auto p : ptrs)
+    if (!p || !aligned16(p)) return DYCORE_EINVAL;
+  if (oU == U || oV == V || oPhi == Phi || ops == ps) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->prec == DYCORE_FP32)
+    return stage_impl<float>(h, process, ch, (const float*)bU, (const float*)bV, (const float*)bPhi,
+                             (const float*)bps, (const float*)U, (const float*)V, (const float*)Phi,
+                             (const float*)ps, (float*)oU, (float*)oV, (float*)oPhi, (float*)ops, s);
+  return stage_impl<double>(h, process, ch, (const double*)bU, (const double*)bV, (const double*)bPhi,
+                            (const double*)bps, (const double*)U, (const double*)V, (const double*)Phi,
+                            (const double*)ps, (double*)oU, (double*)oV, (double*)oPhi, (double*)ops, s);
+}
+
+int dycore_diagnostics(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps, double* mass_out,
+                       double* energy_out, void* stream) {
+  if (!h || !U || !V || !Phi || !ps || !mass_out || !energy_out) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (h->prec == DYCORE_FP32)
+    e = launch_diag<float>(h->g, (const float*)U, (const float*)V, (const float*)Phi, (const float*)ps, h->diag,
+                           h->ny + 1, s);
+  else
+    e = launch_diag<double>(h->g, (const double*)U, (const double*)V, (const double*)Phi, (const double*)ps,
+                            h->diag, h->ny + 1, s);
+  if (e != hipSuccess) return DYCORE_EHIP;
+  std::vector<double> part(3 * (h->ny + 1));
+  if (hipMemcpyAsync(part.data(), h->diag, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return DYCORE_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return DYCORE_EHIP;
+  double m = 0, en = 0, es = 0;
+  for (int j = 0; j <= h->ny; ++j) { m += part[3 * j]; en += part[3 * j + 1]; es += part[3 * j + 2]; }
+  *mass_out = m;
+  *energy_out = h->g.p0 / (2.0 * h->g.g) * en + h->g.rd * h->g.t0 * h->g.p0 / (2.0 * h->g.g) * es;
+  return DYCORE_OK;
+}
+
+int dycore_check_finite(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,
+                        long long* count_out, void* stream) {
+  if (!h || !U || !V || !Phi || !ps) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_zero<unsigned long long>(h->count, 1, s);
+  const void* f[4] = {U, V, Phi, ps};
+  const size_t n[4] = {h->nU, h->nV, h->nF, h->nP};
+  for (int q = 0; q < 4 && e == hipSuccess; ++q)
+    e = (h->prec == DYCORE_FP32) ? launch_nonfinite<float>((const float*)f[q], n[q], h->count, s)
+                                 : launch_nonfinite<double>((const double*)f[q], n[q], h->count, s);
+  if (e != hipSuccess) return DYCORE_EHIP;
+  unsigned long long c = 0;
+  if (hipMemcpyAsync(&c, h->count, sizeof(c), hipMemcpyDeviceToHost, s) != hipSuccess) return DYCORE_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return DYCORE_EHIP;
+  if (count_out) *count_out = (long long)c;
+  return c ? DYCORE_ENONFINITE : DYCORE_OK;
+}
+
+int dycore_leap_table(dycore_t h, int* m_rows, int* m_vrows) {
+  if (!h) return DYCORE_EINVAL;
+  if (m_rows) std::memcpy(m_rows, h->M.data(), sizeof(int) * h->M.size());
+  if (m_vrows) std::memcpy(m_vrows, h->Mv.data(), sizeof(int) * h->Mv.size());
+  return DYCORE_OK;
+}
+
+int dycore_substeps(dycore_t h) { return h ? h->msub : DYCORE_EINVAL; }
+int dycore_block(dycore_t h) { return h ? h->block : DYCORE_EINVAL; }
+size_t dycore_workspace_bytes(dycore_t h) { return h ? h->bytes : 0; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Batches: members of mixed grids advance together, one persistent launch per global stage.
+// ------------------------------------------------------------------------------------------------
+namespace {
+
+struct PrepDesc {
+  int nx, ny, nz, pad;
+  const void* F;
+  const void* P;
+  double* pole;
+};
+
+template <typename T>
+__global__ void k_prep_batch(const PrepDesc* d, int n) {
+  // block (m, v): member m, value v of its 2*(nz+1) pole values; one wavefront each
+  const int m = blockIdx.y;
+  if (m >= n) return;
+  const PrepDesc pd = d[m];
+  const int v = blockIdx.x;
+  if (v >= 2 * (pd.nz + 1)) return;
+  const int p = v / (pd.nz + 1), k = v % (pd.nz + 1);
+  const int j = (p == 0) ? 0 : pd.ny;
+  const T* src = (k < pd.nz) ? (const T*)pd.F + ((size_t)j * pd.nz + k) * pd.nx : (const T*)pd.P + (size_t)j * pd.nx;
+  double s = 0;
+  for (int i = threadIdx.x; i < pd.nx; i += 64) s += (double)src[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0) pd.pole[p * (pd.nz + 1) + k] = s / (double)pd.nx;
+}
+
+template <typename T>
+int batch_build(dycore_batch_s* b) {
+  const int n = b->n;
+  std::vector<StageArgs<T>> args((size_t)b->nstage_max * n);
+  for (int m = 0; m < n; ++m) {
+    dycore_s* h = b->hs[m];
+    T* U = (T*)b->U[m]; T* V = (T*)b->V[m]; T* F = (T*)b->F[m]; T* P = (T*)b->P[m];
+    const int nst = 3 * (h->msub + 1);
+    for (int sidx = 0; sidx < b->nstage_max; ++sidx) {
+      StageArgs<T>& a = args[(size_t)sidx * n + m];
+      if (sidx < nst) {
+        a = step_stage_args<T>(h, sidx / 3, sidx % 3, U, V, F, P);
+      } else {
+        a = make_args<T>(h, -1, 0.0, U, V, F, P, U, V, F, P, U, V, F, P, nullptr, nullptr, nullptr);
+      }
+    }
+  }
+  if (hipMalloc(&b->d_args, sizeof(StageArgs<T>) * args.size()) != hipSuccess) return DYCORE_ENOMEM;
+  if (hipMemcpy(b->d_args, args.data(), sizeof(StageArgs<T>) * args.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return DYCORE_EHIP;
+  // work items: members largest first, rows in XCD order, each member padded to a multiple of 8
+  std::vector<int> order(n);
+  for (int m = 0; m < n; ++m) order[m] = m;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const dycore_s* a = b->hs[x]; const dycore_s* c = b->hs[y];
+    return (size_t)a->nx * a->nz > (size_t)c->nx * c->nz;
+  });
+  std::vector<int2> items;
+  for (int m : order) {
+    const int R = b->hs[m]->ny + 1;
+    const int Rp = (R + 7) / 8 * 8;
+    for (int p = 0; p < Rp; ++p) {
+      int2 it;
+      if (p < R) {
+        const int x = p & 7, slot = p >> 3, q = R >> 3, rem = R & 7;
+        it.x = m;
+        it.y = x * q + std::min(x, rem) + slot;
+      } else {
+        it.x = -1; it.y = 0;
+      }
+      items.push_back(it);
+    }
+  }
+  b->nitems = (int)items.size();
+  if (hipMalloc((void**)&b->d_items, sizeof(int2) * items.size()) != hipSuccess) return DYCORE_ENOMEM;
+  if (hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return DYCORE_EHIP;
+  std::vector<PrepDesc> pd(n);
+  for (int m = 0; m < n; ++m) {
+    dycore_s* h = b->hs[m];
+    pd[m] = PrepDesc{h->nx, h->ny, h->nz, 0, b->F[m], b->P[m], pole_slot(h, 0)};
+  }
+  if (hipMalloc(&b->d_prep, sizeof(PrepDesc) * n) != hipSuccess) return DYCORE_ENOMEM;
+  if (hipMemcpy(b->d_prep, pd.data(), sizeof(PrepDesc) * n, hipMemcpyHostToDevice) != hipSuccess) return DYCORE_EHIP;
+  return DYCORE_OK;
+}
+
+template <typename T>
+int batch_step(dycore_batch_s* b, int nsteps, hipStream_t s) {
+  int maxnz = 0;
+  for (auto h : b->hs) maxnz = std::max(maxnz, h->nz);
+  hipLaunchKernelGGL((k_prep_batch<T>), dim3(2 * (maxnz + 1), b->n), dim3(64), 0, s, (const PrepDesc*)b->d_prep,
+                     b->n);
+  if (hipGetLastError() != hipSuccess) return DYCORE_EHIP;
+  const StageArgs<T>* args = static_cast<const StageArgs<T>*>(b->d_args);
+  for (int n = 0; n < nsteps; ++n)
+    for (int sidx = 0; sidx < b->nstage_max; ++sidx) {
+      hipError_t e = launch_stage_batch<T>(args + (size_t)sidx * b->n, b->d_items, b->nitems, b->grid, b->block,
+                                           b->max_nx, s);
+      if (e != hipSuccess) return DYCORE_EHIP;
+    }
+  return DYCORE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* V, void* const* Phi,
+                        void* const* ps, int block, int grid, dycore_batch_t* out) {
+  if (!out || n < 1 || !hs || !U || !V || !Phi || !ps) return DYCORE_EINVAL;
+  *out = nullptr;
+  const int prec = hs[0] ? hs[0]->prec : -1;
+  int max_nx = 0, nst = 0;
+  for (int m = 0; m < n; ++m) {
+    if (!hs[m] || hs[m]->prec != prec || !U[m] || !V[m] || !Phi[m] || !ps[m]) return DYCORE_EINVAL;
+    if (!aligned16(U[m]) || !aligned16(V[m]) || !aligned16(Phi[m]) || !aligned16(ps[m])) return DYCORE_EINVAL;
+    for (int q = 0; q < m; ++q)
+      if (hs[q] == hs[m]) return DYCORE_EINVAL;   // each member needs its own scratch
+    max_nx = std::max(max_nx, hs[m]->nx);
+    nst = std::max(nst, 3 * (hs[m]->msub + 1));
+  }
+  if (block == 0) block = 256;
+  if (block < 64 || block > 1024 || block % 64) return DYCORE_EINVAL;
+  if (columns_per_thread(max_nx, block) > 8) return DYCORE_EUNSUPPORTED;
+  const size_t elem = prec == DYCORE_FP32 ? 4 : 8;
+  if (std::max(stage_lds_bytes(0, max_nx, (int)elem), stage_lds_bytes(1, max_nx, (int)elem)) > 160 * 1024)
+    return DYCORE_EUNSUPPORTED;
+  dycore_batch_s* b = new (std::nothrow) dycore_batch_s();
+  if (!b) return DYCORE_ENOMEM;
+  b->n = n; b->prec = prec; b->block = block; b->max_nx = max_nx; b->nstage_max = nst;
+  b->hs.assign(hs, hs + n);
+  b->U.assign(U, U + n); b->V.assign(V, V + n); b->F.assign(Phi, Phi + n); b->P.assign(ps, ps + n);
+  const int st = prec == DYCORE_FP32 ? batch_build<float>(b) : batch_build<double>(b);
+  if (st != DYCORE_OK) { dycore_batch_destroy(b); return st; }
+  if (grid <= 0) {
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t lds = std::max(stage_lds_bytes(0, max_nx, (int)elem), stage_lds_bytes(1, max_nx, (int)elem));
+    int per_cu = (int)std::max<size_t>(1, (160 * 1024) / lds);
+    per_cu = std::min(per_cu, std::max(1, 2048 / block));
+    grid = cus * per_cu;
+  }
+  grid = std::max(8, grid / 8 * 8);
+  b->grid = std::min(grid, (b->nitems + 7) / 8 * 8);
+  *out = b;
+  return DYCORE_OK;
+}
+
+int dycore_batch_step(dycore_batch_t b, int nsteps, void* stream) {
+  if (!b || nsteps < 0) return DYCORE_EINVAL;
+  if (nsteps == 0) return DYCORE_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return b->prec == DYCORE_FP32 ? batch_step<float>(b, nsteps, s) : batch_step<double>(b, nsteps, s);
+}
+
+int dycore_batch_destroy(dycore_batch_t b) {
+  if (!b) return DYCORE_EINVAL;
+  (void)hipDeviceSynchronize();
+  if (b->d_args) (void)hipFree(b->d_args);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_prep) (void)hipFree(b->d_prep);
+  delete b;
+  return DYCORE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP translation units of libdycore.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dyc {
+
+// Geometry and constants as the kernels see them (device pointers to FP64 tables).
+struct GeoDev {
+  int nx, ny, nz;
+  double a, omega, g, rd, cp, p0, t0, kappa, b, dlam, dth, acap, RT0;
+  const double* s;      // sin(theta_j), rows 0..ny
+  const double* cot;    // cot(theta_j)
+  const double* f;      // 2 Omega cos(theta_j)
+  const int* M;         // leap span per scalar/U row (odd, 1 at the poles)
+  const double* sv;     // sin(theta_{j+1/2}), V rows 0..ny-1
+  const double* cotv;
+  const double* fv;
+  const int* Mv;        // leap span per V row
+  const double* sigh;   // nz+1 half levels
+  const double* sig;    // nz full levels
+  const double* dsig;   // nz layer thickness
+  const double* cl;     // ln(sigh[l+1]/sigh[l]) for l >= 1, 0 for l = 0
+  const double* cpk;    // ln(sigh[k+1]/sig[k])
+  const double* phis;   // (ny+1)*nx surface geopotential, pole rows = row mean
+};
+
+// Pole slot layout: double[2][nz+1]; [p][k] = Phi pole value at level k, [p][nz] = p_s pole value,
+// p = 0 north, 1 south.
+
+// One stage out = base + ch * T(in) of one member.
+template <typename T>
+struct StageArgs {
+  GeoDev g;
+  const T* inU; const T* inV; const T* inF; const T* inP;
+  const T* bU; const T* bV; const T* bF; const T* bP;
+  T* oU; T* oV; T* oF; T* oP;
+  const double* pin;    // pole values of `in`
+  const double* pbase;  // pole values of `base`
+  double* pout;         // pole values written for `out`
+  double ch;
+  int process;          // 0 adaptation, 1 advection, -1 idle
+  int pad;
+};
+
+// Adjoint of one stage about `in`.
+template <typename T>
+struct AdjArgs {
+  GeoDev g;
+  const T* inU; const T* inV; const T* inF; const T* inP;      // linearisation state
+  const T* aoU; const T* aoV; const T* aoF; const T* aoP;      // adjoint of the stage output
+  T* abU; T* abV; T* abF; T* abP;                             // += adjoint of base
+  T* aiU; T* aiV; T* aiF; T* aiP;                             // += adjoint of in
+  const double* pin;   // pole values of `in`
+  double ch;
+  int process;
+  int pad;
+  // workspace (device), sized at create
+  T* w3[16];           // 3D scratch fields, (ny+1)*(nz+1)*nx entries each
+  T* w2[8];            // 2D scratch fields, (ny+1)*nx entries each
+  double* wpole;       // pole scratch, 64*(nz+1) doubles
+};
+
+// Launch helpers implemented in the kernel translation units.
+template <typename T>
+hipError_t launch_pole_prep(const GeoDev& g, const T* F, const T* ps, double* pole, hipStream_t s);
+template <typename T>
+hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s);
+template <typename T>
+hipError_t launch_stage_batch(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid,
+                              int block, int max_nx, hipStream_t s);
+template <typename T>
+hipError_t launch_stage_adjoint(const AdjArgs<T>& a, int block, hipStream_t s);
+template <typename T>
+hipError_t launch_diag(const GeoDev& g, const T* U, const T* V, const T* F, const T* ps,
+                       double* partial, int npartial, hipStream_t s);
+template <typename T>
+hipError_t launch_nonfinite(const T* x, size_t n, unsigned long long* count, hipStream_t s);
+template <typename T>
+hipError_t launch_axpy_fill(T* dst, const T* src, size_t n, hipStream_t s);   // dst = src (copy) via kernel
+template <typename T>
+hipError_t launch_zero(T* dst, size_t n, hipStream_t s);
+
+size_t stage_lds_bytes(int process, int nx, int elem);
+int columns_per_thread(int nx, int block);
+
+// XCD-aware row order: workgroups are dispatched round-robin over the 8 XCDs,
+// so block b lands on XCD b % 8.  Give each XCD a contiguous band of rows, in
+// order, so that neighbouring rows (which share halo rows) share an L2.
+__device__ __forceinline__ int xcd_row(int b, int nrows) {
+  const int x = b & 7, slot = b >> 3;
+  const int q = nrows >> 3, rem = nrows & 7;
+  const int start = x * q + (x < rem ? x : rem);
+  return start + slot;
+}
+
+}  // namespace dyc

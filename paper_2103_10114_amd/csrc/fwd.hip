@@ -1,0 +1,865 @@
+// Forward stage kernels of the leap-format dynamical core (gfx950).
+//
+// One workgroup owns one latitude row j: the scalar row j (Phi, p_s), the U
+// row j and the V row j+1/2.  It walks the column top to bottom, level by
+// level; each thread owns columns i = t, t+B, ... of the row and keeps its
+// column sums in FP64 registers.  Rows that a leap difference reads at
+// distance up to M (eq. 7, Table 6) are staged whole in LDS, so the periodic
+// zonal wrap is a modular index into LDS and never a halo exchange.  Pole rows
+// are reduced in FP64 by the first wavefront in a fixed lane order, so results
+// do not depend on the workgroup size.
+#include "dycore_internal.h"
+
+namespace dyc {
+namespace {
+
+template <typename T> __device__ __forceinline__ T tsqrt(T x);
+template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T tlog(T x);
+template <> __device__ __forceinline__ float tlog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ double tlog<double>(double x) { return log(x); }
+
+__device__ __forceinline__ int wrp(int i, int nx) {
+  // |offset| < nx for every caller
+  return i >= nx ? i - nx : (i < 0 ? i + nx : i);
+}
+
+// Deterministic FP64 row sum by wavefront 0: lane l adds i = l, l+64, ... in
+// order, then a butterfly (commutative adds give every lane the same total).
+__device__ __forceinline__ double wave_sum(double acc) {
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  return acc;
+}
+
+using C = double;
+
+// ----------------------------------------------------------------------------------------------
+// Adaptation: out = base + ch * A(in)
+// ----------------------------------------------------------------------------------------------
+template <typename T, int NI>
+__device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int B = blockDim.x, t = threadIdx.x;
+  T* sP0 = reinterpret_cast<T*>(smem);
+  T* sP1 = sP0 + nx;
+  T* sDl = sP1 + nx;
+  T* sPhi = sDl + nx;
+  T* sMU = sPhi + nx;
+  T* sL = sMU + nx;
+  T* sQ = sL + nx;
+  double* sRed = reinterpret_cast<double*>(smem + ((7 * nx * sizeof(T) + 15) & ~size_t(15)));
+
+  const bool isPole = (j == 0 || j == ny);
+  const bool hasV = (j < ny);
+  const int pidx = (j == 0) ? 0 : 1;
+  const T p0 = (T)g.p0, b = (T)g.b, RT0 = (T)g.RT0;
+  const C RT0c = g.RT0;
+  const size_t row3 = (size_t)nz * nx;
+
+  auto psA = [&](int jr, int i) -> T {
+    if (jr == 0) return (T)A.pin[nz];
+    if (jr == ny) return (T)A.pin[(nz + 1) + nz];
+    return A.inP[(size_t)jr * nx + i];
+  };
+  auto FA = [&](int jr, int k, int i) -> T {
+    if (jr == 0) return (T)A.pin[k];
+    if (jr == ny) return (T)A.pin[(nz + 1) + k];
+    return A.inF[(size_t)jr * row3 + (size_t)k * nx + i];
+  };
+  auto UA = [&](int jr, int k, int i) -> T {
+    if (jr == 0 || jr == ny) return T(0);
+    return A.inU[(size_t)jr * row3 + (size_t)k * nx + i];
+  };
+  auto VA = [&](int jv, int k, int i) -> T { return A.inV[(size_t)jv * row3 + (size_t)k * nx + i]; };
+
+  // adjacent scalar row of a pole workgroup
+  const int ja = (j == 0) ? 1 : ny - 1;
+
+  // ---- 2D set-up: P rows j and j+1 (or the row next to the pole), l and q of row j
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    if (i < nx) {
+      const T psj = psA(j, i);
+      sP0[i] = tsqrt<T>(psj / p0);
+      const T lj = tlog<T>(psj / p0);
+      if (isPole) {
+        const T psa = psA(ja, i);
+        sP1[i] = tsqrt<T>(psa / p0);
+        sL[i] = tlog<T>(psa / p0);       // l of the adjacent row (pole reductions)
+        sQ[i] = lj;                      // pole l (replicated)
+      } else {
+        sL[i] = lj;
+        sQ[i] = lj + (T)g.phis[(size_t)j * nx + i] / RT0;
+        sP1[i] = tsqrt<T>(psA(j + 1, i) / p0);
+      }
+    }
+  }
+  __syncthreads();
+
+  T P0c[NI], P1c[NI], Pmc[NI], l0c[NI], l1c[NI], lmc[NI], q0c[NI], q1c[NI];
+  T PU0c[NI], PV0c[NI], PVmc[NI], dqc[NI];
+  C H0c[NI], H1c[NI], R0c[NI], R1c[NI], Sc[NI];
+  const int Mj = isPole ? 1 : g.M[j];
+  const int nj = (Mj + 1) / 2;
+  const T dxj = isPole ? T(1) : (T)((double)Mj * g.a * g.s[j] * g.dlam);
+#pragma unroll
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    H0c[c] = 0; H1c[c] = 0; R0c[c] = 0; R1c[c] = 0; Sc[c] = 0;
+    P0c[c] = P1c[c] = Pmc[c] = l0c[c] = l1c[c] = lmc[c] = q0c[c] = q1c[c] = T(0);
+    PU0c[c] = PV0c[c] = PVmc[c] = dqc[c] = T(1);
+    if (i < nx) {
+      P0c[c] = sP0[i];
+      if (isPole) {
+        l0c[c] = sQ[i];
+        q0c[c] = l0c[c] + (T)g.phis[(size_t)j * nx + i] / RT0;
+      } else {
+        l0c[c] = sL[i];
+        q0c[c] = sQ[i];
+      }
+      if (hasV) {
+        P1c[c] = sP1[i];
+        const T ps1 = psA(j + 1, i);
+        l1c[c] = tlog<T>(ps1 / p0);
+        q1c[c] = l1c[c] + (T)g.phis[(size_t)(j + 1) * nx + i] / RT0;
+        PV0c[c] = T(0.5) * (P0c[c] + P1c[c]);
+      }
+      if (j >= 1) {
+        const T psm = psA(j - 1, i);
+        Pmc[c] = tsqrt<T>(psm / p0);
+        lmc[c] = tlog<T>(psm / p0);
+        PVmc[c] = T(0.5) * (Pmc[c] + P0c[c]);
+      }
+      if (!isPole) {
+        const T dl = (sL[wrp(i + nj, nx)] - sL[wrp(i + 1 - nj, nx)]) / dxj;
+        dqc[c] = (sQ[wrp(i + nj, nx)] - sQ[wrp(i + 1 - nj, nx)]) / dxj;
+        sDl[i] = dl;
+        PU0c[c] = T(0.5) * (sP0[i] + sP0[wrp(i + 1, nx)]);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- pass A: column totals H = sum_{l>=1} cl_l RT'_l (FP64) for phi' = H - R_k + cpk_k RT'_k
+  if (j < ny) {
+    for (int k = 0; k < nz; ++k) {
+      const C clk = g.cl[k];
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i < nx) {
+          H0c[c] += clk * (C)(b * FA(j, k, i) / P0c[c]);
+          H1c[c] += clk * (C)(b * FA(j + 1, k, i) / P1c[c]);
+        }
+      }
+    }
+  }
+
+  // ---- pass B: top to bottom
+  C Sp = 0;   // pole prefix sum (pole workgroups)
+  for (int k = 0; k < nz; ++k) {
+    const C clk = g.cl[k], cpk = g.cpk[k];
+    const C dsg = g.dsig[k], sgk = g.sig[k];
+    T Fj[NI], RTj[NI], phij[NI], Uj[NI], RTj1[NI], phij1[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      Fj[c] = RTj[c] = phij[c] = Uj[c] = RTj1[c] = phij1[c] = T(0);
+      if (i < nx) {
+        Fj[c] = FA(j, k, i);
+        RTj[c] = b * Fj[c] / P0c[c];
+        if (hasV) {
+          R0c[c] += clk * (C)RTj[c];
+          phij[c] = (T)(H0c[c] - R0c[c] + cpk * (C)RTj[c]);
+          const T F1 = FA(j + 1, k, i);
+          RTj1[c] = b * F1 / P1c[c];
+          R1c[c] += clk * (C)RTj1[c];
+          phij1[c] = (T)(H1c[c] - R1c[c] + cpk * (C)RTj1[c]);
+        }
+        if (!isPole) {
+          sPhi[i] = phij[c];
+          Uj[c] = UA(j, k, i);
+          sMU[i] = PU0c[c] * Uj[c];
+        }
+      }
+    }
+    __syncthreads();
+
+    if (!isPole) {
+      const T dyS = (T)(g.a * g.s[j] * g.dth);
+      const T dyA = (T)(g.a * g.dth);
+      const T svj = (T)g.sv[j], svm = (T)g.sv[j - 1];
+      const T fj = (T)g.f[j], cota = (T)(g.cot[j] / g.a);
+      const T kap = (T)g.kappa;
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
+        const T Vn = VA(j, k, i), Vs = VA(j - 1, k, i);
+        // divergence of the mass flux: leaped (x,x-1) -> (x+N-1, x-N) plus meridional
+        const T D = (sMU[wrp(i + nj - 1, nx)] - sMU[wrp(i - nj, nx)]) / dxj +
+                    (svj * (PV0c[c] * Vn) - svm * (PVmc[c] * Vs)) / dyS;
+        const C Sk = Sc[c];
+        Sc[c] += (C)D * dsg;
+        // v . grad(l)
+        const int im1 = wrp(i - 1, nx);
+        const T u_i = Uj[c] / PU0c[c];
+        const T PUm = T(0.5) * (sP0[im1] + sP0[i]);
+        const T u_m = UA(j, k, im1) / PUm;
+        const T zon = T(0.5) * (u_i * sDl[i] + u_m * sDl[im1]);
+        const T mer = T(0.5) * ((Vn / PV0c[c]) * (l1c[c] - l0c[c]) + (Vs / PVmc[c]) * (l0c[c] - lmc[c])) / dyA;
+        const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) / (sgk * (C)P0c[c] * (C)P0c[c]);
+        const C TF = ((C)(b * P0c[c]) + (C)(kap * Fj[c])) * wp;
+        A.oF[id] = (T)((C)A.bF[id] + A.ch * TF);
+        // U at i+1/2: pressure gradient with leap (x+1,x) -> (x+N, x-N+1) and Coriolis
+        const int ip1 = wrp(i + 1, nx);
+        const T dphi = (sPhi[wrp(i + nj, nx)] - sPhi[wrp(i + 1 - nj, nx)]) / dxj;
+        const T RTp = b * FA(j, k, ip1) / sP0[ip1];
+        const T rtx = T(0.5) * (RTj[c] + RTp);
+        const C pgf = (C)dphi + RT0c * (C)dqc[c] + (C)rtx * (C)sDl[i];
+        const T VV = T(0.25) * (Vn + VA(j, k, ip1) + Vs + VA(j - 1, k, ip1));
+        const T fs = fj + u_i * cota;
+        const C TU = -(C)PU0c[c] * pgf - (C)fs * (C)VV;
+        A.oU[id] = (T)((C)A.bU[id] + A.ch * TU);
+      }
+    } else {
+      // pole column: cap divergence and zonal-mean v.grad(l) from the adjacent V row
+      const int jva = (j == 0) ? 0 : ny - 1;
+      const T Pp = P0c[0];
+      const T lp = l0c[0];
+      if (t < 64) {
+        C s1 = 0, s2 = 0;
+        for (int i = t; i < nx; i += 64) {
+          const T pv = T(0.5) * (Pp + sP1[i]);
+          const T vv = VA(jva, k, i);
+          s1 += (C)(pv * vv);
+          s2 += (C)((vv / pv) * (j == 0 ? (sL[i] - lp) : (lp - sL[i])));
+        }
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        if (t == 0) { sRed[0] = s1; sRed[1] = s2; }
+      }
+      __syncthreads();
+      const C sgn = (j == 0) ? 1.0 : -1.0;
+      const C Dp = sgn * g.a * g.dlam * g.sv[jva] * sRed[0] / g.acap;
+      const C vglp = sRed[1] / ((double)nx * g.a * g.dth);
+      const C Sk = Sp;
+      Sp += Dp * dsg;
+      const C wp = vglp - (Sk + 0.5 * Dp * dsg) / (sgk * (C)Pp * (C)Pp);
+      const C TF = ((C)(b * Pp) + (C)((T)g.kappa * Fj[0])) * wp;
+      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i < nx) {
+          const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
+          A.oF[id] = val;
+          A.oU[id] = T(0);
+        }
+      }
+      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
+    }
+
+    if (hasV) {
+      const T dyA = (T)(g.a * g.dth);
+      const T fvj = (T)g.fv[j], cotva = (T)(g.cotv[j] / g.a);
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const size_t idv = (size_t)j * row3 + (size_t)k * nx + i;
+        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)(q1c[c] - q0c[c]) +
+                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)(l1c[c] - l0c[c])) / (C)dyA;
+        const int im1 = wrp(i - 1, nx), ip1 = wrp(i + 1, nx);
+        const T U0i = UA(j, k, i), U0m = UA(j, k, im1);
+        const T U1i = UA(j + 1, k, i), U1m = UA(j + 1, k, im1);
+        const T u0i = U0i / (T(0.5) * (sP0[i] + sP0[ip1]));
+        const T u0m = U0m / (T(0.5) * (sP0[im1] + sP0[i]));
+        const T u1i = U1i / (T(0.5) * (sP1[i] + sP1[ip1]));
+        const T u1m = U1m / (T(0.5) * (sP1[im1] + sP1[i]));
+        const T UU = T(0.25) * (U0m + U0i + U1m + U1i);
+        const T uu = T(0.25) * (u0m + u0i + u1m + u1i);
+        const T fs = fvj + uu * cotva;
+        const C TV = -(C)PV0c[c] * pgf + (C)fs * (C)UU;
+        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
+      }
+    }
+    __syncthreads();
+  }
+
+  // surface pressure: -p0 * Pi
+  if (!isPole) {
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) {
+        const size_t id = (size_t)j * nx + i;
+        A.oP[id] = (T)((C)A.bP[id] + A.ch * (-g.p0 * Sc[c]));
+      }
+    }
+  } else {
+    const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp));
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) A.oP[(size_t)j * nx + i] = val;
+    }
+    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Advection: out = base - ch * L(in), L in the IAP skew form, zonal part leaped
+// ----------------------------------------------------------------------------------------------
+template <typename T, int NI>
+__device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int B = blockDim.x, t = threadIdx.x;
+  T* sP0 = reinterpret_cast<T*>(smem);   // P row j (pole WG: pole P)
+  T* sP1 = sP0 + nx;                      // P row j+1 (south pole WG: row ny-1)
+  T* sMU1 = sP1 + nx;                     // MU row j+1 at level k
+  T* su0 = sMU1 + nx;                     // u row j
+  T* suv = su0 + nx;                      // u averaged to the V row j+1/2
+  T* sF = suv + nx;                       // Phi row j
+  T* sU = sF + nx;                        // U row j
+  T* sV = sU + nx;                        // V row j
+  T* svtm = sV + nx;                      // v sin(theta) on V row j-1
+  T* svt0 = svtm + nx;                    // v sin(theta) on V row j
+  T* sSd = svt0 + nx;                     // sigma-dot row j at two half levels [2][nx]
+  double* sRed = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));
+
+  const bool isPole = (j == 0 || j == ny);
+  const bool hasV = (j < ny);
+  const bool j1Pole = (j + 1 == ny);
+  const bool j1Int = (j + 1 >= 1 && j + 1 <= ny - 1);
+  const int pidx = (j == 0) ? 0 : 1;
+  const T p0 = (T)g.p0;
+  const size_t row3 = (size_t)nz * nx;
+
+  auto psA = [&](int jr, int i) -> T {
+    if (jr == 0) return (T)A.pin[nz];
+    if (jr == ny) return (T)A.pin[(nz + 1) + nz];
+    return A.inP[(size_t)jr * nx + i];
+  };
+  auto FA = [&](int jr, int k, int i) -> T {
+    if (jr == 0) return (T)A.pin[k];
+    if (jr == ny) return (T)A.pin[(nz + 1) + k];
+    return A.inF[(size_t)jr * row3 + (size_t)k * nx + i];
+  };
+  auto UA = [&](int jr, int k, int i) -> T {
+    if (jr <= 0 || jr >= ny) return T(0);
+    return A.inU[(size_t)jr * row3 + (size_t)k * nx + i];
+  };
+  auto VA = [&](int jv, int k, int i) -> T { return A.inV[(size_t)jv * row3 + (size_t)k * nx + i]; };
+
+  const int ja = (j == 0) ? 1 : ny - 1;   // row next to a pole
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    if (i < nx) {
+      sP0[i] = tsqrt<T>(psA(j, i) / p0);
+      if (hasV) sP1[i] = tsqrt<T>(psA(j + 1, i) / p0);
+      else sP1[i] = tsqrt<T>(psA(ja, i) / p0);
+      sSd[i] = T(0);
+      sSd[nx + i] = T(0);
+    }
+  }
+  __syncthreads();
+
+  T P0c[NI], P1c[NI], PU0c[NI], PU1c[NI], PVm[NI], PV0[NI], PV1[NI];
+  C Pi0[NI], Pi1[NI], S0[NI], S1[NI], sd0c[NI], sd1c[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    P0c[c] = P1c[c] = T(1);
+    PU0c[c] = PU1c[c] = PVm[c] = PV0[c] = PV1[c] = T(1);
+    Pi0[c] = Pi1[c] = S0[c] = S1[c] = sd0c[c] = sd1c[c] = 0;
+    if (i < nx) {
+      const int ip1 = wrp(i + 1, nx);
+      P0c[c] = sP0[i];
+      if (hasV) {
+        P1c[c] = sP1[i];
+        PV0[c] = T(0.5) * (P0c[c] + P1c[c]);
+      }
+      if (j >= 1) PVm[c] = T(0.5) * (tsqrt<T>(psA(j - 1, i) / p0) + P0c[c]);
+      if (j + 2 <= ny) PV1[c] = T(0.5) * (P1c[c] + tsqrt<T>(psA(j + 2, i) / p0));
+      if (!isPole) PU0c[c] = T(0.5) * (sP0[i] + sP0[ip1]);
+      if (j1Int) PU1c[c] = T(0.5) * (sP1[i] + sP1[ip1]);
+    }
+  }
+
+  const int Mj = isPole ? 1 : g.M[j], nj = (Mj + 1) / 2;
+  const int Mj1 = j1Int ? g.M[j + 1] : 1, nj1 = (Mj1 + 1) / 2;
+  const T dxj = isPole ? T(1) : (T)((double)Mj * g.a * g.s[j] * g.dlam);
+  const T dxj1 = j1Int ? (T)((double)Mj1 * g.a * g.s[j + 1] * g.dlam) : T(1);
+  const T dySj = isPole ? T(1) : (T)(g.a * g.s[j] * g.dth);
+  const T dySj1 = j1Int ? (T)(g.a * g.s[j + 1] * g.dth) : T(1);
+
+  // divergence of rows j and j+1 at level k (phase 2 of both passes); MU row j+1 is in LDS,
+  // MU row j is formed from U row j (in LDS) and P row j.
+  auto div_rows = [&](int k, C* D0, C* D1) {
+    // pole rows via FP64 cap sums by wavefront 0
+    const bool needPole0 = isPole;
+    const bool needPole1 = hasV && j1Pole;
+    if (needPole0 || needPole1) {
+      if (t < 64) {
+        C s = 0;
+        const int jv = (j == 0) ? 0 : ny - 1;
+        for (int i = t; i < nx; i += 64) {
+          // V row adjacent to the pole: for j == 0 it is V row 0 (P rows 0,1 = sP0,sP1);
+          // for j == ny it is V row ny-1 (sP0 pole, sP1 row ny-1); for j == ny-1 it is V row ny-1
+          // (sP0 row ny-1, sP1 pole).
+          const T pv = T(0.5) * (sP0[i] + sP1[i]);
+          s += (C)(pv * VA(jv, k, i));
+        }
+        s = wave_sum(s);
+        if (t == 0) sRed[0] = s;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      D0[c] = 0; D1[c] = 0;
+      if (i >= nx) continue;
+      if (isPole) {
+        const int jv = (j == 0) ? 0 : ny - 1;
+        const C sgn = (j == 0) ? 1.0 : -1.0;
+        D0[c] = sgn * g.a * g.dlam * g.sv[jv] * sRed[0] / g.acap;
+      } else {
+        const T mum = T(0.5) * (sP0[wrp(i + nj - 1, nx)] + sP0[wrp(i + nj, nx)]) * sU[wrp(i + nj - 1, nx)];
+        const T mun = T(0.5) * (sP0[wrp(i - nj, nx)] + sP0[wrp(i - nj + 1, nx)]) * sU[wrp(i - nj, nx)];
+        const T D = (mum - mun) / dxj +
+                    ((T)g.sv[j] * (PV0[c] * VA(j, k, i)) - (T)g.sv[j - 1] * (PVm[c] * VA(j - 1, k, i))) / dySj;
+        D0[c] = (C)D;
+      }
+      if (hasV) {
+        if (j1Pole) {
+          D1[c] = -g.a * g.dlam * g.sv[ny - 1] * sRed[0] / g.acap;
+        } else {
+          const T D = (sMU1[wrp(i + nj1 - 1, nx)] - sMU1[wrp(i - nj1, nx)]) / dxj1 +
+                      ((T)g.sv[j + 1] * (PV1[c] * VA(j + 1, k, i)) - (T)g.sv[j] * (PV0[c] * VA(j, k, i))) / dySj1;
+          D1[c] = (C)D;
+        }
+      }
+    }
+  };
+
+  // ---- pass A: column totals Pi for rows j and j+1
+  for (int k = 0; k < nz; ++k) {
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) {
+        sU[i] = UA(j, k, i);
+        if (j1Int) sMU1[i] = PU1c[c] * UA(j + 1, k, i);
+      }
+    }
+    __syncthreads();
+    C D0[NI], D1[NI];
+    div_rows(k, D0, D1);
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      Pi0[c] += D0[c] * g.dsig[k];
+      Pi1[c] += D1[c] * g.dsig[k];
+    }
+    __syncthreads();
+  }
+
+  // ---- pass B
+  const C cc = g.a * g.dlam / (2.0 * g.acap);
+  for (int k = 0; k < nz; ++k) {
+    const C dsg = g.dsig[k];
+    const int par = k & 1, parn = (k + 1) & 1;
+    T Fj[NI], Uj[NI], Vj[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      Fj[c] = Uj[c] = Vj[c] = T(0);
+      if (i < nx) {
+        Fj[c] = FA(j, k, i);
+        Uj[c] = UA(j, k, i);
+        sF[i] = Fj[c];
+        sU[i] = Uj[c];
+        const T u0 = isPole ? T(0) : Uj[c] / PU0c[c];
+        su0[i] = u0;
+        if (j1Int) sMU1[i] = PU1c[c] * UA(j + 1, k, i);
+        if (hasV) {
+          Vj[c] = VA(j, k, i);
+          sV[i] = Vj[c];
+          svt0[i] = Vj[c] / PV0[c] * (T)g.sv[j];
+          const T u1 = j1Int ? UA(j + 1, k, i) / PU1c[c] : T(0);
+          suv[i] = T(0.5) * (u0 + u1);
+        }
+        if (j >= 1) svtm[i] = VA(j - 1, k, i) / PVm[c] * (T)g.sv[j - 1];
+      }
+    }
+    __syncthreads();
+    C D0[NI], D1[NI];
+    div_rows(k, D0, D1);
+    C sd0n[NI], sd1n[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      S0[c] += D0[c] * dsg;
+      S1[c] += D1[c] * dsg;
+      sd0n[c] = 0; sd1n[c] = 0;
+      if (k + 1 < nz) {
+        const C sh = g.sigh[k + 1];
+        sd0n[c] = (sh * Pi0[c] - S0[c]) / ((C)P0c[c] * (C)P0c[c]);
+        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) / ((C)P1c[c] * (C)P1c[c]);
+      }
+      if (i < nx) sSd[parn * nx + i] = (T)sd0n[c];
+    }
+    // pole: meridional cap flux of Phi (needs every column of the adjacent rows)
+    if (isPole) {
+      if (t < 64) {
+        C s = 0;
+        const int jv = (j == 0) ? 0 : ny - 1;
+        for (int i = t; i < nx; i += 64) {
+          const T pv = T(0.5) * (sP0[i] + sP1[i]);
+          const T vt = VA(jv, k, i) / pv * (T)g.sv[jv];
+          s += (C)(vt * FA(ja, k, i));
+        }
+        s = wave_sum(s);
+        if (t == 0) sRed[1] = s;
+      }
+    }
+    __syncthreads();
+
+    if (!isPole) {
+      const T dx2 = T(2) * dxj;
+      const T dy2 = T(2) * dySj;
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
+        const int ip1 = wrp(i + 1, nx);
+        // Phi: zonal (x+1,x-1) -> (x+2N-1, x-2N+1), u at the midpoints
+        const T L1 = (su0[wrp(i + nj - 1, nx)] * sF[wrp(i + Mj, nx)] - su0[wrp(i - nj, nx)] * sF[wrp(i - Mj, nx)]) / dx2;
+        const T L2 = (svt0[i] * FA(j + 1, k, i) - svtm[i] * FA(j - 1, k, i)) / dy2;
+        C L3 = 0;
+        if (k + 1 < nz) L3 += sd0n[c] * (C)FA(j, k + 1, i);
+        if (k > 0) L3 -= sd0c[c] * (C)FA(j, k - 1, i);
+        L3 /= (2.0 * dsg);
+        const C TF = -((C)L1 + (C)L2 + L3);
+        A.oF[id] = (T)((C)A.bF[id] + A.ch * TF);
+        // U: same leap on U points with u averaged to integer points
+        const int pA = wrp(i + nj, nx), pB = wrp(i + 1 - nj, nx);
+        const T ubA = T(0.5) * (su0[wrp(pA - 1, nx)] + su0[pA]);
+        const T ubB = T(0.5) * (su0[wrp(pB - 1, nx)] + su0[pB]);
+        const T U1 = (ubA * sU[wrp(i + Mj, nx)] - ubB * sU[wrp(i - Mj, nx)]) / dx2;
+        const T vtn = T(0.5) * (svt0[i] + svt0[ip1]);
+        const T vts = T(0.5) * (svtm[i] + svtm[ip1]);
+        const T U2 = (vtn * UA(j + 1, k, i) - vts * UA(j - 1, k, i)) / dy2;
+        C U3 = 0;
+        if (k + 1 < nz) U3 += (C)(T(0.5) * (sSd[parn * nx + i] + sSd[parn * nx + ip1])) * (C)UA(j, k + 1, i);
+        if (k > 0) U3 -= (C)(T(0.5) * (sSd[par * nx + i] + sSd[par * nx + ip1])) * (C)UA(j, k - 1, i);
+        U3 /= (2.0 * dsg);
+        const C TU = -((C)U1 + (C)U2 + U3);
+        A.oU[id] = (T)((C)A.bU[id] + A.ch * TU);
+      }
+    } else {
+      const C sgn = (j == 0) ? 1.0 : -1.0;
+      const C L2 = sgn * cc * sRed[1];
+      C L3 = 0;
+      if (k + 1 < nz) L3 += sd0n[0] * (C)FA(j, k + 1, 0);
+      if (k > 0) L3 -= sd0c[0] * (C)FA(j, k - 1, 0);
+      L3 /= (2.0 * dsg);
+      const C TF = -(L2 + L3);
+      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i < nx) {
+          const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
+          A.oF[id] = val;
+          A.oU[id] = T(0);
+        }
+      }
+      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
+    }
+
+    if (hasV) {
+      const int Mv = g.Mv[j], nv = (Mv + 1) / 2;
+      const T dxv2 = (T)(2.0 * (double)Mv * g.a * g.sv[j] * g.dlam);
+      const T dyv2 = (T)(2.0 * g.a * g.sv[j] * g.dth);
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const size_t idv = (size_t)j * row3 + (size_t)k * nx + i;
+        const T L1 = (suv[wrp(i + nv - 1, nx)] * sV[wrp(i + Mv, nx)] - suv[wrp(i - nv, nx)] * sV[wrp(i - Mv, nx)]) / dxv2;
+        T L2 = T(0);
+        if (j + 1 < ny) {
+          const T vt1 = VA(j + 1, k, i) / PV1[c] * (T)g.sv[j + 1];
+          L2 += T(0.5) * (svt0[i] + vt1) * VA(j + 1, k, i);
+        }
+        if (j > 0) L2 -= T(0.5) * (svtm[i] + svt0[i]) * VA(j - 1, k, i);
+        L2 = L2 / dyv2;
+        C L3 = 0;
+        if (k + 1 < nz) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)VA(j, k + 1, i);
+        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)VA(j, k - 1, i);
+        L3 /= (2.0 * dsg);
+        const C TV = -((C)L1 + (C)L2 + L3);
+        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NI; ++c) { sd0c[c] = sd0n[c]; sd1c[c] = sd1n[c]; }
+    __syncthreads();
+  }
+
+  // p_s is not advected
+  if (!isPole) {
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) A.oP[(size_t)j * nx + i] = A.bP[(size_t)j * nx + i];
+    }
+  } else {
+    const T val = (T)A.pbase[pidx * (nz + 1) + nz];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) A.oP[(size_t)j * nx + i] = val;
+    }
+    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
+  }
+}
+
+template <typename T, int NI>
+__global__ void __launch_bounds__(1024) k_stage(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int j = xcd_row(blockIdx.x, a.g.ny + 1);
+  if (a.process == 0) adapt_row<T, NI>(a, j, smem);
+  else advect_row<T, NI>(a, j, smem);
+}
+
+// Persistent batched stage: work item w = (member, row); block b takes items b, b+G, ...
+template <typename T, int NI>
+__global__ void __launch_bounds__(1024) k_stage_batch(const StageArgs<T>* __restrict__ args,
+                                                     const int2* __restrict__ items, int nitems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const int2 it = items[w];
+    if (it.x < 0) continue;
+    const StageArgs<T> a = args[it.x];
+    if (a.process == 0) adapt_row<T, NI>(a, it.y, smem);
+    else if (a.process == 1) advect_row<T, NI>(a, it.y, smem);
+    __syncthreads();
+  }
+}
+
+// Pole means of Phi (per level) and p_s, FP64, one wavefront per value.
+template <typename T>
+__global__ void __launch_bounds__(64) k_pole_prep(int nx, int ny, int nz, const T* F, const T* ps, double* pole) {
+  const int v = blockIdx.x;          // 0 .. 2*(nz+1)-1
+  const int p = v / (nz + 1), k = v % (nz + 1);
+  const int j = (p == 0) ? 0 : ny;
+  const T* src = (k < nz) ? F + ((size_t)j * nz + k) * nx : ps + (size_t)j * nx;
+  C s = 0;
+  for (int i = threadIdx.x; i < nx; i += 64) s += (C)src[i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) pole[p * (nz + 1) + k] = s / (double)nx;
+}
+
+template <typename T>
+__global__ void k_copy(T* __restrict__ d, const T* __restrict__ s, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) d[i] = s[i];
+}
+template <typename T>
+__global__ void k_zero(T* __restrict__ d, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) d[i] = T(0);
+}
+
+// Global FP64 sums: per block partials of mass, energy (U^2+V^2+Phi^2 weighted), surface q^2.
+// Block r handles scalar row r (and V row r if r < ny); pole rows use their mean.
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag(GeoDev g, const T* U, const T* V, const T* F, const T* ps, double* part) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int j = blockIdx.x;
+  __shared__ double red[3][4];
+  const double a2 = g.a * g.a;
+  double m = 0, e = 0, es = 0;
+  const bool pole = (j == 0 || j == ny);
+  if (!pole) {
+    const double w = a2 * g.s[j] * g.dth * g.dlam;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      const double p = (double)ps[(size_t)j * nx + i];
+      m += w * p;
+      const double q = log(p / g.p0) + g.phis[(size_t)j * nx + i] / (g.rd * g.t0);
+      es += w * q * q;
+      for (int k = 0; k < nz; ++k) {
+        const size_t id = ((size_t)j * nz + k) * nx + i;
+        const double uu = (double)U[id], ff = (double)F[id];
+        e += w * g.dsig[k] * (uu * uu + ff * ff);
+      }
+    }
+  }
+  if (j < ny) {
+    const double w = a2 * g.sv[j] * g.dth * g.dlam;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x)
+      for (int k = 0; k < nz; ++k) {
+        const double vv = (double)V[((size_t)j * nz + k) * nx + i];
+        e += w * g.dsig[k] * vv * vv;
+      }
+  }
+  // wave partials then block partials in a fixed order
+  m = wave_sum(m); e = wave_sum(e); es = wave_sum(es);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  if (ln == 0) { red[0][wv] = m; red[1][wv] = e; red[2][wv] = es; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double M = 0, E = 0, ES = 0;
+    for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) { M += red[0][w2]; E += red[1][w2]; ES += red[2][w2]; }
+    if (pole) {
+      // pole contributions: cap area times the row mean
+      double pm = 0, qm;
+      for (int i = 0; i < nx; ++i) pm += (double)ps[(size_t)j * nx + i];
+      pm /= nx;
+      M = g.acap * pm;
+      qm = log(pm / g.p0) + g.phis[(size_t)j * nx] / (g.rd * g.t0);
+      ES = g.acap * qm * qm;
+      double ef = 0;
+      for (int k = 0; k < nz; ++k) {
+        double fm = 0;
+        for (int i = 0; i < nx; ++i) fm += (double)F[((size_t)j * nz + k) * nx + i];
+        fm /= nx;
+        ef += g.acap * g.dsig[k] * fm * fm;
+      }
+      E += ef;
+    }
+    part[3 * j + 0] = M;
+    part[3 * j + 1] = E;
+    part[3 * j + 2] = ES;
+  }
+}
+
+template <typename T>
+__global__ void k_nonfinite(const T* __restrict__ x, size_t n, unsigned long long* count) {
+  unsigned long long c = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const T v = x[i];
+    if (!(v == v) || v - v != T(0)) ++c;
+  }
+  if (c) atomicAdd(count, c);
+}
+
+// Dynamic LDS above 64 KB must be enabled per kernel (CDNA4 has 160 KB per CU).
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
+template <typename T, int NI>
+hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
+  const size_t lds = stage_lds_bytes(a.process, a.g.nx, sizeof(T));
+  hipError_t e = allow_lds(k_stage<T, NI>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_stage<T, NI>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int NI>
+hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
+                           int max_nx, hipStream_t s) {
+  const size_t lds = std::max(stage_lds_bytes(0, max_nx, sizeof(T)), stage_lds_bytes(1, max_nx, sizeof(T)));
+  hipError_t e = allow_lds(k_stage_batch<T, NI>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_stage_batch<T, NI>), dim3(grid), dim3(block), lds, s, d_args, d_items, nitems);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t stage_lds_bytes(int process, int nx, int elem) {
+  const size_t rows = (process == 0) ? 7 : 12;
+  return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 4 * sizeof(double);
+}
+
+int columns_per_thread(int nx, int block) { return (nx + block - 1) / block; }
+
+template <typename T>
+hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
+  switch (columns_per_thread(a.g.nx, block)) {
+    case 1: return launch_stage_ni<T, 1>(a, block, s);
+    case 2: return launch_stage_ni<T, 2>(a, block, s);
+    case 3: return launch_stage_ni<T, 3>(a, block, s);
+    case 4: return launch_stage_ni<T, 4>(a, block, s);
+    case 5: return launch_stage_ni<T, 5>(a, block, s);
+    case 6: return launch_stage_ni<T, 6>(a, block, s);
+    case 7: return launch_stage_ni<T, 7>(a, block, s);
+    case 8: return launch_stage_ni<T, 8>(a, block, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_stage_batch(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
+                              int max_nx, hipStream_t s) {
+  switch (columns_per_thread(max_nx, block)) {
+    case 1: return launch_batch_ni<T, 1>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 2: return launch_batch_ni<T, 2>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 3: return launch_batch_ni<T, 3>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 4: return launch_batch_ni<T, 4>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 5: return launch_batch_ni<T, 5>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 6: return launch_batch_ni<T, 6>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 7: return launch_batch_ni<T, 7>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 8: return launch_batch_ni<T, 8>(d_args, d_items, nitems, grid, block, max_nx, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_pole_prep(const GeoDev& g, const T* F, const T* ps, double* pole, hipStream_t s) {
+  hipLaunchKernelGGL((k_pole_prep<T>), dim3(2 * (g.nz + 1)), dim3(64), 0, s, g.nx, g.ny, g.nz, F, ps, pole);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diag(const GeoDev& g, const T* U, const T* V, const T* F, const T* ps, double* partial,
+                       int npartial, hipStream_t s) {
+  (void)npartial;
+  hipLaunchKernelGGL((k_diag<T>), dim3(g.ny + 1), dim3(256), 0, s, g, U, V, F, ps, partial);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_nonfinite(const T* x, size_t n, unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL((k_nonfinite<T>), dim3(1024), dim3(256), 0, s, x, n, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpy_fill(T* dst, const T* src, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy<T>), dim3(2048), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero(T* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero<T>), dim3(2048), dim3(256), 0, s, dst, n);
+  return hipGetLastError();
+}
+
+#define DYC_INST(T)                                                                                          \
+  template hipError_t launch_stage<T>(const StageArgs<T>&, int, hipStream_t);                                \
+  template hipError_t launch_stage_batch<T>(const StageArgs<T>*, const int2*, int, int, int, int, hipStream_t); \
+  template hipError_t launch_pole_prep<T>(const GeoDev&, const T*, const T*, double*, hipStream_t);          \
+  template hipError_t launch_diag<T>(const GeoDev&, const T*, const T*, const T*, const T*, double*, int,    \
+                                     hipStream_t);                                                           \
+  template hipError_t launch_nonfinite<T>(const T*, size_t, unsigned long long*, hipStream_t);               \
+  template hipError_t launch_axpy_fill<T>(T*, const T*, size_t, hipStream_t);                                \
+  template hipError_t launch_zero<T>(T*, size_t, hipStream_t);
+DYC_INST(float)
+DYC_INST(double)
+template hipError_t launch_zero<unsigned long long>(unsigned long long*, size_t, hipStream_t);
+
+}  // namespace dyc
