@@ -78,6 +78,12 @@ int dycore_destroy(dycore_t h);
  * advection with dt).  nsteps >= 0. */
 int dycore_step(dycore_t h, void* U, void* V, void* Phi, void* ps, int nsteps, void* stream);
 
+/* n_rk RK3 steps of one process alone (0 adaptation, 1 advection) with step
+ * hstep, in place: the 3 stage launches per RK step are those of dycore_step.
+ * Used to integrate or time one process of the split on its own. */
+int dycore_process_run(dycore_t h, int process, int n_rk, double hstep, void* U, void* V, void* Phi, void* ps,
+                       void* stream);
+
 /* One stage: out = base + ch * T(in), T the adaptation (process 0) or advection
  * (process 1) tendency of eq. 2; pole rows of out hold the base row mean plus
  * ch times the pole tendency, U pole rows 0.  out may alias base (not in). */

@@ -41,6 +41,7 @@ def _load():
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_substeps.restype = ctypes.c_int
         L.orc_substeps.argtypes = [ctypes.c_void_p, ctypes.c_double]
         _lib = L
@@ -200,6 +201,10 @@ class Oracle:
         S = np.zeros(self.nz + 1); psd = np.zeros(self.nz + 1)
         self.L.orc_scan_alg2(self._vh(), _p(D), ctypes.c_int(nblocks), _p(S), _p(psd))
         return S, psd
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
 
 
 def dot(a: dict, b: dict) -> float:

@@ -29,6 +29,9 @@
 #include <cstdlib>
 #include <vector>
 #include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 using cplx = std::complex<double>;
 
@@ -1133,6 +1136,15 @@ void* orc_create(int nx, int ny, int nz, const double* sigma_half, const double*
 }
 
 void orc_destroy(void* h) { delete static_cast<Geo*>(h); }
+
+// Threads the OpenMP loops of the forward map use (the adjoint sweep is serial).
+int orc_num_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // Physical constants in use: a, Omega, g, R, c_p, p0, T0, kappa, b, A_cap
 void orc_constants(void* h, double* out) {

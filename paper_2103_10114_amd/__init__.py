@@ -47,6 +47,7 @@ def lib():
         L.dycore_destroy.argtypes = [vp]
         L.dycore_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
         L.dycore_stage.argtypes = [vp, ctypes.c_int, ctypes.c_double] + [vp] * 12 + [vp]
+        L.dycore_process_run.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double] + [vp] * 4 + [vp]
         L.dycore_step_adjoint.argtypes = [vp] + [vp] * 8 + [vp]
         L.dycore_stage_adjoint.argtypes = [vp, ctypes.c_int, ctypes.c_double] + [vp] * 16 + [vp]
         L.dycore_diagnostics.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
@@ -161,6 +162,12 @@ class Dycore:
     def step(self, st, nsteps=1):
         """Advance the fields of st in place by nsteps outer steps."""
         _check(lib().dycore_step(self.h, *self._p(st), int(nsteps), _stream()))
+        return st
+
+    def process_run(self, st, process, n_rk, hstep):
+        """n_rk RK3 steps of one process alone, in place (same stage kernels as step)."""
+        proc = 0 if process in (0, "A") else 1
+        _check(lib().dycore_process_run(self.h, proc, int(n_rk), float(hstep), *self._p(st), _stream()))
         return st
 
     def stage(self, process, ch, base, inp, out):

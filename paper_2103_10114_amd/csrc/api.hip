@@ -95,13 +95,14 @@ int leap_span(double sin_theta, double dlam, int nx) {
   return std::min(m, cap);
 }
 
+// Threads per row workgroup: one column per thread up to 1024 columns, else the fewest
+// columns per thread (each thread keeps its columns' FP64 sums in registers).
 int default_block(int nx, int prec) {
   (void)prec;
-  // one column per thread up to 256 threads, then several columns per thread
-  if (nx <= 64) return 64;
-  if (nx <= 128) return 128;
-  if (nx <= 256) return 256;
-  return 256;
+  if (nx <= 768) return std::max(64, (nx + 63) / 64 * 64);
+  if (nx <= 1536) return ((nx + 1) / 2 + 63) / 64 * 64;
+  const int ni = (nx + 511) / 512;
+  return ((nx + ni - 1) / ni + 63) / 64 * 64;
 }
 
 template <typename T>
@@ -173,6 +174,32 @@ int step_impl(dycore_s* h, T* U, T* V, T* F, T* P, int nsteps, hipStream_t s) {
   return DYCORE_OK;
 }
 
+// n_rk RK3 steps of one process with step hstep (the 3 stage launches of each
+// exactly as in an outer step, pole slots 0 -> ... -> 0).
+template <typename T>
+int process_run_impl(dycore_s* h, int process, int n_rk, double hstep, T* U, T* V, T* F, T* P, hipStream_t s) {
+  if (n_rk == 0) return DYCORE_OK;
+  hipError_t e = launch_pole_prep<T>(h->g, F, P, pole_slot(h, 0), s);
+  if (e != hipSuccess) return DYCORE_EHIP;
+  Packed<T> y1 = unpack<T>(h, h->scratch);
+  Packed<T> y2 = unpack<T>(h, static_cast<char*>(h->scratch) + h->state_bytes);
+  int b = 0;   // base pole slot alternates between 0 and 3
+  for (int n = 0; n < n_rk; ++n) {
+    const int nb = (b == 0) ? 3 : 0;
+    e = launch_stage<T>(make_args<T>(h, process, hstep / 3.0, U, V, F, P, U, V, F, P, y1.U, y1.V, y1.F, y1.P,
+                                     pole_slot(h, b), pole_slot(h, b), pole_slot(h, 1)), h->block, s);
+    if (e == hipSuccess)
+      e = launch_stage<T>(make_args<T>(h, process, hstep / 2.0, y1.U, y1.V, y1.F, y1.P, U, V, F, P, y2.U, y2.V,
+                                       y2.F, y2.P, pole_slot(h, 1), pole_slot(h, b), pole_slot(h, 2)), h->block, s);
+    if (e == hipSuccess)
+      e = launch_stage<T>(make_args<T>(h, process, hstep, y2.U, y2.V, y2.F, y2.P, U, V, F, P, U, V, F, P,
+                                       pole_slot(h, 2), pole_slot(h, b), pole_slot(h, nb)), h->block, s);
+    if (e != hipSuccess) return DYCORE_EHIP;
+    b = nb;
+  }
+  return DYCORE_OK;
+}
+
 template <typename T>
 int stage_impl(dycore_s* h, int process, double ch, const T* bU, const T* bV, const T* bF, const T* bP,
                const T* U, const T* V, const T* F, const T* P, T* oU, T* oV, T* oF, T* oP, hipStream_t s) {
@@ -225,7 +252,10 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   h->nx = cfg->nx; h->ny = cfg->ny; h->nz = cfg->nz; h->prec = cfg->prec; h->dt = cfg->dt; h->flags = cfg->flags;
   h->elem = (h->prec == DYCORE_FP32) ? 4 : 8;
   h->block = cfg->block ? cfg->block : default_block(h->nx, h->prec);
-  if (columns_per_thread(h->nx, h->block) > 8) { delete h; return DYCORE_EUNSUPPORTED; }
+  if (columns_per_thread(h->nx, h->block) > 8 || !max_block_for(h->nx, h->block)) {
+    delete h;
+    return DYCORE_EUNSUPPORTED;
+  }
   const size_t lds = std::max(stage_lds_bytes(0, h->nx, (int)h->elem), stage_lds_bytes(1, h->nx, (int)h->elem));
   if (lds > 160 * 1024) { delete h; return DYCORE_EUNSUPPORTED; }
   (void)hipGetDevice(&h->device);
@@ -357,6 +387,17 @@ int dycore_step(dycore_t h, void* U, void* V, void* Phi, void* ps, int nsteps, v
   if (h->prec == DYCORE_FP32)
     return step_impl<float>(h, (float*)U, (float*)V, (float*)Phi, (float*)ps, nsteps, s);
   return step_impl<double>(h, (double*)U, (double*)V, (double*)Phi, (double*)ps, nsteps, s);
+}
+
+int dycore_process_run(dycore_t h, int process, int n_rk, double hstep, void* U, void* V, void* Phi, void* ps,
+                       void* stream) {
+  if (!h || (process != 0 && process != 1) || n_rk < 0 || !(hstep > 0.0)) return DYCORE_EINVAL;
+  if (!U || !V || !Phi || !ps || !aligned16(U) || !aligned16(V) || !aligned16(Phi) || !aligned16(ps))
+    return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->prec == DYCORE_FP32)
+    return process_run_impl<float>(h, process, n_rk, hstep, (float*)U, (float*)V, (float*)Phi, (float*)ps, s);
+  return process_run_impl<double>(h, process, n_rk, hstep, (double*)U, (double*)V, (double*)Phi, (double*)ps, s);
 }
 
 int dycore_stage(dycore_t h, int process, double ch, const void* bU, const void* bV, const void* bPhi,
@@ -554,7 +595,7 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
   }
   if (block == 0) block = 256;
   if (block < 64 || block > 1024 || block % 64) return DYCORE_EINVAL;
-  if (columns_per_thread(max_nx, block) > 8) return DYCORE_EUNSUPPORTED;
+  if (columns_per_thread(max_nx, block) > 8 || !max_block_for(max_nx, block)) return DYCORE_EUNSUPPORTED;
   const size_t elem = prec == DYCORE_FP32 ? 4 : 8;
   if (std::max(stage_lds_bytes(0, max_nx, (int)elem), stage_lds_bytes(1, max_nx, (int)elem)) > 160 * 1024)
     return DYCORE_EUNSUPPORTED;

@@ -85,6 +85,7 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s);
 
 size_t stage_lds_bytes(int process, int nx, int elem);
 int columns_per_thread(int nx, int block);
+int max_block_for(int nx, int block);   // 1 if `block` threads are allowed for rows of nx columns
 
 // XCD-aware row order: workgroups are dispatched round-robin over the 8 XCDs,
 // so block b lands on XCD b % 8.  Give each XCD a contiguous band of rows, in

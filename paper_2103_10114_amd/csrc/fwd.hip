@@ -34,22 +34,39 @@ __device__ __forceinline__ double wave_sum(double acc) {
 
 using C = double;
 
+}  // namespace
+
+// Largest workgroup per columns-per-thread: bounds the VGPR budget so that the FP64 column
+// sums and one level's loads of every owned column stay in registers (768 threads: 170 VGPRs).
+constexpr int max_block(int ni) { return ni <= 2 ? 768 : 512; }
+int max_block_for(int nx, int block) { return block <= max_block(columns_per_thread(nx, block)) ? 1 : 0; }
+
+namespace {
+
 // ----------------------------------------------------------------------------------------------
 // Adaptation: out = base + ch * A(in)
 // ----------------------------------------------------------------------------------------------
+// LDS: 2D rows P, l (rows j-1, j, j+1), q (rows j, j+1), leaped d+l and d+q on the U points of
+// row j, and per level the leaped rows phi' and MU of row j.  Only the FP64 column sums live in
+// registers across levels.
 template <typename T, int NI>
 __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
   const GeoDev& g = A.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int B = blockDim.x, t = threadIdx.x;
-  T* sP0 = reinterpret_cast<T*>(smem);
+  T* sPm = reinterpret_cast<T*>(smem);
+  T* sP0 = sPm + nx;
   T* sP1 = sP0 + nx;
-  T* sDl = sP1 + nx;
-  T* sPhi = sDl + nx;
+  T* sLm = sP1 + nx;
+  T* sL0 = sLm + nx;
+  T* sL1 = sL0 + nx;
+  T* sQ0 = sL1 + nx;
+  T* sQ1 = sQ0 + nx;
+  T* sDl = sQ1 + nx;
+  T* sDq = sDl + nx;
+  T* sPhi = sDq + nx;
   T* sMU = sPhi + nx;
-  T* sL = sMU + nx;
-  T* sQ = sL + nx;
-  double* sRed = reinterpret_cast<double*>(smem + ((7 * nx * sizeof(T) + 15) & ~size_t(15)));
+  double* sRed = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));
 
   const bool isPole = (j == 0 || j == ny);
   const bool hasV = (j < ny);
@@ -74,114 +91,101 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
   };
   auto VA = [&](int jv, int k, int i) -> T { return A.inV[(size_t)jv * row3 + (size_t)k * nx + i]; };
 
-  // adjacent scalar row of a pole workgroup
-  const int ja = (j == 0) ? 1 : ny - 1;
-
-  // ---- 2D set-up: P rows j and j+1 (or the row next to the pole), l and q of row j
+  // ---- 2D rows
   for (int c = 0; c < NI; ++c) {
     const int i = t + c * B;
     if (i < nx) {
-      const T psj = psA(j, i);
-      sP0[i] = tsqrt<T>(psj / p0);
-      const T lj = tlog<T>(psj / p0);
-      if (isPole) {
-        const T psa = psA(ja, i);
-        sP1[i] = tsqrt<T>(psa / p0);
-        sL[i] = tlog<T>(psa / p0);       // l of the adjacent row (pole reductions)
-        sQ[i] = lj;                      // pole l (replicated)
-      } else {
-        sL[i] = lj;
-        sQ[i] = lj + (T)g.phis[(size_t)j * nx + i] / RT0;
-        sP1[i] = tsqrt<T>(psA(j + 1, i) / p0);
+      const T ps0 = psA(j, i);
+      sP0[i] = tsqrt<T>(ps0 / p0);
+      sL0[i] = tlog<T>(ps0 / p0);
+      sQ0[i] = sL0[i] + (T)g.phis[(size_t)j * nx + i] / RT0;
+      if (j < ny) {
+        const T ps1 = psA(j + 1, i);
+        sP1[i] = tsqrt<T>(ps1 / p0);
+        sL1[i] = tlog<T>(ps1 / p0);
+        sQ1[i] = sL1[i] + (T)g.phis[(size_t)(j + 1) * nx + i] / RT0;
+      }
+      if (j > 0) {
+        const T psm = psA(j - 1, i);
+        sPm[i] = tsqrt<T>(psm / p0);
+        sLm[i] = tlog<T>(psm / p0);
       }
     }
   }
   __syncthreads();
-
-  T P0c[NI], P1c[NI], Pmc[NI], l0c[NI], l1c[NI], lmc[NI], q0c[NI], q1c[NI];
-  T PU0c[NI], PV0c[NI], PVmc[NI], dqc[NI];
-  C H0c[NI], H1c[NI], R0c[NI], R1c[NI], Sc[NI];
   const int Mj = isPole ? 1 : g.M[j];
   const int nj = (Mj + 1) / 2;
   const T dxj = isPole ? T(1) : (T)((double)Mj * g.a * g.s[j] * g.dlam);
-#pragma unroll
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    H0c[c] = 0; H1c[c] = 0; R0c[c] = 0; R1c[c] = 0; Sc[c] = 0;
-    P0c[c] = P1c[c] = Pmc[c] = l0c[c] = l1c[c] = lmc[c] = q0c[c] = q1c[c] = T(0);
-    PU0c[c] = PV0c[c] = PVmc[c] = dqc[c] = T(1);
-    if (i < nx) {
-      P0c[c] = sP0[i];
-      if (isPole) {
-        l0c[c] = sQ[i];
-        q0c[c] = l0c[c] + (T)g.phis[(size_t)j * nx + i] / RT0;
-      } else {
-        l0c[c] = sL[i];
-        q0c[c] = sQ[i];
-      }
-      if (hasV) {
-        P1c[c] = sP1[i];
-        const T ps1 = psA(j + 1, i);
-        l1c[c] = tlog<T>(ps1 / p0);
-        q1c[c] = l1c[c] + (T)g.phis[(size_t)(j + 1) * nx + i] / RT0;
-        PV0c[c] = T(0.5) * (P0c[c] + P1c[c]);
-      }
-      if (j >= 1) {
-        const T psm = psA(j - 1, i);
-        Pmc[c] = tsqrt<T>(psm / p0);
-        lmc[c] = tlog<T>(psm / p0);
-        PVmc[c] = T(0.5) * (Pmc[c] + P0c[c]);
-      }
-      if (!isPole) {
-        const T dl = (sL[wrp(i + nj, nx)] - sL[wrp(i + 1 - nj, nx)]) / dxj;
-        dqc[c] = (sQ[wrp(i + nj, nx)] - sQ[wrp(i + 1 - nj, nx)]) / dxj;
-        sDl[i] = dl;
-        PU0c[c] = T(0.5) * (sP0[i] + sP0[wrp(i + 1, nx)]);
+  if (!isPole) {
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) {
+        sDl[i] = (sL0[wrp(i + nj, nx)] - sL0[wrp(i + 1 - nj, nx)]) / dxj;
+        sDq[i] = (sQ0[wrp(i + nj, nx)] - sQ0[wrp(i + 1 - nj, nx)]) / dxj;
       }
     }
   }
   __syncthreads();
 
+  C H0c[NI], H1c[NI], R0c[NI], R1c[NI], Sc[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) { H0c[c] = 0; H1c[c] = 0; R0c[c] = 0; R1c[c] = 0; Sc[c] = 0; }
+
   // ---- pass A: column totals H = sum_{l>=1} cl_l RT'_l (FP64) for phi' = H - R_k + cpk_k RT'_k
-  if (j < ny) {
+  if (hasV) {
     for (int k = 0; k < nz; ++k) {
       const C clk = g.cl[k];
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i < nx) {
-          H0c[c] += clk * (C)(b * FA(j, k, i) / P0c[c]);
-          H1c[c] += clk * (C)(b * FA(j + 1, k, i) / P1c[c]);
+          H0c[c] += clk * (C)(b * FA(j, k, i) / sP0[i]);
+          H1c[c] += clk * (C)(b * FA(j + 1, k, i) / sP1[i]);
         }
       }
     }
   }
 
   // ---- pass B: top to bottom
-  C Sp = 0;   // pole prefix sum (pole workgroups)
+  C Sp = 0;
   for (int k = 0; k < nz; ++k) {
     const C clk = g.cl[k], cpk = g.cpk[k];
     const C dsg = g.dsig[k], sgk = g.sig[k];
-    T Fj[NI], RTj[NI], phij[NI], Uj[NI], RTj1[NI], phij1[NI];
+    // phase 1: every global load of this level, phi' and MU into LDS
+    T Fj[NI], Fp[NI], RTj[NI], RTj1[NI], phij[NI], phij1[NI], Uj[NI], Ujm[NI], U1[NI], U1m[NI];
+    T Vn[NI], Vnp[NI], Vs[NI], Vsp[NI], bF[NI], bU[NI], bV[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
-      Fj[c] = RTj[c] = phij[c] = Uj[c] = RTj1[c] = phij1[c] = T(0);
+      Fj[c] = Fp[c] = RTj[c] = RTj1[c] = phij[c] = phij1[c] = Uj[c] = Ujm[c] = U1[c] = U1m[c] = T(0);
+      Vn[c] = Vnp[c] = Vs[c] = Vsp[c] = bF[c] = bU[c] = bV[c] = T(0);
       if (i < nx) {
+        const int ip1 = wrp(i + 1, nx), im1 = wrp(i - 1, nx);
+        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
         Fj[c] = FA(j, k, i);
-        RTj[c] = b * Fj[c] / P0c[c];
+        RTj[c] = b * Fj[c] / sP0[i];
         if (hasV) {
           R0c[c] += clk * (C)RTj[c];
           phij[c] = (T)(H0c[c] - R0c[c] + cpk * (C)RTj[c]);
-          const T F1 = FA(j + 1, k, i);
-          RTj1[c] = b * F1 / P1c[c];
+          RTj1[c] = b * FA(j + 1, k, i) / sP1[i];
           R1c[c] += clk * (C)RTj1[c];
           phij1[c] = (T)(H1c[c] - R1c[c] + cpk * (C)RTj1[c]);
+          U1[c] = UA(j + 1, k, i);
+          U1m[c] = UA(j + 1, k, im1);
+          bV[c] = A.bV[id];
         }
         if (!isPole) {
-          sPhi[i] = phij[c];
+          Fp[c] = FA(j, k, ip1);
           Uj[c] = UA(j, k, i);
-          sMU[i] = PU0c[c] * Uj[c];
+          Ujm[c] = UA(j, k, im1);
+          Vn[c] = VA(j, k, i);
+          Vnp[c] = VA(j, k, ip1);
+          Vs[c] = VA(j - 1, k, i);
+          Vsp[c] = VA(j - 1, k, ip1);
+          bF[c] = A.bF[id];
+          bU[c] = A.bU[id];
+          sPhi[i] = phij[c];
+          sMU[i] = T(0.5) * (sP0[i] + sP0[ip1]) * Uj[c];
         }
       }
     }
@@ -197,46 +201,49 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
+        const int ip1 = wrp(i + 1, nx), im1 = wrp(i - 1, nx);
         const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
-        const T Vn = VA(j, k, i), Vs = VA(j - 1, k, i);
+        const T PU = T(0.5) * (sP0[i] + sP0[ip1]);
+        const T PUm = T(0.5) * (sP0[im1] + sP0[i]);
+        const T PV0 = T(0.5) * (sP0[i] + sP1[i]);
+        const T PVm = T(0.5) * (sPm[i] + sP0[i]);
         // divergence of the mass flux: leaped (x,x-1) -> (x+N-1, x-N) plus meridional
         const T D = (sMU[wrp(i + nj - 1, nx)] - sMU[wrp(i - nj, nx)]) / dxj +
-                    (svj * (PV0c[c] * Vn) - svm * (PVmc[c] * Vs)) / dyS;
+                    (svj * (PV0 * Vn[c]) - svm * (PVm * Vs[c])) / dyS;
         const C Sk = Sc[c];
         Sc[c] += (C)D * dsg;
         // v . grad(l)
-        const int im1 = wrp(i - 1, nx);
-        const T u_i = Uj[c] / PU0c[c];
-        const T PUm = T(0.5) * (sP0[im1] + sP0[i]);
-        const T u_m = UA(j, k, im1) / PUm;
+        const T u_i = Uj[c] / PU;
+        const T u_m = Ujm[c] / PUm;
         const T zon = T(0.5) * (u_i * sDl[i] + u_m * sDl[im1]);
-        const T mer = T(0.5) * ((Vn / PV0c[c]) * (l1c[c] - l0c[c]) + (Vs / PVmc[c]) * (l0c[c] - lmc[c])) / dyA;
-        const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) / (sgk * (C)P0c[c] * (C)P0c[c]);
-        const C TF = ((C)(b * P0c[c]) + (C)(kap * Fj[c])) * wp;
-        A.oF[id] = (T)((C)A.bF[id] + A.ch * TF);
+        const T mer = T(0.5) * ((Vn[c] / PV0) * (sL1[i] - sL0[i]) + (Vs[c] / PVm) * (sL0[i] - sLm[i])) / dyA;
+        const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) / (sgk * (C)sP0[i] * (C)sP0[i]);
+        const C TF = ((C)(b * sP0[i]) + (C)(kap * Fj[c])) * wp;
+        A.oF[id] = (T)((C)bF[c] + A.ch * TF);
         // U at i+1/2: pressure gradient with leap (x+1,x) -> (x+N, x-N+1) and Coriolis
-        const int ip1 = wrp(i + 1, nx);
         const T dphi = (sPhi[wrp(i + nj, nx)] - sPhi[wrp(i + 1 - nj, nx)]) / dxj;
-        const T RTp = b * FA(j, k, ip1) / sP0[ip1];
+        const T RTp = b * Fp[c] / sP0[ip1];
         const T rtx = T(0.5) * (RTj[c] + RTp);
-        const C pgf = (C)dphi + RT0c * (C)dqc[c] + (C)rtx * (C)sDl[i];
-        const T VV = T(0.25) * (Vn + VA(j, k, ip1) + Vs + VA(j - 1, k, ip1));
+        const C pgf = (C)dphi + RT0c * (C)sDq[i] + (C)rtx * (C)sDl[i];
+        const T VV = T(0.25) * (Vn[c] + Vnp[c] + Vs[c] + Vsp[c]);
         const T fs = fj + u_i * cota;
-        const C TU = -(C)PU0c[c] * pgf - (C)fs * (C)VV;
-        A.oU[id] = (T)((C)A.bU[id] + A.ch * TU);
+        const C TU = -(C)PU * pgf - (C)fs * (C)VV;
+        A.oU[id] = (T)((C)bU[c] + A.ch * TU);
       }
     } else {
       // pole column: cap divergence and zonal-mean v.grad(l) from the adjacent V row
       const int jva = (j == 0) ? 0 : ny - 1;
-      const T Pp = P0c[0];
-      const T lp = l0c[0];
+      const T* sPa = (j == 0) ? sP1 : sPm;
+      const T* sLa = (j == 0) ? sL1 : sLm;
+      const T Pp = sP0[0];
+      const T lp = sL0[0];
       if (t < 64) {
         C s1 = 0, s2 = 0;
         for (int i = t; i < nx; i += 64) {
-          const T pv = T(0.5) * (Pp + sP1[i]);
+          const T pv = T(0.5) * (Pp + sPa[i]);
           const T vv = VA(jva, k, i);
           s1 += (C)(pv * vv);
-          s2 += (C)((vv / pv) * (j == 0 ? (sL[i] - lp) : (lp - sL[i])));
+          s2 += (C)((vv / pv) * (j == 0 ? (sLa[i] - lp) : (lp - sLa[i])));
         }
         s1 = wave_sum(s1);
         s2 = wave_sum(s2);
@@ -249,7 +256,8 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
       const C Sk = Sp;
       Sp += Dp * dsg;
       const C wp = vglp - (Sk + 0.5 * Dp * dsg) / (sgk * (C)Pp * (C)Pp);
-      const C TF = ((C)(b * Pp) + (C)((T)g.kappa * Fj[0])) * wp;
+      const T Fpole = FA(j, k, 0);
+      const C TF = ((C)(b * Pp) + (C)((T)g.kappa * Fpole)) * wp;
       const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
@@ -270,21 +278,20 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
+        const int ip1 = wrp(i + 1, nx), im1 = wrp(i - 1, nx);
         const size_t idv = (size_t)j * row3 + (size_t)k * nx + i;
-        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)(q1c[c] - q0c[c]) +
-                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)(l1c[c] - l0c[c])) / (C)dyA;
-        const int im1 = wrp(i - 1, nx), ip1 = wrp(i + 1, nx);
-        const T U0i = UA(j, k, i), U0m = UA(j, k, im1);
-        const T U1i = UA(j + 1, k, i), U1m = UA(j + 1, k, im1);
-        const T u0i = U0i / (T(0.5) * (sP0[i] + sP0[ip1]));
-        const T u0m = U0m / (T(0.5) * (sP0[im1] + sP0[i]));
-        const T u1i = U1i / (T(0.5) * (sP1[i] + sP1[ip1]));
-        const T u1m = U1m / (T(0.5) * (sP1[im1] + sP1[i]));
-        const T UU = T(0.25) * (U0m + U0i + U1m + U1i);
+        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)(sQ1[i] - sQ0[i]) +
+                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)(sL1[i] - sL0[i])) / (C)dyA;
+        const T u0i = Uj[c] / (T(0.5) * (sP0[i] + sP0[ip1]));
+        const T u0m = Ujm[c] / (T(0.5) * (sP0[im1] + sP0[i]));
+        const T u1i = U1[c] / (T(0.5) * (sP1[i] + sP1[ip1]));
+        const T u1m = U1m[c] / (T(0.5) * (sP1[im1] + sP1[i]));
+        const T UU = T(0.25) * (Ujm[c] + Uj[c] + U1m[c] + U1[c]);
         const T uu = T(0.25) * (u0m + u0i + u1m + u1i);
         const T fs = fvj + uu * cotva;
-        const C TV = -(C)PV0c[c] * pgf + (C)fs * (C)UU;
-        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
+        const T PV0 = T(0.5) * (sP0[i] + sP1[i]);
+        const C TV = -(C)PV0 * pgf + (C)fs * (C)UU;
+        A.oV[idv] = (T)((C)bV[c] + A.ch * TV);
       }
     }
     __syncthreads();
@@ -314,23 +321,26 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
 // ----------------------------------------------------------------------------------------------
 // Advection: out = base - ch * L(in), L in the IAP skew form, zonal part leaped
 // ----------------------------------------------------------------------------------------------
+// LDS: P rows j-1..j+2; per level the rows MU(j+1), Phi(j), U(j), V(j+1/2), u on the V row,
+// v sin(theta) on V rows j-1/2 and j+1/2, and sigma-dot of row j at two half levels.
 template <typename T, int NI>
 __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
   const GeoDev& g = A.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int B = blockDim.x, t = threadIdx.x;
-  T* sP0 = reinterpret_cast<T*>(smem);   // P row j (pole WG: pole P)
-  T* sP1 = sP0 + nx;                      // P row j+1 (south pole WG: row ny-1)
-  T* sMU1 = sP1 + nx;                     // MU row j+1 at level k
-  T* su0 = sMU1 + nx;                     // u row j
-  T* suv = su0 + nx;                      // u averaged to the V row j+1/2
-  T* sF = suv + nx;                       // Phi row j
-  T* sU = sF + nx;                        // U row j
-  T* sV = sU + nx;                        // V row j
-  T* svtm = sV + nx;                      // v sin(theta) on V row j-1
-  T* svt0 = svtm + nx;                    // v sin(theta) on V row j
-  T* sSd = svt0 + nx;                     // sigma-dot row j at two half levels [2][nx]
-  double* sRed = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));
+  T* sPm = reinterpret_cast<T*>(smem);    // P row j-1 (north pole WG: unused)
+  T* sP0 = sPm + nx;                       // P row j
+  T* sP1 = sP0 + nx;                       // P row j+1 (south pole WG: row ny-1)
+  T* sP2 = sP1 + nx;                       // P row j+2
+  T* sMU1 = sP2 + nx;                      // MU row j+1 at level k
+  T* suv = sMU1 + nx;                      // u averaged to V row j+1/2
+  T* sF = suv + nx;                        // Phi row j
+  T* sU = sF + nx;                         // U row j
+  T* sV = sU + nx;                         // V row j
+  T* svtm = sV + nx;                       // v sin(theta) on V row j-1
+  T* svt0 = svtm + nx;                     // v sin(theta) on V row j
+  T* sSd = svt0 + nx;                      // sigma-dot row j at two half levels [2][nx]
+  double* sRed = reinterpret_cast<double*>(smem + ((13 * nx * sizeof(T) + 15) & ~size_t(15)));
 
   const bool isPole = (j == 0 || j == ny);
   const bool hasV = (j < ny);
@@ -361,35 +371,14 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
     const int i = t + c * B;
     if (i < nx) {
       sP0[i] = tsqrt<T>(psA(j, i) / p0);
-      if (hasV) sP1[i] = tsqrt<T>(psA(j + 1, i) / p0);
-      else sP1[i] = tsqrt<T>(psA(ja, i) / p0);
+      sP1[i] = tsqrt<T>(psA(hasV ? j + 1 : ja, i) / p0);
+      if (j >= 1) sPm[i] = tsqrt<T>(psA(j - 1, i) / p0);
+      if (j + 2 <= ny) sP2[i] = tsqrt<T>(psA(j + 2, i) / p0);
       sSd[i] = T(0);
       sSd[nx + i] = T(0);
     }
   }
   __syncthreads();
-
-  T P0c[NI], P1c[NI], PU0c[NI], PU1c[NI], PVm[NI], PV0[NI], PV1[NI];
-  C Pi0[NI], Pi1[NI], S0[NI], S1[NI], sd0c[NI], sd1c[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    P0c[c] = P1c[c] = T(1);
-    PU0c[c] = PU1c[c] = PVm[c] = PV0[c] = PV1[c] = T(1);
-    Pi0[c] = Pi1[c] = S0[c] = S1[c] = sd0c[c] = sd1c[c] = 0;
-    if (i < nx) {
-      const int ip1 = wrp(i + 1, nx);
-      P0c[c] = sP0[i];
-      if (hasV) {
-        P1c[c] = sP1[i];
-        PV0[c] = T(0.5) * (P0c[c] + P1c[c]);
-      }
-      if (j >= 1) PVm[c] = T(0.5) * (tsqrt<T>(psA(j - 1, i) / p0) + P0c[c]);
-      if (j + 2 <= ny) PV1[c] = T(0.5) * (P1c[c] + tsqrt<T>(psA(j + 2, i) / p0));
-      if (!isPole) PU0c[c] = T(0.5) * (sP0[i] + sP0[ip1]);
-      if (j1Int) PU1c[c] = T(0.5) * (sP1[i] + sP1[ip1]);
-    }
-  }
 
   const int Mj = isPole ? 1 : g.M[j], nj = (Mj + 1) / 2;
   const int Mj1 = j1Int ? g.M[j + 1] : 1, nj1 = (Mj1 + 1) / 2;
@@ -397,21 +386,24 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
   const T dxj1 = j1Int ? (T)((double)Mj1 * g.a * g.s[j + 1] * g.dlam) : T(1);
   const T dySj = isPole ? T(1) : (T)(g.a * g.s[j] * g.dth);
   const T dySj1 = j1Int ? (T)(g.a * g.s[j + 1] * g.dth) : T(1);
+  auto PU0 = [&](int p) -> T { return T(0.5) * (sP0[p] + sP0[wrp(p + 1, nx)]); };
+  auto PU1 = [&](int p) -> T { return T(0.5) * (sP1[p] + sP1[wrp(p + 1, nx)]); };
 
-  // divergence of rows j and j+1 at level k (phase 2 of both passes); MU row j+1 is in LDS,
-  // MU row j is formed from U row j (in LDS) and P row j.
-  auto div_rows = [&](int k, C* D0, C* D1) {
-    // pole rows via FP64 cap sums by wavefront 0
-    const bool needPole0 = isPole;
-    const bool needPole1 = hasV && j1Pole;
-    if (needPole0 || needPole1) {
+  C Pi0[NI], Pi1[NI], S0[NI], S1[NI], sd0c[NI], sd1c[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) { Pi0[c] = Pi1[c] = S0[c] = S1[c] = sd0c[c] = sd1c[c] = 0; }
+
+  // divergence of rows j and j+1 at level k from the LDS rows sU (row j) and sMU1 (row j+1) and the
+  // V values Vj (row j), Vm (row j-1), V1 (row j+1) of the own column.
+  auto div_rows = [&](int k, const T* Vj, const T* Vm, const T* V1, C* D0, C* D1) {
+    const bool needPole = isPole || (hasV && j1Pole);
+    if (needPole) {
       if (t < 64) {
         C s = 0;
         const int jv = (j == 0) ? 0 : ny - 1;
         for (int i = t; i < nx; i += 64) {
-          // V row adjacent to the pole: for j == 0 it is V row 0 (P rows 0,1 = sP0,sP1);
-          // for j == ny it is V row ny-1 (sP0 pole, sP1 row ny-1); for j == ny-1 it is V row ny-1
-          // (sP0 row ny-1, sP1 pole).
+          // the V row next to the pole with P of its two scalar rows: for j == 0 rows 0,1 (sP0,sP1);
+          // j == ny: pole, ny-1 (sP0,sP1); j == ny-1: ny-1, pole (sP0,sP1)
           const T pv = T(0.5) * (sP0[i] + sP1[i]);
           s += (C)(pv * VA(jv, k, i));
         }
@@ -430,10 +422,10 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
         const C sgn = (j == 0) ? 1.0 : -1.0;
         D0[c] = sgn * g.a * g.dlam * g.sv[jv] * sRed[0] / g.acap;
       } else {
-        const T mum = T(0.5) * (sP0[wrp(i + nj - 1, nx)] + sP0[wrp(i + nj, nx)]) * sU[wrp(i + nj - 1, nx)];
-        const T mun = T(0.5) * (sP0[wrp(i - nj, nx)] + sP0[wrp(i - nj + 1, nx)]) * sU[wrp(i - nj, nx)];
-        const T D = (mum - mun) / dxj +
-                    ((T)g.sv[j] * (PV0[c] * VA(j, k, i)) - (T)g.sv[j - 1] * (PVm[c] * VA(j - 1, k, i))) / dySj;
+        const int pa = wrp(i + nj - 1, nx), pb = wrp(i - nj, nx);
+        const T D = (PU0(pa) * sU[pa] - PU0(pb) * sU[pb]) / dxj +
+                    ((T)g.sv[j] * (T(0.5) * (sP0[i] + sP1[i]) * Vj[c]) -
+                     (T)g.sv[j - 1] * (T(0.5) * (sPm[i] + sP0[i]) * Vm[c])) / dySj;
         D0[c] = (C)D;
       }
       if (hasV) {
@@ -441,7 +433,8 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
           D1[c] = -g.a * g.dlam * g.sv[ny - 1] * sRed[0] / g.acap;
         } else {
           const T D = (sMU1[wrp(i + nj1 - 1, nx)] - sMU1[wrp(i - nj1, nx)]) / dxj1 +
-                      ((T)g.sv[j + 1] * (PV1[c] * VA(j + 1, k, i)) - (T)g.sv[j] * (PV0[c] * VA(j, k, i))) / dySj1;
+                      ((T)g.sv[j + 1] * (T(0.5) * (sP1[i] + sP2[i]) * V1[c]) -
+                       (T)g.sv[j] * (T(0.5) * (sP0[i] + sP1[i]) * Vj[c])) / dySj1;
           D1[c] = (C)D;
         }
       }
@@ -450,17 +443,22 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
 
   // ---- pass A: column totals Pi for rows j and j+1
   for (int k = 0; k < nz; ++k) {
+    T Vj[NI], Vm[NI], V1[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
+      Vj[c] = Vm[c] = V1[c] = T(0);
       if (i < nx) {
         sU[i] = UA(j, k, i);
-        if (j1Int) sMU1[i] = PU1c[c] * UA(j + 1, k, i);
+        if (j1Int) sMU1[i] = PU1(i) * UA(j + 1, k, i);
+        if (hasV) Vj[c] = VA(j, k, i);
+        if (j >= 1) Vm[c] = VA(j - 1, k, i);
+        if (j + 1 < ny) V1[c] = VA(j + 1, k, i);
       }
     }
     __syncthreads();
     C D0[NI], D1[NI];
-    div_rows(k, D0, D1);
+    div_rows(k, Vj, Vm, V1, D0, D1);
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       Pi0[c] += D0[c] * g.dsig[k];
@@ -474,32 +472,55 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
   for (int k = 0; k < nz; ++k) {
     const C dsg = g.dsig[k];
     const int par = k & 1, parn = (k + 1) & 1;
-    T Fj[NI], Uj[NI], Vj[NI];
+    // phase 1: loads of this level; LDS rows
+    T Vj[NI], Vm[NI], V1[NI], Fn[NI], Fs[NI], Fup[NI], Fdn[NI], Un[NI], Us[NI], Uup[NI], Udn[NI];
+    T Vup[NI], Vdn[NI], bF[NI], bU[NI], bV[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
-      Fj[c] = Uj[c] = Vj[c] = T(0);
+      Vj[c] = Vm[c] = V1[c] = Fn[c] = Fs[c] = Fup[c] = Fdn[c] = Un[c] = Us[c] = Uup[c] = Udn[c] = T(0);
+      Vup[c] = Vdn[c] = bF[c] = bU[c] = bV[c] = T(0);
       if (i < nx) {
-        Fj[c] = FA(j, k, i);
-        Uj[c] = UA(j, k, i);
-        sF[i] = Fj[c];
-        sU[i] = Uj[c];
-        const T u0 = isPole ? T(0) : Uj[c] / PU0c[c];
-        su0[i] = u0;
-        if (j1Int) sMU1[i] = PU1c[c] * UA(j + 1, k, i);
+        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
+        const T Fj = FA(j, k, i);
+        const T Uj = UA(j, k, i);
+        sF[i] = Fj;
+        sU[i] = Uj;
+        const T u0 = isPole ? T(0) : Uj / PU0(i);
+        const T U1 = UA(j + 1, k, i);
+        if (j1Int) sMU1[i] = PU1(i) * U1;
         if (hasV) {
           Vj[c] = VA(j, k, i);
           sV[i] = Vj[c];
-          svt0[i] = Vj[c] / PV0[c] * (T)g.sv[j];
-          const T u1 = j1Int ? UA(j + 1, k, i) / PU1c[c] : T(0);
+          svt0[i] = Vj[c] / (T(0.5) * (sP0[i] + sP1[i])) * (T)g.sv[j];
+          const T u1 = j1Int ? U1 / PU1(i) : T(0);
           suv[i] = T(0.5) * (u0 + u1);
+          bV[c] = A.bV[id];
+          if (k > 0) Vup[c] = VA(j, k - 1, i);
+          if (k + 1 < nz) Vdn[c] = VA(j, k + 1, i);
         }
-        if (j >= 1) svtm[i] = VA(j - 1, k, i) / PVm[c] * (T)g.sv[j - 1];
+        if (j >= 1) {
+          Vm[c] = VA(j - 1, k, i);
+          svtm[i] = Vm[c] / (T(0.5) * (sPm[i] + sP0[i])) * (T)g.sv[j - 1];
+        }
+        if (j + 1 < ny) V1[c] = VA(j + 1, k, i);
+        if (k > 0) Fup[c] = FA(j, k - 1, i);
+        if (k + 1 < nz) Fdn[c] = FA(j, k + 1, i);
+        if (!isPole) {
+          Fn[c] = FA(j + 1, k, i);
+          Fs[c] = FA(j - 1, k, i);
+          Un[c] = U1;
+          Us[c] = UA(j - 1, k, i);
+          if (k > 0) Uup[c] = UA(j, k - 1, i);
+          if (k + 1 < nz) Udn[c] = UA(j, k + 1, i);
+          bF[c] = A.bF[id];
+          bU[c] = A.bU[id];
+        }
       }
     }
     __syncthreads();
     C D0[NI], D1[NI];
-    div_rows(k, D0, D1);
+    div_rows(k, Vj, Vm, V1, D0, D1);
     C sd0n[NI], sd1n[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
@@ -507,10 +528,10 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
       S0[c] += D0[c] * dsg;
       S1[c] += D1[c] * dsg;
       sd0n[c] = 0; sd1n[c] = 0;
-      if (k + 1 < nz) {
+      if (k + 1 < nz && i < nx) {
         const C sh = g.sigh[k + 1];
-        sd0n[c] = (sh * Pi0[c] - S0[c]) / ((C)P0c[c] * (C)P0c[c]);
-        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) / ((C)P1c[c] * (C)P1c[c]);
+        sd0n[c] = (sh * Pi0[c] - S0[c]) / ((C)sP0[i] * (C)sP0[i]);
+        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) / ((C)sP1[i] * (C)sP1[i]);
       }
       if (i < nx) sSd[parn * nx + i] = (T)sd0n[c];
     }
@@ -539,29 +560,31 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
         if (i >= nx) continue;
         const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
         const int ip1 = wrp(i + 1, nx);
+        auto u0 = [&](int p) -> T { return sU[p] / PU0(p); };
         // Phi: zonal (x+1,x-1) -> (x+2N-1, x-2N+1), u at the midpoints
-        const T L1 = (su0[wrp(i + nj - 1, nx)] * sF[wrp(i + Mj, nx)] - su0[wrp(i - nj, nx)] * sF[wrp(i - Mj, nx)]) / dx2;
-        const T L2 = (svt0[i] * FA(j + 1, k, i) - svtm[i] * FA(j - 1, k, i)) / dy2;
+        const int qa = wrp(i + nj - 1, nx), qb = wrp(i - nj, nx);
+        const T L1 = (u0(qa) * sF[wrp(i + Mj, nx)] - u0(qb) * sF[wrp(i - Mj, nx)]) / dx2;
+        const T L2 = (svt0[i] * Fn[c] - svtm[i] * Fs[c]) / dy2;
         C L3 = 0;
-        if (k + 1 < nz) L3 += sd0n[c] * (C)FA(j, k + 1, i);
-        if (k > 0) L3 -= sd0c[c] * (C)FA(j, k - 1, i);
+        if (k + 1 < nz) L3 += sd0n[c] * (C)Fdn[c];
+        if (k > 0) L3 -= sd0c[c] * (C)Fup[c];
         L3 /= (2.0 * dsg);
         const C TF = -((C)L1 + (C)L2 + L3);
-        A.oF[id] = (T)((C)A.bF[id] + A.ch * TF);
+        A.oF[id] = (T)((C)bF[c] + A.ch * TF);
         // U: same leap on U points with u averaged to integer points
         const int pA = wrp(i + nj, nx), pB = wrp(i + 1 - nj, nx);
-        const T ubA = T(0.5) * (su0[wrp(pA - 1, nx)] + su0[pA]);
-        const T ubB = T(0.5) * (su0[wrp(pB - 1, nx)] + su0[pB]);
-        const T U1 = (ubA * sU[wrp(i + Mj, nx)] - ubB * sU[wrp(i - Mj, nx)]) / dx2;
+        const T ubA = T(0.5) * (u0(wrp(pA - 1, nx)) + u0(pA));
+        const T ubB = T(0.5) * (u0(wrp(pB - 1, nx)) + u0(pB));
+        const T U1v = (ubA * sU[wrp(i + Mj, nx)] - ubB * sU[wrp(i - Mj, nx)]) / dx2;
         const T vtn = T(0.5) * (svt0[i] + svt0[ip1]);
         const T vts = T(0.5) * (svtm[i] + svtm[ip1]);
-        const T U2 = (vtn * UA(j + 1, k, i) - vts * UA(j - 1, k, i)) / dy2;
+        const T U2v = (vtn * Un[c] - vts * Us[c]) / dy2;
         C U3 = 0;
-        if (k + 1 < nz) U3 += (C)(T(0.5) * (sSd[parn * nx + i] + sSd[parn * nx + ip1])) * (C)UA(j, k + 1, i);
-        if (k > 0) U3 -= (C)(T(0.5) * (sSd[par * nx + i] + sSd[par * nx + ip1])) * (C)UA(j, k - 1, i);
+        if (k + 1 < nz) U3 += (C)(T(0.5) * (sSd[parn * nx + i] + sSd[parn * nx + ip1])) * (C)Udn[c];
+        if (k > 0) U3 -= (C)(T(0.5) * (sSd[par * nx + i] + sSd[par * nx + ip1])) * (C)Uup[c];
         U3 /= (2.0 * dsg);
-        const C TU = -((C)U1 + (C)U2 + U3);
-        A.oU[id] = (T)((C)A.bU[id] + A.ch * TU);
+        const C TU = -((C)U1v + (C)U2v + U3);
+        A.oU[id] = (T)((C)bU[c] + A.ch * TU);
       }
     } else {
       const C sgn = (j == 0) ? 1.0 : -1.0;
@@ -596,17 +619,17 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
         const T L1 = (suv[wrp(i + nv - 1, nx)] * sV[wrp(i + Mv, nx)] - suv[wrp(i - nv, nx)] * sV[wrp(i - Mv, nx)]) / dxv2;
         T L2 = T(0);
         if (j + 1 < ny) {
-          const T vt1 = VA(j + 1, k, i) / PV1[c] * (T)g.sv[j + 1];
-          L2 += T(0.5) * (svt0[i] + vt1) * VA(j + 1, k, i);
+          const T vt1 = V1[c] / (T(0.5) * (sP1[i] + sP2[i])) * (T)g.sv[j + 1];
+          L2 += T(0.5) * (svt0[i] + vt1) * V1[c];
         }
-        if (j > 0) L2 -= T(0.5) * (svtm[i] + svt0[i]) * VA(j - 1, k, i);
+        if (j > 0) L2 -= T(0.5) * (svtm[i] + svt0[i]) * Vm[c];
         L2 = L2 / dyv2;
         C L3 = 0;
-        if (k + 1 < nz) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)VA(j, k + 1, i);
-        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)VA(j, k - 1, i);
+        if (k + 1 < nz) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)Vdn[c];
+        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)Vup[c];
         L3 /= (2.0 * dsg);
         const C TV = -((C)L1 + (C)L2 + L3);
-        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
+        A.oV[idv] = (T)((C)bV[c] + A.ch * TV);
       }
     }
 #pragma unroll
@@ -632,17 +655,19 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
   }
 }
 
-template <typename T, int NI>
-__global__ void __launch_bounds__(1024) k_stage(StageArgs<T> a) {
+// One launch per stage; the process is a template parameter so that the
+// adaptation and advection kernels are separate symbols in a profile.
+template <typename T, int NI, int PROC>
+__global__ void __launch_bounds__(max_block(NI)) k_stage(StageArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int j = xcd_row(blockIdx.x, a.g.ny + 1);
-  if (a.process == 0) adapt_row<T, NI>(a, j, smem);
+  if (PROC == 0) adapt_row<T, NI>(a, j, smem);
   else advect_row<T, NI>(a, j, smem);
 }
 
 // Persistent batched stage: work item w = (member, row); block b takes items b, b+G, ...
 template <typename T, int NI>
-__global__ void __launch_bounds__(1024) k_stage_batch(const StageArgs<T>* __restrict__ args,
+__global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T>* __restrict__ args,
                                                      const int2* __restrict__ items, int nitems) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
@@ -761,9 +786,16 @@ hipError_t allow_lds(K kernel, size_t lds) {
 template <typename T, int NI>
 hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
   const size_t lds = stage_lds_bytes(a.process, a.g.nx, sizeof(T));
-  hipError_t e = allow_lds(k_stage<T, NI>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stage<T, NI>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
+  hipError_t e;
+  if (a.process == 0) {
+    e = allow_lds(k_stage<T, NI, 0>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage<T, NI, 0>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
+  } else {
+    e = allow_lds(k_stage<T, NI, 1>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage<T, NI, 1>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -780,7 +812,7 @@ hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_items, int 
 }  // namespace
 
 size_t stage_lds_bytes(int process, int nx, int elem) {
-  const size_t rows = (process == 0) ? 7 : 12;
+  const size_t rows = (process == 0) ? 12 : 13;
   return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 4 * sizeof(double);
 }
 
