@@ -101,8 +101,9 @@ int dycore_step_adjoint(dycore_t h, const void* U0, const void* V0, const void* 
                         void* aU, void* aV, void* aPhi, void* aps, void* stream);
 
 /* Adjoint of one stage about its input (U..ps): adds J_base^T a_out into
- * (abU..) and J_in^T a_out into (aiU..).  The accumulators must not alias
- * a_out or each other. */
+ * (abU..) and J_in^T a_out into (aiU..).  The two accumulators may be the
+ * same buffers (the stage's base and input then coincide); neither may alias
+ * a_out.  Needs the adjoint workspace. */
 int dycore_stage_adjoint(dycore_t h, int process, double ch,
                          const void* U, const void* V, const void* Phi, const void* ps,
                          const void* aoU, const void* aoV, const void* aoPhi, const void* aops,

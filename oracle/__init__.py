@@ -173,6 +173,16 @@ class Oracle:
                                 _p(o["U"]), _p(o["V"]), _p(o["Phi"]), _p(o["ps"]))
         return o
 
+    def adj_stage(self, yin, a_out, ch, which):
+        """Adjoint of out = base + ch T(yin): returns (adjoint of base, adjoint of yin)."""
+        s = self._c(yin); a = self._c(a_out); b = self.zeros(); i = self.zeros()
+        self.L.orc_adj_stage(self._vh(), 0 if which == "A" else 1, ctypes.c_double(ch),
+                             _p(s["U"]), _p(s["V"]), _p(s["Phi"]), _p(s["ps"]),
+                             _p(a["U"]), _p(a["V"]), _p(a["Phi"]), _p(a["ps"]),
+                             _p(b["U"]), _p(b["V"]), _p(b["Phi"]), _p(b["ps"]),
+                             _p(i["U"]), _p(i["V"]), _p(i["Phi"]), _p(i["ps"]))
+        return b, i
+
     def adj_step(self, st0, a_out, dt, msub=None):
         if msub is None:
             msub = self.substeps(dt)

@@ -1268,6 +1268,21 @@ void orc_adj_tendency(void* h, int which, const double* U, const double* V, cons
   store(g, ay, oU, oV, oF, ops);
 }
 
+// Adjoint of one stage out = base + ch * T(in) about `in`: the adjoint of base and of in.
+void orc_adj_stage(void* h, int which, double ch, const double* U, const double* V, const double* F, const double* ps,
+                   const double* aU, const double* aV, const double* aF, const double* aps,
+                   double* bU, double* bV, double* bF, double* bps, double* iU, double* iV, double* iF, double* ips) {
+  const Geo& g = *static_cast<Geo*>(h);
+  St<double> y, ao, ab, ai;
+  load(g, y, U, V, F, ps);
+  load(g, ao, aU, aV, aF, aps);
+  zero_like(g, ab);
+  zero_like(g, ai);
+  adj_stage(g, y, ch, which, ao, ab, ai);
+  store(g, ab, bU, bV, bF, bps);
+  store(g, ai, iU, iV, iF, ips);
+}
+
 // Adjoint of one outer step about its start state (U0..): a in = adjoint of the output,
 // a out = adjoint of the input (in place).
 void orc_adj_step(void* h, const double* U0, const double* V0, const double* F0, const double* ps0,

@@ -1,18 +1,1092 @@
-// Adjoint (transpose) of the stage and of the outer step.
+// Adjoint (transpose) of one stage and of the outer step (gfx950).
+//
+// The adjoint is the transpose of the forward map under the Euclidean inner
+// product over every stored entry.  Each stage adjoint first recomputes the
+// column diagnostics of its input (P, l, q, the leaped d+l and d+q, R T',
+// phi', divergence D, prefix sums S, sigma-dot, omega/p) into scratch, then
+// runs the transposed operators in reverse order as gather kernels: every
+// adjoint entry collects the contributions of all forward outputs that read it
+// (the transpose of a leaped d+ is a leaped d- with mirrored offsets, of an
+// average the mirrored average, of a prefix sum a suffix sum, of a pole read
+// a spread of the row sum over the row).  No atomics: results are
+// deterministic.  Column sums and pole sums are FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 #include "../../include/dycore.h"
 #include "dycore_internal.h"
 
+using namespace dyc;
+
+namespace {
+
+using C = double;
+
+__device__ __forceinline__ int wrp(int i, int nx) { return i >= nx ? i - nx : (i < 0 ? i + nx : i); }
+
+__device__ __forceinline__ double wave_sum(double acc) {
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  return acc;
+}
+
+template <typename T> __device__ __forceinline__ T tsqrt(T x);
+template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T tlog(T x);
+template <> __device__ __forceinline__ float tlog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ double tlog<double>(double x) { return log(x); }
+
+// Scratch of one stage adjoint.
+template <typename T>
+struct Scr {
+  // forward recompute
+  T *P, *L, *Q, *DL, *DQ;          // 2D (ny+1)*nx
+  T *RT, *PHI, *D, *WP;            // 3D scalar
+  T *S, *SD;                       // half levels (ny+1)*(nz+1)*nx
+  // adjoint intermediates (3D, index like the scalar/U/V fields)
+  T *AVGL, *ASK, *AD, *AFE, *AP3, *HH, *FU, *AUU, *AUD, *MV, *FV, *UV, *AVV, *AVD, *APU3, *APV3;
+  T *APHI, *ART, *AL3, *AQ3, *ADL3, *ADQ3;
+  T *ASD;                          // half levels
+  double *AP2, *APU2, *APV2, *AL2, *AQ2, *ADL2, *ADQ2, *APSR;   // 2D FP64
+  double* psum;                    // pole sums [8][2][nz+1]
+};
+
+// Pole sums slots
+enum { PS_AD = 0, PS_AVGL = 1, PS_AOF = 2, PS_AFE = 3 };
+
+template <typename T>
+struct Ctx {
+  GeoDev g;
+  const T *U, *V, *F, *P;          // linearisation state (stage input)
+  const T *aoU, *aoV, *aoF, *aoP;  // adjoint of the stage output
+  T *abU, *abV, *abF, *abP;        // += adjoint of base
+  T *aiU, *aiV, *aiF, *aiP;        // += adjoint of in
+  const double* pin;               // pole values of the linearisation state
+  double ch;
+  Scr<T> s;
+};
+
+template <typename T>
+__device__ __forceinline__ size_t i3(const GeoDev& g, int j, int k, int i) {
+  return ((size_t)j * g.nz + k) * g.nx + i;
+}
+template <typename T>
+__device__ __forceinline__ size_t ih(const GeoDev& g, int j, int h, int i) {
+  return ((size_t)j * (g.nz + 1) + h) * g.nx + i;
+}
+
+// pole-aware reads of the linearisation state
+template <typename T>
+__device__ __forceinline__ T Fe(const Ctx<T>& c, int j, int k, int i) {
+  const GeoDev& g = c.g;
+  if (j == 0) return (T)c.pin[k];
+  if (j == g.ny) return (T)c.pin[(g.nz + 1) + k];
+  return c.F[i3<T>(g, j, k, i)];
+}
+template <typename T>
+__device__ __forceinline__ T Ue(const Ctx<T>& c, int j, int k, int i) {
+  const GeoDev& g = c.g;
+  if (j <= 0 || j >= g.ny) return T(0);
+  return c.U[i3<T>(g, j, k, i)];
+}
+template <typename T>
+__device__ __forceinline__ T Ve(const Ctx<T>& c, int jv, int k, int i) {
+  return c.V[i3<T>(c.g, jv, k, i)];
+}
+template <typename T>
+__device__ __forceinline__ T psE(const Ctx<T>& c, int j, int i) {
+  const GeoDev& g = c.g;
+  if (j == 0) return (T)c.pin[g.nz];
+  if (j == g.ny) return (T)c.pin[(g.nz + 1) + g.nz];
+  return c.P[(size_t)j * g.nx + i];
+}
+template <typename T>
+__device__ __forceinline__ T P2(const Ctx<T>& c, int j, int i) { return c.s.P[(size_t)j * c.g.nx + i]; }
+template <typename T>
+__device__ __forceinline__ T PUe(const Ctx<T>& c, int j, int i) {
+  return T(0.5) * (P2(c, j, i) + P2(c, j, wrp(i + 1, c.g.nx)));
+}
+template <typename T>
+__device__ __forceinline__ T PVe(const Ctx<T>& c, int jv, int i) {
+  return T(0.5) * (P2(c, jv, i) + P2(c, jv + 1, i));
+}
+template <typename T>
+__device__ __forceinline__ T ue(const Ctx<T>& c, int j, int k, int i) {   // u = U / P^U, 0 on pole rows
+  const GeoDev& g = c.g;
+  if (j <= 0 || j >= g.ny) return T(0);
+  return c.U[i3<T>(g, j, k, i)] / PUe(c, j, i);
+}
+template <typename T>
+__device__ __forceinline__ T vte(const Ctx<T>& c, int jv, int k, int i) {  // v sin(theta) on V row jv
+  return Ve(c, jv, k, i) / PVe(c, jv, i) * (T)c.g.sv[jv];
+}
+
+// ------------------------------------------------------------------------------------------------
+// forward recompute
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_f2d(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y;
+  const T p0 = (T)g.p0, RT0 = (T)g.RT0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.nx; i += gridDim.x * blockDim.x) {
+    const T ps = psE(c, j, i);
+    const size_t id = (size_t)j * g.nx + i;
+    c.s.P[id] = tsqrt<T>(ps / p0);
+    c.s.L[id] = tlog<T>(ps / p0);
+    c.s.Q[id] = c.s.L[id] + (T)g.phis[id] / RT0;
+    T dl = 0, dq = 0;
+    if (j >= 1 && j < g.ny) {
+      const int M = g.M[j], n = (M + 1) / 2;
+      const T dx = (T)((double)M * g.a * g.s[j] * g.dlam);
+      const int pa = wrp(i + n, g.nx), pb = wrp(i + 1 - n, g.nx);
+      const T la = tlog<T>(psE(c, j, pa) / p0), lb = tlog<T>(psE(c, j, pb) / p0);
+      dl = (la - lb) / dx;
+      const T qa = la + (T)g.phis[(size_t)j * g.nx + pa] / RT0;
+      const T qb = lb + (T)g.phis[(size_t)j * g.nx + pb] / RT0;
+      dq = (qa - qb) / dx;
+    }
+    c.s.DL[id] = dl;
+    c.s.DQ[id] = dq;
+  }
+}
+
+// interior columns: RT', D, S, phi', sigma-dot, omega/p
+template <typename T>
+__global__ void k_f1(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y + 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, nz = g.nz;
+  const T b = (T)g.b;
+  const int M = g.M[j], n = (M + 1) / 2;
+  const T dx = (T)((double)M * g.a * g.s[j] * g.dlam);
+  const T dyS = (T)(g.a * g.s[j] * g.dth), dyA = (T)(g.a * g.dth);
+  const T P0 = P2(c, j, i);
+  const T PV0 = PVe(c, j, i), PVm = PVe(c, j - 1, i);
+  const int pa = wrp(i + n - 1, nx), pb = wrp(i - n, nx), im1 = wrp(i - 1, nx);
+  const T PUa = PUe(c, j, pa), PUb = PUe(c, j, pb), PU0 = PUe(c, j, i), PUm = PUe(c, j, im1);
+  C H = 0, S = 0;
+  c.s.S[ih<T>(g, j, 0, i)] = T(0);
+  for (int k = 0; k < nz; ++k) {
+    const T RT = b * Fe(c, j, k, i) / P0;
+    c.s.RT[i3<T>(g, j, k, i)] = RT;
+    H += g.cl[k] * (C)RT;
+    const T D = (PUa * Ue(c, j, k, pa) - PUb * Ue(c, j, k, pb)) / dx +
+                ((T)g.sv[j] * (PV0 * Ve(c, j, k, i)) - (T)g.sv[j - 1] * (PVm * Ve(c, j - 1, k, i))) / dyS;
+    c.s.D[i3<T>(g, j, k, i)] = D;
+    S += (C)D * g.dsig[k];
+    c.s.S[ih<T>(g, j, k + 1, i)] = (T)S;
+  }
+  const C Pi = S;
+  C R = 0, Sk = 0;
+  const C P0s = (C)P0 * (C)P0;
+  const T l0 = c.s.L[(size_t)j * nx + i], l1 = c.s.L[(size_t)(j + 1) * nx + i], lm = c.s.L[(size_t)(j - 1) * nx + i];
+  const T dl0 = c.s.DL[(size_t)j * nx + i], dlm = c.s.DL[(size_t)j * nx + im1];
+  c.s.SD[ih<T>(g, j, 0, i)] = T(0);
+  for (int k = 0; k < nz; ++k) {
+    const size_t id = i3<T>(g, j, k, i);
+    const T RT = c.s.RT[id];
+    R += g.cl[k] * (C)RT;
+    c.s.PHI[id] = (T)(H - R + g.cpk[k] * (C)RT);
+    const C D = (C)c.s.D[id];
+    const T zon = T(0.5) * ((Ue(c, j, k, i) / PU0) * dl0 + (Ue(c, j, k, im1) / PUm) * dlm);
+    const T mer = T(0.5) * ((Ve(c, j, k, i) / PV0) * (l1 - l0) + (Ve(c, j - 1, k, i) / PVm) * (l0 - lm)) / dyA;
+    c.s.WP[id] = (T)(((C)zon + (C)mer) - (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s));
+    Sk += D * g.dsig[k];
+    c.s.SD[ih<T>(g, j, k + 1, i)] = (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - Sk) / P0s) : T(0);
+  }
+}
+
+// pole columns: one wavefront per pole
+template <typename T>
+__global__ void __launch_bounds__(64) k_f1p(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int p = blockIdx.x;                  // 0 north, 1 south
+  const int j = p == 0 ? 0 : g.ny;
+  const int ja = p == 0 ? 1 : g.ny - 1;      // adjacent scalar row
+  const int jv = p == 0 ? 0 : g.ny - 1;      // adjacent V row
+  const int nx = g.nx, nz = g.nz, t = threadIdx.x;
+  const T b = (T)g.b;
+  const T Pp = P2(c, j, 0), lp = c.s.L[(size_t)j * nx];
+  const C sgn = p == 0 ? 1.0 : -1.0;
+  // cap divergence and v.grad(l) per level
+  for (int k = 0; k < nz; ++k) {
+    C s1 = 0, s2 = 0;
+    for (int i = t; i < nx; i += 64) {
+      const T pv = T(0.5) * (Pp + P2(c, ja, i));
+      const T vv = Ve(c, jv, k, i);
+      s1 += (C)(pv * vv);
+      const T la = c.s.L[(size_t)ja * nx + i];
+      s2 += (C)((vv / pv) * (p == 0 ? (la - lp) : (lp - la)));
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    const T D = (T)(sgn * g.a * g.dlam * g.sv[jv] * s1 / g.acap);
+    const T vg = (T)(s2 / ((double)nx * g.a * g.dth));
+    for (int i = t; i < nx; i += 64) {
+      c.s.D[i3<T>(g, j, k, i)] = D;
+      c.s.WP[i3<T>(g, j, k, i)] = vg;   // v.grad(l) for now
+    }
+  }
+  C H = 0, S = 0;
+  for (int k = 0; k < nz; ++k) {
+    const T RT = b * (T)c.pin[p * (nz + 1) + k] / Pp;
+    H += g.cl[k] * (C)RT;
+  }
+  const C P0s = (C)Pp * (C)Pp;
+  C Pi = 0;
+  for (int k = 0; k < nz; ++k) Pi += (C)c.s.D[i3<T>(g, j, k, 0)] * g.dsig[k];
+  C R = 0;
+  for (int k = 0; k < nz; ++k) {
+    const T RT = b * (T)c.pin[p * (nz + 1) + k] / Pp;
+    R += g.cl[k] * (C)RT;
+    const T PHI = (T)(H - R + g.cpk[k] * (C)RT);
+    const C D = (C)c.s.D[i3<T>(g, j, k, 0)];
+    const C vg = (C)c.s.WP[i3<T>(g, j, k, 0)];
+    const T WP = (T)(vg - (S + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s));
+    const T Sk = (T)S;
+    S += D * g.dsig[k];
+    const T SDn = (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - S) / P0s) : T(0);
+    for (int i = t; i < nx; i += 64) {
+      const size_t id = i3<T>(g, j, k, i);
+      c.s.RT[id] = RT;
+      c.s.PHI[id] = PHI;
+      c.s.WP[id] = WP;
+      c.s.S[ih<T>(g, j, k, i)] = Sk;
+      c.s.SD[ih<T>(g, j, k + 1, i)] = SDn;
+      if (k == 0) c.s.SD[ih<T>(g, j, 0, i)] = T(0);
+    }
+  }
+  for (int i = t; i < nx; i += 64) c.s.S[ih<T>(g, j, nz, i)] = (T)S;
+}
+
+// ------------------------------------------------------------------------------------------------
+// base part of the stage transpose (interior rows: identity; pole rows: spread of the row sum) and
+// pole sums of the output adjoint
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_base(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const size_t id = i3<T>(g, j, k, i);
+  if (j < g.ny) c.abV[id] += c.aoV[id];
+  if (j >= 1 && j < g.ny) {
+    c.abU[id] += c.aoU[id];
+    c.abF[id] += c.aoF[id];
+    if (k == 0) c.abP[(size_t)j * g.nx + i] += c.aoP[(size_t)j * g.nx + i];
+  }
+}
+
+// FP64 row sums over a pole row of a scalar-point field (per level) or of p_s (slot nz).
+template <typename T>
+__global__ void __launch_bounds__(64) k_pole_sum(GeoDev g, const T* f3, const T* f2, double* out) {
+  const int v = blockIdx.x;   // 0 .. 2*(nz+1)-1
+  const int p = v / (g.nz + 1), k = v % (g.nz + 1);
+  const int j = p == 0 ? 0 : g.ny;
+  C s = 0;
+  if (k < g.nz) {
+    if (f3)
+      for (int i = threadIdx.x; i < g.nx; i += 64) s += (C)f3[((size_t)j * g.nz + k) * g.nx + i];
+  } else if (f2) {
+    for (int i = threadIdx.x; i < g.nx; i += 64) s += (C)f2[(size_t)j * g.nx + i];
+  }
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[p * (g.nz + 1) + k] = s;
+}
+
+template <typename T>
+__global__ void k_base_pole(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int p = blockIdx.y, k = blockIdx.x;   // k in 0..nz (nz = p_s)
+  const int j = p == 0 ? 0 : g.ny;
+  const double* sf = c.s.psum + PS_AOF * 2 * (g.nz + 1);
+  const T add = (T)(sf[p * (g.nz + 1) + k] / g.nx);
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+    if (k < g.nz) c.abF[i3<T>(g, j, k, i)] += add;
+    else c.abP[(size_t)j * g.nx + i] += add;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// adaptation: first transposes (Phi and p_s tendencies, omega/p, pressure gradients, Coriolis)
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_a1(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny;
+  const T b = (T)g.b, kap = (T)g.kappa;
+  const C ch = c.ch;
+  const size_t id = i3<T>(g, j, k, i);
+  // scalar point (every row; pole rows per stored copy)
+  {
+    const T P = P2(c, j, i);
+    const T F = Fe(c, j, k, i);
+    const C gF = ch * (C)c.aoF[id];
+    const C wp = (C)c.s.WP[id];
+    const C aWP = ((C)(b * P) + (C)(kap * F)) * gF;
+    const C P2c = (C)P * (C)P;
+    const C Sk = (C)c.s.S[ih<T>(g, j, k, i)];
+    const C D = (C)c.s.D[id];
+    c.s.AVGL[id] = (T)aWP;
+    c.s.ASK[id] = (T)(-aWP / (g.sig[k] * P2c));
+    c.s.AD[id] = (T)(-0.5 * g.dsig[k] * aWP / (g.sig[k] * P2c));
+    c.s.AFE[id] = (T)((C)kap * wp * gF);
+    c.s.AP3[id] = (T)((C)b * wp * gF + 2.0 * (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P2c * (C)P) * aWP);
+  }
+  // U point (interior rows)
+  if (j >= 1 && j < ny) {
+    const int M = g.M[j], n = (M + 1) / 2;
+    const T dx = (T)((double)M * g.a * g.s[j] * g.dlam);
+    const int ip1 = wrp(i + 1, nx);
+    const C gU = ch * (C)c.aoU[id];
+    const T PU = PUe(c, j, i);
+    const T dphi = (c.s.PHI[i3<T>(g, j, k, wrp(i + n, nx))] - c.s.PHI[i3<T>(g, j, k, wrp(i + 1 - n, nx))]) / dx;
+    const T rtx = T(0.5) * (c.s.RT[id] + c.s.RT[i3<T>(g, j, k, ip1)]);
+    const C pgf = (C)dphi + g.RT0 * (C)c.s.DQ[(size_t)j * nx + i] + (C)rtx * (C)c.s.DL[(size_t)j * nx + i];
+    const T VV = T(0.25) * (Ve(c, j, k, i) + Ve(c, j, k, ip1) + Ve(c, j - 1, k, i) + Ve(c, j - 1, k, ip1));
+    const T u = c.U[id] / PU;
+    const T fs = (T)g.f[j] + u * (T)(g.cot[j] / g.a);
+    c.s.HH[id] = (T)(-(C)PU * gU);
+    c.s.FU[id] = (T)((C)fs * gU);
+    c.s.AUU[id] = (T)(-(C)VV * (g.cot[j] / g.a) * gU);
+    c.s.APU3[id] = (T)(-pgf * gU);
+  }
+  // V point (V rows)
+  if (j < ny) {
+    const int jv = j;
+    const int im1 = wrp(i - 1, nx);
+    const C gV = ch * (C)c.aoV[id];
+    const T PV = PVe(c, jv, i);
+    const T dyA = (T)(g.a * g.dth);
+    const C pgf = ((C)(c.s.PHI[i3<T>(g, jv + 1, k, i)] - c.s.PHI[id]) +
+                   g.RT0 * (C)(c.s.Q[(size_t)(jv + 1) * nx + i] - c.s.Q[(size_t)jv * nx + i]) +
+                   (C)(T(0.5) * (c.s.RT[id] + c.s.RT[i3<T>(g, jv + 1, k, i)])) *
+                       (C)(c.s.L[(size_t)(jv + 1) * nx + i] - c.s.L[(size_t)jv * nx + i])) / (C)dyA;
+    const T UU = T(0.25) * (Ue(c, jv, k, im1) + Ue(c, jv, k, i) + Ue(c, jv + 1, k, im1) + Ue(c, jv + 1, k, i));
+    const T uu = T(0.25) * (ue(c, jv, k, im1) + ue(c, jv, k, i) + ue(c, jv + 1, k, im1) + ue(c, jv + 1, k, i));
+    const T fs = (T)g.fv[jv] + uu * (T)(g.cotv[jv] / g.a);
+    c.s.MV[id] = (T)(-(C)PV * gV / (C)dyA);
+    c.s.FV[id] = (T)((C)fs * gV);
+    c.s.UV[id] = (T)((C)UU * gV * (g.cotv[jv] / g.a));
+    c.s.APV3[id] = (T)(-pgf * gV);
+  }
+}
+
+// suffix transposes of the column prefix sums: aD_l += dsig_l (aPi + sum_{k>l} aS_k), aPi = -p0 ch aoP
+template <typename T>
+__global__ void k_a2(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const C aPi = -g.p0 * c.ch * (C)c.aoP[(size_t)j * g.nx + i];
+  C acc = 0;
+  for (int k = g.nz - 1; k >= 0; --k) {
+    const size_t id = i3<T>(g, j, k, i);
+    c.s.AD[id] = (T)((C)c.s.AD[id] + g.dsig[k] * (aPi + acc));
+    acc += (C)c.s.ASK[id];
+  }
+}
+
+// gathers of the adaptation transposes at scalar, U and V points
+template <typename T>
+__global__ void k_a3(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const C RT0 = g.RT0;
+  const C aDy = g.a * g.dth;
+  const double* sVG = c.s.psum + PS_AVGL * 2 * (nz + 1);
+  const size_t id = i3<T>(g, j, k, i);
+  // weights of v.grad(l) seen from V row jv: cN (scalar row jv) + cS (scalar row jv+1)
+  auto cvg = [&](int jv) -> C {
+    const C cN = (jv >= 1) ? 0.5 * (C)c.s.AVGL[i3<T>(g, jv, k, i)] : sVG[0 * (nz + 1) + k] / nx;
+    const C cS = (jv + 1 <= ny - 1) ? 0.5 * (C)c.s.AVGL[i3<T>(g, jv + 1, k, i)] : sVG[1 * (nz + 1) + k] / nx;
+    return cN + cS;
+  };
+  auto Lr = [&](int jr) -> C { return (C)c.s.L[(size_t)jr * nx + i]; };
+  // scalar point
+  {
+    C aPHI = 0, aRT = 0, aL = 0, aQ = 0;
+    if (j >= 1 && j < ny) {
+      const int M = g.M[j], n = (M + 1) / 2;
+      const C dx = (C)(T)((double)M * g.a * g.s[j] * g.dlam);
+      const int im1 = wrp(i - 1, nx);
+      aPHI += ((C)c.s.HH[i3<T>(g, j, k, wrp(i - n, nx))] - (C)c.s.HH[i3<T>(g, j, k, wrp(i + n - 1, nx))]) / dx;
+      aRT += 0.5 * ((C)c.s.HH[id] * (C)c.s.DL[(size_t)j * nx + i] +
+                    (C)c.s.HH[i3<T>(g, j, k, im1)] * (C)c.s.DL[(size_t)j * nx + im1]);
+    }
+    if (j >= 1) {   // V row j-1 (north): phi'(j), q(j), l(j) enter with +
+      const int jv = j - 1;
+      const C m = (C)c.s.MV[i3<T>(g, jv, k, i)];
+      aPHI += m;
+      aRT += 0.5 * (Lr(jv + 1) - Lr(jv)) * m;
+      const C rty = 0.5 * ((C)c.s.RT[i3<T>(g, jv, k, i)] + (C)c.s.RT[i3<T>(g, jv + 1, k, i)]);
+      const C w = (C)(Ve(c, jv, k, i) / PVe(c, jv, i)) / aDy * cvg(jv);
+      aL += w + rty * m;
+      aQ += RT0 * m;
+    }
+    if (j <= ny - 1) {   // V row j (south): enter with -
+      const int jv = j;
+      const C m = (C)c.s.MV[i3<T>(g, jv, k, i)];
+      aPHI -= m;
+      aRT += 0.5 * (Lr(jv + 1) - Lr(jv)) * m;
+      const C rty = 0.5 * ((C)c.s.RT[i3<T>(g, jv, k, i)] + (C)c.s.RT[i3<T>(g, jv + 1, k, i)]);
+      const C w = (C)(Ve(c, jv, k, i) / PVe(c, jv, i)) / aDy * cvg(jv);
+      aL -= w + rty * m;
+      aQ -= RT0 * m;
+    }
+    c.s.APHI[id] = (T)aPHI;
+    c.s.ART[id] = (T)aRT;
+    c.s.AL3[id] = (T)aL;
+    c.s.AQ3[id] = (T)aQ;
+  }
+  // U point
+  if (j >= 1 && j < ny) {
+    const int ip1 = wrp(i + 1, nx);
+    const C dl = (C)c.s.DL[(size_t)j * nx + i];
+    C au = (C)c.s.AUU[id] + 0.5 * dl * ((C)c.s.AVGL[id] + (C)c.s.AVGL[i3<T>(g, j, k, ip1)]);
+    au += 0.25 * ((C)c.s.UV[i3<T>(g, j - 1, k, i)] + (C)c.s.UV[i3<T>(g, j - 1, k, ip1)] +
+                  (C)c.s.UV[i3<T>(g, j, k, i)] + (C)c.s.UV[i3<T>(g, j, k, ip1)]);
+    const C aUd = 0.25 * ((C)c.s.FV[i3<T>(g, j - 1, k, i)] + (C)c.s.FV[i3<T>(g, j - 1, k, ip1)] +
+                          (C)c.s.FV[i3<T>(g, j, k, i)] + (C)c.s.FV[i3<T>(g, j, k, ip1)]);
+    const C u = (C)(c.U[id] / PUe(c, j, i));
+    const C rtx = 0.5 * ((C)c.s.RT[id] + (C)c.s.RT[i3<T>(g, j, k, ip1)]);
+    const C hh = (C)c.s.HH[id];
+    c.s.AUU[id] = (T)au;
+    c.s.AUD[id] = (T)aUd;
+    c.s.ADL3[id] = (T)(0.5 * u * ((C)c.s.AVGL[id] + (C)c.s.AVGL[i3<T>(g, j, k, ip1)]) + rtx * hh);
+    c.s.ADQ3[id] = (T)(RT0 * hh);
+  }
+  // V point
+  if (j < ny) {
+    const int jv = j;
+    const int im1 = wrp(i - 1, nx);
+    c.s.AVV[id] = (T)((Lr(jv + 1) - Lr(jv)) / aDy * cvg(jv));
+    C aVd = 0;
+    if (jv >= 1) aVd += (C)c.s.FU[i3<T>(g, jv, k, im1)] + (C)c.s.FU[i3<T>(g, jv, k, i)];
+    if (jv + 1 <= ny - 1) aVd += (C)c.s.FU[i3<T>(g, jv + 1, k, im1)] + (C)c.s.FU[i3<T>(g, jv + 1, k, i)];
+    c.s.AVD[id] = (T)(-0.25 * aVd);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// advection transposes
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_l1(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const C ch = c.ch;
+  const double* sF = c.s.psum + PS_AOF * 2 * (nz + 1);
+  const C AN = -ch * sF[0 * (nz + 1) + k], AS = -ch * sF[1 * (nz + 1) + k];
+  const C cc = g.a * g.dlam / (2.0 * g.acap);
+  auto amF = [&](int jr, int kk, int ii) -> C { return -ch * (C)c.aoF[i3<T>(g, jr, kk, ii)]; };
+  auto amU = [&](int jr, int kk, int ii) -> C { return -ch * (C)c.aoU[i3<T>(g, jr, kk, ii)]; };
+  auto amV = [&](int jv, int kk, int ii) -> C { return -ch * (C)c.aoV[i3<T>(g, jv, kk, ii)]; };
+  auto interior = [&](int jr) { return jr >= 1 && jr <= ny - 1; };
+  auto sd = [&](int jr, int h, int ii) -> C { return (C)c.s.SD[ih<T>(g, jr, h, ii)]; };
+  auto dxr = [&](int jr) -> C { return (C)(T)(2.0 * (double)g.M[jr] * g.a * g.s[jr] * g.dlam); };
+  auto dyr = [&](int jr) -> C { return (C)(T)(2.0 * g.a * g.s[jr] * g.dth); };
+  auto dxv = [&](int jv) -> C { return (C)(T)(2.0 * (double)g.Mv[jv] * g.a * g.sv[jv] * g.dlam); };
+  auto dyv = [&](int jv) -> C { return (C)(T)(2.0 * g.a * g.sv[jv] * g.dth); };
+  auto ub = [&](int jr, int q) -> C {   // u averaged to integer point q of U row jr
+    return 0.5 * ((C)ue(c, jr, k, wrp(q - 1, nx)) + (C)ue(c, jr, k, q));
+  };
+  auto uv = [&](int jv, int q) -> C { return 0.5 * ((C)ue(c, jv, k, q) + (C)ue(c, jv + 1, k, q)); };
+  auto vts = [&](int js, int kk, int ii) -> C {   // v sin(theta) on scalar row js
+    if (js <= 0 || js >= ny) return 0.0;
+    return 0.5 * ((C)vte(c, js - 1, kk, ii) + (C)vte(c, js, kk, ii));
+  };
+  const size_t id = i3<T>(g, j, k, i);
+
+  // ---- scalar point: adjoint of Phi (pole-read copies included)
+  {
+    C a = 0;
+    if (interior(j)) {
+      const int M = g.M[j], n = (M + 1) / 2;
+      const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
+      a += (amF(j, k, pm) * (C)ue(c, j, k, wrp(pm + n - 1, nx)) - amF(j, k, pp) * (C)ue(c, j, k, wrp(pp - n, nx))) / dxr(j);
+    }
+    if (interior(j - 1)) a += amF(j - 1, k, i) * (C)vte(c, j - 1, k, i) / dyr(j - 1);
+    if (interior(j + 1)) a -= amF(j + 1, k, i) * (C)vte(c, j, k, i) / dyr(j + 1);
+    if (j == 1) a += cc * (C)vte(c, 0, k, i) * AN;
+    if (j == ny - 1) a -= cc * (C)vte(c, ny - 1, k, i) * AS;
+    if (k >= 1) a += amF(j, k - 1, i) * sd(j, k, i) / (2.0 * g.dsig[k - 1]);
+    if (k + 1 < nz) a -= amF(j, k + 1, i) * sd(j, k + 1, i) / (2.0 * g.dsig[k + 1]);
+    c.s.AFE[id] = (T)a;
+  }
+  // ---- U point
+  if (interior(j)) {
+    const int M = g.M[j], n = (M + 1) / 2;
+    // adjoint of u (U point i+1/2)
+    C au = 0;
+    {
+      const int qa = wrp(i - n + 1, nx), qb = wrp(i + n, nx);
+      au += (amF(j, k, qa) * (C)Fe(c, j, k, wrp(qa + M, nx)) - amF(j, k, qb) * (C)Fe(c, j, k, wrp(qb - M, nx))) / dxr(j);
+      auto aub = [&](int q) -> C {
+        const int r1 = wrp(q - n, nx), r2 = wrp(q - 1 + n, nx);
+        return (amU(j, k, r1) * (C)Ue(c, j, k, wrp(r1 + M, nx)) - amU(j, k, r2) * (C)Ue(c, j, k, wrp(r2 - M, nx))) / dxr(j);
+      };
+      au += 0.5 * (aub(i) + aub(wrp(i + 1, nx)));
+      for (int jv : {j - 1, j}) {
+        const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
+        const int r1 = wrp(i - nv + 1, nx), r2 = wrp(i + nv, nx);
+        const C auv = (amV(jv, k, r1) * (C)Ve(c, jv, k, wrp(r1 + Mv, nx)) -
+                       amV(jv, k, r2) * (C)Ve(c, jv, k, wrp(r2 - Mv, nx))) / dxv(jv);
+        au += 0.5 * auv;
+      }
+    }
+    c.s.AUU[id] = (T)au;
+    // direct adjoint of U
+    C aU = 0;
+    {
+      const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
+      aU += (amU(j, k, pm) * ub(j, wrp(pm + n, nx)) - amU(j, k, pp) * ub(j, wrp(pp + 1 - n, nx))) / dxr(j);
+      const int ip1 = wrp(i + 1, nx);
+      if (interior(j - 1)) {
+        const C vtu = 0.5 * ((C)vte(c, j - 1, k, i) + (C)vte(c, j - 1, k, ip1));
+        aU += amU(j - 1, k, i) * vtu / dyr(j - 1);
+      }
+      if (interior(j + 1)) {
+        const C vtu = 0.5 * ((C)vte(c, j, k, i) + (C)vte(c, j, k, ip1));
+        aU -= amU(j + 1, k, i) * vtu / dyr(j + 1);
+      }
+      if (k >= 1) aU += amU(j, k - 1, i) * 0.5 * (sd(j, k, i) + sd(j, k, ip1)) / (2.0 * g.dsig[k - 1]);
+      if (k + 1 < nz) aU -= amU(j, k + 1, i) * 0.5 * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) / (2.0 * g.dsig[k + 1]);
+    }
+    c.s.AUD[id] = (T)aU;
+  }
+  // ---- V point
+  if (j < ny) {
+    const int jv = j;
+    const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
+    C aV = 0;
+    {
+      const int pm = wrp(i - Mv, nx), pp = wrp(i + Mv, nx);
+      aV += (amV(jv, k, pm) * uv(jv, wrp(pm + nv - 1, nx)) - amV(jv, k, pp) * uv(jv, wrp(pp - nv, nx))) / dxv(jv);
+      if (jv >= 1) aV += amV(jv - 1, k, i) * vts(jv, k, i) / dyv(jv - 1);
+      if (jv + 1 <= ny - 1) aV -= amV(jv + 1, k, i) * vts(jv + 1, k, i) / dyv(jv + 1);
+      if (k >= 1) aV += amV(jv, k - 1, i) * 0.5 * (sd(jv, k, i) + sd(jv + 1, k, i)) / (2.0 * g.dsig[k - 1]);
+      if (k + 1 < nz)
+        aV -= amV(jv, k + 1, i) * 0.5 * (sd(jv, k + 1, i) + sd(jv + 1, k + 1, i)) / (2.0 * g.dsig[k + 1]);
+    }
+    c.s.AVD[id] = (T)aV;
+    // adjoint of v sin(theta) on this V row
+    C avt = 0;
+    if (interior(jv)) avt += amF(jv, k, i) * (C)Fe(c, jv + 1, k, i) / dyr(jv);
+    if (interior(jv + 1)) avt -= amF(jv + 1, k, i) * (C)Fe(c, jv, k, i) / dyr(jv + 1);
+    if (jv == 0) avt += cc * (C)Fe(c, 1, k, i) * AN;
+    if (jv == ny - 1) avt -= cc * (C)Fe(c, ny - 1, k, i) * AS;
+    auto avtu = [&](int p) -> C {
+      C r = 0;
+      if (interior(jv)) r += amU(jv, k, p) * (C)Ue(c, jv + 1, k, p) / dyr(jv);
+      if (interior(jv + 1)) r -= amU(jv + 1, k, p) * (C)Ue(c, jv, k, p) / dyr(jv + 1);
+      return r;
+    };
+    avt += 0.5 * (avtu(i) + avtu(wrp(i - 1, nx)));
+    auto avts = [&](int js) -> C {
+      if (js <= 0 || js >= ny) return 0.0;
+      return amV(js - 1, k, i) * (C)Ve(c, js, k, i) / dyv(js - 1) - amV(js, k, i) * (C)Ve(c, js - 1, k, i) / dyv(js);
+    };
+    avt += 0.5 * (avts(jv) + avts(jv + 1));
+    c.s.AVV[id] = (T)(avt * g.sv[jv]);
+  }
+  // ---- half level h = k (1..nz-1): adjoint of sigma-dot of scalar row j
+  if (k >= 1) {
+    const int h = k;
+    C a = 0;
+    a += amF(j, h - 1, i) * (C)Fe(c, j, h, i) / (2.0 * g.dsig[h - 1]) -
+         amF(j, h, i) * (C)Fe(c, j, h - 1, i) / (2.0 * g.dsig[h]);
+    if (interior(j)) {
+      auto asdu = [&](int p) -> C {
+        return amU(j, h - 1, p) * (C)Ue(c, j, h, p) / (2.0 * g.dsig[h - 1]) -
+               amU(j, h, p) * (C)Ue(c, j, h - 1, p) / (2.0 * g.dsig[h]);
+      };
+      a += 0.5 * (asdu(i) + asdu(wrp(i - 1, nx)));
+    }
+    auto asdv = [&](int jv) -> C {
+      return amV(jv, h - 1, i) * (C)Ve(c, jv, h, i) / (2.0 * g.dsig[h - 1]) -
+             amV(jv, h, i) * (C)Ve(c, jv, h - 1, i) / (2.0 * g.dsig[h]);
+    };
+    if (j >= 1) a += 0.5 * asdv(j - 1);
+    if (j <= ny - 1) a += 0.5 * asdv(j);
+    c.s.ASD[ih<T>(g, j, h, i)] = (T)a;
+  }
+}
+
+// sigma-dot transposes per column: aPi, aS_h, aP; then aD_l = dsig_l (aPi + sum_{h>l} aS_h)
+template <typename T>
+__global__ void k_l2(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nz = g.nz;
+  const C P = (C)P2(c, j, i), P2c = P * P;
+  const C Pi = (C)c.s.S[ih<T>(g, j, nz, i)];
+  C aPi = 0, aP = 0;
+  for (int h = 1; h < nz; ++h) {
+    const C a = (C)c.s.ASD[ih<T>(g, j, h, i)];
+    aPi += g.sigh[h] * a / P2c;
+    aP += -2.0 * (g.sigh[h] * Pi - (C)c.s.S[ih<T>(g, j, h, i)]) / (P2c * P) * a;
+  }
+  C acc = 0;   // sum_{h > l} aS_h, aS_h = -asd_h / P^2
+  for (int l = nz - 1; l >= 0; --l) {
+    c.s.AD[i3<T>(g, j, l, i)] = (T)(g.dsig[l] * (aPi + acc));
+    if (l >= 1) acc += -(C)c.s.ASD[ih<T>(g, j, l, i)] / P2c;
+  }
+  c.s.AP2[(size_t)j * g.nx + i] = aP;
+}
+
+// ------------------------------------------------------------------------------------------------
+// common tail: divergence and velocity transposes into U and V, staggered-P accumulations
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_t1(Ctx<T> c, int accumulate) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const size_t id = i3<T>(g, j, k, i);
+  const double* sD = c.s.psum + PS_AD * 2 * (nz + 1);
+  if (j >= 1 && j < ny) {
+    const int M = g.M[j], n = (M + 1) / 2;
+    const C dx = (C)(T)((double)M * g.a * g.s[j] * g.dlam);
+    const C aMU = ((C)c.s.AD[i3<T>(g, j, k, wrp(i - n + 1, nx))] - (C)c.s.AD[i3<T>(g, j, k, wrp(i + n, nx))]) / dx;
+    const C PU = (C)PUe(c, j, i), U = (C)c.U[id];
+    const C au = (C)c.s.AUU[id];
+    c.aiU[id] = (T)((C)c.aiU[id] + (C)c.s.AUD[id] + au / PU + PU * aMU);
+    c.s.APU3[id] = (T)((accumulate ? (C)c.s.APU3[id] : 0.0) - U / (PU * PU) * au + U * aMU);
+  }
+  if (j < ny) {
+    const int jv = j;
+    const C tN = (jv >= 1) ? (C)c.s.AD[i3<T>(g, jv, k, i)] / (C)(T)(g.a * g.s[jv] * g.dth)
+                           : g.a * g.dlam / g.acap * sD[0 * (nz + 1) + k];
+    const C tS = (jv + 1 <= ny - 1) ? (C)c.s.AD[i3<T>(g, jv + 1, k, i)] / (C)(T)(g.a * g.s[jv + 1] * g.dth)
+                                    : g.a * g.dlam / g.acap * sD[1 * (nz + 1) + k];
+    const C aMV = (C)(T)g.sv[jv] * (tN - tS);
+    const C PV = (C)PVe(c, jv, i), V = (C)c.V[id];
+    const C av = (C)c.s.AVV[id];
+    c.aiV[id] = (T)((C)c.aiV[id] + (C)c.s.AVD[id] + av / PV + PV * aMV);
+    c.s.APV3[id] = (T)((accumulate ? (C)c.s.APV3[id] : 0.0) - V / (PV * PV) * av + V * aMV);
+  }
+}
+
+// column sums; for the adaptation also the hydrostatic transpose phi' -> R T' -> (Phi, P)
+template <typename T>
+__global__ void k_t2(Ctx<T> c, int adapt) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const T b = (T)g.b;
+  const C P = (C)P2(c, j, i);
+  const bool intr = (j >= 1 && j < ny);
+  C aP = adapt ? 0.0 : c.s.AP2[(size_t)j * nx + i];
+  C aPU = 0, aPV = 0, aL = 0, aQ = 0, aDL = 0, aDQ = 0;
+  C pre = 0;
+  for (int k = 0; k < nz; ++k) {
+    const size_t id = i3<T>(g, j, k, i);
+    C afe = (C)c.s.AFE[id];
+    if (adapt) {
+      const C aphi = (C)c.s.APHI[id];
+      const C art = (C)c.s.ART[id] + g.cl[k] * pre + g.cpk[k] * aphi;
+      pre += aphi;
+      afe += (C)b / P * art;
+      aP += (C)c.s.AP3[id] - (C)b * (C)Fe(c, j, k, i) / (P * P) * art;
+      aL += (C)c.s.AL3[id];
+      aQ += (C)c.s.AQ3[id];
+      if (intr) { aDL += (C)c.s.ADL3[id]; aDQ += (C)c.s.ADQ3[id]; }
+    }
+    if (intr) {
+      aPU += (C)c.s.APU3[id];
+      c.aiF[id] = (T)((C)c.aiF[id] + afe);
+    } else {
+      c.s.AFE[id] = (T)afe;     // pole copies: aggregated later
+    }
+    if (j < ny) aPV += (C)c.s.APV3[id];
+  }
+  const size_t i2 = (size_t)j * nx + i;
+  c.s.AP2[i2] = aP;
+  c.s.APU2[i2] = aPU;
+  c.s.APV2[i2] = aPV;
+  c.s.AL2[i2] = aL;
+  c.s.AQ2[i2] = aQ;
+  c.s.ADL2[i2] = aDL;
+  c.s.ADQ2[i2] = aDQ;
+}
+
+// 2D: staggered P, the leaped d+ transposes for l and q, then p_s
+template <typename T>
+__global__ void k_t3(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny;
+  const size_t i2 = (size_t)j * nx + i;
+  const int im1 = wrp(i - 1, nx);
+  C aP = c.s.AP2[i2];
+  if (j >= 1 && j < ny) aP += 0.5 * (c.s.APU2[i2] + c.s.APU2[(size_t)j * nx + im1]);
+  if (j <= ny - 1) aP += 0.5 * c.s.APV2[i2];
+  if (j >= 1) aP += 0.5 * c.s.APV2[(size_t)(j - 1) * nx + i];
+  C aQ = c.s.AQ2[i2];
+  C aL = c.s.AL2[i2];
+  if (j >= 1 && j < ny) {
+    const int M = g.M[j], n = (M + 1) / 2;
+    const C dx = (C)(T)((double)M * g.a * g.s[j] * g.dlam);
+    const int ra = wrp(i - n, nx), rb = wrp(i + n - 1, nx);
+    aQ += (c.s.ADQ2[(size_t)j * nx + ra] - c.s.ADQ2[(size_t)j * nx + rb]) / dx;
+    aL += (c.s.ADL2[(size_t)j * nx + ra] - c.s.ADL2[(size_t)j * nx + rb]) / dx;
+  }
+  aL += aQ;
+  const C Pv = (C)P2(c, j, i);
+  const C ps = (C)psE(c, j, i);
+  const C aps = aP / (2.0 * g.p0 * Pv) + aL / ps;
+  if (j >= 1 && j < ny) c.aiP[i2] = (T)((C)c.aiP[i2] + aps);
+  else c.s.APSR[i2] = aps;
+}
+
+// pole rows: spread the FP64 row sums of the pole-copy adjoints over the stored row
+template <typename T>
+__global__ void k_t4(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int p = blockIdx.y, k = blockIdx.x;   // k in 0..nz (nz = p_s)
+  const int j = p == 0 ? 0 : g.ny;
+  __shared__ double red[16];
+  C s = 0;
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x)
+    s += (k < g.nz) ? (C)c.s.AFE[i3<T>(g, j, k, i)] : c.s.APSR[(size_t)j * g.nx + i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  C tot = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
+  const T add = (T)(tot / g.nx);
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+    if (k < g.nz) c.aiF[i3<T>(g, j, k, i)] += add;
+    else c.aiP[(size_t)j * g.nx + i] += add;
+  }
+}
+
+template <typename T>
+hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s) {
+  const GeoDev& g = c.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int tb = 256;
+  const int gx = (nx + tb - 1) / tb;
+  const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1), gcol_int(gx, ny - 1);
+  hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_f1p<T>), dim3(2), dim3(64), 0, s, c);
+  hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
+                     c.s.psum + PS_AOF * 2 * (nz + 1));
+  hipLaunchKernelGGL((k_base_pole<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
+  // (process-specific part is launched by the caller between these two groups)
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
+  const GeoDev& g = c.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int tb = 256;
+  const int gx = (nx + tb - 1) / tb;
+  const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
+  hipLaunchKernelGGL((k_a1<T>), g3, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_a2<T>), g2, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
+                     c.s.psum + PS_AD * 2 * (nz + 1));
+  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL, (const T*)nullptr,
+                     c.s.psum + PS_AVGL * 2 * (nz + 1));
+  hipLaunchKernelGGL((k_a3<T>), g3, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_t1<T>), g3, dim3(tb), 0, s, c, 1);
+  hipLaunchKernelGGL((k_t2<T>), g2, dim3(tb), 0, s, c, 1);
+  hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
+  const GeoDev& g = c.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int tb = 256;
+  const int gx = (nx + tb - 1) / tb;
+  const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
+  hipLaunchKernelGGL((k_l1<T>), g3, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_l2<T>), g2, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
+                     c.s.psum + PS_AD * 2 * (nz + 1));
+  hipLaunchKernelGGL((k_t1<T>), g3, dim3(tb), 0, s, c, 0);
+  hipLaunchKernelGGL((k_t2<T>), g2, dim3(tb), 0, s, c, 0);
+  hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// workspace and driver (the handle layout is private to api.hip; it exposes what we need here)
+// ------------------------------------------------------------------------------------------------
 struct dycore_s;
-size_t dyc_adjoint_workspace_bytes(const dycore_s* h) { (void)h; return 256; }
+namespace dyc {
+struct HandleView {
+  GeoDev g;
+  int prec, msub;
+  double dt;
+  size_t nU, nV, nF, nP, elem, state_bytes;
+  void* adj;
+  size_t adj_bytes;
+  double* pole;      // pole slots of the handle
+  void* scratch;     // forward scratch y1, y2
+  int block;
+};
+HandleView view_of(const dycore_s* h);
+}  // namespace dyc
+
+namespace {
+
+size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+constexpr int kN3 = 26;   // 3D scalar-size scratch fields (4 forward + 22 adjoint)
+constexpr int kNH = 3;    // half-level fields
+constexpr int kN2T = 5;   // 2D T fields
+constexpr int kN2D = 8;   // 2D FP64 fields
+
+struct Layout {
+  size_t n3, nh, n2, state;
+  size_t traj_off, lam_off, f3_off, fh_off, f2t_off, f2d_off, psum_off, pole_off, total;
+};
+
+Layout layout(const HandleView& v) {
+  Layout L;
+  const GeoDev& g = v.g;
+  L.n3 = (size_t)(g.ny + 1) * g.nz * g.nx;
+  L.nh = (size_t)(g.ny + 1) * (g.nz + 1) * g.nx;
+  L.n2 = (size_t)(g.ny + 1) * g.nx;
+  L.state = v.state_bytes;
+  const int nst = 3 * (v.msub + 1);
+  size_t o = 0;
+  L.traj_off = o; o += (size_t)nst * L.state;
+  L.lam_off = o; o += 3 * L.state;
+  L.f3_off = o; o += kN3 * a256(L.n3 * v.elem);
+  L.fh_off = o; o += kNH * a256(L.nh * v.elem);
+  L.f2t_off = o; o += kN2T * a256(L.n2 * v.elem);
+  L.f2d_off = o; o += kN2D * a256(L.n2 * 8);
+  L.psum_off = o; o += a256(8 * 2 * (g.nz + 1) * 8);
+  L.pole_off = o; o += a256(4 * 2 * (g.nz + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+Scr<T> scratch_of(const HandleView& v) {
+  const Layout L = layout(v);
+  char* base = static_cast<char*>(v.adj);
+  Scr<T> s;
+  T* f3[kN3];
+  for (int q = 0; q < kN3; ++q) f3[q] = reinterpret_cast<T*>(base + L.f3_off + q * a256(L.n3 * v.elem));
+  s.RT = f3[0]; s.PHI = f3[1]; s.D = f3[2]; s.WP = f3[3];
+  s.AVGL = f3[4]; s.ASK = f3[5]; s.AD = f3[6]; s.AFE = f3[7]; s.AP3 = f3[8]; s.HH = f3[9]; s.FU = f3[10];
+  s.AUU = f3[11]; s.AUD = f3[12]; s.MV = f3[13]; s.FV = f3[14]; s.UV = f3[15]; s.AVV = f3[16]; s.AVD = f3[17];
+  s.APU3 = f3[18]; s.APV3 = f3[19]; s.APHI = f3[20]; s.ART = f3[21]; s.AL3 = f3[22]; s.AQ3 = f3[23];
+  s.ADL3 = f3[24]; s.ADQ3 = f3[25];
+  T* fh[kNH];
+  for (int q = 0; q < kNH; ++q) fh[q] = reinterpret_cast<T*>(base + L.fh_off + q * a256(L.nh * v.elem));
+  s.S = fh[0]; s.SD = fh[1]; s.ASD = fh[2];
+  T* f2[kN2T];
+  for (int q = 0; q < kN2T; ++q) f2[q] = reinterpret_cast<T*>(base + L.f2t_off + q * a256(L.n2 * v.elem));
+  s.P = f2[0]; s.L = f2[1]; s.Q = f2[2]; s.DL = f2[3]; s.DQ = f2[4];
+  double* d2[kN2D];
+  for (int q = 0; q < kN2D; ++q) d2[q] = reinterpret_cast<double*>(base + L.f2d_off + q * a256(L.n2 * 8));
+  s.AP2 = d2[0]; s.APU2 = d2[1]; s.APV2 = d2[2]; s.AL2 = d2[3]; s.AQ2 = d2[4]; s.ADL2 = d2[5]; s.ADQ2 = d2[6];
+  s.APSR = d2[7];
+  s.psum = reinterpret_cast<double*>(base + L.psum_off);
+  return s;
+}
+
+template <typename T>
+struct St4 { T* U; T* V; T* F; T* P; };
+
+template <typename T>
+St4<T> state_at(const HandleView& v, void* base) {
+  char* c = static_cast<char*>(base);
+  St4<T> s;
+  s.U = reinterpret_cast<T*>(c); c += a256(v.nU * sizeof(T));
+  s.V = reinterpret_cast<T*>(c); c += a256(v.nV * sizeof(T));
+  s.F = reinterpret_cast<T*>(c); c += a256(v.nF * sizeof(T));
+  s.P = reinterpret_cast<T*>(c);
+  return s;
+}
+
+template <typename T>
+hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<const T> y, St4<const T> ao,
+                              St4<T> ab, St4<T> ai, double* pin, hipStream_t s) {
+  Ctx<T> c;
+  c.g = v.g;
+  c.U = y.U; c.V = y.V; c.F = y.F; c.P = y.P;
+  c.aoU = ao.U; c.aoV = ao.V; c.aoF = ao.F; c.aoP = ao.P;
+  c.abU = ab.U; c.abV = ab.V; c.abF = ab.F; c.abP = ab.P;
+  c.aiU = ai.U; c.aiV = ai.V; c.aiF = ai.F; c.aiP = ai.P;
+  c.pin = pin;
+  c.ch = ch;
+  c.s = scratch_of<T>(v);
+  hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
+  if (e != hipSuccess) return e;
+  e = run_stage_adjoint<T>(c, s);
+  if (e != hipSuccess) return e;
+  return process == 0 ? run_adapt<T>(c, s) : run_advect<T>(c, s);
+}
+
+template <typename T>
+hipError_t zero_state(const HandleView& v, St4<T> a, hipStream_t s) {
+  hipError_t e = launch_zero<T>(a.U, v.nU, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.V, v.nV, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.F, v.nF, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.P, v.nP, s);
+  return e;
+}
+
+template <typename T>
+hipError_t copy_state(const HandleView& v, St4<T> d, St4<const T> src, hipStream_t s) {
+  hipError_t e = launch_axpy_fill<T>(d.U, src.U, v.nU, s);
+  if (e == hipSuccess) e = launch_axpy_fill<T>(d.V, src.V, v.nV, s);
+  if (e == hipSuccess) e = launch_axpy_fill<T>(d.F, src.F, v.nF, s);
+  if (e == hipSuccess) e = launch_axpy_fill<T>(d.P, src.P, v.nP, s);
+  return e;
+}
+
+template <typename T>
+St4<const T> cst(St4<T> a) { return St4<const T>{a.U, a.V, a.F, a.P}; }
+
+template <typename T>
+int step_adjoint_impl(const HandleView& v, St4<const T> y0, St4<T> lam, hipStream_t s) {
+  const Layout L = layout(v);
+  char* base = static_cast<char*>(v.adj);
+  const int nrk = v.msub + 1;
+  auto traj = [&](int q) { return state_at<T>(v, base + L.traj_off + (size_t)q * L.state); };
+  St4<T> lacc = state_at<T>(v, base + L.lam_off);
+  St4<T> l1 = state_at<T>(v, base + L.lam_off + L.state);
+  St4<T> l2 = state_at<T>(v, base + L.lam_off + 2 * L.state);
+  double* pole = reinterpret_cast<double*>(base + L.pole_off);   // [4][2][nz+1]
+  const size_t ps = 2 * (v.g.nz + 1);
+  hipError_t e;
+  // forward recompute of every stage input: traj[3 rk] = y_rk, traj[3 rk + 1] = y1, traj[3 rk + 2] = y2
+  e = copy_state<T>(v, traj(0), y0, s);
+  if (e != hipSuccess) return DYCORE_EHIP;
+  e = launch_pole_prep<T>(v.g, traj(0).F, traj(0).P, pole, s);
+  if (e != hipSuccess) return DYCORE_EHIP;
+  for (int rk = 0; rk < nrk; ++rk) {
+    const int proc = rk < v.msub ? 0 : 1;
+    const double h = proc == 0 ? v.dt / v.msub : v.dt;
+    St4<T> y = traj(3 * rk), y1 = traj(3 * rk + 1), y2 = traj(3 * rk + 2);
+    auto mk = [&](double chh, St4<T> in, St4<T> out, double* pin, double* pout) {
+      StageArgs<T> a;
+      a.g = v.g;
+      a.inU = in.U; a.inV = in.V; a.inF = in.F; a.inP = in.P;
+      a.bU = y.U; a.bV = y.V; a.bF = y.F; a.bP = y.P;
+      a.oU = out.U; a.oV = out.V; a.oF = out.F; a.oP = out.P;
+      a.pin = pin; a.pbase = pole; a.pout = pout;
+      a.ch = chh;
+      a.process = proc;
+      a.pad = 0;
+      return a;
+    };
+    e = launch_stage<T>(mk(h / 3.0, y, y1, pole, pole + ps), v.block, s);
+    if (e == hipSuccess) e = launch_stage<T>(mk(h / 2.0, y1, y2, pole + ps, pole + 2 * ps), v.block, s);
+    if (e == hipSuccess && rk + 1 < nrk) {
+      St4<T> yn = traj(3 * (rk + 1));
+      e = launch_stage<T>(mk(h, y2, yn, pole + 2 * ps, pole + 3 * ps), v.block, s);
+      if (e == hipSuccess) e = launch_axpy_fill<double>(pole, pole + 3 * ps, ps, s);
+    }
+    if (e != hipSuccess) return DYCORE_EHIP;
+  }
+  // reverse sweep
+  double* pin = pole + 3 * ps;
+  for (int rk = nrk - 1; rk >= 0; --rk) {
+    const int proc = rk < v.msub ? 0 : 1;
+    const double h = proc == 0 ? v.dt / v.msub : v.dt;
+    St4<T> y = traj(3 * rk), y1 = traj(3 * rk + 1), y2 = traj(3 * rk + 2);
+    e = zero_state<T>(v, lacc, s);
+    if (e == hipSuccess) e = zero_state<T>(v, l1, s);
+    if (e == hipSuccess) e = zero_state<T>(v, l2, s);
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), lacc, l2, pin, s);
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lacc, l1, pin, s);
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lacc, lacc, pin, s);
+    if (e == hipSuccess) e = copy_state<T>(v, lam, cst(lacc), s);
+    if (e != hipSuccess) return DYCORE_EHIP;
+  }
+  return DYCORE_OK;
+}
+
+}  // namespace
+
+size_t dyc_adjoint_workspace_bytes(const dycore_s* h) { return layout(view_of(h)).total; }
 
 extern "C" {
-int dycore_step_adjoint(dycore_t h, const void*, const void*, const void*, const void*, void*, void*, void*, void*,
-                        void*) {
-  return h ? DYCORE_EUNSUPPORTED : DYCORE_EINVAL;
+
+int dycore_step_adjoint(dycore_t h, const void* U0, const void* V0, const void* Phi0, const void* ps0, void* aU,
+                        void* aV, void* aPhi, void* aps, void* stream) {
+  if (!h || !U0 || !V0 || !Phi0 || !ps0 || !aU || !aV || !aPhi || !aps) return DYCORE_EINVAL;
+  const HandleView v = view_of(h);
+  if (!v.adj) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (v.prec == DYCORE_FP32)
+    return step_adjoint_impl<float>(v, St4<const float>{(const float*)U0, (const float*)V0, (const float*)Phi0,
+                                                        (const float*)ps0},
+                                    St4<float>{(float*)aU, (float*)aV, (float*)aPhi, (float*)aps}, s);
+  return step_adjoint_impl<double>(v, St4<const double>{(const double*)U0, (const double*)V0, (const double*)Phi0,
+                                                        (const double*)ps0},
+                                   St4<double>{(double*)aU, (double*)aV, (double*)aPhi, (double*)aps}, s);
 }
-int dycore_stage_adjoint(dycore_t h, int, double, const void*, const void*, const void*, const void*, const void*,
-                         const void*, const void*, const void*, void*, void*, void*, void*, void*, void*, void*,
-                         void*, void*) {
-  return h ? DYCORE_EUNSUPPORTED : DYCORE_EINVAL;
+
+int dycore_stage_adjoint(dycore_t h, int process, double ch, const void* U, const void* V, const void* Phi,
+                         const void* ps, const void* aoU, const void* aoV, const void* aoPhi, const void* aops,
+                         void* abU, void* abV, void* abPhi, void* abps, void* aiU, void* aiV, void* aiPhi,
+                         void* aips, void* stream) {
+  if (!h || (process != 0 && process != 1)) return DYCORE_EINVAL;
+  const void* ptrs[16] = {U, V, Phi, ps, aoU, aoV, aoPhi, aops, abU, abV, abPhi, abps, aiU, aiV, aiPhi, aips};
+  for (auto p : ptrs)
+    if (!p) return DYCORE_EINVAL;
+  const HandleView v = view_of(h);
+  if (!v.adj) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout L = layout(v);
+  double* pin = reinterpret_cast<double*>(static_cast<char*>(v.adj) + L.pole_off);
+  hipError_t e;
+  if (v.prec == DYCORE_FP32) {
+    using T = float;
+    e = stage_adjoint_impl<T>(v, process, ch, St4<const T>{(const T*)U, (const T*)V, (const T*)Phi, (const T*)ps},
+                              St4<const T>{(const T*)aoU, (const T*)aoV, (const T*)aoPhi, (const T*)aops},
+                              St4<T>{(T*)abU, (T*)abV, (T*)abPhi, (T*)abps}, St4<T>{(T*)aiU, (T*)aiV, (T*)aiPhi, (T*)aips},
+                              pin, s);
+  } else {
+    using T = double;
+    e = stage_adjoint_impl<T>(v, process, ch, St4<const T>{(const T*)U, (const T*)V, (const T*)Phi, (const T*)ps},
+                              St4<const T>{(const T*)aoU, (const T*)aoV, (const T*)aoPhi, (const T*)aops},
+                              St4<T>{(T*)abU, (T*)abV, (T*)abPhi, (T*)abps}, St4<T>{(T*)aiU, (T*)aiV, (T*)aiPhi, (T*)aips},
+                              pin, s);
+  }
+  return e == hipSuccess ? DYCORE_OK : DYCORE_EHIP;
 }
-}
+
+}  // extern "C"

@@ -45,6 +45,20 @@ struct dycore_s {
 };
 
 size_t dyc_adjoint_workspace_bytes(const dycore_s* h);
+namespace dyc {
+struct HandleView {
+  GeoDev g;
+  int prec, msub;
+  double dt;
+  size_t nU, nV, nF, nP, elem, state_bytes;
+  void* adj;
+  size_t adj_bytes;
+  double* pole;
+  void* scratch;
+  int block;
+};
+HandleView view_of(const dycore_s* h);
+}  // namespace dyc
 
 struct dycore_batch_s {
   int n, prec, block, grid, max_nx, nstage_max;
@@ -227,6 +241,23 @@ int validate_cfg(const dycore_config* c) {
 }
 
 }  // namespace
+
+dyc::HandleView dyc::view_of(const dycore_s* h) {
+  HandleView v;
+  v.g = h->g;
+  v.prec = h->prec;
+  v.msub = h->msub;
+  v.dt = h->dt;
+  v.nU = h->nU; v.nV = h->nV; v.nF = h->nF; v.nP = h->nP;
+  v.elem = h->elem;
+  v.state_bytes = h->state_bytes;
+  v.adj = h->adj;
+  v.adj_bytes = h->adj_bytes;
+  v.pole = h->pole;
+  v.scratch = h->scratch;
+  v.block = h->block;
+  return v;
+}
 
 extern "C" {
 

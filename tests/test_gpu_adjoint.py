@@ -1,0 +1,153 @@
+"""GPU parity of the hand-written adjoint (stage and outer step) against the FP64 oracle adjoint,
+plus the dot-product test against the oracle's complex-step tangent-linear and central finite
+differences of the GPU forward step."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_10114_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _core(cfg, st, prec, **kw):
+    from paper_2103_10114_amd import Dycore
+    return Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec=prec, phis=st["phis"], **kw)
+
+
+def _host(d):
+    return {k: v.detach().cpu().numpy().astype(np.float64) for k, v in d.items()}
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def small(nx, ny, nz, seed=3, degree=5):
+    return dataclasses.replace(synth.CONFIGS["c1"], nx=nx, ny=ny, nz=nz, degree=degree, seed=seed)
+
+
+GRIDS = [small(16, 8, 3), small(40, 20, 4), small(130, 66, 5)]
+
+
+@pytest.mark.parametrize("cfg", GRIDS, ids=lambda c: f"{c.nx}x{c.ny}x{c.nz}")
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_stage_adjoint_fp64(cfg, process):
+    """Adjoint of one stage (base and input parts) in FP64 equals the oracle's to 1e-12 relative."""
+    print(f"stage adjoint fp64 {cfg.nx}x{cfg.ny}x{cfg.nz} {process}", flush=True)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    ao = synth.random_like(st, 21)
+    ch = 250.0
+    wb, wi = o.adj_stage(st, ao, ch, process)
+    core = _core(cfg, st, "fp64")
+    d = core.to_device(st)
+    a = core.to_device(ao)
+    ab = {k: torch.zeros_like(v) for k, v in d.items()}
+    ai = {k: torch.zeros_like(v) for k, v in d.items()}
+    core.stage_adjoint(process, ch, d, a, ab, ai)
+    gb, gi = _host(ab), _host(ai)
+    for k in ("U", "V", "Phi", "ps"):
+        assert _rel(gb[k], wb[k]) < 1e-12, ("base", k, _rel(gb[k], wb[k]))
+        assert _rel(gi[k], wi[k]) < 1e-12, ("in", k, _rel(gi[k], wi[k]))
+
+
+@pytest.mark.parametrize("cfg", GRIDS + [synth.CONFIGS["c1"]], ids=lambda c: f"{c.nx}x{c.ny}x{c.nz}")
+def test_step_adjoint_fp64(cfg):
+    """Adjoint of a whole outer step (recompute + 3M + 3 reversed stages) equals the oracle's."""
+    print(f"step adjoint fp64 {cfg.nx}x{cfg.ny}x{cfg.nz}", flush=True)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    lam = synth.random_like(st, 22)
+    want = o.adj_step(st, lam, cfg.dt)
+    core = _core(cfg, st, "fp64")
+    a = core.to_device(lam)
+    core.step_adjoint(core.to_device(st), a)
+    got = _host(a)
+    for k in ("U", "V", "Phi", "ps"):
+        assert _rel(got[k], want[k]) < 1e-11, (k, _rel(got[k], want[k]))
+
+
+def test_dot_product_c3_fp64():
+    """C3 (720x360x30): <J x, y> with J x from the oracle's complex-step tangent-linear against
+    <x, J^T y> from the GPU adjoint in FP64 mode, seeded unit-variance x and y: <= 1e-10 relative."""
+    cfg = synth.CONFIGS["c3"]
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    x = synth.random_like(st, 1031)
+    y = synth.random_like(st, 1032)
+    print("oracle complex-step TL at C3 ...", flush=True)
+    jx = o.tl_step(st, x, cfg.dt)
+    core = _core(cfg, st, "fp64")
+    a = core.to_device(y)
+    core.step_adjoint(core.to_device(st), a)
+    jty = _host(a)
+    lhs = oracle.dot(jx, y)
+    rhs = oracle.dot(x, jty)
+    rel = abs(lhs - rhs) / abs(lhs)
+    print(f"C3 dot test fp64: <Jx,y>={lhs:.17e} <x,JTy>={rhs:.17e} rel={rel:.3e}", flush=True)
+    assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("eps_rel,tol", [(1e-6, 1e-4), (1e-4, 1e-6)])
+def test_fd_c3_fp64(eps_rel, tol):
+    """C3: central differences of the GPU FP64 forward step at 64 seeded grid points against the GPU
+    adjoint gradient of <y, step(x)>.  With eps = 1e-6 of the field RMS the difference quotient carries
+    FP64 rounding noise of the perturbed outputs (|p_s| ~ 1e5 Pa over the step's domain of dependence)
+    of order 1e-5 relative, so it is checked to 1e-4; with eps = 1e-4 the noise falls 100-fold while
+    the truncation error stays near eps^2 ~ 1e-8, and the check is 1e-6."""
+    cfg = synth.CONFIGS["c3"]
+    st = synth.make_state(cfg)
+    core = _core(cfg, st, "fp64")
+    y = synth.random_like(st, 1032)
+    a = core.to_device(y)
+    core.step_adjoint(core.to_device(st), a)
+    grad = _host(a)
+    yd = core.to_device(y)
+    rng = np.random.default_rng(1033)
+    keys = ["U", "V", "Phi", "ps"]
+    worst = 0.0
+    for t in range(64):
+        key = keys[t % 4]
+        shp = st[key].shape
+        idx = [int(rng.integers(0, s)) for s in shp]
+        if key in ("U", "Phi", "ps"):
+            idx[0] = int(rng.integers(1, shp[0] - 1))   # interior rows (pole rows are row means)
+        idx = tuple(idx)
+        eps = eps_rel * float(np.sqrt(np.mean(st[key] ** 2)))
+        outs = []
+        for sgn in (1.0, -1.0):
+            d = core.to_device(st)
+            d[key][idx] += sgn * eps
+            core.step(d, 1)
+            outs.append(d)
+        # difference the perturbed outputs first, then take the inner product (no cancellation)
+        fd = sum(float(torch.sum((outs[0][k] - outs[1][k]) * yd[k])) for k in keys) / (2 * eps)
+        g = grad[key][idx]
+        err = abs(fd - g) / max(abs(g), abs(fd), 1e-300)
+        worst = max(worst, err)
+        assert abs(fd - g) <= tol * max(abs(g), abs(fd)) + 1e-9 * np.abs(grad[key]).max(), (key, idx, fd, g)
+    print(f"C3 FD check fp64 eps={eps_rel:g}: worst relative difference {worst:.3e}", flush=True)
+
+
+def test_adjoint_fp32_vs_fp64():
+    """FP32-mode adjoint (FP32 storage, FP64 sums) against the FP64-mode adjoint at 130x66x5."""
+    cfg = GRIDS[2]
+    st = synth.make_state(cfg)
+    st32 = {k: st[k].astype(np.float32).astype(np.float64) for k in ("U", "V", "Phi", "ps")}
+    lam = synth.random_like(st, 23)
+    c64 = _core(cfg, st, "fp64")
+    a64 = c64.to_device(lam)
+    c64.step_adjoint(c64.to_device(st32), a64)
+    c32 = _core(cfg, st, "fp32")
+    a32 = c32.to_device(lam)
+    c32.step_adjoint(c32.to_device(st32), a32)
+    g64, g32 = _host(a64), _host(a32)
+    for k in ("U", "V", "Phi", "ps"):
+        l2 = np.linalg.norm(g32[k] - g64[k]) / np.linalg.norm(g64[k])
+        print(f"adjoint fp32 vs fp64 {k}: rel-L2 {l2:.3e}", flush=True)
+        assert l2 < 1e-3
