@@ -188,7 +188,7 @@ def main():
         kh = kernel_source_hash()
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kh),
-                           "kernel": "k_stage<float,6,0> (adaptation stage)",
+                           "kernel": f"k_stage<float,{-(-cfg.nx // core.block)},0> (adaptation stage)",
                            "avg_launch_ms": ms["A"], "advection_launch_ms": ms["L"],
                            "alg_bytes_per_launch": alg, "kernel_hash": kh}
     del core, d

@@ -234,3 +234,91 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------------------------------
+# autograd and multi-step adjoint windows
+# ------------------------------------------------------------------------------------------------
+def _clone(st):
+    return {k: st[k].clone() for k in KEYS}
+
+
+class _StepFn:
+    """torch.autograd.Function for one outer step (built lazily so that importing the package does
+    not import torch)."""
+    _cls = None
+
+    @classmethod
+    def get(cls):
+        if cls._cls is None:
+            import torch
+
+            class DycoreStep(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, core, U, V, Phi, ps):
+                    st0 = {"U": U.detach().contiguous(), "V": V.detach().contiguous(),
+                           "Phi": Phi.detach().contiguous(), "ps": ps.detach().contiguous()}
+                    out = _clone(st0)
+                    core.step(out, 1)
+                    ctx.core = core
+                    ctx.save_for_backward(st0["U"], st0["V"], st0["Phi"], st0["ps"])
+                    return out["U"], out["V"], out["Phi"], out["ps"]
+
+                @staticmethod
+                def backward(ctx, gU, gV, gPhi, gps):
+                    U, V, Phi, ps = ctx.saved_tensors
+                    core = ctx.core
+                    lam = {}
+                    for k, gk, ref in (("U", gU, U), ("V", gV, V), ("Phi", gPhi, Phi), ("ps", gps, ps)):
+                        lam[k] = (gk if gk is not None else torch.zeros_like(ref)).contiguous().clone()
+                    core.step_adjoint({"U": U, "V": V, "Phi": Phi, "ps": ps}, lam)
+                    return None, lam["U"], lam["V"], lam["Phi"], lam["ps"]
+
+            cls._cls = DycoreStep
+        return cls._cls
+
+
+def dycore_step_fn(core, U, V, Phi, ps):
+    """Differentiable outer step: returns (U, V, Phi, ps) after one step; backward runs the
+    hand-written adjoint kernels."""
+    return _StepFn.get().apply(core, U, V, Phi, ps)
+
+
+def adjoint_window(core, state, nsteps, lam, ckpt_every=8, keep_trajectory=False):
+    """Adjoint of nsteps outer steps starting at `state`: lam (adjoint of the final state) is
+    replaced by the adjoint of the initial state.  Checkpoints are kept every ckpt_every steps;
+    each window's step-start states are recomputed from its checkpoint in the reverse pass
+    (keep_trajectory=True stores every step-start state instead).  Returns the final state and a
+    dict with the checkpoint and window memory in bytes."""
+    import torch
+    nbytes = sum(state[k].numel() * state[k].element_size() for k in KEYS)
+    y = _clone(state)
+    ckpts = {}
+    traj = {}
+    for n in range(nsteps):
+        if keep_trajectory:
+            traj[n] = _clone(y)
+        elif n % ckpt_every == 0:
+            ckpts[n] = _clone(y)
+        core.step(y, 1)
+    final = y
+    mem = {"state_bytes": nbytes, "checkpoints": len(ckpts), "checkpoint_bytes": len(ckpts) * nbytes,
+           "window_bytes": 0 if keep_trajectory else min(ckpt_every, nsteps) * nbytes,
+           "trajectory_bytes": len(traj) * nbytes}
+    if keep_trajectory:
+        for n in range(nsteps - 1, -1, -1):
+            core.step_adjoint(traj[n], lam)
+        return final, mem
+    starts = sorted(ckpts)
+    for w in reversed(starts):
+        end = min(w + ckpt_every, nsteps)
+        window = [_clone(ckpts[w])]
+        for n in range(w, end - 1):
+            nxt = _clone(window[-1])
+            core.step(nxt, 1)
+            window.append(nxt)
+        for n in range(end - 1, w - 1, -1):
+            core.step_adjoint(window[n - w], lam)
+        del window
+        torch.cuda.current_stream().synchronize()
+    return final, mem

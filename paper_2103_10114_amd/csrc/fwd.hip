@@ -776,11 +776,17 @@ __global__ void k_nonfinite(const T* __restrict__ x, size_t n, unsigned long lon
 }
 
 // Dynamic LDS above 64 KB must be enabled per kernel (CDNA4 has 160 KB per CU).
-template <typename K>
-hipError_t allow_lds(K kernel, size_t lds) {
+// The attribute is raised to the CDNA4 maximum once per kernel (so that later launches, also inside a
+// stream capture, make no runtime call besides the launch).
+template <auto Kernel>
+hipError_t allow_lds(size_t lds) {
   if (lds <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+  static bool done = false;   // one flag per kernel
+  if (done) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess) done = true;
+  return e;
 }
 
 template <typename T, int NI>
@@ -788,11 +794,11 @@ hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
   const size_t lds = stage_lds_bytes(a.process, a.g.nx, sizeof(T));
   hipError_t e;
   if (a.process == 0) {
-    e = allow_lds(k_stage<T, NI, 0>, lds);
+    e = allow_lds<k_stage<T, NI, 0>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 0>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
   } else {
-    e = allow_lds(k_stage<T, NI, 1>, lds);
+    e = allow_lds<k_stage<T, NI, 1>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 1>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
   }
@@ -803,7 +809,7 @@ template <typename T, int NI>
 hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
                            int max_nx, hipStream_t s) {
   const size_t lds = std::max(stage_lds_bytes(0, max_nx, sizeof(T)), stage_lds_bytes(1, max_nx, sizeof(T)));
-  hipError_t e = allow_lds(k_stage_batch<T, NI>, lds);
+  hipError_t e = allow_lds<k_stage_batch<T, NI>>(lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_stage_batch<T, NI>), dim3(grid), dim3(block), lds, s, d_args, d_items, nitems);
   return hipGetLastError();

@@ -1,0 +1,172 @@
+"""GPU tests at the configured workloads: long FP32/FP64 runs against the oracle, batched ensembles
+(bitwise equal to per-member runs, also when replayed from a captured hipGraph), the
+torch.autograd.Function and checkpointed multi-step adjoint windows."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_10114_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _core(cfg, st, prec, **kw):
+    from paper_2103_10114_amd import Dycore
+    return Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec=prec, phis=st["phis"], **kw)
+
+
+def _host(d):
+    return {k: v.detach().cpu().numpy().astype(np.float64) for k, v in d.items() if k in ("U", "V", "Phi", "ps")}
+
+
+def _errs(got, want):
+    out = {}
+    for k in ("U", "V", "Phi", "ps"):
+        l2 = float(np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k]))
+        mx = float(np.abs(got[k] - want[k]).max() / np.abs(want[k]).max())
+        out[k] = (l2, mx)
+    return out
+
+
+def test_c2_100_steps_fp64_and_fp32():
+    """C2 (256x128x30, dt 300 s, 100 steps) from the FP32-rounded initial state: FP64 mode within 1e-11
+    of the FP64 oracle; FP32 storage with FP64 accumulation reported per field (rel-L2, max) and bounded."""
+    cfg = synth.CONFIGS["c2"]
+    st = synth.make_state(cfg)
+    st32 = {k: st[k].astype(np.float32).astype(np.float64) for k in ("U", "V", "Phi", "ps")}
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    print("oracle: C2 100 steps ...", flush=True)
+    want = o.step(st32, cfg.steps, cfg.dt)
+    c64 = _core(cfg, st, "fp64", forward_only=True)
+    d64 = c64.to_device(st32)
+    m0, _ = c64.diagnostics(d64)
+    c64.step(d64, cfg.steps)
+    m1, _ = c64.diagnostics(d64)
+    e64 = _errs(_host(d64), want)
+    c32 = _core(cfg, st, "fp32", forward_only=True)
+    d32 = c32.to_device(st32)
+    c32.step(d32, cfg.steps)
+    e32 = _errs(_host(d32), want)
+    for k in ("U", "V", "Phi", "ps"):
+        print(f"C2 100 steps {k}: fp64 rel-L2 {e64[k][0]:.3e} max {e64[k][1]:.3e} | "
+              f"fp32 rel-L2 {e32[k][0]:.3e} max {e32[k][1]:.3e}", flush=True)
+        assert e64[k][0] < 1e-11 and e64[k][1] < 1e-11
+        assert e32[k][0] < 1e-3 and e32[k][1] < 1e-2
+    print(f"C2 mass drift fp64: {(m1 - m0) / m0:.3e}")
+    assert abs(m1 - m0) / m0 < 1e-12
+
+
+def _members(cfgs):
+    from paper_2103_10114_amd import Dycore
+    cores, states, hosts = [], [], []
+    for cfg in cfgs:
+        st = synth.make_state(cfg)
+        c = Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec="fp32", phis=st["phis"], forward_only=True)
+        cores.append(c)
+        states.append(c.to_device(st))
+        hosts.append(st)
+    return cores, states, hosts
+
+
+def test_batch_bitwise_small():
+    """A mixed batch (three grids, M = 2 and 4) equals per-member dycore_step bit for bit."""
+    from paper_2103_10114_amd import Batch
+    cfgs = [dataclasses.replace(synth.CONFIGS["c1"], nx=64, ny=32, nz=5, degree=5, seed=11),
+            dataclasses.replace(synth.CONFIGS["c1"], seed=12),
+            dataclasses.replace(synth.CONFIGS["c3"], nx=200, ny=100, nz=7, degree=8, seed=13)]
+    cores, states, hosts = _members(cfgs)
+    refs = [c.to_device(h) for c, h in zip(cores, hosts)]
+    b = Batch(cores, states)
+    b.step(3)
+    for c, r in zip(cores, refs):
+        c.step(r, 3)
+    torch.cuda.synchronize()
+    for s, r in zip(states, refs):
+        for k in ("U", "V", "Phi", "ps"):
+            assert torch.equal(s[k], r[k]), k
+
+
+def test_ensemble_c5_bitwise_and_graph_replay():
+    """The 24-member mixed ensemble (8 each of 128x64x9, 256x128x30, 720x360x30, seeds 500+m, 0.5 m/s
+    wind noise): one persistent launch per stage, captured in a hipGraph and replayed; after each
+    replay every member equals its eager per-member run bit for bit."""
+    from paper_2103_10114_amd import Batch
+    cfgs = [synth.ensemble_member(m) for m in range(24)]
+    cores, states, hosts = _members(cfgs)
+    refs = [c.to_device(h) for c, h in zip(cores, hosts)]
+    b = Batch(cores, states)
+    b.step(1)                      # eager batched step
+    for c, r in zip(cores, refs):
+        c.step(r, 1)
+    torch.cuda.synchronize()
+    for s, r in zip(states, refs):
+        for k in ("U", "V", "Phi", "ps"):
+            assert torch.equal(s[k], r[k]), ("eager", k)
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        b.step(1)
+    # capture does not execute: states are unchanged; replay three times with eager checks between
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        for c, r in zip(cores, refs):
+            c.step(r, 1)
+        torch.cuda.synchronize()
+        for m, (s, r) in enumerate(zip(states, refs)):
+            for k in ("U", "V", "Phi", "ps"):
+                assert torch.equal(s[k], r[k]), ("replay", rep, m, k)
+    for c, s in zip(cores, states):
+        assert c.count_nonfinite(s) == 0
+
+
+def test_autograd_function():
+    """Gradients through the torch.autograd.Function equal dycore_step_adjoint (and the oracle)."""
+    from paper_2103_10114_amd import dycore_step_fn
+    cfg = dataclasses.replace(synth.CONFIGS["c1"], nx=64, ny=32, nz=5, degree=6)
+    st = synth.make_state(cfg)
+    core = _core(cfg, st, "fp64")
+    d = core.to_device(st)
+    for k in d:
+        d[k].requires_grad_(True)
+    out = dycore_step_fn(core, d["U"], d["V"], d["Phi"], d["ps"])
+    y = core.to_device(synth.random_like(st, 44))
+    loss = sum((o * y[k]).sum() for o, k in zip(out, ("U", "V", "Phi", "ps")))
+    loss.backward()
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    want = o.adj_step(st, synth.random_like(st, 44), cfg.dt)
+    for k in ("U", "V", "Phi", "ps"):
+        got = d[k].grad.cpu().numpy()
+        assert np.abs(got - want[k]).max() <= 1e-11 * np.abs(want[k]).max(), k
+
+
+def test_adjoint_window_checkpoints_bitwise():
+    """Recompute-from-checkpoint adjoint over 10 steps (checkpoints every 4) equals the adjoint with
+    every step-start state stored, bit for bit, and matches the oracle's chained step adjoints."""
+    from paper_2103_10114_amd import adjoint_window
+    cfg = dataclasses.replace(synth.CONFIGS["c1"], nx=64, ny=32, nz=5, degree=6)
+    st = synth.make_state(cfg)
+    core = _core(cfg, st, "fp64")
+    lam0 = synth.random_like(st, 45)
+    la = core.to_device(lam0)
+    lb = core.to_device(lam0)
+    adjoint_window(core, core.to_device(st), 10, la, ckpt_every=4)
+    _, mem = adjoint_window(core, core.to_device(st), 10, lb, keep_trajectory=True)
+    torch.cuda.synchronize()
+    for k in ("U", "V", "Phi", "ps"):
+        assert torch.equal(la[k], lb[k]), k
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    traj = [st]
+    for _ in range(9):
+        traj.append(o.step(traj[-1], 1, cfg.dt))
+    lam = lam0
+    for n in range(9, -1, -1):
+        lam = o.adj_step(traj[n], lam, cfg.dt)
+    got = _host(la)
+    for k in ("U", "V", "Phi", "ps"):
+        assert np.abs(got[k] - lam[k]).max() <= 1e-10 * np.abs(lam[k]).max(), k
