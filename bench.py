@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the whole global grid is resident on one MI355X; "
@@ -153,6 +155,12 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calib_copy:
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = synth.CONFIGS[args.config]
     print(f"[bench] building synthetic state {cfg.nx}x{cfg.ny}x{cfg.nz}", file=sys.stderr, flush=True)
     st = synth.make_state(cfg)
