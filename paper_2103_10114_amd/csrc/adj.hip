@@ -200,46 +200,56 @@ __global__ void k_f1(Ctx<T> c) {
   }
 }
 
-// pole columns: one wavefront per pole
+// pole columns, step 1: per (pole, level) cap divergence and zonal-mean v.grad(l) (FP64, one block each)
 template <typename T>
-__global__ void __launch_bounds__(64) k_f1p(Ctx<T> c) {
+__global__ void __launch_bounds__(256) k_f1p_red(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int p = blockIdx.x;                  // 0 north, 1 south
+  const int k = blockIdx.x, p = blockIdx.y;
   const int j = p == 0 ? 0 : g.ny;
-  const int ja = p == 0 ? 1 : g.ny - 1;      // adjacent scalar row
-  const int jv = p == 0 ? 0 : g.ny - 1;      // adjacent V row
+  const int ja = p == 0 ? 1 : g.ny - 1;
+  const int jv = p == 0 ? 0 : g.ny - 1;
+  const int nx = g.nx, t = threadIdx.x;
+  __shared__ double red[2][4];
+  const T Pp = P2(c, j, 0), lp = c.s.L[(size_t)j * nx];
+  C s1 = 0, s2 = 0;
+  for (int i = t; i < nx; i += blockDim.x) {
+    const T pv = T(0.5) * (Pp + P2(c, ja, i));
+    const T vv = Ve(c, jv, k, i);
+    s1 += (C)(pv * vv);
+    const T la = c.s.L[(size_t)ja * nx + i];
+    s2 += (C)((vv / pv) * (p == 0 ? (la - lp) : (lp - la)));
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if ((t & 63) == 0) { red[0][t >> 6] = s1; red[1][t >> 6] = s2; }
+  __syncthreads();
+  C S1 = 0, S2 = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { S1 += red[0][w]; S2 += red[1][w]; }
+  const C sgn = p == 0 ? 1.0 : -1.0;
+  const T D = (T)(sgn * g.a * g.dlam * g.sv[jv] * S1 / g.acap);
+  const T vg = (T)(S2 / ((double)nx * g.a * g.dth));
+  for (int i = t; i < nx; i += blockDim.x) {
+    c.s.D[i3<T>(g, j, k, i)] = D;
+    c.s.WP[i3<T>(g, j, k, i)] = vg;   // v.grad(l) until step 2 overwrites it with omega/p
+  }
+}
+
+// pole columns, step 2: the column scans on the pole scalars, written to the whole row
+template <typename T>
+__global__ void __launch_bounds__(256) k_f1p(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int p = blockIdx.x;
+  const int j = p == 0 ? 0 : g.ny;
   const int nx = g.nx, nz = g.nz, t = threadIdx.x;
   const T b = (T)g.b;
-  const T Pp = P2(c, j, 0), lp = c.s.L[(size_t)j * nx];
-  const C sgn = p == 0 ? 1.0 : -1.0;
-  // cap divergence and v.grad(l) per level
+  const T Pp = P2(c, j, 0);
+  C H = 0, Pi = 0;
   for (int k = 0; k < nz; ++k) {
-    C s1 = 0, s2 = 0;
-    for (int i = t; i < nx; i += 64) {
-      const T pv = T(0.5) * (Pp + P2(c, ja, i));
-      const T vv = Ve(c, jv, k, i);
-      s1 += (C)(pv * vv);
-      const T la = c.s.L[(size_t)ja * nx + i];
-      s2 += (C)((vv / pv) * (p == 0 ? (la - lp) : (lp - la)));
-    }
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    const T D = (T)(sgn * g.a * g.dlam * g.sv[jv] * s1 / g.acap);
-    const T vg = (T)(s2 / ((double)nx * g.a * g.dth));
-    for (int i = t; i < nx; i += 64) {
-      c.s.D[i3<T>(g, j, k, i)] = D;
-      c.s.WP[i3<T>(g, j, k, i)] = vg;   // v.grad(l) for now
-    }
-  }
-  C H = 0, S = 0;
-  for (int k = 0; k < nz; ++k) {
-    const T RT = b * (T)c.pin[p * (nz + 1) + k] / Pp;
-    H += g.cl[k] * (C)RT;
+    H += g.cl[k] * (C)(b * (T)c.pin[p * (nz + 1) + k] / Pp);
+    Pi += (C)c.s.D[i3<T>(g, j, k, 0)] * g.dsig[k];
   }
   const C P0s = (C)Pp * (C)Pp;
-  C Pi = 0;
-  for (int k = 0; k < nz; ++k) Pi += (C)c.s.D[i3<T>(g, j, k, 0)] * g.dsig[k];
-  C R = 0;
+  C R = 0, S = 0;
   for (int k = 0; k < nz; ++k) {
     const T RT = b * (T)c.pin[p * (nz + 1) + k] / Pp;
     R += g.cl[k] * (C)RT;
@@ -250,7 +260,8 @@ __global__ void __launch_bounds__(64) k_f1p(Ctx<T> c) {
     const T Sk = (T)S;
     S += D * g.dsig[k];
     const T SDn = (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - S) / P0s) : T(0);
-    for (int i = t; i < nx; i += 64) {
+    __syncthreads();   // every thread has read this level's D and v.grad(l) before WP is overwritten
+    for (int i = t; i < nx; i += blockDim.x) {
       const size_t id = i3<T>(g, j, k, i);
       c.s.RT[id] = RT;
       c.s.PHI[id] = PHI;
@@ -260,7 +271,7 @@ __global__ void __launch_bounds__(64) k_f1p(Ctx<T> c) {
       if (k == 0) c.s.SD[ih<T>(g, j, 0, i)] = T(0);
     }
   }
-  for (int i = t; i < nx; i += 64) c.s.S[ih<T>(g, j, nz, i)] = (T)S;
+  for (int i = t; i < nx; i += blockDim.x) c.s.S[ih<T>(g, j, nz, i)] = (T)S;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -794,7 +805,8 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s) {
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1), gcol_int(gx, ny - 1);
   hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_f1p<T>), dim3(2), dim3(64), 0, s, c);
+  hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
+  hipLaunchKernelGGL((k_f1p<T>), dim3(2), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
                      c.s.psum + PS_AOF * 2 * (nz + 1));

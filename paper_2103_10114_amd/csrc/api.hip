@@ -62,6 +62,8 @@ HandleView view_of(const dycore_s* h);
 
 struct dycore_batch_s {
   int n, prec, block, grid, max_nx, nstage_max;
+  size_t lds;   // dynamic LDS of the batched stage kernel: the largest need of any member
+  int pipe;     // adaptation form: 1 all members pipelined, 0 none, 2 mixed
   std::vector<dycore_t> hs;
   void* d_args = nullptr;       // nstage_max x n StageArgs
   int2* d_items = nullptr;
@@ -600,7 +602,7 @@ int batch_step(dycore_batch_s* b, int nsteps, hipStream_t s) {
   for (int n = 0; n < nsteps; ++n)
     for (int sidx = 0; sidx < b->nstage_max; ++sidx) {
       hipError_t e = launch_stage_batch<T>(args + (size_t)sidx * b->n, b->d_items, b->nitems, b->grid, b->block,
-                                           b->max_nx, s);
+                                           b->max_nx, b->lds, b->pipe, s);
       if (e != hipSuccess) return DYCORE_EHIP;
     }
   return DYCORE_OK;
@@ -616,6 +618,8 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
   *out = nullptr;
   const int prec = hs[0] ? hs[0]->prec : -1;
   int max_nx = 0, nst = 0;
+  size_t lds = 0;
+  int npipe = 0;
   for (int m = 0; m < n; ++m) {
     if (!hs[m] || hs[m]->prec != prec || !U[m] || !V[m] || !Phi[m] || !ps[m]) return DYCORE_EINVAL;
     if (!aligned16(U[m]) || !aligned16(V[m]) || !aligned16(Phi[m]) || !aligned16(ps[m])) return DYCORE_EINVAL;
@@ -623,16 +627,18 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
       if (hs[q] == hs[m]) return DYCORE_EINVAL;   // each member needs its own scratch
     max_nx = std::max(max_nx, hs[m]->nx);
     nst = std::max(nst, 3 * (hs[m]->msub + 1));
+    const int el = hs[m]->prec == DYCORE_FP32 ? 4 : 8;
+    lds = std::max(lds, std::max(stage_lds_bytes(0, hs[m]->nx, el), stage_lds_bytes(1, hs[m]->nx, el)));
+    npipe += adapt_pipelined(hs[m]->nx, el);
   }
   if (block == 0) block = 256;
   if (block < 64 || block > 1024 || block % 64) return DYCORE_EINVAL;
   if (columns_per_thread(max_nx, block) > 8 || !max_block_for(max_nx, block)) return DYCORE_EUNSUPPORTED;
-  const size_t elem = prec == DYCORE_FP32 ? 4 : 8;
-  if (std::max(stage_lds_bytes(0, max_nx, (int)elem), stage_lds_bytes(1, max_nx, (int)elem)) > 160 * 1024)
-    return DYCORE_EUNSUPPORTED;
+  if (lds > 160 * 1024) return DYCORE_EUNSUPPORTED;
   dycore_batch_s* b = new (std::nothrow) dycore_batch_s();
   if (!b) return DYCORE_ENOMEM;
-  b->n = n; b->prec = prec; b->block = block; b->max_nx = max_nx; b->nstage_max = nst;
+  b->n = n; b->prec = prec; b->block = block; b->max_nx = max_nx; b->nstage_max = nst; b->lds = lds;
+  b->pipe = npipe == n ? 1 : (npipe == 0 ? 0 : 2);
   b->hs.assign(hs, hs + n);
   b->U.assign(U, U + n); b->V.assign(V, V + n); b->F.assign(Phi, Phi + n); b->P.assign(ps, ps + n);
   const int st = prec == DYCORE_FP32 ? batch_build<float>(b) : batch_build<double>(b);
@@ -641,7 +647,6 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const size_t lds = std::max(stage_lds_bytes(0, max_nx, (int)elem), stage_lds_bytes(1, max_nx, (int)elem));
     int per_cu = (int)std::max<size_t>(1, (160 * 1024) / lds);
     per_cu = std::min(per_cu, std::max(1, 2048 / block));
     grid = cus * per_cu;

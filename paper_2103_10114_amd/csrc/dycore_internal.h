@@ -70,7 +70,7 @@ template <typename T>
 hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s);
 template <typename T>
 hipError_t launch_stage_batch(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid,
-                              int block, int max_nx, hipStream_t s);
+                              int block, int max_nx, size_t lds, int pipe, hipStream_t s);
 template <typename T>
 hipError_t launch_stage_adjoint(const AdjArgs<T>& a, int block, hipStream_t s);
 template <typename T>
@@ -85,6 +85,7 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s);
 
 size_t stage_lds_bytes(int process, int nx, int elem);
 int columns_per_thread(int nx, int block);
+int adapt_pipelined(int nx, int elem);   // 1 if the adaptation stage of rows of nx columns is pipelined
 int max_block_for(int nx, int block);   // 1 if `block` threads are allowed for rows of nx columns
 
 // XCD-aware row order: workgroups are dispatched round-robin over the 8 XCDs,

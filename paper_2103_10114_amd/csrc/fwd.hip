@@ -34,6 +34,17 @@ __device__ __forceinline__ double wave_sum(double acc) {
 
 using C = double;
 
+// A uniform pointer, opaque to the optimiser: loop strength reduction would otherwise turn every
+// (array, owned column) address stream of a level loop into its own 64-bit induction variable in
+// VGPRs; this way each access is an SGPR base plus the column's 32-bit VGPR offset.
+template <typename P>
+__device__ __forceinline__ P uni(P p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
+  return reinterpret_cast<P>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 }  // namespace
 
 // Largest workgroup per columns-per-thread: bounds the VGPR budget so that the FP64 column
@@ -47,8 +58,9 @@ namespace {
 // Adaptation: out = base + ch * A(in)
 // ----------------------------------------------------------------------------------------------
 // LDS: 2D rows P, l (rows j-1, j, j+1), q (rows j, j+1), leaped d+l and d+q on the U points of
-// row j, and per level the leaped rows phi' and MU of row j.  Only the FP64 column sums live in
-// registers across levels.
+// row j, and per level the leaped rows phi' and MU of row j.  Registers per owned column: the
+// FP64 column sums, the wrapped neighbour indices and the reciprocals of the P averages (so the
+// level loop divides only where a neighbour's P enters).
 template <typename T, int NI>
 __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
   const GeoDev& g = A.g;
@@ -66,7 +78,7 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
   T* sDq = sDl + nx;
   T* sPhi = sDq + nx;
   T* sMU = sPhi + nx;
-  double* sRed = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));
+  double* sCap = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));  // [2][nz]
 
   const bool isPole = (j == 0 || j == ny);
   const bool hasV = (j < ny);
@@ -80,16 +92,6 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
     if (jr == ny) return (T)A.pin[(nz + 1) + nz];
     return A.inP[(size_t)jr * nx + i];
   };
-  auto FA = [&](int jr, int k, int i) -> T {
-    if (jr == 0) return (T)A.pin[k];
-    if (jr == ny) return (T)A.pin[(nz + 1) + k];
-    return A.inF[(size_t)jr * row3 + (size_t)k * nx + i];
-  };
-  auto UA = [&](int jr, int k, int i) -> T {
-    if (jr == 0 || jr == ny) return T(0);
-    return A.inU[(size_t)jr * row3 + (size_t)k * nx + i];
-  };
-  auto VA = [&](int jv, int k, int i) -> T { return A.inV[(size_t)jv * row3 + (size_t)k * nx + i]; };
 
   // ---- 2D rows
   for (int c = 0; c < NI; ++c) {
@@ -115,32 +117,75 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
   __syncthreads();
   const int Mj = isPole ? 1 : g.M[j];
   const int nj = (Mj + 1) / 2;
-  const T dxj = isPole ? T(1) : (T)((double)Mj * g.a * g.s[j] * g.dlam);
+  const T rdx = isPole ? T(0) : (T)(1.0 / ((double)Mj * g.a * g.s[j] * g.dlam));
   if (!isPole) {
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
       if (i < nx) {
-        sDl[i] = (sL0[wrp(i + nj, nx)] - sL0[wrp(i + 1 - nj, nx)]) / dxj;
-        sDq[i] = (sQ0[wrp(i + nj, nx)] - sQ0[wrp(i + 1 - nj, nx)]) / dxj;
+        sDl[i] = (sL0[wrp(i + nj, nx)] - sL0[wrp(i + 1 - nj, nx)]) * rdx;
+        sDq[i] = (sQ0[wrp(i + nj, nx)] - sQ0[wrp(i + 1 - nj, nx)]) * rdx;
       }
+    }
+  }
+  // pole workgroups: cap divergence and zonal-mean v.grad(l) of every level, FP64, wavefront 0
+  if (isPole && t < 64) {
+    const int jva = (j == 0) ? 0 : ny - 1;
+    const T* sPa = (j == 0) ? sP1 : sPm;
+    const T* sLa = (j == 0) ? sL1 : sLm;
+    const T Pp = sP0[0], lp = sL0[0];
+    for (int k = 0; k < nz; ++k) {
+      const T* pV = A.inV + (size_t)jva * row3 + (size_t)k * nx;
+      C s1 = 0, s2 = 0;
+      for (int i = t; i < nx; i += 64) {
+        const T pv = T(0.5) * (Pp + sPa[i]);
+        const T vv = pV[i];
+        s1 += (C)(pv * vv);
+        s2 += (C)((vv / pv) * (j == 0 ? (sLa[i] - lp) : (lp - sLa[i])));
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
     }
   }
   __syncthreads();
 
+  // per-column constants
+  T rPU0[NI], rPU1[NI], rPV0[NI], rPVm[NI], rP0[NI], rP1[NI];
   C H0c[NI], H1c[NI], R0c[NI], R1c[NI], Sc[NI];
 #pragma unroll
-  for (int c = 0; c < NI; ++c) { H0c[c] = 0; H1c[c] = 0; R0c[c] = 0; R1c[c] = 0; Sc[c] = 0; }
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    const int ii = i < nx ? i : 0;
+    const int ip = wrp(ii + 1, nx);
+    const T P0 = sP0[ii];
+    rP0[c] = T(1) / P0;
+    rPU0[c] = T(2) / (P0 + sP0[ip]);
+    rP1[c] = rPU1[c] = rPV0[c] = rPVm[c] = T(1);
+    if (hasV) {
+      rP1[c] = T(1) / sP1[ii];
+      rPU1[c] = T(2) / (sP1[ii] + sP1[ip]);
+      rPV0[c] = T(2) / (P0 + sP1[ii]);
+    }
+    if (j >= 1) rPVm[c] = T(2) / (sPm[ii] + P0);
+    H0c[c] = 0; H1c[c] = 0; R0c[c] = 0; R1c[c] = 0; Sc[c] = 0;
+  }
 
   // ---- pass A: column totals H = sum_{l>=1} cl_l RT'_l (FP64) for phi' = H - R_k + cpk_k RT'_k
   if (hasV) {
+#pragma unroll 1
     for (int k = 0; k < nz; ++k) {
       const C clk = g.cl[k];
+      const size_t lev = (size_t)k * nx;
+      const T* pF0 = isPole ? nullptr : A.inF + (size_t)j * row3 + lev;
+      const T* pF1 = (j + 1 < ny) ? A.inF + (size_t)(j + 1) * row3 + lev : nullptr;
+      const T F0p = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
+      const T F1p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i < nx) {
-          H0c[c] += clk * (C)(b * FA(j, k, i) / sP0[i]);
-          H1c[c] += clk * (C)(b * FA(j + 1, k, i) / sP1[i]);
+          H0c[c] += clk * (C)(b * (pF0 ? pF0[i] : F0p) * rP0[c]);
+          H1c[c] += clk * (C)(b * (pF1 ? pF1[i] : F1p) * rP1[c]);
         }
       }
     }
@@ -148,52 +193,58 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
 
   // ---- pass B: top to bottom
   C Sp = 0;
+  const T rdyS = isPole ? T(0) : (T)(1.0 / (g.a * g.s[j] * g.dth));
+  const T rdyA = (T)(1.0 / (g.a * g.dth));
+  const C rdyAc = 1.0 / (C)(T)(g.a * g.dth);
   for (int k = 0; k < nz; ++k) {
     const C clk = g.cl[k], cpk = g.cpk[k];
-    const C dsg = g.dsig[k], sgk = g.sig[k];
+    const C dsg = g.dsig[k], rsg = 1.0 / g.sig[k];
+    const size_t lev = (size_t)k * nx;
+    const T* pF0 = isPole ? nullptr : A.inF + (size_t)j * row3 + lev;
+    const T* pF1 = (j + 1 < ny) ? A.inF + (size_t)(j + 1) * row3 + lev : nullptr;
+    const T F0p = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
+    const T F1p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
+    const T* pU0 = isPole ? nullptr : A.inU + (size_t)j * row3 + lev;
+    const T* pU1 = (j + 1 < ny) ? A.inU + (size_t)(j + 1) * row3 + lev : nullptr;
+    const T* pV0 = hasV ? A.inV + (size_t)j * row3 + lev : nullptr;
+    const T* pVm = (j >= 1) ? A.inV + (size_t)(j - 1) * row3 + lev : nullptr;
     // phase 1: every global load of this level, phi' and MU into LDS
     T Fj[NI], Fp[NI], RTj[NI], RTj1[NI], phij[NI], phij1[NI], Uj[NI], Ujm[NI], U1[NI], U1m[NI];
-    T Vn[NI], Vnp[NI], Vs[NI], Vsp[NI], bF[NI], bU[NI], bV[NI];
+    T Vn[NI], Vnp[NI], Vs[NI], Vsp[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
       Fj[c] = Fp[c] = RTj[c] = RTj1[c] = phij[c] = phij1[c] = Uj[c] = Ujm[c] = U1[c] = U1m[c] = T(0);
-      Vn[c] = Vnp[c] = Vs[c] = Vsp[c] = bF[c] = bU[c] = bV[c] = T(0);
+      Vn[c] = Vnp[c] = Vs[c] = Vsp[c] = T(0);
       if (i < nx) {
-        const int ip1 = wrp(i + 1, nx), im1 = wrp(i - 1, nx);
-        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
-        Fj[c] = FA(j, k, i);
-        RTj[c] = b * Fj[c] / sP0[i];
+        const size_t idx = (size_t)j * row3 + lev + i;
+        const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
+        Fj[c] = pF0 ? pF0[i] : F0p;
+        RTj[c] = b * Fj[c] * rP0[c];
         if (hasV) {
           R0c[c] += clk * (C)RTj[c];
           phij[c] = (T)(H0c[c] - R0c[c] + cpk * (C)RTj[c]);
-          RTj1[c] = b * FA(j + 1, k, i) / sP1[i];
+          RTj1[c] = b * (pF1 ? pF1[i] : F1p) * rP1[c];
           R1c[c] += clk * (C)RTj1[c];
           phij1[c] = (T)(H1c[c] - R1c[c] + cpk * (C)RTj1[c]);
-          U1[c] = UA(j + 1, k, i);
-          U1m[c] = UA(j + 1, k, im1);
-          bV[c] = A.bV[id];
+          if (pU1) { U1[c] = pU1[i]; U1m[c] = pU1[im]; }
         }
         if (!isPole) {
-          Fp[c] = FA(j, k, ip1);
-          Uj[c] = UA(j, k, i);
-          Ujm[c] = UA(j, k, im1);
-          Vn[c] = VA(j, k, i);
-          Vnp[c] = VA(j, k, ip1);
-          Vs[c] = VA(j - 1, k, i);
-          Vsp[c] = VA(j - 1, k, ip1);
-          bF[c] = A.bF[id];
-          bU[c] = A.bU[id];
+          Fp[c] = pF0[ip];
+          Uj[c] = pU0[i];
+          Ujm[c] = pU0[im];
+          Vn[c] = pV0[i];
+          Vnp[c] = pV0[ip];
+          Vs[c] = pVm[i];
+          Vsp[c] = pVm[ip];
           sPhi[i] = phij[c];
-          sMU[i] = T(0.5) * (sP0[i] + sP0[ip1]) * Uj[c];
+          sMU[i] = T(0.5) * (sP0[i] + sP0[ip]) * Uj[c];
         }
       }
     }
     __syncthreads();
 
     if (!isPole) {
-      const T dyS = (T)(g.a * g.s[j] * g.dth);
-      const T dyA = (T)(g.a * g.dth);
       const T svj = (T)g.sv[j], svm = (T)g.sv[j - 1];
       const T fj = (T)g.f[j], cota = (T)(g.cot[j] / g.a);
       const T kap = (T)g.kappa;
@@ -201,97 +252,77 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
-        const int ip1 = wrp(i + 1, nx), im1 = wrp(i - 1, nx);
-        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
-        const T PU = T(0.5) * (sP0[i] + sP0[ip1]);
-        const T PUm = T(0.5) * (sP0[im1] + sP0[i]);
-        const T PV0 = T(0.5) * (sP0[i] + sP1[i]);
-        const T PVm = T(0.5) * (sPm[i] + sP0[i]);
+        const size_t idx = (size_t)j * row3 + lev + i;
+        const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
+        const T PV0 = T(0.5) * (sP0[i] + sP1[i]), PVm = T(0.5) * (sPm[i] + sP0[i]);
         // divergence of the mass flux: leaped (x,x-1) -> (x+N-1, x-N) plus meridional
-        const T D = (sMU[wrp(i + nj - 1, nx)] - sMU[wrp(i - nj, nx)]) / dxj +
-                    (svj * (PV0 * Vn[c]) - svm * (PVm * Vs[c])) / dyS;
+        const T D = (sMU[wrp(i + nj - 1, nx)] - sMU[wrp(i - nj, nx)]) * rdx + (svj * (PV0 * Vn[c]) - svm * (PVm * Vs[c])) * rdyS;
         const C Sk = Sc[c];
         Sc[c] += (C)D * dsg;
         // v . grad(l)
-        const T u_i = Uj[c] / PU;
-        const T u_m = Ujm[c] / PUm;
-        const T zon = T(0.5) * (u_i * sDl[i] + u_m * sDl[im1]);
-        const T mer = T(0.5) * ((Vn[c] / PV0) * (sL1[i] - sL0[i]) + (Vs[c] / PVm) * (sL0[i] - sLm[i])) / dyA;
-        const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) / (sgk * (C)sP0[i] * (C)sP0[i]);
+        const T u_i = Uj[c] * rPU0[c];
+        const T u_m = Ujm[c] / (T(0.5) * (sP0[im] + sP0[i]));
+        const T zon = T(0.5) * (u_i * sDl[i] + u_m * sDl[im]);
+        const T mer = T(0.5) * ((Vn[c] * rPV0[c]) * (sL1[i] - sL0[i]) + (Vs[c] * rPVm[c]) * (sL0[i] - sLm[i])) * rdyA;
+        const C rp = (C)rP0[c];
+        const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) * rsg * (rp * rp);
         const C TF = ((C)(b * sP0[i]) + (C)(kap * Fj[c])) * wp;
-        A.oF[id] = (T)((C)bF[c] + A.ch * TF);
+        A.oF[idx] = (T)((C)A.bF[idx] + A.ch * TF);
         // U at i+1/2: pressure gradient with leap (x+1,x) -> (x+N, x-N+1) and Coriolis
-        const T dphi = (sPhi[wrp(i + nj, nx)] - sPhi[wrp(i + 1 - nj, nx)]) / dxj;
-        const T RTp = b * Fp[c] / sP0[ip1];
+        const T dphi = (sPhi[wrp(i + nj, nx)] - sPhi[wrp(i + 1 - nj, nx)]) * rdx;
+        const T RTp = b * Fp[c] / sP0[ip];
         const T rtx = T(0.5) * (RTj[c] + RTp);
         const C pgf = (C)dphi + RT0c * (C)sDq[i] + (C)rtx * (C)sDl[i];
         const T VV = T(0.25) * (Vn[c] + Vnp[c] + Vs[c] + Vsp[c]);
         const T fs = fj + u_i * cota;
-        const C TU = -(C)PU * pgf - (C)fs * (C)VV;
-        A.oU[id] = (T)((C)bU[c] + A.ch * TU);
+        const C TU = -(C)(T(0.5) * (sP0[i] + sP0[ip])) * pgf - (C)fs * (C)VV;
+        A.oU[idx] = (T)((C)A.bU[idx] + A.ch * TU);
+        __builtin_amdgcn_sched_barrier(0);   // one column at a time: bounds the live registers
       }
     } else {
-      // pole column: cap divergence and zonal-mean v.grad(l) from the adjacent V row
+      // pole column from the precomputed cap sums
       const int jva = (j == 0) ? 0 : ny - 1;
-      const T* sPa = (j == 0) ? sP1 : sPm;
-      const T* sLa = (j == 0) ? sL1 : sLm;
       const T Pp = sP0[0];
-      const T lp = sL0[0];
-      if (t < 64) {
-        C s1 = 0, s2 = 0;
-        for (int i = t; i < nx; i += 64) {
-          const T pv = T(0.5) * (Pp + sPa[i]);
-          const T vv = VA(jva, k, i);
-          s1 += (C)(pv * vv);
-          s2 += (C)((vv / pv) * (j == 0 ? (sLa[i] - lp) : (lp - sLa[i])));
-        }
-        s1 = wave_sum(s1);
-        s2 = wave_sum(s2);
-        if (t == 0) { sRed[0] = s1; sRed[1] = s2; }
-      }
-      __syncthreads();
       const C sgn = (j == 0) ? 1.0 : -1.0;
-      const C Dp = sgn * g.a * g.dlam * g.sv[jva] * sRed[0] / g.acap;
-      const C vglp = sRed[1] / ((double)nx * g.a * g.dth);
+      const C Dp = sgn * g.a * g.dlam * g.sv[jva] * sCap[k] / g.acap;
+      const C vglp = sCap[nz + k] / ((double)nx * g.a * g.dth);
       const C Sk = Sp;
       Sp += Dp * dsg;
-      const C wp = vglp - (Sk + 0.5 * Dp * dsg) / (sgk * (C)Pp * (C)Pp);
-      const T Fpole = FA(j, k, 0);
-      const C TF = ((C)(b * Pp) + (C)((T)g.kappa * Fpole)) * wp;
+      const C wp = vglp - (Sk + 0.5 * Dp * dsg) * rsg / ((C)Pp * (C)Pp);
+      const C TF = ((C)(b * Pp) + (C)((T)g.kappa * F0p)) * wp;
       const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i < nx) {
-          const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
-          A.oF[id] = val;
-          A.oU[id] = T(0);
+          const size_t idx = (size_t)j * row3 + lev + i;
+          A.oF[idx] = val;
+          A.oU[idx] = T(0);
         }
       }
       if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
     }
 
     if (hasV) {
-      const T dyA = (T)(g.a * g.dth);
       const T fvj = (T)g.fv[j], cotva = (T)(g.cotv[j] / g.a);
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
-        const int ip1 = wrp(i + 1, nx), im1 = wrp(i - 1, nx);
-        const size_t idv = (size_t)j * row3 + (size_t)k * nx + i;
+        const size_t idv = (size_t)j * row3 + lev + i;
+        const int im = wrp(i - 1, nx);
         const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)(sQ1[i] - sQ0[i]) +
-                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)(sL1[i] - sL0[i])) / (C)dyA;
-        const T u0i = Uj[c] / (T(0.5) * (sP0[i] + sP0[ip1]));
-        const T u0m = Ujm[c] / (T(0.5) * (sP0[im1] + sP0[i]));
-        const T u1i = U1[c] / (T(0.5) * (sP1[i] + sP1[ip1]));
-        const T u1m = U1m[c] / (T(0.5) * (sP1[im1] + sP1[i]));
+                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)(sL1[i] - sL0[i])) * rdyAc;
+        const T u0i = isPole ? T(0) : Uj[c] * rPU0[c];
+        const T u0m = isPole ? T(0) : Ujm[c] / (T(0.5) * (sP0[im] + sP0[i]));
+        const T u1i = pU1 ? U1[c] * rPU1[c] : T(0);
+        const T u1m = pU1 ? U1m[c] / (T(0.5) * (sP1[im] + sP1[i])) : T(0);
         const T UU = T(0.25) * (Ujm[c] + Uj[c] + U1m[c] + U1[c]);
         const T uu = T(0.25) * (u0m + u0i + u1m + u1i);
         const T fs = fvj + uu * cotva;
-        const T PV0 = T(0.5) * (sP0[i] + sP1[i]);
-        const C TV = -(C)PV0 * pgf + (C)fs * (C)UU;
-        A.oV[idv] = (T)((C)bV[c] + A.ch * TV);
+        const C TV = -(C)(T(0.5) * (sP0[i] + sP1[i])) * pgf + (C)fs * (C)UU;
+        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();
@@ -303,8 +334,355 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
       if (i < nx) {
-        const size_t id = (size_t)j * nx + i;
-        A.oP[id] = (T)((C)A.bP[id] + A.ch * (-g.p0 * Sc[c]));
+        const size_t idx = (size_t)j * nx + i;
+        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c]));
+      }
+    }
+  } else {
+    const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp));
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) A.oP[(size_t)j * nx + i] = val;
+    }
+    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
+  }
+}
+
+// Adaptation, FP32 storage, software-pipelined.  Every value the level loop reads at another
+// column sits in LDS: 13 2D rows (P, the reciprocals of P and of its U-point averages, the
+// leaped d+l and d+q, the V-point averages of P and the meridional l and q differences) and,
+// double-buffered, the 7 per-level rows (phi', MU, Phi, U of rows j and j+1, V of rows j+-1/2).
+// Level k+1 is fetched into registers while level k is computed and written to the other
+// buffer afterwards, so one barrier per level suffices and the fetch latency hides behind the
+// arithmetic.  The column totals of pass A are summed over unrolled groups of levels.
+constexpr int kAdaptPipeRows2D = 13, kAdaptPipeRowsLev = 7;
+__host__ __device__ constexpr size_t adapt_pipe_lds(int nx) {
+  return (((size_t)(kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev) * nx * 4 + 15) & ~size_t(15)) + 2 * 128 * sizeof(double);
+}
+__host__ __device__ constexpr bool adapt_pipe_ok(int nx) { return adapt_pipe_lds(nx) <= 160 * 1024; }
+
+template <typename T, int NI>
+__device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char* smem) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int B = blockDim.x, t = threadIdx.x;
+  T* r = reinterpret_cast<T*>(smem);
+  T* sP0 = r;            T* srP0 = r + nx;      T* srP1 = r + 2 * nx;  T* srU0 = r + 3 * nx;
+  T* srU1 = r + 4 * nx;  T* sDl = r + 5 * nx;   T* sDq = r + 6 * nx;   T* sPV0 = r + 7 * nx;
+  T* sPVm = r + 8 * nx;  T* sgN = r + 9 * nx;   T* sgS = r + 10 * nx;  T* sdL = r + 11 * nx;
+  T* sdQ = r + 12 * nx;
+  T* lev0 = r + kAdaptPipeRows2D * nx;            // [2][7][nx]
+  const size_t bufStride = (size_t)kAdaptPipeRowsLev * nx;
+  double* sCap = reinterpret_cast<double*>(smem + ((((size_t)kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev) * nx * sizeof(T) + 15) & ~size_t(15)));
+
+  const bool isPole = (j == 0 || j == ny);
+  const bool hasV = (j < ny);
+  const int pidx = (j == 0) ? 0 : 1;
+  const T p0 = (T)g.p0, b = (T)g.b, RT0 = (T)g.RT0;
+  const C RT0c = g.RT0;
+  const size_t row3 = (size_t)nz * nx;
+  auto psA = [&](int jr, int i) -> T {
+    if (jr == 0) return (T)A.pin[nz];
+    if (jr == ny) return (T)A.pin[(nz + 1) + nz];
+    return A.inP[(size_t)jr * nx + i];
+  };
+
+  // ---- 2D rows.  Temporaries (P, l, q of the neighbour rows) live in the level buffers.
+  T* tP1 = lev0;          T* tL0 = lev0 + nx;     T* tQ0 = lev0 + 2 * nx;
+  T* tPa = lev0 + 3 * nx; T* tLa = lev0 + 4 * nx;  // pole rows: P and l of the adjacent row
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    if (i < nx) {
+      const T ps0 = psA(j, i);
+      const T P0 = tsqrt<T>(ps0 / p0), L0 = tlog<T>(ps0 / p0);
+      const T Q0 = L0 + (T)g.phis[(size_t)j * nx + i] / RT0;
+      sP0[i] = P0;
+      srP0[i] = T(1) / P0;
+      tL0[i] = L0;
+      tQ0[i] = Q0;
+      T P1 = T(1), L1 = T(0);
+      if (hasV) {
+        const T ps1 = psA(j + 1, i);
+        P1 = tsqrt<T>(ps1 / p0);
+        L1 = tlog<T>(ps1 / p0);
+        const T Q1 = L1 + (T)g.phis[(size_t)(j + 1) * nx + i] / RT0;
+        tP1[i] = P1;
+        srP1[i] = T(1) / P1;
+        const T PV0 = T(0.5) * (P0 + P1);
+        sPV0[i] = PV0;
+        sgN[i] = (L1 - L0) / PV0;
+        sdL[i] = L1 - L0;
+        sdQ[i] = Q1 - Q0;
+      }
+      if (j >= 1) {
+        const T psm = psA(j - 1, i);
+        const T Pm = tsqrt<T>(psm / p0), Lm = tlog<T>(psm / p0);
+        const T PVm = T(0.5) * (Pm + P0);
+        sPVm[i] = PVm;
+        sgS[i] = (L0 - Lm) / PVm;
+        if (j == ny) { tPa[i] = Pm; tLa[i] = Lm; }
+      }
+      if (j == 0) { tPa[i] = P1; tLa[i] = L1; }
+    }
+  }
+  __syncthreads();
+  const int Mj = isPole ? 1 : g.M[j];
+  const int nj = (Mj + 1) / 2;
+  const T rdx = isPole ? T(0) : (T)(1.0 / ((double)Mj * g.a * g.s[j] * g.dlam));
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    if (i < nx) {
+      const int ip = wrp(i + 1, nx);
+      srU0[i] = T(2) / (sP0[i] + sP0[ip]);
+      if (hasV) srU1[i] = T(2) / (tP1[i] + tP1[ip]);
+      if (!isPole) {
+        sDl[i] = (tL0[wrp(i + nj, nx)] - tL0[wrp(i + 1 - nj, nx)]) * rdx;
+        sDq[i] = (tQ0[wrp(i + nj, nx)] - tQ0[wrp(i + 1 - nj, nx)]) * rdx;
+      }
+    }
+  }
+  if (isPole && t < 64) {
+    const int jva = (j == 0) ? 0 : ny - 1;
+    const T Pp = sP0[0], lp = tL0[0];
+    for (int k = 0; k < nz; ++k) {
+      const T* pV = A.inV + (size_t)jva * row3 + (size_t)k * nx;
+      C s1 = 0, s2 = 0;
+      for (int i = t; i < nx; i += 64) {
+        const T pv = T(0.5) * (Pp + tPa[i]);
+        const T vv = pV[i];
+        s1 += (C)(pv * vv);
+        s2 += (C)((vv / pv) * (j == 0 ? (tLa[i] - lp) : (lp - tLa[i])));
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
+    }
+  }
+  __syncthreads();
+
+  // ---- pass A: column totals of R T' (the hydrostatic suffix sums start from them)
+  C Q0c[NI], Q1c[NI], Sc[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) { Q0c[c] = 0; Q1c[c] = 0; Sc[c] = 0; }
+  if (hasV) {
+    T rp0[NI], rp1[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      rp0[c] = (i < nx) ? b * srP0[i] : T(0);
+      rp1[c] = (i < nx) ? b * srP1[i] : T(0);
+    }
+    const T* pF0 = isPole ? nullptr : A.inF + (size_t)j * row3;
+    const T* pF1 = (j + 1 < ny) ? A.inF + (size_t)(j + 1) * row3 : nullptr;
+    constexpr int KU = 6;
+    int k = 0;
+    for (; k + KU <= nz; k += KU) {
+      T f0[KU][NI], f1[KU][NI];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+          const int i = t + c * B;
+          const size_t o = (size_t)(k + u) * nx + (i < nx ? i : 0);
+          f0[u][c] = pF0 ? pF0[o] : (T)A.pin[k + u];
+          f1[u][c] = pF1 ? pF1[o] : (T)A.pin[(nz + 1) + k + u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const C clk = g.cl[k + u];
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+          Q0c[c] += clk * (C)(f0[u][c] * rp0[c]);
+          Q1c[c] += clk * (C)(f1[u][c] * rp1[c]);
+        }
+      }
+    }
+    for (; k < nz; ++k) {
+      const C clk = g.cl[k];
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        const size_t o = (size_t)k * nx + (i < nx ? i : 0);
+        const T f0 = pF0 ? pF0[o] : (T)A.pin[k];
+        const T f1 = pF1 ? pF1[o] : (T)A.pin[(nz + 1) + k];
+        Q0c[c] += clk * (C)(f0 * rp0[c]);
+        Q1c[c] += clk * (C)(f1 * rp1[c]);
+      }
+    }
+  }
+
+  // ---- pass B, pipelined over levels
+  // raw values of one level for the owned columns
+  T nF0[NI], nF1[NI], nU0[NI], nU1[NI], nV0[NI], nVm[NI];
+  auto fetch = [&](int k) {
+    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
+    const T F0p = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
+    const T F1p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
+    const T* gF0 = uni(A.inF + lo);
+    const T* gU0 = uni(A.inU + lo);
+    const T* gF1 = uni(A.inF + lo + row3);
+    const T* gU1 = uni(A.inU + lo + row3);
+    const T* gV0 = uni(A.inV + lo);
+    const T* gVm = uni(A.inV + (lo - (j >= 1 ? row3 : 0)));
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      const unsigned ii = i < nx ? (unsigned)i : 0u;
+      nF0[c] = isPole ? F0p : gF0[ii];
+      nU0[c] = isPole ? T(0) : gU0[ii];
+      nF1[c] = (j + 1 < ny) ? gF1[ii] : F1p;
+      nU1[c] = (j + 1 < ny) ? gU1[ii] : T(0);
+      nV0[c] = hasV ? gV0[ii] : T(0);
+      nVm[c] = (j >= 1) ? gVm[ii] : T(0);
+    }
+  };
+  // R T' and phi' of rows j and j+1 at the current level (registers)
+  T RTj[NI], RTj1[NI], phij[NI], phij1[NI];
+  auto commit = [&](int k, T* buf) {
+    const C clk = g.cl[k], cpk = g.cpk[k];
+    T* bPhi = buf;          T* bMU = buf + nx;      T* bF = buf + 2 * nx;  T* bU0 = buf + 3 * nx;
+    T* bU1 = buf + 4 * nx;  T* bV0 = buf + 5 * nx;  T* bVm = buf + 6 * nx;
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      RTj[c] = RTj1[c] = phij[c] = phij1[c] = T(0);
+      if (i < nx) {
+        RTj[c] = b * nF0[c] * srP0[i];
+        bF[i] = nF0[c];
+        bU0[i] = nU0[c];
+        bMU[i] = T(0.5) * (sP0[i] + sP0[wrp(i + 1, nx)]) * nU0[c];
+        if (hasV) {
+          Q0c[c] -= clk * (C)RTj[c];
+          phij[c] = (T)(Q0c[c] + cpk * (C)RTj[c]);
+          RTj1[c] = b * nF1[c] * srP1[i];
+          Q1c[c] -= clk * (C)RTj1[c];
+          phij1[c] = (T)(Q1c[c] + cpk * (C)RTj1[c]);
+          bU1[i] = nU1[c];
+          bV0[i] = nV0[c];
+        }
+        bVm[i] = nVm[c];
+        bPhi[i] = phij[c];
+      }
+    }
+  };
+
+  fetch(0);
+  commit(0, lev0);
+  __syncthreads();
+
+  C Sp = 0;
+  const T rdyS = isPole ? T(0) : (T)(1.0 / (g.a * g.s[j] * g.dth));
+  const T rdyA = (T)(1.0 / (g.a * g.dth));
+  const C rdyAc = 1.0 / (C)(T)(g.a * g.dth);
+  const T svj = isPole ? T(0) : (T)g.sv[j], svm = isPole ? T(0) : (T)g.sv[j - 1];
+  const T fj = (T)g.f[j], cota = (T)(g.cot[j] / g.a);
+  const T kap = (T)g.kappa;
+  const T fvj = hasV ? (T)g.fv[j] : T(0), cotva = hasV ? (T)(g.cotv[j] / g.a) : T(0);
+#pragma unroll 1
+  for (int k = 0; k < nz; ++k) {
+    if (k + 1 < nz) fetch(k + 1);
+    T* buf = lev0 + (size_t)(k & 1) * bufStride;
+    const T* bPhi = buf;          const T* bMU = buf + nx;      const T* bF = buf + 2 * nx;
+    const T* bU0 = buf + 3 * nx;  const T* bU1 = buf + 4 * nx;  const T* bV0 = buf + 5 * nx;
+    const T* bVm = buf + 6 * nx;
+    const C clk = g.cl[k];
+    (void)clk;
+    const C dsg = g.dsig[k], rsg = 1.0 / g.sig[k];
+    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
+    const T* gbF = uni(A.bF + lo);
+    const T* gbU = uni(A.bU + lo);
+    const T* gbV = uni(A.bV + lo);
+    T* goF = uni(A.oF + lo);
+    T* goU = uni(A.oU + lo);
+    T* goV = uni(A.oV + lo);
+
+    if (!isPole) {
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const unsigned idx = (unsigned)i;
+        const T baseF = gbF[idx], baseU = gbU[idx];
+        const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
+        const T Vn = bV0[i], Vs = bVm[i];
+        const T D = (bMU[wrp(i + nj - 1, nx)] - bMU[wrp(i - nj, nx)]) * rdx +
+                    (svj * (sPV0[i] * Vn) - svm * (sPVm[i] * Vs)) * rdyS;
+        const C Sk = Sc[c];
+        Sc[c] += (C)D * dsg;
+        const T u_i = bU0[i] * srU0[i];
+        const T u_m = bU0[im] * srU0[im];
+        const T zon = T(0.5) * (u_i * sDl[i] + u_m * sDl[im]);
+        const T mer = T(0.5) * (Vn * sgN[i] + Vs * sgS[i]) * rdyA;
+        const C rp = (C)srP0[i];
+        const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) * rsg * (rp * rp);
+        const C TF = ((C)(b * sP0[i]) + (C)(kap * bF[i])) * wp;
+        goF[idx] = (T)((C)baseF + A.ch * TF);
+        const T dphi = (bPhi[wrp(i + nj, nx)] - bPhi[wrp(i + 1 - nj, nx)]) * rdx;
+        const T rtx = T(0.5) * (RTj[c] + b * bF[ip] * srP0[ip]);
+        const C pgf = (C)dphi + RT0c * (C)sDq[i] + (C)rtx * (C)sDl[i];
+        const T VV = T(0.25) * (Vn + bV0[ip] + Vs + bVm[ip]);
+        const T fs = fj + u_i * cota;
+        const C TU = -(C)(T(0.5) * (sP0[i] + sP0[ip])) * pgf - (C)fs * (C)VV;
+        goU[idx] = (T)((C)baseU + A.ch * TU);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      const T F0p = (T)A.pin[pidx * (nz + 1) + k];
+      const int jva = (j == 0) ? 0 : ny - 1;
+      const T Pp = sP0[0];
+      const C sgn = (j == 0) ? 1.0 : -1.0;
+      const C Dp = sgn * g.a * g.dlam * g.sv[jva] * sCap[k] / g.acap;
+      const C vglp = sCap[nz + k] / ((double)nx * g.a * g.dth);
+      const C Sk = Sp;
+      Sp += Dp * dsg;
+      const C wp = vglp - (Sk + 0.5 * Dp * dsg) * rsg / ((C)Pp * (C)Pp);
+      const C TF = ((C)(b * Pp) + (C)(kap * F0p)) * wp;
+      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i < nx) {
+          goF[i] = val;
+          goU[i] = T(0);
+        }
+      }
+      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
+    }
+
+    if (hasV) {
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const unsigned idv = (unsigned)i;
+        const T baseV = gbV[idv];
+        const int im = wrp(i - 1, nx);
+        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)sdQ[i] +
+                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)sdL[i]) * rdyAc;
+        const T U0i = bU0[i], U0m = bU0[im], U1i = bU1[i], U1m = bU1[im];
+        const T u0i = U0i * srU0[i], u0m = U0m * srU0[im];
+        const T u1i = U1i * srU1[i], u1m = U1m * srU1[im];
+        const T UU = T(0.25) * (U0m + U0i + U1m + U1i);
+        const T uu = T(0.25) * (u0m + u0i + u1m + u1i);
+        const T fs = fvj + uu * cotva;
+        const C TV = -(C)sPV0[i] * pgf + (C)fs * (C)UU;
+        goV[idv] = (T)((C)baseV + A.ch * TV);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (k + 1 < nz) commit(k + 1, lev0 + (size_t)((k + 1) & 1) * bufStride);
+    __syncthreads();
+  }
+
+  if (!isPole) {
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) {
+        const size_t idx = (size_t)j * nx + i;
+        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c]));
       }
     }
   } else {
@@ -321,26 +699,26 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
 // ----------------------------------------------------------------------------------------------
 // Advection: out = base - ch * L(in), L in the IAP skew form, zonal part leaped
 // ----------------------------------------------------------------------------------------------
-// LDS: P rows j-1..j+2; per level the rows MU(j+1), Phi(j), U(j), V(j+1/2), u on the V row,
-// v sin(theta) on V rows j-1/2 and j+1/2, and sigma-dot of row j at two half levels.
+// LDS: P rows j and j+1; per level the rows MU(j+1), u(j), u on the V row, Phi(j), U(j), V(j+1/2),
+// v sin(theta) on V rows j-1/2 and j+1/2, and sigma-dot of row j at two half levels.  The first
+// pass (column totals Pi) reads leap neighbours straight from global memory, without barriers.
 template <typename T, int NI>
 __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
   const GeoDev& g = A.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int B = blockDim.x, t = threadIdx.x;
-  T* sPm = reinterpret_cast<T*>(smem);    // P row j-1 (north pole WG: unused)
-  T* sP0 = sPm + nx;                       // P row j
+  T* sP0 = reinterpret_cast<T*>(smem);    // P row j
   T* sP1 = sP0 + nx;                       // P row j+1 (south pole WG: row ny-1)
-  T* sP2 = sP1 + nx;                       // P row j+2
-  T* sMU1 = sP2 + nx;                      // MU row j+1 at level k
-  T* suv = sMU1 + nx;                      // u averaged to V row j+1/2
+  T* sMU1 = sP1 + nx;                      // MU row j+1 at level k
+  T* su0 = sMU1 + nx;                      // u row j
+  T* suv = su0 + nx;                       // u averaged to V row j+1/2
   T* sF = suv + nx;                        // Phi row j
   T* sU = sF + nx;                         // U row j
   T* sV = sU + nx;                         // V row j
   T* svtm = sV + nx;                       // v sin(theta) on V row j-1
   T* svt0 = svtm + nx;                     // v sin(theta) on V row j
   T* sSd = svt0 + nx;                      // sigma-dot row j at two half levels [2][nx]
-  double* sRed = reinterpret_cast<double*>(smem + ((13 * nx * sizeof(T) + 15) & ~size_t(15)));
+  double* sCap = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));  // [2][nz]
 
   const bool isPole = (j == 0 || j == ny);
   const bool hasV = (j < ny);
@@ -360,11 +738,6 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
     if (jr == ny) return (T)A.pin[(nz + 1) + k];
     return A.inF[(size_t)jr * row3 + (size_t)k * nx + i];
   };
-  auto UA = [&](int jr, int k, int i) -> T {
-    if (jr <= 0 || jr >= ny) return T(0);
-    return A.inU[(size_t)jr * row3 + (size_t)k * nx + i];
-  };
-  auto VA = [&](int jv, int k, int i) -> T { return A.inV[(size_t)jv * row3 + (size_t)k * nx + i]; };
 
   const int ja = (j == 0) ? 1 : ny - 1;   // row next to a pole
   for (int c = 0; c < NI; ++c) {
@@ -372,264 +745,257 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
     if (i < nx) {
       sP0[i] = tsqrt<T>(psA(j, i) / p0);
       sP1[i] = tsqrt<T>(psA(hasV ? j + 1 : ja, i) / p0);
-      if (j >= 1) sPm[i] = tsqrt<T>(psA(j - 1, i) / p0);
-      if (j + 2 <= ny) sP2[i] = tsqrt<T>(psA(j + 2, i) / p0);
       sSd[i] = T(0);
       sSd[nx + i] = T(0);
     }
   }
   __syncthreads();
 
+  // pole caps of every level (FP64, wavefront 0): cap divergence of the pole row (j pole) or of
+  // the south pole seen from row ny-1, and the cap flux of Phi for a pole row
+  if ((isPole || (hasV && j1Pole)) && t < 64) {
+    const int jv = (j == 0) ? 0 : ny - 1;
+    for (int k = 0; k < nz; ++k) {
+      const T* pV = A.inV + (size_t)jv * row3 + (size_t)k * nx;
+      C s1 = 0, s2 = 0;
+      for (int i = t; i < nx; i += 64) {
+        const T pv = T(0.5) * (sP0[i] + sP1[i]);
+        const T vv = pV[i];
+        s1 += (C)(pv * vv);
+        if (isPole) s2 += (C)(vv / pv * (T)g.sv[jv] * FA(ja, k, i));
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
+    }
+  }
+  __syncthreads();
+
   const int Mj = isPole ? 1 : g.M[j], nj = (Mj + 1) / 2;
   const int Mj1 = j1Int ? g.M[j + 1] : 1, nj1 = (Mj1 + 1) / 2;
-  const T dxj = isPole ? T(1) : (T)((double)Mj * g.a * g.s[j] * g.dlam);
-  const T dxj1 = j1Int ? (T)((double)Mj1 * g.a * g.s[j + 1] * g.dlam) : T(1);
-  const T dySj = isPole ? T(1) : (T)(g.a * g.s[j] * g.dth);
-  const T dySj1 = j1Int ? (T)(g.a * g.s[j + 1] * g.dth) : T(1);
-  auto PU0 = [&](int p) -> T { return T(0.5) * (sP0[p] + sP0[wrp(p + 1, nx)]); };
-  auto PU1 = [&](int p) -> T { return T(0.5) * (sP1[p] + sP1[wrp(p + 1, nx)]); };
+  const T rdx = isPole ? T(0) : (T)(1.0 / ((double)Mj * g.a * g.s[j] * g.dlam));
+  const T rdx1 = j1Int ? (T)(1.0 / ((double)Mj1 * g.a * g.s[j + 1] * g.dlam)) : T(0);
+  const T rdyS = isPole ? T(0) : (T)(1.0 / (g.a * g.s[j] * g.dth));
+  const T rdyS1 = j1Int ? (T)(1.0 / (g.a * g.s[j + 1] * g.dth)) : T(0);
+  const T svj = hasV ? (T)g.sv[j] : T(0), svm = (j >= 1) ? (T)g.sv[j - 1] : T(0);
+  const T sv1 = (j + 1 < ny) ? (T)g.sv[j + 1] : T(0);
+  const C capD0 = isPole ? ((j == 0) ? 1.0 : -1.0) * g.a * g.dlam * g.sv[(j == 0) ? 0 : ny - 1] / g.acap : 0.0;
+  const C capD1 = (hasV && j1Pole) ? -g.a * g.dlam * g.sv[ny - 1] / g.acap : 0.0;
 
-  C Pi0[NI], Pi1[NI], S0[NI], S1[NI], sd0c[NI], sd1c[NI];
+  // per-column constants
+  int ip1[NI], ic[NI], id[NI], ic1[NI], id1[NI];
+  T PUc[NI], PUd[NI], rPU0[NI], rPU1[NI], PVm[NI], PV0[NI], PV1[NI], rPVm[NI], rPV0[NI], rPV1[NI];
+  C rP0sq[NI], rP1sq[NI], Pi0[NI], Pi1[NI], S0[NI], S1[NI], sd0c[NI], sd1c[NI];
 #pragma unroll
-  for (int c = 0; c < NI; ++c) { Pi0[c] = Pi1[c] = S0[c] = S1[c] = sd0c[c] = sd1c[c] = 0; }
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    const int ii = i < nx ? i : 0;
+    ip1[c] = wrp(ii + 1, nx);
+    ic[c] = wrp(ii + nj - 1, nx); id[c] = wrp(ii - nj, nx);
+    ic1[c] = wrp(ii + nj1 - 1, nx); id1[c] = wrp(ii - nj1, nx);
+    const T P0 = sP0[ii], P1 = sP1[ii];
+    rP0sq[c] = 1.0 / ((C)P0 * (C)P0);
+    rP1sq[c] = hasV ? 1.0 / ((C)P1 * (C)P1) : 0.0;
+    PUc[c] = T(0.5) * (sP0[ic[c]] + sP0[wrp(ic[c] + 1, nx)]);
+    PUd[c] = T(0.5) * (sP0[id[c]] + sP0[wrp(id[c] + 1, nx)]);
+    rPU0[c] = isPole ? T(0) : T(2) / (P0 + sP0[ip1[c]]);
+    rPU1[c] = j1Int ? T(2) / (P1 + sP1[ip1[c]]) : T(0);
+    PVm[c] = PV0[c] = PV1[c] = rPVm[c] = rPV0[c] = rPV1[c] = T(1);
+    if (hasV) { PV0[c] = T(0.5) * (P0 + P1); rPV0[c] = T(1) / PV0[c]; }
+    if (j >= 1) { PVm[c] = T(0.5) * (tsqrt<T>(psA(j - 1, ii) / p0) + P0); rPVm[c] = T(1) / PVm[c]; }
+    if (j + 2 <= ny) { PV1[c] = T(0.5) * (P1 + tsqrt<T>(psA(j + 2, ii) / p0)); rPV1[c] = T(1) / PV1[c]; }
+    Pi0[c] = Pi1[c] = S0[c] = S1[c] = sd0c[c] = sd1c[c] = 0;
+  }
+  // MU of row j+1 at leap positions comes from LDS in pass B; in pass A from global
+  T PU1c[NI], PU1d[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) {
+    PU1c[c] = j1Int ? T(0.5) * (sP1[ic1[c]] + sP1[wrp(ic1[c] + 1, nx)]) : T(0);
+    PU1d[c] = j1Int ? T(0.5) * (sP1[id1[c]] + sP1[wrp(id1[c] + 1, nx)]) : T(0);
+  }
 
-  // divergence of rows j and j+1 at level k from the LDS rows sU (row j) and sMU1 (row j+1) and the
-  // V values Vj (row j), Vm (row j-1), V1 (row j+1) of the own column.
-  auto div_rows = [&](int k, const T* Vj, const T* Vm, const T* V1, C* D0, C* D1) {
-    const bool needPole = isPole || (hasV && j1Pole);
-    if (needPole) {
-      if (t < 64) {
-        C s = 0;
-        const int jv = (j == 0) ? 0 : ny - 1;
-        for (int i = t; i < nx; i += 64) {
-          // the V row next to the pole with P of its two scalar rows: for j == 0 rows 0,1 (sP0,sP1);
-          // j == ny: pole, ny-1 (sP0,sP1); j == ny-1: ny-1, pole (sP0,sP1)
-          const T pv = T(0.5) * (sP0[i] + sP1[i]);
-          s += (C)(pv * VA(jv, k, i));
-        }
-        s = wave_sum(s);
-        if (t == 0) sRed[0] = s;
-      }
-      __syncthreads();
-    }
+  // ---- pass A: column totals Pi for rows j and j+1 (no LDS, no barriers)
+#pragma unroll 1
+  for (int k = 0; k < nz; ++k) {
+    const size_t lev = (size_t)k * nx;
+    const T* pU0 = isPole ? nullptr : A.inU + (size_t)j * row3 + lev;
+    const T* pU1 = j1Int ? A.inU + (size_t)(j + 1) * row3 + lev : nullptr;
+    const T* pV0 = hasV ? A.inV + (size_t)j * row3 + lev : nullptr;
+    const T* pVm = (j >= 1) ? A.inV + (size_t)(j - 1) * row3 + lev : nullptr;
+    const T* pV1 = (j + 1 < ny) ? A.inV + (size_t)(j + 1) * row3 + lev : nullptr;
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
-      D0[c] = 0; D1[c] = 0;
       if (i >= nx) continue;
+      const T Vj = pV0 ? pV0[i] : T(0);
+      C D0, D1 = 0;
       if (isPole) {
-        const int jv = (j == 0) ? 0 : ny - 1;
-        const C sgn = (j == 0) ? 1.0 : -1.0;
-        D0[c] = sgn * g.a * g.dlam * g.sv[jv] * sRed[0] / g.acap;
+        D0 = capD0 * sCap[k];
       } else {
-        const int pa = wrp(i + nj - 1, nx), pb = wrp(i - nj, nx);
-        const T D = (PU0(pa) * sU[pa] - PU0(pb) * sU[pb]) / dxj +
-                    ((T)g.sv[j] * (T(0.5) * (sP0[i] + sP1[i]) * Vj[c]) -
-                     (T)g.sv[j - 1] * (T(0.5) * (sPm[i] + sP0[i]) * Vm[c])) / dySj;
-        D0[c] = (C)D;
+        D0 = (C)((PUc[c] * pU0[ic[c]] - PUd[c] * pU0[id[c]]) * rdx +
+                 (svj * (PV0[c] * Vj) - svm * (PVm[c] * pVm[i])) * rdyS);
       }
       if (hasV) {
-        if (j1Pole) {
-          D1[c] = -g.a * g.dlam * g.sv[ny - 1] * sRed[0] / g.acap;
-        } else {
-          const T D = (sMU1[wrp(i + nj1 - 1, nx)] - sMU1[wrp(i - nj1, nx)]) / dxj1 +
-                      ((T)g.sv[j + 1] * (T(0.5) * (sP1[i] + sP2[i]) * V1[c]) -
-                       (T)g.sv[j] * (T(0.5) * (sP0[i] + sP1[i]) * Vj[c])) / dySj1;
-          D1[c] = (C)D;
-        }
+        if (j1Pole) D1 = capD1 * sCap[k];
+        else
+          D1 = (C)((PU1c[c] * pU1[ic1[c]] - PU1d[c] * pU1[id1[c]]) * rdx1 +
+                   (sv1 * (PV1[c] * pV1[i]) - svj * (PV0[c] * Vj)) * rdyS1);
       }
+      Pi0[c] += D0 * g.dsig[k];
+      Pi1[c] += D1 * g.dsig[k];
     }
-  };
-
-  // ---- pass A: column totals Pi for rows j and j+1
-  for (int k = 0; k < nz; ++k) {
-    T Vj[NI], Vm[NI], V1[NI];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      Vj[c] = Vm[c] = V1[c] = T(0);
-      if (i < nx) {
-        sU[i] = UA(j, k, i);
-        if (j1Int) sMU1[i] = PU1(i) * UA(j + 1, k, i);
-        if (hasV) Vj[c] = VA(j, k, i);
-        if (j >= 1) Vm[c] = VA(j - 1, k, i);
-        if (j + 1 < ny) V1[c] = VA(j + 1, k, i);
-      }
-    }
-    __syncthreads();
-    C D0[NI], D1[NI];
-    div_rows(k, Vj, Vm, V1, D0, D1);
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      Pi0[c] += D0[c] * g.dsig[k];
-      Pi1[c] += D1[c] * g.dsig[k];
-    }
-    __syncthreads();
   }
 
   // ---- pass B
   const C cc = g.a * g.dlam / (2.0 * g.acap);
+  const T rdx2 = T(0.5) * rdx;
+  const T rdy2 = T(0.5) * rdyS;
+  const int Mv = hasV ? g.Mv[j] : 1, nv = (Mv + 1) / 2;
+  const T rdxv2 = hasV ? (T)(1.0 / (2.0 * (double)Mv * g.a * g.sv[j] * g.dlam)) : T(0);
+  const T rdyv2 = hasV ? (T)(1.0 / (2.0 * g.a * g.sv[j] * g.dth)) : T(0);
   for (int k = 0; k < nz; ++k) {
-    const C dsg = g.dsig[k];
+    const C dsg = g.dsig[k], r2d = 1.0 / (2.0 * dsg);
     const int par = k & 1, parn = (k + 1) & 1;
+    const size_t lev = (size_t)k * nx;
+    const T* pU0 = isPole ? nullptr : A.inU + (size_t)j * row3 + lev;
+    const T* pU1 = j1Int ? A.inU + (size_t)(j + 1) * row3 + lev : nullptr;
+    const T* pV0 = hasV ? A.inV + (size_t)j * row3 + lev : nullptr;
+    const T* pVm = (j >= 1) ? A.inV + (size_t)(j - 1) * row3 + lev : nullptr;
+    const T* pV1 = (j + 1 < ny) ? A.inV + (size_t)(j + 1) * row3 + lev : nullptr;
     // phase 1: loads of this level; LDS rows
-    T Vj[NI], Vm[NI], V1[NI], Fn[NI], Fs[NI], Fup[NI], Fdn[NI], Un[NI], Us[NI], Uup[NI], Udn[NI];
-    T Vup[NI], Vdn[NI], bF[NI], bU[NI], bV[NI];
+    T Vj[NI], Vm[NI], V1[NI], Fn[NI], Fs[NI], Un[NI], Us[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
-      Vj[c] = Vm[c] = V1[c] = Fn[c] = Fs[c] = Fup[c] = Fdn[c] = Un[c] = Us[c] = Uup[c] = Udn[c] = T(0);
-      Vup[c] = Vdn[c] = bF[c] = bU[c] = bV[c] = T(0);
+      Vj[c] = Vm[c] = V1[c] = Fn[c] = Fs[c] = Un[c] = Us[c] = T(0);
       if (i < nx) {
-        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
+        const size_t idx = (size_t)j * row3 + lev + i;
         const T Fj = FA(j, k, i);
-        const T Uj = UA(j, k, i);
+        const T Uj = pU0 ? pU0[i] : T(0);
         sF[i] = Fj;
         sU[i] = Uj;
-        const T u0 = isPole ? T(0) : Uj / PU0(i);
-        const T U1 = UA(j + 1, k, i);
-        if (j1Int) sMU1[i] = PU1(i) * U1;
+        const T u0 = Uj * rPU0[c];
+        su0[i] = u0;
+        const T U1 = pU1 ? pU1[i] : T(0);
+        if (j1Int) sMU1[i] = T(0.5) * (sP1[i] + sP1[ip1[c]]) * U1;
         if (hasV) {
-          Vj[c] = VA(j, k, i);
+          Vj[c] = pV0[i];
           sV[i] = Vj[c];
-          svt0[i] = Vj[c] / (T(0.5) * (sP0[i] + sP1[i])) * (T)g.sv[j];
-          const T u1 = j1Int ? U1 / PU1(i) : T(0);
-          suv[i] = T(0.5) * (u0 + u1);
-          bV[c] = A.bV[id];
-          if (k > 0) Vup[c] = VA(j, k - 1, i);
-          if (k + 1 < nz) Vdn[c] = VA(j, k + 1, i);
+          svt0[i] = Vj[c] * rPV0[c] * svj;
+          suv[i] = T(0.5) * (u0 + U1 * rPU1[c]);
         }
         if (j >= 1) {
-          Vm[c] = VA(j - 1, k, i);
-          svtm[i] = Vm[c] / (T(0.5) * (sPm[i] + sP0[i])) * (T)g.sv[j - 1];
+          Vm[c] = pVm[i];
+          svtm[i] = Vm[c] * rPVm[c] * svm;
         }
-        if (j + 1 < ny) V1[c] = VA(j + 1, k, i);
-        if (k > 0) Fup[c] = FA(j, k - 1, i);
-        if (k + 1 < nz) Fdn[c] = FA(j, k + 1, i);
+        if (pV1) V1[c] = pV1[i];
         if (!isPole) {
           Fn[c] = FA(j + 1, k, i);
           Fs[c] = FA(j - 1, k, i);
           Un[c] = U1;
-          Us[c] = UA(j - 1, k, i);
-          if (k > 0) Uup[c] = UA(j, k - 1, i);
-          if (k + 1 < nz) Udn[c] = UA(j, k + 1, i);
-          bF[c] = A.bF[id];
-          bU[c] = A.bU[id];
+          Us[c] = (j - 1 >= 1) ? A.inU[(size_t)(j - 1) * row3 + lev + i] : T(0);
         }
       }
     }
     __syncthreads();
-    C D0[NI], D1[NI];
-    div_rows(k, Vj, Vm, V1, D0, D1);
     C sd0n[NI], sd1n[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
-      S0[c] += D0[c] * dsg;
-      S1[c] += D1[c] * dsg;
+      C D0 = 0, D1 = 0;
+      if (i < nx) {
+        if (isPole) {
+          D0 = capD0 * sCap[k];
+        } else {
+          D0 = (C)((PUc[c] * sU[ic[c]] - PUd[c] * sU[id[c]]) * rdx +
+                   (svj * (PV0[c] * Vj[c]) - svm * (PVm[c] * Vm[c])) * rdyS);
+        }
+        if (hasV) {
+          if (j1Pole) D1 = capD1 * sCap[k];
+          else
+            D1 = (C)((sMU1[ic1[c]] - sMU1[id1[c]]) * rdx1 + (sv1 * (PV1[c] * V1[c]) - svj * (PV0[c] * Vj[c])) * rdyS1);
+        }
+      }
+      S0[c] += D0 * dsg;
+      S1[c] += D1 * dsg;
       sd0n[c] = 0; sd1n[c] = 0;
       if (k + 1 < nz && i < nx) {
         const C sh = g.sigh[k + 1];
-        sd0n[c] = (sh * Pi0[c] - S0[c]) / ((C)sP0[i] * (C)sP0[i]);
-        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) / ((C)sP1[i] * (C)sP1[i]);
+        sd0n[c] = (sh * Pi0[c] - S0[c]) * rP0sq[c];
+        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) * rP1sq[c];
       }
       if (i < nx) sSd[parn * nx + i] = (T)sd0n[c];
-    }
-    // pole: meridional cap flux of Phi (needs every column of the adjacent rows)
-    if (isPole) {
-      if (t < 64) {
-        C s = 0;
-        const int jv = (j == 0) ? 0 : ny - 1;
-        for (int i = t; i < nx; i += 64) {
-          const T pv = T(0.5) * (sP0[i] + sP1[i]);
-          const T vt = VA(jv, k, i) / pv * (T)g.sv[jv];
-          s += (C)(vt * FA(ja, k, i));
-        }
-        s = wave_sum(s);
-        if (t == 0) sRed[1] = s;
-      }
     }
     __syncthreads();
 
     if (!isPole) {
-      const T dx2 = T(2) * dxj;
-      const T dy2 = T(2) * dySj;
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
-        const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
-        const int ip1 = wrp(i + 1, nx);
-        auto u0 = [&](int p) -> T { return sU[p] / PU0(p); };
+        const size_t idx = (size_t)j * row3 + lev + i;
+        const int pM = wrp(i + Mj, nx), mM = wrp(i - Mj, nx);
         // Phi: zonal (x+1,x-1) -> (x+2N-1, x-2N+1), u at the midpoints
-        const int qa = wrp(i + nj - 1, nx), qb = wrp(i - nj, nx);
-        const T L1 = (u0(qa) * sF[wrp(i + Mj, nx)] - u0(qb) * sF[wrp(i - Mj, nx)]) / dx2;
-        const T L2 = (svt0[i] * Fn[c] - svtm[i] * Fs[c]) / dy2;
+        const T L1 = (su0[ic[c]] * sF[pM] - su0[id[c]] * sF[mM]) * rdx2;
+        const T L2 = (svt0[i] * Fn[c] - svtm[i] * Fs[c]) * rdy2;
         C L3 = 0;
-        if (k + 1 < nz) L3 += sd0n[c] * (C)Fdn[c];
-        if (k > 0) L3 -= sd0c[c] * (C)Fup[c];
-        L3 /= (2.0 * dsg);
-        const C TF = -((C)L1 + (C)L2 + L3);
-        A.oF[id] = (T)((C)bF[c] + A.ch * TF);
-        // U: same leap on U points with u averaged to integer points
+        if (k + 1 < nz) L3 += sd0n[c] * (C)A.inF[idx + nx];
+        if (k > 0) L3 -= sd0c[c] * (C)A.inF[idx - nx];
+        const C TF = -((C)L1 + (C)L2 + L3 * r2d);
+        A.oF[idx] = (T)((C)A.bF[idx] + A.ch * TF);
+        // U: same leap on U points with u averaged to the integer points i+n and i+1-n
         const int pA = wrp(i + nj, nx), pB = wrp(i + 1 - nj, nx);
-        const T ubA = T(0.5) * (u0(wrp(pA - 1, nx)) + u0(pA));
-        const T ubB = T(0.5) * (u0(wrp(pB - 1, nx)) + u0(pB));
-        const T U1v = (ubA * sU[wrp(i + Mj, nx)] - ubB * sU[wrp(i - Mj, nx)]) / dx2;
-        const T vtn = T(0.5) * (svt0[i] + svt0[ip1]);
-        const T vts = T(0.5) * (svtm[i] + svtm[ip1]);
-        const T U2v = (vtn * Un[c] - vts * Us[c]) / dy2;
+        const T ubA = T(0.5) * (su0[ic[c]] + su0[pA]);
+        const T ubB = T(0.5) * (su0[id[c]] + su0[pB]);
+        const T U1v = (ubA * sU[pM] - ubB * sU[mM]) * rdx2;
+        const int ip = ip1[c];
+        const T vtn = T(0.5) * (svt0[i] + svt0[ip]);
+        const T vts = T(0.5) * (svtm[i] + svtm[ip]);
+        const T U2v = (vtn * Un[c] - vts * Us[c]) * rdy2;
         C U3 = 0;
-        if (k + 1 < nz) U3 += (C)(T(0.5) * (sSd[parn * nx + i] + sSd[parn * nx + ip1])) * (C)Udn[c];
-        if (k > 0) U3 -= (C)(T(0.5) * (sSd[par * nx + i] + sSd[par * nx + ip1])) * (C)Uup[c];
-        U3 /= (2.0 * dsg);
-        const C TU = -((C)U1v + (C)U2v + U3);
-        A.oU[id] = (T)((C)bU[c] + A.ch * TU);
+        if (k + 1 < nz) U3 += (C)(T(0.5) * (sSd[parn * nx + i] + sSd[parn * nx + ip])) * (C)A.inU[idx + nx];
+        if (k > 0) U3 -= (C)(T(0.5) * (sSd[par * nx + i] + sSd[par * nx + ip])) * (C)A.inU[idx - nx];
+        const C TU = -((C)U1v + (C)U2v + U3 * r2d);
+        A.oU[idx] = (T)((C)A.bU[idx] + A.ch * TU);
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       const C sgn = (j == 0) ? 1.0 : -1.0;
-      const C L2 = sgn * cc * sRed[1];
+      const C L2 = sgn * cc * sCap[nz + k];
       C L3 = 0;
       if (k + 1 < nz) L3 += sd0n[0] * (C)FA(j, k + 1, 0);
       if (k > 0) L3 -= sd0c[0] * (C)FA(j, k - 1, 0);
-      L3 /= (2.0 * dsg);
-      const C TF = -(L2 + L3);
+      const C TF = -(L2 + L3 * r2d);
       const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i < nx) {
-          const size_t id = (size_t)j * row3 + (size_t)k * nx + i;
-          A.oF[id] = val;
-          A.oU[id] = T(0);
+          const size_t idx = (size_t)j * row3 + lev + i;
+          A.oF[idx] = val;
+          A.oU[idx] = T(0);
         }
       }
       if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
     }
 
     if (hasV) {
-      const int Mv = g.Mv[j], nv = (Mv + 1) / 2;
-      const T dxv2 = (T)(2.0 * (double)Mv * g.a * g.sv[j] * g.dlam);
-      const T dyv2 = (T)(2.0 * g.a * g.sv[j] * g.dth);
 #pragma unroll
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
-        const size_t idv = (size_t)j * row3 + (size_t)k * nx + i;
-        const T L1 = (suv[wrp(i + nv - 1, nx)] * sV[wrp(i + Mv, nx)] - suv[wrp(i - nv, nx)] * sV[wrp(i - Mv, nx)]) / dxv2;
+        const size_t idv = (size_t)j * row3 + lev + i;
+        const T L1 = (suv[wrp(i + nv - 1, nx)] * sV[wrp(i + Mv, nx)] - suv[wrp(i - nv, nx)] * sV[wrp(i - Mv, nx)]) * rdxv2;
         T L2 = T(0);
-        if (j + 1 < ny) {
-          const T vt1 = V1[c] / (T(0.5) * (sP1[i] + sP2[i])) * (T)g.sv[j + 1];
-          L2 += T(0.5) * (svt0[i] + vt1) * V1[c];
-        }
+        if (j + 1 < ny) L2 += T(0.5) * (svt0[i] + V1[c] * rPV1[c] * sv1) * V1[c];
         if (j > 0) L2 -= T(0.5) * (svtm[i] + svt0[i]) * Vm[c];
-        L2 = L2 / dyv2;
+        L2 = L2 * rdyv2;
         C L3 = 0;
-        if (k + 1 < nz) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)Vdn[c];
-        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)Vup[c];
-        L3 /= (2.0 * dsg);
-        const C TV = -((C)L1 + (C)L2 + L3);
-        A.oV[idv] = (T)((C)bV[c] + A.ch * TV);
+        if (k + 1 < nz) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)A.inV[idv + nx];
+        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)A.inV[idv - nx];
+        const C TV = -((C)L1 + (C)L2 + L3 * r2d);
+        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
 #pragma unroll
@@ -656,17 +1022,20 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
 }
 
 // One launch per stage; the process is a template parameter so that the
-// adaptation and advection kernels are separate symbols in a profile.
+// adaptation and advection kernels are separate symbols in a profile.  PROC: 0 adaptation,
+// 1 advection, 2 adaptation pipelined (FP32 rows that fit the LDS).
 template <typename T, int NI, int PROC>
 __global__ void __launch_bounds__(max_block(NI)) k_stage(StageArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int j = xcd_row(blockIdx.x, a.g.ny + 1);
-  if (PROC == 0) adapt_row<T, NI>(a, j, smem);
+  if constexpr (PROC == 0) adapt_row<T, NI>(a, j, smem);
+  else if constexpr (PROC == 2) adapt_row_pipe<T, NI>(a, j, smem);
   else advect_row<T, NI>(a, j, smem);
 }
 
 // Persistent batched stage: work item w = (member, row); block b takes items b, b+G, ...
-template <typename T, int NI>
+// PIPE: 1 when every member's adaptation takes the pipelined form, 0 when none does, 2 mixed.
+template <typename T, int NI, int PIPE>
 __global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T>* __restrict__ args,
                                                      const int2* __restrict__ items, int nitems) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -674,7 +1043,12 @@ __global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T
     const int2 it = items[w];
     if (it.x < 0) continue;
     const StageArgs<T> a = args[it.x];
-    if (a.process == 0) adapt_row<T, NI>(a, it.y, smem);
+    if (a.process == 0) {
+      if constexpr (PIPE == 1) adapt_row_pipe<T, NI>(a, it.y, smem);
+      else if constexpr (PIPE == 0) adapt_row<T, NI>(a, it.y, smem);
+      else if (adapt_pipe_ok(a.g.nx)) adapt_row_pipe<T, NI>(a, it.y, smem);
+      else adapt_row<T, NI>(a, it.y, smem);
+    }
     else if (a.process == 1) advect_row<T, NI>(a, it.y, smem);
     __syncthreads();
   }
@@ -793,7 +1167,11 @@ template <typename T, int NI>
 hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
   const size_t lds = stage_lds_bytes(a.process, a.g.nx, sizeof(T));
   hipError_t e;
-  if (a.process == 0) {
+  if (a.process == 0 && sizeof(T) == 4 && adapt_pipe_ok(a.g.nx)) {
+    e = allow_lds<k_stage<T, NI, 2>>(lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage<T, NI, 2>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
+  } else if (a.process == 0) {
     e = allow_lds<k_stage<T, NI, 0>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 0>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
@@ -805,24 +1183,33 @@ hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int NI, int PIPE>
+hipError_t launch_batch_pipe(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
+                             size_t lds, hipStream_t s) {
+  hipError_t e = allow_lds<k_stage_batch<T, NI, PIPE>>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_stage_batch<T, NI, PIPE>), dim3(grid), dim3(block), lds, s, d_args, d_items, nitems);
+  return hipGetLastError();
+}
+
 template <typename T, int NI>
 hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
-                           int max_nx, hipStream_t s) {
-  const size_t lds = std::max(stage_lds_bytes(0, max_nx, sizeof(T)), stage_lds_bytes(1, max_nx, sizeof(T)));
-  hipError_t e = allow_lds<k_stage_batch<T, NI>>(lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stage_batch<T, NI>), dim3(grid), dim3(block), lds, s, d_args, d_items, nitems);
-  return hipGetLastError();
+                           size_t lds, int pipe, hipStream_t s) {
+  if (sizeof(T) == 4 && pipe == 1) return launch_batch_pipe<T, NI, 1>(d_args, d_items, nitems, grid, block, lds, s);
+  if (sizeof(T) == 4 && pipe == 2) return launch_batch_pipe<T, NI, 2>(d_args, d_items, nitems, grid, block, lds, s);
+  return launch_batch_pipe<T, NI, 0>(d_args, d_items, nitems, grid, block, lds, s);
 }
 
 }  // namespace
 
 size_t stage_lds_bytes(int process, int nx, int elem) {
-  const size_t rows = (process == 0) ? 12 : 13;
-  return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 4 * sizeof(double);
+  if (process == 0 && elem == 4 && adapt_pipe_ok(nx)) return adapt_pipe_lds(nx);
+  const size_t rows = 12;
+  return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 2 * 128 * sizeof(double);
 }
 
 int columns_per_thread(int nx, int block) { return (nx + block - 1) / block; }
+int adapt_pipelined(int nx, int elem) { return elem == 4 && adapt_pipe_ok(nx) ? 1 : 0; }
 
 template <typename T>
 hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
@@ -841,16 +1228,16 @@ hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_stage_batch(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
-                              int max_nx, hipStream_t s) {
+                              int max_nx, size_t lds, int pipe, hipStream_t s) {
   switch (columns_per_thread(max_nx, block)) {
-    case 1: return launch_batch_ni<T, 1>(d_args, d_items, nitems, grid, block, max_nx, s);
-    case 2: return launch_batch_ni<T, 2>(d_args, d_items, nitems, grid, block, max_nx, s);
-    case 3: return launch_batch_ni<T, 3>(d_args, d_items, nitems, grid, block, max_nx, s);
-    case 4: return launch_batch_ni<T, 4>(d_args, d_items, nitems, grid, block, max_nx, s);
-    case 5: return launch_batch_ni<T, 5>(d_args, d_items, nitems, grid, block, max_nx, s);
-    case 6: return launch_batch_ni<T, 6>(d_args, d_items, nitems, grid, block, max_nx, s);
-    case 7: return launch_batch_ni<T, 7>(d_args, d_items, nitems, grid, block, max_nx, s);
-    case 8: return launch_batch_ni<T, 8>(d_args, d_items, nitems, grid, block, max_nx, s);
+    case 1: return launch_batch_ni<T, 1>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 2: return launch_batch_ni<T, 2>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 3: return launch_batch_ni<T, 3>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 4: return launch_batch_ni<T, 4>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 5: return launch_batch_ni<T, 5>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 6: return launch_batch_ni<T, 6>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 7: return launch_batch_ni<T, 7>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 8: return launch_batch_ni<T, 8>(d_args, d_items, nitems, grid, block, lds, pipe, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -889,7 +1276,8 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s) {
 
 #define DYC_INST(T)                                                                                          \
   template hipError_t launch_stage<T>(const StageArgs<T>&, int, hipStream_t);                                \
-  template hipError_t launch_stage_batch<T>(const StageArgs<T>*, const int2*, int, int, int, int, hipStream_t); \
+  template hipError_t launch_stage_batch<T>(const StageArgs<T>*, const int2*, int, int, int, int, size_t, int,  \
+                                            hipStream_t);                                                    \
   template hipError_t launch_pole_prep<T>(const GeoDev&, const T*, const T*, double*, hipStream_t);          \
   template hipError_t launch_diag<T>(const GeoDev&, const T*, const T*, const T*, const T*, double*, int,    \
                                      hipStream_t);                                                           \
