@@ -63,7 +63,7 @@ HandleView view_of(const dycore_s* h);
 struct dycore_batch_s {
   int n, prec, block, grid, max_nx, nstage_max;
   size_t lds;   // dynamic LDS of the batched stage kernel: the largest need of any member
-  int pipe;     // adaptation form: 1 all members pipelined, 0 none, 2 mixed
+  int pipe;     // stage kernel form: 1 all members pipelined, 0 none, 2 mixed
   std::vector<dycore_t> hs;
   void* d_args = nullptr;       // nstage_max x n StageArgs
   int2* d_items = nullptr;
@@ -629,7 +629,7 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
     nst = std::max(nst, 3 * (hs[m]->msub + 1));
     const int el = hs[m]->prec == DYCORE_FP32 ? 4 : 8;
     lds = std::max(lds, std::max(stage_lds_bytes(0, hs[m]->nx, el), stage_lds_bytes(1, hs[m]->nx, el)));
-    npipe += adapt_pipelined(hs[m]->nx, el);
+    npipe += stage_pipelined(hs[m]->nx, el);
   }
   if (block == 0) block = 256;
   if (block < 64 || block > 1024 || block % 64) return DYCORE_EINVAL;

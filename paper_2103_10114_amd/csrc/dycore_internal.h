@@ -85,7 +85,7 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s);
 
 size_t stage_lds_bytes(int process, int nx, int elem);
 int columns_per_thread(int nx, int block);
-int adapt_pipelined(int nx, int elem);   // 1 if the adaptation stage of rows of nx columns is pipelined
+int stage_pipelined(int nx, int elem);   // 1 if the stage kernels for rows of nx columns are pipelined
 int max_block_for(int nx, int block);   // 1 if `block` threads are allowed for rows of nx columns
 
 // XCD-aware row order: workgroups are dispatched round-robin over the 8 XCDs,

@@ -1021,20 +1021,417 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
   }
 }
 
+// Advection, FP32 storage, software-pipelined.  LDS: the P rows j and j+1, the reciprocal
+// U-point averages of P on rows j and j+1, the V-point averages of P (and their reciprocals) on
+// V rows j-1/2, j+1/2, j+3/2, the per-level rows (Phi, U, u of row j, V, the u average on the V
+// row, v sin(theta) on V rows j+-1/2) double-buffered, and sigma-dot of row j in a ring of three
+// half levels.  Level k+1 (own columns, the leap gathers of U that its divergence needs, and the
+// base values) is fetched while level k is computed; the vertical neighbours come from a rolling
+// register window, so each level is read from memory once.  One barrier per level.
+constexpr int kAdvectPipeRows2D = 10, kAdvectPipeRowsLev = 7;
+__host__ __device__ constexpr size_t advect_pipe_lds(int nx) {
+  return (((size_t)(kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3) * nx * 4 + 15) & ~size_t(15)) +
+         2 * 128 * sizeof(double);
+}
+__host__ __device__ constexpr bool advect_pipe_ok(int nx) { return advect_pipe_lds(nx) <= 160 * 1024; }
+
+template <typename T, int NI>
+__device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned char* smem) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int B = blockDim.x;
+  int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
+  T* r = reinterpret_cast<T*>(smem);
+  T* sP0 = r;             T* sP1 = r + nx;        T* srPU0 = r + 2 * nx;  T* srPU1 = r + 3 * nx;
+  T* sPV0 = r + 4 * nx;   T* sPVm = r + 5 * nx;   T* sPV1 = r + 6 * nx;   T* srPV0 = r + 7 * nx;
+  T* srPVm = r + 8 * nx;  T* srPV1 = r + 9 * nx;
+  T* lev0 = r + kAdvectPipeRows2D * nx;                       // [2][7][nx]
+  const size_t bufStride = (size_t)kAdvectPipeRowsLev * nx;
+  T* sSd = lev0 + 2 * bufStride;                              // [3][nx], slot h % 3 for half level h
+  double* sCap = reinterpret_cast<double*>(
+      smem + ((((size_t)kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3) * nx * sizeof(T) + 15) & ~size_t(15)));
+
+  const bool isPole = (j == 0 || j == ny);
+  const bool hasV = (j < ny);
+  const bool j1Pole = (j + 1 == ny);
+  const bool j1Int = (j + 1 >= 1 && j + 1 <= ny - 1);
+  const int pidx = (j == 0) ? 0 : 1;
+  const T p0 = (T)g.p0;
+  const size_t row3 = (size_t)nz * nx;
+  auto psA = [&](int jr, int i) -> T {
+    if (jr == 0) return (T)A.pin[nz];
+    if (jr == ny) return (T)A.pin[(nz + 1) + nz];
+    return A.inP[(size_t)jr * nx + i];
+  };
+  auto FA = [&](int jr, int k, int i) -> T {
+    if (jr == 0) return (T)A.pin[k];
+    if (jr == ny) return (T)A.pin[(nz + 1) + k];
+    return A.inF[(size_t)jr * row3 + (size_t)k * nx + i];
+  };
+
+  // ---- 2D rows
+  const int ja = (j == 0) ? 1 : ny - 1;   // row next to a pole
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    if (i < nx) {
+      const T P0 = tsqrt<T>(psA(j, i) / p0);
+      const T P1 = tsqrt<T>(psA(hasV ? j + 1 : ja, i) / p0);
+      sP0[i] = P0;
+      sP1[i] = P1;
+      T PV0 = T(1), PVm = T(1), PV1 = T(1);
+      if (hasV) PV0 = T(0.5) * (P0 + P1);
+      if (j >= 1) PVm = T(0.5) * (tsqrt<T>(psA(j - 1, i) / p0) + P0);
+      if (j + 2 <= ny) PV1 = T(0.5) * (P1 + tsqrt<T>(psA(j + 2, i) / p0));
+      sPV0[i] = PV0; sPVm[i] = PVm; sPV1[i] = PV1;
+      srPV0[i] = T(1) / PV0; srPVm[i] = T(1) / PVm; srPV1[i] = T(1) / PV1;
+      sSd[i] = T(0);   // half level 0
+    }
+  }
+  __syncthreads();
+  if ((isPole || (hasV && j1Pole)) && t < 64) {
+    const int jv = (j == 0) ? 0 : ny - 1;
+    for (int k = 0; k < nz; ++k) {
+      const T* pV = A.inV + (size_t)jv * row3 + (size_t)k * nx;
+      C s1 = 0, s2 = 0;
+      for (int i = t; i < nx; i += 64) {
+        const T pv = T(0.5) * (sP0[i] + sP1[i]);
+        const T vv = pV[i];
+        s1 += (C)(pv * vv);
+        if (isPole) s2 += (C)(vv / pv * (T)g.sv[jv] * FA(ja, k, i));
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
+    }
+  }
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    if (i < nx) {
+      const int ip = wrp(i + 1, nx);
+      srPU0[i] = isPole ? T(0) : T(2) / (sP0[i] + sP0[ip]);
+      srPU1[i] = j1Int ? T(2) / (sP1[i] + sP1[ip]) : T(0);
+    }
+  }
+
+  const int Mj = isPole ? 1 : g.M[j], nj = (Mj + 1) / 2;
+  const int Mj1 = j1Int ? g.M[j + 1] : 1, nj1 = (Mj1 + 1) / 2;
+  const T rdx = isPole ? T(0) : (T)(1.0 / ((double)Mj * g.a * g.s[j] * g.dlam));
+  const T rdx1 = j1Int ? (T)(1.0 / ((double)Mj1 * g.a * g.s[j + 1] * g.dlam)) : T(0);
+  const T rdyS = isPole ? T(0) : (T)(1.0 / (g.a * g.s[j] * g.dth));
+  const T rdyS1 = j1Int ? (T)(1.0 / (g.a * g.s[j + 1] * g.dth)) : T(0);
+  const T svj = hasV ? (T)g.sv[j] : T(0), svm = (j >= 1) ? (T)g.sv[j - 1] : T(0);
+  const T sv1 = (j + 1 < ny) ? (T)g.sv[j + 1] : T(0);
+  const C capD0 = isPole ? ((j == 0) ? 1.0 : -1.0) * g.a * g.dlam * g.sv[(j == 0) ? 0 : ny - 1] / g.acap : 0.0;
+  const C capD1 = (hasV && j1Pole) ? -g.a * g.dlam * g.sv[ny - 1] / g.acap : 0.0;
+
+  // per-column constants: 1 / P^2 (FP64)
+  C rP0sq[NI], rP1sq[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) {
+    const int i = t + c * B;
+    const int ii = i < nx ? i : 0;
+    rP0sq[c] = 1.0 / ((C)sP0[ii] * (C)sP0[ii]);
+    rP1sq[c] = hasV ? 1.0 / ((C)sP1[ii] * (C)sP1[ii]) : 0.0;
+  }
+  __syncthreads();
+
+  // divergence of rows j and j+1 at level k from the owned column's values and leap gathers
+  auto div0 = [&](int k, int c, T Uic, T Uid, T Vj, T Vm) -> C {
+    if (isPole) return capD0 * sCap[k];
+    const int i = t + c * B;
+    const int ii = i < nx ? i : 0;
+    const int ic = wrp(ii + nj - 1, nx), id = wrp(ii - nj, nx);
+    const T PUc = T(0.5) * (sP0[ic] + sP0[wrp(ic + 1, nx)]);
+    const T PUd = T(0.5) * (sP0[id] + sP0[wrp(id + 1, nx)]);
+    return (C)((PUc * Uic - PUd * Uid) * rdx + (svj * (sPV0[ii] * Vj) - svm * (sPVm[ii] * Vm)) * rdyS);
+  };
+  auto div1 = [&](int k, int c, T U1ic, T U1id, T Vj, T V1) -> C {
+    if (!hasV) return 0.0;
+    if (j1Pole) return capD1 * sCap[k];
+    const int i = t + c * B;
+    const int ii = i < nx ? i : 0;
+    const int ic1 = wrp(ii + nj1 - 1, nx), id1 = wrp(ii - nj1, nx);
+    const T PU1c = T(0.5) * (sP1[ic1] + sP1[wrp(ic1 + 1, nx)]);
+    const T PU1d = T(0.5) * (sP1[id1] + sP1[wrp(id1 + 1, nx)]);
+    return (C)((PU1c * U1ic - PU1d * U1id) * rdx1 + (sv1 * (sPV1[ii] * V1) - svj * (sPV0[ii] * Vj)) * rdyS1);
+  };
+
+  // ---- pass A: column totals Pi of rows j and j+1
+  C Pi0[NI], Pi1[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) { Pi0[c] = 0; Pi1[c] = 0; }
+  {
+    constexpr int KU = 3;
+    for (int k0 = 0; k0 < nz; k0 += KU) {
+      T a0[KU][NI], a1[KU][NI], a2[KU][NI], a3[KU][NI], a4[KU][NI], a5[KU][NI], a6[KU][NI];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + u < nz ? k0 + u : nz - 1;
+        const size_t lo = (size_t)j * row3 + (size_t)k * nx;
+        const T* gU0 = uni(A.inU + lo);
+        const T* gU1 = uni(A.inU + lo + row3);
+        const T* gV0 = uni(A.inV + lo);
+        const T* gVm = uni(A.inV + (lo - (j >= 1 ? row3 : 0)));
+        const T* gV1 = uni(A.inV + lo + row3);
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+          const int i = t + c * B;
+          const int ii = i < nx ? i : 0;
+          a0[u][c] = isPole ? T(0) : gU0[(unsigned)wrp(ii + nj - 1, nx)];
+          a1[u][c] = isPole ? T(0) : gU0[(unsigned)wrp(ii - nj, nx)];
+          a2[u][c] = j1Int ? gU1[(unsigned)wrp(ii + nj1 - 1, nx)] : T(0);
+          a3[u][c] = j1Int ? gU1[(unsigned)wrp(ii - nj1, nx)] : T(0);
+          a4[u][c] = hasV ? gV0[(unsigned)ii] : T(0);
+          a5[u][c] = (j >= 1) ? gVm[(unsigned)ii] : T(0);
+          a6[u][c] = (j + 1 < ny) ? gV1[(unsigned)ii] : T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + u;
+        if (k < nz) {
+          const C dsg = g.dsig[k];
+#pragma unroll
+          for (int c = 0; c < NI; ++c) {
+            Pi0[c] += div0(k, c, a0[u][c], a1[u][c], a4[u][c], a5[u][c]) * dsg;
+            Pi1[c] += div1(k, c, a2[u][c], a3[u][c], a4[u][c], a6[u][c]) * dsg;
+          }
+        }
+      }
+    }
+  }
+
+  // ---- pass B, pipelined over levels
+  // next level (fetched one level ahead)
+  T nF[NI], nU[NI], nV[NI], nVm[NI], nU1[NI], nV1[NI], nFn[NI], nFs[NI], nUs[NI];
+  T nUic[NI], nUid[NI], nU1ic[NI], nU1id[NI];
+  // current level (the level above is read back from the other LDS buffer)
+  T cVm[NI], cU1[NI], cV1[NI], cFn[NI], cFs[NI], cUs[NI];
+  C S0[NI], S1[NI], sd0c[NI], sd0n[NI], sd1c[NI], sd1n[NI];
+#pragma unroll
+  for (int c = 0; c < NI; ++c) S0[c] = S1[c] = sd0c[c] = sd0n[c] = sd1c[c] = sd1n[c] = 0;
+
+  auto fetch = [&](int k) {
+    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
+    const T* gF0 = uni(A.inF + lo);
+    const T* gU0 = uni(A.inU + lo);
+    const T* gV0 = uni(A.inV + lo);
+    const T* gVm = uni(A.inV + (lo - (j >= 1 ? row3 : 0)));
+    const T* gU1 = uni(A.inU + lo + row3);
+    const T* gV1 = uni(A.inV + lo + row3);
+    const T* gF1 = uni(A.inF + lo + row3);
+    const T* gFs = uni(A.inF + (lo - (j >= 1 ? row3 : 0)));
+    const T* gUs = uni(A.inU + (lo - (j >= 1 ? row3 : 0)));
+    const T Fp0 = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
+    const T Fn_p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
+    const T Fs_p = (j - 1 == 0) ? (T)A.pin[k] : T(0);
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      const unsigned ii = i < nx ? (unsigned)i : 0u;
+      nF[c] = isPole ? Fp0 : gF0[ii];
+      nU[c] = isPole ? T(0) : gU0[ii];
+      nV[c] = hasV ? gV0[ii] : T(0);
+      nVm[c] = (j >= 1) ? gVm[ii] : T(0);
+      nU1[c] = j1Int ? gU1[ii] : T(0);
+      nV1[c] = (j + 1 < ny) ? gV1[ii] : T(0);
+      nFn[c] = (!isPole && j + 1 < ny) ? gF1[ii] : Fn_p;
+      nFs[c] = (!isPole && j - 1 >= 1) ? gFs[ii] : Fs_p;
+      nUs[c] = (!isPole && j - 1 >= 1) ? gUs[ii] : T(0);
+      nUic[c] = isPole ? T(0) : gU0[(unsigned)wrp((int)ii + nj - 1, nx)];
+      nUid[c] = isPole ? T(0) : gU0[(unsigned)wrp((int)ii - nj, nx)];
+      nU1ic[c] = j1Int ? gU1[(unsigned)wrp((int)ii + nj1 - 1, nx)] : T(0);
+      nU1id[c] = j1Int ? gU1[(unsigned)wrp((int)ii - nj1, nx)] : T(0);
+    }
+  };
+  // level k into LDS buffer k & 1; sigma-dot of its lower half level into slot (k + 1) % 3;
+  // then the window moves down one level
+  auto commit = [&](int k) {
+    T* buf = lev0 + (size_t)(k & 1) * bufStride;
+    T* bF = buf;            T* bU = buf + nx;       T* bu0 = buf + 2 * nx;  T* bV = buf + 3 * nx;
+    T* buv = buf + 4 * nx;  T* bvt0 = buf + 5 * nx; T* bvtm = buf + 6 * nx;
+    T* sdn = sSd + (size_t)((k + 1) % 3) * nx;
+    const C dsg = g.dsig[k];
+    const C sh = (k + 1 < nz) ? g.sigh[k + 1] : 0.0;
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      const C D0 = div0(k, c, nUic[c], nUid[c], nV[c], nVm[c]);
+      const C D1 = div1(k, c, nU1ic[c], nU1id[c], nV[c], nV1[c]);
+      S0[c] += D0 * dsg;
+      S1[c] += D1 * dsg;
+      sd0c[c] = sd0n[c];
+      sd1c[c] = sd1n[c];
+      sd0n[c] = 0;
+      sd1n[c] = 0;
+      if (k + 1 < nz) {
+        sd0n[c] = (sh * Pi0[c] - S0[c]) * rP0sq[c];
+        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) * rP1sq[c];
+      }
+      if (i < nx) {
+        bF[i] = nF[c];
+        bU[i] = nU[c];
+        const T u0 = nU[c] * srPU0[i];
+        bu0[i] = u0;
+        if (hasV) {
+          bV[i] = nV[c];
+          bvt0[i] = nV[c] * srPV0[i] * svj;
+          buv[i] = T(0.5) * (u0 + nU1[c] * srPU1[i]);
+        }
+        if (j >= 1) bvtm[i] = nVm[c] * srPVm[i] * svm;
+        sdn[i] = (T)sd0n[c];
+      }
+      cVm[c] = nVm[c]; cU1[c] = nU1[c]; cV1[c] = nV1[c];
+      cFn[c] = nFn[c]; cFs[c] = nFs[c]; cUs[c] = nUs[c];
+    }
+  };
+
+  fetch(0);
+  commit(0);
+  __syncthreads();
+
+  const C cc = g.a * g.dlam / (2.0 * g.acap);
+  const T rdx2 = T(0.5) * rdx;
+  const T rdy2 = T(0.5) * rdyS;
+  const int Mv = hasV ? g.Mv[j] : 1, nv = (Mv + 1) / 2;
+  const T rdxv2 = hasV ? (T)(1.0 / (2.0 * (double)Mv * g.a * g.sv[j] * g.dlam)) : T(0);
+  const T rdyv2 = hasV ? (T)(1.0 / (2.0 * g.a * g.sv[j] * g.dth)) : T(0);
+#pragma unroll 1
+  for (int k = 0; k < nz; ++k) {
+    asm volatile("" : "+v"(t));
+    const bool more = k + 1 < nz;
+    if (more) fetch(k + 1);
+    const C dsg = g.dsig[k], r2d = 1.0 / (2.0 * dsg);
+    const T* buf = lev0 + (size_t)(k & 1) * bufStride;
+    const T* bF = buf;            const T* bU = buf + nx;       const T* bu0 = buf + 2 * nx;
+    const T* bV = buf + 3 * nx;   const T* buv = buf + 4 * nx;  const T* bvt0 = buf + 5 * nx;
+    const T* bvtm = buf + 6 * nx;
+    const T* obuf = lev0 + (size_t)((k + 1) & 1) * bufStride;   // level k-1 (own columns only)
+    const T* pFr = obuf;          const T* pUr = obuf + nx;     const T* pVr = obuf + 3 * nx;
+    const T* sdTop = sSd + (size_t)(k % 3) * nx;
+    const T* sdBot = sSd + (size_t)((k + 1) % 3) * nx;
+    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
+    T* goF = uni(A.oF + lo);
+    T* goU = uni(A.oU + lo);
+    T* goV = uni(A.oV + lo);
+    const T* gbF = uni(A.bF + lo);
+    const T* gbU = uni(A.bU + lo);
+    const T* gbV = uni(A.bV + lo);
+    T cbF[NI], cbU[NI], cbV[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      const unsigned ii = i < nx ? (unsigned)i : 0u;
+      cbF[c] = isPole ? T(0) : gbF[ii];
+      cbU[c] = isPole ? T(0) : gbU[ii];
+      cbV[c] = hasV ? gbV[ii] : T(0);
+    }
+
+    if (!isPole) {
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const int ic = wrp(i + nj - 1, nx), id = wrp(i - nj, nx);
+        const int pM = wrp(i + Mj, nx), mM = wrp(i - Mj, nx);
+        // Phi: zonal (x+1, x-1) -> (x+2N-1, x-2N+1) with u at the midpoints
+        const T L1 = (bu0[ic] * bF[pM] - bu0[id] * bF[mM]) * rdx2;
+        const T L2 = (bvt0[i] * cFn[c] - bvtm[i] * cFs[c]) * rdy2;
+        C L3 = 0;
+        if (more) L3 += sd0n[c] * (C)nF[c];
+        if (k > 0) L3 -= sd0c[c] * (C)pFr[i];
+        const C TF = -((C)L1 + (C)L2 + L3 * r2d);
+        goF[i] = (T)((C)cbF[c] + A.ch * TF);
+        // U: the same leap on U points, u averaged to the integer points i+n and i+1-n
+        const int pA = wrp(i + nj, nx), pB = wrp(i + 1 - nj, nx);
+        const T ubA = T(0.5) * (bu0[ic] + bu0[pA]);
+        const T ubB = T(0.5) * (bu0[id] + bu0[pB]);
+        const T U1v = (ubA * bU[pM] - ubB * bU[mM]) * rdx2;
+        const int ip = wrp(i + 1, nx);
+        const T vtn = T(0.5) * (bvt0[i] + bvt0[ip]);
+        const T vts = T(0.5) * (bvtm[i] + bvtm[ip]);
+        const T U2v = (vtn * cU1[c] - vts * cUs[c]) * rdy2;
+        C U3 = 0;
+        if (more) U3 += (C)(T(0.5) * (sdBot[i] + sdBot[ip])) * (C)nU[c];
+        if (k > 0) U3 -= (C)(T(0.5) * (sdTop[i] + sdTop[ip])) * (C)pUr[i];
+        const C TU = -((C)U1v + (C)U2v + U3 * r2d);
+        goU[i] = (T)((C)cbU[c] + A.ch * TU);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      const C sgn = (j == 0) ? 1.0 : -1.0;
+      const C L2 = sgn * cc * sCap[nz + k];
+      C L3 = 0;
+      if (more) L3 += sd0n[0] * (C)FA(j, k + 1, 0);
+      if (k > 0) L3 -= sd0c[0] * (C)FA(j, k - 1, 0);
+      const C TF = -(L2 + L3 * r2d);
+      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i < nx) {
+          goF[i] = val;
+          goU[i] = T(0);
+        }
+      }
+      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
+    }
+
+    if (hasV) {
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int i = t + c * B;
+        if (i >= nx) continue;
+        const T L1 = (buv[wrp(i + nv - 1, nx)] * bV[wrp(i + Mv, nx)] - buv[wrp(i - nv, nx)] * bV[wrp(i - Mv, nx)]) * rdxv2;
+        T L2 = T(0);
+        if (j + 1 < ny) L2 += T(0.5) * (bvt0[i] + cV1[c] * srPV1[i] * sv1) * cV1[c];
+        if (j > 0) L2 -= T(0.5) * (bvtm[i] + bvt0[i]) * cVm[c];
+        L2 = L2 * rdyv2;
+        C L3 = 0;
+        if (more) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)nV[c];
+        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)pVr[i];
+        const C TV = -((C)L1 + (C)L2 + L3 * r2d);
+        goV[i] = (T)((C)cbV[c] + A.ch * TV);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (more) commit(k + 1);
+    __syncthreads();
+  }
+
+  // p_s is not advected
+  if (!isPole) {
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) A.oP[(size_t)j * nx + i] = A.bP[(size_t)j * nx + i];
+    }
+  } else {
+    const T val = (T)A.pbase[pidx * (nz + 1) + nz];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const int i = t + c * B;
+      if (i < nx) A.oP[(size_t)j * nx + i] = val;
+    }
+    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
+  }
+}
+
 // One launch per stage; the process is a template parameter so that the
 // adaptation and advection kernels are separate symbols in a profile.  PROC: 0 adaptation,
-// 1 advection, 2 adaptation pipelined (FP32 rows that fit the LDS).
+// 1 advection, 2 and 3 their pipelined forms (FP32 rows that fit the LDS).
 template <typename T, int NI, int PROC>
 __global__ void __launch_bounds__(max_block(NI)) k_stage(StageArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int j = xcd_row(blockIdx.x, a.g.ny + 1);
   if constexpr (PROC == 0) adapt_row<T, NI>(a, j, smem);
   else if constexpr (PROC == 2) adapt_row_pipe<T, NI>(a, j, smem);
+  else if constexpr (PROC == 3) advect_row_pipe<T, NI>(a, j, smem);
   else advect_row<T, NI>(a, j, smem);
 }
 
 // Persistent batched stage: work item w = (member, row); block b takes items b, b+G, ...
-// PIPE: 1 when every member's adaptation takes the pipelined form, 0 when none does, 2 mixed.
+// PIPE: 1 when every member's stages take the pipelined forms, 0 when none does, 2 mixed.
 template <typename T, int NI, int PIPE>
 __global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T>* __restrict__ args,
                                                      const int2* __restrict__ items, int nitems) {
@@ -1049,7 +1446,12 @@ __global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T
       else if (adapt_pipe_ok(a.g.nx)) adapt_row_pipe<T, NI>(a, it.y, smem);
       else adapt_row<T, NI>(a, it.y, smem);
     }
-    else if (a.process == 1) advect_row<T, NI>(a, it.y, smem);
+    else if (a.process == 1) {
+      if constexpr (PIPE == 1) advect_row_pipe<T, NI>(a, it.y, smem);
+      else if constexpr (PIPE == 0) advect_row<T, NI>(a, it.y, smem);
+      else if (advect_pipe_ok(a.g.nx)) advect_row_pipe<T, NI>(a, it.y, smem);
+      else advect_row<T, NI>(a, it.y, smem);
+    }
     __syncthreads();
   }
 }
@@ -1175,6 +1577,10 @@ hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
     e = allow_lds<k_stage<T, NI, 0>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 0>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
+  } else if (sizeof(T) == 4 && advect_pipe_ok(a.g.nx)) {
+    e = allow_lds<k_stage<T, NI, 3>>(lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage<T, NI, 3>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
   } else {
     e = allow_lds<k_stage<T, NI, 1>>(lds);
     if (e != hipSuccess) return e;
@@ -1204,12 +1610,13 @@ hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_items, int 
 
 size_t stage_lds_bytes(int process, int nx, int elem) {
   if (process == 0 && elem == 4 && adapt_pipe_ok(nx)) return adapt_pipe_lds(nx);
+  if (process == 1 && elem == 4 && advect_pipe_ok(nx)) return advect_pipe_lds(nx);
   const size_t rows = 12;
   return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 2 * 128 * sizeof(double);
 }
 
 int columns_per_thread(int nx, int block) { return (nx + block - 1) / block; }
-int adapt_pipelined(int nx, int elem) { return elem == 4 && adapt_pipe_ok(nx) ? 1 : 0; }
+int stage_pipelined(int nx, int elem) { return elem == 4 && adapt_pipe_ok(nx) && advect_pipe_ok(nx) ? 1 : 0; }
 
 template <typename T>
 hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
