@@ -349,7 +349,7 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
   }
 }
 
-// Adaptation, FP32 storage, software-pipelined.  Every value the level loop reads at another
+// Adaptation, software-pipelined (rows whose LDS rows fit in 160 KB: nx <= 1497 in FP32, 748 in FP64).  Every value the level loop reads at another
 // column sits in LDS: 13 2D rows (P, the reciprocals of P and of its U-point averages, the
 // leaped d+l and d+q, the V-point averages of P and the meridional l and q differences) and,
 // double-buffered, the 7 per-level rows (phi', MU, Phi, U of rows j and j+1, V of rows j+-1/2).
@@ -357,10 +357,11 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
 // buffer afterwards, so one barrier per level suffices and the fetch latency hides behind the
 // arithmetic.  The column totals of pass A are summed over unrolled groups of levels.
 constexpr int kAdaptPipeRows2D = 13, kAdaptPipeRowsLev = 7;
-__host__ __device__ constexpr size_t adapt_pipe_lds(int nx) {
-  return (((size_t)(kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev) * nx * 4 + 15) & ~size_t(15)) + 2 * 128 * sizeof(double);
+__host__ __device__ constexpr size_t adapt_pipe_lds(int nx, int elem) {
+  return (((size_t)(kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev) * nx * elem + 15) & ~size_t(15)) +
+         2 * 128 * sizeof(double);
 }
-__host__ __device__ constexpr bool adapt_pipe_ok(int nx) { return adapt_pipe_lds(nx) <= 160 * 1024; }
+__host__ __device__ constexpr bool adapt_pipe_ok(int nx, int elem) { return adapt_pipe_lds(nx, elem) <= 160 * 1024; }
 
 template <typename T, int NI>
 __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char* smem) {
@@ -1021,7 +1022,7 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
   }
 }
 
-// Advection, FP32 storage, software-pipelined.  LDS: the P rows j and j+1, the reciprocal
+// Advection, software-pipelined (the same LDS limit as the adaptation).  LDS: the P rows j and j+1, the reciprocal
 // U-point averages of P on rows j and j+1, the V-point averages of P (and their reciprocals) on
 // V rows j-1/2, j+1/2, j+3/2, the per-level rows (Phi, U, u of row j, V, the u average on the V
 // row, v sin(theta) on V rows j+-1/2) double-buffered, and sigma-dot of row j in a ring of three
@@ -1029,11 +1030,11 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
 // base values) is fetched while level k is computed; the vertical neighbours come from a rolling
 // register window, so each level is read from memory once.  One barrier per level.
 constexpr int kAdvectPipeRows2D = 10, kAdvectPipeRowsLev = 7;
-__host__ __device__ constexpr size_t advect_pipe_lds(int nx) {
-  return (((size_t)(kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3) * nx * 4 + 15) & ~size_t(15)) +
+__host__ __device__ constexpr size_t advect_pipe_lds(int nx, int elem) {
+  return (((size_t)(kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3) * nx * elem + 15) & ~size_t(15)) +
          2 * 128 * sizeof(double);
 }
-__host__ __device__ constexpr bool advect_pipe_ok(int nx) { return advect_pipe_lds(nx) <= 160 * 1024; }
+__host__ __device__ constexpr bool advect_pipe_ok(int nx, int elem) { return advect_pipe_lds(nx, elem) <= 160 * 1024; }
 
 template <typename T, int NI>
 __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned char* smem) {
@@ -1419,7 +1420,7 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
 
 // One launch per stage; the process is a template parameter so that the
 // adaptation and advection kernels are separate symbols in a profile.  PROC: 0 adaptation,
-// 1 advection, 2 and 3 their pipelined forms (FP32 rows that fit the LDS).
+// 1 advection, 2 and 3 their pipelined forms (rows whose 27 LDS rows fit in 160 KB).
 template <typename T, int NI, int PROC>
 __global__ void __launch_bounds__(max_block(NI)) k_stage(StageArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1443,13 +1444,13 @@ __global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T
     if (a.process == 0) {
       if constexpr (PIPE == 1) adapt_row_pipe<T, NI>(a, it.y, smem);
       else if constexpr (PIPE == 0) adapt_row<T, NI>(a, it.y, smem);
-      else if (adapt_pipe_ok(a.g.nx)) adapt_row_pipe<T, NI>(a, it.y, smem);
+      else if (adapt_pipe_ok(a.g.nx, sizeof(T))) adapt_row_pipe<T, NI>(a, it.y, smem);
       else adapt_row<T, NI>(a, it.y, smem);
     }
     else if (a.process == 1) {
       if constexpr (PIPE == 1) advect_row_pipe<T, NI>(a, it.y, smem);
       else if constexpr (PIPE == 0) advect_row<T, NI>(a, it.y, smem);
-      else if (advect_pipe_ok(a.g.nx)) advect_row_pipe<T, NI>(a, it.y, smem);
+      else if (advect_pipe_ok(a.g.nx, sizeof(T))) advect_row_pipe<T, NI>(a, it.y, smem);
       else advect_row<T, NI>(a, it.y, smem);
     }
     __syncthreads();
@@ -1569,7 +1570,7 @@ template <typename T, int NI>
 hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
   const size_t lds = stage_lds_bytes(a.process, a.g.nx, sizeof(T));
   hipError_t e;
-  if (a.process == 0 && sizeof(T) == 4 && adapt_pipe_ok(a.g.nx)) {
+  if (a.process == 0 && adapt_pipe_ok(a.g.nx, sizeof(T))) {
     e = allow_lds<k_stage<T, NI, 2>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 2>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
@@ -1577,7 +1578,7 @@ hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
     e = allow_lds<k_stage<T, NI, 0>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 0>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
-  } else if (sizeof(T) == 4 && advect_pipe_ok(a.g.nx)) {
+  } else if (advect_pipe_ok(a.g.nx, sizeof(T))) {
     e = allow_lds<k_stage<T, NI, 3>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 3>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
@@ -1601,22 +1602,22 @@ hipError_t launch_batch_pipe(const StageArgs<T>* d_args, const int2* d_items, in
 template <typename T, int NI>
 hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
                            size_t lds, int pipe, hipStream_t s) {
-  if (sizeof(T) == 4 && pipe == 1) return launch_batch_pipe<T, NI, 1>(d_args, d_items, nitems, grid, block, lds, s);
-  if (sizeof(T) == 4 && pipe == 2) return launch_batch_pipe<T, NI, 2>(d_args, d_items, nitems, grid, block, lds, s);
+  if (pipe == 1) return launch_batch_pipe<T, NI, 1>(d_args, d_items, nitems, grid, block, lds, s);
+  if (pipe == 2) return launch_batch_pipe<T, NI, 2>(d_args, d_items, nitems, grid, block, lds, s);
   return launch_batch_pipe<T, NI, 0>(d_args, d_items, nitems, grid, block, lds, s);
 }
 
 }  // namespace
 
 size_t stage_lds_bytes(int process, int nx, int elem) {
-  if (process == 0 && elem == 4 && adapt_pipe_ok(nx)) return adapt_pipe_lds(nx);
-  if (process == 1 && elem == 4 && advect_pipe_ok(nx)) return advect_pipe_lds(nx);
+  if (process == 0 && adapt_pipe_ok(nx, elem)) return adapt_pipe_lds(nx, elem);
+  if (process == 1 && advect_pipe_ok(nx, elem)) return advect_pipe_lds(nx, elem);
   const size_t rows = 12;
   return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 2 * 128 * sizeof(double);
 }
 
 int columns_per_thread(int nx, int block) { return (nx + block - 1) / block; }
-int stage_pipelined(int nx, int elem) { return elem == 4 && adapt_pipe_ok(nx) && advect_pipe_ok(nx) ? 1 : 0; }
+int stage_pipelined(int nx, int elem) { return adapt_pipe_ok(nx, elem) && advect_pipe_ok(nx, elem) ? 1 : 0; }
 
 template <typename T>
 hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
