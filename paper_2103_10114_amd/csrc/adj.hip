@@ -45,8 +45,8 @@ struct Scr {
   T *RT, *PHI, *D, *WP;            // 3D scalar
   T *S, *SD;                       // half levels (ny+1)*(nz+1)*nx
   // adjoint intermediates (3D, index like the scalar/U/V fields)
-  T *AVGL, *ASK, *AD, *AFE, *AP3, *HH, *FU, *AUU, *AUD, *MV, *FV, *UV, *AVV, *AVD, *APU3, *APV3;
-  T *APHI, *ART, *AL3, *AQ3, *ADL3, *ADQ3;
+  T *AVGL, *AD, *AFE, *AP3, *HH, *FU, *AUU, *AUD, *MV, *FV, *UV, *AVV, *AVD, *APU3, *APV3;
+  T *APHI, *ART, *AL3, *AQ3, *ADL3, *ADQ3;   // adaptation: per-point inputs of the column sums
   T *ASD;                          // half levels
   double *AP2, *APU2, *APV2, *AL2, *AQ2, *ADL2, *ADQ2, *APSR;   // 2D FP64
   double* psum;                    // pole sums [8][2][nz+1]
@@ -327,11 +327,8 @@ __global__ void k_base_pole(Ctx<T> c) {
 // adaptation: first transposes (Phi and p_s tendencies, omega/p, pressure gradients, Coriolis)
 // ------------------------------------------------------------------------------------------------
 template <typename T>
-__global__ void k_a1(Ctx<T> c) {
+__device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C& aWPo, C& aSKo, C& aDo) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.z, k = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny;
   const T b = (T)g.b, kap = (T)g.kappa;
   const C ch = c.ch;
@@ -347,8 +344,9 @@ __global__ void k_a1(Ctx<T> c) {
     const C Sk = (C)c.s.S[ih<T>(g, j, k, i)];
     const C D = (C)c.s.D[id];
     c.s.AVGL[id] = (T)aWP;
-    c.s.ASK[id] = (T)(-aWP / (g.sig[k] * P2c));
-    c.s.AD[id] = (T)(-0.5 * g.dsig[k] * aWP / (g.sig[k] * P2c));
+    aWPo = aWP;
+    aSKo = -aWP / (g.sig[k] * P2c);
+    aDo = -0.5 * g.dsig[k] * aWP / (g.sig[k] * P2c);
     c.s.AFE[id] = (T)((C)kap * wp * gF);
     c.s.AP3[id] = (T)((C)b * wp * gF + 2.0 * (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P2c * (C)P) * aWP);
   }
@@ -391,29 +389,37 @@ __global__ void k_a1(Ctx<T> c) {
   }
 }
 
-// suffix transposes of the column prefix sums: aD_l += dsig_l (aPi + sum_{k>l} aS_k), aPi = -p0 ch aoP
+// First adaptation transposes (Phi and p_s tendencies, omega/p, pressure gradients, Coriolis) per
+// column, bottom to top, with the suffix transpose of the column prefix sums folded in:
+// aD_l = (direct part) + dsig_l (aPi + sum_{k>l} aS_k), aPi = -p0 ch aoP.
 template <typename T>
-__global__ void k_a2(Ctx<T> c) {
+__global__ void k_a12(Ctx<T> c) {
   const GeoDev& g = c.g;
   const int j = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const C aPi = -g.p0 * c.ch * (C)c.aoP[(size_t)j * g.nx + i];
   C acc = 0;
   for (int k = g.nz - 1; k >= 0; --k) {
-    const size_t id = i3<T>(g, j, k, i);
-    c.s.AD[id] = (T)((C)c.s.AD[id] + g.dsig[k] * (aPi + acc));
-    acc += (C)c.s.ASK[id];
+    // opaque column index: addresses are formed per level rather than held as per-array
+    // induction variables across the loop
+    asm volatile("" : "+v"(i));
+    C aWP, aSK, aD;
+    a1_point(c, j, k, i, aWP, aSK, aD);
+    c.s.AD[i3<T>(g, j, k, i)] = (T)(aD + g.dsig[k] * (aPi + acc));
+    acc += aSK;
   }
 }
 
 // gathers of the adaptation transposes at scalar, U and V points
+struct A3Out {
+  C aphi, art, al, aq;   // scalar point: adjoints of phi', R T', l, q
+  C au, aud, adl, adq;   // U point: adjoints of u and (directly) U, leaped d+l and d+q
+  C avv, avd;            // V point: adjoints of v and (directly) V
+};
 template <typename T>
-__global__ void k_a3(Ctx<T> c) {
+__device__ __forceinline__ void a3_point(const Ctx<T>& c, int j, int k, int i, A3Out& o) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.z, k = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const C RT0 = g.RT0;
   const C aDy = g.a * g.dth;
@@ -457,10 +463,10 @@ __global__ void k_a3(Ctx<T> c) {
       aL -= w + rty * m;
       aQ -= RT0 * m;
     }
-    c.s.APHI[id] = (T)aPHI;
-    c.s.ART[id] = (T)aRT;
-    c.s.AL3[id] = (T)aL;
-    c.s.AQ3[id] = (T)aQ;
+    o.aphi = aPHI;
+    o.art = aRT;
+    o.al = aL;
+    o.aq = aQ;
   }
   // U point
   if (j >= 1 && j < ny) {
@@ -474,20 +480,20 @@ __global__ void k_a3(Ctx<T> c) {
     const C u = (C)(c.U[id] / PUe(c, j, i));
     const C rtx = 0.5 * ((C)c.s.RT[id] + (C)c.s.RT[i3<T>(g, j, k, ip1)]);
     const C hh = (C)c.s.HH[id];
-    c.s.AUU[id] = (T)au;
-    c.s.AUD[id] = (T)aUd;
-    c.s.ADL3[id] = (T)(0.5 * u * ((C)c.s.AVGL[id] + (C)c.s.AVGL[i3<T>(g, j, k, ip1)]) + rtx * hh);
-    c.s.ADQ3[id] = (T)(RT0 * hh);
+    o.au = au;
+    o.aud = aUd;
+    o.adl = 0.5 * u * ((C)c.s.AVGL[id] + (C)c.s.AVGL[i3<T>(g, j, k, ip1)]) + rtx * hh;
+    o.adq = RT0 * hh;
   }
   // V point
   if (j < ny) {
     const int jv = j;
     const int im1 = wrp(i - 1, nx);
-    c.s.AVV[id] = (T)((Lr(jv + 1) - Lr(jv)) / aDy * cvg(jv));
+    o.avv = (Lr(jv + 1) - Lr(jv)) / aDy * cvg(jv);
     C aVd = 0;
     if (jv >= 1) aVd += (C)c.s.FU[i3<T>(g, jv, k, im1)] + (C)c.s.FU[i3<T>(g, jv, k, i)];
     if (jv + 1 <= ny - 1) aVd += (C)c.s.FU[i3<T>(g, jv + 1, k, im1)] + (C)c.s.FU[i3<T>(g, jv + 1, k, i)];
-    c.s.AVD[id] = (T)(-0.25 * aVd);
+    o.avd = -0.25 * aVd;
   }
 }
 
@@ -666,23 +672,23 @@ __global__ void k_l2(Ctx<T> c) {
 // ------------------------------------------------------------------------------------------------
 // common tail: divergence and velocity transposes into U and V, staggered-P accumulations
 // ------------------------------------------------------------------------------------------------
+// Divergence and velocity transposes into U and V at one point, given the adjoints of u, U (direct),
+// v, V (direct) there; returns the point's staggered-P adjoint contributions.
 template <typename T>
-__global__ void k_t1(Ctx<T> c, int accumulate) {
+__device__ __forceinline__ void t1_point(const Ctx<T>& c, int j, int k, int i, const A3Out& o, C& aPU3, C& aPV3) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.z, k = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const size_t id = i3<T>(g, j, k, i);
   const double* sD = c.s.psum + PS_AD * 2 * (nz + 1);
+  const size_t id = i3<T>(g, j, k, i);
+  aPU3 = 0;
+  aPV3 = 0;
   if (j >= 1 && j < ny) {
     const int M = g.M[j], n = (M + 1) / 2;
     const C dx = (C)(T)((double)M * g.a * g.s[j] * g.dlam);
     const C aMU = ((C)c.s.AD[i3<T>(g, j, k, wrp(i - n + 1, nx))] - (C)c.s.AD[i3<T>(g, j, k, wrp(i + n, nx))]) / dx;
     const C PU = (C)PUe(c, j, i), U = (C)c.U[id];
-    const C au = (C)c.s.AUU[id];
-    c.aiU[id] = (T)((C)c.aiU[id] + (C)c.s.AUD[id] + au / PU + PU * aMU);
-    c.s.APU3[id] = (T)((accumulate ? (C)c.s.APU3[id] : 0.0) - U / (PU * PU) * au + U * aMU);
+    c.aiU[id] = (T)((C)c.aiU[id] + o.aud + o.au / PU + PU * aMU);
+    aPU3 = -U / (PU * PU) * o.au + U * aMU;
   }
   if (j < ny) {
     const int jv = j;
@@ -692,40 +698,63 @@ __global__ void k_t1(Ctx<T> c, int accumulate) {
                                     : g.a * g.dlam / g.acap * sD[1 * (nz + 1) + k];
     const C aMV = (C)(T)g.sv[jv] * (tN - tS);
     const C PV = (C)PVe(c, jv, i), V = (C)c.V[id];
-    const C av = (C)c.s.AVV[id];
-    c.aiV[id] = (T)((C)c.aiV[id] + (C)c.s.AVD[id] + av / PV + PV * aMV);
-    c.s.APV3[id] = (T)((accumulate ? (C)c.s.APV3[id] : 0.0) - V / (PV * PV) * av + V * aMV);
+    c.aiV[id] = (T)((C)c.aiV[id] + o.avd + o.avv / PV + PV * aMV);
+    aPV3 = -V / (PV * PV) * o.avv + V * aMV;
   }
 }
 
-// column sums; for the adaptation also the hydrostatic transpose phi' -> R T' -> (Phi, P)
+// Adaptation, per point: the gathers of the first transposes, then the divergence and velocity
+// transposes into U and V; the per-point inputs of the column sums go to scratch.
 template <typename T>
-__global__ void k_t2(Ctx<T> c, int adapt) {
+__global__ void k_a3t1(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const size_t id = i3<T>(g, j, k, i);
+  A3Out o{};
+  a3_point(c, j, k, i, o);
+  C aPU3, aPV3;
+  t1_point(c, j, k, i, o, aPU3, aPV3);
+  c.s.APHI[id] = (T)o.aphi;
+  c.s.ART[id] = (T)o.art;
+  c.s.AL3[id] = (T)o.al;
+  c.s.AQ3[id] = (T)o.aq;
+  if (j >= 1 && j < g.ny) {
+    c.s.ADL3[id] = (T)o.adl;
+    c.s.ADQ3[id] = (T)o.adq;
+    c.s.APU3[id] = (T)((C)c.s.APU3[id] + aPU3);
+  }
+  if (j < g.ny) c.s.APV3[id] = (T)((C)c.s.APV3[id] + aPV3);
+}
+
+// Adaptation, per column, top to bottom: hydrostatic transpose phi' -> R T' -> (Phi, P) and the
+// column sums of the 2D adjoints.
+template <typename T>
+__global__ void k_a4(Ctx<T> c) {
   const GeoDev& g = c.g;
   const int j = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const T b = (T)g.b;
   const C P = (C)P2(c, j, i);
+  const C bP = (C)b / P, bP2 = (C)b / (P * P);
   const bool intr = (j >= 1 && j < ny);
-  C aP = adapt ? 0.0 : c.s.AP2[(size_t)j * nx + i];
-  C aPU = 0, aPV = 0, aL = 0, aQ = 0, aDL = 0, aDQ = 0;
-  C pre = 0;
+  C aP = 0, aPU = 0, aPV = 0, aL = 0, aQ = 0, aDL = 0, aDQ = 0, pre = 0;
   for (int k = 0; k < nz; ++k) {
+    asm volatile("" : "+v"(i));
     const size_t id = i3<T>(g, j, k, i);
-    C afe = (C)c.s.AFE[id];
-    if (adapt) {
-      const C aphi = (C)c.s.APHI[id];
-      const C art = (C)c.s.ART[id] + g.cl[k] * pre + g.cpk[k] * aphi;
-      pre += aphi;
-      afe += (C)b / P * art;
-      aP += (C)c.s.AP3[id] - (C)b * (C)Fe(c, j, k, i) / (P * P) * art;
-      aL += (C)c.s.AL3[id];
-      aQ += (C)c.s.AQ3[id];
-      if (intr) { aDL += (C)c.s.ADL3[id]; aDQ += (C)c.s.ADQ3[id]; }
-    }
+    const C aphi = (C)c.s.APHI[id];
+    const C art = (C)c.s.ART[id] + g.cl[k] * pre + g.cpk[k] * aphi;
+    pre += aphi;
+    const C afe = (C)c.s.AFE[id] + bP * art;
+    aP += (C)c.s.AP3[id] - bP2 * (C)Fe(c, j, k, i) * art;
+    aL += (C)c.s.AL3[id];
+    aQ += (C)c.s.AQ3[id];
     if (intr) {
+      aDL += (C)c.s.ADL3[id];
+      aDQ += (C)c.s.ADQ3[id];
       aPU += (C)c.s.APU3[id];
       c.aiF[id] = (T)((C)c.aiF[id] + afe);
     } else {
@@ -741,6 +770,71 @@ __global__ void k_t2(Ctx<T> c, int adapt) {
   c.s.AQ2[i2] = aQ;
   c.s.ADL2[i2] = aDL;
   c.s.ADQ2[i2] = aDQ;
+}
+
+// Advection, per column, top to bottom: the divergence and velocity transposes into U and V (the
+// adjoints of u, U, v, V at each point come from the advection transposes) and the column sums of
+// the staggered-P adjoints.
+template <typename T>
+__global__ void k_l3(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const double* sD = c.s.psum + PS_AD * 2 * (nz + 1);
+  const bool intr = (j >= 1 && j < ny);
+  const size_t i2 = (size_t)j * nx + i;
+  // U-point constants
+  int n = 1;
+  C dxU = 1, PU = 1;
+  if (intr) {
+    const int M = g.M[j];
+    n = (M + 1) / 2;
+    dxU = (C)(T)((double)M * g.a * g.s[j] * g.dlam);
+    PU = (C)PUe(c, j, i);
+  }
+  // V-point constants
+  C PV = 1, dyN = 1, dyS = 1, capD = g.a * g.dlam / g.acap;
+  if (j < ny) {
+    PV = (C)PVe(c, j, i);
+    if (j >= 1) dyN = (C)(T)(g.a * g.s[j] * g.dth);
+    if (j + 1 <= ny - 1) dyS = (C)(T)(g.a * g.s[j + 1] * g.dth);
+  }
+  C aP = c.s.AP2[i2];
+  C aPU = 0, aPV = 0;
+  for (int k = 0; k < nz; ++k) {
+    asm volatile("" : "+v"(i));
+    const size_t id = i3<T>(g, j, k, i);
+    A3Out o{};
+    if (intr) { o.au = (C)c.s.AUU[id]; o.aud = (C)c.s.AUD[id]; }
+    if (j < ny) { o.avv = (C)c.s.AVV[id]; o.avd = (C)c.s.AVD[id]; }
+    if (intr) {
+      const C aMU = ((C)c.s.AD[i3<T>(g, j, k, wrp(i - n + 1, nx))] - (C)c.s.AD[i3<T>(g, j, k, wrp(i + n, nx))]) / dxU;
+      const C U = (C)c.U[id];
+      c.aiU[id] = (T)((C)c.aiU[id] + o.aud + o.au / PU + PU * aMU);
+      aPU += -U / (PU * PU) * o.au + U * aMU;
+    }
+    if (j < ny) {
+      const int jv = j;
+      const C tN = (jv >= 1) ? (C)c.s.AD[i3<T>(g, jv, k, i)] / dyN : capD * sD[0 * (nz + 1) + k];
+      const C tS = (jv + 1 <= ny - 1) ? (C)c.s.AD[i3<T>(g, jv + 1, k, i)] / dyS : capD * sD[1 * (nz + 1) + k];
+      const C aMV = (C)(T)g.sv[jv] * (tN - tS);
+      const C V = (C)c.V[id];
+      c.aiV[id] = (T)((C)c.aiV[id] + o.avd + o.avv / PV + PV * aMV);
+      aPV += -V / (PV * PV) * o.avv + V * aMV;
+    }
+    const C afe = (C)c.s.AFE[id];
+    if (intr) c.aiF[id] = (T)((C)c.aiF[id] + afe);
+    else c.s.AFE[id] = (T)afe;     // pole copies: aggregated later
+  }
+  c.s.AP2[i2] = aP;
+  c.s.APU2[i2] = aPU;
+  c.s.APV2[i2] = aPV;
+  c.s.AL2[i2] = 0;
+  c.s.AQ2[i2] = 0;
+  c.s.ADL2[i2] = 0;
+  c.s.ADQ2[i2] = 0;
 }
 
 // 2D: staggered P, the leaped d+ transposes for l and q, then p_s
@@ -796,6 +890,28 @@ __global__ void k_t4(Ctx<T> c) {
   }
 }
 
+// The base transpose of a stage applied in place: pole rows of Phi and p_s become the spread of
+// their row mean (FP64 sum), pole rows of U become 0; interior rows and V are left as they are.
+template <typename T>
+__global__ void __launch_bounds__(256) k_base_inplace(GeoDev g, T* U, T* F, T* P) {
+  const int p = blockIdx.y, k = blockIdx.x;   // k in 0..nz (nz = p_s)
+  const int j = p == 0 ? 0 : g.ny;
+  __shared__ double red[4];
+  T* row = (k < g.nz) ? F + ((size_t)j * g.nz + k) * g.nx : P + (size_t)j * g.nx;
+  C s = 0;
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) s += (C)row[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  C tot = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
+  const T mean = (T)(tot / g.nx);
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+    row[i] = mean;
+    if (k < g.nz) U[((size_t)j * g.nz + k) * g.nx + i] = T(0);
+  }
+}
+
 template <typename T>
 hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s) {
   const GeoDev& g = c.g;
@@ -807,10 +923,10 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s) {
   hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_f1p<T>), dim3(2), dim3(256), 0, s, c);
-  hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
+  if (c.abU) hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
                      c.s.psum + PS_AOF * 2 * (nz + 1));
-  hipLaunchKernelGGL((k_base_pole<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
+  if (c.abU) hipLaunchKernelGGL((k_base_pole<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
   // (process-specific part is launched by the caller between these two groups)
   return hipGetLastError();
 }
@@ -822,15 +938,13 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
-  hipLaunchKernelGGL((k_a1<T>), g3, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_a2<T>), g2, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_a12<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
                      c.s.psum + PS_AD * 2 * (nz + 1));
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL, (const T*)nullptr,
                      c.s.psum + PS_AVGL * 2 * (nz + 1));
-  hipLaunchKernelGGL((k_a3<T>), g3, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_t1<T>), g3, dim3(tb), 0, s, c, 1);
-  hipLaunchKernelGGL((k_t2<T>), g2, dim3(tb), 0, s, c, 1);
+  hipLaunchKernelGGL((k_a3t1<T>), g3, dim3(tb), 0, s, c);
+  hipLaunchKernelGGL((k_a4<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
   return hipGetLastError();
@@ -847,8 +961,7 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
   hipLaunchKernelGGL((k_l2<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
                      c.s.psum + PS_AD * 2 * (nz + 1));
-  hipLaunchKernelGGL((k_t1<T>), g3, dim3(tb), 0, s, c, 0);
-  hipLaunchKernelGGL((k_t2<T>), g2, dim3(tb), 0, s, c, 0);
+  hipLaunchKernelGGL((k_l3<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
   return hipGetLastError();
@@ -879,7 +992,7 @@ namespace {
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
-constexpr int kN3 = 26;   // 3D scalar-size scratch fields (4 forward + 22 adjoint)
+constexpr int kN3 = 25;   // 3D scalar-size scratch fields (4 forward + 21 adjoint)
 constexpr int kNH = 3;    // half-level fields
 constexpr int kN2T = 5;   // 2D T fields
 constexpr int kN2D = 8;   // 2D FP64 fields
@@ -899,7 +1012,7 @@ Layout layout(const HandleView& v) {
   const int nst = 3 * (v.msub + 1);
   size_t o = 0;
   L.traj_off = o; o += (size_t)nst * L.state;
-  L.lam_off = o; o += 3 * L.state;
+  L.lam_off = o; o += 2 * L.state;
   L.f3_off = o; o += kN3 * a256(L.n3 * v.elem);
   L.fh_off = o; o += kNH * a256(L.nh * v.elem);
   L.f2t_off = o; o += kN2T * a256(L.n2 * v.elem);
@@ -918,10 +1031,10 @@ Scr<T> scratch_of(const HandleView& v) {
   T* f3[kN3];
   for (int q = 0; q < kN3; ++q) f3[q] = reinterpret_cast<T*>(base + L.f3_off + q * a256(L.n3 * v.elem));
   s.RT = f3[0]; s.PHI = f3[1]; s.D = f3[2]; s.WP = f3[3];
-  s.AVGL = f3[4]; s.ASK = f3[5]; s.AD = f3[6]; s.AFE = f3[7]; s.AP3 = f3[8]; s.HH = f3[9]; s.FU = f3[10];
-  s.AUU = f3[11]; s.AUD = f3[12]; s.MV = f3[13]; s.FV = f3[14]; s.UV = f3[15]; s.AVV = f3[16]; s.AVD = f3[17];
-  s.APU3 = f3[18]; s.APV3 = f3[19]; s.APHI = f3[20]; s.ART = f3[21]; s.AL3 = f3[22]; s.AQ3 = f3[23];
-  s.ADL3 = f3[24]; s.ADQ3 = f3[25];
+  s.AVGL = f3[4]; s.AD = f3[5]; s.AFE = f3[6]; s.AP3 = f3[7]; s.HH = f3[8]; s.FU = f3[9];
+  s.AUU = f3[10]; s.AUD = f3[11]; s.MV = f3[12]; s.FV = f3[13]; s.UV = f3[14]; s.AVV = f3[15]; s.AVD = f3[16];
+  s.APU3 = f3[17]; s.APV3 = f3[18];
+  s.APHI = f3[19]; s.ART = f3[20]; s.AL3 = f3[21]; s.AQ3 = f3[22]; s.ADL3 = f3[23]; s.ADQ3 = f3[24];
   T* fh[kNH];
   for (int q = 0; q < kNH; ++q) fh[q] = reinterpret_cast<T*>(base + L.fh_off + q * a256(L.nh * v.elem));
   s.S = fh[0]; s.SD = fh[1]; s.ASD = fh[2];
@@ -996,9 +1109,8 @@ int step_adjoint_impl(const HandleView& v, St4<const T> y0, St4<T> lam, hipStrea
   char* base = static_cast<char*>(v.adj);
   const int nrk = v.msub + 1;
   auto traj = [&](int q) { return state_at<T>(v, base + L.traj_off + (size_t)q * L.state); };
-  St4<T> lacc = state_at<T>(v, base + L.lam_off);
-  St4<T> l1 = state_at<T>(v, base + L.lam_off + L.state);
-  St4<T> l2 = state_at<T>(v, base + L.lam_off + 2 * L.state);
+  St4<T> l1 = state_at<T>(v, base + L.lam_off);
+  St4<T> l2 = state_at<T>(v, base + L.lam_off + L.state);
   double* pole = reinterpret_cast<double*>(base + L.pole_off);   // [4][2][nz+1]
   const size_t ps = 2 * (v.g.nz + 1);
   hipError_t e;
@@ -1032,19 +1144,24 @@ int step_adjoint_impl(const HandleView& v, St4<const T> y0, St4<T> lam, hipStrea
     }
     if (e != hipSuccess) return DYCORE_EHIP;
   }
-  // reverse sweep
+  // reverse sweep.  lam accumulates the adjoint of the RK step's input: every stage adds the base
+  // transpose of its output adjoint to it; the last stage's share is lam itself with the base
+  // transpose applied in place once that stage has read it.
   double* pin = pole + 3 * ps;
+  const St4<T> none{nullptr, nullptr, nullptr, nullptr};
   for (int rk = nrk - 1; rk >= 0; --rk) {
     const int proc = rk < v.msub ? 0 : 1;
     const double h = proc == 0 ? v.dt / v.msub : v.dt;
     St4<T> y = traj(3 * rk), y1 = traj(3 * rk + 1), y2 = traj(3 * rk + 2);
-    e = zero_state<T>(v, lacc, s);
-    if (e == hipSuccess) e = zero_state<T>(v, l1, s);
+    e = zero_state<T>(v, l1, s);
     if (e == hipSuccess) e = zero_state<T>(v, l2, s);
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), lacc, l2, pin, s);
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lacc, l1, pin, s);
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lacc, lacc, pin, s);
-    if (e == hipSuccess) e = copy_state<T>(v, lam, cst(lacc), s);
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, pin, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((k_base_inplace<T>), dim3(v.g.nz + 1, 2), dim3(256), 0, s, v.g, lam.U, lam.F, lam.P);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lam, l1, pin, s);
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lam, lam, pin, s);
     if (e != hipSuccess) return DYCORE_EHIP;
   }
   return DYCORE_OK;

@@ -217,7 +217,6 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
       Fj[c] = Fp[c] = RTj[c] = RTj1[c] = phij[c] = phij1[c] = Uj[c] = Ujm[c] = U1[c] = U1m[c] = T(0);
       Vn[c] = Vnp[c] = Vs[c] = Vsp[c] = T(0);
       if (i < nx) {
-        const size_t idx = (size_t)j * row3 + lev + i;
         const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
         Fj[c] = pF0 ? pF0[i] : F0p;
         RTj[c] = b * Fj[c] * rP0[c];
@@ -870,7 +869,6 @@ __device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* sm
       const int i = t + c * B;
       Vj[c] = Vm[c] = V1[c] = Fn[c] = Fs[c] = Un[c] = Us[c] = T(0);
       if (i < nx) {
-        const size_t idx = (size_t)j * row3 + lev + i;
         const T Fj = FA(j, k, i);
         const T Uj = pU0 ? pU0[i] : T(0);
         sF[i] = Fj;
