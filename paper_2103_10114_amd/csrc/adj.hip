@@ -47,6 +47,7 @@ struct Scr {
   // adjoint intermediates (3D, index like the scalar/U/V fields)
   T *AVGL, *AD, *AFE, *AP3, *HH, *FU, *AUU, *AUD, *MV, *FV, *UV, *AVV, *AVD, *APU3, *APV3;
   T *APHI, *ART, *AL3, *AQ3, *ADL3, *ADQ3;   // adaptation: per-point inputs of the column sums
+  T *UA, *VT;                      // advection: u at U points, v sin(theta) at V points
   T *ASD;                          // half levels
   double *AP2, *APU2, *APV2, *AL2, *AQ2, *ADL2, *ADQ2, *APSR;   // 2D FP64
   double* psum;                    // pole sums [8][2][nz+1]
@@ -65,6 +66,7 @@ struct Ctx {
   const double* pin;               // pole values of the linearisation state
   double ch;
   Scr<T> s;
+  GeoFac f;                        // difference factors of the forward stages
 };
 
 template <typename T>
@@ -500,6 +502,22 @@ __device__ __forceinline__ void a3_point(const Ctx<T>& c, int j, int k, int i, A
 // ------------------------------------------------------------------------------------------------
 // advection transposes
 // ------------------------------------------------------------------------------------------------
+// The advecting velocities of the linearisation state as the advection stage forms them:
+// u = U * (2 / (P_i + P_{i+1})) on interior U rows (0 on the pole rows), v sin(theta) =
+// V * (1 / P^V) * sin(theta) on V rows.
+template <typename T>
+__global__ void k_uv(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const size_t id = i3<T>(g, j, k, i);
+  T u = T(0);
+  if (j >= 1 && j < g.ny) u = c.U[id] * (T(2) / (P2(c, j, i) + P2(c, j, wrp(i + 1, g.nx))));
+  c.s.UA[id] = u;
+  if (j < g.ny) c.s.VT[id] = c.V[id] * (T(1) / (T(0.5) * (P2(c, j, i) + P2(c, j + 1, i)))) * (T)g.sv[j];
+}
+
 template <typename T>
 __global__ void k_l1(Ctx<T> c) {
   const GeoDev& g = c.g;
@@ -516,17 +534,20 @@ __global__ void k_l1(Ctx<T> c) {
   auto amV = [&](int jv, int kk, int ii) -> C { return -ch * (C)c.aoV[i3<T>(g, jv, kk, ii)]; };
   auto interior = [&](int jr) { return jr >= 1 && jr <= ny - 1; };
   auto sd = [&](int jr, int h, int ii) -> C { return (C)c.s.SD[ih<T>(g, jr, h, ii)]; };
-  auto dxr = [&](int jr) -> C { return (C)(T)(2.0 * (double)g.M[jr] * g.a * g.s[jr] * g.dlam); };
-  auto dyr = [&](int jr) -> C { return (C)(T)(2.0 * g.a * g.s[jr] * g.dth); };
-  auto dxv = [&](int jv) -> C { return (C)(T)(2.0 * (double)g.Mv[jv] * g.a * g.sv[jv] * g.dlam); };
-  auto dyv = [&](int jv) -> C { return (C)(T)(2.0 * g.a * g.sv[jv] * g.dth); };
+  // the forward's difference factors (rounded to the field precision)
+  auto rdx2 = [&](int jr) -> C { return 0.5 * c.f.rdx[jr]; };
+  auto rdy2 = [&](int jr) -> C { return 0.5 * c.f.rdy[jr]; };
+  auto rdxv2 = [&](int jv) -> C { return c.f.rdxv2[jv]; };
+  auto rdyv2 = [&](int jv) -> C { return c.f.rdyv2[jv]; };
+  auto uA = [&](int jr, int q) -> C { return (jr >= 1 && jr < ny) ? (C)c.s.UA[i3<T>(g, jr, k, q)] : 0.0; };
+  auto vA = [&](int jv, int kk, int ii) -> C { return (C)c.s.VT[i3<T>(g, jv, kk, ii)]; };
   auto ub = [&](int jr, int q) -> C {   // u averaged to integer point q of U row jr
-    return 0.5 * ((C)ue(c, jr, k, wrp(q - 1, nx)) + (C)ue(c, jr, k, q));
+    return 0.5 * (uA(jr, wrp(q - 1, nx)) + uA(jr, q));
   };
-  auto uv = [&](int jv, int q) -> C { return 0.5 * ((C)ue(c, jv, k, q) + (C)ue(c, jv + 1, k, q)); };
+  auto uv = [&](int jv, int q) -> C { return 0.5 * (uA(jv, q) + uA(jv + 1, q)); };
   auto vts = [&](int js, int kk, int ii) -> C {   // v sin(theta) on scalar row js
     if (js <= 0 || js >= ny) return 0.0;
-    return 0.5 * ((C)vte(c, js - 1, kk, ii) + (C)vte(c, js, kk, ii));
+    return 0.5 * (vA(js - 1, kk, ii) + vA(js, kk, ii));
   };
   const size_t id = i3<T>(g, j, k, i);
 
@@ -536,14 +557,14 @@ __global__ void k_l1(Ctx<T> c) {
     if (interior(j)) {
       const int M = g.M[j], n = (M + 1) / 2;
       const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
-      a += (amF(j, k, pm) * (C)ue(c, j, k, wrp(pm + n - 1, nx)) - amF(j, k, pp) * (C)ue(c, j, k, wrp(pp - n, nx))) / dxr(j);
+      a += (amF(j, k, pm) * uA(j, wrp(pm + n - 1, nx)) - amF(j, k, pp) * uA(j, wrp(pp - n, nx))) * rdx2(j);
     }
-    if (interior(j - 1)) a += amF(j - 1, k, i) * (C)vte(c, j - 1, k, i) / dyr(j - 1);
-    if (interior(j + 1)) a -= amF(j + 1, k, i) * (C)vte(c, j, k, i) / dyr(j + 1);
-    if (j == 1) a += cc * (C)vte(c, 0, k, i) * AN;
-    if (j == ny - 1) a -= cc * (C)vte(c, ny - 1, k, i) * AS;
-    if (k >= 1) a += amF(j, k - 1, i) * sd(j, k, i) / (2.0 * g.dsig[k - 1]);
-    if (k + 1 < nz) a -= amF(j, k + 1, i) * sd(j, k + 1, i) / (2.0 * g.dsig[k + 1]);
+    if (interior(j - 1)) a += amF(j - 1, k, i) * vA(j - 1, k, i) * rdy2(j - 1);
+    if (interior(j + 1)) a -= amF(j + 1, k, i) * vA(j, k, i) * rdy2(j + 1);
+    if (j == 1) a += cc * vA(0, k, i) * AN;
+    if (j == ny - 1) a -= cc * vA(ny - 1, k, i) * AS;
+    if (k >= 1) a += amF(j, k - 1, i) * sd(j, k, i) * c.f.r2d[k - 1];
+    if (k + 1 < nz) a -= amF(j, k + 1, i) * sd(j, k + 1, i) * c.f.r2d[k + 1];
     c.s.AFE[id] = (T)a;
   }
   // ---- U point
@@ -553,17 +574,17 @@ __global__ void k_l1(Ctx<T> c) {
     C au = 0;
     {
       const int qa = wrp(i - n + 1, nx), qb = wrp(i + n, nx);
-      au += (amF(j, k, qa) * (C)Fe(c, j, k, wrp(qa + M, nx)) - amF(j, k, qb) * (C)Fe(c, j, k, wrp(qb - M, nx))) / dxr(j);
+      au += (amF(j, k, qa) * (C)Fe(c, j, k, wrp(qa + M, nx)) - amF(j, k, qb) * (C)Fe(c, j, k, wrp(qb - M, nx))) * rdx2(j);
       auto aub = [&](int q) -> C {
         const int r1 = wrp(q - n, nx), r2 = wrp(q - 1 + n, nx);
-        return (amU(j, k, r1) * (C)Ue(c, j, k, wrp(r1 + M, nx)) - amU(j, k, r2) * (C)Ue(c, j, k, wrp(r2 - M, nx))) / dxr(j);
+        return (amU(j, k, r1) * (C)Ue(c, j, k, wrp(r1 + M, nx)) - amU(j, k, r2) * (C)Ue(c, j, k, wrp(r2 - M, nx))) * rdx2(j);
       };
       au += 0.5 * (aub(i) + aub(wrp(i + 1, nx)));
       for (int jv : {j - 1, j}) {
         const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
         const int r1 = wrp(i - nv + 1, nx), r2 = wrp(i + nv, nx);
         const C auv = (amV(jv, k, r1) * (C)Ve(c, jv, k, wrp(r1 + Mv, nx)) -
-                       amV(jv, k, r2) * (C)Ve(c, jv, k, wrp(r2 - Mv, nx))) / dxv(jv);
+                       amV(jv, k, r2) * (C)Ve(c, jv, k, wrp(r2 - Mv, nx))) * rdxv2(jv);
         au += 0.5 * auv;
       }
     }
@@ -572,18 +593,18 @@ __global__ void k_l1(Ctx<T> c) {
     C aU = 0;
     {
       const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
-      aU += (amU(j, k, pm) * ub(j, wrp(pm + n, nx)) - amU(j, k, pp) * ub(j, wrp(pp + 1 - n, nx))) / dxr(j);
+      aU += (amU(j, k, pm) * ub(j, wrp(pm + n, nx)) - amU(j, k, pp) * ub(j, wrp(pp + 1 - n, nx))) * rdx2(j);
       const int ip1 = wrp(i + 1, nx);
       if (interior(j - 1)) {
-        const C vtu = 0.5 * ((C)vte(c, j - 1, k, i) + (C)vte(c, j - 1, k, ip1));
-        aU += amU(j - 1, k, i) * vtu / dyr(j - 1);
+        const C vtu = 0.5 * (vA(j - 1, k, i) + vA(j - 1, k, ip1));
+        aU += amU(j - 1, k, i) * vtu * rdy2(j - 1);
       }
       if (interior(j + 1)) {
-        const C vtu = 0.5 * ((C)vte(c, j, k, i) + (C)vte(c, j, k, ip1));
-        aU -= amU(j + 1, k, i) * vtu / dyr(j + 1);
+        const C vtu = 0.5 * (vA(j, k, i) + vA(j, k, ip1));
+        aU -= amU(j + 1, k, i) * vtu * rdy2(j + 1);
       }
-      if (k >= 1) aU += amU(j, k - 1, i) * 0.5 * (sd(j, k, i) + sd(j, k, ip1)) / (2.0 * g.dsig[k - 1]);
-      if (k + 1 < nz) aU -= amU(j, k + 1, i) * 0.5 * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) / (2.0 * g.dsig[k + 1]);
+      if (k >= 1) aU += amU(j, k - 1, i) * 0.5 * (sd(j, k, i) + sd(j, k, ip1)) * c.f.r2d[k - 1];
+      if (k + 1 < nz) aU -= amU(j, k + 1, i) * 0.5 * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) * c.f.r2d[k + 1];
     }
     c.s.AUD[id] = (T)aU;
   }
@@ -594,30 +615,30 @@ __global__ void k_l1(Ctx<T> c) {
     C aV = 0;
     {
       const int pm = wrp(i - Mv, nx), pp = wrp(i + Mv, nx);
-      aV += (amV(jv, k, pm) * uv(jv, wrp(pm + nv - 1, nx)) - amV(jv, k, pp) * uv(jv, wrp(pp - nv, nx))) / dxv(jv);
-      if (jv >= 1) aV += amV(jv - 1, k, i) * vts(jv, k, i) / dyv(jv - 1);
-      if (jv + 1 <= ny - 1) aV -= amV(jv + 1, k, i) * vts(jv + 1, k, i) / dyv(jv + 1);
-      if (k >= 1) aV += amV(jv, k - 1, i) * 0.5 * (sd(jv, k, i) + sd(jv + 1, k, i)) / (2.0 * g.dsig[k - 1]);
+      aV += (amV(jv, k, pm) * uv(jv, wrp(pm + nv - 1, nx)) - amV(jv, k, pp) * uv(jv, wrp(pp - nv, nx))) * rdxv2(jv);
+      if (jv >= 1) aV += amV(jv - 1, k, i) * vts(jv, k, i) * rdyv2(jv - 1);
+      if (jv + 1 <= ny - 1) aV -= amV(jv + 1, k, i) * vts(jv + 1, k, i) * rdyv2(jv + 1);
+      if (k >= 1) aV += amV(jv, k - 1, i) * 0.5 * (sd(jv, k, i) + sd(jv + 1, k, i)) * c.f.r2d[k - 1];
       if (k + 1 < nz)
-        aV -= amV(jv, k + 1, i) * 0.5 * (sd(jv, k + 1, i) + sd(jv + 1, k + 1, i)) / (2.0 * g.dsig[k + 1]);
+        aV -= amV(jv, k + 1, i) * 0.5 * (sd(jv, k + 1, i) + sd(jv + 1, k + 1, i)) * c.f.r2d[k + 1];
     }
     c.s.AVD[id] = (T)aV;
     // adjoint of v sin(theta) on this V row
     C avt = 0;
-    if (interior(jv)) avt += amF(jv, k, i) * (C)Fe(c, jv + 1, k, i) / dyr(jv);
-    if (interior(jv + 1)) avt -= amF(jv + 1, k, i) * (C)Fe(c, jv, k, i) / dyr(jv + 1);
+    if (interior(jv)) avt += amF(jv, k, i) * (C)Fe(c, jv + 1, k, i) * rdy2(jv);
+    if (interior(jv + 1)) avt -= amF(jv + 1, k, i) * (C)Fe(c, jv, k, i) * rdy2(jv + 1);
     if (jv == 0) avt += cc * (C)Fe(c, 1, k, i) * AN;
     if (jv == ny - 1) avt -= cc * (C)Fe(c, ny - 1, k, i) * AS;
     auto avtu = [&](int p) -> C {
       C r = 0;
-      if (interior(jv)) r += amU(jv, k, p) * (C)Ue(c, jv + 1, k, p) / dyr(jv);
-      if (interior(jv + 1)) r -= amU(jv + 1, k, p) * (C)Ue(c, jv, k, p) / dyr(jv + 1);
+      if (interior(jv)) r += amU(jv, k, p) * (C)Ue(c, jv + 1, k, p) * rdy2(jv);
+      if (interior(jv + 1)) r -= amU(jv + 1, k, p) * (C)Ue(c, jv, k, p) * rdy2(jv + 1);
       return r;
     };
     avt += 0.5 * (avtu(i) + avtu(wrp(i - 1, nx)));
     auto avts = [&](int js) -> C {
       if (js <= 0 || js >= ny) return 0.0;
-      return amV(js - 1, k, i) * (C)Ve(c, js, k, i) / dyv(js - 1) - amV(js, k, i) * (C)Ve(c, js - 1, k, i) / dyv(js);
+      return amV(js - 1, k, i) * (C)Ve(c, js, k, i) * rdyv2(js - 1) - amV(js, k, i) * (C)Ve(c, js - 1, k, i) * rdyv2(js);
     };
     avt += 0.5 * (avts(jv) + avts(jv + 1));
     c.s.AVV[id] = (T)(avt * g.sv[jv]);
@@ -626,18 +647,18 @@ __global__ void k_l1(Ctx<T> c) {
   if (k >= 1) {
     const int h = k;
     C a = 0;
-    a += amF(j, h - 1, i) * (C)Fe(c, j, h, i) / (2.0 * g.dsig[h - 1]) -
-         amF(j, h, i) * (C)Fe(c, j, h - 1, i) / (2.0 * g.dsig[h]);
+    a += amF(j, h - 1, i) * (C)Fe(c, j, h, i) * c.f.r2d[h - 1] -
+         amF(j, h, i) * (C)Fe(c, j, h - 1, i) * c.f.r2d[h];
     if (interior(j)) {
       auto asdu = [&](int p) -> C {
-        return amU(j, h - 1, p) * (C)Ue(c, j, h, p) / (2.0 * g.dsig[h - 1]) -
-               amU(j, h, p) * (C)Ue(c, j, h - 1, p) / (2.0 * g.dsig[h]);
+        return amU(j, h - 1, p) * (C)Ue(c, j, h, p) * c.f.r2d[h - 1] -
+               amU(j, h, p) * (C)Ue(c, j, h - 1, p) * c.f.r2d[h];
       };
       a += 0.5 * (asdu(i) + asdu(wrp(i - 1, nx)));
     }
     auto asdv = [&](int jv) -> C {
-      return amV(jv, h - 1, i) * (C)Ve(c, jv, h, i) / (2.0 * g.dsig[h - 1]) -
-             amV(jv, h, i) * (C)Ve(c, jv, h - 1, i) / (2.0 * g.dsig[h]);
+      return amV(jv, h - 1, i) * (C)Ve(c, jv, h, i) * c.f.r2d[h - 1] -
+             amV(jv, h, i) * (C)Ve(c, jv, h - 1, i) * c.f.r2d[h];
     };
     if (j >= 1) a += 0.5 * asdv(j - 1);
     if (j <= ny - 1) a += 0.5 * asdv(j);
@@ -957,6 +978,7 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
+  hipLaunchKernelGGL((k_uv<T>), g3, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_l1<T>), g3, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_l2<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
@@ -984,6 +1006,7 @@ struct HandleView {
   double* pole;      // pole slots of the handle
   void* scratch;     // forward scratch y1, y2
   int block;
+  GeoFac fac;
 };
 HandleView view_of(const dycore_s* h);
 }  // namespace dyc
@@ -992,7 +1015,7 @@ namespace {
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
-constexpr int kN3 = 25;   // 3D scalar-size scratch fields (4 forward + 21 adjoint)
+constexpr int kN3 = 27;   // 3D scalar-size scratch fields (4 forward + 23 adjoint)
 constexpr int kNH = 3;    // half-level fields
 constexpr int kN2T = 5;   // 2D T fields
 constexpr int kN2D = 8;   // 2D FP64 fields
@@ -1035,6 +1058,7 @@ Scr<T> scratch_of(const HandleView& v) {
   s.AUU = f3[10]; s.AUD = f3[11]; s.MV = f3[12]; s.FV = f3[13]; s.UV = f3[14]; s.AVV = f3[15]; s.AVD = f3[16];
   s.APU3 = f3[17]; s.APV3 = f3[18];
   s.APHI = f3[19]; s.ART = f3[20]; s.AL3 = f3[21]; s.AQ3 = f3[22]; s.ADL3 = f3[23]; s.ADQ3 = f3[24];
+  s.UA = f3[25]; s.VT = f3[26];
   T* fh[kNH];
   for (int q = 0; q < kNH; ++q) fh[q] = reinterpret_cast<T*>(base + L.fh_off + q * a256(L.nh * v.elem));
   s.S = fh[0]; s.SD = fh[1]; s.ASD = fh[2];
@@ -1075,6 +1099,7 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.pin = pin;
   c.ch = ch;
   c.s = scratch_of<T>(v);
+  c.f = v.fac;
   hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
   if (e != hipSuccess) return e;
   e = run_stage_adjoint<T>(c, s);

@@ -30,6 +30,7 @@ struct dycore_s {
   double dt;
   int device;
   GeoDev g;
+  GeoFac fac;
   std::vector<int> M, Mv;
   size_t nU, nV, nF, nP;        // element counts of each field
   size_t elem;                  // 4 or 8
@@ -56,6 +57,7 @@ struct HandleView {
   double* pole;
   void* scratch;
   int block;
+  GeoFac fac;
 };
 HandleView view_of(const dycore_s* h);
 }  // namespace dyc
@@ -258,6 +260,7 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.pole = h->pole;
   v.scratch = h->scratch;
   v.block = h->block;
+  v.fac = h->fac;
   return v;
 }
 
@@ -343,6 +346,17 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
     m /= nx;
     for (int i = 0; i < nx; ++i) phis[(size_t)p * nx + i] = m;
   }
+  auto rnd = [&](double x) { return h->prec == DYCORE_FP32 ? (double)(float)x : x; };
+  std::vector<double> rdx(ny + 1, 0.0), rdy(ny + 1, 0.0), rdxv2(ny), rdyv2(ny), r2d(nz);
+  for (int j = 1; j < ny; ++j) {
+    rdx[j] = rnd(1.0 / ((double)h->M[j] * g.a * s[j] * g.dlam));
+    rdy[j] = rnd(1.0 / (g.a * s[j] * g.dth));
+  }
+  for (int j = 0; j < ny; ++j) {
+    rdxv2[j] = rnd(1.0 / (2.0 * (double)h->Mv[j] * g.a * sv[j] * g.dlam));
+    rdyv2[j] = rnd(1.0 / (2.0 * g.a * sv[j] * g.dth));
+  }
+  for (int k = 0; k < nz; ++k) r2d[k] = 1.0 / (2.0 * dsig[k]);
   if (cfg->n_adapt_substeps > 0) {
     h->msub = cfg->n_adapt_substeps;
   } else {
@@ -357,7 +371,9 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       {h->M.data(), h->M.size() * 4}, {sv.data(), sv.size() * 8},     {cotv.data(), cotv.size() * 8},
       {fv.data(), fv.size() * 8},     {h->Mv.data(), h->Mv.size() * 4}, {sigh.data(), sigh.size() * 8},
       {sig.data(), sig.size() * 8},   {dsig.data(), dsig.size() * 8}, {cl.data(), cl.size() * 8},
-      {cpk.data(), cpk.size() * 8},   {phis.data(), phis.size() * 8}};
+      {cpk.data(), cpk.size() * 8},   {phis.data(), phis.size() * 8}, {rdx.data(), rdx.size() * 8},
+      {rdy.data(), rdy.size() * 8},   {rdxv2.data(), rdxv2.size() * 8}, {rdyv2.data(), rdyv2.size() * 8},
+      {r2d.data(), r2d.size() * 8}};
   size_t gbytes = 0;
   for (auto& pr : parts) gbytes += align256(pr.second);
   if (hipMalloc(&h->geo, gbytes) != hipSuccess) { delete h; return DYCORE_ENOMEM; }
@@ -378,6 +394,9 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   g.fv = (const double*)(gb + off[6]); g.Mv = (const int*)(gb + off[7]); g.sigh = (const double*)(gb + off[8]);
   g.sig = (const double*)(gb + off[9]); g.dsig = (const double*)(gb + off[10]); g.cl = (const double*)(gb + off[11]);
   g.cpk = (const double*)(gb + off[12]); g.phis = (const double*)(gb + off[13]);
+  h->fac.rdx = (const double*)(gb + off[14]); h->fac.rdy = (const double*)(gb + off[15]);
+  h->fac.rdxv2 = (const double*)(gb + off[16]); h->fac.rdyv2 = (const double*)(gb + off[17]);
+  h->fac.r2d = (const double*)(gb + off[18]);
 
   h->nU = (size_t)(ny + 1) * nz * nx;
   h->nV = (size_t)ny * nz * nx;

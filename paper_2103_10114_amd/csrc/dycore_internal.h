@@ -27,6 +27,17 @@ struct GeoDev {
   const double* phis;   // (ny+1)*nx surface geopotential, pole rows = row mean
 };
 
+// Difference factors as the forward stages multiply by them, rounded to the field precision
+// (device tables; used by the adjoint kernels, kept out of GeoDev so that the forward kernels'
+// arguments stay small).
+struct GeoFac {
+  const double* rdx;    // scalar/U rows: 1 / (M a sin(theta) dlam), 0 at the poles
+  const double* rdy;    // scalar/U rows: 1 / (a sin(theta) dtheta), 0 at the poles
+  const double* rdxv2;  // V rows: 1 / (2 Mv a sin(theta) dlam)
+  const double* rdyv2;  // V rows: 1 / (2 a sin(theta) dtheta)
+  const double* r2d;    // levels: 1 / (2 dsigma)
+};
+
 // Pole slot layout: double[2][nz+1]; [p][k] = Phi pole value at level k, [p][nz] = p_s pole value,
 // p = 0 north, 1 south.
 
