@@ -9,9 +9,12 @@ adaptation + 3 advection stage launches) followed by one adjoint outer step
 (forward recompute + reverse sweep) in FP32 storage with FP64 accumulation.
 The metric is grid-point updates per second: nx * ny * nz per bench step.
 
-Printed: one JSON line with the value, the FP64 repeat and FP32/FP64 speedup, the
-HBM roofline of the dominant kernel (adaptation stage) measured live with HIP
-events on the launch stream, and the FP64 CPU oracle timed on the host.
+Printed: one JSON line with the value, forward-only and adjoint-only rates, a
+48-step adjoint window with checkpoints every 8 steps (time and checkpoint bytes),
+the FP64 repeat and FP32/FP64 speedup, the HBM roofline of the dominant kernel
+(adaptation stage) measured live with HIP events on the launch stream, the
+24-member mixed ensemble (one persistent launch per stage, hipGraph replay), and
+the FP64 CPU oracle timed on the host on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -112,28 +115,100 @@ def traffic_from_profiles(kernel_hash):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline():
-    """The FP64 oracle as it stands, on the host: one forward and one adjoint outer step with the
-    0.25-degree step structure (dt = 120 s, M = 4: 15 stages each way) on the 256 x 128 x 30 grid."""
-    import dataclasses
+def cpu_baseline(msub):
+    """The FP64 oracle as it stands, on the host, on a bounded sample of the 0.25-degree workload:
+    one adaptation stage and one advection stage, each forward and adjoint, on the full
+    1440x720x30 grid with all OpenMP threads.  The rate of a whole bench step (one forward outer
+    step + one adjoint outer step, whose forward recompute repeats the forward stages) is scaled
+    from these four timings: 2 (3M t_A + 3 t_L) + 3M t_A' + 3 t_L'.  Also: one forward outer step
+    of the 128x64x9 grid at 1 thread and at all threads."""
     import oracle
     from paper_2103_10114_amd import synth
-    cfg = dataclasses.replace(synth.CONFIGS["c2"], dt=120.0)
+    cfg = synth.CONFIGS["c4"]
     st = synth.make_state(cfg)
     o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
     lam = synth.random_like(st, 7)
-    t0 = time.perf_counter()
-    s1 = o.step(st, 1, cfg.dt, msub=4)
-    t1 = time.perf_counter()
-    o.adj_step(s1, lam, cfg.dt, msub=4)
-    t2 = time.perf_counter()
+    threads = oracle.num_threads()
+    h = cfg.dt / msub
+    t = {}
+    for which, ch in (("A", h), ("L", cfg.dt)):
+        t0 = time.perf_counter()
+        o.stage(st, st, ch, which)
+        t1 = time.perf_counter()
+        o.adj_stage(st, lam, ch, which)
+        t2 = time.perf_counter()
+        t[which] = (t1 - t0, t2 - t1)
+    del o, st, lam
+    fwd = 3 * msub * t["A"][0] + 3 * t["L"][0]
+    step = 2 * fwd + 3 * msub * t["A"][1] + 3 * t["L"][1]
     pts = cfg.nx * cfg.ny * cfg.nz
-    return {"value": pts / (t2 - t0), "unit": "grid-pt updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": (f"1 forward + 1 adjoint outer step, 15 stages each (dt 120 s, M 4), FP64, on the "
-                       f"256x128x30 grid ({pts} points); forward {t1 - t0:.2f} s with OpenMP over rows, "
-                       f"adjoint {t2 - t1:.2f} s serial"),
-            "forward_updates_per_s": pts / (t1 - t0)}
+    # thread scaling on a small grid
+    c1 = synth.CONFIGS["c1"]
+    s1 = synth.make_state(c1)
+    o1 = oracle.Oracle(c1.nx, c1.ny, c1.nz, phis=s1["phis"])
+    rates = {}
+    for n in (1, threads):
+        oracle.set_num_threads(n)
+        t0 = time.perf_counter()
+        o1.step(s1, 1, c1.dt)
+        rates[n] = c1.nx * c1.ny * c1.nz / (time.perf_counter() - t0)
+    oracle.set_num_threads(threads)
+    return {"value": pts / step, "unit": "grid-pt updates/s", "cores": threads, "kind": "oracle",
+            "sample": (f"1440x720x30 grid, FP64: one adaptation stage forward {t['A'][0]:.2f} s and adjoint "
+                       f"{t['A'][1]:.2f} s, one advection stage forward {t['L'][0]:.2f} s and adjoint "
+                       f"{t['L'][1]:.2f} s ({threads} OpenMP threads over rows for the forward; the "
+                       f"adjoint sweep is serial); scaled to one forward + one adjoint outer step "
+                       f"(M {msub}: {3 * msub} + 3 stages each way, forward stages twice)"),
+            "forward_updates_per_s": pts / fwd,
+            "c1_forward_updates_per_s": {"threads_1": rates[1], f"threads_{threads}": rates[threads]}}
+
+
+def ensemble_c5(steps):
+    """The 24-member mixed ensemble (8 each of 128x64x9, 256x128x30, 720x360x30): one persistent
+    launch per stage, the batched step captured once in a hipGraph and replayed."""
+    import torch
+    from paper_2103_10114_amd import Batch, Dycore, synth
+    cfgs = [synth.ensemble_member(m) for m in range(24)]
+    cores, states = [], []
+    for cfg in cfgs:
+        st = synth.make_state(cfg)
+        c = Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec="fp32", phis=st["phis"], forward_only=True)
+        cores.append(c)
+        states.append(c.to_device(st))
+    b = Batch(cores, states)
+    b.step(1)
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        b.step(1)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pts = sum(c.nx * c.ny * c.nz for c in cfgs)
+    bad = sum(core.count_nonfinite(st) for core, st in zip(cores, states))
+    return {"value": pts * steps / el, "unit": "grid-pt updates/s", "members": len(cfgs), "points_per_step": pts,
+            "steps": steps, "ms_per_step": el / steps * 1e3, "graph_replay": True, "nonfinite_after": bad}
+
+
+def window_adjoint(core, d, lam, nsteps, ckpt):
+    """nsteps forward outer steps, then the adjoint over all of them with recompute from checkpoints
+    taken every ckpt steps (the window's step-start states recomputed from its checkpoint)."""
+    import torch
+    from paper_2103_10114_amd import adjoint_window
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, mem = adjoint_window(core, d, nsteps, lam, ckpt_every=ckpt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pts = core.nx * core.ny * core.nz
+    return {"steps": nsteps, "ckpt_every": ckpt, "seconds": el, "updates_per_s": pts * nsteps / el,
+            "checkpoint_bytes": mem["checkpoint_bytes"], "window_bytes": mem["window_bytes"],
+            "checkpoints": mem["checkpoints"]}
 
 
 def main():
@@ -146,6 +221,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 24-member ensemble")
+    ap.add_argument("--window", type=int, default=48, help="steps of the checkpointed adjoint window (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -195,6 +272,26 @@ def main():
                    "adjoint": adjoint, "block": core.block, "seed": cfg.seed},
         "nonfinite_after": nonfin,
     }
+    if adjoint:
+        import torch
+        from paper_2103_10114_amd import synth as _s
+        lam = core.to_device(_s.random_like(st, 7))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            core.step(d, 1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            core.step_adjoint(d, lam)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out["forward_updates_per_s"] = pts * args.steps / (t1 - t0)
+        out["adjoint_updates_per_s"] = pts * args.steps / (t2 - t1)
+        if args.window > 0:
+            print(f"[bench] checkpointed adjoint window, {args.window} steps", file=sys.stderr, flush=True)
+            out["adjoint_window"] = window_adjoint(core, d, lam, args.window, 8)
+        del lam
     if not args.no_roofline:
         print("[bench] roofline timing", file=sys.stderr, flush=True)
         ms, alg, ach = roofline(core, d, cfg, 4)
@@ -218,9 +315,12 @@ def main():
             ms64, alg64, ach64 = roofline(core64, d64, cfg, 8, reps=5)
             out["fp64"]["roofline"] = {"achieved": ach64, "frac": ach64 / HBM_PEAK_GBS, "avg_launch_ms": ms64["A"]}
         del core64, d64
+    if not args.no_c5:
+        print("[bench] 24-member ensemble", file=sys.stderr, flush=True)
+        out["ensemble_c5"] = ensemble_c5(5)
     if not args.no_cpu:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(msub)
     print(json.dumps(out), flush=True)
 
 

@@ -42,6 +42,7 @@ def _load():
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_substeps.restype = ctypes.c_int
         L.orc_substeps.argtypes = [ctypes.c_void_p, ctypes.c_double]
         _lib = L
@@ -215,6 +216,11 @@ class Oracle:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the forward map's OpenMP loops (timing only; results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def dot(a: dict, b: dict) -> float:

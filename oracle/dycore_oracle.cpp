@@ -1146,6 +1146,15 @@ int orc_num_threads() {
 #endif
 }
 
+// Sets the thread count of the forward map's OpenMP loops (for timing at 1 and at all threads).
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 // Physical constants in use: a, Omega, g, R, c_p, p0, T0, kappa, b, A_cap
 void orc_constants(void* h, double* out) {
   const Geo& g = *static_cast<Geo*>(h);
