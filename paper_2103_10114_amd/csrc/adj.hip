@@ -67,6 +67,8 @@ struct Ctx {
   double ch;
   Scr<T> s;
   GeoFac f;                        // difference factors of the forward stages
+  int jr0 = 0, jrs = 1;            // rows a launch covers: jr0 + jrs * (grid row index)
+  int blk = 0;                     // workgroup size of the row-fused kernel (the handle's)
 };
 
 template <typename T>
@@ -158,7 +160,7 @@ __global__ void k_f2d(Ctx<T> c) {
 template <typename T>
 __global__ void k_f1(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.y + 1;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, nz = g.nz;
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(256) k_f1p(Ctx<T> c) {
 template <typename T>
 __global__ void k_base(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.z, k = blockIdx.y;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.z, k = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const size_t id = i3<T>(g, j, k, i);
@@ -397,7 +399,7 @@ __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C
 template <typename T>
 __global__ void k_a12(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.y;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const C aPi = -g.p0 * c.ch * (C)c.aoP[(size_t)j * g.nx + i];
@@ -729,7 +731,7 @@ __device__ __forceinline__ void t1_point(const Ctx<T>& c, int j, int k, int i, c
 template <typename T>
 __global__ void k_a3t1(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.z, k = blockIdx.y;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.z, k = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const size_t id = i3<T>(g, j, k, i);
@@ -754,7 +756,7 @@ __global__ void k_a3t1(Ctx<T> c) {
 template <typename T>
 __global__ void k_a4(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.y;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -911,6 +913,365 @@ __global__ void k_t4(Ctx<T> c) {
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Adaptation-stage adjoint, row-fused (interior rows 1..ny-1).  One workgroup per scalar row j
+// (and its U row and V row j+1/2) walks the levels top to bottom, like the forward stage kernel:
+// the forward column diagnostics of rows j and j+1 (R T', phi', D, S, omega/p) are recomputed
+// on the way, and the first transposes of every output that reads row j's inputs (U row j, V
+// rows j-1/2 and j+1/2, scalar rows j-1..j+1) are formed per level for the owned columns and
+// staged in LDS, so that the gathers at leap and +-1 neighbours are LDS reads.  Suffix sums
+// (the adjoint of S) run top-down from column totals taken in a first pass.  Two barriers per
+// level.  The pole rows' share goes through the per-point kernels (restricted to the pole rows);
+// this kernel writes the few row-1 and row-(ny-1) intermediates those read.
+// ------------------------------------------------------------------------------------------------
+constexpr int kAar2D = 10, kAarLev = 13;
+__host__ __device__ constexpr size_t aar_lds(int nx, int elem) {
+  return ((size_t)(kAar2D + kAarLev) * nx * elem + 15) & ~size_t(15);
+}
+__host__ __device__ constexpr bool aar_ok(int nx, int elem) { return aar_lds(nx, elem) <= 160 * 1024; }
+constexpr int aar_block(int ni) { return ni <= 2 ? 768 : 512; }
+
+template <typename T, int NI>
+__global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const GeoDev& g = c.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int j = 1 + xcd_row(blockIdx.x, ny - 1);
+  const int B = blockDim.x;
+  int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
+  T* r = reinterpret_cast<T*>(smem);
+  // 2D rows
+  T* sPm = r;            T* sP0 = r + nx;       T* sP1 = r + 2 * nx;
+  T* sLm = r + 3 * nx;   T* sL0 = r + 4 * nx;   T* sL1 = r + 5 * nx;
+  T* sQ0 = r + 6 * nx;   T* sQ1 = r + 7 * nx;   T* sDL = r + 8 * nx;   T* sDQ = r + 9 * nx;
+  // per-level rows
+  T* q = r + kAar2D * nx;
+  T* sHH = q;            T* sAV = q + nx;       T* sFVm = q + 2 * nx;  T* sFV0 = q + 3 * nx;
+  T* sUVm = q + 4 * nx;  T* sUV0 = q + 5 * nx;  T* sFU0 = q + 6 * nx;  T* sFU1 = q + 7 * nx;
+  T* sAD = q + 8 * nx;   T* sPH = q + 9 * nx;   T* sRT = q + 10 * nx;  T* sMU = q + 11 * nx;
+  T* su = q + 12 * nx;
+
+  const bool nPole = (j - 1 == 0);        // scalar row j-1 is the north pole
+  const bool sPole = (j + 1 == ny);       // scalar row j+1 is the south pole
+  const T b = (T)g.b, kap = (T)g.kappa;
+  const C ch = c.ch, RT0 = g.RT0;
+  const int M = g.M[j], n = (M + 1) / 2;
+  const T dxT = (T)((double)M * g.a * g.s[j] * g.dlam);
+  const C dxC = (C)dxT;
+  const T dySj = (T)(g.a * g.s[j] * g.dth);
+  const T dySm = (T)(g.a * g.s[j - 1] * g.dth);       // unused when j-1 is the pole
+  const C dyS1C = sPole ? 1.0 : (C)(T)(g.a * g.s[j + 1] * g.dth);
+  const T dyA = (T)(g.a * g.dth);
+  const C aDy = g.a * g.dth;
+  const T svj = (T)g.sv[j], svm = (T)g.sv[j - 1];
+  const T cotj = (T)(g.cot[j] / g.a), fj = (T)g.f[j];
+  const C cotjC = g.cot[j] / g.a;
+  const T cot1 = sPole ? T(0) : (T)(g.cot[j + 1] / g.a), f1 = sPole ? T(0) : (T)g.f[j + 1];
+  const C capD = g.a * g.dlam / g.acap;
+  const double* sDs = c.s.psum + PS_AD * 2 * (nz + 1);
+  const double* sVG = c.s.psum + PS_AVGL * 2 * (nz + 1);
+  const size_t row3 = (size_t)nz * nx;
+  (void)dySm;
+
+  // ---- 2D rows from the forward recompute
+  for (int cc = 0; cc < NI; ++cc) {
+    const int i = t + cc * B;
+    if (i < nx) {
+      sPm[i] = c.s.P[(size_t)(j - 1) * nx + i];
+      sP0[i] = c.s.P[(size_t)j * nx + i];
+      sP1[i] = c.s.P[(size_t)(j + 1) * nx + i];
+      sLm[i] = c.s.L[(size_t)(j - 1) * nx + i];
+      sL0[i] = c.s.L[(size_t)j * nx + i];
+      sL1[i] = c.s.L[(size_t)(j + 1) * nx + i];
+      sQ0[i] = c.s.Q[(size_t)j * nx + i];
+      sQ1[i] = c.s.Q[(size_t)(j + 1) * nx + i];
+      sDL[i] = c.s.DL[(size_t)j * nx + i];
+      sDQ[i] = c.s.DQ[(size_t)j * nx + i];
+    }
+  }
+  __syncthreads();
+  auto PUr = [&](const T* sP, int i) -> T { return T(0.5) * (sP[i] + sP[wrp(i + 1, nx)]); };
+
+  // ---- pass A: column totals (hydrostatic H of rows j and j+1; sum of the adjoint of S)
+  // HRj, HR1: hydrostatic totals, then (running) the part below the level; Asj, As1: the adjoint
+  // of S summed over the column, then (running) over the levels below
+  C HRj[NI], HR1[NI], Asj[NI], As1[NI];
+#pragma unroll
+  for (int cc = 0; cc < NI; ++cc) { HRj[cc] = HR1[cc] = Asj[cc] = As1[cc] = 0; }
+  for (int k = 0; k < nz; ++k) {
+    asm volatile("" : "+v"(t));
+    const C clk = g.cl[k], sg = g.sig[k];
+#pragma unroll
+    for (int cc = 0; cc < NI; ++cc) {
+      const int i = t + cc * B;
+      if (i >= nx) continue;
+      const size_t lo = (size_t)k * nx + i;
+      const T Fj = c.F[(size_t)j * row3 + lo];
+      const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : c.F[(size_t)(j + 1) * row3 + lo];
+      const T P0 = sP0[i], P1 = sP1[i];
+      HRj[cc] += clk * (C)(b * Fj / P0);
+      HR1[cc] += clk * (C)(b * F1 / P1);
+      const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * (ch * (C)c.aoF[(size_t)j * row3 + lo]);
+      Asj[cc] += -aWPj / (sg * ((C)P0 * (C)P0));
+      if (!sPole) {
+        const C aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)c.aoF[(size_t)(j + 1) * row3 + lo]);
+        As1[cc] += -aWP1 / (sg * ((C)P1 * (C)P1));
+      }
+    }
+  }
+
+  // ---- level loop
+  // aLQ: column sum of the l and q adjoints (they enter p_s only as a sum); aDLQ: of the leaped
+  // d+l and d+q adjoints (the same leap transposes both)
+  C Sj[NI], pre[NI], aP[NI], aPU[NI], aPV[NI], aLQ[NI], aDLQ[NI];
+#pragma unroll
+  for (int cc = 0; cc < NI; ++cc) Sj[cc] = pre[cc] = aP[cc] = aPU[cc] = aPV[cc] = aLQ[cc] = aDLQ[cc] = 0;
+#pragma unroll 1
+  for (int k = 0; k < nz; ++k) {
+    asm volatile("" : "+v"(t));
+    const C clk = g.cl[k], cpk = g.cpk[k], sg = g.sig[k], dsg = g.dsig[k];
+    const size_t lvl = (size_t)k * nx;
+    const T* pFm = uni(c.F + ((size_t)(j - 1) * row3 + lvl));
+    const T* pFj = uni(c.F + ((size_t)j * row3 + lvl));
+    const T* pF1 = uni(c.F + ((size_t)(j + 1) * row3 + lvl));
+    const T* pUm = uni(c.U + ((size_t)(j - 1) * row3 + lvl));
+    const T* pUj = uni(c.U + ((size_t)j * row3 + lvl));
+    const T* pU1 = uni(c.U + ((size_t)(j + 1) * row3 + lvl));
+    const T* pVm = uni(c.V + ((size_t)(j - 1) * row3 + lvl));
+    const T* pVj = uni(c.V + ((size_t)j * row3 + lvl));
+    const T* qFm = uni(c.aoF + ((size_t)(j - 1) * row3 + lvl));
+    const T* qFj = uni(c.aoF + ((size_t)j * row3 + lvl));
+    const T* qF1 = uni(c.aoF + ((size_t)(j + 1) * row3 + lvl));
+    const T* qUj = uni(c.aoU + ((size_t)j * row3 + lvl));
+    const T* qU1 = uni(c.aoU + ((size_t)(j + 1) * row3 + lvl));
+    const T* qVm = uni(c.aoV + ((size_t)(j - 1) * row3 + lvl));
+    const T* qVj = uni(c.aoV + ((size_t)j * row3 + lvl));
+    // values of the owned columns carried from phase 1 to phase 2
+    // (the owned columns' entries of the LDS rows are read back in phase 2)
+    T vRTm[NI], vRT1[NI], vPH1[NI], vFj[NI], vUj[NI], vVj[NI], vVm[NI];
+    T vAVm[NI], vAV1[NI], vAD1[NI], vMVm[NI], vMVj[NI], voF[NI], voU[NI], voV[NI], vAUU[NI];
+    // ---- phase 1: per-point quantities of the owned columns
+#pragma unroll
+    for (int cc = 0; cc < NI; ++cc) {
+      const int i = t + cc * B;
+      if (i >= nx) continue;
+      const int im = wrp(i - 1, nx), ip = wrp(i + 1, nx);
+      const size_t oj = (size_t)j * row3 + lvl;
+      const unsigned ui = (unsigned)i, uim = (unsigned)im, uip = (unsigned)ip;
+      const T Fm = nPole ? (T)c.pin[k] : pFm[ui];
+      const T Fj = pFj[ui];
+      const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : pF1[ui];
+      const T Uj = pUj[ui], Ujm = pUj[uim];
+      const T Um = nPole ? T(0) : pUm[ui], Umm = nPole ? T(0) : pUm[uim];
+      const T U1 = sPole ? T(0) : pU1[ui], U1m = sPole ? T(0) : pU1[uim];
+      const T Vj = pVj[ui], Vjp = pVj[uip];                    // V row j+1/2
+      const T Vm = pVm[ui], Vmp = pVm[uip];                    // V row j-1/2
+      const T Pm = sPm[i], P0 = sP0[i], P1 = sP1[i];
+      // forward: R T', phi'
+      const T RTm = b * Fm / Pm, RTj = b * Fj / P0, RT1 = b * F1 / P1;
+      HRj[cc] -= clk * (C)RTj;
+      HR1[cc] -= clk * (C)RT1;
+      const T PHj = (T)(HRj[cc] + cpk * (C)RTj);
+      const T PH1 = (T)(HR1[cc] + cpk * (C)RT1);
+      const T PU0 = PUr(sP0, i), PUm0 = PUr(sP0, im);
+      const T uj = Uj / PU0;
+      // adjoint seeds
+      voF[cc] = qFj[ui];
+      voU[cc] = qUj[ui];
+      voV[cc] = qVj[ui];
+      const C gF = ch * (C)voF[cc];
+      const C gU = ch * (C)voU[cc];
+      const C gV = ch * (C)voV[cc];
+      const C gVm = ch * (C)qVm[ui];
+      const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * gF;
+      C aWPm = 0, aWP1 = 0;
+      if (!nPole) aWPm = ((C)(b * Pm) + (C)(kap * Fm)) * (ch * (C)qFm[ui]);
+      C AD1 = 0;
+      if (!sPole) {
+        aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)qF1[ui]);
+        const C aSK1 = -aWP1 / (sg * ((C)P1 * (C)P1));
+        As1[cc] -= aSK1;
+        const C aPi1 = -g.p0 * ch * (C)c.aoP[(size_t)(j + 1) * nx + i];
+        AD1 = -0.5 * dsg * aWP1 / (sg * ((C)P1 * (C)P1)) + dsg * (aPi1 + As1[cc]);
+      }
+      const C aSKj = -aWPj / (sg * ((C)P0 * (C)P0));
+      Asj[cc] -= aSKj;
+      const C aPij = -g.p0 * ch * (C)c.aoP[(size_t)j * nx + i];
+      const C ADj = -0.5 * dsg * aWPj / (sg * ((C)P0 * (C)P0)) + dsg * (aPij + Asj[cc]);
+      // U row j
+      const T VV = T(0.25) * (Vj + Vjp + Vm + Vmp);
+      const T fs = fj + uj * cotj;
+      const C HH = -(C)PU0 * gU;
+      const C FUj = (C)fs * gU;
+      const C AUU = -(C)VV * cotjC * gU;
+      // U row j+1 (Coriolis read of V row j+1/2)
+      C FU1 = 0;
+      if (!sPole) {
+        const T fs1 = f1 + (U1 / PUr(sP1, i)) * cot1;
+        FU1 = (C)fs1 * (ch * (C)qU1[ui]);
+      }
+      // V rows j-1/2 (jv = j-1) and j+1/2 (jv = j)
+      auto vrow = [&](int jv, const T* sPa, const T* sPb, T Ua, T Uam, T Ub, T Ubm, C gv, C& MV, C& FV, C& UV) {
+        const T PV = T(0.5) * (sPa[i] + sPb[i]);
+        const T ua = (jv >= 1) ? Ua / PUr(sPa, i) : T(0), uam = (jv >= 1) ? Uam / PUr(sPa, im) : T(0);
+        const T ub = (jv + 1 <= ny - 1) ? Ub / PUr(sPb, i) : T(0), ubm = (jv + 1 <= ny - 1) ? Ubm / PUr(sPb, im) : T(0);
+        const T UU = T(0.25) * (Uam + Ua + Ubm + Ub);
+        const T uu = T(0.25) * (uam + ua + ubm + ub);
+        const T fsv = (T)g.fv[jv] + uu * (T)(g.cotv[jv] / g.a);
+        MV = -(C)PV * gv / (C)dyA;
+        FV = (C)fsv * gv;
+        UV = (C)UU * gv * (g.cotv[jv] / g.a);
+      };
+      C MVm, FVm, UVm, MVj, FVj, UVj;
+      vrow(j - 1, sPm, sP0, Um, Umm, Uj, Ujm, gVm, MVm, FVm, UVm);
+      vrow(j, sP0, sP1, Uj, Ujm, U1, U1m, gV, MVj, FVj, UVj);
+      (void)PUm0;
+      // LDS rows
+      sHH[i] = (T)HH;
+      sAV[i] = (T)aWPj;
+      sFVm[i] = (T)FVm;
+      sFV0[i] = (T)FVj;
+      sUVm[i] = (T)UVm;
+      sUV0[i] = (T)UVj;
+      sFU0[i] = (T)FUj;
+      sFU1[i] = (T)FU1;
+      sAD[i] = (T)ADj;
+      sPH[i] = PHj;
+      sRT[i] = RTj;
+      sMU[i] = PU0 * Uj;
+      su[i] = uj;
+      // carried values
+      vRTm[cc] = RTm; vRT1[cc] = RT1; vPH1[cc] = PH1;
+      vFj[cc] = Fj; vUj[cc] = Uj; vVj[cc] = Vj; vVm[cc] = Vm;
+      vAVm[cc] = (T)aWPm; vAV1[cc] = (T)aWP1;
+      vAD1[cc] = (T)AD1;
+      vMVm[cc] = (T)MVm; vMVj[cc] = (T)MVj;
+      vAUU[cc] = (T)AUU;
+      // intermediates the pole rows' per-point kernels read
+      if (j == 1) {
+        c.s.AVGL[oj + i] = (T)aWPj;
+        c.s.FU[oj + i] = (T)FUj;
+        c.s.AD[oj + i] = (T)ADj;
+        c.s.PHI[oj + i] = PHj;
+        c.s.RT[oj + i] = RTj;
+      }
+      if (j == ny - 1) {
+        c.s.AVGL[oj + i] = (T)aWPj;
+        c.s.MV[oj + i] = (T)MVj;
+        c.s.RT[oj + i] = RTj;
+      }
+      // base transpose of the interior row (identity)
+      if (c.abU) {
+        c.abF[oj + i] += c.aoF[oj + i];
+        c.abU[oj + i] += c.aoU[oj + i];
+        c.abV[oj + i] += c.aoV[oj + i];
+        if (k == 0) c.abP[(size_t)j * nx + i] += c.aoP[(size_t)j * nx + i];
+      }
+    }
+    __syncthreads();
+
+    // ---- phase 2: forward D, S, omega/p; gathers; transposes into the owned columns
+#pragma unroll
+    for (int cc = 0; cc < NI; ++cc) {
+      const int i = t + cc * B;
+      if (i >= nx) continue;
+      const int im = wrp(i - 1, nx), ip = wrp(i + 1, nx);
+      const size_t oj = (size_t)j * row3 + (size_t)k * nx + i;
+      const T P0 = sP0[i];
+      const T vRTj = sRT[i], vPHj = sPH[i];
+      const C vAVj = (C)sAV[i], vADj = (C)sAD[i], vHH = (C)sHH[i];
+      const C vUVm = (C)sUVm[i], vUVj = (C)sUV0[i], vFVm = (C)sFVm[i], vFVj = (C)sFV0[i];
+      const C vFUj = (C)sFU0[i], vFU1 = (C)sFU1[i];
+      const T PU0 = PUr(sP0, i);
+      const T PV0 = T(0.5) * (sP0[i] + sP1[i]), PVm = T(0.5) * (sPm[i] + sP0[i]);
+      // forward D, S, omega/p (as the forward recompute forms them)
+      const T D = (sMU[wrp(i + n - 1, nx)] - sMU[wrp(i - n, nx)]) / dxT +
+                  (svj * (PV0 * vVj[cc]) - svm * (PVm * vVm[cc])) / dySj;
+      const C SkC = Sj[cc];
+      const T Sk = (T)SkC;
+      Sj[cc] += (C)D * dsg;
+      const T zon = T(0.5) * (su[i] * sDL[i] + su[im] * sDL[im]);
+      const T mer = T(0.5) * ((vVj[cc] / PV0) * (sL1[i] - sL0[i]) + (vVm[cc] / PVm) * (sL0[i] - sLm[i])) / dyA;
+      const C P2c = (C)P0 * (C)P0;
+      const T WP = (T)(((C)zon + (C)mer) - (SkC + 0.5 * (C)D * dsg) / (sg * P2c));
+      const C wp = (C)WP, gF = ch * (C)voF[cc], aWP = vAVj;
+      const C AFE = (C)(T)((C)kap * wp * gF);
+      const C AP3 = (C)(T)((C)b * wp * gF + 2.0 * ((C)Sk + 0.5 * (C)D * dsg) / (sg * P2c * (C)P0) * aWP);
+      // U point: pressure gradient seen by U row j
+      const T dphi = (sPH[wrp(i + n, nx)] - sPH[wrp(i + 1 - n, nx)]) / dxT;
+      const T rtx = T(0.5) * (vRTj + sRT[ip]);
+      const C pgf = (C)dphi + RT0 * (C)sDQ[i] + (C)rtx * (C)sDL[i];
+      const C gU = ch * (C)voU[cc], gV = ch * (C)voV[cc];
+      const C APU3 = (C)(T)(-pgf * gU);
+      // V point: pressure gradient seen by V row j+1/2
+      const C pgfV = ((C)(vPH1[cc] - vPHj) + RT0 * (C)(sQ1[i] - sQ0[i]) +
+                      (C)(T(0.5) * (vRTj + vRT1[cc])) * (C)(sL1[i] - sL0[i])) / (C)dyA;
+      const C APV3 = (C)(T)(-pgfV * gV);
+      // gathers: scalar point
+      const C mM = (C)vMVm[cc], mJ = (C)vMVj[cc];
+      const C aPHI = ((C)sHH[wrp(i - n, nx)] - (C)sHH[wrp(i + n - 1, nx)]) / dxC + mM - mJ;
+      const C aRT = 0.5 * ((C)sHH[i] * (C)sDL[i] + (C)sHH[im] * (C)sDL[im]) +
+                    0.5 * ((C)sL0[i] - (C)sLm[i]) * mM + 0.5 * ((C)sL1[i] - (C)sL0[i]) * mJ;
+      const C cvgm = (nPole ? sVG[0 * (nz + 1) + k] / nx : 0.5 * (C)vAVm[cc]) + 0.5 * vAVj;
+      const C cvgj = 0.5 * vAVj + (sPole ? sVG[1 * (nz + 1) + k] / nx : 0.5 * (C)vAV1[cc]);
+      const C rtym = 0.5 * ((C)vRTm[cc] + (C)vRTj), rtyj = 0.5 * ((C)vRTj + (C)vRT1[cc]);
+      const C wm = (C)(vVm[cc] / PVm) / aDy * cvgm, wj = (C)(vVj[cc] / PV0) / aDy * cvgj;
+      const C aL = (wm + rtym * mM) - (wj + rtyj * mJ);
+      const C aQ = RT0 * mM - RT0 * mJ;
+      // gathers: U point
+      const C dl = (C)sDL[i];
+      const C au = (C)vAUU[cc] + 0.5 * dl * (vAVj + (C)sAV[ip]) +
+                   0.25 * (vUVm + (C)sUVm[ip] + vUVj + (C)sUV0[ip]);
+      const C aUd = 0.25 * (vFVm + (C)sFVm[ip] + vFVj + (C)sFV0[ip]);
+      const C u = (C)(vUj[cc] / PU0);
+      const C rtxC = 0.5 * ((C)vRTj + (C)sRT[ip]);
+      const C adl = 0.5 * u * (vAVj + (C)sAV[ip]) + rtxC * vHH;
+      const C adq = RT0 * vHH;
+      // gathers: V point
+      const C avv = ((C)sL1[i] - (C)sL0[i]) / aDy * cvgj;
+      C aVd = (C)sFU0[im] + vFUj;
+      if (!sPole) aVd += (C)sFU1[im] + vFU1;
+      const C avd = -0.25 * aVd;
+      // divergence and velocity transposes
+      const C aMU = ((C)sAD[wrp(i - n + 1, nx)] - (C)sAD[wrp(i + n, nx)]) / dxC;
+      const C PUc = (C)PU0, Uc = (C)vUj[cc];
+      c.aiU[oj] = (T)((C)c.aiU[oj] + aUd + au / PUc + PUc * aMU);
+      const C aPU3 = -Uc / (PUc * PUc) * au + Uc * aMU;
+      const C tN = vADj / (C)dySj;
+      const C tS = sPole ? capD * sDs[1 * (nz + 1) + k] : (C)vAD1[cc] / dyS1C;
+      const C aMV = (C)svj * (tN - tS);
+      const C PVc = (C)PV0, Vc = (C)vVj[cc];
+      c.aiV[oj] = (T)((C)c.aiV[oj] + avd + avv / PVc + PVc * aMV);
+      const C aPV3 = -Vc / (PVc * PVc) * avv + Vc * aMV;
+      // hydrostatic transpose and column sums
+      const C art = aRT + clk * pre[cc] + cpk * aPHI;
+      pre[cc] += aPHI;
+      const C Pc = (C)P0;
+      const C afe = AFE + (C)b / Pc * art;
+      aP[cc] += AP3 - (C)b / (Pc * Pc) * (C)vFj[cc] * art;
+      aLQ[cc] += aL + aQ;
+      aDLQ[cc] += adl + adq;
+      aPU[cc] += APU3 + aPU3;
+      aPV[cc] += APV3 + aPV3;
+      c.aiF[oj] = (T)((C)c.aiF[oj] + afe);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cc = 0; cc < NI; ++cc) {
+    const int i = t + cc * B;
+    if (i >= nx) continue;
+    const size_t i2 = (size_t)j * nx + i;
+    c.s.AP2[i2] = aP[cc];
+    c.s.APU2[i2] = aPU[cc];
+    c.s.APV2[i2] = aPV[cc];
+    c.s.AL2[i2] = aLQ[cc];
+    c.s.AQ2[i2] = 0;
+    c.s.ADL2[i2] = aDLQ[cc];
+    c.s.ADQ2[i2] = 0;
+  }
+}
+
 // The base transpose of a stage applied in place: pole rows of Phi and p_s become the spread of
 // their row mean (FP64 sum), pole rows of U become 0; interior rows and V are left as they are.
 template <typename T>
@@ -933,18 +1294,52 @@ __global__ void __launch_bounds__(256) k_base_inplace(GeoDev g, T* U, T* F, T* P
   }
 }
 
+// Dynamic LDS above 64 KB is enabled once per kernel.
+template <auto Kernel>
+hipError_t allow_lds_adj(size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  static bool done = false;
+  if (done) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+// The row-fused adaptation adjoint serves grids whose rows fit the LDS at <= 2 columns per thread.
 template <typename T>
-hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s) {
+bool aar_used(const Ctx<T>& c) {
+  return c.blk > 0 && aar_ok(c.g.nx, (int)sizeof(T)) && (c.g.nx + c.blk - 1) / c.blk <= 2 && c.g.ny >= 4;
+}
+
+template <typename T, int NI>
+hipError_t launch_aar(const Ctx<T>& c, hipStream_t s) {
+  const size_t lds = aar_lds(c.g.nx, (int)sizeof(T));
+  hipError_t e = allow_lds_adj<k_aar<T, NI>>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_aar<T, NI>), dim3(c.g.ny - 1), dim3(c.blk), lds, s, c);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   const GeoDev& g = c.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1), gcol_int(gx, ny - 1);
+  const bool rows = adapt && aar_used(c);
   hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, c);
+  Ctx<T> cf = c;
+  cf.jr0 = 1;
+  cf.jrs = rows ? ny - 2 : 1;   // the row-fused kernel recomputes its rows; the pole kernels read rows 1, ny-1
+  hipLaunchKernelGGL((k_f1<T>), rows ? dim3(gx, 2) : gcol_int, dim3(tb), 0, s, cf);
   hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_f1p<T>), dim3(2), dim3(256), 0, s, c);
-  if (c.abU) hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
+  if (c.abU) {
+    // interior rows' base transpose is folded into the row-fused kernel; V row 1/2 stays here
+    hipLaunchKernelGGL((k_base<T>), rows ? dim3(gx, nz, 1) : g3, dim3(tb), 0, s, c);
+  }
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
                      c.s.psum + PS_AOF * 2 * (nz + 1));
   if (c.abU) hipLaunchKernelGGL((k_base_pole<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
@@ -959,13 +1354,29 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
-  hipLaunchKernelGGL((k_a12<T>), g2, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
-                     c.s.psum + PS_AD * 2 * (nz + 1));
-  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL, (const T*)nullptr,
-                     c.s.psum + PS_AVGL * 2 * (nz + 1));
-  hipLaunchKernelGGL((k_a3t1<T>), g3, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_a4<T>), g2, dim3(tb), 0, s, c);
+  if (aar_used(c)) {
+    // pole rows through the per-point kernels, interior rows row-fused
+    Ctx<T> cp = c;
+    cp.jr0 = 0;
+    cp.jrs = ny;
+    hipLaunchKernelGGL((k_a12<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
+                       (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL,
+                       (const T*)nullptr, c.s.psum + PS_AVGL * 2 * (nz + 1));
+    const hipError_t e = (nx + c.blk - 1) / c.blk == 1 ? launch_aar<T, 1>(c, s) : launch_aar<T, 2>(c, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_a3t1<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
+    hipLaunchKernelGGL((k_a4<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
+  } else {
+    hipLaunchKernelGGL((k_a12<T>), g2, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
+                       (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL,
+                       (const T*)nullptr, c.s.psum + PS_AVGL * 2 * (nz + 1));
+    hipLaunchKernelGGL((k_a3t1<T>), g3, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_a4<T>), g2, dim3(tb), 0, s, c);
+  }
   hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
   return hipGetLastError();
@@ -1100,9 +1511,10 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.ch = ch;
   c.s = scratch_of<T>(v);
   c.f = v.fac;
+  c.blk = v.block;
   hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
   if (e != hipSuccess) return e;
-  e = run_stage_adjoint<T>(c, s);
+  e = run_stage_adjoint<T>(c, s, process == 0);
   if (e != hipSuccess) return e;
   return process == 0 ? run_adapt<T>(c, s) : run_advect<T>(c, s);
 }

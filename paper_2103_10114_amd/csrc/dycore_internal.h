@@ -99,6 +99,17 @@ int columns_per_thread(int nx, int block);
 int stage_pipelined(int nx, int elem);   // 1 if the stage kernels for rows of nx columns are pipelined
 int max_block_for(int nx, int block);   // 1 if `block` threads are allowed for rows of nx columns
 
+// A uniform pointer, opaque to the optimiser: loop strength reduction would otherwise turn every
+// (array, owned column) address stream of a level loop into its own 64-bit induction variable in
+// VGPRs; this way each access is an SGPR base plus the column's 32-bit VGPR offset.
+template <typename P>
+__device__ __forceinline__ P uni(P p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
+  return reinterpret_cast<P>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 // XCD-aware row order: workgroups are dispatched round-robin over the 8 XCDs,
 // so block b lands on XCD b % 8.  Give each XCD a contiguous band of rows, in
 // order, so that neighbouring rows (which share halo rows) share an L2.

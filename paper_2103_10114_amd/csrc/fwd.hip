@@ -34,17 +34,6 @@ __device__ __forceinline__ double wave_sum(double acc) {
 
 using C = double;
 
-// A uniform pointer, opaque to the optimiser: loop strength reduction would otherwise turn every
-// (array, owned column) address stream of a level loop into its own 64-bit induction variable in
-// VGPRs; this way each access is an SGPR base plus the column's 32-bit VGPR offset.
-template <typename P>
-__device__ __forceinline__ P uni(P p) {
-  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
-  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
-  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
-  return reinterpret_cast<P>((static_cast<unsigned long long>(hi) << 32) | lo);
-}
-
 }  // namespace
 
 // Largest workgroup per columns-per-thread: bounds the VGPR budget so that the FP64 column
@@ -626,7 +615,6 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         const T fs = fj + u_i * cota;
         const C TU = -(C)(T(0.5) * (sP0[i] + sP0[ip])) * pgf - (C)fs * (C)VV;
         goU[idx] = (T)((C)baseU + A.ch * TU);
-        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       const T F0p = (T)A.pin[pidx * (nz + 1) + k];
@@ -669,7 +657,6 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         const T fs = fvj + uu * cotva;
         const C TV = -(C)sPV0[i] * pgf + (C)fs * (C)UU;
         goV[idv] = (T)((C)baseV + A.ch * TV);
-        __builtin_amdgcn_sched_barrier(0);
       }
     }
     if (k + 1 < nz) commit(k + 1, lev0 + (size_t)((k + 1) & 1) * bufStride);
