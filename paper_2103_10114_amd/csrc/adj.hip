@@ -69,6 +69,7 @@ struct Ctx {
   GeoFac f;                        // difference factors of the forward stages
   int jr0 = 0, jrs = 1;            // rows a launch covers: jr0 + jrs * (grid row index)
   int blk = 0;                     // workgroup size of the row-fused kernel (the handle's)
+  int parts = 7;                   // first adaptation transposes: 1 scalar point (+ suffix), 2 U, 4 V
 };
 
 template <typename T>
@@ -332,13 +333,14 @@ __global__ void k_base_pole(Ctx<T> c) {
 // ------------------------------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C& aWPo, C& aSKo, C& aDo) {
+  aWPo = aSKo = aDo = 0;
   const GeoDev& g = c.g;
   const int nx = g.nx, ny = g.ny;
   const T b = (T)g.b, kap = (T)g.kappa;
   const C ch = c.ch;
   const size_t id = i3<T>(g, j, k, i);
   // scalar point (every row; pole rows per stored copy)
-  {
+  if (c.parts & 1) {
     const T P = P2(c, j, i);
     const T F = Fe(c, j, k, i);
     const C gF = ch * (C)c.aoF[id];
@@ -355,7 +357,7 @@ __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C
     c.s.AP3[id] = (T)((C)b * wp * gF + 2.0 * (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P2c * (C)P) * aWP);
   }
   // U point (interior rows)
-  if (j >= 1 && j < ny) {
+  if ((c.parts & 2) && j >= 1 && j < ny) {
     const int M = g.M[j], n = (M + 1) / 2;
     const T dx = (T)((double)M * g.a * g.s[j] * g.dlam);
     const int ip1 = wrp(i + 1, nx);
@@ -373,7 +375,7 @@ __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C
     c.s.APU3[id] = (T)(-pgf * gU);
   }
   // V point (V rows)
-  if (j < ny) {
+  if ((c.parts & 4) && j < ny) {
     const int jv = j;
     const int im1 = wrp(i - 1, nx);
     const C gV = ch * (C)c.aoV[id];
@@ -410,7 +412,7 @@ __global__ void k_a12(Ctx<T> c) {
     asm volatile("" : "+v"(i));
     C aWP, aSK, aD;
     a1_point(c, j, k, i, aWP, aSK, aD);
-    c.s.AD[i3<T>(g, j, k, i)] = (T)(aD + g.dsig[k] * (aPi + acc));
+    if (c.parts & 1) c.s.AD[i3<T>(g, j, k, i)] = (T)(aD + g.dsig[k] * (aPi + acc));
     acc += aSK;
   }
 }
@@ -924,7 +926,7 @@ __global__ void k_t4(Ctx<T> c) {
 // level.  The pole rows' share goes through the per-point kernels (restricted to the pole rows);
 // this kernel writes the few row-1 and row-(ny-1) intermediates those read.
 // ------------------------------------------------------------------------------------------------
-constexpr int kAar2D = 10, kAarLev = 13;
+constexpr int kAar2D = 13, kAarLev = 13;
 __host__ __device__ constexpr size_t aar_lds(int nx, int elem) {
   return ((size_t)(kAar2D + kAarLev) * nx * elem + 15) & ~size_t(15);
 }
@@ -940,10 +942,11 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   const int B = blockDim.x;
   int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
   T* r = reinterpret_cast<T*>(smem);
-  // 2D rows
+  // 2D rows: P of rows j-1, j, j+1; the meridional l and q differences; the leaped d+l, d+q of
+  // row j; reciprocals of P (rows j, j+1) and of its U-point averages (rows j-1, j, j+1)
   T* sPm = r;            T* sP0 = r + nx;       T* sP1 = r + 2 * nx;
-  T* sLm = r + 3 * nx;   T* sL0 = r + 4 * nx;   T* sL1 = r + 5 * nx;
-  T* sQ0 = r + 6 * nx;   T* sQ1 = r + 7 * nx;   T* sDL = r + 8 * nx;   T* sDQ = r + 9 * nx;
+  T* sdLm = r + 3 * nx;  T* sdL0 = r + 4 * nx;  T* sdQ0 = r + 5 * nx;  T* sDL = r + 6 * nx;   T* sDQ = r + 7 * nx;
+  T* srP0 = r + 8 * nx;  T* srP1 = r + 9 * nx;  T* srUm = r + 10 * nx; T* srU0 = r + 11 * nx; T* srU1 = r + 12 * nx;
   // per-level rows
   T* q = r + kAar2D * nx;
   T* sHH = q;            T* sAV = q + nx;       T* sFVm = q + 2 * nx;  T* sFV0 = q + 3 * nx;
@@ -970,6 +973,10 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   const C capD = g.a * g.dlam / g.acap;
   const double* sDs = c.s.psum + PS_AD * 2 * (nz + 1);
   const double* sVG = c.s.psum + PS_AVGL * 2 * (nz + 1);
+  // reciprocals of the row constants
+  const T rdxT = T(1) / dxT, rdySjT = T(1) / dySj, rdyAT = T(1) / dyA;
+  const C rdxC = 1.0 / dxC, rdySjC = 1.0 / (C)dySj, rdyS1C = 1.0 / dyS1C, rdyAC = 1.0 / (C)dyA, raDy = 1.0 / aDy;
+  const C rnx = 1.0 / (C)nx;
   const size_t row3 = (size_t)nz * nx;
   (void)dySm;
 
@@ -977,20 +984,33 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   for (int cc = 0; cc < NI; ++cc) {
     const int i = t + cc * B;
     if (i < nx) {
-      sPm[i] = c.s.P[(size_t)(j - 1) * nx + i];
-      sP0[i] = c.s.P[(size_t)j * nx + i];
-      sP1[i] = c.s.P[(size_t)(j + 1) * nx + i];
-      sLm[i] = c.s.L[(size_t)(j - 1) * nx + i];
-      sL0[i] = c.s.L[(size_t)j * nx + i];
-      sL1[i] = c.s.L[(size_t)(j + 1) * nx + i];
-      sQ0[i] = c.s.Q[(size_t)j * nx + i];
-      sQ1[i] = c.s.Q[(size_t)(j + 1) * nx + i];
+      const T Pm = c.s.P[(size_t)(j - 1) * nx + i], P0 = c.s.P[(size_t)j * nx + i];
+      const T P1 = c.s.P[(size_t)(j + 1) * nx + i];
+      sPm[i] = Pm;
+      sP0[i] = P0;
+      sP1[i] = P1;
+      const T Lm = c.s.L[(size_t)(j - 1) * nx + i], L0 = c.s.L[(size_t)j * nx + i];
+      const T L1 = c.s.L[(size_t)(j + 1) * nx + i];
+      sdLm[i] = L0 - Lm;
+      sdL0[i] = L1 - L0;
+      sdQ0[i] = c.s.Q[(size_t)(j + 1) * nx + i] - c.s.Q[(size_t)j * nx + i];
       sDL[i] = c.s.DL[(size_t)j * nx + i];
       sDQ[i] = c.s.DQ[(size_t)j * nx + i];
+      srP0[i] = T(1) / P0;
+      srP1[i] = T(1) / P1;
     }
   }
   __syncthreads();
   auto PUr = [&](const T* sP, int i) -> T { return T(0.5) * (sP[i] + sP[wrp(i + 1, nx)]); };
+  for (int cc = 0; cc < NI; ++cc) {
+    const int i = t + cc * B;
+    if (i < nx) {
+      srUm[i] = T(1) / PUr(sPm, i);
+      srU0[i] = T(1) / PUr(sP0, i);
+      srU1[i] = T(1) / PUr(sP1, i);
+    }
+  }
+  __syncthreads();
 
   // ---- pass A: column totals (hydrostatic H of rows j and j+1; sum of the adjoint of S)
   // HRj, HR1: hydrostatic totals, then (running) the part below the level; Asj, As1: the adjoint
@@ -1009,13 +1029,15 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const T Fj = c.F[(size_t)j * row3 + lo];
       const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : c.F[(size_t)(j + 1) * row3 + lo];
       const T P0 = sP0[i], P1 = sP1[i];
-      HRj[cc] += clk * (C)(b * Fj / P0);
-      HR1[cc] += clk * (C)(b * F1 / P1);
+      const C rP0 = (C)srP0[i], rP1 = (C)srP1[i];
+      HRj[cc] += clk * (C)(b * Fj * srP0[i]);
+      HR1[cc] += clk * (C)(b * F1 * srP1[i]);
+      const C rsg = 1.0 / sg;
       const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * (ch * (C)c.aoF[(size_t)j * row3 + lo]);
-      Asj[cc] += -aWPj / (sg * ((C)P0 * (C)P0));
+      Asj[cc] += -aWPj * rsg * (rP0 * rP0);
       if (!sPole) {
         const C aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)c.aoF[(size_t)(j + 1) * row3 + lo]);
-        As1[cc] += -aWP1 / (sg * ((C)P1 * (C)P1));
+        As1[cc] += -aWP1 * rsg * (rP1 * rP1);
       }
     }
   }
@@ -1030,6 +1052,7 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   for (int k = 0; k < nz; ++k) {
     asm volatile("" : "+v"(t));
     const C clk = g.cl[k], cpk = g.cpk[k], sg = g.sig[k], dsg = g.dsig[k];
+    const C rsg = 1.0 / sg;
     const size_t lvl = (size_t)k * nx;
     const T* pFm = uni(c.F + ((size_t)(j - 1) * row3 + lvl));
     const T* pFj = uni(c.F + ((size_t)j * row3 + lvl));
@@ -1068,13 +1091,13 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const T Vm = pVm[ui], Vmp = pVm[uip];                    // V row j-1/2
       const T Pm = sPm[i], P0 = sP0[i], P1 = sP1[i];
       // forward: R T', phi'
-      const T RTm = b * Fm / Pm, RTj = b * Fj / P0, RT1 = b * F1 / P1;
+      const T RTm = b * Fm / Pm, RTj = b * Fj * srP0[i], RT1 = b * F1 * srP1[i];
       HRj[cc] -= clk * (C)RTj;
       HR1[cc] -= clk * (C)RT1;
       const T PHj = (T)(HRj[cc] + cpk * (C)RTj);
       const T PH1 = (T)(HR1[cc] + cpk * (C)RT1);
-      const T PU0 = PUr(sP0, i), PUm0 = PUr(sP0, im);
-      const T uj = Uj / PU0;
+      const T PU0 = PUr(sP0, i);
+      const T uj = Uj * srU0[i];
       // adjoint seeds
       voF[cc] = qFj[ui];
       voU[cc] = qUj[ui];
@@ -1089,15 +1112,17 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       C AD1 = 0;
       if (!sPole) {
         aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)qF1[ui]);
-        const C aSK1 = -aWP1 / (sg * ((C)P1 * (C)P1));
+        const C rP1 = (C)srP1[i];
+        const C aSK1 = -aWP1 * rsg * (rP1 * rP1);
         As1[cc] -= aSK1;
         const C aPi1 = -g.p0 * ch * (C)c.aoP[(size_t)(j + 1) * nx + i];
-        AD1 = -0.5 * dsg * aWP1 / (sg * ((C)P1 * (C)P1)) + dsg * (aPi1 + As1[cc]);
+        AD1 = 0.5 * dsg * aSK1 + dsg * (aPi1 + As1[cc]);
       }
-      const C aSKj = -aWPj / (sg * ((C)P0 * (C)P0));
+      const C rP0 = (C)srP0[i];
+      const C aSKj = -aWPj * rsg * (rP0 * rP0);
       Asj[cc] -= aSKj;
       const C aPij = -g.p0 * ch * (C)c.aoP[(size_t)j * nx + i];
-      const C ADj = -0.5 * dsg * aWPj / (sg * ((C)P0 * (C)P0)) + dsg * (aPij + Asj[cc]);
+      const C ADj = 0.5 * dsg * aSKj + dsg * (aPij + Asj[cc]);
       // U row j
       const T VV = T(0.25) * (Vj + Vjp + Vm + Vmp);
       const T fs = fj + uj * cotj;
@@ -1107,25 +1132,25 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       // U row j+1 (Coriolis read of V row j+1/2)
       C FU1 = 0;
       if (!sPole) {
-        const T fs1 = f1 + (U1 / PUr(sP1, i)) * cot1;
+        const T fs1 = f1 + (U1 * srU1[i]) * cot1;
         FU1 = (C)fs1 * (ch * (C)qU1[ui]);
       }
       // V rows j-1/2 (jv = j-1) and j+1/2 (jv = j)
-      auto vrow = [&](int jv, const T* sPa, const T* sPb, T Ua, T Uam, T Ub, T Ubm, C gv, C& MV, C& FV, C& UV) {
+      auto vrow = [&](int jv, const T* sPa, const T* sPb, const T* sRa, const T* sRb, T Ua, T Uam, T Ub, T Ubm,
+                      C gv, C& MV, C& FV, C& UV) {
         const T PV = T(0.5) * (sPa[i] + sPb[i]);
-        const T ua = (jv >= 1) ? Ua / PUr(sPa, i) : T(0), uam = (jv >= 1) ? Uam / PUr(sPa, im) : T(0);
-        const T ub = (jv + 1 <= ny - 1) ? Ub / PUr(sPb, i) : T(0), ubm = (jv + 1 <= ny - 1) ? Ubm / PUr(sPb, im) : T(0);
+        const T ua = (jv >= 1) ? Ua * sRa[i] : T(0), uam = (jv >= 1) ? Uam * sRa[im] : T(0);
+        const T ub = (jv + 1 <= ny - 1) ? Ub * sRb[i] : T(0), ubm = (jv + 1 <= ny - 1) ? Ubm * sRb[im] : T(0);
         const T UU = T(0.25) * (Uam + Ua + Ubm + Ub);
         const T uu = T(0.25) * (uam + ua + ubm + ub);
         const T fsv = (T)g.fv[jv] + uu * (T)(g.cotv[jv] / g.a);
-        MV = -(C)PV * gv / (C)dyA;
+        MV = -(C)PV * gv * rdyAC;
         FV = (C)fsv * gv;
         UV = (C)UU * gv * (g.cotv[jv] / g.a);
       };
       C MVm, FVm, UVm, MVj, FVj, UVj;
-      vrow(j - 1, sPm, sP0, Um, Umm, Uj, Ujm, gVm, MVm, FVm, UVm);
-      vrow(j, sP0, sP1, Uj, Ujm, U1, U1m, gV, MVj, FVj, UVj);
-      (void)PUm0;
+      vrow(j - 1, sPm, sP0, srUm, srU0, Um, Umm, Uj, Ujm, gVm, MVm, FVm, UVm);
+      vrow(j, sP0, sP1, srU0, srU1, Uj, Ujm, U1, U1m, gV, MVj, FVj, UVj);
       // LDS rows
       sHH[i] = (T)HH;
       sAV[i] = (T)aWPj;
@@ -1177,7 +1202,6 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       if (i >= nx) continue;
       const int im = wrp(i - 1, nx), ip = wrp(i + 1, nx);
       const size_t oj = (size_t)j * row3 + (size_t)k * nx + i;
-      const T P0 = sP0[i];
       const T vRTj = sRT[i], vPHj = sPH[i];
       const C vAVj = (C)sAV[i], vADj = (C)sAD[i], vHH = (C)sHH[i];
       const C vUVm = (C)sUVm[i], vUVj = (C)sUV0[i], vFVm = (C)sFVm[i], vFVj = (C)sFV0[i];
@@ -1185,37 +1209,38 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const T PU0 = PUr(sP0, i);
       const T PV0 = T(0.5) * (sP0[i] + sP1[i]), PVm = T(0.5) * (sPm[i] + sP0[i]);
       // forward D, S, omega/p (as the forward recompute forms them)
-      const T D = (sMU[wrp(i + n - 1, nx)] - sMU[wrp(i - n, nx)]) / dxT +
-                  (svj * (PV0 * vVj[cc]) - svm * (PVm * vVm[cc])) / dySj;
+      const T D = (sMU[wrp(i + n - 1, nx)] - sMU[wrp(i - n, nx)]) * rdxT +
+                  (svj * (PV0 * vVj[cc]) - svm * (PVm * vVm[cc])) * rdySjT;
+      const T rPV0 = T(1) / PV0, rPVm = T(1) / PVm;
       const C SkC = Sj[cc];
       const T Sk = (T)SkC;
       Sj[cc] += (C)D * dsg;
       const T zon = T(0.5) * (su[i] * sDL[i] + su[im] * sDL[im]);
-      const T mer = T(0.5) * ((vVj[cc] / PV0) * (sL1[i] - sL0[i]) + (vVm[cc] / PVm) * (sL0[i] - sLm[i])) / dyA;
-      const C P2c = (C)P0 * (C)P0;
-      const T WP = (T)(((C)zon + (C)mer) - (SkC + 0.5 * (C)D * dsg) / (sg * P2c));
+      const T mer = T(0.5) * ((vVj[cc] * rPV0) * sdL0[i] + (vVm[cc] * rPVm) * sdLm[i]) * rdyAT;
+      const C rPc = (C)srP0[i], rP2c = rPc * rPc;
+      const T WP = (T)(((C)zon + (C)mer) - (SkC + 0.5 * (C)D * dsg) * rsg * rP2c);
       const C wp = (C)WP, gF = ch * (C)voF[cc], aWP = vAVj;
       const C AFE = (C)(T)((C)kap * wp * gF);
-      const C AP3 = (C)(T)((C)b * wp * gF + 2.0 * ((C)Sk + 0.5 * (C)D * dsg) / (sg * P2c * (C)P0) * aWP);
+      const C AP3 = (C)(T)((C)b * wp * gF + 2.0 * ((C)Sk + 0.5 * (C)D * dsg) * rsg * (rP2c * rPc) * aWP);
       // U point: pressure gradient seen by U row j
-      const T dphi = (sPH[wrp(i + n, nx)] - sPH[wrp(i + 1 - n, nx)]) / dxT;
+      const T dphi = (sPH[wrp(i + n, nx)] - sPH[wrp(i + 1 - n, nx)]) * rdxT;
       const T rtx = T(0.5) * (vRTj + sRT[ip]);
       const C pgf = (C)dphi + RT0 * (C)sDQ[i] + (C)rtx * (C)sDL[i];
       const C gU = ch * (C)voU[cc], gV = ch * (C)voV[cc];
       const C APU3 = (C)(T)(-pgf * gU);
       // V point: pressure gradient seen by V row j+1/2
-      const C pgfV = ((C)(vPH1[cc] - vPHj) + RT0 * (C)(sQ1[i] - sQ0[i]) +
-                      (C)(T(0.5) * (vRTj + vRT1[cc])) * (C)(sL1[i] - sL0[i])) / (C)dyA;
+      const C pgfV = ((C)(vPH1[cc] - vPHj) + RT0 * (C)sdQ0[i] +
+                      (C)(T(0.5) * (vRTj + vRT1[cc])) * (C)sdL0[i]) * rdyAC;
       const C APV3 = (C)(T)(-pgfV * gV);
       // gathers: scalar point
       const C mM = (C)vMVm[cc], mJ = (C)vMVj[cc];
-      const C aPHI = ((C)sHH[wrp(i - n, nx)] - (C)sHH[wrp(i + n - 1, nx)]) / dxC + mM - mJ;
+      const C aPHI = ((C)sHH[wrp(i - n, nx)] - (C)sHH[wrp(i + n - 1, nx)]) * rdxC + mM - mJ;
       const C aRT = 0.5 * ((C)sHH[i] * (C)sDL[i] + (C)sHH[im] * (C)sDL[im]) +
-                    0.5 * ((C)sL0[i] - (C)sLm[i]) * mM + 0.5 * ((C)sL1[i] - (C)sL0[i]) * mJ;
-      const C cvgm = (nPole ? sVG[0 * (nz + 1) + k] / nx : 0.5 * (C)vAVm[cc]) + 0.5 * vAVj;
-      const C cvgj = 0.5 * vAVj + (sPole ? sVG[1 * (nz + 1) + k] / nx : 0.5 * (C)vAV1[cc]);
+                    0.5 * (C)sdLm[i] * mM + 0.5 * (C)sdL0[i] * mJ;
+      const C cvgm = (nPole ? sVG[0 * (nz + 1) + k] * rnx : 0.5 * (C)vAVm[cc]) + 0.5 * vAVj;
+      const C cvgj = 0.5 * vAVj + (sPole ? sVG[1 * (nz + 1) + k] * rnx : 0.5 * (C)vAV1[cc]);
       const C rtym = 0.5 * ((C)vRTm[cc] + (C)vRTj), rtyj = 0.5 * ((C)vRTj + (C)vRT1[cc]);
-      const C wm = (C)(vVm[cc] / PVm) / aDy * cvgm, wj = (C)(vVj[cc] / PV0) / aDy * cvgj;
+      const C wm = (C)(vVm[cc] * rPVm) * raDy * cvgm, wj = (C)(vVj[cc] * rPV0) * raDy * cvgj;
       const C aL = (wm + rtym * mM) - (wj + rtyj * mJ);
       const C aQ = RT0 * mM - RT0 * mJ;
       // gathers: U point
@@ -1223,32 +1248,32 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const C au = (C)vAUU[cc] + 0.5 * dl * (vAVj + (C)sAV[ip]) +
                    0.25 * (vUVm + (C)sUVm[ip] + vUVj + (C)sUV0[ip]);
       const C aUd = 0.25 * (vFVm + (C)sFVm[ip] + vFVj + (C)sFV0[ip]);
-      const C u = (C)(vUj[cc] / PU0);
+      const C rPUc = (C)srU0[i];
+      const C u = (C)(vUj[cc] * srU0[i]);
       const C rtxC = 0.5 * ((C)vRTj + (C)sRT[ip]);
       const C adl = 0.5 * u * (vAVj + (C)sAV[ip]) + rtxC * vHH;
       const C adq = RT0 * vHH;
       // gathers: V point
-      const C avv = ((C)sL1[i] - (C)sL0[i]) / aDy * cvgj;
+      const C avv = (C)sdL0[i] * raDy * cvgj;
       C aVd = (C)sFU0[im] + vFUj;
       if (!sPole) aVd += (C)sFU1[im] + vFU1;
       const C avd = -0.25 * aVd;
       // divergence and velocity transposes
-      const C aMU = ((C)sAD[wrp(i - n + 1, nx)] - (C)sAD[wrp(i + n, nx)]) / dxC;
+      const C aMU = ((C)sAD[wrp(i - n + 1, nx)] - (C)sAD[wrp(i + n, nx)]) * rdxC;
       const C PUc = (C)PU0, Uc = (C)vUj[cc];
-      c.aiU[oj] = (T)((C)c.aiU[oj] + aUd + au / PUc + PUc * aMU);
-      const C aPU3 = -Uc / (PUc * PUc) * au + Uc * aMU;
-      const C tN = vADj / (C)dySj;
-      const C tS = sPole ? capD * sDs[1 * (nz + 1) + k] : (C)vAD1[cc] / dyS1C;
+      c.aiU[oj] = (T)((C)c.aiU[oj] + aUd + au * rPUc + PUc * aMU);
+      const C aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;
+      const C tN = vADj * rdySjC;
+      const C tS = sPole ? capD * sDs[1 * (nz + 1) + k] : (C)vAD1[cc] * rdyS1C;
       const C aMV = (C)svj * (tN - tS);
-      const C PVc = (C)PV0, Vc = (C)vVj[cc];
-      c.aiV[oj] = (T)((C)c.aiV[oj] + avd + avv / PVc + PVc * aMV);
-      const C aPV3 = -Vc / (PVc * PVc) * avv + Vc * aMV;
+      const C PVc = (C)PV0, Vc = (C)vVj[cc], rPVc = (C)rPV0;
+      c.aiV[oj] = (T)((C)c.aiV[oj] + avd + avv * rPVc + PVc * aMV);
+      const C aPV3 = -Vc * (rPVc * rPVc) * avv + Vc * aMV;
       // hydrostatic transpose and column sums
       const C art = aRT + clk * pre[cc] + cpk * aPHI;
       pre[cc] += aPHI;
-      const C Pc = (C)P0;
-      const C afe = AFE + (C)b / Pc * art;
-      aP[cc] += AP3 - (C)b / (Pc * Pc) * (C)vFj[cc] * art;
+      const C afe = AFE + (C)b * rPc * art;
+      aP[cc] += AP3 - (C)b * rP2c * (C)vFj[cc] * art;
       aLQ[cc] += aL + aQ;
       aDLQ[cc] += adl + adq;
       aPU[cc] += APU3 + aPU3;
@@ -1332,8 +1357,9 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
   Ctx<T> cf = c;
   cf.jr0 = 1;
-  cf.jrs = rows ? ny - 2 : 1;   // the row-fused kernel recomputes its rows; the pole kernels read rows 1, ny-1
-  hipLaunchKernelGGL((k_f1<T>), rows ? dim3(gx, 2) : gcol_int, dim3(tb), 0, s, cf);
+  cf.jrs = 1;
+  // the row-fused kernel recomputes its rows itself (and writes what the pole rows read)
+  if (!rows) hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, cf);
   hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_f1p<T>), dim3(2), dim3(256), 0, s, c);
   if (c.abU) {
@@ -1359,6 +1385,7 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     Ctx<T> cp = c;
     cp.jr0 = 0;
     cp.jrs = ny;
+    cp.parts = 1;   // scalar points of the pole rows (their sums feed the interior rows)
     hipLaunchKernelGGL((k_a12<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
                        (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
@@ -1366,6 +1393,10 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
                        (const T*)nullptr, c.s.psum + PS_AVGL * 2 * (nz + 1));
     const hipError_t e = (nx + c.blk - 1) / c.blk == 1 ? launch_aar<T, 1>(c, s) : launch_aar<T, 2>(c, s);
     if (e != hipSuccess) return e;
+    Ctx<T> cv = c;   // V row 1/2: reads phi' and R T' of row 1, written by the row-fused kernel
+    cv.parts = 4;
+    hipLaunchKernelGGL((k_a12<T>), dim3(gx, 1), dim3(tb), 0, s, cv);
+    cp.parts = 7;
     hipLaunchKernelGGL((k_a3t1<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
     hipLaunchKernelGGL((k_a4<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
   } else {
