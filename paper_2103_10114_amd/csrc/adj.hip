@@ -161,8 +161,10 @@ __global__ void k_f2d(Ctx<T> c) {
 template <typename T>
 __global__ void k_f1(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int tx, k0, jy;
+  xcd_tile3((int)gridDim.x, 1, (int)gridDim.y, tx, k0, jy);
+  const int j = c.jr0 + c.jrs * jy;
+  const int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, nz = g.nz;
   const T b = (T)g.b;
@@ -512,8 +514,9 @@ __device__ __forceinline__ void a3_point(const Ctx<T>& c, int j, int k, int i, A
 template <typename T>
 __global__ void k_uv(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.z, k = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int tx, k, j;
+  xcd_tile3((int)gridDim.x, g.nz, g.ny + 1, tx, k, j);
+  const int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const size_t id = i3<T>(g, j, k, i);
   T u = T(0);
@@ -525,8 +528,9 @@ __global__ void k_uv(Ctx<T> c) {
 template <typename T>
 __global__ void k_l1(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.z, k = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int tx, k, j;
+  xcd_tile3((int)gridDim.x, g.nz, g.ny + 1, tx, k, j);
+  const int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const C ch = c.ch;
@@ -803,8 +807,9 @@ __global__ void k_a4(Ctx<T> c) {
 template <typename T>
 __global__ void k_l3(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.y;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int tx, k0, j;
+  xcd_tile3((int)gridDim.x, 1, (int)gridDim.y, tx, k0, j);
+  int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const double* sD = c.s.psum + PS_AD * 2 * (nz + 1);

@@ -120,4 +120,19 @@ __device__ __forceinline__ int xcd_row(int b, int nrows) {
   return start + slot;
 }
 
+// XCD-aware order for a (column tile, level, row) grid launched as dim3(gx, nz, nrows): the
+// linear block index goes round-robin over the XCDs; each XCD gets a contiguous band of the
+// (row, level, tile) tuples, row slowest, so that the rows a point reads around it (j-1, j+1)
+// are mostly in the same L2.
+__device__ __forceinline__ void xcd_tile3(int gx, int nz, int nrows, int& x, int& k, int& j) {
+  const int b = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+  const int total = gx * nz * nrows;
+  const int xc = b & 7, slot = b >> 3;
+  const int q = total >> 3, rem = total & 7;
+  const int tup = xc * q + (xc < rem ? xc : rem) + slot;
+  x = tup % gx;
+  k = (tup / gx) % nz;
+  j = tup / (gx * nz);
+}
+
 }  // namespace dyc
