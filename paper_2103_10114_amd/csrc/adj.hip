@@ -982,6 +982,10 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   const T rdxT = T(1) / dxT, rdySjT = T(1) / dySj, rdyAT = T(1) / dyA;
   const C rdxC = 1.0 / dxC, rdySjC = 1.0 / (C)dySj, rdyS1C = 1.0 / dyS1C, rdyAC = 1.0 / (C)dyA, raDy = 1.0 / aDy;
   const C rnx = 1.0 / (C)nx;
+  // per-point transposes run in the field precision (the sums below stay FP64)
+  using A = T;
+  const A chA = (A)ch, RT0A = (A)RT0, rdxA = (A)rdxC, rdySjA = (A)rdySjC, rdyS1A = (A)rdyS1C;
+  const A rdyAA = (A)rdyAC, raDyA = (A)raDy, cotjA = (A)cotjC;
   const size_t row3 = (size_t)nz * nx;
   (void)dySm;
 
@@ -1107,53 +1111,53 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       voF[cc] = qFj[ui];
       voU[cc] = qUj[ui];
       voV[cc] = qVj[ui];
-      const C gF = ch * (C)voF[cc];
-      const C gU = ch * (C)voU[cc];
-      const C gV = ch * (C)voV[cc];
-      const C gVm = ch * (C)qVm[ui];
-      const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * gF;
-      C aWPm = 0, aWP1 = 0;
-      if (!nPole) aWPm = ((C)(b * Pm) + (C)(kap * Fm)) * (ch * (C)qFm[ui]);
+      const A gF = chA * (A)voF[cc];
+      const A gU = chA * (A)voU[cc];
+      const A gV = chA * (A)voV[cc];
+      const A gVm = chA * (A)qVm[ui];
+      const A aWPj = ((A)(b * P0) + (A)(kap * Fj)) * gF;
+      A aWPm = 0, aWP1 = 0;
+      if (!nPole) aWPm = ((A)(b * Pm) + (A)(kap * Fm)) * (chA * (A)qFm[ui]);
       C AD1 = 0;
       if (!sPole) {
-        aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)qF1[ui]);
+        aWP1 = ((A)(b * P1) + (A)(kap * F1)) * (chA * (A)qF1[ui]);
         const C rP1 = (C)srP1[i];
-        const C aSK1 = -aWP1 * rsg * (rP1 * rP1);
+        const C aSK1 = -(C)aWP1 * rsg * (rP1 * rP1);
         As1[cc] -= aSK1;
         const C aPi1 = -g.p0 * ch * (C)c.aoP[(size_t)(j + 1) * nx + i];
         AD1 = 0.5 * dsg * aSK1 + dsg * (aPi1 + As1[cc]);
       }
       const C rP0 = (C)srP0[i];
-      const C aSKj = -aWPj * rsg * (rP0 * rP0);
+      const C aSKj = -(C)aWPj * rsg * (rP0 * rP0);
       Asj[cc] -= aSKj;
       const C aPij = -g.p0 * ch * (C)c.aoP[(size_t)j * nx + i];
       const C ADj = 0.5 * dsg * aSKj + dsg * (aPij + Asj[cc]);
       // U row j
       const T VV = T(0.25) * (Vj + Vjp + Vm + Vmp);
       const T fs = fj + uj * cotj;
-      const C HH = -(C)PU0 * gU;
-      const C FUj = (C)fs * gU;
-      const C AUU = -(C)VV * cotjC * gU;
+      const A HH = -(A)PU0 * gU;
+      const A FUj = (A)fs * gU;
+      const A AUU = -(A)VV * cotjA * gU;
       // U row j+1 (Coriolis read of V row j+1/2)
-      C FU1 = 0;
+      A FU1 = 0;
       if (!sPole) {
         const T fs1 = f1 + (U1 * srU1[i]) * cot1;
-        FU1 = (C)fs1 * (ch * (C)qU1[ui]);
+        FU1 = (A)fs1 * (chA * (A)qU1[ui]);
       }
       // V rows j-1/2 (jv = j-1) and j+1/2 (jv = j)
       auto vrow = [&](int jv, const T* sPa, const T* sPb, const T* sRa, const T* sRb, T Ua, T Uam, T Ub, T Ubm,
-                      C gv, C& MV, C& FV, C& UV) {
+                      A gv, A& MV, A& FV, A& UV) {
         const T PV = T(0.5) * (sPa[i] + sPb[i]);
         const T ua = (jv >= 1) ? Ua * sRa[i] : T(0), uam = (jv >= 1) ? Uam * sRa[im] : T(0);
         const T ub = (jv + 1 <= ny - 1) ? Ub * sRb[i] : T(0), ubm = (jv + 1 <= ny - 1) ? Ubm * sRb[im] : T(0);
         const T UU = T(0.25) * (Uam + Ua + Ubm + Ub);
         const T uu = T(0.25) * (uam + ua + ubm + ub);
         const T fsv = (T)g.fv[jv] + uu * (T)(g.cotv[jv] / g.a);
-        MV = -(C)PV * gv * rdyAC;
-        FV = (C)fsv * gv;
-        UV = (C)UU * gv * (g.cotv[jv] / g.a);
+        MV = -(A)PV * gv * rdyAA;
+        FV = (A)fsv * gv;
+        UV = (A)UU * gv * (A)(g.cotv[jv] / g.a);
       };
-      C MVm, FVm, UVm, MVj, FVj, UVj;
+      A MVm, FVm, UVm, MVj, FVj, UVj;
       vrow(j - 1, sPm, sP0, srUm, srU0, Um, Umm, Uj, Ujm, gVm, MVm, FVm, UVm);
       vrow(j, sP0, sP1, srU0, srU1, Uj, Ujm, U1, U1m, gV, MVj, FVj, UVj);
       // LDS rows
@@ -1208,9 +1212,9 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const int im = wrp(i - 1, nx), ip = wrp(i + 1, nx);
       const size_t oj = (size_t)j * row3 + (size_t)k * nx + i;
       const T vRTj = sRT[i], vPHj = sPH[i];
-      const C vAVj = (C)sAV[i], vADj = (C)sAD[i], vHH = (C)sHH[i];
-      const C vUVm = (C)sUVm[i], vUVj = (C)sUV0[i], vFVm = (C)sFVm[i], vFVj = (C)sFV0[i];
-      const C vFUj = (C)sFU0[i], vFU1 = (C)sFU1[i];
+      const A vAVj = (A)sAV[i], vADj = (A)sAD[i], vHH = (A)sHH[i];
+      const A vUVm = (A)sUVm[i], vUVj = (A)sUV0[i], vFVm = (A)sFVm[i], vFVj = (A)sFV0[i];
+      const A vFUj = (A)sFU0[i], vFU1 = (A)sFU1[i];
       const T PU0 = PUr(sP0, i);
       const T PV0 = T(0.5) * (sP0[i] + sP1[i]), PVm = T(0.5) * (sPm[i] + sP0[i]);
       // forward D, S, omega/p (as the forward recompute forms them)
@@ -1224,65 +1228,66 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const T mer = T(0.5) * ((vVj[cc] * rPV0) * sdL0[i] + (vVm[cc] * rPVm) * sdLm[i]) * rdyAT;
       const C rPc = (C)srP0[i], rP2c = rPc * rPc;
       const T WP = (T)(((C)zon + (C)mer) - (SkC + 0.5 * (C)D * dsg) * rsg * rP2c);
-      const C wp = (C)WP, gF = ch * (C)voF[cc], aWP = vAVj;
-      const C AFE = (C)(T)((C)kap * wp * gF);
-      const C AP3 = (C)(T)((C)b * wp * gF + 2.0 * ((C)Sk + 0.5 * (C)D * dsg) * rsg * (rP2c * rPc) * aWP);
+      const A wp = (A)WP, gF = chA * (A)voF[cc], aWP = vAVj;
+      const A rPA = (A)srP0[i], rP2A = rPA * rPA;
+      const A AFE = (A)kap * wp * gF;
+      const A AP3 = (A)b * wp * gF + A(2) * ((A)Sk + A(0.5) * (A)D * (A)dsg) * (A)rsg * (rP2A * rPA) * aWP;
       // U point: pressure gradient seen by U row j
       const T dphi = (sPH[wrp(i + n, nx)] - sPH[wrp(i + 1 - n, nx)]) * rdxT;
       const T rtx = T(0.5) * (vRTj + sRT[ip]);
-      const C pgf = (C)dphi + RT0 * (C)sDQ[i] + (C)rtx * (C)sDL[i];
-      const C gU = ch * (C)voU[cc], gV = ch * (C)voV[cc];
-      const C APU3 = (C)(T)(-pgf * gU);
+      const A pgf = (A)dphi + RT0A * (A)sDQ[i] + (A)rtx * (A)sDL[i];
+      const A gU = chA * (A)voU[cc], gV = chA * (A)voV[cc];
+      const A APU3 = -pgf * gU;
       // V point: pressure gradient seen by V row j+1/2
-      const C pgfV = ((C)(vPH1[cc] - vPHj) + RT0 * (C)sdQ0[i] +
-                      (C)(T(0.5) * (vRTj + vRT1[cc])) * (C)sdL0[i]) * rdyAC;
-      const C APV3 = (C)(T)(-pgfV * gV);
+      const A pgfV = ((A)(vPH1[cc] - vPHj) + RT0A * (A)sdQ0[i] +
+                      (A)(T(0.5) * (vRTj + vRT1[cc])) * (A)sdL0[i]) * rdyAA;
+      const A APV3 = -pgfV * gV;
       // gathers: scalar point
-      const C mM = (C)vMVm[cc], mJ = (C)vMVj[cc];
-      const C aPHI = ((C)sHH[wrp(i - n, nx)] - (C)sHH[wrp(i + n - 1, nx)]) * rdxC + mM - mJ;
-      const C aRT = 0.5 * ((C)sHH[i] * (C)sDL[i] + (C)sHH[im] * (C)sDL[im]) +
-                    0.5 * (C)sdLm[i] * mM + 0.5 * (C)sdL0[i] * mJ;
-      const C cvgm = (nPole ? sVG[0 * (nz + 1) + k] * rnx : 0.5 * (C)vAVm[cc]) + 0.5 * vAVj;
-      const C cvgj = 0.5 * vAVj + (sPole ? sVG[1 * (nz + 1) + k] * rnx : 0.5 * (C)vAV1[cc]);
-      const C rtym = 0.5 * ((C)vRTm[cc] + (C)vRTj), rtyj = 0.5 * ((C)vRTj + (C)vRT1[cc]);
-      const C wm = (C)(vVm[cc] * rPVm) * raDy * cvgm, wj = (C)(vVj[cc] * rPV0) * raDy * cvgj;
-      const C aL = (wm + rtym * mM) - (wj + rtyj * mJ);
-      const C aQ = RT0 * mM - RT0 * mJ;
+      const A mM = (A)vMVm[cc], mJ = (A)vMVj[cc];
+      const A aPHI = ((A)sHH[wrp(i - n, nx)] - (A)sHH[wrp(i + n - 1, nx)]) * rdxA + mM - mJ;
+      const A aRT = A(0.5) * ((A)sHH[i] * (A)sDL[i] + (A)sHH[im] * (A)sDL[im]) +
+                    A(0.5) * (A)sdLm[i] * mM + A(0.5) * (A)sdL0[i] * mJ;
+      const A cvgm = (nPole ? (A)(sVG[0 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAVm[cc]) + A(0.5) * vAVj;
+      const A cvgj = A(0.5) * vAVj + (sPole ? (A)(sVG[1 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAV1[cc]);
+      const A rtym = A(0.5) * ((A)vRTm[cc] + (A)vRTj), rtyj = A(0.5) * ((A)vRTj + (A)vRT1[cc]);
+      const A wm = (A)(vVm[cc] * rPVm) * raDyA * cvgm, wj = (A)(vVj[cc] * rPV0) * raDyA * cvgj;
+      const A aL = (wm + rtym * mM) - (wj + rtyj * mJ);
+      const A aQ = RT0A * mM - RT0A * mJ;
       // gathers: U point
-      const C dl = (C)sDL[i];
-      const C au = (C)vAUU[cc] + 0.5 * dl * (vAVj + (C)sAV[ip]) +
-                   0.25 * (vUVm + (C)sUVm[ip] + vUVj + (C)sUV0[ip]);
-      const C aUd = 0.25 * (vFVm + (C)sFVm[ip] + vFVj + (C)sFV0[ip]);
-      const C rPUc = (C)srU0[i];
-      const C u = (C)(vUj[cc] * srU0[i]);
-      const C rtxC = 0.5 * ((C)vRTj + (C)sRT[ip]);
-      const C adl = 0.5 * u * (vAVj + (C)sAV[ip]) + rtxC * vHH;
-      const C adq = RT0 * vHH;
+      const A dl = (A)sDL[i];
+      const A au = (A)vAUU[cc] + A(0.5) * dl * (vAVj + (A)sAV[ip]) +
+                   A(0.25) * (vUVm + (A)sUVm[ip] + vUVj + (A)sUV0[ip]);
+      const A aUd = A(0.25) * (vFVm + (A)sFVm[ip] + vFVj + (A)sFV0[ip]);
+      const A rPUc = (A)srU0[i];
+      const A u = (A)(vUj[cc] * srU0[i]);
+      const A rtxA = A(0.5) * ((A)vRTj + (A)sRT[ip]);
+      const A adl = A(0.5) * u * (vAVj + (A)sAV[ip]) + rtxA * vHH;
+      const A adq = RT0A * vHH;
       // gathers: V point
-      const C avv = (C)sdL0[i] * raDy * cvgj;
-      C aVd = (C)sFU0[im] + vFUj;
-      if (!sPole) aVd += (C)sFU1[im] + vFU1;
-      const C avd = -0.25 * aVd;
+      const A avv = (A)sdL0[i] * raDyA * cvgj;
+      A aVd = (A)sFU0[im] + vFUj;
+      if (!sPole) aVd += (A)sFU1[im] + vFU1;
+      const A avd = A(-0.25) * aVd;
       // divergence and velocity transposes
-      const C aMU = ((C)sAD[wrp(i - n + 1, nx)] - (C)sAD[wrp(i + n, nx)]) * rdxC;
-      const C PUc = (C)PU0, Uc = (C)vUj[cc];
-      c.aiU[oj] = (T)((C)c.aiU[oj] + aUd + au * rPUc + PUc * aMU);
-      const C aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;
-      const C tN = vADj * rdySjC;
-      const C tS = sPole ? capD * sDs[1 * (nz + 1) + k] : (C)vAD1[cc] * rdyS1C;
-      const C aMV = (C)svj * (tN - tS);
-      const C PVc = (C)PV0, Vc = (C)vVj[cc], rPVc = (C)rPV0;
-      c.aiV[oj] = (T)((C)c.aiV[oj] + avd + avv * rPVc + PVc * aMV);
-      const C aPV3 = -Vc * (rPVc * rPVc) * avv + Vc * aMV;
+      const A aMU = ((A)sAD[wrp(i - n + 1, nx)] - (A)sAD[wrp(i + n, nx)]) * rdxA;
+      const A PUc = (A)PU0, Uc = (A)vUj[cc];
+      c.aiU[oj] = (T)((C)c.aiU[oj] + (C)(aUd + au * rPUc + PUc * aMU));
+      const A aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;
+      const A tN = vADj * rdySjA;
+      const A tS = sPole ? (A)(capD * sDs[1 * (nz + 1) + k]) : (A)vAD1[cc] * rdyS1A;
+      const A aMV = (A)svj * (tN - tS);
+      const A PVc = (A)PV0, Vc = (A)vVj[cc], rPVc = (A)rPV0;
+      c.aiV[oj] = (T)((C)c.aiV[oj] + (C)(avd + avv * rPVc + PVc * aMV));
+      const A aPV3 = -Vc * (rPVc * rPVc) * avv + Vc * aMV;
       // hydrostatic transpose and column sums
-      const C art = aRT + clk * pre[cc] + cpk * aPHI;
-      pre[cc] += aPHI;
-      const C afe = AFE + (C)b * rPc * art;
-      aP[cc] += AP3 - (C)b * rP2c * (C)vFj[cc] * art;
-      aLQ[cc] += aL + aQ;
-      aDLQ[cc] += adl + adq;
-      aPU[cc] += APU3 + aPU3;
-      aPV[cc] += APV3 + aPV3;
+      const C art = (C)aRT + clk * pre[cc] + cpk * (C)aPHI;
+      pre[cc] += (C)aPHI;
+      const C afe = (C)AFE + (C)b * rPc * art;
+      aP[cc] += (C)AP3 - (C)b * rP2c * (C)vFj[cc] * art;
+      aLQ[cc] += (C)(aL + aQ);
+      aDLQ[cc] += (C)(adl + adq);
+      aPU[cc] += (C)(APU3 + aPU3);
+      aPV[cc] += (C)(APV3 + aPV3);
       c.aiF[oj] = (T)((C)c.aiF[oj] + afe);
     }
     __syncthreads();
