@@ -533,35 +533,38 @@ __global__ void k_l1(Ctx<T> c) {
   const int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const C ch = c.ch;
+  // per-point arithmetic in the field precision (every output is stored in it)
+  using A = T;
+  const A ch = (A)c.ch;
   const double* sF = c.s.psum + PS_AOF * 2 * (nz + 1);
-  const C AN = -ch * sF[0 * (nz + 1) + k], AS = -ch * sF[1 * (nz + 1) + k];
-  const C cc = g.a * g.dlam / (2.0 * g.acap);
-  auto amF = [&](int jr, int kk, int ii) -> C { return -ch * (C)c.aoF[i3<T>(g, jr, kk, ii)]; };
-  auto amU = [&](int jr, int kk, int ii) -> C { return -ch * (C)c.aoU[i3<T>(g, jr, kk, ii)]; };
-  auto amV = [&](int jv, int kk, int ii) -> C { return -ch * (C)c.aoV[i3<T>(g, jv, kk, ii)]; };
+  const A AN = (A)(-c.ch * sF[0 * (nz + 1) + k]), AS = (A)(-c.ch * sF[1 * (nz + 1) + k]);
+  const A cc = (A)(g.a * g.dlam / (2.0 * g.acap));
+  auto amF = [&](int jr, int kk, int ii) -> A { return -ch * (A)c.aoF[i3<T>(g, jr, kk, ii)]; };
+  auto amU = [&](int jr, int kk, int ii) -> A { return -ch * (A)c.aoU[i3<T>(g, jr, kk, ii)]; };
+  auto amV = [&](int jv, int kk, int ii) -> A { return -ch * (A)c.aoV[i3<T>(g, jv, kk, ii)]; };
   auto interior = [&](int jr) { return jr >= 1 && jr <= ny - 1; };
-  auto sd = [&](int jr, int h, int ii) -> C { return (C)c.s.SD[ih<T>(g, jr, h, ii)]; };
+  auto sd = [&](int jr, int h, int ii) -> A { return (A)c.s.SD[ih<T>(g, jr, h, ii)]; };
   // the forward's difference factors (rounded to the field precision)
-  auto rdx2 = [&](int jr) -> C { return 0.5 * c.f.rdx[jr]; };
-  auto rdy2 = [&](int jr) -> C { return 0.5 * c.f.rdy[jr]; };
-  auto rdxv2 = [&](int jv) -> C { return c.f.rdxv2[jv]; };
-  auto rdyv2 = [&](int jv) -> C { return c.f.rdyv2[jv]; };
-  auto uA = [&](int jr, int q) -> C { return (jr >= 1 && jr < ny) ? (C)c.s.UA[i3<T>(g, jr, k, q)] : 0.0; };
-  auto vA = [&](int jv, int kk, int ii) -> C { return (C)c.s.VT[i3<T>(g, jv, kk, ii)]; };
-  auto ub = [&](int jr, int q) -> C {   // u averaged to integer point q of U row jr
-    return 0.5 * (uA(jr, wrp(q - 1, nx)) + uA(jr, q));
+  auto rdx2 = [&](int jr) -> A { return (A)(0.5 * c.f.rdx[jr]); };
+  auto rdy2 = [&](int jr) -> A { return (A)(0.5 * c.f.rdy[jr]); };
+  auto rdxv2 = [&](int jv) -> A { return (A)c.f.rdxv2[jv]; };
+  auto rdyv2 = [&](int jv) -> A { return (A)c.f.rdyv2[jv]; };
+  auto r2d = [&](int kk) -> A { return (A)c.f.r2d[kk]; };
+  auto uA = [&](int jr, int q) -> A { return (jr >= 1 && jr < ny) ? (A)c.s.UA[i3<T>(g, jr, k, q)] : A(0); };
+  auto vA = [&](int jv, int kk, int ii) -> A { return (A)c.s.VT[i3<T>(g, jv, kk, ii)]; };
+  auto ub = [&](int jr, int q) -> A {   // u averaged to integer point q of U row jr
+    return A(0.5) * (uA(jr, wrp(q - 1, nx)) + uA(jr, q));
   };
-  auto uv = [&](int jv, int q) -> C { return 0.5 * (uA(jv, q) + uA(jv + 1, q)); };
-  auto vts = [&](int js, int kk, int ii) -> C {   // v sin(theta) on scalar row js
-    if (js <= 0 || js >= ny) return 0.0;
-    return 0.5 * (vA(js - 1, kk, ii) + vA(js, kk, ii));
+  auto uv = [&](int jv, int q) -> A { return A(0.5) * (uA(jv, q) + uA(jv + 1, q)); };
+  auto vts = [&](int js, int kk, int ii) -> A {   // v sin(theta) on scalar row js
+    if (js <= 0 || js >= ny) return A(0);
+    return A(0.5) * (vA(js - 1, kk, ii) + vA(js, kk, ii));
   };
   const size_t id = i3<T>(g, j, k, i);
 
   // ---- scalar point: adjoint of Phi (pole-read copies included)
   {
-    C a = 0;
+    A a = 0;
     if (interior(j)) {
       const int M = g.M[j], n = (M + 1) / 2;
       const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
@@ -571,48 +574,48 @@ __global__ void k_l1(Ctx<T> c) {
     if (interior(j + 1)) a -= amF(j + 1, k, i) * vA(j, k, i) * rdy2(j + 1);
     if (j == 1) a += cc * vA(0, k, i) * AN;
     if (j == ny - 1) a -= cc * vA(ny - 1, k, i) * AS;
-    if (k >= 1) a += amF(j, k - 1, i) * sd(j, k, i) * c.f.r2d[k - 1];
-    if (k + 1 < nz) a -= amF(j, k + 1, i) * sd(j, k + 1, i) * c.f.r2d[k + 1];
+    if (k >= 1) a += amF(j, k - 1, i) * sd(j, k, i) * r2d(k - 1);
+    if (k + 1 < nz) a -= amF(j, k + 1, i) * sd(j, k + 1, i) * r2d(k + 1);
     c.s.AFE[id] = (T)a;
   }
   // ---- U point
   if (interior(j)) {
     const int M = g.M[j], n = (M + 1) / 2;
     // adjoint of u (U point i+1/2)
-    C au = 0;
+    A au = 0;
     {
       const int qa = wrp(i - n + 1, nx), qb = wrp(i + n, nx);
-      au += (amF(j, k, qa) * (C)Fe(c, j, k, wrp(qa + M, nx)) - amF(j, k, qb) * (C)Fe(c, j, k, wrp(qb - M, nx))) * rdx2(j);
-      auto aub = [&](int q) -> C {
+      au += (amF(j, k, qa) * (A)Fe(c, j, k, wrp(qa + M, nx)) - amF(j, k, qb) * (A)Fe(c, j, k, wrp(qb - M, nx))) * rdx2(j);
+      auto aub = [&](int q) -> A {
         const int r1 = wrp(q - n, nx), r2 = wrp(q - 1 + n, nx);
-        return (amU(j, k, r1) * (C)Ue(c, j, k, wrp(r1 + M, nx)) - amU(j, k, r2) * (C)Ue(c, j, k, wrp(r2 - M, nx))) * rdx2(j);
+        return (amU(j, k, r1) * (A)Ue(c, j, k, wrp(r1 + M, nx)) - amU(j, k, r2) * (A)Ue(c, j, k, wrp(r2 - M, nx))) * rdx2(j);
       };
-      au += 0.5 * (aub(i) + aub(wrp(i + 1, nx)));
+      au += A(0.5) * (aub(i) + aub(wrp(i + 1, nx)));
       for (int jv : {j - 1, j}) {
         const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
         const int r1 = wrp(i - nv + 1, nx), r2 = wrp(i + nv, nx);
-        const C auv = (amV(jv, k, r1) * (C)Ve(c, jv, k, wrp(r1 + Mv, nx)) -
-                       amV(jv, k, r2) * (C)Ve(c, jv, k, wrp(r2 - Mv, nx))) * rdxv2(jv);
-        au += 0.5 * auv;
+        const A auv = (amV(jv, k, r1) * (A)Ve(c, jv, k, wrp(r1 + Mv, nx)) -
+                       amV(jv, k, r2) * (A)Ve(c, jv, k, wrp(r2 - Mv, nx))) * rdxv2(jv);
+        au += A(0.5) * auv;
       }
     }
     c.s.AUU[id] = (T)au;
     // direct adjoint of U
-    C aU = 0;
+    A aU = 0;
     {
       const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
       aU += (amU(j, k, pm) * ub(j, wrp(pm + n, nx)) - amU(j, k, pp) * ub(j, wrp(pp + 1 - n, nx))) * rdx2(j);
       const int ip1 = wrp(i + 1, nx);
       if (interior(j - 1)) {
-        const C vtu = 0.5 * (vA(j - 1, k, i) + vA(j - 1, k, ip1));
+        const A vtu = A(0.5) * (vA(j - 1, k, i) + vA(j - 1, k, ip1));
         aU += amU(j - 1, k, i) * vtu * rdy2(j - 1);
       }
       if (interior(j + 1)) {
-        const C vtu = 0.5 * (vA(j, k, i) + vA(j, k, ip1));
+        const A vtu = A(0.5) * (vA(j, k, i) + vA(j, k, ip1));
         aU -= amU(j + 1, k, i) * vtu * rdy2(j + 1);
       }
-      if (k >= 1) aU += amU(j, k - 1, i) * 0.5 * (sd(j, k, i) + sd(j, k, ip1)) * c.f.r2d[k - 1];
-      if (k + 1 < nz) aU -= amU(j, k + 1, i) * 0.5 * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) * c.f.r2d[k + 1];
+      if (k >= 1) aU += amU(j, k - 1, i) * A(0.5) * (sd(j, k, i) + sd(j, k, ip1)) * r2d(k - 1);
+      if (k + 1 < nz) aU -= amU(j, k + 1, i) * A(0.5) * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) * r2d(k + 1);
     }
     c.s.AUD[id] = (T)aU;
   }
@@ -620,56 +623,56 @@ __global__ void k_l1(Ctx<T> c) {
   if (j < ny) {
     const int jv = j;
     const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
-    C aV = 0;
+    A aV = 0;
     {
       const int pm = wrp(i - Mv, nx), pp = wrp(i + Mv, nx);
       aV += (amV(jv, k, pm) * uv(jv, wrp(pm + nv - 1, nx)) - amV(jv, k, pp) * uv(jv, wrp(pp - nv, nx))) * rdxv2(jv);
       if (jv >= 1) aV += amV(jv - 1, k, i) * vts(jv, k, i) * rdyv2(jv - 1);
       if (jv + 1 <= ny - 1) aV -= amV(jv + 1, k, i) * vts(jv + 1, k, i) * rdyv2(jv + 1);
-      if (k >= 1) aV += amV(jv, k - 1, i) * 0.5 * (sd(jv, k, i) + sd(jv + 1, k, i)) * c.f.r2d[k - 1];
+      if (k >= 1) aV += amV(jv, k - 1, i) * A(0.5) * (sd(jv, k, i) + sd(jv + 1, k, i)) * r2d(k - 1);
       if (k + 1 < nz)
-        aV -= amV(jv, k + 1, i) * 0.5 * (sd(jv, k + 1, i) + sd(jv + 1, k + 1, i)) * c.f.r2d[k + 1];
+        aV -= amV(jv, k + 1, i) * A(0.5) * (sd(jv, k + 1, i) + sd(jv + 1, k + 1, i)) * r2d(k + 1);
     }
     c.s.AVD[id] = (T)aV;
     // adjoint of v sin(theta) on this V row
-    C avt = 0;
-    if (interior(jv)) avt += amF(jv, k, i) * (C)Fe(c, jv + 1, k, i) * rdy2(jv);
-    if (interior(jv + 1)) avt -= amF(jv + 1, k, i) * (C)Fe(c, jv, k, i) * rdy2(jv + 1);
-    if (jv == 0) avt += cc * (C)Fe(c, 1, k, i) * AN;
-    if (jv == ny - 1) avt -= cc * (C)Fe(c, ny - 1, k, i) * AS;
-    auto avtu = [&](int p) -> C {
-      C r = 0;
-      if (interior(jv)) r += amU(jv, k, p) * (C)Ue(c, jv + 1, k, p) * rdy2(jv);
-      if (interior(jv + 1)) r -= amU(jv + 1, k, p) * (C)Ue(c, jv, k, p) * rdy2(jv + 1);
+    A avt = 0;
+    if (interior(jv)) avt += amF(jv, k, i) * (A)Fe(c, jv + 1, k, i) * rdy2(jv);
+    if (interior(jv + 1)) avt -= amF(jv + 1, k, i) * (A)Fe(c, jv, k, i) * rdy2(jv + 1);
+    if (jv == 0) avt += cc * (A)Fe(c, 1, k, i) * AN;
+    if (jv == ny - 1) avt -= cc * (A)Fe(c, ny - 1, k, i) * AS;
+    auto avtu = [&](int p) -> A {
+      A r = 0;
+      if (interior(jv)) r += amU(jv, k, p) * (A)Ue(c, jv + 1, k, p) * rdy2(jv);
+      if (interior(jv + 1)) r -= amU(jv + 1, k, p) * (A)Ue(c, jv, k, p) * rdy2(jv + 1);
       return r;
     };
-    avt += 0.5 * (avtu(i) + avtu(wrp(i - 1, nx)));
-    auto avts = [&](int js) -> C {
-      if (js <= 0 || js >= ny) return 0.0;
-      return amV(js - 1, k, i) * (C)Ve(c, js, k, i) * rdyv2(js - 1) - amV(js, k, i) * (C)Ve(c, js - 1, k, i) * rdyv2(js);
+    avt += A(0.5) * (avtu(i) + avtu(wrp(i - 1, nx)));
+    auto avts = [&](int js) -> A {
+      if (js <= 0 || js >= ny) return A(0);
+      return amV(js - 1, k, i) * (A)Ve(c, js, k, i) * rdyv2(js - 1) - amV(js, k, i) * (A)Ve(c, js - 1, k, i) * rdyv2(js);
     };
-    avt += 0.5 * (avts(jv) + avts(jv + 1));
-    c.s.AVV[id] = (T)(avt * g.sv[jv]);
+    avt += A(0.5) * (avts(jv) + avts(jv + 1));
+    c.s.AVV[id] = (T)(avt * (A)g.sv[jv]);
   }
   // ---- half level h = k (1..nz-1): adjoint of sigma-dot of scalar row j
   if (k >= 1) {
     const int h = k;
-    C a = 0;
-    a += amF(j, h - 1, i) * (C)Fe(c, j, h, i) * c.f.r2d[h - 1] -
-         amF(j, h, i) * (C)Fe(c, j, h - 1, i) * c.f.r2d[h];
+    A a = 0;
+    a += amF(j, h - 1, i) * (A)Fe(c, j, h, i) * r2d(h - 1) -
+         amF(j, h, i) * (A)Fe(c, j, h - 1, i) * r2d(h);
     if (interior(j)) {
-      auto asdu = [&](int p) -> C {
-        return amU(j, h - 1, p) * (C)Ue(c, j, h, p) * c.f.r2d[h - 1] -
-               amU(j, h, p) * (C)Ue(c, j, h - 1, p) * c.f.r2d[h];
+      auto asdu = [&](int p) -> A {
+        return amU(j, h - 1, p) * (A)Ue(c, j, h, p) * r2d(h - 1) -
+               amU(j, h, p) * (A)Ue(c, j, h - 1, p) * r2d(h);
       };
-      a += 0.5 * (asdu(i) + asdu(wrp(i - 1, nx)));
+      a += A(0.5) * (asdu(i) + asdu(wrp(i - 1, nx)));
     }
-    auto asdv = [&](int jv) -> C {
-      return amV(jv, h - 1, i) * (C)Ve(c, jv, h, i) * c.f.r2d[h - 1] -
-             amV(jv, h, i) * (C)Ve(c, jv, h - 1, i) * c.f.r2d[h];
+    auto asdv = [&](int jv) -> A {
+      return amV(jv, h - 1, i) * (A)Ve(c, jv, h, i) * r2d(h - 1) -
+             amV(jv, h, i) * (A)Ve(c, jv, h - 1, i) * r2d(h);
     };
-    if (j >= 1) a += 0.5 * asdv(j - 1);
-    if (j <= ny - 1) a += 0.5 * asdv(j);
+    if (j >= 1) a += A(0.5) * asdv(j - 1);
+    if (j <= ny - 1) a += A(0.5) * asdv(j);
     c.s.ASD[ih<T>(g, j, h, i)] = (T)a;
   }
 }
