@@ -1085,6 +1085,21 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
     // (the owned columns' entries of the LDS rows are read back in phase 2)
     T vRTm[NI], vRT1[NI], vPH1[NI], vFj[NI], vUj[NI], vVj[NI], vVm[NI];
     T vAVm[NI], vAV1[NI], vAD1[NI], vMVm[NI], vMVj[NI], voF[NI], voU[NI], voV[NI], vAUU[NI];
+    // the accumulators the second phase updates, fetched now
+    T aiU0[NI], aiV0[NI], aiF0[NI];
+    {
+      T* gaU = uni(c.aiU + ((size_t)j * row3 + lvl));
+      T* gaV = uni(c.aiV + ((size_t)j * row3 + lvl));
+      T* gaF = uni(c.aiF + ((size_t)j * row3 + lvl));
+#pragma unroll
+      for (int cc = 0; cc < NI; ++cc) {
+        const int i0 = t + cc * B;
+        const unsigned ui = (unsigned)(i0 < nx ? i0 : 0);
+        aiU0[cc] = gaU[ui];
+        aiV0[cc] = gaV[ui];
+        aiF0[cc] = gaF[ui];
+      }
+    }
     // ---- phase 1: per-point quantities of the owned columns
 #pragma unroll
     for (int cc = 0; cc < NI; ++cc) {
@@ -1197,11 +1212,12 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
         c.s.MV[oj + i] = (T)MVj;
         c.s.RT[oj + i] = RTj;
       }
-      // base transpose of the interior row (identity)
+      // base transpose of the interior row (identity); where the base and input adjoints are one
+      // buffer, into the accumulator values already fetched for the second phase
       if (c.abU) {
-        c.abF[oj + i] += c.aoF[oj + i];
-        c.abU[oj + i] += c.aoU[oj + i];
-        c.abV[oj + i] += c.aoV[oj + i];
+        if (c.abF == c.aiF) aiF0[cc] += voF[cc]; else c.abF[oj + i] += voF[cc];
+        if (c.abU == c.aiU) aiU0[cc] += voU[cc]; else c.abU[oj + i] += voU[cc];
+        if (c.abV == c.aiV) aiV0[cc] += voV[cc]; else c.abV[oj + i] += voV[cc];
         if (k == 0) c.abP[(size_t)j * nx + i] += c.aoP[(size_t)j * nx + i];
       }
     }
@@ -1274,13 +1290,13 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       // divergence and velocity transposes
       const A aMU = ((A)sAD[wrp(i - n + 1, nx)] - (A)sAD[wrp(i + n, nx)]) * rdxA;
       const A PUc = (A)PU0, Uc = (A)vUj[cc];
-      c.aiU[oj] = (T)((C)c.aiU[oj] + (C)(aUd + au * rPUc + PUc * aMU));
+      c.aiU[oj] = (T)((C)aiU0[cc] + (C)(aUd + au * rPUc + PUc * aMU));
       const A aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;
       const A tN = vADj * rdySjA;
       const A tS = sPole ? (A)(capD * sDs[1 * (nz + 1) + k]) : (A)vAD1[cc] * rdyS1A;
       const A aMV = (A)svj * (tN - tS);
       const A PVc = (A)PV0, Vc = (A)vVj[cc], rPVc = (A)rPV0;
-      c.aiV[oj] = (T)((C)c.aiV[oj] + (C)(avd + avv * rPVc + PVc * aMV));
+      c.aiV[oj] = (T)((C)aiV0[cc] + (C)(avd + avv * rPVc + PVc * aMV));
       const A aPV3 = -Vc * (rPVc * rPVc) * avv + Vc * aMV;
       // hydrostatic transpose and column sums
       const C art = (C)aRT + clk * pre[cc] + cpk * (C)aPHI;
@@ -1291,7 +1307,7 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       aDLQ[cc] += (C)(adl + adq);
       aPU[cc] += (C)(APU3 + aPU3);
       aPV[cc] += (C)(APV3 + aPV3);
-      c.aiF[oj] = (T)((C)c.aiF[oj] + afe);
+      c.aiF[oj] = (T)((C)aiF0[cc] + afe);
     }
     __syncthreads();
   }
