@@ -224,6 +224,36 @@ class Batch:
     def step(self, nsteps=1):
         _check(lib().dycore_batch_step(self.b, int(nsteps), _stream()))
 
+    @classmethod
+    def autotune(cls, cores, states, blocks=(256, 384, 512, 768, 1024), steps=2):
+        """Time the batched step at each workgroup size in `blocks` (on copies of the states, so the
+        members are not advanced) and return (Batch at the fastest size, {block: ms per step}).
+        Sizes the grid cannot use (too many columns per thread, too large for the register budget)
+        are skipped.  Results do not depend on the workgroup size, so tuning changes speed only."""
+        import torch
+        copies = [_clone(st) for st in states]
+        table = {}
+        for blk in blocks:
+            try:
+                b = cls(cores, copies, block=blk)
+            except DycoreError:
+                continue
+            b.step(1)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.step(steps)
+            e1.record()
+            e1.synchronize()
+            table[blk] = e0.elapsed_time(e1) / steps
+            b.close()
+        del copies
+        if not table:
+            raise DycoreError("no workgroup size fits this batch")
+        best = min(table, key=table.get)
+        return cls(cores, states, block=best), table
+
     def close(self):
         if getattr(self, "b", None) is not None and self.b.value:
             lib().dycore_batch_destroy(self.b)

@@ -90,6 +90,30 @@ def test_batch_bitwise_small():
             assert torch.equal(s[k], r[k]), k
 
 
+def test_batch_autotune_bitwise():
+    """The workgroup-size autotuner leaves the members untouched while timing, picks a size it
+    timed, and the tuned batch equals per-member steps bit for bit."""
+    from paper_2103_10114_amd import Batch
+    cfgs = [dataclasses.replace(synth.CONFIGS["c1"], nx=64, ny=32, nz=5, degree=5, seed=21),
+            dataclasses.replace(synth.CONFIGS["c3"], nx=200, ny=100, nz=7, degree=8, seed=22)]
+    cores, states, hosts = _members(cfgs)
+    refs = [c.to_device(h) for c, h in zip(cores, hosts)]
+    b, table = Batch.autotune(cores, states, blocks=(64, 128, 256, 512))
+    print("autotune ms per step:", table, flush=True)
+    assert len(table) >= 2 and b is not None
+    torch.cuda.synchronize()
+    for s, r in zip(states, refs):
+        for k in ("U", "V", "Phi", "ps"):
+            assert torch.equal(s[k], r[k]), ("timing advanced the members", k)
+    b.step(2)
+    for c, r in zip(cores, refs):
+        c.step(r, 2)
+    torch.cuda.synchronize()
+    for s, r in zip(states, refs):
+        for k in ("U", "V", "Phi", "ps"):
+            assert torch.equal(s[k], r[k]), k
+
+
 def test_ensemble_c5_bitwise_and_graph_replay():
     """The 24-member mixed ensemble (8 each of 128x64x9, 256x128x30, 720x360x30, seeds 500+m, 0.5 m/s
     wind noise): one persistent launch per stage, captured in a hipGraph and replayed; after each
