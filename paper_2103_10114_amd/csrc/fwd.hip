@@ -337,7 +337,7 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
   }
 }
 
-// Adaptation, software-pipelined (rows whose LDS rows fit in 160 KB: nx <= 1497 in FP32, 748 in FP64).  Every value the level loop reads at another
+// Adaptation, software-pipelined (rows whose LDS rows fit in 160 KB: nx <= 1498 in FP32, 749 in FP64).  Every value the level loop reads at another
 // column sits in LDS: 13 2D rows (P, the reciprocals of P and of its U-point averages, the
 // leaped d+l and d+q, the V-point averages of P and the meridional l and q differences) and,
 // double-buffered, the 7 per-level rows (phi', MU, Phi, U of rows j and j+1, V of rows j+-1/2).

@@ -1,0 +1,168 @@
+"""GPU edge cases: every kernel form on both sides of the row length at which its LDS rows stop
+fitting (the pipelined stage kernels, the row-fused adaptation adjoint), ragged rows at two columns
+per thread, a single sigma level, zero steps, sizes the library refuses, and a stage adjoint whose
+base and input adjoints are one buffer."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_10114_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def small(nx, ny, nz, seed=7, degree=4):
+    return dataclasses.replace(synth.CONFIGS["c1"], nx=nx, ny=ny, nz=nz, degree=degree, seed=seed)
+
+
+def _core(cfg, st, prec, **kw):
+    from paper_2103_10114_amd import Dycore
+    return Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec=prec, phis=st["phis"], **kw)
+
+
+def _host(d):
+    return {k: v.detach().cpu().numpy().astype(np.float64) for k, v in d.items()}
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _lds_fits(rows, nx, elem):
+    """Whether `rows` LDS rows of nx values (16-byte aligned) plus 2 KiB of pole sums fit 160 KiB."""
+    return ((rows * nx * elem + 15) // 16) * 16 + 2048 <= 160 * 1024
+
+
+# The pipelined stage kernels hold 27 rows: FP64 rows of 749 columns fit, 750 do not.
+assert _lds_fits(27, 749, 8) and not _lds_fits(27, 750, 8)
+assert _lds_fits(27, 1498, 4) and not _lds_fits(27, 1499, 4)
+
+
+@pytest.mark.parametrize("nx", [749, 750])
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_tendency_fp64_across_pipeline_limit(nx, process):
+    """Both stage-kernel forms (pipelined at 749 columns, per-level barriers at 750) equal the oracle."""
+    print(f"tendency fp64 nx={nx} {process}", flush=True)
+    cfg = small(nx, 8, 3)
+    st = synth.make_state(cfg)
+    want = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).tendency(st, process)
+    core = _core(cfg, st, "fp64", forward_only=True)
+    got = _host(core.tendency(core.to_device(st), process))
+    for k in ("U", "V", "Phi", "ps"):
+        if np.abs(want[k]).max() == 0:
+            assert np.abs(got[k]).max() == 0
+            continue
+        assert _rel(got[k], want[k]) < 1e-12, (k, _rel(got[k], want[k]))
+
+
+@pytest.mark.parametrize("nx", [1000, 1498, 1499])
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_stage_fp32_ragged_and_limit(nx, process):
+    """FP32 stages at two columns per thread with a ragged second column (1000), at the last row
+    length the pipelined kernels take (1498) and the first they do not (1499)."""
+    print(f"stage fp32 nx={nx} {process}", flush=True)
+    cfg = small(nx, 10, 3)
+    st = synth.make_state(cfg)
+    st32 = {k: st[k].astype(np.float32).astype(np.float64) for k in ("U", "V", "Phi", "ps")}
+    ch = 100.0
+    want = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).stage(st32, st32, ch, process)
+    core = _core(cfg, st, "fp32", forward_only=True)
+    d = core.to_device(st32)
+    out = {k: torch.empty_like(v) for k, v in d.items()}
+    got = _host(core.stage(process, ch, d, d, out))
+    for k in ("U", "V", "Phi", "ps"):
+        inc = want[k] - st32[k]
+        scale = max(np.abs(inc).max(), np.abs(want[k]).max() * 1e-7)
+        err = np.abs(got[k] - want[k]).max() / scale
+        assert err < 2e-3, (k, err)
+
+
+# The row-fused adaptation adjoint holds 26 rows (no pole-sum block): FP64 fits at 787 columns.
+@pytest.mark.parametrize("nx", [787, 788])
+def test_stage_adjoint_fp64_across_row_kernel_limit(nx):
+    """The adaptation-stage adjoint equals the oracle on both sides of the row-fused kernel's limit."""
+    assert (((26 * 787 * 8 + 15) // 16) * 16 <= 160 * 1024) and (((26 * 788 * 8 + 15) // 16) * 16 > 160 * 1024)
+    print(f"stage adjoint fp64 nx={nx}", flush=True)
+    cfg = small(nx, 8, 3)
+    st = synth.make_state(cfg)
+    ao = synth.random_like(st, 31)
+    ch = 200.0
+    wb, wi = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).adj_stage(st, ao, ch, "A")
+    core = _core(cfg, st, "fp64")
+    d = core.to_device(st)
+    a = core.to_device(ao)
+    ab = {k: torch.zeros_like(v) for k, v in d.items()}
+    ai = {k: torch.zeros_like(v) for k, v in d.items()}
+    core.stage_adjoint("A", ch, d, a, ab, ai)
+    gb, gi = _host(ab), _host(ai)
+    for k in ("U", "V", "Phi", "ps"):
+        assert _rel(gb[k], wb[k]) < 1e-12, ("base", k)
+        assert _rel(gi[k], wi[k]) < 1e-12, ("in", k)
+
+
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_stage_adjoint_aliased_buffers(process):
+    """With the base and input adjoints in one buffer, the result is the sum of both parts."""
+    cfg = small(64, 32, 4)
+    st = synth.make_state(cfg)
+    ao = synth.random_like(st, 32)
+    ch = 150.0
+    wb, wi = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).adj_stage(st, ao, ch, process)
+    core = _core(cfg, st, "fp64")
+    d = core.to_device(st)
+    a = core.to_device(ao)
+    acc = {k: torch.zeros_like(v) for k, v in d.items()}
+    core.stage_adjoint(process, ch, d, a, acc, acc)
+    got = _host(acc)
+    for k in ("U", "V", "Phi", "ps"):
+        want = wb[k] + wi[k]
+        assert _rel(got[k], want) < 1e-12, (k, _rel(got[k], want))
+
+
+def test_single_level():
+    """nz = 1: a step and the step adjoint equal the oracle."""
+    cfg = small(64, 32, 1)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    core = _core(cfg, st, "fp64")
+    d = core.to_device(st)
+    core.step(d, 2)
+    want = o.step(st, 2, cfg.dt)
+    got = _host(d)
+    for k in ("U", "V", "Phi", "ps"):
+        assert _rel(got[k], want[k]) < 1e-11, (k, _rel(got[k], want[k]))
+    lam0 = synth.random_like(st, 33)
+    wl = o.adj_step(st, lam0, cfg.dt)
+    lam = core.to_device(lam0)
+    core.step_adjoint(core.to_device(st), lam)
+    gl = _host(lam)
+    for k in ("U", "V", "Phi", "ps"):
+        assert _rel(gl[k], wl[k]) < 1e-11, (k, _rel(gl[k], wl[k]))
+
+
+def test_zero_steps_is_identity():
+    cfg = small(40, 20, 3)
+    st = synth.make_state(cfg)
+    core = _core(cfg, st, "fp32", forward_only=True)
+    d = core.to_device(st)
+    ref = {k: v.clone() for k, v in d.items()}
+    core.step(d, 0)
+    torch.cuda.synchronize()
+    for k in d:
+        assert torch.equal(d[k], ref[k]), k
+
+
+def test_refused_sizes():
+    """Rows too long for any kernel form's LDS are refused at create (not at the first step);
+    grids below the minimum and too many levels are argument errors."""
+    from paper_2103_10114_amd import Dycore, DycoreError
+    with pytest.raises(DycoreError):
+        Dycore(4096, 8, 3, 60.0, prec="fp32", forward_only=True)
+    with pytest.raises(DycoreError):
+        Dycore(7, 8, 3, 60.0, prec="fp64", forward_only=True)
+    with pytest.raises(DycoreError):
+        Dycore(64, 8, 129, 60.0, prec="fp64", forward_only=True)
