@@ -100,6 +100,19 @@ int dycore_stage(dycore_t h, int process, double ch,
 int dycore_step_adjoint(dycore_t h, const void* U0, const void* V0, const void* Phi0, const void* ps0,
                         void* aU, void* aV, void* aPhi, void* aps, void* stream);
 
+/* One outer step in place, as dycore_step with nsteps = 1 (same kernels, same result bit for bit),
+ * that also keeps the step's 3(M+1) stage inputs in the handle's adjoint workspace, so that
+ * dycore_step_adjoint_recorded can sweep back without recomputing them (storing instead of
+ * recomputing the forward stages of one step, as an adjoint of a just-taken step needs).  Needs
+ * the adjoint workspace: DYCORE_EINVAL for a DYCORE_FORWARD_ONLY handle or NULL fields. */
+int dycore_step_record(dycore_t h, void* U, void* V, void* Phi, void* ps, void* stream);
+
+/* Adjoint of the step last taken with dycore_step_record, equal to dycore_step_adjoint about that
+ * step's start state: (aU..aps) hold the adjoint of the step's output on entry and of its input
+ * on return.  The recorded stages stay valid for further calls (other adjoint seeds) until the
+ * next dycore_step_record or dycore_step_adjoint on the handle; DYCORE_EINVAL when none is held. */
+int dycore_step_adjoint_recorded(dycore_t h, void* aU, void* aV, void* aPhi, void* aps, void* stream);
+
 /* Adjoint of one stage about its input (U..ps): adds J_base^T a_out into
  * (abU..) and J_in^T a_out into (aiU..).  The two accumulators may be the
  * same buffers (the stage's base and input then coincide); neither may alias

@@ -49,6 +49,8 @@ def lib():
         L.dycore_stage.argtypes = [vp, ctypes.c_int, ctypes.c_double] + [vp] * 12 + [vp]
         L.dycore_process_run.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double] + [vp] * 4 + [vp]
         L.dycore_step_adjoint.argtypes = [vp] + [vp] * 8 + [vp]
+        L.dycore_step_record.argtypes = [vp] + [vp] * 4 + [vp]
+        L.dycore_step_adjoint_recorded.argtypes = [vp] + [vp] * 4 + [vp]
         L.dycore_stage_adjoint.argtypes = [vp, ctypes.c_int, ctypes.c_double] + [vp] * 16 + [vp]
         L.dycore_diagnostics.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double), vp]
@@ -184,6 +186,16 @@ class Dycore:
     def step_adjoint(self, st0, adj):
         """adj (adjoint of the step output) is replaced in place by the adjoint of the step input."""
         _check(lib().dycore_step_adjoint(self.h, *self._p(st0), *self._p(adj), _stream()))
+        return adj
+
+    def step_record(self, st):
+        """One outer step in place (as step(st, 1)) that keeps its stage inputs for step_adjoint_recorded."""
+        _check(lib().dycore_step_record(self.h, *self._p(st), _stream()))
+        return st
+
+    def step_adjoint_recorded(self, adj):
+        """Adjoint of the step last taken with step_record; adj is replaced in place as in step_adjoint."""
+        _check(lib().dycore_step_adjoint_recorded(self.h, *self._p(adj), _stream()))
         return adj
 
     def stage_adjoint(self, process, ch, inp, aout, abase, ain):

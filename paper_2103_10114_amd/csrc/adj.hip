@@ -1478,6 +1478,7 @@ struct HandleView {
   void* scratch;     // forward scratch y1, y2
   int block;
   GeoFac fac;
+  int* recorded;     // 1 while the adjoint workspace holds the stage inputs of a recorded step
 };
 HandleView view_of(const dycore_s* h);
 }  // namespace dyc
@@ -1600,18 +1601,18 @@ hipError_t copy_state(const HandleView& v, St4<T> d, St4<const T> src, hipStream
 template <typename T>
 St4<const T> cst(St4<T> a) { return St4<const T>{a.U, a.V, a.F, a.P}; }
 
+// Forward pass of one outer step that keeps every stage input in the workspace: traj[3 rk] = y_rk,
+// traj[3 rk + 1] = y1, traj[3 rk + 2] = y2.  With `out` set, the last stage of the last RK step is
+// run too and writes the step's result there (out may be y0's buffers: y0 is copied first).
 template <typename T>
-int step_adjoint_impl(const HandleView& v, St4<const T> y0, St4<T> lam, hipStream_t s) {
+int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s) {
   const Layout L = layout(v);
   char* base = static_cast<char*>(v.adj);
   const int nrk = v.msub + 1;
   auto traj = [&](int q) { return state_at<T>(v, base + L.traj_off + (size_t)q * L.state); };
-  St4<T> l1 = state_at<T>(v, base + L.lam_off);
-  St4<T> l2 = state_at<T>(v, base + L.lam_off + L.state);
   double* pole = reinterpret_cast<double*>(base + L.pole_off);   // [4][2][nz+1]
   const size_t ps = 2 * (v.g.nz + 1);
   hipError_t e;
-  // forward recompute of every stage input: traj[3 rk] = y_rk, traj[3 rk + 1] = y1, traj[3 rk + 2] = y2
   e = copy_state<T>(v, traj(0), y0, s);
   if (e != hipSuccess) return DYCORE_EHIP;
   e = launch_pole_prep<T>(v.g, traj(0).F, traj(0).P, pole, s);
@@ -1638,9 +1639,26 @@ int step_adjoint_impl(const HandleView& v, St4<const T> y0, St4<T> lam, hipStrea
       St4<T> yn = traj(3 * (rk + 1));
       e = launch_stage<T>(mk(h, y2, yn, pole + 2 * ps, pole + 3 * ps), v.block, s);
       if (e == hipSuccess) e = launch_axpy_fill<double>(pole, pole + 3 * ps, ps, s);
+    } else if (e == hipSuccess && out.U) {
+      e = launch_stage<T>(mk(h, y2, out, pole + 2 * ps, pole + 3 * ps), v.block, s);
     }
     if (e != hipSuccess) return DYCORE_EHIP;
   }
+  return DYCORE_OK;
+}
+
+// Reverse sweep over the stage inputs held in the workspace.
+template <typename T>
+int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
+  const Layout L = layout(v);
+  char* base = static_cast<char*>(v.adj);
+  const int nrk = v.msub + 1;
+  auto traj = [&](int q) { return state_at<T>(v, base + L.traj_off + (size_t)q * L.state); };
+  St4<T> l1 = state_at<T>(v, base + L.lam_off);
+  St4<T> l2 = state_at<T>(v, base + L.lam_off + L.state);
+  double* pole = reinterpret_cast<double*>(base + L.pole_off);
+  const size_t ps = 2 * (v.g.nz + 1);
+  hipError_t e;
   // reverse sweep.  lam accumulates the adjoint of the RK step's input: every stage adds the base
   // transpose of its output adjoint to it; the last stage's share is lam itself with the base
   // transpose applied in place once that stage has read it.
@@ -1664,6 +1682,14 @@ int step_adjoint_impl(const HandleView& v, St4<const T> y0, St4<T> lam, hipStrea
   return DYCORE_OK;
 }
 
+template <typename T>
+int step_adjoint_impl(const HandleView& v, St4<const T> y0, St4<T> lam, hipStream_t s) {
+  const St4<T> none{nullptr, nullptr, nullptr, nullptr};
+  *v.recorded = 0;
+  const int st = record_impl<T>(v, y0, none, s);
+  return st != DYCORE_OK ? st : reverse_impl<T>(v, lam, s);
+}
+
 }  // namespace
 
 size_t dyc_adjoint_workspace_bytes(const dycore_s* h) { return layout(view_of(h)).total; }
@@ -1683,6 +1709,36 @@ int dycore_step_adjoint(dycore_t h, const void* U0, const void* V0, const void* 
   return step_adjoint_impl<double>(v, St4<const double>{(const double*)U0, (const double*)V0, (const double*)Phi0,
                                                         (const double*)ps0},
                                    St4<double>{(double*)aU, (double*)aV, (double*)aPhi, (double*)aps}, s);
+}
+
+int dycore_step_record(dycore_t h, void* U, void* V, void* Phi, void* ps, void* stream) {
+  if (!h || !U || !V || !Phi || !ps) return DYCORE_EINVAL;
+  const HandleView v = view_of(h);
+  if (!v.adj) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  *v.recorded = 0;
+  int st;
+  if (v.prec == DYCORE_FP32) {
+    using T = float;
+    st = record_impl<T>(v, St4<const T>{(const T*)U, (const T*)V, (const T*)Phi, (const T*)ps},
+                        St4<T>{(T*)U, (T*)V, (T*)Phi, (T*)ps}, s);
+  } else {
+    using T = double;
+    st = record_impl<T>(v, St4<const T>{(const T*)U, (const T*)V, (const T*)Phi, (const T*)ps},
+                        St4<T>{(T*)U, (T*)V, (T*)Phi, (T*)ps}, s);
+  }
+  if (st == DYCORE_OK) *v.recorded = 1;
+  return st;
+}
+
+int dycore_step_adjoint_recorded(dycore_t h, void* aU, void* aV, void* aPhi, void* aps, void* stream) {
+  if (!h || !aU || !aV || !aPhi || !aps) return DYCORE_EINVAL;
+  const HandleView v = view_of(h);
+  if (!v.adj || !*v.recorded) return DYCORE_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (v.prec == DYCORE_FP32)
+    return reverse_impl<float>(v, St4<float>{(float*)aU, (float*)aV, (float*)aPhi, (float*)aps}, s);
+  return reverse_impl<double>(v, St4<double>{(double*)aU, (double*)aV, (double*)aPhi, (double*)aps}, s);
 }
 
 int dycore_stage_adjoint(dycore_t h, int process, double ch, const void* U, const void* V, const void* Phi,

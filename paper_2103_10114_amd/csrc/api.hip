@@ -31,6 +31,7 @@ struct dycore_s {
   int device;
   GeoDev g;
   GeoFac fac;
+  int recorded = 0;             // the adjoint workspace holds the stage inputs of a recorded step
   std::vector<int> M, Mv;
   size_t nU, nV, nF, nP;        // element counts of each field
   size_t elem;                  // 4 or 8
@@ -58,6 +59,7 @@ struct HandleView {
   void* scratch;
   int block;
   GeoFac fac;
+  int* recorded;
 };
 HandleView view_of(const dycore_s* h);
 }  // namespace dyc
@@ -261,6 +263,7 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.scratch = h->scratch;
   v.block = h->block;
   v.fac = h->fac;
+  v.recorded = const_cast<int*>(&h->recorded);
   return v;
 }
 

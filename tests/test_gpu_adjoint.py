@@ -151,3 +151,33 @@ def test_adjoint_fp32_vs_fp64():
         l2 = np.linalg.norm(g32[k] - g64[k]) / np.linalg.norm(g64[k])
         print(f"adjoint fp32 vs fp64 {k}: rel-L2 {l2:.3e}", flush=True)
         assert l2 < 1e-3
+
+
+def test_recorded_step_and_adjoint():
+    """step_record equals step bit for bit; the recorded adjoint equals the recomputing one bit for
+    bit (also a second time with another seed); without a recording it is refused."""
+    from paper_2103_10114_amd import DycoreError
+    cfg = GRIDS[2]
+    st = synth.make_state(cfg)
+    for prec in ("fp64", "fp32"):
+        core = _core(cfg, st, prec)
+        with pytest.raises(DycoreError):
+            core.step_adjoint_recorded(core.to_device(synth.random_like(st, 40)))
+        a = core.to_device(st)
+        b = core.to_device(st)
+        core.step(a, 1)
+        core.step_record(b)
+        torch.cuda.synchronize()
+        for k in ("U", "V", "Phi", "ps"):
+            assert torch.equal(a[k], b[k]), (prec, "forward", k)
+        for seed in (41, 42):
+            l1 = core.to_device(synth.random_like(st, seed))
+            l2 = core.to_device(synth.random_like(st, seed))
+            core.step_adjoint_recorded(l1)
+            torch.cuda.synchronize()
+            core.step_adjoint(core.to_device(st), l2)   # recomputes (and drops the recording)
+            torch.cuda.synchronize()
+            for k in ("U", "V", "Phi", "ps"):
+                assert torch.equal(l1[k], l2[k]), (prec, seed, k)
+            if seed == 41:
+                core.step_record(core.to_device(st))
