@@ -53,7 +53,7 @@ enum {
 typedef struct {
   int nx;                  /* longitudes, >= 8, <= 4096 */
   int ny;                  /* latitude intervals (ny+1 scalar rows incl. both poles), >= 4 */
-  int nz;                  /* sigma levels, >= 1, <= 128 */
+  int nz;                  /* sigma levels, >= 1, <= 128; nx (ny+1) (nz+1) x element size < 4 GiB */
   double dt;               /* outer time step, seconds, > 0 */
   int n_adapt_substeps;    /* M of Sec. III-D; 0 = from the CFL bound ceil(w_max dt / (0.8 sqrt 3)) */
   int prec;                /* dycore_precision of every field pointer */

@@ -1030,26 +1030,48 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   C HRj[NI], HR1[NI], Asj[NI], As1[NI];
 #pragma unroll
   for (int cc = 0; cc < NI; ++cc) { HRj[cc] = HR1[cc] = Asj[cc] = As1[cc] = 0; }
-  for (int k = 0; k < nz; ++k) {
+  // levels in batches of kAarKU: the loads of a batch are all in flight before its sums
+  constexpr int kAarKU = 6;
+  for (int k0 = 0; k0 < nz; k0 += kAarKU) {
     asm volatile("" : "+v"(t));
-    const C clk = g.cl[k], sg = g.sig[k];
+    T vF[kAarKU][NI], vF1[kAarKU][NI], vq[kAarKU][NI], vq1[kAarKU][NI];
 #pragma unroll
-    for (int cc = 0; cc < NI; ++cc) {
-      const int i = t + cc * B;
-      if (i >= nx) continue;
-      const size_t lo = (size_t)k * nx + i;
-      const T Fj = c.F[(size_t)j * row3 + lo];
-      const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : c.F[(size_t)(j + 1) * row3 + lo];
-      const T P0 = sP0[i], P1 = sP1[i];
-      const C rP0 = (C)srP0[i], rP1 = (C)srP1[i];
-      HRj[cc] += clk * (C)(b * Fj * srP0[i]);
-      HR1[cc] += clk * (C)(b * F1 * srP1[i]);
-      const C rsg = 1.0 / sg;
-      const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * (ch * (C)c.aoF[(size_t)j * row3 + lo]);
-      Asj[cc] += -aWPj * rsg * (rP0 * rP0);
-      if (!sPole) {
-        const C aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)c.aoF[(size_t)(j + 1) * row3 + lo]);
-        As1[cc] += -aWP1 * rsg * (rP1 * rP1);
+    for (int u = 0; u < kAarKU; ++u) {
+      const int k = k0 + u < nz ? k0 + u : nz - 1;
+      const auto rF = urow(c.F, (size_t)j * row3 + (size_t)k * nx);
+      const auto rq = urow(c.aoF, (size_t)j * row3 + (size_t)k * nx);
+      const auto rF1 = urow(c.F, (size_t)(j + 1) * row3 + (size_t)k * nx);
+      const auto rq1 = urow(c.aoF, (size_t)(j + 1) * row3 + (size_t)k * nx);
+#pragma unroll
+      for (int cc = 0; cc < NI; ++cc) {
+        const int i = t + cc * B;
+        const unsigned ui = (unsigned)(i < nx ? i : 0);
+        vF[u][cc] = rF[ui];
+        vq[u][cc] = rq[ui];
+        vF1[u][cc] = sPole ? (T)c.pin[(nz + 1) + k] : rF1[ui];
+        vq1[u][cc] = sPole ? T(0) : rq1[ui];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kAarKU; ++u) {
+      const int k = k0 + u;
+      if (k >= nz) break;
+      const C clk = g.cl[k], rsg = c.f.rsig[k];
+#pragma unroll
+      for (int cc = 0; cc < NI; ++cc) {
+        const int i = t + cc * B;
+        if (i >= nx) continue;
+        const T Fj = vF[u][cc], F1 = vF1[u][cc];
+        const T P0 = sP0[i], P1 = sP1[i];
+        const C rP0 = (C)srP0[i], rP1 = (C)srP1[i];
+        HRj[cc] += clk * (C)(b * Fj * srP0[i]);
+        HR1[cc] += clk * (C)(b * F1 * srP1[i]);
+        const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * (ch * (C)vq[u][cc]);
+        Asj[cc] += -aWPj * rsg * (rP0 * rP0);
+        if (!sPole) {
+          const C aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)vq1[u][cc]);
+          As1[cc] += -aWP1 * rsg * (rP1 * rP1);
+        }
       }
     }
   }
@@ -1063,24 +1085,24 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
 #pragma unroll 1
   for (int k = 0; k < nz; ++k) {
     asm volatile("" : "+v"(t));
-    const C clk = g.cl[k], cpk = g.cpk[k], sg = g.sig[k], dsg = g.dsig[k];
-    const C rsg = 1.0 / sg;
+    const C clk = g.cl[k], cpk = g.cpk[k], dsg = g.dsig[k];
+    const C rsg = c.f.rsig[k];
     const size_t lvl = (size_t)k * nx;
-    const T* pFm = uni(c.F + ((size_t)(j - 1) * row3 + lvl));
-    const T* pFj = uni(c.F + ((size_t)j * row3 + lvl));
-    const T* pF1 = uni(c.F + ((size_t)(j + 1) * row3 + lvl));
-    const T* pUm = uni(c.U + ((size_t)(j - 1) * row3 + lvl));
-    const T* pUj = uni(c.U + ((size_t)j * row3 + lvl));
-    const T* pU1 = uni(c.U + ((size_t)(j + 1) * row3 + lvl));
-    const T* pVm = uni(c.V + ((size_t)(j - 1) * row3 + lvl));
-    const T* pVj = uni(c.V + ((size_t)j * row3 + lvl));
-    const T* qFm = uni(c.aoF + ((size_t)(j - 1) * row3 + lvl));
-    const T* qFj = uni(c.aoF + ((size_t)j * row3 + lvl));
-    const T* qF1 = uni(c.aoF + ((size_t)(j + 1) * row3 + lvl));
-    const T* qUj = uni(c.aoU + ((size_t)j * row3 + lvl));
-    const T* qU1 = uni(c.aoU + ((size_t)(j + 1) * row3 + lvl));
-    const T* qVm = uni(c.aoV + ((size_t)(j - 1) * row3 + lvl));
-    const T* qVj = uni(c.aoV + ((size_t)j * row3 + lvl));
+    const auto pFm = urow(c.F, ((size_t)(j - 1) * row3 + lvl));
+    const auto pFj = urow(c.F, ((size_t)j * row3 + lvl));
+    const auto pF1 = urow(c.F, ((size_t)(j + 1) * row3 + lvl));
+    const auto pUm = urow(c.U, ((size_t)(j - 1) * row3 + lvl));
+    const auto pUj = urow(c.U, ((size_t)j * row3 + lvl));
+    const auto pU1 = urow(c.U, ((size_t)(j + 1) * row3 + lvl));
+    const auto pVm = urow(c.V, ((size_t)(j - 1) * row3 + lvl));
+    const auto pVj = urow(c.V, ((size_t)j * row3 + lvl));
+    const auto qFm = urow(c.aoF, ((size_t)(j - 1) * row3 + lvl));
+    const auto qFj = urow(c.aoF, ((size_t)j * row3 + lvl));
+    const auto qF1 = urow(c.aoF, ((size_t)(j + 1) * row3 + lvl));
+    const auto qUj = urow(c.aoU, ((size_t)j * row3 + lvl));
+    const auto qU1 = urow(c.aoU, ((size_t)(j + 1) * row3 + lvl));
+    const auto qVm = urow(c.aoV, ((size_t)(j - 1) * row3 + lvl));
+    const auto qVj = urow(c.aoV, ((size_t)j * row3 + lvl));
     // values of the owned columns carried from phase 1 to phase 2
     // (the owned columns' entries of the LDS rows are read back in phase 2)
     T vRTm[NI], vRT1[NI], vPH1[NI], vFj[NI], vUj[NI], vVj[NI], vVm[NI];
@@ -1088,9 +1110,9 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
     // the accumulators the second phase updates, fetched now
     T aiU0[NI], aiV0[NI], aiF0[NI];
     {
-      T* gaU = uni(c.aiU + ((size_t)j * row3 + lvl));
-      T* gaV = uni(c.aiV + ((size_t)j * row3 + lvl));
-      T* gaF = uni(c.aiF + ((size_t)j * row3 + lvl));
+      const auto gaU = urow(c.aiU, ((size_t)j * row3 + lvl));
+      const auto gaV = urow(c.aiV, ((size_t)j * row3 + lvl));
+      const auto gaF = urow(c.aiF, ((size_t)j * row3 + lvl));
 #pragma unroll
       for (int cc = 0; cc < NI; ++cc) {
         const int i0 = t + cc * B;

@@ -238,6 +238,10 @@ int validate_cfg(const dycore_config* c) {
   if (c->n_adapt_substeps < 0) return DYCORE_EINVAL;
   if (c->prec != DYCORE_FP32 && c->prec != DYCORE_FP64) return DYCORE_EINVAL;
   if (c->block != 0 && (c->block < 64 || c->block > 1024 || (c->block % 64) != 0)) return DYCORE_EINVAL;
+  // kernels address a field's rows with 32-bit byte offsets: every field (half levels included)
+  // stays below 4 GiB
+  const size_t elem = c->prec == DYCORE_FP64 ? 8 : 4;
+  if ((size_t)c->nx * (size_t)(c->ny + 1) * (size_t)(c->nz + 1) * elem >= (size_t(1) << 32)) return DYCORE_EINVAL;
   if (c->sigma_half) {
     if (c->sigma_half[0] != 0.0 || c->sigma_half[c->nz] != 1.0) return DYCORE_EINVAL;
     for (int k = 0; k < c->nz; ++k)
@@ -350,7 +354,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
     for (int i = 0; i < nx; ++i) phis[(size_t)p * nx + i] = m;
   }
   auto rnd = [&](double x) { return h->prec == DYCORE_FP32 ? (double)(float)x : x; };
-  std::vector<double> rdx(ny + 1, 0.0), rdy(ny + 1, 0.0), rdxv2(ny), rdyv2(ny), r2d(nz);
+  std::vector<double> rdx(ny + 1, 0.0), rdy(ny + 1, 0.0), rdxv2(ny), rdyv2(ny), r2d(nz), rsig(nz);
   for (int j = 1; j < ny; ++j) {
     rdx[j] = rnd(1.0 / ((double)h->M[j] * g.a * s[j] * g.dlam));
     rdy[j] = rnd(1.0 / (g.a * s[j] * g.dth));
@@ -360,6 +364,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
     rdyv2[j] = rnd(1.0 / (2.0 * g.a * sv[j] * g.dth));
   }
   for (int k = 0; k < nz; ++k) r2d[k] = 1.0 / (2.0 * dsig[k]);
+  for (int k = 0; k < nz; ++k) rsig[k] = 1.0 / sig[k];
   if (cfg->n_adapt_substeps > 0) {
     h->msub = cfg->n_adapt_substeps;
   } else {
@@ -376,7 +381,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       {sig.data(), sig.size() * 8},   {dsig.data(), dsig.size() * 8}, {cl.data(), cl.size() * 8},
       {cpk.data(), cpk.size() * 8},   {phis.data(), phis.size() * 8}, {rdx.data(), rdx.size() * 8},
       {rdy.data(), rdy.size() * 8},   {rdxv2.data(), rdxv2.size() * 8}, {rdyv2.data(), rdyv2.size() * 8},
-      {r2d.data(), r2d.size() * 8}};
+      {r2d.data(), r2d.size() * 8},   {rsig.data(), rsig.size() * 8}};
   size_t gbytes = 0;
   for (auto& pr : parts) gbytes += align256(pr.second);
   if (hipMalloc(&h->geo, gbytes) != hipSuccess) { delete h; return DYCORE_ENOMEM; }
@@ -400,6 +405,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   h->fac.rdx = (const double*)(gb + off[14]); h->fac.rdy = (const double*)(gb + off[15]);
   h->fac.rdxv2 = (const double*)(gb + off[16]); h->fac.rdyv2 = (const double*)(gb + off[17]);
   h->fac.r2d = (const double*)(gb + off[18]);
+  h->fac.rsig = (const double*)(gb + off[19]);
 
   h->nU = (size_t)(ny + 1) * nz * nx;
   h->nV = (size_t)ny * nz * nx;

@@ -509,12 +509,12 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
     const size_t lo = (size_t)j * row3 + (size_t)k * nx;
     const T F0p = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
     const T F1p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
-    const T* gF0 = uni(A.inF + lo);
-    const T* gU0 = uni(A.inU + lo);
-    const T* gF1 = uni(A.inF + lo + row3);
-    const T* gU1 = uni(A.inU + lo + row3);
-    const T* gV0 = uni(A.inV + lo);
-    const T* gVm = uni(A.inV + (lo - (j >= 1 ? row3 : 0)));
+    const auto gF0 = urow(A.inF, lo);
+    const auto gU0 = urow(A.inU, lo);
+    const auto gF1 = urow(A.inF, lo + row3);
+    const auto gU1 = urow(A.inU, lo + row3);
+    const auto gV0 = urow(A.inV, lo);
+    const auto gVm = urow(A.inV, (lo - (j >= 1 ? row3 : 0)));
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
@@ -580,12 +580,12 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
     (void)clk;
     const C dsg = g.dsig[k], rsg = 1.0 / g.sig[k];
     const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-    const T* gbF = uni(A.bF + lo);
-    const T* gbU = uni(A.bU + lo);
-    const T* gbV = uni(A.bV + lo);
-    T* goF = uni(A.oF + lo);
-    T* goU = uni(A.oU + lo);
-    T* goV = uni(A.oV + lo);
+    const auto gbF = urow(A.bF, lo);
+    const auto gbU = urow(A.bU, lo);
+    const auto gbV = urow(A.bV, lo);
+    const auto goF = urow(A.oF, lo);
+    const auto goU = urow(A.oU, lo);
+    const auto goV = urow(A.oV, lo);
 
     if (!isPole) {
 #pragma unroll
@@ -1154,11 +1154,11 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
       for (int u = 0; u < KU; ++u) {
         const int k = k0 + u < nz ? k0 + u : nz - 1;
         const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-        const T* gU0 = uni(A.inU + lo);
-        const T* gU1 = uni(A.inU + lo + row3);
-        const T* gV0 = uni(A.inV + lo);
-        const T* gVm = uni(A.inV + (lo - (j >= 1 ? row3 : 0)));
-        const T* gV1 = uni(A.inV + lo + row3);
+        const auto gU0 = urow(A.inU, lo);
+        const auto gU1 = urow(A.inU, lo + row3);
+        const auto gV0 = urow(A.inV, lo);
+        const auto gVm = urow(A.inV, (lo - (j >= 1 ? row3 : 0)));
+        const auto gV1 = urow(A.inV, lo + row3);
 #pragma unroll
         for (int c = 0; c < NI; ++c) {
           const int i = t + c * B;
@@ -1199,15 +1199,15 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
 
   auto fetch = [&](int k) {
     const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-    const T* gF0 = uni(A.inF + lo);
-    const T* gU0 = uni(A.inU + lo);
-    const T* gV0 = uni(A.inV + lo);
-    const T* gVm = uni(A.inV + (lo - (j >= 1 ? row3 : 0)));
-    const T* gU1 = uni(A.inU + lo + row3);
-    const T* gV1 = uni(A.inV + lo + row3);
-    const T* gF1 = uni(A.inF + lo + row3);
-    const T* gFs = uni(A.inF + (lo - (j >= 1 ? row3 : 0)));
-    const T* gUs = uni(A.inU + (lo - (j >= 1 ? row3 : 0)));
+    const auto gF0 = urow(A.inF, lo);
+    const auto gU0 = urow(A.inU, lo);
+    const auto gV0 = urow(A.inV, lo);
+    const auto gVm = urow(A.inV, (lo - (j >= 1 ? row3 : 0)));
+    const auto gU1 = urow(A.inU, lo + row3);
+    const auto gV1 = urow(A.inV, lo + row3);
+    const auto gF1 = urow(A.inF, lo + row3);
+    const auto gFs = urow(A.inF, (lo - (j >= 1 ? row3 : 0)));
+    const auto gUs = urow(A.inU, (lo - (j >= 1 ? row3 : 0)));
     const T Fp0 = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
     const T Fn_p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
     const T Fs_p = (j - 1 == 0) ? (T)A.pin[k] : T(0);
@@ -1297,12 +1297,12 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     const T* sdTop = sSd + (size_t)(k % 3) * nx;
     const T* sdBot = sSd + (size_t)((k + 1) % 3) * nx;
     const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-    T* goF = uni(A.oF + lo);
-    T* goU = uni(A.oU + lo);
-    T* goV = uni(A.oV + lo);
-    const T* gbF = uni(A.bF + lo);
-    const T* gbU = uni(A.bU + lo);
-    const T* gbV = uni(A.bV + lo);
+    const auto goF = urow(A.oF, lo);
+    const auto goU = urow(A.oU, lo);
+    const auto goV = urow(A.oV, lo);
+    const auto gbF = urow(A.bF, lo);
+    const auto gbU = urow(A.bU, lo);
+    const auto gbV = urow(A.bV, lo);
     T cbF[NI], cbU[NI], cbV[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {

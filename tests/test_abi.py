@@ -42,3 +42,22 @@ def test_strerror_and_invalid_config_without_gpu():
     # a NULL config is rejected before any device call
     h = ctypes.c_void_p()
     assert L.dycore_create(None, ctypes.byref(h)) == -1
+
+
+@pytest.mark.parametrize("nx,ny,nz,prec,ok", [
+    (1440, 8000, 100, 0, False),   # FP32 fields of 4.65 GB
+    (1440, 4000, 100, 1, False),   # FP64 fields of 4.65 GB
+])
+def test_fields_above_4gib_refused_without_gpu(nx, ny, nz, prec, ok):
+    """Kernels address field rows with 32-bit byte offsets, so create refuses grids whose fields
+    (half levels included) reach 4 GiB, before any allocation or device call."""
+    if not os.path.exists(LIB):
+        pytest.skip("libdycore.so not built")
+    from paper_2103_10114_amd import _Config
+    assert nx * (ny + 1) * (nz + 1) * (8 if prec else 4) >= 1 << 32
+    L = ctypes.CDLL(LIB)
+    cfg = _Config()
+    cfg.nx, cfg.ny, cfg.nz, cfg.dt, cfg.prec = nx, ny, nz, 60.0, prec
+    h = ctypes.c_void_p()
+    assert L.dycore_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert not h.value
