@@ -13,7 +13,9 @@ The metric is grid-point updates per second: nx * ny * nz per bench step.
 Printed: one JSON line with the value, forward-only and adjoint-only rates, a
 48-step adjoint window with checkpoints every 8 steps (time and checkpoint bytes),
 the FP64 repeat and FP32/FP64 speedup, the HBM roofline of the dominant kernel
-(adaptation stage) measured live with HIP events on the launch stream, the
+(the row-fused adaptation-stage adjoint, timed live with HIP events that the library records
+on its launch stream around each of its launches in the timed steps; the forward adaptation
+and advection stages beside it), the
 24-member mixed ensemble (one persistent launch per stage, hipGraph replay), and
 the FP64 CPU oracle timed on the host on a bounded sample of the same workload.
 """
@@ -34,9 +36,9 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
-    """Hash of the sources the stage kernels are built from (the adjoint's file is not among them)."""
+    """Hash of the sources every kernel is built from (stage kernels, adjoint kernels, shared header)."""
     h = hashlib.sha256()
-    for f in ("fwd.hip", "dycore_internal.h"):
+    for f in ("fwd.hip", "adj.hip", "dycore_internal.h"):
         p = os.path.join(ROOT, "paper_2103_10114_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -82,12 +84,16 @@ def run_prec(cfg, st, prec, steps, warmup, adjoint, seed_lam=7):
 
     for _ in range(warmup):
         one()
+    if adjoint:
+        # events around each launch of the row-fused adaptation-stage adjoint in the timed steps
+        core.kernel_timer_start(3 * core.substeps * steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         one()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    core.kernel_timing = core.kernel_timer_stop() if adjoint else (0.0, 0)
     nonfinite = core.count_nonfinite(d)
     return core, d, el, nonfinite
 
@@ -107,17 +113,22 @@ def roofline(core, d, cfg, elem, reps=10):
     return ms, alg, ach
 
 
-def traffic_from_profiles(kernel_hash):
-    p = os.path.join(ROOT, "profiles", "traffic_adapt_stage_c4_fp32.json")
-    if not os.path.exists(p):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c4_fp32.json")
+
+
+def traffic_from_profiles(kernel_hash, key):
+    """HBM bytes per launch of kernel `key` from the committed PMC summary, while it was taken
+    from the kernels built now (same source hash); None otherwise."""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
-        t = json.load(open(p))
+        t = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
     if t.get("kernel_hash") != kernel_hash:
         return None
-    return t.get("bytes_per_launch")
+    k = t.get("kernels", {}).get(key)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
 def cpu_baseline(msub):
@@ -301,14 +312,34 @@ def main():
         del lam
     if not args.no_roofline:
         print("[bench] roofline timing", file=sys.stderr, flush=True)
-        ms, alg, ach = roofline(core, d, cfg, 4)
         kh = kernel_source_hash()
-        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kh),
-                           "kernel": f"k_stage<float,{-(-cfg.nx // core.block)},{2 if adapt_pipelined(cfg.nx) else 0}> "
-                                     "(adaptation stage)",
-                           "avg_launch_ms": ms["A"], "advection_launch_ms": ms["L"],
-                           "alg_bytes_per_launch": alg, "kernel_hash": kh}
+        sb = state_bytes(cfg.nx, cfg.ny, cfg.nz, 4)
+        ni = -(-cfg.nx // core.block)
+        ms, alg, ach = roofline(core, d, cfg, 4)
+        stage_name = f"k_stage<float,{ni},{2 if adapt_pipelined(cfg.nx) else 0}>"
+        fwd = {"kernel": stage_name + " (adaptation stage)", "avg_launch_ms": ms["A"],
+               "alg_bytes_per_launch": alg, "achieved": ach, "frac": ach / HBM_PEAK_GBS,
+               "traffic": traffic_from_profiles(kh, stage_name),
+               "advection_launch_ms": ms["L"]}
+        tot, n = core.kernel_timing
+        if n > 0:
+            # the dominant kernel of the bench step: over the three stages of an RK step the
+            # adjoint reads the stage input and the output adjoint, writes the stage's input
+            # adjoint and updates the step-input adjoint: 3 + 5 + 4 = 12 states, 4 per launch
+            ams = tot / n
+            aalg = 4.0 * sb
+            aach = aalg / (ams * 1e-3) / 1e9
+            aname = f"k_aar<float,{ni}>"
+            out["roofline"] = {"bound": "hbm", "achieved": aach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": aach / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kh, aname),
+                               "kernel": aname + " (row-fused adaptation-stage adjoint)",
+                               "avg_launch_ms": ams, "launches_timed": n, "alg_bytes_per_launch": aalg,
+                               "kernel_hash": kh, "forward_stage": fwd}
+        else:
+            out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS, "traffic": fwd["traffic"],
+                               "kernel": fwd["kernel"], "avg_launch_ms": ms["A"],
+                               "advection_launch_ms": ms["L"], "alg_bytes_per_launch": alg, "kernel_hash": kh}
     del core, d
     torch.cuda.empty_cache()
     if not args.no_fp64:

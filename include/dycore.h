@@ -143,6 +143,17 @@ int dycore_block(dycore_t h);
 /* Bytes of device memory the handle holds. */
 size_t dycore_workspace_bytes(dycore_t h);
 
+/* Live timing of the row-fused adaptation-stage adjoint kernel (the dominant kernel of
+ * dycore_step_adjoint and dycore_step_adjoint_recorded; Sec. III-D, eq. 7, transposed):
+ * start makes 2 max_launches HIP events (host call, allocates; not for a timed region) and
+ * arms the handle; every later launch of that kernel on the handle, up to max_launches, is
+ * bracketed by events recorded on its launch stream.  stop waits for the last recorded event,
+ * writes the sum of the bracketed durations (ms) and the number of timed launches, disarms
+ * and frees the events.  DYCORE_EINVAL: NULL arguments, max_launches outside 1..65536, stop
+ * without start; DYCORE_EHIP: event creation or query failed (the timer is released). */
+int dycore_kernel_timer_start(dycore_t h, int max_launches);
+int dycore_kernel_timer_stop(dycore_t h, double* total_ms, int* launches);
+
 /* Batches of ensemble members (any grids, one precision) advanced together:
  * one persistent launch per global stage, each workgroup pulling (member,
  * row) work items, so the launch sequence of a step is fixed and can be

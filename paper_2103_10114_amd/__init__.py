@@ -59,6 +59,8 @@ def lib():
         L.dycore_substeps.argtypes = [vp]
         L.dycore_block.argtypes = [vp]
         L.dycore_workspace_bytes.argtypes = [vp]
+        L.dycore_kernel_timer_start.argtypes = [vp, ctypes.c_int]
+        L.dycore_kernel_timer_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.dycore_workspace_bytes.restype = ctypes.c_size_t
         L.dycore_strerror.argtypes = [ctypes.c_int]
         L.dycore_strerror.restype = ctypes.c_char_p
@@ -197,6 +199,16 @@ class Dycore:
         """Adjoint of the step last taken with step_record; adj is replaced in place as in step_adjoint."""
         _check(lib().dycore_step_adjoint_recorded(self.h, *self._p(adj), _stream()))
         return adj
+
+    def kernel_timer_start(self, max_launches):
+        """Arm live HIP-event timing of the row-fused adaptation-stage adjoint kernel's launches."""
+        _check(lib().dycore_kernel_timer_start(self.h, int(max_launches)))
+
+    def kernel_timer_stop(self):
+        """(total ms, launches) of the launches timed since kernel_timer_start; disarms."""
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        _check(lib().dycore_kernel_timer_stop(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def stage_adjoint(self, process, ch, inp, aout, abase, ain):
         proc = 0 if process in (0, "A") else 1

@@ -70,6 +70,7 @@ struct Ctx {
   int jr0 = 0, jrs = 1;            // rows a launch covers: jr0 + jrs * (grid row index)
   int blk = 0;                     // workgroup size of the row-fused kernel (the handle's)
   int parts = 7;                   // first adaptation transposes: 1 scalar point (+ suffix), 2 U, 4 V
+  KTimer* timer = nullptr;         // host side: times the row-fused kernel's launches when armed
 };
 
 template <typename T>
@@ -1393,8 +1394,17 @@ hipError_t launch_aar(const Ctx<T>& c, hipStream_t s) {
   const size_t lds = aar_lds(c.g.nx, (int)sizeof(T));
   hipError_t e = allow_lds_adj<k_aar<T, NI>>(lds);
   if (e != hipSuccess) return e;
+  KTimer* t = c.timer;
+  const bool timed = t && t->armed && t->n < t->cap;
+  if (timed && (e = hipEventRecord(t->ev[2 * t->n], s)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_aar<T, NI>), dim3(c.g.ny - 1), dim3(c.blk), lds, s, c);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (timed) {
+    if ((e = hipEventRecord(t->ev[2 * t->n + 1], s)) != hipSuccess) return e;
+    ++t->n;
+  }
+  return hipSuccess;
 }
 
 template <typename T>
@@ -1487,23 +1497,6 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
 // ------------------------------------------------------------------------------------------------
 // workspace and driver (the handle layout is private to api.hip; it exposes what we need here)
 // ------------------------------------------------------------------------------------------------
-struct dycore_s;
-namespace dyc {
-struct HandleView {
-  GeoDev g;
-  int prec, msub;
-  double dt;
-  size_t nU, nV, nF, nP, elem, state_bytes;
-  void* adj;
-  size_t adj_bytes;
-  double* pole;      // pole slots of the handle
-  void* scratch;     // forward scratch y1, y2
-  int block;
-  GeoFac fac;
-  int* recorded;     // 1 while the adjoint workspace holds the stage inputs of a recorded step
-};
-HandleView view_of(const dycore_s* h);
-}  // namespace dyc
 
 namespace {
 
@@ -1595,6 +1588,7 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.s = scratch_of<T>(v);
   c.f = v.fac;
   c.blk = v.block;
+  c.timer = v.timer;
   hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
   if (e != hipSuccess) return e;
   e = run_stage_adjoint<T>(c, s, process == 0);

@@ -32,6 +32,7 @@ struct dycore_s {
   GeoDev g;
   GeoFac fac;
   int recorded = 0;             // the adjoint workspace holds the stage inputs of a recorded step
+  dyc::KTimer timer;            // live timing of the row-fused adaptation-stage adjoint
   std::vector<int> M, Mv;
   size_t nU, nV, nF, nP;        // element counts of each field
   size_t elem;                  // 4 or 8
@@ -47,22 +48,6 @@ struct dycore_s {
 };
 
 size_t dyc_adjoint_workspace_bytes(const dycore_s* h);
-namespace dyc {
-struct HandleView {
-  GeoDev g;
-  int prec, msub;
-  double dt;
-  size_t nU, nV, nF, nP, elem, state_bytes;
-  void* adj;
-  size_t adj_bytes;
-  double* pole;
-  void* scratch;
-  int block;
-  GeoFac fac;
-  int* recorded;
-};
-HandleView view_of(const dycore_s* h);
-}  // namespace dyc
 
 struct dycore_batch_s {
   int n, prec, block, grid, max_nx, nstage_max;
@@ -231,6 +216,15 @@ int stage_impl(dycore_s* h, int process, double ch, const T* bU, const T* bV, co
   return hip_status(e);
 }
 
+void release_timer(dycore_s* h) {
+  dyc::KTimer& t = h->timer;
+  if (t.ev) {
+    for (int q = 0; q < 2 * t.cap; ++q) (void)hipEventDestroy(t.ev[q]);
+    delete[] t.ev;
+  }
+  t = dyc::KTimer{};
+}
+
 int validate_cfg(const dycore_config* c) {
   if (!c) return DYCORE_EINVAL;
   if (c->nx < 8 || c->nx > 4096 || c->ny < 4 || c->ny > 8192 || c->nz < 1 || c->nz > 128) return DYCORE_EINVAL;
@@ -268,6 +262,7 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.block = h->block;
   v.fac = h->fac;
   v.recorded = const_cast<int*>(&h->recorded);
+  v.timer = const_cast<dyc::KTimer*>(&h->timer);
   return v;
 }
 
@@ -428,6 +423,48 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   return DYCORE_OK;
 }
 
+int dycore_kernel_timer_start(dycore_t h, int max_launches) {
+  if (!h || max_launches < 1 || max_launches > 65536) return DYCORE_EINVAL;
+  release_timer(h);
+  dyc::KTimer& t = h->timer;
+  t.ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches];
+  if (!t.ev) return DYCORE_ENOMEM;
+  for (int q = 0; q < 2 * max_launches; ++q) {
+    if (hipEventCreate(&t.ev[q]) != hipSuccess) {
+      t.cap = q / 2;   // whole pairs made so far; the odd one out is destroyed here
+      if (q % 2) (void)hipEventDestroy(t.ev[q - 1]);
+      release_timer(h);
+      return DYCORE_EHIP;
+    }
+  }
+  t.cap = max_launches;
+  t.n = 0;
+  t.armed = 1;
+  return DYCORE_OK;
+}
+
+int dycore_kernel_timer_stop(dycore_t h, double* total_ms, int* launches) {
+  if (!h || !total_ms || !launches) return DYCORE_EINVAL;
+  dyc::KTimer& t = h->timer;
+  if (!t.ev) return DYCORE_EINVAL;
+  t.armed = 0;
+  double sum = 0;
+  int st = DYCORE_OK;
+  for (int q = 0; q < t.n; ++q) {
+    float ms = 0;
+    if (hipEventSynchronize(t.ev[2 * q + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, t.ev[2 * q], t.ev[2 * q + 1]) != hipSuccess) {
+      st = DYCORE_EHIP;
+      break;
+    }
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = st == DYCORE_OK ? t.n : 0;
+  release_timer(h);
+  return st;
+}
+
 int dycore_destroy(dycore_t h) {
   if (!h) return DYCORE_EINVAL;
   (void)hipDeviceSynchronize();
@@ -437,6 +474,7 @@ int dycore_destroy(dycore_t h) {
   if (h->diag) (void)hipFree(h->diag);
   if (h->count) (void)hipFree(h->count);
   if (h->adj) (void)hipFree(h->adj);
+  release_timer(h);
   delete h;
   return DYCORE_OK;
 }

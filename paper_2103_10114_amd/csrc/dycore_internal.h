@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct dycore_s;
+
 namespace dyc {
 
 // Geometry and constants as the kernels see them (device pointers to FP64 tables).
@@ -37,6 +39,13 @@ struct GeoFac {
   const double* rdyv2;  // V rows: 1 / (2 a sin(theta) dtheta)
   const double* r2d;    // levels: 1 / (2 dsigma)
   const double* rsig;   // levels: 1 / sigma (correctly rounded, as a division on the device)
+};
+
+// Live timing of one kernel's launches: HIP events recorded on the launch stream right before
+// and after each launch, up to `cap` launches.
+struct KTimer {
+  int armed = 0, n = 0, cap = 0;
+  hipEvent_t* ev = nullptr;   // 2 cap events: start and end of each timed launch
 };
 
 // Pole slot layout: double[2][nz+1]; [p][k] = Phi pole value at level k, [p][nz] = p_s pole value,
@@ -163,5 +172,22 @@ __device__ __forceinline__ void xcd_tile3(int gx, int nz, int nrows, int& x, int
   k = (tup / gx) % nz;
   j = tup / (gx * nz);
 }
+
+// What the adjoint translation unit sees of a handle.
+struct HandleView {
+  GeoDev g;
+  int prec, msub;
+  double dt;
+  size_t nU, nV, nF, nP, elem, state_bytes;
+  void* adj;
+  size_t adj_bytes;
+  double* pole;      // pole slots of the handle
+  void* scratch;     // forward scratch y1, y2
+  int block;
+  GeoFac fac;
+  int* recorded;     // 1 while the adjoint workspace holds the stage inputs of a recorded step
+  KTimer* timer;     // launches of the row-fused adaptation-stage adjoint kernel
+};
+HandleView view_of(const dycore_s* h);
 
 }  // namespace dyc

@@ -181,3 +181,31 @@ def test_recorded_step_and_adjoint():
                 assert torch.equal(l1[k], l2[k]), (prec, seed, k)
             if seed == 41:
                 core.step_record(core.to_device(st))
+
+
+def test_kernel_timer_counts_row_adjoint_launches():
+    """The live timer brackets every launch of the row-fused adaptation-stage adjoint (one per
+    adaptation stage of the step: 3 M), up to its capacity; timing does not change the result."""
+    from paper_2103_10114_amd import DycoreError
+    cfg = GRIDS[2]
+    st = synth.make_state(cfg)
+    core = _core(cfg, st, "fp32")
+    with pytest.raises(DycoreError):
+        core.kernel_timer_stop()
+    with pytest.raises(DycoreError):
+        core.kernel_timer_start(0)
+    m = core.substeps
+    ref = core.to_device(synth.random_like(st, 44))
+    core.step_record(core.to_device(st))
+    core.step_adjoint_recorded(ref)
+    for cap, want in ((4 * m, 3 * m), (2, 2)):
+        lam = core.to_device(synth.random_like(st, 44))
+        core.step_record(core.to_device(st))
+        core.kernel_timer_start(cap)
+        core.step_adjoint_recorded(lam)
+        total, n = core.kernel_timer_stop()
+        assert n == want, (cap, n)
+        assert total > 0
+        torch.cuda.synchronize()
+        for k in ("U", "V", "Phi", "ps"):
+            assert torch.equal(lam[k], ref[k]), (cap, k)
