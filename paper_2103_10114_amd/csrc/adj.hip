@@ -71,6 +71,7 @@ struct Ctx {
   int blk = 0;                     // workgroup size of the row-fused kernel (the handle's)
   int parts = 7;                   // first adaptation transposes: 1 scalar point (+ suffix), 2 U, 4 V
   KTimer* timer = nullptr;         // host side: times the row-fused kernel's launches when armed
+  int fwd_all = 1;                 // forward recompute of R T', phi', omega/p too (0: D, S, sigma-dot only)
 };
 
 template <typename T>
@@ -82,23 +83,41 @@ __device__ __forceinline__ size_t ih(const GeoDev& g, int j, int h, int i) {
   return ((size_t)j * (g.nz + 1) + h) * g.nx + i;
 }
 
+// 32-bit forms: a field holds fewer than 2^30 elements (create refuses larger grids), so element
+// indices and byte offsets fit 32 bits and a load is the array's base plus a 32-bit offset
+__device__ __forceinline__ unsigned i3u(const GeoDev& g, int j, int k, int i) {
+  return (unsigned)((j * g.nz + k) * g.nx + i);
+}
+__device__ __forceinline__ unsigned ihu(const GeoDev& g, int j, int h, int i) {
+  return (unsigned)((j * (g.nz + 1) + h) * g.nx + i);
+}
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, unsigned idx) {
+  return *(const __attribute__((address_space(1))) T*)(
+      (const __attribute__((address_space(1))) char*)p + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, unsigned idx, T v) {
+  *(__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)p + idx * (unsigned)sizeof(T)) = v;
+}
+
 // pole-aware reads of the linearisation state
 template <typename T>
 __device__ __forceinline__ T Fe(const Ctx<T>& c, int j, int k, int i) {
   const GeoDev& g = c.g;
   if (j == 0) return (T)c.pin[k];
   if (j == g.ny) return (T)c.pin[(g.nz + 1) + k];
-  return c.F[i3<T>(g, j, k, i)];
+  return ldg(c.F, i3u(g, j, k, i));
 }
 template <typename T>
 __device__ __forceinline__ T Ue(const Ctx<T>& c, int j, int k, int i) {
   const GeoDev& g = c.g;
   if (j <= 0 || j >= g.ny) return T(0);
-  return c.U[i3<T>(g, j, k, i)];
+  return ldg(c.U, i3u(g, j, k, i));
 }
 template <typename T>
 __device__ __forceinline__ T Ve(const Ctx<T>& c, int jv, int k, int i) {
-  return c.V[i3<T>(c.g, jv, k, i)];
+  return ldg(c.V, i3u(c.g, jv, k, i));
 }
 template <typename T>
 __device__ __forceinline__ T psE(const Ctx<T>& c, int j, int i) {
@@ -168,6 +187,7 @@ __global__ void k_f1(Ctx<T> c) {
   const int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, nz = g.nz;
+  const bool all = c.fwd_all;   // the advection adjoint reads only D, S and sigma-dot
   const T b = (T)g.b;
   const int M = g.M[j], n = (M + 1) / 2;
   const T dx = (T)((double)M * g.a * g.s[j] * g.dlam);
@@ -177,34 +197,42 @@ __global__ void k_f1(Ctx<T> c) {
   const int pa = wrp(i + n - 1, nx), pb = wrp(i - n, nx), im1 = wrp(i - 1, nx);
   const T PUa = PUe(c, j, pa), PUb = PUe(c, j, pb), PU0 = PUe(c, j, i), PUm = PUe(c, j, im1);
   C H = 0, S = 0;
-  c.s.S[ih<T>(g, j, 0, i)] = T(0);
+  stg(c.s.S, ihu(g, j, 0, i), T(0));
   for (int k = 0; k < nz; ++k) {
-    const T RT = b * Fe(c, j, k, i) / P0;
-    c.s.RT[i3<T>(g, j, k, i)] = RT;
-    H += g.cl[k] * (C)RT;
+    const unsigned id = i3u(g, j, k, i);
+    if (all) {
+      const T RT = b * Fe(c, j, k, i) / P0;
+      stg(c.s.RT, id, RT);
+      H += g.cl[k] * (C)RT;
+    }
     const T D = (PUa * Ue(c, j, k, pa) - PUb * Ue(c, j, k, pb)) / dx +
                 ((T)g.sv[j] * (PV0 * Ve(c, j, k, i)) - (T)g.sv[j - 1] * (PVm * Ve(c, j - 1, k, i))) / dyS;
-    c.s.D[i3<T>(g, j, k, i)] = D;
+    stg(c.s.D, id, D);
     S += (C)D * g.dsig[k];
-    c.s.S[ih<T>(g, j, k + 1, i)] = (T)S;
+    stg(c.s.S, ihu(g, j, k + 1, i), (T)S);
   }
   const C Pi = S;
   C R = 0, Sk = 0;
   const C P0s = (C)P0 * (C)P0;
-  const T l0 = c.s.L[(size_t)j * nx + i], l1 = c.s.L[(size_t)(j + 1) * nx + i], lm = c.s.L[(size_t)(j - 1) * nx + i];
-  const T dl0 = c.s.DL[(size_t)j * nx + i], dlm = c.s.DL[(size_t)j * nx + im1];
-  c.s.SD[ih<T>(g, j, 0, i)] = T(0);
+  T l0 = 0, l1 = 0, lm = 0, dl0 = 0, dlm = 0;
+  if (all) {
+    l0 = c.s.L[(size_t)j * nx + i]; l1 = c.s.L[(size_t)(j + 1) * nx + i]; lm = c.s.L[(size_t)(j - 1) * nx + i];
+    dl0 = c.s.DL[(size_t)j * nx + i]; dlm = c.s.DL[(size_t)j * nx + im1];
+  }
+  stg(c.s.SD, ihu(g, j, 0, i), T(0));
   for (int k = 0; k < nz; ++k) {
-    const size_t id = i3<T>(g, j, k, i);
-    const T RT = c.s.RT[id];
-    R += g.cl[k] * (C)RT;
-    c.s.PHI[id] = (T)(H - R + g.cpk[k] * (C)RT);
-    const C D = (C)c.s.D[id];
-    const T zon = T(0.5) * ((Ue(c, j, k, i) / PU0) * dl0 + (Ue(c, j, k, im1) / PUm) * dlm);
-    const T mer = T(0.5) * ((Ve(c, j, k, i) / PV0) * (l1 - l0) + (Ve(c, j - 1, k, i) / PVm) * (l0 - lm)) / dyA;
-    c.s.WP[id] = (T)(((C)zon + (C)mer) - (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s));
+    const unsigned id = i3u(g, j, k, i);
+    const C D = (C)ldg(c.s.D, id);
+    if (all) {
+      const T RT = ldg(c.s.RT, id);
+      R += g.cl[k] * (C)RT;
+      stg(c.s.PHI, id, (T)(H - R + g.cpk[k] * (C)RT));
+      const T zon = T(0.5) * ((Ue(c, j, k, i) / PU0) * dl0 + (Ue(c, j, k, im1) / PUm) * dlm);
+      const T mer = T(0.5) * ((Ve(c, j, k, i) / PV0) * (l1 - l0) + (Ve(c, j - 1, k, i) / PVm) * (l0 - lm)) / dyA;
+      stg(c.s.WP, id, (T)(((C)zon + (C)mer) - (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s)));
+    }
     Sk += D * g.dsig[k];
-    c.s.SD[ih<T>(g, j, k + 1, i)] = (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - Sk) / P0s) : T(0);
+    stg(c.s.SD, ihu(g, j, k + 1, i), (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - Sk) / P0s) : T(0));
   }
 }
 
@@ -540,19 +568,19 @@ __global__ void k_l1(Ctx<T> c) {
   const double* sF = c.s.psum + PS_AOF * 2 * (nz + 1);
   const A AN = (A)(-c.ch * sF[0 * (nz + 1) + k]), AS = (A)(-c.ch * sF[1 * (nz + 1) + k]);
   const A cc = (A)(g.a * g.dlam / (2.0 * g.acap));
-  auto amF = [&](int jr, int kk, int ii) -> A { return -ch * (A)c.aoF[i3<T>(g, jr, kk, ii)]; };
-  auto amU = [&](int jr, int kk, int ii) -> A { return -ch * (A)c.aoU[i3<T>(g, jr, kk, ii)]; };
-  auto amV = [&](int jv, int kk, int ii) -> A { return -ch * (A)c.aoV[i3<T>(g, jv, kk, ii)]; };
+  auto amF = [&](int jr, int kk, int ii) -> A { return -ch * (A)ldg(c.aoF, i3u(g, jr, kk, ii)); };
+  auto amU = [&](int jr, int kk, int ii) -> A { return -ch * (A)ldg(c.aoU, i3u(g, jr, kk, ii)); };
+  auto amV = [&](int jv, int kk, int ii) -> A { return -ch * (A)ldg(c.aoV, i3u(g, jv, kk, ii)); };
   auto interior = [&](int jr) { return jr >= 1 && jr <= ny - 1; };
-  auto sd = [&](int jr, int h, int ii) -> A { return (A)c.s.SD[ih<T>(g, jr, h, ii)]; };
+  auto sd = [&](int jr, int h, int ii) -> A { return (A)ldg(c.s.SD, ihu(g, jr, h, ii)); };
   // the forward's difference factors (rounded to the field precision)
   auto rdx2 = [&](int jr) -> A { return (A)(0.5 * c.f.rdx[jr]); };
   auto rdy2 = [&](int jr) -> A { return (A)(0.5 * c.f.rdy[jr]); };
   auto rdxv2 = [&](int jv) -> A { return (A)c.f.rdxv2[jv]; };
   auto rdyv2 = [&](int jv) -> A { return (A)c.f.rdyv2[jv]; };
   auto r2d = [&](int kk) -> A { return (A)c.f.r2d[kk]; };
-  auto uA = [&](int jr, int q) -> A { return (jr >= 1 && jr < ny) ? (A)c.s.UA[i3<T>(g, jr, k, q)] : A(0); };
-  auto vA = [&](int jv, int kk, int ii) -> A { return (A)c.s.VT[i3<T>(g, jv, kk, ii)]; };
+  auto uA = [&](int jr, int q) -> A { return (jr >= 1 && jr < ny) ? (A)ldg(c.s.UA, i3u(g, jr, k, q)) : A(0); };
+  auto vA = [&](int jv, int kk, int ii) -> A { return (A)ldg(c.s.VT, i3u(g, jv, kk, ii)); };
   auto ub = [&](int jr, int q) -> A {   // u averaged to integer point q of U row jr
     return A(0.5) * (uA(jr, wrp(q - 1, nx)) + uA(jr, q));
   };
@@ -561,7 +589,7 @@ __global__ void k_l1(Ctx<T> c) {
     if (js <= 0 || js >= ny) return A(0);
     return A(0.5) * (vA(js - 1, kk, ii) + vA(js, kk, ii));
   };
-  const size_t id = i3<T>(g, j, k, i);
+  const unsigned id = i3u(g, j, k, i);
 
   // ---- scalar point: adjoint of Phi (pole-read copies included)
   {
@@ -577,7 +605,7 @@ __global__ void k_l1(Ctx<T> c) {
     if (j == ny - 1) a -= cc * vA(ny - 1, k, i) * AS;
     if (k >= 1) a += amF(j, k - 1, i) * sd(j, k, i) * r2d(k - 1);
     if (k + 1 < nz) a -= amF(j, k + 1, i) * sd(j, k + 1, i) * r2d(k + 1);
-    c.s.AFE[id] = (T)a;
+    stg(c.s.AFE, id, (T)a);
   }
   // ---- U point
   if (interior(j)) {
@@ -600,7 +628,7 @@ __global__ void k_l1(Ctx<T> c) {
         au += A(0.5) * auv;
       }
     }
-    c.s.AUU[id] = (T)au;
+    stg(c.s.AUU, id, (T)au);
     // direct adjoint of U
     A aU = 0;
     {
@@ -618,7 +646,7 @@ __global__ void k_l1(Ctx<T> c) {
       if (k >= 1) aU += amU(j, k - 1, i) * A(0.5) * (sd(j, k, i) + sd(j, k, ip1)) * r2d(k - 1);
       if (k + 1 < nz) aU -= amU(j, k + 1, i) * A(0.5) * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) * r2d(k + 1);
     }
-    c.s.AUD[id] = (T)aU;
+    stg(c.s.AUD, id, (T)aU);
   }
   // ---- V point
   if (j < ny) {
@@ -634,7 +662,7 @@ __global__ void k_l1(Ctx<T> c) {
       if (k + 1 < nz)
         aV -= amV(jv, k + 1, i) * A(0.5) * (sd(jv, k + 1, i) + sd(jv + 1, k + 1, i)) * r2d(k + 1);
     }
-    c.s.AVD[id] = (T)aV;
+    stg(c.s.AVD, id, (T)aV);
     // adjoint of v sin(theta) on this V row
     A avt = 0;
     if (interior(jv)) avt += amF(jv, k, i) * (A)Fe(c, jv + 1, k, i) * rdy2(jv);
@@ -653,7 +681,7 @@ __global__ void k_l1(Ctx<T> c) {
       return amV(js - 1, k, i) * (A)Ve(c, js, k, i) * rdyv2(js - 1) - amV(js, k, i) * (A)Ve(c, js - 1, k, i) * rdyv2(js);
     };
     avt += A(0.5) * (avts(jv) + avts(jv + 1));
-    c.s.AVV[id] = (T)(avt * (A)g.sv[jv]);
+    stg(c.s.AVV, id, (T)(avt * (A)g.sv[jv]));
   }
   // ---- half level h = k (1..nz-1): adjoint of sigma-dot of scalar row j
   if (k >= 1) {
@@ -674,7 +702,7 @@ __global__ void k_l1(Ctx<T> c) {
     };
     if (j >= 1) a += A(0.5) * asdv(j - 1);
     if (j <= ny - 1) a += A(0.5) * asdv(j);
-    c.s.ASD[ih<T>(g, j, h, i)] = (T)a;
+    stg(c.s.ASD, ihu(g, j, h, i), (T)a);
   }
 }
 
@@ -819,48 +847,52 @@ __global__ void k_l3(Ctx<T> c) {
   const double* sD = c.s.psum + PS_AD * 2 * (nz + 1);
   const bool intr = (j >= 1 && j < ny);
   const size_t i2 = (size_t)j * nx + i;
-  // U-point constants
+  // U-point constants (as reciprocals: the level loop only multiplies)
   int n = 1;
-  C dxU = 1, PU = 1;
+  C rdxU = 1, PU = 1, rPU = 1;
   if (intr) {
     const int M = g.M[j];
     n = (M + 1) / 2;
-    dxU = (C)(T)((double)M * g.a * g.s[j] * g.dlam);
+    rdxU = 1.0 / (C)(T)((double)M * g.a * g.s[j] * g.dlam);
     PU = (C)PUe(c, j, i);
+    rPU = 1.0 / PU;
   }
   // V-point constants
-  C PV = 1, dyN = 1, dyS = 1, capD = g.a * g.dlam / g.acap;
+  C PV = 1, rPV = 1, rdyN = 1, rdyS = 1, capD = g.a * g.dlam / g.acap;
   if (j < ny) {
     PV = (C)PVe(c, j, i);
-    if (j >= 1) dyN = (C)(T)(g.a * g.s[j] * g.dth);
-    if (j + 1 <= ny - 1) dyS = (C)(T)(g.a * g.s[j + 1] * g.dth);
+    rPV = 1.0 / PV;
+    if (j >= 1) rdyN = 1.0 / (C)(T)(g.a * g.s[j] * g.dth);
+    if (j + 1 <= ny - 1) rdyS = 1.0 / (C)(T)(g.a * g.s[j + 1] * g.dth);
   }
+  const C svj = j < ny ? (C)(T)g.sv[j] : 0.0;
+  const int ia = wrp(i - n + 1, nx), ib = wrp(i + n, nx);
   C aP = c.s.AP2[i2];
   C aPU = 0, aPV = 0;
   for (int k = 0; k < nz; ++k) {
     asm volatile("" : "+v"(i));
-    const size_t id = i3<T>(g, j, k, i);
+    const unsigned id = i3u(g, j, k, i);
     A3Out o{};
-    if (intr) { o.au = (C)c.s.AUU[id]; o.aud = (C)c.s.AUD[id]; }
-    if (j < ny) { o.avv = (C)c.s.AVV[id]; o.avd = (C)c.s.AVD[id]; }
+    if (intr) { o.au = (C)ldg(c.s.AUU, id); o.aud = (C)ldg(c.s.AUD, id); }
+    if (j < ny) { o.avv = (C)ldg(c.s.AVV, id); o.avd = (C)ldg(c.s.AVD, id); }
     if (intr) {
-      const C aMU = ((C)c.s.AD[i3<T>(g, j, k, wrp(i - n + 1, nx))] - (C)c.s.AD[i3<T>(g, j, k, wrp(i + n, nx))]) / dxU;
-      const C U = (C)c.U[id];
-      c.aiU[id] = (T)((C)c.aiU[id] + o.aud + o.au / PU + PU * aMU);
-      aPU += -U / (PU * PU) * o.au + U * aMU;
+      const C aMU = ((C)ldg(c.s.AD, i3u(g, j, k, ia)) - (C)ldg(c.s.AD, i3u(g, j, k, ib))) * rdxU;
+      const C U = (C)ldg(c.U, id);
+      stg(c.aiU, id, (T)((C)ldg((const T*)c.aiU, id) + o.aud + o.au * rPU + PU * aMU));
+      aPU += -U * (rPU * rPU) * o.au + U * aMU;
     }
     if (j < ny) {
       const int jv = j;
-      const C tN = (jv >= 1) ? (C)c.s.AD[i3<T>(g, jv, k, i)] / dyN : capD * sD[0 * (nz + 1) + k];
-      const C tS = (jv + 1 <= ny - 1) ? (C)c.s.AD[i3<T>(g, jv + 1, k, i)] / dyS : capD * sD[1 * (nz + 1) + k];
-      const C aMV = (C)(T)g.sv[jv] * (tN - tS);
-      const C V = (C)c.V[id];
-      c.aiV[id] = (T)((C)c.aiV[id] + o.avd + o.avv / PV + PV * aMV);
-      aPV += -V / (PV * PV) * o.avv + V * aMV;
+      const C tN = (jv >= 1) ? (C)ldg(c.s.AD, i3u(g, jv, k, i)) * rdyN : capD * sD[0 * (nz + 1) + k];
+      const C tS = (jv + 1 <= ny - 1) ? (C)ldg(c.s.AD, i3u(g, jv + 1, k, i)) * rdyS : capD * sD[1 * (nz + 1) + k];
+      const C aMV = svj * (tN - tS);
+      const C V = (C)ldg(c.V, id);
+      stg(c.aiV, id, (T)((C)ldg((const T*)c.aiV, id) + o.avd + o.avv * rPV + PV * aMV));
+      aPV += -V * (rPV * rPV) * o.avv + V * aMV;
     }
-    const C afe = (C)c.s.AFE[id];
-    if (intr) c.aiF[id] = (T)((C)c.aiF[id] + afe);
-    else c.s.AFE[id] = (T)afe;     // pole copies: aggregated later
+    const C afe = (C)ldg(c.s.AFE, id);
+    if (intr) stg(c.aiF, id, (T)((C)ldg((const T*)c.aiF, id) + afe));
+    else stg(c.s.AFE, id, (T)afe);     // pole copies: aggregated later
   }
   c.s.AP2[i2] = aP;
   c.s.APU2[i2] = aPU;
@@ -1419,6 +1451,7 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   Ctx<T> cf = c;
   cf.jr0 = 1;
   cf.jrs = 1;
+  cf.fwd_all = adapt ? 1 : 0;
   // the row-fused kernel recomputes its rows itself (and writes what the pole rows read)
   if (!rows) hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, cf);
   hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
