@@ -982,18 +982,18 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   const int j = 1 + xcd_row(blockIdx.x, ny - 1);
   const int B = blockDim.x;
   int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
-  T* r = reinterpret_cast<T*>(smem);
+  // LDS cells column-major in two blocks of 13 rows: (row r, column i) at i*13 + r, so that one
+  // address per column index serves every row (the row is the instruction's immediate offset) and
+  // consecutive lanes stride 13 words (no bank conflicts)
+  T* s2 = reinterpret_cast<T*>(smem);   // 2D rows from the forward recompute
+  T* sl = s2 + kAar2D * nx;             // per-level rows
   // 2D rows: P of rows j-1, j, j+1; the meridional l and q differences; the leaped d+l, d+q of
   // row j; reciprocals of P (rows j, j+1) and of its U-point averages (rows j-1, j, j+1)
-  T* sPm = r;            T* sP0 = r + nx;       T* sP1 = r + 2 * nx;
-  T* sdLm = r + 3 * nx;  T* sdL0 = r + 4 * nx;  T* sdQ0 = r + 5 * nx;  T* sDL = r + 6 * nx;   T* sDQ = r + 7 * nx;
-  T* srP0 = r + 8 * nx;  T* srP1 = r + 9 * nx;  T* srUm = r + 10 * nx; T* srU0 = r + 11 * nx; T* srU1 = r + 12 * nx;
+  enum { RPm, RP0, RP1, RdLm, RdL0, RdQ0, RDL, RDQ, RrP0, RrP1, RrUm, RrU0, RrU1 };
   // per-level rows
-  T* q = r + kAar2D * nx;
-  T* sHH = q;            T* sAV = q + nx;       T* sFVm = q + 2 * nx;  T* sFV0 = q + 3 * nx;
-  T* sUVm = q + 4 * nx;  T* sUV0 = q + 5 * nx;  T* sFU0 = q + 6 * nx;  T* sFU1 = q + 7 * nx;
-  T* sAD = q + 8 * nx;   T* sPH = q + 9 * nx;   T* sRT = q + 10 * nx;  T* sMU = q + 11 * nx;
-  T* su = q + 12 * nx;
+  enum { LHH, LAV, LFVm, LFV0, LUVm, LUV0, LFU0, LFU1, LAD, LPH, LRT, LMU, Lu };
+  auto S2 = [&](int row, int col) -> T& { return s2[col * kAar2D + row]; };
+  auto SL = [&](int row, int col) -> T& { return sl[col * kAarLev + row]; };
 
   const bool nPole = (j - 1 == 0);        // scalar row j-1 is the north pole
   const bool sPole = (j + 1 == ny);       // scalar row j+1 is the south pole
@@ -1031,28 +1031,28 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
     if (i < nx) {
       const T Pm = c.s.P[(size_t)(j - 1) * nx + i], P0 = c.s.P[(size_t)j * nx + i];
       const T P1 = c.s.P[(size_t)(j + 1) * nx + i];
-      sPm[i] = Pm;
-      sP0[i] = P0;
-      sP1[i] = P1;
+      S2(RPm, i) = Pm;
+      S2(RP0, i) = P0;
+      S2(RP1, i) = P1;
       const T Lm = c.s.L[(size_t)(j - 1) * nx + i], L0 = c.s.L[(size_t)j * nx + i];
       const T L1 = c.s.L[(size_t)(j + 1) * nx + i];
-      sdLm[i] = L0 - Lm;
-      sdL0[i] = L1 - L0;
-      sdQ0[i] = c.s.Q[(size_t)(j + 1) * nx + i] - c.s.Q[(size_t)j * nx + i];
-      sDL[i] = c.s.DL[(size_t)j * nx + i];
-      sDQ[i] = c.s.DQ[(size_t)j * nx + i];
-      srP0[i] = T(1) / P0;
-      srP1[i] = T(1) / P1;
+      S2(RdLm, i) = L0 - Lm;
+      S2(RdL0, i) = L1 - L0;
+      S2(RdQ0, i) = c.s.Q[(size_t)(j + 1) * nx + i] - c.s.Q[(size_t)j * nx + i];
+      S2(RDL, i) = c.s.DL[(size_t)j * nx + i];
+      S2(RDQ, i) = c.s.DQ[(size_t)j * nx + i];
+      S2(RrP0, i) = T(1) / P0;
+      S2(RrP1, i) = T(1) / P1;
     }
   }
   __syncthreads();
-  auto PUr = [&](const T* sP, int i) -> T { return T(0.5) * (sP[i] + sP[wrp(i + 1, nx)]); };
+  auto PUr = [&](int rP, int i) -> T { return T(0.5) * (S2(rP, i) + S2(rP, wrp(i + 1, nx))); };
   for (int cc = 0; cc < NI; ++cc) {
     const int i = t + cc * B;
     if (i < nx) {
-      srUm[i] = T(1) / PUr(sPm, i);
-      srU0[i] = T(1) / PUr(sP0, i);
-      srU1[i] = T(1) / PUr(sP1, i);
+      S2(RrUm, i) = T(1) / PUr(RPm, i);
+      S2(RrU0, i) = T(1) / PUr(RP0, i);
+      S2(RrU1, i) = T(1) / PUr(RP1, i);
     }
   }
   __syncthreads();
@@ -1095,10 +1095,10 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
         const int i = t + cc * B;
         if (i >= nx) continue;
         const T Fj = vF[u][cc], F1 = vF1[u][cc];
-        const T P0 = sP0[i], P1 = sP1[i];
-        const C rP0 = (C)srP0[i], rP1 = (C)srP1[i];
-        HRj[cc] += clk * (C)(b * Fj * srP0[i]);
-        HR1[cc] += clk * (C)(b * F1 * srP1[i]);
+        const T P0 = S2(RP0, i), P1 = S2(RP1, i);
+        const C rP0 = (C)S2(RrP0, i), rP1 = (C)S2(RrP1, i);
+        HRj[cc] += clk * (C)(b * Fj * S2(RrP0, i));
+        HR1[cc] += clk * (C)(b * F1 * S2(RrP1, i));
         const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * (ch * (C)vq[u][cc]);
         Asj[cc] += -aWPj * rsg * (rP0 * rP0);
         if (!sPole) {
@@ -1171,15 +1171,15 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const T U1 = sPole ? T(0) : pU1[ui], U1m = sPole ? T(0) : pU1[uim];
       const T Vj = pVj[ui], Vjp = pVj[uip];                    // V row j+1/2
       const T Vm = pVm[ui], Vmp = pVm[uip];                    // V row j-1/2
-      const T Pm = sPm[i], P0 = sP0[i], P1 = sP1[i];
+      const T Pm = S2(RPm, i), P0 = S2(RP0, i), P1 = S2(RP1, i);
       // forward: R T', phi'
-      const T RTm = b * Fm / Pm, RTj = b * Fj * srP0[i], RT1 = b * F1 * srP1[i];
+      const T RTm = b * Fm / Pm, RTj = b * Fj * S2(RrP0, i), RT1 = b * F1 * S2(RrP1, i);
       HRj[cc] -= clk * (C)RTj;
       HR1[cc] -= clk * (C)RT1;
       const T PHj = (T)(HRj[cc] + cpk * (C)RTj);
       const T PH1 = (T)(HR1[cc] + cpk * (C)RT1);
-      const T PU0 = PUr(sP0, i);
-      const T uj = Uj * srU0[i];
+      const T PU0 = PUr(RP0, i);
+      const T uj = Uj * S2(RrU0, i);
       // adjoint seeds
       voF[cc] = qFj[ui];
       voU[cc] = qUj[ui];
@@ -1194,13 +1194,13 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       C AD1 = 0;
       if (!sPole) {
         aWP1 = ((A)(b * P1) + (A)(kap * F1)) * (chA * (A)qF1[ui]);
-        const C rP1 = (C)srP1[i];
+        const C rP1 = (C)S2(RrP1, i);
         const C aSK1 = -(C)aWP1 * rsg * (rP1 * rP1);
         As1[cc] -= aSK1;
         const C aPi1 = -g.p0 * ch * (C)c.aoP[(size_t)(j + 1) * nx + i];
         AD1 = 0.5 * dsg * aSK1 + dsg * (aPi1 + As1[cc]);
       }
-      const C rP0 = (C)srP0[i];
+      const C rP0 = (C)S2(RrP0, i);
       const C aSKj = -(C)aWPj * rsg * (rP0 * rP0);
       Asj[cc] -= aSKj;
       const C aPij = -g.p0 * ch * (C)c.aoP[(size_t)j * nx + i];
@@ -1214,15 +1214,15 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       // U row j+1 (Coriolis read of V row j+1/2)
       A FU1 = 0;
       if (!sPole) {
-        const T fs1 = f1 + (U1 * srU1[i]) * cot1;
+        const T fs1 = f1 + (U1 * S2(RrU1, i)) * cot1;
         FU1 = (A)fs1 * (chA * (A)qU1[ui]);
       }
       // V rows j-1/2 (jv = j-1) and j+1/2 (jv = j)
-      auto vrow = [&](int jv, const T* sPa, const T* sPb, const T* sRa, const T* sRb, T Ua, T Uam, T Ub, T Ubm,
+      auto vrow = [&](int jv, int sPa, int sPb, int sRa, int sRb, T Ua, T Uam, T Ub, T Ubm,
                       A gv, A& MV, A& FV, A& UV) {
-        const T PV = T(0.5) * (sPa[i] + sPb[i]);
-        const T ua = (jv >= 1) ? Ua * sRa[i] : T(0), uam = (jv >= 1) ? Uam * sRa[im] : T(0);
-        const T ub = (jv + 1 <= ny - 1) ? Ub * sRb[i] : T(0), ubm = (jv + 1 <= ny - 1) ? Ubm * sRb[im] : T(0);
+        const T PV = T(0.5) * (S2(sPa, i) + S2(sPb, i));
+        const T ua = (jv >= 1) ? Ua * S2(sRa, i) : T(0), uam = (jv >= 1) ? Uam * S2(sRa, im) : T(0);
+        const T ub = (jv + 1 <= ny - 1) ? Ub * S2(sRb, i) : T(0), ubm = (jv + 1 <= ny - 1) ? Ubm * S2(sRb, im) : T(0);
         const T UU = T(0.25) * (Uam + Ua + Ubm + Ub);
         const T uu = T(0.25) * (uam + ua + ubm + ub);
         const T fsv = (T)g.fv[jv] + uu * (T)(g.cotv[jv] / g.a);
@@ -1231,22 +1231,22 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
         UV = (A)UU * gv * (A)(g.cotv[jv] / g.a);
       };
       A MVm, FVm, UVm, MVj, FVj, UVj;
-      vrow(j - 1, sPm, sP0, srUm, srU0, Um, Umm, Uj, Ujm, gVm, MVm, FVm, UVm);
-      vrow(j, sP0, sP1, srU0, srU1, Uj, Ujm, U1, U1m, gV, MVj, FVj, UVj);
+      vrow(j - 1, RPm, RP0, RrUm, RrU0, Um, Umm, Uj, Ujm, gVm, MVm, FVm, UVm);
+      vrow(j, RP0, RP1, RrU0, RrU1, Uj, Ujm, U1, U1m, gV, MVj, FVj, UVj);
       // LDS rows
-      sHH[i] = (T)HH;
-      sAV[i] = (T)aWPj;
-      sFVm[i] = (T)FVm;
-      sFV0[i] = (T)FVj;
-      sUVm[i] = (T)UVm;
-      sUV0[i] = (T)UVj;
-      sFU0[i] = (T)FUj;
-      sFU1[i] = (T)FU1;
-      sAD[i] = (T)ADj;
-      sPH[i] = PHj;
-      sRT[i] = RTj;
-      sMU[i] = PU0 * Uj;
-      su[i] = uj;
+      SL(LHH, i) = (T)HH;
+      SL(LAV, i) = (T)aWPj;
+      SL(LFVm, i) = (T)FVm;
+      SL(LFV0, i) = (T)FVj;
+      SL(LUVm, i) = (T)UVm;
+      SL(LUV0, i) = (T)UVj;
+      SL(LFU0, i) = (T)FUj;
+      SL(LFU1, i) = (T)FU1;
+      SL(LAD, i) = (T)ADj;
+      SL(LPH, i) = PHj;
+      SL(LRT, i) = RTj;
+      SL(LMU, i) = PU0 * Uj;
+      SL(Lu, i) = uj;
       // carried values
       vRTm[cc] = RTm; vRT1[cc] = RT1; vPH1[cc] = PH1;
       vFj[cc] = Fj; vUj[cc] = Uj; vVj[cc] = Vj; vVm[cc] = Vm;
@@ -1285,42 +1285,42 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       if (i >= nx) continue;
       const int im = wrp(i - 1, nx), ip = wrp(i + 1, nx);
       const size_t oj = (size_t)j * row3 + (size_t)k * nx + i;
-      const T vRTj = sRT[i], vPHj = sPH[i];
-      const A vAVj = (A)sAV[i], vADj = (A)sAD[i], vHH = (A)sHH[i];
-      const A vUVm = (A)sUVm[i], vUVj = (A)sUV0[i], vFVm = (A)sFVm[i], vFVj = (A)sFV0[i];
-      const A vFUj = (A)sFU0[i], vFU1 = (A)sFU1[i];
-      const T PU0 = PUr(sP0, i);
-      const T PV0 = T(0.5) * (sP0[i] + sP1[i]), PVm = T(0.5) * (sPm[i] + sP0[i]);
+      const T vRTj = SL(LRT, i), vPHj = SL(LPH, i);
+      const A vAVj = (A)SL(LAV, i), vADj = (A)SL(LAD, i), vHH = (A)SL(LHH, i);
+      const A vUVm = (A)SL(LUVm, i), vUVj = (A)SL(LUV0, i), vFVm = (A)SL(LFVm, i), vFVj = (A)SL(LFV0, i);
+      const A vFUj = (A)SL(LFU0, i), vFU1 = (A)SL(LFU1, i);
+      const T PU0 = PUr(RP0, i);
+      const T PV0 = T(0.5) * (S2(RP0, i) + S2(RP1, i)), PVm = T(0.5) * (S2(RPm, i) + S2(RP0, i));
       // forward D, S, omega/p (as the forward recompute forms them)
-      const T D = (sMU[wrp(i + n - 1, nx)] - sMU[wrp(i - n, nx)]) * rdxT +
+      const T D = (SL(LMU, wrp(i + n - 1, nx)) - SL(LMU, wrp(i - n, nx))) * rdxT +
                   (svj * (PV0 * vVj[cc]) - svm * (PVm * vVm[cc])) * rdySjT;
       const T rPV0 = T(1) / PV0, rPVm = T(1) / PVm;
       const C SkC = Sj[cc];
       const T Sk = (T)SkC;
       Sj[cc] += (C)D * dsg;
-      const T zon = T(0.5) * (su[i] * sDL[i] + su[im] * sDL[im]);
-      const T mer = T(0.5) * ((vVj[cc] * rPV0) * sdL0[i] + (vVm[cc] * rPVm) * sdLm[i]) * rdyAT;
-      const C rPc = (C)srP0[i], rP2c = rPc * rPc;
+      const T zon = T(0.5) * (SL(Lu, i) * S2(RDL, i) + SL(Lu, im) * S2(RDL, im));
+      const T mer = T(0.5) * ((vVj[cc] * rPV0) * S2(RdL0, i) + (vVm[cc] * rPVm) * S2(RdLm, i)) * rdyAT;
+      const C rPc = (C)S2(RrP0, i), rP2c = rPc * rPc;
       const T WP = (T)(((C)zon + (C)mer) - (SkC + 0.5 * (C)D * dsg) * rsg * rP2c);
       const A wp = (A)WP, gF = chA * (A)voF[cc], aWP = vAVj;
-      const A rPA = (A)srP0[i], rP2A = rPA * rPA;
+      const A rPA = (A)S2(RrP0, i), rP2A = rPA * rPA;
       const A AFE = (A)kap * wp * gF;
       const A AP3 = (A)b * wp * gF + A(2) * ((A)Sk + A(0.5) * (A)D * (A)dsg) * (A)rsg * (rP2A * rPA) * aWP;
       // U point: pressure gradient seen by U row j
-      const T dphi = (sPH[wrp(i + n, nx)] - sPH[wrp(i + 1 - n, nx)]) * rdxT;
-      const T rtx = T(0.5) * (vRTj + sRT[ip]);
-      const A pgf = (A)dphi + RT0A * (A)sDQ[i] + (A)rtx * (A)sDL[i];
+      const T dphi = (SL(LPH, wrp(i + n, nx)) - SL(LPH, wrp(i + 1 - n, nx))) * rdxT;
+      const T rtx = T(0.5) * (vRTj + SL(LRT, ip));
+      const A pgf = (A)dphi + RT0A * (A)S2(RDQ, i) + (A)rtx * (A)S2(RDL, i);
       const A gU = chA * (A)voU[cc], gV = chA * (A)voV[cc];
       const A APU3 = -pgf * gU;
       // V point: pressure gradient seen by V row j+1/2
-      const A pgfV = ((A)(vPH1[cc] - vPHj) + RT0A * (A)sdQ0[i] +
-                      (A)(T(0.5) * (vRTj + vRT1[cc])) * (A)sdL0[i]) * rdyAA;
+      const A pgfV = ((A)(vPH1[cc] - vPHj) + RT0A * (A)S2(RdQ0, i) +
+                      (A)(T(0.5) * (vRTj + vRT1[cc])) * (A)S2(RdL0, i)) * rdyAA;
       const A APV3 = -pgfV * gV;
       // gathers: scalar point
       const A mM = (A)vMVm[cc], mJ = (A)vMVj[cc];
-      const A aPHI = ((A)sHH[wrp(i - n, nx)] - (A)sHH[wrp(i + n - 1, nx)]) * rdxA + mM - mJ;
-      const A aRT = A(0.5) * ((A)sHH[i] * (A)sDL[i] + (A)sHH[im] * (A)sDL[im]) +
-                    A(0.5) * (A)sdLm[i] * mM + A(0.5) * (A)sdL0[i] * mJ;
+      const A aPHI = ((A)SL(LHH, wrp(i - n, nx)) - (A)SL(LHH, wrp(i + n - 1, nx))) * rdxA + mM - mJ;
+      const A aRT = A(0.5) * ((A)SL(LHH, i) * (A)S2(RDL, i) + (A)SL(LHH, im) * (A)S2(RDL, im)) +
+                    A(0.5) * (A)S2(RdLm, i) * mM + A(0.5) * (A)S2(RdL0, i) * mJ;
       const A cvgm = (nPole ? (A)(sVG[0 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAVm[cc]) + A(0.5) * vAVj;
       const A cvgj = A(0.5) * vAVj + (sPole ? (A)(sVG[1 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAV1[cc]);
       const A rtym = A(0.5) * ((A)vRTm[cc] + (A)vRTj), rtyj = A(0.5) * ((A)vRTj + (A)vRT1[cc]);
@@ -1328,22 +1328,22 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const A aL = (wm + rtym * mM) - (wj + rtyj * mJ);
       const A aQ = RT0A * mM - RT0A * mJ;
       // gathers: U point
-      const A dl = (A)sDL[i];
-      const A au = (A)vAUU[cc] + A(0.5) * dl * (vAVj + (A)sAV[ip]) +
-                   A(0.25) * (vUVm + (A)sUVm[ip] + vUVj + (A)sUV0[ip]);
-      const A aUd = A(0.25) * (vFVm + (A)sFVm[ip] + vFVj + (A)sFV0[ip]);
-      const A rPUc = (A)srU0[i];
-      const A u = (A)(vUj[cc] * srU0[i]);
-      const A rtxA = A(0.5) * ((A)vRTj + (A)sRT[ip]);
-      const A adl = A(0.5) * u * (vAVj + (A)sAV[ip]) + rtxA * vHH;
+      const A dl = (A)S2(RDL, i);
+      const A au = (A)vAUU[cc] + A(0.5) * dl * (vAVj + (A)SL(LAV, ip)) +
+                   A(0.25) * (vUVm + (A)SL(LUVm, ip) + vUVj + (A)SL(LUV0, ip));
+      const A aUd = A(0.25) * (vFVm + (A)SL(LFVm, ip) + vFVj + (A)SL(LFV0, ip));
+      const A rPUc = (A)S2(RrU0, i);
+      const A u = (A)(vUj[cc] * S2(RrU0, i));
+      const A rtxA = A(0.5) * ((A)vRTj + (A)SL(LRT, ip));
+      const A adl = A(0.5) * u * (vAVj + (A)SL(LAV, ip)) + rtxA * vHH;
       const A adq = RT0A * vHH;
       // gathers: V point
-      const A avv = (A)sdL0[i] * raDyA * cvgj;
-      A aVd = (A)sFU0[im] + vFUj;
-      if (!sPole) aVd += (A)sFU1[im] + vFU1;
+      const A avv = (A)S2(RdL0, i) * raDyA * cvgj;
+      A aVd = (A)SL(LFU0, im) + vFUj;
+      if (!sPole) aVd += (A)SL(LFU1, im) + vFU1;
       const A avd = A(-0.25) * aVd;
       // divergence and velocity transposes
-      const A aMU = ((A)sAD[wrp(i - n + 1, nx)] - (A)sAD[wrp(i + n, nx)]) * rdxA;
+      const A aMU = ((A)SL(LAD, wrp(i - n + 1, nx)) - (A)SL(LAD, wrp(i + n, nx))) * rdxA;
       const A PUc = (A)PU0, Uc = (A)vUj[cc];
       c.aiU[oj] = (T)((C)aiU0[cc] + (C)(aUd + au * rPUc + PUc * aMU));
       const A aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;
