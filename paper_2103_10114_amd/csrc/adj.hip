@@ -270,44 +270,49 @@ __global__ void __launch_bounds__(256) k_f1p_red(Ctx<T> c) {
   }
 }
 
-// pole columns, step 2: the column scans on the pole scalars, written to the whole row
+// pole columns, step 2: the column scans on the pole scalars (each block redoes them over the nz
+// scalars, in the same order) and the values of one level, written to the whole row
 template <typename T>
 __global__ void __launch_bounds__(256) k_f1p(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int p = blockIdx.x;
+  const int k = blockIdx.x, p = blockIdx.y;
   const int j = p == 0 ? 0 : g.ny;
   const int nx = g.nx, nz = g.nz, t = threadIdx.x;
   const T b = (T)g.b;
   const T Pp = P2(c, j, 0);
+  auto RTl = [&](int kk) -> T { return b * (T)c.pin[p * (nz + 1) + kk] / Pp; };
+  auto Dl = [&](int kk) -> C { return (C)c.s.D[i3<T>(g, j, kk, 0)]; };
   C H = 0, Pi = 0;
-  for (int k = 0; k < nz; ++k) {
-    H += g.cl[k] * (C)(b * (T)c.pin[p * (nz + 1) + k] / Pp);
-    Pi += (C)c.s.D[i3<T>(g, j, k, 0)] * g.dsig[k];
+  for (int kk = 0; kk < nz; ++kk) {
+    H += g.cl[kk] * (C)RTl(kk);
+    Pi += Dl(kk) * g.dsig[kk];
+  }
+  C R = 0, S = 0;
+  for (int kk = 0; kk < k; ++kk) {
+    R += g.cl[kk] * (C)RTl(kk);
+    S += Dl(kk) * g.dsig[kk];
   }
   const C P0s = (C)Pp * (C)Pp;
-  C R = 0, S = 0;
-  for (int k = 0; k < nz; ++k) {
-    const T RT = b * (T)c.pin[p * (nz + 1) + k] / Pp;
-    R += g.cl[k] * (C)RT;
-    const T PHI = (T)(H - R + g.cpk[k] * (C)RT);
-    const C D = (C)c.s.D[i3<T>(g, j, k, 0)];
-    const C vg = (C)c.s.WP[i3<T>(g, j, k, 0)];
-    const T WP = (T)(vg - (S + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s));
-    const T Sk = (T)S;
-    S += D * g.dsig[k];
-    const T SDn = (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - S) / P0s) : T(0);
-    __syncthreads();   // every thread has read this level's D and v.grad(l) before WP is overwritten
-    for (int i = t; i < nx; i += blockDim.x) {
-      const size_t id = i3<T>(g, j, k, i);
-      c.s.RT[id] = RT;
-      c.s.PHI[id] = PHI;
-      c.s.WP[id] = WP;
-      c.s.S[ih<T>(g, j, k, i)] = Sk;
-      c.s.SD[ih<T>(g, j, k + 1, i)] = SDn;
-      if (k == 0) c.s.SD[ih<T>(g, j, 0, i)] = T(0);
-    }
+  const T RT = RTl(k);
+  R += g.cl[k] * (C)RT;
+  const T PHI = (T)(H - R + g.cpk[k] * (C)RT);
+  const C D = Dl(k);
+  const C vg = (C)c.s.WP[i3<T>(g, j, k, 0)];
+  const T WP = (T)(vg - (S + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s));
+  const T Sk = (T)S;
+  S += D * g.dsig[k];
+  const T SDn = (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - S) / P0s) : T(0);
+  __syncthreads();   // every thread has read this level's v.grad(l) before WP is overwritten
+  for (int i = t; i < nx; i += blockDim.x) {
+    const size_t id = i3<T>(g, j, k, i);
+    c.s.RT[id] = RT;
+    c.s.PHI[id] = PHI;
+    c.s.WP[id] = WP;
+    c.s.S[ih<T>(g, j, k, i)] = Sk;
+    c.s.SD[ih<T>(g, j, k + 1, i)] = SDn;
+    if (k == 0) c.s.SD[ih<T>(g, j, 0, i)] = T(0);
+    if (k == nz - 1) c.s.S[ih<T>(g, j, nz, i)] = (T)S;
   }
-  for (int i = t; i < nx; i += blockDim.x) c.s.S[ih<T>(g, j, nz, i)] = (T)S;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -362,8 +367,22 @@ __global__ void k_base_pole(Ctx<T> c) {
 // ------------------------------------------------------------------------------------------------
 // adaptation: first transposes (Phi and p_s tendencies, omega/p, pressure gradients, Coriolis)
 // ------------------------------------------------------------------------------------------------
+// The scalar part takes the point's output adjoint of Phi, omega/p, S and D as loaded by the caller.
 template <typename T>
-__device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C& aWPo, C& aSKo, C& aDo) {
+struct A1In { T aoF, wp, S, D; };
+
+template <typename T>
+__device__ __forceinline__ A1In<T> a1_load(const Ctx<T>& c, int j, int k, int i) {
+  const unsigned id = i3u(c.g, j, k, i);
+  return A1In<T>{ldg(c.aoF, id), ldg((const T*)c.s.WP, id), ldg((const T*)c.s.S, ihu(c.g, j, k, i)),
+                 ldg((const T*)c.s.D, id)};
+}
+
+// PM: the parts as a compile-time mask (0: the context's)
+template <typename T, int PM = 0>
+__device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, const A1In<T>& in, C& aWPo, C& aSKo,
+                                         C& aDo) {
+  const int parts = PM ? PM : c.parts;
   aWPo = aSKo = aDo = 0;
   const GeoDev& g = c.g;
   const int nx = g.nx, ny = g.ny;
@@ -371,15 +390,15 @@ __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C
   const C ch = c.ch;
   const size_t id = i3<T>(g, j, k, i);
   // scalar point (every row; pole rows per stored copy)
-  if (c.parts & 1) {
+  if (parts & 1) {
     const T P = P2(c, j, i);
     const T F = Fe(c, j, k, i);
-    const C gF = ch * (C)c.aoF[id];
-    const C wp = (C)c.s.WP[id];
+    const C gF = ch * (C)in.aoF;
+    const C wp = (C)in.wp;
     const C aWP = ((C)(b * P) + (C)(kap * F)) * gF;
     const C P2c = (C)P * (C)P;
-    const C Sk = (C)c.s.S[ih<T>(g, j, k, i)];
-    const C D = (C)c.s.D[id];
+    const C Sk = (C)in.S;
+    const C D = (C)in.D;
     c.s.AVGL[id] = (T)aWP;
     aWPo = aWP;
     aSKo = -aWP / (g.sig[k] * P2c);
@@ -388,7 +407,7 @@ __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C
     c.s.AP3[id] = (T)((C)b * wp * gF + 2.0 * (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P2c * (C)P) * aWP);
   }
   // U point (interior rows)
-  if ((c.parts & 2) && j >= 1 && j < ny) {
+  if ((parts & 2) && j >= 1 && j < ny) {
     const int M = g.M[j], n = (M + 1) / 2;
     const T dx = (T)((double)M * g.a * g.s[j] * g.dlam);
     const int ip1 = wrp(i + 1, nx);
@@ -406,7 +425,7 @@ __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C
     c.s.APU3[id] = (T)(-pgf * gU);
   }
   // V point (V rows)
-  if ((c.parts & 4) && j < ny) {
+  if ((parts & 4) && j < ny) {
     const int jv = j;
     const int im1 = wrp(i - 1, nx);
     const C gV = ch * (C)c.aoV[id];
@@ -429,23 +448,46 @@ __device__ __forceinline__ void a1_point(const Ctx<T>& c, int j, int k, int i, C
 // First adaptation transposes (Phi and p_s tendencies, omega/p, pressure gradients, Coriolis) per
 // column, bottom to top, with the suffix transpose of the column prefix sums folded in:
 // aD_l = (direct part) + dsig_l (aPi + sum_{k>l} aS_k), aPi = -p0 ch aoP.
-template <typename T>
+template <typename T, int KB, int PM>
 __global__ void k_a12(Ctx<T> c) {
   const GeoDev& g = c.g;
   const int j = c.jr0 + c.jrs * (int)blockIdx.y;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const C aPi = -g.p0 * c.ch * (C)c.aoP[(size_t)j * g.nx + i];
+  const bool sc = (PM ? PM : c.parts) & 1;
   C acc = 0;
-  for (int k = g.nz - 1; k >= 0; --k) {
-    // opaque column index: addresses are formed per level rather than held as per-array
+  // levels in batches of KB, top of the batch first: the scalar-point loads of a batch are all in
+  // flight before its column sums
+  for (int k0 = g.nz - 1; k0 >= 0; k0 -= KB) {
+    // opaque column index: addresses are formed per batch rather than held as per-array
     // induction variables across the loop
     asm volatile("" : "+v"(i));
-    C aWP, aSK, aD;
-    a1_point(c, j, k, i, aWP, aSK, aD);
-    if (c.parts & 1) c.s.AD[i3<T>(g, j, k, i)] = (T)(aD + g.dsig[k] * (aPi + acc));
-    acc += aSK;
+    A1In<T> in[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) in[u] = sc ? a1_load(c, j, k0 - u >= 0 ? k0 - u : 0, i) : A1In<T>{};
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = k0 - u;
+      if (k < 0) break;
+      C aWP, aSK, aD;
+      a1_point<T, PM>(c, j, k, i, in[u], aWP, aSK, aD);
+      if (sc) c.s.AD[i3<T>(g, j, k, i)] = (T)(aD + g.dsig[k] * (aPi + acc));
+      acc += aSK;
+    }
   }
+}
+
+// The first adaptation transposes without the scalar points' column sums (parts without bit 1):
+// levels are independent, one thread per (column, level, row).
+template <typename T>
+__global__ void k_a1lev(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.z, k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  C aWP, aSK, aD;
+  a1_point(c, j, k, i, A1In<T>{}, aWP, aSK, aD);
 }
 
 // gathers of the adaptation transposes at scalar, U and V points
@@ -1455,7 +1497,7 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   // the row-fused kernel recomputes its rows itself (and writes what the pole rows read)
   if (!rows) hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, cf);
   hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
-  hipLaunchKernelGGL((k_f1p<T>), dim3(2), dim3(256), 0, s, c);
+  hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, s, c);
   if (c.abU) {
     // interior rows' base transpose is folded into the row-fused kernel; V row 1/2 stays here
     hipLaunchKernelGGL((k_base<T>), rows ? dim3(gx, nz, 1) : g3, dim3(tb), 0, s, c);
@@ -1480,7 +1522,7 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     cp.jr0 = 0;
     cp.jrs = ny;
     cp.parts = 1;   // scalar points of the pole rows (their sums feed the interior rows)
-    hipLaunchKernelGGL((k_a12<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
+    hipLaunchKernelGGL((k_a12<T, 6, 1>), dim3(gx, 2), dim3(tb), 0, s, cp);
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
                        (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL,
@@ -1489,12 +1531,12 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     if (e != hipSuccess) return e;
     Ctx<T> cv = c;   // V row 1/2: reads phi' and R T' of row 1, written by the row-fused kernel
     cv.parts = 4;
-    hipLaunchKernelGGL((k_a12<T>), dim3(gx, 1), dim3(tb), 0, s, cv);
+    hipLaunchKernelGGL((k_a1lev<T>), dim3(gx, nz, 1), dim3(tb), 0, s, cv);
     cp.parts = 7;
     hipLaunchKernelGGL((k_a3t1<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
     hipLaunchKernelGGL((k_a4<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
   } else {
-    hipLaunchKernelGGL((k_a12<T>), g2, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_a12<T, 1, 0>), g2, dim3(tb), 0, s, c);
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
                        (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL,
