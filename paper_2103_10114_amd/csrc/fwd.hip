@@ -356,13 +356,17 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
   const GeoDev& g = A.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int B = blockDim.x, t = threadIdx.x;
+  // LDS cells column-major, 27 words per column: the 13 2D rows, then the two buffers of 7 level
+  // rows; one address per column index serves every row (the row is an immediate offset) and
+  // consecutive lanes stride 27 words (no bank conflicts)
+  constexpr int RS = kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev;
   T* r = reinterpret_cast<T*>(smem);
-  T* sP0 = r;            T* srP0 = r + nx;      T* srP1 = r + 2 * nx;  T* srU0 = r + 3 * nx;
-  T* srU1 = r + 4 * nx;  T* sDl = r + 5 * nx;   T* sDq = r + 6 * nx;   T* sPV0 = r + 7 * nx;
-  T* sPVm = r + 8 * nx;  T* sgN = r + 9 * nx;   T* sgS = r + 10 * nx;  T* sdL = r + 11 * nx;
-  T* sdQ = r + 12 * nx;
-  T* lev0 = r + kAdaptPipeRows2D * nx;            // [2][7][nx]
-  const size_t bufStride = (size_t)kAdaptPipeRowsLev * nx;
+  auto S2 = [&](int row, int col) -> T& { return r[col * RS + row]; };
+  auto SB = [&](int bsel, int row, int col) -> T& {
+    return r[col * RS + kAdaptPipeRows2D + bsel * kAdaptPipeRowsLev + row];
+  };
+  enum { RP0, RrP0, RrP1, RrU0, RrU1, RDl, RDq, RPV0, RPVm, RgN, RgS, RdL, RdQ };
+  enum { BPhi, BMU, BF, BU0, BU1, BV0, BVm };
   double* sCap = reinterpret_cast<double*>(smem + ((((size_t)kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev) * nx * sizeof(T) + 15) & ~size_t(15)));
 
   const bool isPole = (j == 0 || j == ny);
@@ -378,41 +382,40 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
   };
 
   // ---- 2D rows.  Temporaries (P, l, q of the neighbour rows) live in the level buffers.
-  T* tP1 = lev0;          T* tL0 = lev0 + nx;     T* tQ0 = lev0 + 2 * nx;
-  T* tPa = lev0 + 3 * nx; T* tLa = lev0 + 4 * nx;  // pole rows: P and l of the adjacent row
+  // (tP1, tL0, tQ0 and, for pole rows, P and l of the adjacent row in rows 0..4 of buffer 0)
   for (int c = 0; c < NI; ++c) {
     const int i = t + c * B;
     if (i < nx) {
       const T ps0 = psA(j, i);
       const T P0 = tsqrt<T>(ps0 / p0), L0 = tlog<T>(ps0 / p0);
       const T Q0 = L0 + (T)g.phis[(size_t)j * nx + i] / RT0;
-      sP0[i] = P0;
-      srP0[i] = T(1) / P0;
-      tL0[i] = L0;
-      tQ0[i] = Q0;
+      S2(RP0, i) = P0;
+      S2(RrP0, i) = T(1) / P0;
+      SB(0, 1, i) = L0;
+      SB(0, 2, i) = Q0;
       T P1 = T(1), L1 = T(0);
       if (hasV) {
         const T ps1 = psA(j + 1, i);
         P1 = tsqrt<T>(ps1 / p0);
         L1 = tlog<T>(ps1 / p0);
         const T Q1 = L1 + (T)g.phis[(size_t)(j + 1) * nx + i] / RT0;
-        tP1[i] = P1;
-        srP1[i] = T(1) / P1;
+        SB(0, 0, i) = P1;
+        S2(RrP1, i) = T(1) / P1;
         const T PV0 = T(0.5) * (P0 + P1);
-        sPV0[i] = PV0;
-        sgN[i] = (L1 - L0) / PV0;
-        sdL[i] = L1 - L0;
-        sdQ[i] = Q1 - Q0;
+        S2(RPV0, i) = PV0;
+        S2(RgN, i) = (L1 - L0) / PV0;
+        S2(RdL, i) = L1 - L0;
+        S2(RdQ, i) = Q1 - Q0;
       }
       if (j >= 1) {
         const T psm = psA(j - 1, i);
         const T Pm = tsqrt<T>(psm / p0), Lm = tlog<T>(psm / p0);
         const T PVm = T(0.5) * (Pm + P0);
-        sPVm[i] = PVm;
-        sgS[i] = (L0 - Lm) / PVm;
-        if (j == ny) { tPa[i] = Pm; tLa[i] = Lm; }
+        S2(RPVm, i) = PVm;
+        S2(RgS, i) = (L0 - Lm) / PVm;
+        if (j == ny) { SB(0, 3, i) = Pm; SB(0, 4, i) = Lm; }
       }
-      if (j == 0) { tPa[i] = P1; tLa[i] = L1; }
+      if (j == 0) { SB(0, 3, i) = P1; SB(0, 4, i) = L1; }
     }
   }
   __syncthreads();
@@ -423,25 +426,25 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
     const int i = t + c * B;
     if (i < nx) {
       const int ip = wrp(i + 1, nx);
-      srU0[i] = T(2) / (sP0[i] + sP0[ip]);
-      if (hasV) srU1[i] = T(2) / (tP1[i] + tP1[ip]);
+      S2(RrU0, i) = T(2) / (S2(RP0, i) + S2(RP0, ip));
+      if (hasV) S2(RrU1, i) = T(2) / (SB(0, 0, i) + SB(0, 0, ip));
       if (!isPole) {
-        sDl[i] = (tL0[wrp(i + nj, nx)] - tL0[wrp(i + 1 - nj, nx)]) * rdx;
-        sDq[i] = (tQ0[wrp(i + nj, nx)] - tQ0[wrp(i + 1 - nj, nx)]) * rdx;
+        S2(RDl, i) = (SB(0, 1, wrp(i + nj, nx)) - SB(0, 1, wrp(i + 1 - nj, nx))) * rdx;
+        S2(RDq, i) = (SB(0, 2, wrp(i + nj, nx)) - SB(0, 2, wrp(i + 1 - nj, nx))) * rdx;
       }
     }
   }
   if (isPole && t < 64) {
     const int jva = (j == 0) ? 0 : ny - 1;
-    const T Pp = sP0[0], lp = tL0[0];
+    const T Pp = S2(RP0, 0), lp = SB(0, 1, 0);
     for (int k = 0; k < nz; ++k) {
       const T* pV = A.inV + (size_t)jva * row3 + (size_t)k * nx;
       C s1 = 0, s2 = 0;
       for (int i = t; i < nx; i += 64) {
-        const T pv = T(0.5) * (Pp + tPa[i]);
+        const T pv = T(0.5) * (Pp + SB(0, 3, i));
         const T vv = pV[i];
         s1 += (C)(pv * vv);
-        s2 += (C)((vv / pv) * (j == 0 ? (tLa[i] - lp) : (lp - tLa[i])));
+        s2 += (C)((vv / pv) * (j == 0 ? (SB(0, 4, i) - lp) : (lp - SB(0, 4, i))));
       }
       s1 = wave_sum(s1);
       s2 = wave_sum(s2);
@@ -459,8 +462,8 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
-      rp0[c] = (i < nx) ? b * srP0[i] : T(0);
-      rp1[c] = (i < nx) ? b * srP1[i] : T(0);
+      rp0[c] = (i < nx) ? b * S2(RrP0, i) : T(0);
+      rp1[c] = (i < nx) ? b * S2(RrP1, i) : T(0);
     }
     const T* pF0 = isPole ? nullptr : A.inF + (size_t)j * row3;
     const T* pF1 = (j + 1 < ny) ? A.inF + (size_t)(j + 1) * row3 : nullptr;
@@ -529,36 +532,34 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
   };
   // R T' and phi' of rows j and j+1 at the current level (registers)
   T RTj[NI], RTj1[NI], phij[NI], phij1[NI];
-  auto commit = [&](int k, T* buf) {
+  auto commit = [&](int k, int bs) {
     const C clk = g.cl[k], cpk = g.cpk[k];
-    T* bPhi = buf;          T* bMU = buf + nx;      T* bF = buf + 2 * nx;  T* bU0 = buf + 3 * nx;
-    T* bU1 = buf + 4 * nx;  T* bV0 = buf + 5 * nx;  T* bVm = buf + 6 * nx;
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
       RTj[c] = RTj1[c] = phij[c] = phij1[c] = T(0);
       if (i < nx) {
-        RTj[c] = b * nF0[c] * srP0[i];
-        bF[i] = nF0[c];
-        bU0[i] = nU0[c];
-        bMU[i] = T(0.5) * (sP0[i] + sP0[wrp(i + 1, nx)]) * nU0[c];
+        RTj[c] = b * nF0[c] * S2(RrP0, i);
+        SB(bs, BF, i) = nF0[c];
+        SB(bs, BU0, i) = nU0[c];
+        SB(bs, BMU, i) = T(0.5) * (S2(RP0, i) + S2(RP0, wrp(i + 1, nx))) * nU0[c];
         if (hasV) {
           Q0c[c] -= clk * (C)RTj[c];
           phij[c] = (T)(Q0c[c] + cpk * (C)RTj[c]);
-          RTj1[c] = b * nF1[c] * srP1[i];
+          RTj1[c] = b * nF1[c] * S2(RrP1, i);
           Q1c[c] -= clk * (C)RTj1[c];
           phij1[c] = (T)(Q1c[c] + cpk * (C)RTj1[c]);
-          bU1[i] = nU1[c];
-          bV0[i] = nV0[c];
+          SB(bs, BU1, i) = nU1[c];
+          SB(bs, BV0, i) = nV0[c];
         }
-        bVm[i] = nVm[c];
-        bPhi[i] = phij[c];
+        SB(bs, BVm, i) = nVm[c];
+        SB(bs, BPhi, i) = phij[c];
       }
     }
   };
 
   fetch(0);
-  commit(0, lev0);
+  commit(0, 0);
   __syncthreads();
 
   C Sp = 0;
@@ -572,10 +573,7 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
 #pragma unroll 1
   for (int k = 0; k < nz; ++k) {
     if (k + 1 < nz) fetch(k + 1);
-    T* buf = lev0 + (size_t)(k & 1) * bufStride;
-    const T* bPhi = buf;          const T* bMU = buf + nx;      const T* bF = buf + 2 * nx;
-    const T* bU0 = buf + 3 * nx;  const T* bU1 = buf + 4 * nx;  const T* bV0 = buf + 5 * nx;
-    const T* bVm = buf + 6 * nx;
+    const int bs = k & 1;
     const C clk = g.cl[k];
     (void)clk;
     const C dsg = g.dsig[k], rsg = 1.0 / g.sig[k];
@@ -595,31 +593,31 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         const unsigned idx = (unsigned)i;
         const T baseF = gbF[idx], baseU = gbU[idx];
         const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
-        const T Vn = bV0[i], Vs = bVm[i];
-        const T D = (bMU[wrp(i + nj - 1, nx)] - bMU[wrp(i - nj, nx)]) * rdx +
-                    (svj * (sPV0[i] * Vn) - svm * (sPVm[i] * Vs)) * rdyS;
+        const T Vn = SB(bs, BV0, i), Vs = SB(bs, BVm, i);
+        const T D = (SB(bs, BMU, wrp(i + nj - 1, nx)) - SB(bs, BMU, wrp(i - nj, nx))) * rdx +
+                    (svj * (S2(RPV0, i) * Vn) - svm * (S2(RPVm, i) * Vs)) * rdyS;
         const C Sk = Sc[c];
         Sc[c] += (C)D * dsg;
-        const T u_i = bU0[i] * srU0[i];
-        const T u_m = bU0[im] * srU0[im];
-        const T zon = T(0.5) * (u_i * sDl[i] + u_m * sDl[im]);
-        const T mer = T(0.5) * (Vn * sgN[i] + Vs * sgS[i]) * rdyA;
-        const C rp = (C)srP0[i];
+        const T u_i = SB(bs, BU0, i) * S2(RrU0, i);
+        const T u_m = SB(bs, BU0, im) * S2(RrU0, im);
+        const T zon = T(0.5) * (u_i * S2(RDl, i) + u_m * S2(RDl, im));
+        const T mer = T(0.5) * (Vn * S2(RgN, i) + Vs * S2(RgS, i)) * rdyA;
+        const C rp = (C)S2(RrP0, i);
         const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) * rsg * (rp * rp);
-        const C TF = ((C)(b * sP0[i]) + (C)(kap * bF[i])) * wp;
+        const C TF = ((C)(b * S2(RP0, i)) + (C)(kap * SB(bs, BF, i))) * wp;
         goF[idx] = (T)((C)baseF + A.ch * TF);
-        const T dphi = (bPhi[wrp(i + nj, nx)] - bPhi[wrp(i + 1 - nj, nx)]) * rdx;
-        const T rtx = T(0.5) * (RTj[c] + b * bF[ip] * srP0[ip]);
-        const C pgf = (C)dphi + RT0c * (C)sDq[i] + (C)rtx * (C)sDl[i];
-        const T VV = T(0.25) * (Vn + bV0[ip] + Vs + bVm[ip]);
+        const T dphi = (SB(bs, BPhi, wrp(i + nj, nx)) - SB(bs, BPhi, wrp(i + 1 - nj, nx))) * rdx;
+        const T rtx = T(0.5) * (RTj[c] + b * SB(bs, BF, ip) * S2(RrP0, ip));
+        const C pgf = (C)dphi + RT0c * (C)S2(RDq, i) + (C)rtx * (C)S2(RDl, i);
+        const T VV = T(0.25) * (Vn + SB(bs, BV0, ip) + Vs + SB(bs, BVm, ip));
         const T fs = fj + u_i * cota;
-        const C TU = -(C)(T(0.5) * (sP0[i] + sP0[ip])) * pgf - (C)fs * (C)VV;
+        const C TU = -(C)(T(0.5) * (S2(RP0, i) + S2(RP0, ip))) * pgf - (C)fs * (C)VV;
         goU[idx] = (T)((C)baseU + A.ch * TU);
       }
     } else {
       const T F0p = (T)A.pin[pidx * (nz + 1) + k];
       const int jva = (j == 0) ? 0 : ny - 1;
-      const T Pp = sP0[0];
+      const T Pp = S2(RP0, 0);
       const C sgn = (j == 0) ? 1.0 : -1.0;
       const C Dp = sgn * g.a * g.dlam * g.sv[jva] * sCap[k] / g.acap;
       const C vglp = sCap[nz + k] / ((double)nx * g.a * g.dth);
@@ -647,19 +645,19 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         const unsigned idv = (unsigned)i;
         const T baseV = gbV[idv];
         const int im = wrp(i - 1, nx);
-        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)sdQ[i] +
-                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)sdL[i]) * rdyAc;
-        const T U0i = bU0[i], U0m = bU0[im], U1i = bU1[i], U1m = bU1[im];
-        const T u0i = U0i * srU0[i], u0m = U0m * srU0[im];
-        const T u1i = U1i * srU1[i], u1m = U1m * srU1[im];
+        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)S2(RdQ, i) +
+                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)S2(RdL, i)) * rdyAc;
+        const T U0i = SB(bs, BU0, i), U0m = SB(bs, BU0, im), U1i = SB(bs, BU1, i), U1m = SB(bs, BU1, im);
+        const T u0i = U0i * S2(RrU0, i), u0m = U0m * S2(RrU0, im);
+        const T u1i = U1i * S2(RrU1, i), u1m = U1m * S2(RrU1, im);
         const T UU = T(0.25) * (U0m + U0i + U1m + U1i);
         const T uu = T(0.25) * (u0m + u0i + u1m + u1i);
         const T fs = fvj + uu * cotva;
-        const C TV = -(C)sPV0[i] * pgf + (C)fs * (C)UU;
+        const C TV = -(C)S2(RPV0, i) * pgf + (C)fs * (C)UU;
         goV[idv] = (T)((C)baseV + A.ch * TV);
       }
     }
-    if (k + 1 < nz) commit(k + 1, lev0 + (size_t)((k + 1) & 1) * bufStride);
+    if (k + 1 < nz) commit(k + 1, (k + 1) & 1);
     __syncthreads();
   }
 
@@ -1027,13 +1025,18 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int B = blockDim.x;
   int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
+  // LDS cells column-major, 27 words per column: the 10 2D rows, the two buffers of 7 level rows
+  // and the 3-slot sigma-dot ring; one address per column index serves every row (the row is an
+  // immediate offset) and consecutive lanes stride 27 words (no bank conflicts)
+  constexpr int RS = kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3;
   T* r = reinterpret_cast<T*>(smem);
-  T* sP0 = r;             T* sP1 = r + nx;        T* srPU0 = r + 2 * nx;  T* srPU1 = r + 3 * nx;
-  T* sPV0 = r + 4 * nx;   T* sPVm = r + 5 * nx;   T* sPV1 = r + 6 * nx;   T* srPV0 = r + 7 * nx;
-  T* srPVm = r + 8 * nx;  T* srPV1 = r + 9 * nx;
-  T* lev0 = r + kAdvectPipeRows2D * nx;                       // [2][7][nx]
-  const size_t bufStride = (size_t)kAdvectPipeRowsLev * nx;
-  T* sSd = lev0 + 2 * bufStride;                              // [3][nx], slot h % 3 for half level h
+  auto S2 = [&](int row, int col) -> T& { return r[col * RS + row]; };
+  auto SB = [&](int bsel, int row, int col) -> T& {
+    return r[col * RS + kAdvectPipeRows2D + bsel * kAdvectPipeRowsLev + row];
+  };
+  auto SD = [&](int slot, int col) -> T& { return r[col * RS + kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + slot]; };
+  enum { RP0, RP1, RrPU0, RrPU1, RPV0, RPVm, RPV1, RrPV0, RrPVm, RrPV1 };
+  enum { BF, BU, Bu0, BV, Buv, Bvt0, Bvtm };
   double* sCap = reinterpret_cast<double*>(
       smem + ((((size_t)kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3) * nx * sizeof(T) + 15) & ~size_t(15)));
 
@@ -1062,15 +1065,15 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     if (i < nx) {
       const T P0 = tsqrt<T>(psA(j, i) / p0);
       const T P1 = tsqrt<T>(psA(hasV ? j + 1 : ja, i) / p0);
-      sP0[i] = P0;
-      sP1[i] = P1;
+      S2(RP0, i) = P0;
+      S2(RP1, i) = P1;
       T PV0 = T(1), PVm = T(1), PV1 = T(1);
       if (hasV) PV0 = T(0.5) * (P0 + P1);
       if (j >= 1) PVm = T(0.5) * (tsqrt<T>(psA(j - 1, i) / p0) + P0);
       if (j + 2 <= ny) PV1 = T(0.5) * (P1 + tsqrt<T>(psA(j + 2, i) / p0));
-      sPV0[i] = PV0; sPVm[i] = PVm; sPV1[i] = PV1;
-      srPV0[i] = T(1) / PV0; srPVm[i] = T(1) / PVm; srPV1[i] = T(1) / PV1;
-      sSd[i] = T(0);   // half level 0
+      S2(RPV0, i) = PV0; S2(RPVm, i) = PVm; S2(RPV1, i) = PV1;
+      S2(RrPV0, i) = T(1) / PV0; S2(RrPVm, i) = T(1) / PVm; S2(RrPV1, i) = T(1) / PV1;
+      SD(0, i) = T(0);   // half level 0
     }
   }
   __syncthreads();
@@ -1080,7 +1083,7 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
       const T* pV = A.inV + (size_t)jv * row3 + (size_t)k * nx;
       C s1 = 0, s2 = 0;
       for (int i = t; i < nx; i += 64) {
-        const T pv = T(0.5) * (sP0[i] + sP1[i]);
+        const T pv = T(0.5) * (S2(RP0, i) + S2(RP1, i));
         const T vv = pV[i];
         s1 += (C)(pv * vv);
         if (isPole) s2 += (C)(vv / pv * (T)g.sv[jv] * FA(ja, k, i));
@@ -1094,8 +1097,8 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     const int i = t + c * B;
     if (i < nx) {
       const int ip = wrp(i + 1, nx);
-      srPU0[i] = isPole ? T(0) : T(2) / (sP0[i] + sP0[ip]);
-      srPU1[i] = j1Int ? T(2) / (sP1[i] + sP1[ip]) : T(0);
+      S2(RrPU0, i) = isPole ? T(0) : T(2) / (S2(RP0, i) + S2(RP0, ip));
+      S2(RrPU1, i) = j1Int ? T(2) / (S2(RP1, i) + S2(RP1, ip)) : T(0);
     }
   }
 
@@ -1116,8 +1119,8 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
   for (int c = 0; c < NI; ++c) {
     const int i = t + c * B;
     const int ii = i < nx ? i : 0;
-    rP0sq[c] = 1.0 / ((C)sP0[ii] * (C)sP0[ii]);
-    rP1sq[c] = hasV ? 1.0 / ((C)sP1[ii] * (C)sP1[ii]) : 0.0;
+    rP0sq[c] = 1.0 / ((C)S2(RP0, ii) * (C)S2(RP0, ii));
+    rP1sq[c] = hasV ? 1.0 / ((C)S2(RP1, ii) * (C)S2(RP1, ii)) : 0.0;
   }
   __syncthreads();
 
@@ -1127,9 +1130,9 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     const int i = t + c * B;
     const int ii = i < nx ? i : 0;
     const int ic = wrp(ii + nj - 1, nx), id = wrp(ii - nj, nx);
-    const T PUc = T(0.5) * (sP0[ic] + sP0[wrp(ic + 1, nx)]);
-    const T PUd = T(0.5) * (sP0[id] + sP0[wrp(id + 1, nx)]);
-    return (C)((PUc * Uic - PUd * Uid) * rdx + (svj * (sPV0[ii] * Vj) - svm * (sPVm[ii] * Vm)) * rdyS);
+    const T PUc = T(0.5) * (S2(RP0, ic) + S2(RP0, wrp(ic + 1, nx)));
+    const T PUd = T(0.5) * (S2(RP0, id) + S2(RP0, wrp(id + 1, nx)));
+    return (C)((PUc * Uic - PUd * Uid) * rdx + (svj * (S2(RPV0, ii) * Vj) - svm * (S2(RPVm, ii) * Vm)) * rdyS);
   };
   auto div1 = [&](int k, int c, T U1ic, T U1id, T Vj, T V1) -> C {
     if (!hasV) return 0.0;
@@ -1137,9 +1140,9 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     const int i = t + c * B;
     const int ii = i < nx ? i : 0;
     const int ic1 = wrp(ii + nj1 - 1, nx), id1 = wrp(ii - nj1, nx);
-    const T PU1c = T(0.5) * (sP1[ic1] + sP1[wrp(ic1 + 1, nx)]);
-    const T PU1d = T(0.5) * (sP1[id1] + sP1[wrp(id1 + 1, nx)]);
-    return (C)((PU1c * U1ic - PU1d * U1id) * rdx1 + (sv1 * (sPV1[ii] * V1) - svj * (sPV0[ii] * Vj)) * rdyS1);
+    const T PU1c = T(0.5) * (S2(RP1, ic1) + S2(RP1, wrp(ic1 + 1, nx)));
+    const T PU1d = T(0.5) * (S2(RP1, id1) + S2(RP1, wrp(id1 + 1, nx)));
+    return (C)((PU1c * U1ic - PU1d * U1id) * rdx1 + (sv1 * (S2(RPV1, ii) * V1) - svj * (S2(RPV0, ii) * Vj)) * rdyS1);
   };
 
   // ---- pass A: column totals Pi of rows j and j+1
@@ -1233,10 +1236,7 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
   // level k into LDS buffer k & 1; sigma-dot of its lower half level into slot (k + 1) % 3;
   // then the window moves down one level
   auto commit = [&](int k) {
-    T* buf = lev0 + (size_t)(k & 1) * bufStride;
-    T* bF = buf;            T* bU = buf + nx;       T* bu0 = buf + 2 * nx;  T* bV = buf + 3 * nx;
-    T* buv = buf + 4 * nx;  T* bvt0 = buf + 5 * nx; T* bvtm = buf + 6 * nx;
-    T* sdn = sSd + (size_t)((k + 1) % 3) * nx;
+    const int bs = k & 1, sn = (k + 1) % 3;
     const C dsg = g.dsig[k];
     const C sh = (k + 1 < nz) ? g.sigh[k + 1] : 0.0;
 #pragma unroll
@@ -1255,17 +1255,17 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
         if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) * rP1sq[c];
       }
       if (i < nx) {
-        bF[i] = nF[c];
-        bU[i] = nU[c];
-        const T u0 = nU[c] * srPU0[i];
-        bu0[i] = u0;
+        SB(bs, BF, i) = nF[c];
+        SB(bs, BU, i) = nU[c];
+        const T u0 = nU[c] * S2(RrPU0, i);
+        SB(bs, Bu0, i) = u0;
         if (hasV) {
-          bV[i] = nV[c];
-          bvt0[i] = nV[c] * srPV0[i] * svj;
-          buv[i] = T(0.5) * (u0 + nU1[c] * srPU1[i]);
+          SB(bs, BV, i) = nV[c];
+          SB(bs, Bvt0, i) = nV[c] * S2(RrPV0, i) * svj;
+          SB(bs, Buv, i) = T(0.5) * (u0 + nU1[c] * S2(RrPU1, i));
         }
-        if (j >= 1) bvtm[i] = nVm[c] * srPVm[i] * svm;
-        sdn[i] = (T)sd0n[c];
+        if (j >= 1) SB(bs, Bvtm, i) = nVm[c] * S2(RrPVm, i) * svm;
+        SD(sn, i) = (T)sd0n[c];
       }
       cVm[c] = nVm[c]; cU1[c] = nU1[c]; cV1[c] = nV1[c];
       cFn[c] = nFn[c]; cFs[c] = nFs[c]; cUs[c] = nUs[c];
@@ -1288,14 +1288,8 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     const bool more = k + 1 < nz;
     if (more) fetch(k + 1);
     const C dsg = g.dsig[k], r2d = 1.0 / (2.0 * dsg);
-    const T* buf = lev0 + (size_t)(k & 1) * bufStride;
-    const T* bF = buf;            const T* bU = buf + nx;       const T* bu0 = buf + 2 * nx;
-    const T* bV = buf + 3 * nx;   const T* buv = buf + 4 * nx;  const T* bvt0 = buf + 5 * nx;
-    const T* bvtm = buf + 6 * nx;
-    const T* obuf = lev0 + (size_t)((k + 1) & 1) * bufStride;   // level k-1 (own columns only)
-    const T* pFr = obuf;          const T* pUr = obuf + nx;     const T* pVr = obuf + 3 * nx;
-    const T* sdTop = sSd + (size_t)(k % 3) * nx;
-    const T* sdBot = sSd + (size_t)((k + 1) % 3) * nx;
+    // buffer of level k, the other buffer (level k-1, own columns only), sigma-dot slots above and below
+    const int bs = k & 1, ob = (k + 1) & 1, st = k % 3, sb = (k + 1) % 3;
     const size_t lo = (size_t)j * row3 + (size_t)k * nx;
     const auto goF = urow(A.oF, lo);
     const auto goU = urow(A.oU, lo);
@@ -1321,25 +1315,25 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
         const int ic = wrp(i + nj - 1, nx), id = wrp(i - nj, nx);
         const int pM = wrp(i + Mj, nx), mM = wrp(i - Mj, nx);
         // Phi: zonal (x+1, x-1) -> (x+2N-1, x-2N+1) with u at the midpoints
-        const T L1 = (bu0[ic] * bF[pM] - bu0[id] * bF[mM]) * rdx2;
-        const T L2 = (bvt0[i] * cFn[c] - bvtm[i] * cFs[c]) * rdy2;
+        const T L1 = (SB(bs, Bu0, ic) * SB(bs, BF, pM) - SB(bs, Bu0, id) * SB(bs, BF, mM)) * rdx2;
+        const T L2 = (SB(bs, Bvt0, i) * cFn[c] - SB(bs, Bvtm, i) * cFs[c]) * rdy2;
         C L3 = 0;
         if (more) L3 += sd0n[c] * (C)nF[c];
-        if (k > 0) L3 -= sd0c[c] * (C)pFr[i];
+        if (k > 0) L3 -= sd0c[c] * (C)SB(ob, BF, i);
         const C TF = -((C)L1 + (C)L2 + L3 * r2d);
         goF[i] = (T)((C)cbF[c] + A.ch * TF);
         // U: the same leap on U points, u averaged to the integer points i+n and i+1-n
         const int pA = wrp(i + nj, nx), pB = wrp(i + 1 - nj, nx);
-        const T ubA = T(0.5) * (bu0[ic] + bu0[pA]);
-        const T ubB = T(0.5) * (bu0[id] + bu0[pB]);
-        const T U1v = (ubA * bU[pM] - ubB * bU[mM]) * rdx2;
+        const T ubA = T(0.5) * (SB(bs, Bu0, ic) + SB(bs, Bu0, pA));
+        const T ubB = T(0.5) * (SB(bs, Bu0, id) + SB(bs, Bu0, pB));
+        const T U1v = (ubA * SB(bs, BU, pM) - ubB * SB(bs, BU, mM)) * rdx2;
         const int ip = wrp(i + 1, nx);
-        const T vtn = T(0.5) * (bvt0[i] + bvt0[ip]);
-        const T vts = T(0.5) * (bvtm[i] + bvtm[ip]);
+        const T vtn = T(0.5) * (SB(bs, Bvt0, i) + SB(bs, Bvt0, ip));
+        const T vts = T(0.5) * (SB(bs, Bvtm, i) + SB(bs, Bvtm, ip));
         const T U2v = (vtn * cU1[c] - vts * cUs[c]) * rdy2;
         C U3 = 0;
-        if (more) U3 += (C)(T(0.5) * (sdBot[i] + sdBot[ip])) * (C)nU[c];
-        if (k > 0) U3 -= (C)(T(0.5) * (sdTop[i] + sdTop[ip])) * (C)pUr[i];
+        if (more) U3 += (C)(T(0.5) * (SD(sb, i) + SD(sb, ip))) * (C)nU[c];
+        if (k > 0) U3 -= (C)(T(0.5) * (SD(st, i) + SD(st, ip))) * (C)SB(ob, BU, i);
         const C TU = -((C)U1v + (C)U2v + U3 * r2d);
         goU[i] = (T)((C)cbU[c] + A.ch * TU);
         __builtin_amdgcn_sched_barrier(0);
@@ -1368,14 +1362,14 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
-        const T L1 = (buv[wrp(i + nv - 1, nx)] * bV[wrp(i + Mv, nx)] - buv[wrp(i - nv, nx)] * bV[wrp(i - Mv, nx)]) * rdxv2;
+        const T L1 = (SB(bs, Buv, wrp(i + nv - 1, nx)) * SB(bs, BV, wrp(i + Mv, nx)) - SB(bs, Buv, wrp(i - nv, nx)) * SB(bs, BV, wrp(i - Mv, nx))) * rdxv2;
         T L2 = T(0);
-        if (j + 1 < ny) L2 += T(0.5) * (bvt0[i] + cV1[c] * srPV1[i] * sv1) * cV1[c];
-        if (j > 0) L2 -= T(0.5) * (bvtm[i] + bvt0[i]) * cVm[c];
+        if (j + 1 < ny) L2 += T(0.5) * (SB(bs, Bvt0, i) + cV1[c] * S2(RrPV1, i) * sv1) * cV1[c];
+        if (j > 0) L2 -= T(0.5) * (SB(bs, Bvtm, i) + SB(bs, Bvt0, i)) * cVm[c];
         L2 = L2 * rdyv2;
         C L3 = 0;
         if (more) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)nV[c];
-        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)pVr[i];
+        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)SB(ob, BV, i);
         const C TV = -((C)L1 + (C)L2 + L3 * r2d);
         goV[i] = (T)((C)cbV[c] + A.ch * TV);
         __builtin_amdgcn_sched_barrier(0);
