@@ -72,6 +72,8 @@ struct Ctx {
   int parts = 7;                   // first adaptation transposes: 1 scalar point (+ suffix), 2 U, 4 V
   KTimer* timer = nullptr;         // host side: times the row-fused kernel's launches when armed
   int fwd_all = 1;                 // forward recompute of R T', phi', omega/p too (0: D, S, sigma-dot only)
+  int ai_zero = 0;                 // the input adjoint was zeroed by the caller and, in its interior rows,
+                                   // only the row-fused kernel adds to it: stored there without a read
 };
 
 template <typename T>
@@ -1184,7 +1186,9 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
     T vAVm[NI], vAV1[NI], vAD1[NI], vMVm[NI], vMVj[NI], voF[NI], voU[NI], voV[NI], vAUU[NI];
     // the accumulators the second phase updates, fetched now
     T aiU0[NI], aiV0[NI], aiF0[NI];
-    {
+#pragma unroll
+    for (int cc = 0; cc < NI; ++cc) aiU0[cc] = aiV0[cc] = aiF0[cc] = T(0);
+    if (!c.ai_zero) {
       const auto gaU = urow(c.aiU, ((size_t)j * row3 + lvl));
       const auto gaV = urow(c.aiV, ((size_t)j * row3 + lvl));
       const auto gaF = urow(c.aiF, ((size_t)j * row3 + lvl));
@@ -1651,7 +1655,7 @@ St4<T> state_at(const HandleView& v, void* base) {
 
 template <typename T>
 hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<const T> y, St4<const T> ao,
-                              St4<T> ab, St4<T> ai, double* pin, hipStream_t s) {
+                              St4<T> ab, St4<T> ai, double* pin, hipStream_t s, bool ai_zero = false) {
   Ctx<T> c;
   c.g = v.g;
   c.U = y.U; c.V = y.V; c.F = y.F; c.P = y.P;
@@ -1664,6 +1668,7 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.f = v.fac;
   c.blk = v.block;
   c.timer = v.timer;
+  c.ai_zero = ai_zero && ab.U != ai.U;
   hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
   if (e != hipSuccess) return e;
   e = run_stage_adjoint<T>(c, s, process == 0);
@@ -1761,12 +1766,13 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
     St4<T> y = traj(3 * rk), y1 = traj(3 * rk + 1), y2 = traj(3 * rk + 2);
     e = zero_state<T>(v, l1, s);
     if (e == hipSuccess) e = zero_state<T>(v, l2, s);
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, pin, s);
+    // l2 and l1 were zeroed just above: the row-fused kernel stores their interior rows
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, pin, s, true);
     if (e == hipSuccess) {
       hipLaunchKernelGGL((k_base_inplace<T>), dim3(v.g.nz + 1, 2), dim3(256), 0, s, v.g, lam.U, lam.F, lam.P);
       e = hipGetLastError();
     }
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lam, l1, pin, s);
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lam, l1, pin, s, true);
     if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lam, lam, pin, s);
     if (e != hipSuccess) return DYCORE_EHIP;
   }
