@@ -72,8 +72,9 @@ struct Ctx {
   int parts = 7;                   // first adaptation transposes: 1 scalar point (+ suffix), 2 U, 4 V
   KTimer* timer = nullptr;         // host side: times the row-fused kernel's launches when armed
   int fwd_all = 1;                 // forward recompute of R T', phi', omega/p too (0: D, S, sigma-dot only)
-  int ai_zero = 0;                 // the input adjoint was zeroed by the caller and, in its interior rows,
-                                   // only the row-fused kernel adds to it: stored there without a read
+  int ai_zero = 0;                 // the input adjoint starts at zero and, in its interior rows, only the
+                                   // row-fused kernel adds to it: those rows are stored without a read
+                                   // (and need not be cleared by the caller)
 };
 
 template <typename T>
@@ -591,11 +592,11 @@ __global__ void k_uv(Ctx<T> c) {
   xcd_tile3((int)gridDim.x, g.nz, g.ny + 1, tx, k, j);
   const int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
-  const size_t id = i3<T>(g, j, k, i);
+  const unsigned id = i3u(g, j, k, i);
   T u = T(0);
-  if (j >= 1 && j < g.ny) u = c.U[id] * (T(2) / (P2(c, j, i) + P2(c, j, wrp(i + 1, g.nx))));
-  c.s.UA[id] = u;
-  if (j < g.ny) c.s.VT[id] = c.V[id] * (T(1) / (T(0.5) * (P2(c, j, i) + P2(c, j + 1, i)))) * (T)g.sv[j];
+  if (j >= 1 && j < g.ny) u = ldg(c.U, id) * (T(2) / (P2(c, j, i) + P2(c, j, wrp(i + 1, g.nx))));
+  stg(c.s.UA, id, u);
+  if (j < g.ny) stg(c.s.VT, id, ldg(c.V, id) * (T(1) / (T(0.5) * (P2(c, j, i) + P2(c, j + 1, i)))) * (T)g.sv[j]);
 }
 
 template <typename T>
@@ -1685,6 +1686,28 @@ hipError_t zero_state(const HandleView& v, St4<T> a, hipStream_t s) {
   return e;
 }
 
+// Zeroes only what kernels other than the row-fused adaptation adjoint add to: pole rows of U and
+// Phi, V row 1/2 and p_s.  The row-fused kernel stores the interior rows of an input adjoint the
+// caller marks as zeroed (Ctx::ai_zero).
+template <typename T>
+hipError_t zero_outside_rows(const HandleView& v, St4<T> a, hipStream_t s) {
+  const size_t row = (size_t)v.g.nz * v.g.nx;
+  hipError_t e = launch_zero<T>(a.U, row, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.U + (size_t)v.g.ny * row, row, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.F, row, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.F + (size_t)v.g.ny * row, row, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.V, row, s);
+  if (e == hipSuccess) e = launch_zero<T>(a.P, v.nP, s);
+  return e;
+}
+
+// Whether the adaptation-stage adjoint of this handle runs the row-fused kernel (as aar_used).
+template <typename T>
+bool rows_fused(const HandleView& v) {
+  const Ctx<T> c = [&] { Ctx<T> x; x.g = v.g; x.blk = v.block; return x; }();
+  return aar_used(c);
+}
+
 template <typename T>
 hipError_t copy_state(const HandleView& v, St4<T> d, St4<const T> src, hipStream_t s) {
   hipError_t e = launch_axpy_fill<T>(d.U, src.U, v.nU, s);
@@ -1764,9 +1787,11 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
     const int proc = rk < v.msub ? 0 : 1;
     const double h = proc == 0 ? v.dt / v.msub : v.dt;
     St4<T> y = traj(3 * rk), y1 = traj(3 * rk + 1), y2 = traj(3 * rk + 2);
-    e = zero_state<T>(v, l1, s);
-    if (e == hipSuccess) e = zero_state<T>(v, l2, s);
-    // l2 and l1 were zeroed just above: the row-fused kernel stores their interior rows
+    // l2 and l1 start at zero: where the row-fused kernel stores their interior rows, only the
+    // rest is cleared
+    const bool fused = proc == 0 && rows_fused<T>(v);
+    e = fused ? zero_outside_rows<T>(v, l1, s) : zero_state<T>(v, l1, s);
+    if (e == hipSuccess) e = fused ? zero_outside_rows<T>(v, l2, s) : zero_state<T>(v, l2, s);
     if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, pin, s, true);
     if (e == hipSuccess) {
       hipLaunchKernelGGL((k_base_inplace<T>), dim3(v.g.nz + 1, 2), dim3(256), 0, s, v.g, lam.U, lam.F, lam.P);
