@@ -109,31 +109,11 @@ int columns_per_thread(int nx, int block);
 int stage_pipelined(int nx, int elem);   // 1 if the stage kernels for rows of nx columns are pipelined
 int max_block_for(int nx, int block);   // 1 if `block` threads are allowed for rows of nx columns
 
-// A uniform row of a global array, indexed by a 32-bit column: the base stays in an SGPR pair and
-// every access is a global load or store of that base plus the column's 32-bit VGPR byte offset.
-template <typename T>
-struct GRow {
-  __attribute__((address_space(1))) T* p;
-  __device__ __forceinline__ __attribute__((address_space(1))) T& operator[](unsigned i) const {
-    return *(__attribute__((address_space(1))) T*)(
-        reinterpret_cast<__attribute__((address_space(1))) const char*>(p) + i * (unsigned)sizeof(T));
-  }
-};
-
-// A uniform row pointer, opaque to the optimiser (loop strength reduction would otherwise turn every
-// (array, owned column) address stream of a level loop into its own 64-bit induction variable in
-// VGPRs), in the global address space (a generic pointer would make every access a flat one).
-template <typename T>
-__device__ __forceinline__ GRow<T> uni(T* p) {
-  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
-  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
-  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
-  return GRow<T>{reinterpret_cast<__attribute__((address_space(1))) T*>((static_cast<unsigned long long>(hi) << 32) | lo)};
-}
-
-// The same as a uniform array base plus a uniform 32-bit element offset: one SGPR per row instead
-// of a pair (the base is the kernel argument's), one VALU add per (row, column) access.  Arrays
-// are limited to 2^32 bytes.
+// A uniform row of a global array: the array base (the kernel argument's, one SGPR pair for every
+// row) plus a uniform 32-bit element offset made opaque with readfirstlane (one SGPR per row; loop
+// strength reduction would otherwise keep one 64-bit address per array and owned column in VGPRs).
+// Indexed by a 32-bit column, every access is a global load or store of base + 32-bit VGPR byte
+// offset (a generic pointer would make it a flat access).  Arrays are limited to 2^32 bytes.
 template <typename T>
 struct ORow {
   __attribute__((address_space(1))) T* p;
