@@ -166,3 +166,38 @@ def test_refused_sizes():
         Dycore(7, 8, 3, 60.0, prec="fp64", forward_only=True)
     with pytest.raises(DycoreError):
         Dycore(64, 8, 129, 60.0, prec="fp64", forward_only=True)
+
+
+@pytest.mark.parametrize("process", ["A", "L"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_adjoint_adds_to_nonzero_accumulators(process, prec):
+    """The stage adjoint adds into accumulators that already hold values (on a grid where the
+    adaptation adjoint runs row-fused): FP64 totals equal initial values + the oracle's
+    contributions to 1e-12; FP32 increments equal the contributions to 1e-3 relative L2 (as the FP32
+    step adjoint).  An overwrite would miss by the size of the initial values."""
+    print(f"stage adjoint += {prec} {process}", flush=True)
+    cfg = small(96, 24, 4)
+    st = synth.make_state(cfg)
+    if prec == "fp32":
+        st = dict(st, **{k: st[k].astype(np.float32).astype(np.float64) for k in ("U", "V", "Phi", "ps")})
+    ao = synth.random_like(st, 34)
+    ch = 120.0
+    wb, wi = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).adj_stage(st, ao, ch, process)
+    core = _core(cfg, st, prec)
+    d = core.to_device(st)
+    a = core.to_device(ao)
+    ab = core.to_device(synth.random_like(st, 35))
+    ai = core.to_device(synth.random_like(st, 36))
+    b0, i0 = _host(ab), _host(ai)
+    core.stage_adjoint(process, ch, d, a, ab, ai)
+    gb, gi = _host(ab), _host(ai)
+    for k in ("U", "V", "Phi", "ps"):
+        for tag, got, start, want in (("base", gb, b0, wb), ("in", gi, i0, wi)):
+            inc = got[k] - start[k]
+            if prec == "fp64":
+                err = _rel(got[k], start[k] + want[k])
+                assert err < 1e-12, (tag, k, err)
+            else:
+                nw = np.linalg.norm(want[k])
+                err = np.linalg.norm(inc - want[k]) / max(nw, 1e-30)
+                assert err < 1e-3 or np.linalg.norm(inc - want[k]) < 1e-5 * np.linalg.norm(start[k]), (tag, k, err)
