@@ -24,6 +24,9 @@ namespace {
 using C = double;
 
 __device__ __forceinline__ int wrp(int i, int nx) { return i >= nx ? i - nx : (i < 0 ? i + nx : i); }
+// one-sided forms, where the offset's sign is known: 0 <= i < 2 nx, and -nx <= i < nx
+__device__ __forceinline__ int wrp_up(int i, int nx) { return i >= nx ? i - nx : i; }
+__device__ __forceinline__ int wrp_dn(int i, int nx) { return i < 0 ? i + nx : i; }
 
 __device__ __forceinline__ double wave_sum(double acc) {
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -1012,7 +1015,7 @@ __global__ void k_t4(Ctx<T> c) {
 // level.  The pole rows' share goes through the per-point kernels (restricted to the pole rows);
 // this kernel writes the few row-1 and row-(ny-1) intermediates those read.
 // ------------------------------------------------------------------------------------------------
-constexpr int kAar2D = 13, kAarLev = 13;
+constexpr int kAar2D = 15, kAarLev = 13;
 __host__ __device__ constexpr size_t aar_lds(int nx, int elem) {
   return ((size_t)(kAar2D + kAarLev) * nx * elem + 15) & ~size_t(15);
 }
@@ -1027,14 +1030,16 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   const int j = 1 + xcd_row(blockIdx.x, ny - 1);
   const int B = blockDim.x;
   int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
-  // LDS cells column-major in two blocks of 13 rows: (row r, column i) at i*13 + r, so that one
-  // address per column index serves every row (the row is the instruction's immediate offset) and
-  // consecutive lanes stride 13 words (no bank conflicts)
+  // LDS cells column-major in two blocks, of 15 and 13 rows: (row r, column i) at i*15 + r and
+  // i*13 + r, so that one address per column index serves every row of a block (the row is the
+  // instruction's immediate offset) and consecutive lanes stride an odd number of words (no bank
+  // conflicts)
   T* s2 = reinterpret_cast<T*>(smem);   // 2D rows from the forward recompute
   T* sl = s2 + kAar2D * nx;             // per-level rows
   // 2D rows: P of rows j-1, j, j+1; the meridional l and q differences; the leaped d+l, d+q of
-  // row j; reciprocals of P (rows j, j+1) and of its U-point averages (rows j-1, j, j+1)
-  enum { RPm, RP0, RP1, RdLm, RdL0, RdQ0, RDL, RDQ, RrP0, RrP1, RrUm, RrU0, RrU1 };
+  // row j; reciprocals of P (rows j, j+1), of its U-point averages (rows j-1, j, j+1) and of its
+  // V-point averages (V rows j+1/2, j-1/2)
+  enum { RPm, RP0, RP1, RdLm, RdL0, RdQ0, RDL, RDQ, RrP0, RrP1, RrUm, RrU0, RrU1, RrPV0, RrPVm };
   // per-level rows
   enum { LHH, LAV, LFVm, LFV0, LUVm, LUV0, LFU0, LFU1, LAD, LPH, LRT, LMU, Lu };
   auto S2 = [&](int row, int col) -> T& { return s2[col * kAar2D + row]; };
@@ -1091,13 +1096,15 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
     }
   }
   __syncthreads();
-  auto PUr = [&](int rP, int i) -> T { return T(0.5) * (S2(rP, i) + S2(rP, wrp(i + 1, nx))); };
+  auto PUr = [&](int rP, int i) -> T { return T(0.5) * (S2(rP, i) + S2(rP, wrp_up(i + 1, nx))); };
   for (int cc = 0; cc < NI; ++cc) {
     const int i = t + cc * B;
     if (i < nx) {
       S2(RrUm, i) = T(1) / PUr(RPm, i);
       S2(RrU0, i) = T(1) / PUr(RP0, i);
       S2(RrU1, i) = T(1) / PUr(RP1, i);
+      S2(RrPV0, i) = T(1) / (T(0.5) * (S2(RP0, i) + S2(RP1, i)));
+      S2(RrPVm, i) = T(1) / (T(0.5) * (S2(RPm, i) + S2(RP0, i)));
     }
   }
   __syncthreads();
@@ -1207,7 +1214,7 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
     for (int cc = 0; cc < NI; ++cc) {
       const int i = t + cc * B;
       if (i >= nx) continue;
-      const int im = wrp(i - 1, nx), ip = wrp(i + 1, nx);
+      const int im = wrp_dn(i - 1, nx), ip = wrp_up(i + 1, nx);
       const size_t oj = (size_t)j * row3 + lvl;
       const unsigned ui = (unsigned)i, uim = (unsigned)im, uip = (unsigned)ip;
       const T Fm = nPole ? (T)c.pin[k] : pFm[ui];
@@ -1330,7 +1337,7 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
     for (int cc = 0; cc < NI; ++cc) {
       const int i = t + cc * B;
       if (i >= nx) continue;
-      const int im = wrp(i - 1, nx), ip = wrp(i + 1, nx);
+      const int im = wrp_dn(i - 1, nx), ip = wrp_up(i + 1, nx);
       const size_t oj = (size_t)j * row3 + (size_t)k * nx + i;
       const T vRTj = SL(LRT, i), vPHj = SL(LPH, i);
       const A vAVj = (A)SL(LAV, i), vADj = (A)SL(LAD, i), vHH = (A)SL(LHH, i);
@@ -1339,9 +1346,9 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const T PU0 = PUr(RP0, i);
       const T PV0 = T(0.5) * (S2(RP0, i) + S2(RP1, i)), PVm = T(0.5) * (S2(RPm, i) + S2(RP0, i));
       // forward D, S, omega/p (as the forward recompute forms them)
-      const T D = (SL(LMU, wrp(i + n - 1, nx)) - SL(LMU, wrp(i - n, nx))) * rdxT +
+      const T D = (SL(LMU, wrp_up(i + n - 1, nx)) - SL(LMU, wrp_dn(i - n, nx))) * rdxT +
                   (svj * (PV0 * vVj[cc]) - svm * (PVm * vVm[cc])) * rdySjT;
-      const T rPV0 = T(1) / PV0, rPVm = T(1) / PVm;
+      const T rPV0 = S2(RrPV0, i), rPVm = S2(RrPVm, i);
       const C SkC = Sj[cc];
       const T Sk = (T)SkC;
       Sj[cc] += (C)D * dsg;
@@ -1354,7 +1361,7 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const A AFE = (A)kap * wp * gF;
       const A AP3 = (A)b * wp * gF + A(2) * ((A)Sk + A(0.5) * (A)D * (A)dsg) * (A)rsg * (rP2A * rPA) * aWP;
       // U point: pressure gradient seen by U row j
-      const T dphi = (SL(LPH, wrp(i + n, nx)) - SL(LPH, wrp(i + 1 - n, nx))) * rdxT;
+      const T dphi = (SL(LPH, wrp_up(i + n, nx)) - SL(LPH, wrp_dn(i + 1 - n, nx))) * rdxT;
       const T rtx = T(0.5) * (vRTj + SL(LRT, ip));
       const A pgf = (A)dphi + RT0A * (A)S2(RDQ, i) + (A)rtx * (A)S2(RDL, i);
       const A gU = chA * (A)voU[cc], gV = chA * (A)voV[cc];
@@ -1365,7 +1372,7 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const A APV3 = -pgfV * gV;
       // gathers: scalar point
       const A mM = (A)vMVm[cc], mJ = (A)vMVj[cc];
-      const A aPHI = ((A)SL(LHH, wrp(i - n, nx)) - (A)SL(LHH, wrp(i + n - 1, nx))) * rdxA + mM - mJ;
+      const A aPHI = ((A)SL(LHH, wrp_dn(i - n, nx)) - (A)SL(LHH, wrp_up(i + n - 1, nx))) * rdxA + mM - mJ;
       const A aRT = A(0.5) * ((A)SL(LHH, i) * (A)S2(RDL, i) + (A)SL(LHH, im) * (A)S2(RDL, im)) +
                     A(0.5) * (A)S2(RdLm, i) * mM + A(0.5) * (A)S2(RdL0, i) * mJ;
       const A cvgm = (nPole ? (A)(sVG[0 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAVm[cc]) + A(0.5) * vAVj;
@@ -1390,7 +1397,7 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       if (!sPole) aVd += (A)SL(LFU1, im) + vFU1;
       const A avd = A(-0.25) * aVd;
       // divergence and velocity transposes
-      const A aMU = ((A)SL(LAD, wrp(i - n + 1, nx)) - (A)SL(LAD, wrp(i + n, nx))) * rdxA;
+      const A aMU = ((A)SL(LAD, wrp_dn(i - n + 1, nx)) - (A)SL(LAD, wrp_up(i + n, nx))) * rdxA;
       const A PUc = (A)PU0, Uc = (A)vUj[cc];
       c.aiU[oj] = (T)((C)aiU0[cc] + (C)(aUd + au * rPUc + PUc * aMU));
       const A aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;

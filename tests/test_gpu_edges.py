@@ -81,11 +81,11 @@ def test_stage_fp32_ragged_and_limit(nx, process):
         assert err < 2e-3, (k, err)
 
 
-# The row-fused adaptation adjoint holds 26 rows (no pole-sum block): FP64 fits at 787 columns.
-@pytest.mark.parametrize("nx", [787, 788])
+# The row-fused adaptation adjoint holds 28 rows (no pole-sum block): FP64 fits at 731 columns.
+@pytest.mark.parametrize("nx", [731, 732])
 def test_stage_adjoint_fp64_across_row_kernel_limit(nx):
     """The adaptation-stage adjoint equals the oracle on both sides of the row-fused kernel's limit."""
-    assert (((26 * 787 * 8 + 15) // 16) * 16 <= 160 * 1024) and (((26 * 788 * 8 + 15) // 16) * 16 > 160 * 1024)
+    assert (((28 * 731 * 8 + 15) // 16) * 16 <= 160 * 1024) and (((28 * 732 * 8 + 15) // 16) * 16 > 160 * 1024)
     print(f"stage adjoint fp64 nx={nx}", flush=True)
     cfg = small(nx, 8, 3)
     st = synth.make_state(cfg)
