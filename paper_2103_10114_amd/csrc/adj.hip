@@ -630,7 +630,7 @@ __global__ void k_l1(Ctx<T> c) {
   auto uA = [&](int jr, int q) -> A { return (jr >= 1 && jr < ny) ? (A)ldg(c.s.UA, i3u(g, jr, k, q)) : A(0); };
   auto vA = [&](int jv, int kk, int ii) -> A { return (A)ldg(c.s.VT, i3u(g, jv, kk, ii)); };
   auto ub = [&](int jr, int q) -> A {   // u averaged to integer point q of U row jr
-    return A(0.5) * (uA(jr, wrp(q - 1, nx)) + uA(jr, q));
+    return A(0.5) * (uA(jr, wrp_dn(q - 1, nx)) + uA(jr, q));
   };
   auto uv = [&](int jv, int q) -> A { return A(0.5) * (uA(jv, q) + uA(jv + 1, q)); };
   auto vts = [&](int js, int kk, int ii) -> A {   // v sin(theta) on scalar row js
@@ -644,8 +644,8 @@ __global__ void k_l1(Ctx<T> c) {
     A a = 0;
     if (interior(j)) {
       const int M = g.M[j], n = (M + 1) / 2;
-      const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
-      a += (amF(j, k, pm) * uA(j, wrp(pm + n - 1, nx)) - amF(j, k, pp) * uA(j, wrp(pp - n, nx))) * rdx2(j);
+      const int pm = wrp_dn(i - M, nx), pp = wrp_up(i + M, nx);
+      a += (amF(j, k, pm) * uA(j, wrp_up(pm + n - 1, nx)) - amF(j, k, pp) * uA(j, wrp_dn(pp - n, nx))) * rdx2(j);
     }
     if (interior(j - 1)) a += amF(j - 1, k, i) * vA(j - 1, k, i) * rdy2(j - 1);
     if (interior(j + 1)) a -= amF(j + 1, k, i) * vA(j, k, i) * rdy2(j + 1);
@@ -661,18 +661,18 @@ __global__ void k_l1(Ctx<T> c) {
     // adjoint of u (U point i+1/2)
     A au = 0;
     {
-      const int qa = wrp(i - n + 1, nx), qb = wrp(i + n, nx);
-      au += (amF(j, k, qa) * (A)Fe(c, j, k, wrp(qa + M, nx)) - amF(j, k, qb) * (A)Fe(c, j, k, wrp(qb - M, nx))) * rdx2(j);
+      const int qa = wrp_dn(i - n + 1, nx), qb = wrp_up(i + n, nx);
+      au += (amF(j, k, qa) * (A)Fe(c, j, k, wrp_up(qa + M, nx)) - amF(j, k, qb) * (A)Fe(c, j, k, wrp_dn(qb - M, nx))) * rdx2(j);
       auto aub = [&](int q) -> A {
-        const int r1 = wrp(q - n, nx), r2 = wrp(q - 1 + n, nx);
-        return (amU(j, k, r1) * (A)Ue(c, j, k, wrp(r1 + M, nx)) - amU(j, k, r2) * (A)Ue(c, j, k, wrp(r2 - M, nx))) * rdx2(j);
+        const int r1 = wrp_dn(q - n, nx), r2 = wrp_up(q - 1 + n, nx);
+        return (amU(j, k, r1) * (A)Ue(c, j, k, wrp_up(r1 + M, nx)) - amU(j, k, r2) * (A)Ue(c, j, k, wrp_dn(r2 - M, nx))) * rdx2(j);
       };
-      au += A(0.5) * (aub(i) + aub(wrp(i + 1, nx)));
+      au += A(0.5) * (aub(i) + aub(wrp_up(i + 1, nx)));
       for (int jv : {j - 1, j}) {
         const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
-        const int r1 = wrp(i - nv + 1, nx), r2 = wrp(i + nv, nx);
-        const A auv = (amV(jv, k, r1) * (A)Ve(c, jv, k, wrp(r1 + Mv, nx)) -
-                       amV(jv, k, r2) * (A)Ve(c, jv, k, wrp(r2 - Mv, nx))) * rdxv2(jv);
+        const int r1 = wrp_dn(i - nv + 1, nx), r2 = wrp_up(i + nv, nx);
+        const A auv = (amV(jv, k, r1) * (A)Ve(c, jv, k, wrp_up(r1 + Mv, nx)) -
+                       amV(jv, k, r2) * (A)Ve(c, jv, k, wrp_dn(r2 - Mv, nx))) * rdxv2(jv);
         au += A(0.5) * auv;
       }
     }
@@ -680,9 +680,9 @@ __global__ void k_l1(Ctx<T> c) {
     // direct adjoint of U
     A aU = 0;
     {
-      const int pm = wrp(i - M, nx), pp = wrp(i + M, nx);
-      aU += (amU(j, k, pm) * ub(j, wrp(pm + n, nx)) - amU(j, k, pp) * ub(j, wrp(pp + 1 - n, nx))) * rdx2(j);
-      const int ip1 = wrp(i + 1, nx);
+      const int pm = wrp_dn(i - M, nx), pp = wrp_up(i + M, nx);
+      aU += (amU(j, k, pm) * ub(j, wrp_up(pm + n, nx)) - amU(j, k, pp) * ub(j, wrp_dn(pp + 1 - n, nx))) * rdx2(j);
+      const int ip1 = wrp_up(i + 1, nx);
       if (interior(j - 1)) {
         const A vtu = A(0.5) * (vA(j - 1, k, i) + vA(j - 1, k, ip1));
         aU += amU(j - 1, k, i) * vtu * rdy2(j - 1);
@@ -702,8 +702,8 @@ __global__ void k_l1(Ctx<T> c) {
     const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
     A aV = 0;
     {
-      const int pm = wrp(i - Mv, nx), pp = wrp(i + Mv, nx);
-      aV += (amV(jv, k, pm) * uv(jv, wrp(pm + nv - 1, nx)) - amV(jv, k, pp) * uv(jv, wrp(pp - nv, nx))) * rdxv2(jv);
+      const int pm = wrp_dn(i - Mv, nx), pp = wrp_up(i + Mv, nx);
+      aV += (amV(jv, k, pm) * uv(jv, wrp_up(pm + nv - 1, nx)) - amV(jv, k, pp) * uv(jv, wrp_dn(pp - nv, nx))) * rdxv2(jv);
       if (jv >= 1) aV += amV(jv - 1, k, i) * vts(jv, k, i) * rdyv2(jv - 1);
       if (jv + 1 <= ny - 1) aV -= amV(jv + 1, k, i) * vts(jv + 1, k, i) * rdyv2(jv + 1);
       if (k >= 1) aV += amV(jv, k - 1, i) * A(0.5) * (sd(jv, k, i) + sd(jv + 1, k, i)) * r2d(k - 1);
@@ -723,7 +723,7 @@ __global__ void k_l1(Ctx<T> c) {
       if (interior(jv + 1)) r -= amU(jv + 1, k, p) * (A)Ue(c, jv, k, p) * rdy2(jv + 1);
       return r;
     };
-    avt += A(0.5) * (avtu(i) + avtu(wrp(i - 1, nx)));
+    avt += A(0.5) * (avtu(i) + avtu(wrp_dn(i - 1, nx)));
     auto avts = [&](int js) -> A {
       if (js <= 0 || js >= ny) return A(0);
       return amV(js - 1, k, i) * (A)Ve(c, js, k, i) * rdyv2(js - 1) - amV(js, k, i) * (A)Ve(c, js - 1, k, i) * rdyv2(js);
@@ -742,7 +742,7 @@ __global__ void k_l1(Ctx<T> c) {
         return amU(j, h - 1, p) * (A)Ue(c, j, h, p) * r2d(h - 1) -
                amU(j, h, p) * (A)Ue(c, j, h - 1, p) * r2d(h);
       };
-      a += A(0.5) * (asdu(i) + asdu(wrp(i - 1, nx)));
+      a += A(0.5) * (asdu(i) + asdu(wrp_dn(i - 1, nx)));
     }
     auto asdv = [&](int jv) -> A {
       return amV(jv, h - 1, i) * (A)Ve(c, jv, h, i) * r2d(h - 1) -

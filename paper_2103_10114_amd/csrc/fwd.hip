@@ -24,6 +24,9 @@ __device__ __forceinline__ int wrp(int i, int nx) {
   // |offset| < nx for every caller
   return i >= nx ? i - nx : (i < 0 ? i + nx : i);
 }
+// one-sided forms, where the offset's sign is known: 0 <= i < 2 nx, and -nx <= i < nx
+__device__ __forceinline__ int wrp_up(int i, int nx) { return i >= nx ? i - nx : i; }
+__device__ __forceinline__ int wrp_dn(int i, int nx) { return i < 0 ? i + nx : i; }
 
 // Deterministic FP64 row sum by wavefront 0: lane l adds i = l, l+64, ... in
 // order, then a butterfly (commutative adds give every lane the same total).
@@ -425,12 +428,12 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
   for (int c = 0; c < NI; ++c) {
     const int i = t + c * B;
     if (i < nx) {
-      const int ip = wrp(i + 1, nx);
+      const int ip = wrp_up(i + 1, nx);
       S2(RrU0, i) = T(2) / (S2(RP0, i) + S2(RP0, ip));
       if (hasV) S2(RrU1, i) = T(2) / (SB(0, 0, i) + SB(0, 0, ip));
       if (!isPole) {
-        S2(RDl, i) = (SB(0, 1, wrp(i + nj, nx)) - SB(0, 1, wrp(i + 1 - nj, nx))) * rdx;
-        S2(RDq, i) = (SB(0, 2, wrp(i + nj, nx)) - SB(0, 2, wrp(i + 1 - nj, nx))) * rdx;
+        S2(RDl, i) = (SB(0, 1, wrp_up(i + nj, nx)) - SB(0, 1, wrp_dn(i + 1 - nj, nx))) * rdx;
+        S2(RDq, i) = (SB(0, 2, wrp_up(i + nj, nx)) - SB(0, 2, wrp_dn(i + 1 - nj, nx))) * rdx;
       }
     }
   }
@@ -542,7 +545,7 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         RTj[c] = b * nF0[c] * S2(RrP0, i);
         SB(bs, BF, i) = nF0[c];
         SB(bs, BU0, i) = nU0[c];
-        SB(bs, BMU, i) = T(0.5) * (S2(RP0, i) + S2(RP0, wrp(i + 1, nx))) * nU0[c];
+        SB(bs, BMU, i) = T(0.5) * (S2(RP0, i) + S2(RP0, wrp_up(i + 1, nx))) * nU0[c];
         if (hasV) {
           Q0c[c] -= clk * (C)RTj[c];
           phij[c] = (T)(Q0c[c] + cpk * (C)RTj[c]);
@@ -592,9 +595,9 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         if (i >= nx) continue;
         const unsigned idx = (unsigned)i;
         const T baseF = gbF[idx], baseU = gbU[idx];
-        const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
+        const int ip = wrp_up(i + 1, nx), im = wrp_dn(i - 1, nx);
         const T Vn = SB(bs, BV0, i), Vs = SB(bs, BVm, i);
-        const T D = (SB(bs, BMU, wrp(i + nj - 1, nx)) - SB(bs, BMU, wrp(i - nj, nx))) * rdx +
+        const T D = (SB(bs, BMU, wrp_up(i + nj - 1, nx)) - SB(bs, BMU, wrp_dn(i - nj, nx))) * rdx +
                     (svj * (S2(RPV0, i) * Vn) - svm * (S2(RPVm, i) * Vs)) * rdyS;
         const C Sk = Sc[c];
         Sc[c] += (C)D * dsg;
@@ -606,7 +609,7 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) * rsg * (rp * rp);
         const C TF = ((C)(b * S2(RP0, i)) + (C)(kap * SB(bs, BF, i))) * wp;
         goF[idx] = (T)((C)baseF + A.ch * TF);
-        const T dphi = (SB(bs, BPhi, wrp(i + nj, nx)) - SB(bs, BPhi, wrp(i + 1 - nj, nx))) * rdx;
+        const T dphi = (SB(bs, BPhi, wrp_up(i + nj, nx)) - SB(bs, BPhi, wrp_dn(i + 1 - nj, nx))) * rdx;
         const T rtx = T(0.5) * (RTj[c] + b * SB(bs, BF, ip) * S2(RrP0, ip));
         const C pgf = (C)dphi + RT0c * (C)S2(RDq, i) + (C)rtx * (C)S2(RDl, i);
         const T VV = T(0.25) * (Vn + SB(bs, BV0, ip) + Vs + SB(bs, BVm, ip));
@@ -644,7 +647,7 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
         if (i >= nx) continue;
         const unsigned idv = (unsigned)i;
         const T baseV = gbV[idv];
-        const int im = wrp(i - 1, nx);
+        const int im = wrp_dn(i - 1, nx);
         const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)S2(RdQ, i) +
                        (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)S2(RdL, i)) * rdyAc;
         const T U0i = SB(bs, BU0, i), U0m = SB(bs, BU0, im), U1i = SB(bs, BU1, i), U1m = SB(bs, BU1, im);
@@ -1096,7 +1099,7 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
   for (int c = 0; c < NI; ++c) {
     const int i = t + c * B;
     if (i < nx) {
-      const int ip = wrp(i + 1, nx);
+      const int ip = wrp_up(i + 1, nx);
       S2(RrPU0, i) = isPole ? T(0) : T(2) / (S2(RP0, i) + S2(RP0, ip));
       S2(RrPU1, i) = j1Int ? T(2) / (S2(RP1, i) + S2(RP1, ip)) : T(0);
     }
@@ -1129,9 +1132,9 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     if (isPole) return capD0 * sCap[k];
     const int i = t + c * B;
     const int ii = i < nx ? i : 0;
-    const int ic = wrp(ii + nj - 1, nx), id = wrp(ii - nj, nx);
-    const T PUc = T(0.5) * (S2(RP0, ic) + S2(RP0, wrp(ic + 1, nx)));
-    const T PUd = T(0.5) * (S2(RP0, id) + S2(RP0, wrp(id + 1, nx)));
+    const int ic = wrp_up(ii + nj - 1, nx), id = wrp_dn(ii - nj, nx);
+    const T PUc = T(0.5) * (S2(RP0, ic) + S2(RP0, wrp_up(ic + 1, nx)));
+    const T PUd = T(0.5) * (S2(RP0, id) + S2(RP0, wrp_up(id + 1, nx)));
     return (C)((PUc * Uic - PUd * Uid) * rdx + (svj * (S2(RPV0, ii) * Vj) - svm * (S2(RPVm, ii) * Vm)) * rdyS);
   };
   auto div1 = [&](int k, int c, T U1ic, T U1id, T Vj, T V1) -> C {
@@ -1139,9 +1142,9 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
     if (j1Pole) return capD1 * sCap[k];
     const int i = t + c * B;
     const int ii = i < nx ? i : 0;
-    const int ic1 = wrp(ii + nj1 - 1, nx), id1 = wrp(ii - nj1, nx);
-    const T PU1c = T(0.5) * (S2(RP1, ic1) + S2(RP1, wrp(ic1 + 1, nx)));
-    const T PU1d = T(0.5) * (S2(RP1, id1) + S2(RP1, wrp(id1 + 1, nx)));
+    const int ic1 = wrp_up(ii + nj1 - 1, nx), id1 = wrp_dn(ii - nj1, nx);
+    const T PU1c = T(0.5) * (S2(RP1, ic1) + S2(RP1, wrp_up(ic1 + 1, nx)));
+    const T PU1d = T(0.5) * (S2(RP1, id1) + S2(RP1, wrp_up(id1 + 1, nx)));
     return (C)((PU1c * U1ic - PU1d * U1id) * rdx1 + (sv1 * (S2(RPV1, ii) * V1) - svj * (S2(RPV0, ii) * Vj)) * rdyS1);
   };
 
@@ -1166,10 +1169,10 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
         for (int c = 0; c < NI; ++c) {
           const int i = t + c * B;
           const int ii = i < nx ? i : 0;
-          a0[u][c] = isPole ? T(0) : gU0[(unsigned)wrp(ii + nj - 1, nx)];
-          a1[u][c] = isPole ? T(0) : gU0[(unsigned)wrp(ii - nj, nx)];
-          a2[u][c] = j1Int ? gU1[(unsigned)wrp(ii + nj1 - 1, nx)] : T(0);
-          a3[u][c] = j1Int ? gU1[(unsigned)wrp(ii - nj1, nx)] : T(0);
+          a0[u][c] = isPole ? T(0) : gU0[(unsigned)wrp_up(ii + nj - 1, nx)];
+          a1[u][c] = isPole ? T(0) : gU0[(unsigned)wrp_dn(ii - nj, nx)];
+          a2[u][c] = j1Int ? gU1[(unsigned)wrp_up(ii + nj1 - 1, nx)] : T(0);
+          a3[u][c] = j1Int ? gU1[(unsigned)wrp_dn(ii - nj1, nx)] : T(0);
           a4[u][c] = hasV ? gV0[(unsigned)ii] : T(0);
           a5[u][c] = (j >= 1) ? gVm[(unsigned)ii] : T(0);
           a6[u][c] = (j + 1 < ny) ? gV1[(unsigned)ii] : T(0);
@@ -1227,10 +1230,10 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
       nFn[c] = (!isPole && j + 1 < ny) ? gF1[ii] : Fn_p;
       nFs[c] = (!isPole && j - 1 >= 1) ? gFs[ii] : Fs_p;
       nUs[c] = (!isPole && j - 1 >= 1) ? gUs[ii] : T(0);
-      nUic[c] = isPole ? T(0) : gU0[(unsigned)wrp((int)ii + nj - 1, nx)];
-      nUid[c] = isPole ? T(0) : gU0[(unsigned)wrp((int)ii - nj, nx)];
-      nU1ic[c] = j1Int ? gU1[(unsigned)wrp((int)ii + nj1 - 1, nx)] : T(0);
-      nU1id[c] = j1Int ? gU1[(unsigned)wrp((int)ii - nj1, nx)] : T(0);
+      nUic[c] = isPole ? T(0) : gU0[(unsigned)wrp_up((int)ii + nj - 1, nx)];
+      nUid[c] = isPole ? T(0) : gU0[(unsigned)wrp_dn((int)ii - nj, nx)];
+      nU1ic[c] = j1Int ? gU1[(unsigned)wrp_up((int)ii + nj1 - 1, nx)] : T(0);
+      nU1id[c] = j1Int ? gU1[(unsigned)wrp_dn((int)ii - nj1, nx)] : T(0);
     }
   };
   // level k into LDS buffer k & 1; sigma-dot of its lower half level into slot (k + 1) % 3;
@@ -1312,8 +1315,8 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
-        const int ic = wrp(i + nj - 1, nx), id = wrp(i - nj, nx);
-        const int pM = wrp(i + Mj, nx), mM = wrp(i - Mj, nx);
+        const int ic = wrp_up(i + nj - 1, nx), id = wrp_dn(i - nj, nx);
+        const int pM = wrp_up(i + Mj, nx), mM = wrp_dn(i - Mj, nx);
         // Phi: zonal (x+1, x-1) -> (x+2N-1, x-2N+1) with u at the midpoints
         const T L1 = (SB(bs, Bu0, ic) * SB(bs, BF, pM) - SB(bs, Bu0, id) * SB(bs, BF, mM)) * rdx2;
         const T L2 = (SB(bs, Bvt0, i) * cFn[c] - SB(bs, Bvtm, i) * cFs[c]) * rdy2;
@@ -1323,11 +1326,11 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
         const C TF = -((C)L1 + (C)L2 + L3 * r2d);
         goF[i] = (T)((C)cbF[c] + A.ch * TF);
         // U: the same leap on U points, u averaged to the integer points i+n and i+1-n
-        const int pA = wrp(i + nj, nx), pB = wrp(i + 1 - nj, nx);
+        const int pA = wrp_up(i + nj, nx), pB = wrp_dn(i + 1 - nj, nx);
         const T ubA = T(0.5) * (SB(bs, Bu0, ic) + SB(bs, Bu0, pA));
         const T ubB = T(0.5) * (SB(bs, Bu0, id) + SB(bs, Bu0, pB));
         const T U1v = (ubA * SB(bs, BU, pM) - ubB * SB(bs, BU, mM)) * rdx2;
-        const int ip = wrp(i + 1, nx);
+        const int ip = wrp_up(i + 1, nx);
         const T vtn = T(0.5) * (SB(bs, Bvt0, i) + SB(bs, Bvt0, ip));
         const T vts = T(0.5) * (SB(bs, Bvtm, i) + SB(bs, Bvtm, ip));
         const T U2v = (vtn * cU1[c] - vts * cUs[c]) * rdy2;
@@ -1362,7 +1365,7 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
       for (int c = 0; c < NI; ++c) {
         const int i = t + c * B;
         if (i >= nx) continue;
-        const T L1 = (SB(bs, Buv, wrp(i + nv - 1, nx)) * SB(bs, BV, wrp(i + Mv, nx)) - SB(bs, Buv, wrp(i - nv, nx)) * SB(bs, BV, wrp(i - Mv, nx))) * rdxv2;
+        const T L1 = (SB(bs, Buv, wrp_up(i + nv - 1, nx)) * SB(bs, BV, wrp_up(i + Mv, nx)) - SB(bs, Buv, wrp_dn(i - nv, nx)) * SB(bs, BV, wrp_dn(i - Mv, nx))) * rdxv2;
         T L2 = T(0);
         if (j + 1 < ny) L2 += T(0.5) * (SB(bs, Bvt0, i) + cV1[c] * S2(RrPV1, i) * sv1) * cV1[c];
         if (j > 0) L2 -= T(0.5) * (SB(bs, Bvtm, i) + SB(bs, Bvt0, i)) * cVm[c];
