@@ -602,14 +602,15 @@ __global__ void k_uv(Ctx<T> c) {
   if (j < g.ny) stg(c.s.VT, id, ldg(c.V, id) * (T(1) / (T(0.5) * (P2(c, j, i) + P2(c, j + 1, i)))) * (T)g.sv[j]);
 }
 
-template <typename T>
-__global__ void k_l1(Ctx<T> c) {
+// FAST: rows 2..ny-2 at levels 1..nz-2, where every neighbour row and level exists and none is a
+// pole: the pole and boundary branches fold away and the reads shared by several outputs (with
+// every store at the end) are made once.
+template <typename T, bool FAST>
+__device__ __forceinline__ void l1_point(const Ctx<T>& c, int j, int k, int i) {
   const GeoDev& g = c.g;
-  int tx, k, j;
-  xcd_tile3((int)gridDim.x, g.nz, g.ny + 1, tx, k, j);
-  const int i = tx * blockDim.x + threadIdx.x;
-  if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
+  auto tr = [&](bool x) { return FAST || x; };    // holds on the fast path
+  auto fl = [&](bool x) { return !FAST && x; };   // fails on the fast path
   // per-point arithmetic in the field precision (every output is stored in it)
   using A = T;
   const A ch = (A)c.ch;
@@ -619,7 +620,9 @@ __global__ void k_l1(Ctx<T> c) {
   auto amF = [&](int jr, int kk, int ii) -> A { return -ch * (A)ldg(c.aoF, i3u(g, jr, kk, ii)); };
   auto amU = [&](int jr, int kk, int ii) -> A { return -ch * (A)ldg(c.aoU, i3u(g, jr, kk, ii)); };
   auto amV = [&](int jv, int kk, int ii) -> A { return -ch * (A)ldg(c.aoV, i3u(g, jv, kk, ii)); };
-  auto interior = [&](int jr) { return jr >= 1 && jr <= ny - 1; };
+  auto interior = [&](int jr) { return tr(jr >= 1 && jr <= ny - 1); };
+  auto FeL = [&](int jr, int kk, int ii) -> A { return FAST ? (A)ldg(c.F, i3u(g, jr, kk, ii)) : (A)Fe(c, jr, kk, ii); };
+  auto UeL = [&](int jr, int kk, int ii) -> A { return FAST ? (A)ldg(c.U, i3u(g, jr, kk, ii)) : (A)Ue(c, jr, kk, ii); };
   auto sd = [&](int jr, int h, int ii) -> A { return (A)ldg(c.s.SD, ihu(g, jr, h, ii)); };
   // the forward's difference factors (rounded to the field precision)
   auto rdx2 = [&](int jr) -> A { return (A)(0.5 * c.f.rdx[jr]); };
@@ -627,17 +630,19 @@ __global__ void k_l1(Ctx<T> c) {
   auto rdxv2 = [&](int jv) -> A { return (A)c.f.rdxv2[jv]; };
   auto rdyv2 = [&](int jv) -> A { return (A)c.f.rdyv2[jv]; };
   auto r2d = [&](int kk) -> A { return (A)c.f.r2d[kk]; };
-  auto uA = [&](int jr, int q) -> A { return (jr >= 1 && jr < ny) ? (A)ldg(c.s.UA, i3u(g, jr, k, q)) : A(0); };
+  auto uA = [&](int jr, int q) -> A { return tr(jr >= 1 && jr < ny) ? (A)ldg(c.s.UA, i3u(g, jr, k, q)) : A(0); };
   auto vA = [&](int jv, int kk, int ii) -> A { return (A)ldg(c.s.VT, i3u(g, jv, kk, ii)); };
   auto ub = [&](int jr, int q) -> A {   // u averaged to integer point q of U row jr
     return A(0.5) * (uA(jr, wrp_dn(q - 1, nx)) + uA(jr, q));
   };
   auto uv = [&](int jv, int q) -> A { return A(0.5) * (uA(jv, q) + uA(jv + 1, q)); };
   auto vts = [&](int js, int kk, int ii) -> A {   // v sin(theta) on scalar row js
-    if (js <= 0 || js >= ny) return A(0);
+    if (fl(js <= 0 || js >= ny)) return A(0);
     return A(0.5) * (vA(js - 1, kk, ii) + vA(js, kk, ii));
   };
   const unsigned id = i3u(g, j, k, i);
+  // every output is stored at the end, so that the loads shared by several outputs are made once
+  A oFE = 0, oUU = 0, oUD = 0, oVD = 0, oVV = 0, oSD = 0;
 
   // ---- scalar point: adjoint of Phi (pole-read copies included)
   {
@@ -649,11 +654,11 @@ __global__ void k_l1(Ctx<T> c) {
     }
     if (interior(j - 1)) a += amF(j - 1, k, i) * vA(j - 1, k, i) * rdy2(j - 1);
     if (interior(j + 1)) a -= amF(j + 1, k, i) * vA(j, k, i) * rdy2(j + 1);
-    if (j == 1) a += cc * vA(0, k, i) * AN;
-    if (j == ny - 1) a -= cc * vA(ny - 1, k, i) * AS;
-    if (k >= 1) a += amF(j, k - 1, i) * sd(j, k, i) * r2d(k - 1);
-    if (k + 1 < nz) a -= amF(j, k + 1, i) * sd(j, k + 1, i) * r2d(k + 1);
-    stg(c.s.AFE, id, (T)a);
+    if (fl(j == 1)) a += cc * vA(0, k, i) * AN;
+    if (fl(j == ny - 1)) a -= cc * vA(ny - 1, k, i) * AS;
+    if (tr(k >= 1)) a += amF(j, k - 1, i) * sd(j, k, i) * r2d(k - 1);
+    if (tr(k + 1 < nz)) a -= amF(j, k + 1, i) * sd(j, k + 1, i) * r2d(k + 1);
+    oFE = a;
   }
   // ---- U point
   if (interior(j)) {
@@ -662,10 +667,10 @@ __global__ void k_l1(Ctx<T> c) {
     A au = 0;
     {
       const int qa = wrp_dn(i - n + 1, nx), qb = wrp_up(i + n, nx);
-      au += (amF(j, k, qa) * (A)Fe(c, j, k, wrp_up(qa + M, nx)) - amF(j, k, qb) * (A)Fe(c, j, k, wrp_dn(qb - M, nx))) * rdx2(j);
+      au += (amF(j, k, qa) * FeL(j, k, wrp_up(qa + M, nx)) - amF(j, k, qb) * FeL(j, k, wrp_dn(qb - M, nx))) * rdx2(j);
       auto aub = [&](int q) -> A {
         const int r1 = wrp_dn(q - n, nx), r2 = wrp_up(q - 1 + n, nx);
-        return (amU(j, k, r1) * (A)Ue(c, j, k, wrp_up(r1 + M, nx)) - amU(j, k, r2) * (A)Ue(c, j, k, wrp_dn(r2 - M, nx))) * rdx2(j);
+        return (amU(j, k, r1) * UeL(j, k, wrp_up(r1 + M, nx)) - amU(j, k, r2) * UeL(j, k, wrp_dn(r2 - M, nx))) * rdx2(j);
       };
       au += A(0.5) * (aub(i) + aub(wrp_up(i + 1, nx)));
       for (int jv : {j - 1, j}) {
@@ -676,7 +681,7 @@ __global__ void k_l1(Ctx<T> c) {
         au += A(0.5) * auv;
       }
     }
-    stg(c.s.AUU, id, (T)au);
+    oUU = au;
     // direct adjoint of U
     A aU = 0;
     {
@@ -691,56 +696,56 @@ __global__ void k_l1(Ctx<T> c) {
         const A vtu = A(0.5) * (vA(j, k, i) + vA(j, k, ip1));
         aU -= amU(j + 1, k, i) * vtu * rdy2(j + 1);
       }
-      if (k >= 1) aU += amU(j, k - 1, i) * A(0.5) * (sd(j, k, i) + sd(j, k, ip1)) * r2d(k - 1);
-      if (k + 1 < nz) aU -= amU(j, k + 1, i) * A(0.5) * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) * r2d(k + 1);
+      if (tr(k >= 1)) aU += amU(j, k - 1, i) * A(0.5) * (sd(j, k, i) + sd(j, k, ip1)) * r2d(k - 1);
+      if (tr(k + 1 < nz)) aU -= amU(j, k + 1, i) * A(0.5) * (sd(j, k + 1, i) + sd(j, k + 1, ip1)) * r2d(k + 1);
     }
-    stg(c.s.AUD, id, (T)aU);
+    oUD = aU;
   }
   // ---- V point
-  if (j < ny) {
+  if (tr(j < ny)) {
     const int jv = j;
     const int Mv = g.Mv[jv], nv = (Mv + 1) / 2;
     A aV = 0;
     {
       const int pm = wrp_dn(i - Mv, nx), pp = wrp_up(i + Mv, nx);
       aV += (amV(jv, k, pm) * uv(jv, wrp_up(pm + nv - 1, nx)) - amV(jv, k, pp) * uv(jv, wrp_dn(pp - nv, nx))) * rdxv2(jv);
-      if (jv >= 1) aV += amV(jv - 1, k, i) * vts(jv, k, i) * rdyv2(jv - 1);
-      if (jv + 1 <= ny - 1) aV -= amV(jv + 1, k, i) * vts(jv + 1, k, i) * rdyv2(jv + 1);
-      if (k >= 1) aV += amV(jv, k - 1, i) * A(0.5) * (sd(jv, k, i) + sd(jv + 1, k, i)) * r2d(k - 1);
-      if (k + 1 < nz)
+      if (tr(jv >= 1)) aV += amV(jv - 1, k, i) * vts(jv, k, i) * rdyv2(jv - 1);
+      if (tr(jv + 1 <= ny - 1)) aV -= amV(jv + 1, k, i) * vts(jv + 1, k, i) * rdyv2(jv + 1);
+      if (tr(k >= 1)) aV += amV(jv, k - 1, i) * A(0.5) * (sd(jv, k, i) + sd(jv + 1, k, i)) * r2d(k - 1);
+      if (tr(k + 1 < nz))
         aV -= amV(jv, k + 1, i) * A(0.5) * (sd(jv, k + 1, i) + sd(jv + 1, k + 1, i)) * r2d(k + 1);
     }
-    stg(c.s.AVD, id, (T)aV);
+    oVD = aV;
     // adjoint of v sin(theta) on this V row
     A avt = 0;
-    if (interior(jv)) avt += amF(jv, k, i) * (A)Fe(c, jv + 1, k, i) * rdy2(jv);
-    if (interior(jv + 1)) avt -= amF(jv + 1, k, i) * (A)Fe(c, jv, k, i) * rdy2(jv + 1);
-    if (jv == 0) avt += cc * (A)Fe(c, 1, k, i) * AN;
-    if (jv == ny - 1) avt -= cc * (A)Fe(c, ny - 1, k, i) * AS;
+    if (interior(jv)) avt += amF(jv, k, i) * FeL(jv + 1, k, i) * rdy2(jv);
+    if (interior(jv + 1)) avt -= amF(jv + 1, k, i) * FeL(jv, k, i) * rdy2(jv + 1);
+    if (fl(jv == 0)) avt += cc * (A)Fe(c, 1, k, i) * AN;
+    if (fl(jv == ny - 1)) avt -= cc * (A)Fe(c, ny - 1, k, i) * AS;
     auto avtu = [&](int p) -> A {
       A r = 0;
-      if (interior(jv)) r += amU(jv, k, p) * (A)Ue(c, jv + 1, k, p) * rdy2(jv);
-      if (interior(jv + 1)) r -= amU(jv + 1, k, p) * (A)Ue(c, jv, k, p) * rdy2(jv + 1);
+      if (interior(jv)) r += amU(jv, k, p) * UeL(jv + 1, k, p) * rdy2(jv);
+      if (interior(jv + 1)) r -= amU(jv + 1, k, p) * UeL(jv, k, p) * rdy2(jv + 1);
       return r;
     };
     avt += A(0.5) * (avtu(i) + avtu(wrp_dn(i - 1, nx)));
     auto avts = [&](int js) -> A {
-      if (js <= 0 || js >= ny) return A(0);
+      if (fl(js <= 0 || js >= ny)) return A(0);
       return amV(js - 1, k, i) * (A)Ve(c, js, k, i) * rdyv2(js - 1) - amV(js, k, i) * (A)Ve(c, js - 1, k, i) * rdyv2(js);
     };
     avt += A(0.5) * (avts(jv) + avts(jv + 1));
-    stg(c.s.AVV, id, (T)(avt * (A)g.sv[jv]));
+    oVV = avt * (A)g.sv[jv];
   }
   // ---- half level h = k (1..nz-1): adjoint of sigma-dot of scalar row j
-  if (k >= 1) {
+  if (tr(k >= 1)) {
     const int h = k;
     A a = 0;
-    a += amF(j, h - 1, i) * (A)Fe(c, j, h, i) * r2d(h - 1) -
-         amF(j, h, i) * (A)Fe(c, j, h - 1, i) * r2d(h);
+    a += amF(j, h - 1, i) * FeL(j, h, i) * r2d(h - 1) -
+         amF(j, h, i) * FeL(j, h - 1, i) * r2d(h);
     if (interior(j)) {
       auto asdu = [&](int p) -> A {
-        return amU(j, h - 1, p) * (A)Ue(c, j, h, p) * r2d(h - 1) -
-               amU(j, h, p) * (A)Ue(c, j, h - 1, p) * r2d(h);
+        return amU(j, h - 1, p) * UeL(j, h, p) * r2d(h - 1) -
+               amU(j, h, p) * UeL(j, h - 1, p) * r2d(h);
       };
       a += A(0.5) * (asdu(i) + asdu(wrp_dn(i - 1, nx)));
     }
@@ -748,10 +753,30 @@ __global__ void k_l1(Ctx<T> c) {
       return amV(jv, h - 1, i) * (A)Ve(c, jv, h, i) * r2d(h - 1) -
              amV(jv, h, i) * (A)Ve(c, jv, h - 1, i) * r2d(h);
     };
-    if (j >= 1) a += A(0.5) * asdv(j - 1);
-    if (j <= ny - 1) a += A(0.5) * asdv(j);
-    stg(c.s.ASD, ihu(g, j, h, i), (T)a);
+    if (tr(j >= 1)) a += A(0.5) * asdv(j - 1);
+    if (tr(j <= ny - 1)) a += A(0.5) * asdv(j);
+    oSD = a;
   }
+  stg(c.s.AFE, id, (T)oFE);
+  if (interior(j)) {
+    stg(c.s.AUU, id, (T)oUU);
+    stg(c.s.AUD, id, (T)oUD);
+  }
+  if (tr(j < ny)) {
+    stg(c.s.AVD, id, (T)oVD);
+    stg(c.s.AVV, id, (T)oVV);
+  }
+  if (tr(k >= 1)) stg(c.s.ASD, ihu(g, j, k, i), (T)oSD);
+}
+
+template <typename T>
+__global__ void k_l1(Ctx<T> c) {
+  int tx, k, j;
+  xcd_tile3((int)gridDim.x, c.g.nz, c.g.ny + 1, tx, k, j);
+  const int i = tx * blockDim.x + threadIdx.x;
+  if (i >= c.g.nx) return;
+  if (j >= 2 && j <= c.g.ny - 2 && k >= 1 && k + 1 < c.g.nz) l1_point<T, true>(c, j, k, i);
+  else l1_point<T, false>(c, j, k, i);
 }
 
 // sigma-dot transposes per column: aPi, aS_h, aP; then aD_l = dsig_l (aPi + sum_{h>l} aS_h)
