@@ -203,9 +203,16 @@ __global__ void k_f1(Ctx<T> c) {
   const int pa = wrp(i + n - 1, nx), pb = wrp(i - n, nx), im1 = wrp(i - 1, nx);
   const T PUa = PUe(c, j, pa), PUb = PUe(c, j, pb), PU0 = PUe(c, j, i), PUm = PUe(c, j, im1);
   C H = 0, S = 0;
+  // advection: u at the U point and v sin(theta) on V row j, as k_uv forms them (rows 1..ny-1)
+  const T rPU2 = all ? T(0) : T(2) / (P0 + P2(c, j, wrp(i + 1, nx)));
+  const T rPVs = all ? T(0) : T(1) / (T(0.5) * (P2(c, j, i) + P2(c, j + 1, i)));
   stg(c.s.S, ihu(g, j, 0, i), T(0));
   for (int k = 0; k < nz; ++k) {
     const unsigned id = i3u(g, j, k, i);
+    if (!all) {
+      stg(c.s.UA, id, ldg(c.U, id) * rPU2);
+      stg(c.s.VT, id, ldg(c.V, id) * rPVs * (T)g.sv[j]);
+    }
     if (all) {
       const T RT = b * Fe(c, j, k, i) / P0;
       stg(c.s.RT, id, RT);
@@ -591,8 +598,9 @@ __device__ __forceinline__ void a3_point(const Ctx<T>& c, int j, int k, int i, A
 template <typename T>
 __global__ void k_uv(Ctx<T> c) {
   const GeoDev& g = c.g;
-  int tx, k, j;
-  xcd_tile3((int)gridDim.x, g.nz, g.ny + 1, tx, k, j);
+  int tx, k, jy;
+  xcd_tile3((int)gridDim.x, g.nz, (int)gridDim.z, tx, k, jy);
+  const int j = c.jr0 + c.jrs * jy;   // rows jr0 + jrs * (grid row index)
   const int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const unsigned id = i3u(g, j, k, i);
@@ -1593,7 +1601,13 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
-  hipLaunchKernelGGL((k_uv<T>), g3, dim3(tb), 0, s, c);
+  {
+    // u and v sin(theta) of rows 1..ny-1 come from the forward recompute (k_f1); here the pole rows
+    Ctx<T> cu = c;
+    cu.jr0 = 0;
+    cu.jrs = ny;
+    hipLaunchKernelGGL((k_uv<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cu);
+  }
   hipLaunchKernelGGL((k_l1<T>), g3, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_l2<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
