@@ -796,17 +796,18 @@ __global__ void k_l2(Ctx<T> c) {
   if (i >= g.nx) return;
   const int nz = g.nz;
   const C P = (C)P2(c, j, i), P2c = P * P;
-  const C Pi = (C)c.s.S[ih<T>(g, j, nz, i)];
+  const C rP2 = 1.0 / P2c, rP3 = 1.0 / (P2c * P);   // the level loops only multiply
+  const C Pi = (C)ldg((const T*)c.s.S, ihu(g, j, nz, i));
   C aPi = 0, aP = 0;
   for (int h = 1; h < nz; ++h) {
-    const C a = (C)c.s.ASD[ih<T>(g, j, h, i)];
-    aPi += g.sigh[h] * a / P2c;
-    aP += -2.0 * (g.sigh[h] * Pi - (C)c.s.S[ih<T>(g, j, h, i)]) / (P2c * P) * a;
+    const C a = (C)ldg((const T*)c.s.ASD, ihu(g, j, h, i));
+    aPi += g.sigh[h] * a * rP2;
+    aP += -2.0 * (g.sigh[h] * Pi - (C)ldg((const T*)c.s.S, ihu(g, j, h, i))) * rP3 * a;
   }
   C acc = 0;   // sum_{h > l} aS_h, aS_h = -asd_h / P^2
   for (int l = nz - 1; l >= 0; --l) {
-    c.s.AD[i3<T>(g, j, l, i)] = (T)(g.dsig[l] * (aPi + acc));
-    if (l >= 1) acc += -(C)c.s.ASD[ih<T>(g, j, l, i)] / P2c;
+    stg(c.s.AD, i3u(g, j, l, i), (T)(g.dsig[l] * (aPi + acc)));
+    if (l >= 1) acc += -(C)ldg((const T*)c.s.ASD, ihu(g, j, l, i)) * rP2;
   }
   c.s.AP2[(size_t)j * g.nx + i] = aP;
 }
