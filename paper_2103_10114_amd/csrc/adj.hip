@@ -364,6 +364,24 @@ __global__ void __launch_bounds__(64) k_pole_sum(GeoDev g, const T* f3, const T*
   if (threadIdx.x == 0) out[p * (g.nz + 1) + k] = s;
 }
 
+// The pole sums of two level fields in one launch: blocks [0, 2(nz+1)) sum fa into outa, the next
+// 2(nz+1) fb into outb, each exactly as k_pole_sum does.
+template <typename T>
+__global__ void __launch_bounds__(64) k_pole_sum2(GeoDev g, const T* fa, double* outa, const T* fb, double* outb) {
+  const int nb = 2 * (g.nz + 1);
+  const bool second = (int)blockIdx.x >= nb;
+  const int v = second ? (int)blockIdx.x - nb : (int)blockIdx.x;
+  const T* f3 = second ? fb : fa;
+  double* out = second ? outb : outa;
+  const int p = v / (g.nz + 1), k = v % (g.nz + 1);
+  const int j = p == 0 ? 0 : g.ny;
+  C s = 0;
+  if (k < g.nz)
+    for (int i = threadIdx.x; i < g.nx; i += 64) s += (C)f3[((size_t)j * g.nz + k) * g.nx + i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[p * (g.nz + 1) + k] = s;
+}
+
 template <typename T>
 __global__ void k_base_pole(Ctx<T> c) {
   const GeoDev& g = c.g;
@@ -1569,10 +1587,8 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     cp.jrs = ny;
     cp.parts = 1;   // scalar points of the pole rows (their sums feed the interior rows)
     hipLaunchKernelGGL((k_a12<T, 6, 1>), dim3(gx, 2), dim3(tb), 0, s, cp);
-    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
-                       (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
-    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL,
-                       (const T*)nullptr, c.s.psum + PS_AVGL * 2 * (nz + 1));
+    hipLaunchKernelGGL((k_pole_sum2<T>), dim3(4 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
+                       c.s.psum + PS_AD * 2 * (nz + 1), (const T*)c.s.AVGL, c.s.psum + PS_AVGL * 2 * (nz + 1));
     const hipError_t e = (nx + c.blk - 1) / c.blk == 1 ? launch_aar<T, 1>(c, s) : launch_aar<T, 2>(c, s);
     if (e != hipSuccess) return e;
     Ctx<T> cv = c;   // V row 1/2: reads phi' and R T' of row 1, written by the row-fused kernel
@@ -1583,10 +1599,8 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     hipLaunchKernelGGL((k_a4<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
   } else {
     hipLaunchKernelGGL((k_a12<T, 1, 0>), g2, dim3(tb), 0, s, c);
-    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
-                       (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
-    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AVGL,
-                       (const T*)nullptr, c.s.psum + PS_AVGL * 2 * (nz + 1));
+    hipLaunchKernelGGL((k_pole_sum2<T>), dim3(4 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
+                       c.s.psum + PS_AD * 2 * (nz + 1), (const T*)c.s.AVGL, c.s.psum + PS_AVGL * 2 * (nz + 1));
     hipLaunchKernelGGL((k_a3t1<T>), g3, dim3(tb), 0, s, c);
     hipLaunchKernelGGL((k_a4<T>), g2, dim3(tb), 0, s, c);
   }
