@@ -78,6 +78,8 @@ struct Ctx {
   int ai_zero = 0;                 // the input adjoint starts at zero and, in its interior rows, only the
                                    // row-fused kernel adds to it: those rows are stored without a read
                                    // (and need not be cleared by the caller)
+  int base_in_tail = 0;            // advection with one base and input adjoint: the interior base transpose
+                                   // is added by the column tail (k_l3, k_t3) instead of k_base
 };
 
 template <typename T>
@@ -978,7 +980,8 @@ __global__ void k_l3(Ctx<T> c) {
     if (intr) {
       const C aMU = ((C)ldg(c.s.AD, i3u(g, j, k, ia)) - (C)ldg(c.s.AD, i3u(g, j, k, ib))) * rdxU;
       const C U = (C)ldg(c.U, id);
-      stg(c.aiU, id, (T)((C)ldg((const T*)c.aiU, id) + o.aud + o.au * rPU + PU * aMU));
+      const C bU = c.base_in_tail ? (C)ldg(c.aoU, id) : 0.0;
+      stg(c.aiU, id, (T)((C)ldg((const T*)c.aiU, id) + bU + o.aud + o.au * rPU + PU * aMU));
       aPU += -U * (rPU * rPU) * o.au + U * aMU;
     }
     if (j < ny) {
@@ -987,11 +990,12 @@ __global__ void k_l3(Ctx<T> c) {
       const C tS = (jv + 1 <= ny - 1) ? (C)ldg(c.s.AD, i3u(g, jv + 1, k, i)) * rdyS : capD * sD[1 * (nz + 1) + k];
       const C aMV = svj * (tN - tS);
       const C V = (C)ldg(c.V, id);
-      stg(c.aiV, id, (T)((C)ldg((const T*)c.aiV, id) + o.avd + o.avv * rPV + PV * aMV));
+      const C bV = c.base_in_tail ? (C)ldg(c.aoV, id) : 0.0;
+      stg(c.aiV, id, (T)((C)ldg((const T*)c.aiV, id) + bV + o.avd + o.avv * rPV + PV * aMV));
       aPV += -V * (rPV * rPV) * o.avv + V * aMV;
     }
     const C afe = (C)ldg(c.s.AFE, id);
-    if (intr) stg(c.aiF, id, (T)((C)ldg((const T*)c.aiF, id) + afe));
+    if (intr) stg(c.aiF, id, (T)((C)ldg((const T*)c.aiF, id) + (c.base_in_tail ? (C)ldg(c.aoF, id) : 0.0) + afe));
     else stg(c.s.AFE, id, (T)afe);     // pole copies: aggregated later
   }
   c.s.AP2[i2] = aP;
@@ -1030,7 +1034,7 @@ __global__ void k_t3(Ctx<T> c) {
   const C Pv = (C)P2(c, j, i);
   const C ps = (C)psE(c, j, i);
   const C aps = aP / (2.0 * g.p0 * Pv) + aL / ps;
-  if (j >= 1 && j < ny) c.aiP[i2] = (T)((C)c.aiP[i2] + aps);
+  if (j >= 1 && j < ny) c.aiP[i2] = (T)((C)c.aiP[i2] + (c.base_in_tail ? (C)c.aoP[i2] : 0.0) + aps);
   else c.s.APSR[i2] = aps;
 }
 
@@ -1562,8 +1566,9 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   if (!rows) hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, cf);
   hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, s, c);
-  if (c.abU) {
-    // interior rows' base transpose is folded into the row-fused kernel; V row 1/2 stays here
+  if (c.abU && !c.base_in_tail) {
+    // interior rows' base transpose is folded into the row-fused kernel (adaptation) or the column
+    // tail (advection with one accumulator); V row 1/2 stays here for the row-fused case
     hipLaunchKernelGGL((k_base<T>), rows ? dim3(gx, nz, 1) : g3, dim3(tb), 0, s, c);
   }
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
@@ -1731,6 +1736,7 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.blk = v.block;
   c.timer = v.timer;
   c.ai_zero = ai_zero && ab.U != ai.U;
+  c.base_in_tail = process == 1 && ab.U && ab.U == ai.U && ab.V == ai.V && ab.F == ai.F && ab.P == ai.P;
   hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
   if (e != hipSuccess) return e;
   e = run_stage_adjoint<T>(c, s, process == 0);
