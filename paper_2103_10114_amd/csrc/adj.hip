@@ -1756,16 +1756,30 @@ hipError_t zero_state(const HandleView& v, St4<T> a, hipStream_t s) {
 // Zeroes only what kernels other than the row-fused adaptation adjoint add to: pole rows of U and
 // Phi, V row 1/2 and p_s.  The row-fused kernel stores the interior rows of an input adjoint the
 // caller marks as zeroed (Ctx::ai_zero).
+// The six segments cleared in one launch: blockIdx.y picks the segment, the blocks along x stride
+// over it (vector stores).
+template <typename T>
+struct ZeroSegs {
+  T* p[6];
+  unsigned n[6];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_segs(ZeroSegs<T> z) {
+  T* p = z.p[blockIdx.y];
+  const unsigned n = z.n[blockIdx.y];
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) p[i] = T(0);
+}
+
 template <typename T>
 hipError_t zero_outside_rows(const HandleView& v, St4<T> a, hipStream_t s) {
   const size_t row = (size_t)v.g.nz * v.g.nx;
-  hipError_t e = launch_zero<T>(a.U, row, s);
-  if (e == hipSuccess) e = launch_zero<T>(a.U + (size_t)v.g.ny * row, row, s);
-  if (e == hipSuccess) e = launch_zero<T>(a.F, row, s);
-  if (e == hipSuccess) e = launch_zero<T>(a.F + (size_t)v.g.ny * row, row, s);
-  if (e == hipSuccess) e = launch_zero<T>(a.V, row, s);
-  if (e == hipSuccess) e = launch_zero<T>(a.P, v.nP, s);
-  return e;
+  const ZeroSegs<T> z{{a.U, a.U + (size_t)v.g.ny * row, a.F, a.F + (size_t)v.g.ny * row, a.V, a.P},
+                      {(unsigned)row, (unsigned)row, (unsigned)row, (unsigned)row, (unsigned)row, (unsigned)v.nP}};
+  const size_t most = std::max(row, v.nP);
+  const unsigned gx = (unsigned)std::min<size_t>((most + 255) / 256, 1024);
+  hipLaunchKernelGGL((k_zero_segs<T>), dim3(gx, 6), dim3(256), 0, s, z);
+  return hipGetLastError();
 }
 
 // Whether the adaptation-stage adjoint of this handle runs the row-fused kernel (as aar_used).
