@@ -4,8 +4,8 @@
  * primitive equations (eq. 1 of AGCM-3DLF, arXiv 2103.10114): zonal wind U,
  * meridional wind V, temperature variable Phi and surface pressure p_s, on the
  * latitude-longitude-sigma Arakawa C grid (Sec. III-B).  Zonal differences use
- * the leap format (eq. 7) with the per-latitude span of eq. 8 and the leap
- * patterns of Table 6; a step is the split of eq. 2 with 3M adaptation and 3
+ * the leap format (eq. 6) with the per-latitude span of eq. 7 and the leap
+ * patterns of Table VII; a step is the split of eq. 2 with 3M adaptation and 3
  * advection calls (Sec. III-D, message aggregation).
  *
  * Layout of every field: contiguous [j][k][i], longitude i fastest, then
@@ -55,7 +55,8 @@ typedef struct {
   int ny;                  /* latitude intervals (ny+1 scalar rows incl. both poles), >= 4 */
   int nz;                  /* sigma levels, >= 1, <= 128; nx (ny+1) (nz+1) x element size < 4 GiB */
   double dt;               /* outer time step, seconds, > 0 */
-  int n_adapt_substeps;    /* M of Sec. III-D; 0 = from the CFL bound ceil(w_max dt / (0.8 sqrt 3)) */
+  int n_adapt_substeps;    /* M of Sec. III-D; 0 = from the CFL bound ceil(w_max dt / (0.8 sqrt 3));
+                              a given M below that bound (dt / M above the CFL limit) is EINVAL */
   int prec;                /* dycore_precision of every field pointer */
   const double* sigma_half;/* host, nz+1 increasing values from 0 to 1, or NULL for uniform */
   const double* phis;      /* host, (ny+1)*nx surface geopotential (m^2/s^2), copied; NULL = flat */
@@ -65,7 +66,7 @@ typedef struct {
   int block;               /* threads per row workgroup (64..1024, multiple of 64); 0 = tuned default */
 } dycore_config;
 
-/* Create a handle: validates the config, builds the leap table (eq. 8; span made
+/* Create a handle: validates the config, builds the leap table (eq. 7; span made
  * odd, Sec. III-B) and geometry, uploads them and reserves all scratch.
  * Returns DYCORE_EINVAL (bad config), DYCORE_ENOMEM, DYCORE_EHIP. */
 int dycore_create(const dycore_config* cfg, dycore_t* out);
@@ -133,7 +134,7 @@ int dycore_diagnostics(dycore_t h, const void* U, const void* V, const void* Phi
 int dycore_check_finite(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,
                         long long* count_out, void* stream);
 
-/* Leap spans (odd, eq. 8): ny+1 values for scalar/U rows (1 at the poles) and ny for V rows. */
+/* Leap spans (odd, eq. 7): ny+1 values for scalar/U rows (1 at the poles) and ny for V rows. */
 int dycore_leap_table(dycore_t h, int* m_rows, int* m_vrows);
 
 /* Adaptation sub-steps M in use; block size in use. */
@@ -144,7 +145,7 @@ int dycore_block(dycore_t h);
 size_t dycore_workspace_bytes(dycore_t h);
 
 /* Live timing of the row-fused adaptation-stage adjoint kernel (the dominant kernel of
- * dycore_step_adjoint and dycore_step_adjoint_recorded; Sec. III-D, eq. 7, transposed):
+ * dycore_step_adjoint and dycore_step_adjoint_recorded; Sec. III-D, eq. 6, transposed):
  * start makes 2 max_launches HIP events (host call, allocates; not for a timed region) and
  * arms the handle; every later launch of that kernel on the handle, up to max_launches, is
  * bracketed by events recorded on its launch stream.  stop waits for the last recorded event,

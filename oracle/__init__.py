@@ -122,10 +122,10 @@ class Oracle:
         s = self._c(st)
         nx, ny, nz = self.nx, self.ny, self.nz
         D = np.zeros((ny + 1, nz, nx)); phi = np.zeros_like(D); wp = np.zeros_like(D)
-        sd = np.zeros((ny + 1, nz + 1, nx)); Pi = np.zeros((ny + 1, nx))
+        sd = np.zeros((ny + 1, nz + 1, nx)); Pi = np.zeros((ny + 1, nx)); vgl = np.zeros_like(D)
         self.L.orc_column_diag(self._vh(), _p(s["U"]), _p(s["V"]), _p(s["Phi"]), _p(s["ps"]),
-                               _p(D), _p(phi), _p(wp), _p(sd), _p(Pi))
-        return {"D": D, "phi": phi, "wp": wp, "sd": sd, "Pi": Pi}
+                               _p(D), _p(phi), _p(wp), _p(sd), _p(Pi), _p(vgl))
+        return {"D": D, "phi": phi, "wp": wp, "sd": sd, "Pi": Pi, "vgl": vgl}
 
     def stage(self, base, yin, ch, which):
         b = self._c(base)
@@ -200,18 +200,6 @@ class Oracle:
         self.L.orc_diagnostics(self._vh(), _p(s["U"]), _p(s["V"]), _p(s["Phi"]), _p(s["ps"]),
                                ctypes.byref(m), ctypes.byref(e))
         return m.value, e.value
-
-    def scan_alg1(self, D):
-        D = np.ascontiguousarray(D, dtype=np.float64)
-        S = np.zeros(self.nz + 1); psd = np.zeros(self.nz + 1)
-        self.L.orc_scan_alg1(self._vh(), _p(D), _p(S), _p(psd))
-        return S, psd
-
-    def scan_alg2(self, D, nblocks):
-        D = np.ascontiguousarray(D, dtype=np.float64)
-        S = np.zeros(self.nz + 1); psd = np.zeros(self.nz + 1)
-        self.L.orc_scan_alg2(self._vh(), _p(D), ctypes.c_int(nblocks), _p(S), _p(psd))
-        return S, psd
 
 
 def num_threads() -> int:

@@ -8,11 +8,13 @@
 //   * eq. 1  : the IAP-transformed primitive equations for U, V, Phi, p_s
 //   * eq. 2  : the split dF/dt = -L_F + A_F into advection and adaptation
 //   * Sec. III-B, C grid: U at (x+1/2,y), V at (x,y+1/2), scalars at (x,y)
-//   * eq. 6/7: central zonal difference and its leap-format generalisation
-//   * eq. 8  : N_leap from the 45-degree reference spacing
-//   * Table 6: the leap patterns (x+1,x)->(x+N,x-N+1), (x,x-1)->(x+N-1,x-N),
+//   * eq. 5/6: central zonal difference and its leap-format generalisation
+//   * eq. 7  : N_leap from the 45-degree reference spacing
+//   * Table VII: the leap patterns (x+1,x)->(x+N,x-N+1), (x,x-1)->(x+N-1,x-N),
 //              (x+1,x-1)->(x+2N-1,x-2N+1) with N the half width
-//   * Alg. 1/2: column sum and prefix sum behind the sigma-dot diagnosis
+//   * Alg. 1/2: the column sum and prefix sum behind the sigma-dot diagnosis
+//     (one plain sequential scan per column; the blocked form of Alg. 2 is the
+//     same sum regrouped)
 //   * Sec. III-D (message aggregation): 3M adaptation and 3 advection calls
 //     per step
 // Every difference form that the paper names without printing it is a stated
@@ -43,13 +45,13 @@ struct Geo {
   double dlam, dth, acap;
   std::vector<double> s, cot, f;        // scalar/U rows j = 0..ny (theta_j = j*dth)
   std::vector<double> sv, cotv, fv;     // V rows jv = 0..ny-1 (theta = (jv+1/2)*dth)
-  std::vector<double> r, rv;            // eq. 8 ratio per row
+  std::vector<double> r, rv;            // eq. 7 ratio per row
   std::vector<int> M, n, Mv, nv;        // leap span (odd) and half width
   std::vector<double> sigh, sig, dsig, cl, cpk;
   std::vector<double> phis;             // (ny+1)*nx, pole rows replaced by their mean
 };
 
-// eq. 8 with res = dlam and cos(90deg - theta) = sin(theta); the result is
+// eq. 7 with res = dlam and cos(90deg - theta) = sin(theta); the result is
 // rounded up, made odd (a U-point difference must land on U points), and kept
 // below nx/2 so that i+M and i-M are distinct columns.
 int leap_span(double sin_theta, double dlam, int nx, double* ratio) {
@@ -193,7 +195,7 @@ void diagnose(const Geo& g, const St<T>& y, Work<T>& w) {
         w.MV[id] = w.PV[z.i2(jv, i)] * y.V[id];
       }
 
-  // Divergence D of the mass flux: leaped zonal part (Table 6 pattern (x,x-1) ->
+  // Divergence D of the mass flux: leaped zonal part (Table VII pattern (x,x-1) ->
   // (x+N-1, x-N)) plus the plain meridional part; cap divergences at the poles.
 #pragma omp parallel for
   for (int j = 1; j < ny; ++j) {
@@ -349,7 +351,7 @@ void tend_L(const Geo& g, const St<T>& y, const Work<T>& w, St<T>& t) {
   auto vt = [&](int jv, int k, int i) -> T { return w.v[z.i3(jv, k, i)] * g.sv[jv]; };
 
   // Phi at interior scalar rows: zonal (x+1,x-1) -> (x+2N-1, x-2N+1) with the advecting
-  // u at the midpoints (Table 6 "Ustar" positions), plain meridional and vertical parts.
+  // u at the midpoints (Table VII "Ustar" positions), plain meridional and vertical parts.
 #pragma omp parallel for
   for (int j = 1; j < ny; ++j) {
     const int M = g.M[j], n = g.n[j];
@@ -389,7 +391,7 @@ void tend_L(const Geo& g, const St<T>& y, const Work<T>& w, St<T>& t) {
   }
 
   // U at interior rows: zonal (x+1,x-1) -> (x+2N-1,x-2N+1) on U points with the advecting
-  // u averaged to the integer midpoints (Table 6 "Ustar" (x+1,x) -> (x+N, x-N+1)).
+  // u averaged to the integer midpoints (Table VII "Ustar" (x+1,x) -> (x+N, x-N+1)).
 #pragma omp parallel for
   for (int j = 1; j < ny; ++j) {
     const int M = g.M[j], n = g.n[j];
@@ -1163,7 +1165,7 @@ void orc_constants(void* h, double* out) {
 }
 
 // Leap table: span M (odd) per scalar/U row (ny+1, poles 1) and per V row (ny),
-// and the raw eq. 8 ratios before rounding.
+// and the raw eq. 7 ratios before rounding.
 void orc_leap_table(void* h, int* m_rows, int* m_vrows, double* r_rows, double* r_vrows) {
   const Geo& g = *static_cast<Geo*>(h);
   for (int j = 0; j <= g.ny; ++j) { if (m_rows) m_rows[j] = g.M[j]; if (r_rows) r_rows[j] = g.r[j]; }
@@ -1188,9 +1190,10 @@ void orc_tendency(void* h, int which, const double* U, const double* V, const do
   store(g, t, tU, tV, tF, tps);
 }
 
-// Column diagnostics of a state: D, phi', omega/p (scalar 3D), sigma-dot at half levels, Pi (2D).
+// Column diagnostics of a state: D, phi', omega/p, v.grad(l) (scalar 3D), sigma-dot at half
+// levels, Pi (2D).  Any output pointer may be NULL.
 void orc_column_diag(void* h, const double* U, const double* V, const double* F, const double* ps,
-                     double* D, double* phi, double* wp, double* sd, double* Pi) {
+                     double* D, double* phi, double* wp, double* sd, double* Pi, double* vgl) {
   const Geo& g = *static_cast<Geo*>(h);
   const Sizes z(g);
   St<double> y;
@@ -1201,6 +1204,7 @@ void orc_column_diag(void* h, const double* U, const double* V, const double* F,
   if (phi) std::memcpy(phi, w.phi.data(), sizeof(double) * z.n3);
   if (wp) std::memcpy(wp, w.wp.data(), sizeof(double) * z.n3);
   if (sd) std::memcpy(sd, w.sd.data(), sizeof(double) * z.nh3);
+  if (vgl) std::memcpy(vgl, w.vgl.data(), sizeof(double) * z.n3);
   if (Pi)
     for (int j = 0; j <= g.ny; ++j)
       for (int i = 0; i < g.nx; ++i) Pi[z.i2(j, i)] = w.S[z.ih(j, g.nz, i)];
@@ -1362,47 +1366,6 @@ int orc_substeps(void* h, double dt) {
   const double wmax = 2.0 * 350.0 * std::sqrt(1.0 / (dx45 * dx45) + 1.0 / (dy * dy));
   int m = (int)std::ceil(wmax * dt / (0.8 * std::sqrt(3.0)));
   return m < 1 ? 1 : m;
-}
-
-// Column scan of Alg. 1 (gather the whole column, then sum and prefix sum) and of
-// Alg. 2 (local prefix sums per block of levels, block totals, exclusive scan of the
-// block totals, and the correction added back).  Both return S_h for h = 0..nz and
-// P^2 sigma-dot_h = sigh_h * Pi - S_h for one column of divergences.
-void orc_scan_alg1(void* h, const double* D, double* S, double* psd) {
-  const Geo& g = *static_cast<Geo*>(h);
-  const int nz = g.nz;
-  std::vector<double> col(D, D + nz);  // the "gathered" column
-  double eps = 0;
-  for (int k = 0; k < nz; ++k) eps += col[k] * g.dsig[k];
-  S[0] = 0;
-  for (int k = 0; k < nz; ++k) S[k + 1] = S[k] + col[k] * g.dsig[k];
-  for (int hh = 0; hh <= nz; ++hh) psd[hh] = g.sigh[hh] * eps - S[hh];
-}
-
-void orc_scan_alg2(void* h, const double* D, int nblocks, double* S, double* psd) {
-  const Geo& g = *static_cast<Geo*>(h);
-  const int nz = g.nz;
-  if (nblocks < 1) nblocks = 1;
-  if (nblocks > nz) nblocks = nz;
-  std::vector<int> beg(nblocks + 1);
-  for (int b = 0; b <= nblocks; ++b) beg[b] = (int)((long)b * nz / nblocks);
-  std::vector<double> local(nz + 1, 0.0), tot(nblocks, 0.0), ex(nblocks, 0.0);
-  for (int b = 0; b < nblocks; ++b) {  // local scan and local sum, per block
-    double acc = 0;
-    for (int k = beg[b]; k < beg[b + 1]; ++k) {
-      acc += D[k] * g.dsig[k];
-      local[k + 1] = acc;
-    }
-    tot[b] = acc;
-  }
-  double sum = 0;                      // "Allreduce(sum)"
-  for (int b = 0; b < nblocks; ++b) sum += tot[b];
-  double run = 0;                      // "Exscan"
-  for (int b = 0; b < nblocks; ++b) { ex[b] = run; run += tot[b]; }
-  S[0] = 0;
-  for (int b = 0; b < nblocks; ++b)
-    for (int k = beg[b]; k < beg[b + 1]; ++k) S[k + 1] = local[k + 1] + ex[b];
-  for (int hh = 0; hh <= nz; ++hh) psd[hh] = g.sigh[hh] * sum - S[hh];
 }
 
 }  // extern "C"

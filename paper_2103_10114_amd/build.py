@@ -1,15 +1,18 @@
-"""Build libdycore.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libdycore.so (HIP, gfx950) in-tree with hipcc: one object per source, compiled in
+parallel, then linked."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["api.hip", "fwd.hip", "adj.hip"]
 LIB = os.path.join(HERE, "libdycore.so")
+OBJDIR = os.path.join(HERE, "_build")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=on",
     # packed FP32 VALU forms are avoided on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -19,9 +22,21 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(HERE, "csrc", s) for s in SOURCES]
+    os.makedirs(OBJDIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc] + FLAGS + inc + ["-c", "-o", obj, os.path.join(HERE, "csrc", src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -89,7 +89,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 int hip_status(hipError_t e) { return e == hipSuccess ? DYCORE_OK : DYCORE_EHIP; }
 
 int leap_span(double sin_theta, double dlam, int nx) {
-  // eq. 8 with res = dlam, cos(90 deg - theta) = sin(theta); ceiling, then odd (Sec. III-B), then < nx/2
+  // eq. 7 with res = dlam, cos(90 deg - theta) = sin(theta); ceiling, then odd (Sec. III-B), then < nx/2
   const double r = std::asin(std::cos(M_PI / 4.0) * std::sin(dlam)) / std::asin(sin_theta * std::sin(dlam));
   int m = (int)std::ceil(r - 1e-9);
   if (m < 1) m = 1;
@@ -225,6 +225,16 @@ void release_timer(dycore_s* h) {
   t = dyc::KTimer{};
 }
 
+// Fewest adaptation sub-steps that keep dt / M within the CFL bound of the fastest gravity wave
+// on the 45-degree reference spacing (eq. 6's reference row): ceil(w_max dt / (0.8 sqrt 3)) with
+// w_max = 2 c sqrt(1/dx45^2 + 1/dy^2), c = 350 m/s.
+int cfl_substeps(const dycore_config* c) {
+  const double a = c->a != 0.0 ? c->a : 6.371e6;
+  const double dx45 = a * std::cos(M_PI / 4.0) * (2.0 * M_PI / c->nx), dy = a * (M_PI / c->ny);
+  const double wmax = 2.0 * 350.0 * std::sqrt(1.0 / (dx45 * dx45) + 1.0 / (dy * dy));
+  return std::max(1, (int)std::ceil(wmax * c->dt / (0.8 * std::sqrt(3.0))));
+}
+
 int validate_cfg(const dycore_config* c) {
   if (!c) return DYCORE_EINVAL;
   if (c->nx < 8 || c->nx > 4096 || c->ny < 4 || c->ny > 8192 || c->nz < 1 || c->nz > 128) return DYCORE_EINVAL;
@@ -236,6 +246,9 @@ int validate_cfg(const dycore_config* c) {
   // stays below 4 GiB
   const size_t elem = c->prec == DYCORE_FP64 ? 8 : 4;
   if ((size_t)c->nx * (size_t)(c->ny + 1) * (size_t)(c->nz + 1) * elem >= (size_t(1) << 32)) return DYCORE_EINVAL;
+  // a given sub-step count must keep the adaptation sub-step within the CFL bound of the
+  // gravity-wave speed: w_max dt / M <= 0.8 sqrt 3 (the count chosen when M = 0)
+  if (c->n_adapt_substeps > 0 && cfl_substeps(c) > c->n_adapt_substeps) return DYCORE_EINVAL;
   if (c->sigma_half) {
     if (c->sigma_half[0] != 0.0 || c->sigma_half[c->nz] != 1.0) return DYCORE_EINVAL;
     for (int k = 0; k < c->nz; ++k)
@@ -360,13 +373,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   }
   for (int k = 0; k < nz; ++k) r2d[k] = 1.0 / (2.0 * dsig[k]);
   for (int k = 0; k < nz; ++k) rsig[k] = 1.0 / sig[k];
-  if (cfg->n_adapt_substeps > 0) {
-    h->msub = cfg->n_adapt_substeps;
-  } else {
-    const double dx45 = g.a * std::cos(M_PI / 4.0) * g.dlam, dy = g.a * g.dth;
-    const double wmax = 2.0 * 350.0 * std::sqrt(1.0 / (dx45 * dx45) + 1.0 / (dy * dy));
-    h->msub = std::max(1, (int)std::ceil(wmax * h->dt / (0.8 * std::sqrt(3.0))));
-  }
+  h->msub = cfg->n_adapt_substeps > 0 ? cfg->n_adapt_substeps : cfl_substeps(cfg);
 
   // one device block for the tables
   std::vector<std::pair<const void*, size_t>> parts = {

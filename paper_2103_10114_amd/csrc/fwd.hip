@@ -4,7 +4,7 @@
 // row j and the V row j+1/2.  It walks the column top to bottom, level by
 // level; each thread owns columns i = t, t+B, ... of the row and keeps its
 // column sums in FP64 registers.  Rows that a leap difference reads at
-// distance up to M (eq. 7, Table 6) are staged whole in LDS, so the periodic
+// distance up to M (eq. 6, Table VII) are staged whole in LDS, so the periodic
 // zonal wrap is a modular index into LDS and never a halo exchange.  Pole rows
 // are reduced in FP64 by the first wavefront in a fixed lane order, so results
 // do not depend on the workgroup size.

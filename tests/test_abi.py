@@ -61,3 +61,27 @@ def test_fields_above_4gib_refused_without_gpu(nx, ny, nz, prec, ok):
     h = ctypes.c_void_p()
     assert L.dycore_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
     assert not h.value
+
+
+@pytest.mark.parametrize("msub,ok", [(3, False), (4, True), (0, True)])
+def test_substeps_below_cfl_refused_without_gpu(msub, ok):
+    """A given adaptation sub-step count M with dt / M above the CFL bound is an argument error
+    (the 0.25 deg grid at dt = 120 s needs M >= 4), reported before any device call."""
+    if not os.path.exists(LIB):
+        pytest.skip("libdycore.so not built")
+    from paper_2103_10114_amd import _Config
+    L = ctypes.CDLL(LIB)
+    cfg = _Config()
+    cfg.nx, cfg.ny, cfg.nz, cfg.dt, cfg.prec = 1440, 720, 30, 120.0, 0
+    cfg.n_adapt_substeps = msub
+    h = ctypes.c_void_p()
+    if not ok:
+        assert L.dycore_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+        assert not h.value
+    else:
+        # the config passes validation; without a GPU the create call fails later or succeeds,
+        # but never with EINVAL
+        rc = L.dycore_create(ctypes.byref(cfg), ctypes.byref(h))
+        assert rc != -1
+        if rc == 0:
+            L.dycore_destroy(h)
