@@ -124,8 +124,11 @@ int dycore_stage_adjoint(dycore_t h, int process, double ch,
                          void* abU, void* abV, void* abPhi, void* abps,
                          void* aiU, void* aiV, void* aiPhi, void* aips, void* stream);
 
-/* FP64 global mass (sum_j w_j sum_i p_s + cap areas times the pole values) and
- * the quadratic energy measure; written to host doubles (synchronises the stream). */
+/* FP64 global mass (sum_j w_j sum_i p_s + cap areas times the pole values) and the quadratic
+ * energy measure (p0/2g) sum w dsig (U^2 + V^2 + Phi^2) + (R T0 p0/2g) sum w q^2: the conserved
+ * quantities whose drift Sec. IV-B follows.  Both sums run on the device in a fixed order (row
+ * partials, then one fixed-order reduction); only the two scalars are copied to the host doubles
+ * (synchronises the stream).  EINVAL on NULL arguments. */
 int dycore_diagnostics(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,
                        double* mass_out, double* energy_out, void* stream);
 

@@ -40,7 +40,7 @@ struct dycore_s {
   void* geo = nullptr;          // tables
   void* scratch = nullptr;      // forward scratch: y1, y2
   double* pole = nullptr;       // kPoleSlots x 2 x (nz+1)
-  double* diag = nullptr;       // 3*(ny+1) partials
+  double* diag = nullptr;       // 3*(ny+1) row partials, then the 2 global sums
   unsigned long long* count = nullptr;
   void* adj = nullptr;          // adjoint workspace
   size_t adj_bytes = 0;
@@ -418,14 +418,14 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   h->bytes = gbytes;
   bool ok = hipMalloc(&h->scratch, 2 * h->state_bytes) == hipSuccess;
   ok = ok && hipMalloc((void**)&h->pole, sizeof(double) * kPoleSlots * 2 * (nz + 1)) == hipSuccess;
-  ok = ok && hipMalloc((void**)&h->diag, sizeof(double) * 3 * (ny + 1)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&h->diag, sizeof(double) * (3 * (ny + 1) + 2)) == hipSuccess;
   ok = ok && hipMalloc((void**)&h->count, sizeof(unsigned long long)) == hipSuccess;
   if (ok && !(h->flags & DYCORE_FORWARD_ONLY)) {
     h->adj_bytes = dyc_adjoint_workspace_bytes(h);
     ok = hipMalloc(&h->adj, h->adj_bytes) == hipSuccess;
   }
   if (!ok) { dycore_destroy(h); return DYCORE_ENOMEM; }
-  h->bytes += 2 * h->state_bytes + sizeof(double) * (kPoleSlots * 2 * (nz + 1) + 3 * (ny + 1)) + 8 + h->adj_bytes;
+  h->bytes += 2 * h->state_bytes + sizeof(double) * (kPoleSlots * 2 * (nz + 1) + 3 * (ny + 1) + 2) + 8 + h->adj_bytes;
   *out = h;
   return DYCORE_OK;
 }
@@ -528,22 +528,20 @@ int dycore_diagnostics(dycore_t h, const void* U, const void* V, const void* Phi
                        double* energy_out, void* stream) {
   if (!h || !U || !V || !Phi || !ps || !mass_out || !energy_out) return DYCORE_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  double* sums = h->diag + 3 * (h->ny + 1);
   hipError_t e;
   if (h->prec == DYCORE_FP32)
     e = launch_diag<float>(h->g, (const float*)U, (const float*)V, (const float*)Phi, (const float*)ps, h->diag,
-                           h->ny + 1, s);
+                           sums, s);
   else
     e = launch_diag<double>(h->g, (const double*)U, (const double*)V, (const double*)Phi, (const double*)ps,
-                            h->diag, h->ny + 1, s);
+                            h->diag, sums, s);
   if (e != hipSuccess) return DYCORE_EHIP;
-  std::vector<double> part(3 * (h->ny + 1));
-  if (hipMemcpyAsync(part.data(), h->diag, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return DYCORE_EHIP;
+  double out[2];
+  if (hipMemcpyAsync(out, sums, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess) return DYCORE_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return DYCORE_EHIP;
-  double m = 0, en = 0, es = 0;
-  for (int j = 0; j <= h->ny; ++j) { m += part[3 * j]; en += part[3 * j + 1]; es += part[3 * j + 2]; }
-  *mass_out = m;
-  *energy_out = h->g.p0 / (2.0 * h->g.g) * en + h->g.rd * h->g.t0 * h->g.p0 / (2.0 * h->g.g) * es;
+  *mass_out = out[0];
+  *energy_out = out[1];
   return DYCORE_OK;
 }
 

@@ -94,9 +94,11 @@ hipError_t launch_stage_batch(const StageArgs<T>* d_args, const int2* d_items, i
                               int block, int max_nx, size_t lds, int pipe, hipStream_t s);
 template <typename T>
 hipError_t launch_stage_adjoint(const AdjArgs<T>& a, int block, hipStream_t s);
+// FP64 mass and energy: per-row partials (3 (ny+1) doubles in `partial`), then their fixed-order
+// sum into out[0] (mass) and out[1] (energy), both device memory.
 template <typename T>
 hipError_t launch_diag(const GeoDev& g, const T* U, const T* V, const T* F, const T* ps,
-                       double* partial, int npartial, hipStream_t s);
+                       double* partial, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_nonfinite(const T* x, size_t n, unsigned long long* count, hipStream_t s);
 template <typename T>

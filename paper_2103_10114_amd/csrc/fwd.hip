@@ -1524,6 +1524,25 @@ __global__ void __launch_bounds__(256) k_diag(GeoDev g, const T* U, const T* V, 
   }
 }
 
+// Global sums of the per-row partials of k_diag, in a fixed order (each lane adds its rows in
+// ascending order, then a fixed butterfly; lane 0's result is written), so a result never depends
+// on timing.  out[0] = mass, out[1] = (p0/2g) sum w dsig (U^2 + V^2 + Phi^2) + (R T0 p0/2g) sum w q^2.
+__global__ void __launch_bounds__(64) k_diag_final(GeoDev g, const double* part, int nrows, double* out) {
+  double m = 0, e = 0, es = 0;
+  for (int j = threadIdx.x; j < nrows; j += 64) {
+    m += part[3 * j];
+    e += part[3 * j + 1];
+    es += part[3 * j + 2];
+  }
+  m = wave_sum(m);
+  e = wave_sum(e);
+  es = wave_sum(es);
+  if (threadIdx.x == 0) {
+    out[0] = m;
+    out[1] = g.p0 / (2.0 * g.g) * e + g.rd * g.t0 * g.p0 / (2.0 * g.g) * es;
+  }
+}
+
 template <typename T>
 __global__ void k_nonfinite(const T* __restrict__ x, size_t n, unsigned long long* count) {
   unsigned long long c = 0;
@@ -1640,9 +1659,9 @@ hipError_t launch_pole_prep(const GeoDev& g, const T* F, const T* ps, double* po
 
 template <typename T>
 hipError_t launch_diag(const GeoDev& g, const T* U, const T* V, const T* F, const T* ps, double* partial,
-                       int npartial, hipStream_t s) {
-  (void)npartial;
+                       double* out, hipStream_t s) {
   hipLaunchKernelGGL((k_diag<T>), dim3(g.ny + 1), dim3(256), 0, s, g, U, V, F, ps, partial);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, g, (const double*)partial, g.ny + 1, out);
   return hipGetLastError();
 }
 
@@ -1669,7 +1688,7 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s) {
   template hipError_t launch_stage_batch<T>(const StageArgs<T>*, const int2*, int, int, int, int, size_t, int,  \
                                             hipStream_t);                                                    \
   template hipError_t launch_pole_prep<T>(const GeoDev&, const T*, const T*, double*, hipStream_t);          \
-  template hipError_t launch_diag<T>(const GeoDev&, const T*, const T*, const T*, const T*, double*, int,    \
+  template hipError_t launch_diag<T>(const GeoDev&, const T*, const T*, const T*, const T*, double*, double*, \
                                      hipStream_t);                                                           \
   template hipError_t launch_nonfinite<T>(const T*, size_t, unsigned long long*, hipStream_t);               \
   template hipError_t launch_axpy_fill<T>(T*, const T*, size_t, hipStream_t);                                \

@@ -93,6 +93,29 @@ def test_dot_product_c3_fp64():
     assert rel <= 1e-10
 
 
+def test_dot_product_c3_fp32():
+    """C3 in FP32 mode (FP32 storage, FP64 sums): the dot-test residual of the GPU adjoint against the
+    oracle's complex-step tangent-linear about the same FP32-rounded state, reported and bounded."""
+    cfg = synth.CONFIGS["c3"]
+    st = synth.make_state(cfg)
+    st32 = {k: st[k].astype(np.float32).astype(np.float64) for k in ("U", "V", "Phi", "ps")}
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+    x = synth.random_like(st, 1031)
+    y = synth.random_like(st, 1032)
+    y32 = {k: y[k].astype(np.float32).astype(np.float64) for k in y}
+    print("oracle complex-step TL at C3 (FP32-rounded state) ...", flush=True)
+    jx = o.tl_step(st32, x, cfg.dt)
+    core = _core(cfg, st, "fp32")
+    a = core.to_device(y32)
+    core.step_adjoint(core.to_device(st32), a)
+    jty = _host(a)
+    lhs = oracle.dot(jx, y32)
+    rhs = oracle.dot(x, jty)
+    rel = abs(lhs - rhs) / abs(lhs)
+    print(f"C3 dot test fp32: <Jx,y>={lhs:.10e} <x,JTy>={rhs:.10e} rel={rel:.3e}", flush=True)
+    assert rel <= 1e-4
+
+
 @pytest.mark.parametrize("eps_rel,tol", [(1e-6, 1e-4), (1e-4, 1e-6)])
 def test_fd_c3_fp64(eps_rel, tol):
     """C3: central differences of the GPU FP64 forward step at 64 seeded grid points against the GPU

@@ -1,0 +1,156 @@
+"""GPU parity at the 0.25-degree workload (1440 x 720 x 30, dt 120 s, M = 4), in the launch
+configuration the benchmark times: the default workgroup of 768 threads with two columns per thread,
+the pipelined FP32 stage kernels and the row-fused FP32 adaptation-stage adjoint at the full leap
+spans (163 on U rows, 325 on V rows).  Every case starts from the FP32-rounded state, so FP32 and FP64
+modes are compared with one set of FP64 oracle results.
+
+FP32 bounds (see the tolerance notes of the design): the FP32 rounding of the stored fields and of the
+leap-difference operands (relative 6e-8) divided by the relative size of a difference (down to ~1e-4
+of the values) gives increment errors up to ~1e-3 of the increment scale; the adjoint carries the same
+factors transposed.  FP64 mode: 1e-12 of the field's largest value."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_10114_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+KEYS = ("U", "V", "Phi", "ps")
+_CACHE = {}
+
+
+def _case():
+    """The C4 state (FP32-rounded), its oracle and the stage coefficients, built once per module."""
+    if not _CACHE:
+        cfg = synth.CONFIGS["c4"]
+        print("C4 state ...", flush=True)
+        st = synth.make_state(cfg)
+        st32 = {k: st[k].astype(np.float32).astype(np.float64) for k in KEYS}
+        o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
+        m = o.substeps(cfg.dt)
+        assert m == 4
+        ao = synth.random_like(st, 1041)
+        ao32 = {k: ao[k].astype(np.float32).astype(np.float64) for k in KEYS}
+        _CACHE.update(cfg=cfg, st=st, st32=st32, o=o, ch={"A": cfg.dt / m / 3.0, "L": cfg.dt / 2.0},
+                      ao32=ao32, fwd={}, adj={}, cores={})
+    return _CACHE
+
+
+def _want_fwd(process):
+    c = _case()
+    if process not in c["fwd"]:
+        print(f"oracle C4 stage {process} ...", flush=True)
+        c["fwd"][process] = c["o"].stage(c["st32"], c["st32"], c["ch"][process], process)
+    return c["fwd"][process]
+
+
+def _want_adj(process):
+    c = _case()
+    if process not in c["adj"]:
+        print(f"oracle C4 stage adjoint {process} ...", flush=True)
+        c["adj"][process] = c["o"].adj_stage(c["st32"], c["ao32"], c["ch"][process], process)
+    return c["adj"][process]
+
+
+def _core(prec):
+    c = _case()
+    if prec not in c["cores"]:
+        from paper_2103_10114_amd import Dycore
+        cfg = c["cfg"]
+        c["cores"].clear()          # one handle at a time (the adjoint workspace is large)
+        c["cores"][prec] = Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec=prec, phis=c["st"]["phis"])
+    return c["cores"][prec]
+
+
+def _host(d):
+    return {k: v.detach().cpu().numpy().astype(np.float64) for k, v in d.items()}
+
+
+def test_c4_launch_configuration():
+    """The handle the benchmark uses: 768 threads per row, so 2 columns per thread at 1440 columns."""
+    core = _core("fp32")
+    assert core.block == 768 and core.substeps == 4
+    m, mv = core.leap_table()
+    assert m.max() == 163 and mv.max() == 325
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_c4_stage(prec, process):
+    """One stage y + ch T(y) at C4 against the oracle: FP64 within 1e-12 of the field scale; FP32
+    increments elementwise within 2e-3 of the increment scale."""
+    c = _case()
+    want = _want_fwd(process)
+    core = _core(prec)
+    print(f"C4 stage {process} {prec}", flush=True)
+    d = core.to_device(c["st32"])
+    out = {k: torch.empty_like(v) for k, v in d.items()}
+    got = _host(core.stage(process, c["ch"][process], d, d, out))
+    for k in KEYS:
+        inc = want[k] - c["st32"][k]
+        if prec == "fp64":
+            err = np.abs(got[k] - want[k]).max() / np.abs(want[k]).max()
+            print(f"  {k}: max err / field scale {err:.3e}", flush=True)
+            assert err < 1e-12, (k, err)
+        else:
+            scale = max(np.abs(inc).max(), np.abs(want[k]).max() * 1e-7)
+            err = np.abs(got[k] - want[k]).max() / scale
+            l2 = np.linalg.norm(got[k] - want[k]) / max(np.linalg.norm(inc), 1e-300)
+            print(f"  {k}: max err / increment scale {err:.3e}, rel-L2 of the increment {l2:.3e}", flush=True)
+            assert err < 2e-3, (k, err)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_c4_stage_adjoint(prec, process):
+    """Adjoint of one stage at C4 (base and input parts, separate zeroed accumulators) against the
+    oracle's: FP64 within 1e-12; FP32 elementwise within 2e-3 of each part's largest value."""
+    c = _case()
+    wb, wi = _want_adj(process)
+    core = _core(prec)
+    print(f"C4 stage adjoint {process} {prec}", flush=True)
+    d = core.to_device(c["st32"])
+    a = core.to_device(c["ao32"])
+    ab = {k: torch.zeros_like(v) for k, v in d.items()}
+    ai = {k: torch.zeros_like(v) for k, v in d.items()}
+    core.stage_adjoint(process, c["ch"][process], d, a, ab, ai)
+    gb, gi = _host(ab), _host(ai)
+    tol = 1e-12 if prec == "fp64" else 2e-3
+    for k in KEYS:
+        for part, g, w in (("base", gb, wb), ("in", gi, wi)):
+            err = np.abs(g[k] - w[k]).max() / np.abs(w[k]).max()
+            l2 = np.linalg.norm(g[k] - w[k]) / np.linalg.norm(w[k])
+            print(f"  {part} {k}: max err / scale {err:.3e}, rel-L2 {l2:.3e}", flush=True)
+            assert err < tol, (part, k, err)
+
+
+def test_c4_recorded_step_fp32():
+    """The benchmark's forward (dycore_step_record: 12 adaptation and 3 advection stages) at C4 in FP32
+    against one oracle step from the same FP32-rounded state: per-field rel-L2 and max error, and the
+    recorded adjoint of that step is finite and equals the recomputing adjoint bit for bit."""
+    c = _case()
+    cfg = c["cfg"]
+    core = _core("fp32")
+    print("oracle C4 step ...", flush=True)
+    want = c["o"].step(c["st32"], 1, cfg.dt)
+    d = core.to_device(c["st32"])
+    core.step_record(d)
+    got = _host(d)
+    for k in KEYS:
+        inc = want[k] - c["st32"][k]
+        l2 = np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k])
+        mx = np.abs(got[k] - want[k]).max() / np.abs(want[k]).max()
+        ei = np.abs(got[k] - want[k]).max() / np.abs(inc).max()
+        print(f"  C4 step fp32 {k}: rel-L2 {l2:.3e} max {mx:.3e} max/increment {ei:.3e}", flush=True)
+        assert ei < 2e-3, (k, ei)
+    l1 = core.to_device(c["ao32"])
+    l2_ = core.to_device(c["ao32"])
+    core.step_adjoint_recorded(l1)
+    core.step_adjoint(core.to_device(c["st32"]), l2_)
+    torch.cuda.synchronize()
+    for k in KEYS:
+        assert torch.isfinite(l1[k]).all(), k
+        assert torch.equal(l1[k], l2_[k]), k
