@@ -95,7 +95,8 @@ def test_dot_product_c3_fp64():
 
 def test_dot_product_c3_fp32():
     """C3 in FP32 mode (FP32 storage, FP64 sums): the dot-test residual of the GPU adjoint against the
-    oracle's complex-step tangent-linear about the same FP32-rounded state, reported and bounded."""
+    oracle's complex-step tangent-linear about the same FP32-rounded state, reported and bounded at 3e-6
+    (measured 5.9e-7; FP64 mode: 8e-15)."""
     cfg = synth.CONFIGS["c3"]
     st = synth.make_state(cfg)
     st32 = {k: st[k].astype(np.float32).astype(np.float64) for k in ("U", "V", "Phi", "ps")}
@@ -113,7 +114,7 @@ def test_dot_product_c3_fp32():
     rhs = oracle.dot(x, jty)
     rel = abs(lhs - rhs) / abs(lhs)
     print(f"C3 dot test fp32: <Jx,y>={lhs:.10e} <x,JTy>={rhs:.10e} rel={rel:.3e}", flush=True)
-    assert rel <= 1e-4
+    assert rel <= 3e-6
 
 
 @pytest.mark.parametrize("eps_rel,tol", [(1e-6, 1e-4), (1e-4, 1e-6)])
@@ -173,7 +174,7 @@ def test_adjoint_fp32_vs_fp64():
     for k in ("U", "V", "Phi", "ps"):
         l2 = np.linalg.norm(g32[k] - g64[k]) / np.linalg.norm(g64[k])
         print(f"adjoint fp32 vs fp64 {k}: rel-L2 {l2:.3e}", flush=True)
-        assert l2 < 1e-3
+        assert l2 < 5e-7   # measured at most 1.1e-7
 
 
 def test_recorded_step_and_adjoint():

@@ -4,10 +4,12 @@ the pipelined FP32 stage kernels and the row-fused FP32 adaptation-stage adjoint
 spans (163 on U rows, 325 on V rows).  Every case starts from the FP32-rounded state, so FP32 and FP64
 modes are compared with one set of FP64 oracle results.
 
-FP32 bounds (see the tolerance notes of the design): the FP32 rounding of the stored fields and of the
-leap-difference operands (relative 6e-8) divided by the relative size of a difference (down to ~1e-4
-of the values) gives increment errors up to ~1e-3 of the increment scale; the adjoint carries the same
-factors transposed.  FP64 mode: 1e-12 of the field's largest value."""
+FP32 bounds: 5x the errors measured on MI355X (stated per process and field; the measured values are
+in the docstrings).  Their size follows from the FP32 rounding of the stored fields and of the leap
+difference operands (relative 6e-8) divided by the relative size of a difference: the p_s and Phi
+increments of an adaptation stage are ~1e-4 of the values, so their errors reach a few 1e-4 of the
+increment; winds and the advection stay near 1e-5.  FP64 mode: 1e-12 of the field's largest value
+(measured below 1e-15)."""
 import numpy as np
 import pytest
 
@@ -77,11 +79,17 @@ def test_c4_launch_configuration():
     assert m.max() == 163 and mv.max() == 325
 
 
+# FP32 stage bounds, max error over the increment scale; measured A: U 2.5e-6, V 2.3e-6, Phi 1.8e-4,
+# p_s 5.2e-4; L: U 4.6e-5, V 6.2e-6, Phi 1.1e-6 (p_s has no advection increment)
+STAGE32 = {"A": {"U": 1.3e-5, "V": 1.2e-5, "Phi": 1e-3, "ps": 2.6e-3},
+           "L": {"U": 2.3e-4, "V": 3.1e-5, "Phi": 5.4e-6, "ps": 0.0}}
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("process", ["A", "L"])
 def test_c4_stage(prec, process):
     """One stage y + ch T(y) at C4 against the oracle: FP64 within 1e-12 of the field scale; FP32
-    increments elementwise within 2e-3 of the increment scale."""
+    increments elementwise within the bounds of STAGE32 (of the increment scale)."""
     c = _case()
     want = _want_fwd(process)
     core = _core(prec)
@@ -100,14 +108,15 @@ def test_c4_stage(prec, process):
             err = np.abs(got[k] - want[k]).max() / scale
             l2 = np.linalg.norm(got[k] - want[k]) / max(np.linalg.norm(inc), 1e-300)
             print(f"  {k}: max err / increment scale {err:.3e}, rel-L2 of the increment {l2:.3e}", flush=True)
-            assert err < 2e-3, (k, err)
+            assert err <= STAGE32[process][k], (k, err)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("process", ["A", "L"])
 def test_c4_stage_adjoint(prec, process):
     """Adjoint of one stage at C4 (base and input parts, separate zeroed accumulators) against the
-    oracle's: FP64 within 1e-12; FP32 elementwise within 2e-3 of each part's largest value."""
+    oracle's: FP64 within 1e-12; FP32 elementwise within 1e-6 of each part's largest value (measured
+    at most 2.2e-7)."""
     c = _case()
     wb, wi = _want_adj(process)
     core = _core(prec)
@@ -118,7 +127,7 @@ def test_c4_stage_adjoint(prec, process):
     ai = {k: torch.zeros_like(v) for k, v in d.items()}
     core.stage_adjoint(process, c["ch"][process], d, a, ab, ai)
     gb, gi = _host(ab), _host(ai)
-    tol = 1e-12 if prec == "fp64" else 2e-3
+    tol = 1e-12 if prec == "fp64" else 1e-6
     for k in KEYS:
         for part, g, w in (("base", gb, wb), ("in", gi, wi)):
             err = np.abs(g[k] - w[k]).max() / np.abs(w[k]).max()
@@ -129,8 +138,9 @@ def test_c4_stage_adjoint(prec, process):
 
 def test_c4_recorded_step_fp32():
     """The benchmark's forward (dycore_step_record: 12 adaptation and 3 advection stages) at C4 in FP32
-    against one oracle step from the same FP32-rounded state: per-field rel-L2 and max error, and the
-    recorded adjoint of that step is finite and equals the recomputing adjoint bit for bit."""
+    against one oracle step from the same FP32-rounded state: per-field rel-L2 and max error, the max
+    within 4.5e-5 of the step's increment scale (measured at most 8.8e-6), and the recorded adjoint of
+    that step is finite and equals the recomputing adjoint bit for bit."""
     c = _case()
     cfg = c["cfg"]
     core = _core("fp32")
@@ -145,7 +155,7 @@ def test_c4_recorded_step_fp32():
         mx = np.abs(got[k] - want[k]).max() / np.abs(want[k]).max()
         ei = np.abs(got[k] - want[k]).max() / np.abs(inc).max()
         print(f"  C4 step fp32 {k}: rel-L2 {l2:.3e} max {mx:.3e} max/increment {ei:.3e}", flush=True)
-        assert ei < 2e-3, (k, ei)
+        assert ei < 4.5e-5, (k, ei)
     l1 = core.to_device(c["ao32"])
     l2_ = core.to_device(c["ao32"])
     core.step_adjoint_recorded(l1)
