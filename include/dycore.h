@@ -132,6 +132,16 @@ int dycore_stage_adjoint(dycore_t h, int process, double ch,
 int dycore_diagnostics(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,
                        double* mass_out, double* energy_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid hipMalloc): dycore_diagnostics with its row partials in a static device array of the
+ * library (3 (ny+1) doubles, at most 4097 rows, one copy per GPU held until the process ends) and
+ * the results written to device memory, out_dev[0] = mass and out_dev[1] = energy, without copying
+ * to the host or synchronising.  Allocates nothing.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race.  Results equal
+ * dycore_diagnostics bit for bit.  EINVAL: NULL arguments or ny + 1 > 4097. */
+int dycore_diagnostics_noalloc(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,
+                               double* out_dev, void* stream);
+
 /* Count of non-finite stored entries in the four fields (synchronises the
  * stream).  Returns DYCORE_ENONFINITE if the count is positive. */
 int dycore_check_finite(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,

@@ -54,6 +54,7 @@ def lib():
         L.dycore_stage_adjoint.argtypes = [vp, ctypes.c_int, ctypes.c_double] + [vp] * 16 + [vp]
         L.dycore_diagnostics.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double), vp]
+        L.dycore_diagnostics_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.dycore_check_finite.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_longlong), vp]
         L.dycore_leap_table.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.dycore_substeps.argtypes = [vp]
@@ -220,6 +221,12 @@ class Dycore:
         e = ctypes.c_double()
         _check(lib().dycore_diagnostics(self.h, *self._p(st), ctypes.byref(m), ctypes.byref(e), _stream()))
         return m.value, e.value
+
+    def diagnostics_noalloc(self, st, out):
+        """Mass and energy into out (a float64 GPU tensor of 2 entries), with no allocation and no
+        host synchronisation."""
+        _check(lib().dycore_diagnostics_noalloc(self.h, *self._p(st), _ptr(out), _stream()))
+        return out
 
     def count_nonfinite(self, st):
         c = ctypes.c_longlong()

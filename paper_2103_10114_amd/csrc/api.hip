@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -14,6 +15,32 @@ using namespace dyc;
 namespace {
 
 constexpr int kPoleSlots = 8;
+
+// Row partials of dycore_diagnostics_noalloc: a file-scope device array, one copy per GPU, held
+// until the process ends.  Host code never passes its name to a kernel (on the host it stands for
+// no device address); it uses the address hipGetSymbolAddress returns for each device.
+constexpr int kNoallocMaxRows = 4097;                  // ny + 1 <= 4097 (0.044-degree rows)
+constexpr int kNoallocDoubles = 3 * kNoallocMaxRows + 2;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+namespace {
+
+// Resolves, once per device and with that device current, the address of `scratch` on it.
+int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return DYCORE_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return DYCORE_OK;
+  double* ptr = nullptr;
+  if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DYCORE_EHIP;
+  g_scratch_dev[device] = ptr;
+  return DYCORE_OK;
+}
 
 struct DeviceBuf {
   void* p = nullptr;
@@ -310,6 +337,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   const size_t lds = std::max(stage_lds_bytes(0, h->nx, (int)h->elem), stage_lds_bytes(1, h->nx, (int)h->elem));
   if (lds > 160 * 1024) { delete h; return DYCORE_EUNSUPPORTED; }
   (void)hipGetDevice(&h->device);
+  if ((st = resolve_scratch(h->device)) != DYCORE_OK) { delete h; return st; }
 
   const int nx = h->nx, ny = h->ny, nz = h->nz;
   GeoDev& g = h->g;
@@ -543,6 +571,23 @@ int dycore_diagnostics(dycore_t h, const void* U, const void* V, const void* Phi
   *mass_out = out[0];
   *energy_out = out[1];
   return DYCORE_OK;
+}
+
+int dycore_diagnostics_noalloc(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,
+                               double* out_dev, void* stream) {
+  if (!h || !U || !V || !Phi || !ps || !out_dev) return DYCORE_EINVAL;
+  if (h->ny + 1 > kNoallocMaxRows) return DYCORE_EINVAL;
+  double* part = (h->device >= 0 && h->device < kMaxDevices) ? g_scratch_dev[h->device] : nullptr;
+  if (!part) return DYCORE_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (h->prec == DYCORE_FP32)
+    e = launch_diag<float>(h->g, (const float*)U, (const float*)V, (const float*)Phi, (const float*)ps, part,
+                           out_dev, s);
+  else
+    e = launch_diag<double>(h->g, (const double*)U, (const double*)V, (const double*)Phi, (const double*)ps,
+                            part, out_dev, s);
+  return hip_status(e);
 }
 
 int dycore_check_finite(dycore_t h, const void* U, const void* V, const void* Phi, const void* ps,
