@@ -329,10 +329,10 @@ def main():
             ams = tot / n
             aalg = 4.0 * sb
             aach = aalg / (ams * 1e-3) / 1e9
-            aname = f"k_aar<float,{ni}>"
+            aname = "k_aat<float>"
             out["roofline"] = {"bound": "hbm", "achieved": aach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": aach / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kh, aname),
-                               "kernel": aname + " (row-fused adaptation-stage adjoint)",
+                               "kernel": aname + " (tiled row-fused adaptation-stage adjoint)",
                                "avg_launch_ms": ams, "launches_timed": n, "alg_bytes_per_launch": aalg,
                                "kernel_hash": kh, "forward_stage": fwd}
         else:

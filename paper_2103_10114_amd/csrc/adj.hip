@@ -74,6 +74,9 @@ struct Ctx {
   int blk = 0;                     // workgroup size of the row-fused kernel (the handle's)
   int parts = 7;                   // first adaptation transposes: 1 scalar point (+ suffix), 2 U, 4 V
   KTimer* timer = nullptr;         // host side: times the row-fused kernel's launches when armed
+  const AatItem* aat = nullptr;    // work items of the tiled row-fused adaptation adjoint (NULL: per point)
+  int aat_n = 0;                   // item count
+  int aat_blk = 0;                 // threads per tile workgroup
   int fwd_all = 1;                 // forward recompute of R T', phi', omega/p too (0: D, S, sigma-dot only)
   int ai_zero = 0;                 // the input adjoint starts at zero and, in its interior rows, only the
                                    // row-fused kernel adds to it: those rows are stored without a read
@@ -1061,158 +1064,126 @@ __global__ void k_t4(Ctx<T> c) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// Adaptation-stage adjoint, row-fused (interior rows 1..ny-1).  One workgroup per scalar row j
-// (and its U row and V row j+1/2) walks the levels top to bottom, like the forward stage kernel:
-// the forward column diagnostics of rows j and j+1 (R T', phi', D, S, omega/p) are recomputed
-// on the way, and the first transposes of every output that reads row j's inputs (U row j, V
-// rows j-1/2 and j+1/2, scalar rows j-1..j+1) are formed per level for the owned columns and
-// staged in LDS, so that the gathers at leap and +-1 neighbours are LDS reads.  Suffix sums
-// (the adjoint of S) run top-down from column totals taken in a first pass.  Two barriers per
-// level.  The pole rows' share goes through the per-point kernels (restricted to the pole rows);
-// this kernel writes the few row-1 and row-(ny-1) intermediates those read.
+// Adaptation-stage adjoint, row-fused and tiled (interior rows 1..ny-1).  One workgroup per work
+// item (row j, a zonal tile of w owned columns and a halo of hl = n_j + 1 columns on each side; one
+// column per thread) walks the levels top to bottom, as the forward stage kernel does: the forward
+// column diagnostics of rows j and j+1 (R T', phi', D, S, omega/p) are recomputed on the way, and
+// the first transposes of every output that reads row j's inputs (U row j, V rows j-1/2 and j+1/2,
+// scalar rows j-1..j+1) are formed per level for every slot of the tile and staged in LDS, so that
+// the owned columns' gathers at the leap offsets (+-n_j) and at +-1 are LDS reads of slots that the
+// halo covers: no modular index in LDS, and the tile's LDS and registers leave room for two
+// workgroups per CU.  The level rows are double-buffered (one barrier per level).  Suffix sums (the
+// adjoint of S, the hydrostatic totals) run top-down from column totals taken in a first pass.  The
+// pole rows' share goes through the per-point kernels (restricted to the pole rows); this kernel
+// writes the few row-1 and row-(ny-1) intermediates those read.
 // ------------------------------------------------------------------------------------------------
-constexpr int kAar2D = 15, kAarLev = 13;
-__host__ __device__ constexpr size_t aar_lds(int nx, int elem) {
-  return ((size_t)(kAar2D + kAarLev) * nx * elem + 15) & ~size_t(15);
-}
-__host__ __device__ constexpr bool aar_ok(int nx, int elem) { return aar_lds(nx, elem) <= 160 * 1024; }
-constexpr int aar_block(int ni) { return ni <= 2 ? 768 : 512; }
+constexpr int kAatLev = 13;   // per-level LDS rows (odd: consecutive slots stride an odd word count)
+__host__ __device__ constexpr size_t aat_lds(int block, int elem) { return (size_t)2 * kAatLev * block * elem; }
 
-template <typename T, int NI>
-__global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
+template <typename T>
+__global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat(Ctx<T> c) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const AatItem it = c.aat[blockIdx.x];
+  if (it.j < 0) return;
   const GeoDev& g = c.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int j = 1 + xcd_row(blockIdx.x, ny - 1);
-  const int B = blockDim.x;
-  int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
-  // LDS cells column-major in two blocks, of 15 and 13 rows: (row r, column i) at i*15 + r and
-  // i*13 + r, so that one address per column index serves every row of a block (the row is the
-  // instruction's immediate offset) and consecutive lanes stride an odd number of words (no bank
-  // conflicts)
-  T* s2 = reinterpret_cast<T*>(smem);   // 2D rows from the forward recompute
-  T* sl = s2 + kAar2D * nx;             // per-level rows
-  // 2D rows: P of rows j-1, j, j+1; the meridional l and q differences; the leaped d+l, d+q of
-  // row j; reciprocals of P (rows j, j+1), of its U-point averages (rows j-1, j, j+1) and of its
-  // V-point averages (V rows j+1/2, j-1/2)
-  enum { RPm, RP0, RP1, RdLm, RdL0, RdQ0, RDL, RDQ, RrP0, RrP1, RrUm, RrU0, RrU1, RrPV0, RrPVm };
-  // per-level rows
+  const int j = it.j, hl = it.hl, w = it.w;
+  const int NS = w + 2 * hl;                 // slots of the tile, halo included
+  const int sl = threadIdx.x;                // this thread's slot
+  const bool act = sl < NS;                  // slots past NS only meet the barriers
+  const bool own = sl >= hl && sl < hl + w;  // owned column: phase 2 and every global write
+  int col = (it.i0 - hl + sl) % nx;
+  if (col < 0) col += nx;
+  const int colm = col == 0 ? nx - 1 : col - 1, colp = col == nx - 1 ? 0 : col + 1;
+  const unsigned ui = (unsigned)col, uim = (unsigned)colm, uip = (unsigned)colp;
+  // LDS: two buffers of kAatLev rows, slot-major ((slot, row) at slot * kAatLev + row)
+  T* lb0 = reinterpret_cast<T*>(smem);
+  T* lb1 = lb0 + kAatLev * blockDim.x;
   enum { LHH, LAV, LFVm, LFV0, LUVm, LUV0, LFU0, LFU1, LAD, LPH, LRT, LMU, Lu };
-  auto S2 = [&](int row, int col) -> T& { return s2[col * kAar2D + row]; };
-  auto SL = [&](int row, int col) -> T& { return sl[col * kAarLev + row]; };
 
   const bool nPole = (j - 1 == 0);        // scalar row j-1 is the north pole
   const bool sPole = (j + 1 == ny);       // scalar row j+1 is the south pole
   const T b = (T)g.b, kap = (T)g.kappa;
-  const C ch = c.ch, RT0 = g.RT0;
+  const C ch = c.ch;
   const int M = g.M[j], n = (M + 1) / 2;
   const T dxT = (T)((double)M * g.a * g.s[j] * g.dlam);
-  const C dxC = (C)dxT;
   const T dySj = (T)(g.a * g.s[j] * g.dth);
-  const T dySm = (T)(g.a * g.s[j - 1] * g.dth);       // unused when j-1 is the pole
   const C dyS1C = sPole ? 1.0 : (C)(T)(g.a * g.s[j + 1] * g.dth);
   const T dyA = (T)(g.a * g.dth);
-  const C aDy = g.a * g.dth;
   const T svj = (T)g.sv[j], svm = (T)g.sv[j - 1];
   const T cotj = (T)(g.cot[j] / g.a), fj = (T)g.f[j];
-  const C cotjC = g.cot[j] / g.a;
   const T cot1 = sPole ? T(0) : (T)(g.cot[j + 1] / g.a), f1 = sPole ? T(0) : (T)g.f[j + 1];
+  const T cvm = (T)(g.cotv[j - 1] / g.a), cv0 = (T)(g.cotv[j] / g.a);
+  const T fvm = (T)g.fv[j - 1], fv0 = (T)g.fv[j];
   const C capD = g.a * g.dlam / g.acap;
   const double* sDs = c.s.psum + PS_AD * 2 * (nz + 1);
   const double* sVG = c.s.psum + PS_AVGL * 2 * (nz + 1);
-  // reciprocals of the row constants
   const T rdxT = T(1) / dxT, rdySjT = T(1) / dySj, rdyAT = T(1) / dyA;
-  const C rdxC = 1.0 / dxC, rdySjC = 1.0 / (C)dySj, rdyS1C = 1.0 / dyS1C, rdyAC = 1.0 / (C)dyA, raDy = 1.0 / aDy;
   const C rnx = 1.0 / (C)nx;
   // per-point transposes run in the field precision (the sums below stay FP64)
   using A = T;
-  const A chA = (A)ch, RT0A = (A)RT0, rdxA = (A)rdxC, rdySjA = (A)rdySjC, rdyS1A = (A)rdyS1C;
-  const A rdyAA = (A)rdyAC, raDyA = (A)raDy, cotjA = (A)cotjC;
-  const size_t row3 = (size_t)nz * nx;
-  (void)dySm;
+  const A chA = (A)ch, RT0A = (A)g.RT0, rdxA = (A)(1.0 / (C)dxT), rdySjA = (A)(1.0 / (C)dySj);
+  const A rdyS1A = (A)(1.0 / dyS1C), rdyAA = (A)(1.0 / (C)dyA), raDyA = (A)(1.0 / (g.a * g.dth));
+  const A cotjA = (A)(g.cot[j] / g.a), cvmA = (A)(g.cotv[j - 1] / g.a), cv0A = (A)(g.cotv[j] / g.a);
+  const unsigned row3 = (unsigned)(nz * nx);
+  const unsigned oJ = (unsigned)j * row3, oJm = oJ - row3, oJ1 = oJ + row3;
 
-  // ---- 2D rows from the forward recompute
-  for (int cc = 0; cc < NI; ++cc) {
-    const int i = t + cc * B;
-    if (i < nx) {
-      const T Pm = c.s.P[(size_t)(j - 1) * nx + i], P0 = c.s.P[(size_t)j * nx + i];
-      const T P1 = c.s.P[(size_t)(j + 1) * nx + i];
-      S2(RPm, i) = Pm;
-      S2(RP0, i) = P0;
-      S2(RP1, i) = P1;
-      const T Lm = c.s.L[(size_t)(j - 1) * nx + i], L0 = c.s.L[(size_t)j * nx + i];
-      const T L1 = c.s.L[(size_t)(j + 1) * nx + i];
-      S2(RdLm, i) = L0 - Lm;
-      S2(RdL0, i) = L1 - L0;
-      S2(RdQ0, i) = c.s.Q[(size_t)(j + 1) * nx + i] - c.s.Q[(size_t)j * nx + i];
-      S2(RDL, i) = c.s.DL[(size_t)j * nx + i];
-      S2(RDQ, i) = c.s.DQ[(size_t)j * nx + i];
-      S2(RrP0, i) = T(1) / P0;
-      S2(RrP1, i) = T(1) / P1;
-    }
+  // ---- 2D values of this slot's column (and of its western neighbour) from the forward recompute
+  auto p2 = [&](int jj, unsigned ii) { return ldg(c.s.P, (unsigned)jj * (unsigned)nx + ii); };
+  T Pm = 0, P0 = 0, P1 = 0, rPm = 0, rP0 = 0, rP1 = 0, PU0 = 0, rU0 = 0, rU1 = 0, rUm = 0, rU0w = 0, rU1w = 0;
+  T rUmw = 0, rPV0 = 0, rPVm = 0, DLc = 0, DLw = 0, DQc = 0, dL0 = 0, dLm = 0, dQ0 = 0;
+  C aPij = 0, aPi1 = 0;
+  if (act) {
+    Pm = p2(j - 1, ui); P0 = p2(j, ui); P1 = p2(j + 1, ui);
+    const T Pmp = p2(j - 1, uip), P0p = p2(j, uip), P1p = p2(j + 1, uip);
+    const T Pmw = p2(j - 1, uim), P0w = p2(j, uim), P1w = p2(j + 1, uim);
+    rPm = T(1) / Pm; rP0 = T(1) / P0; rP1 = T(1) / P1;
+    PU0 = T(0.5) * (P0 + P0p);
+    rU0 = T(1) / PU0;
+    rU1 = T(1) / (T(0.5) * (P1 + P1p));
+    rUm = T(1) / (T(0.5) * (Pm + Pmp));
+    rU0w = T(1) / (T(0.5) * (P0w + P0));
+    rU1w = T(1) / (T(0.5) * (P1w + P1));
+    rUmw = T(1) / (T(0.5) * (Pmw + Pm));
+    rPV0 = T(1) / (T(0.5) * (P0 + P1));
+    rPVm = T(1) / (T(0.5) * (Pm + P0));
+    const unsigned r0 = (unsigned)j * (unsigned)nx;
+    const T Lm = ldg(c.s.L, r0 - nx + ui), L0 = ldg(c.s.L, r0 + ui), L1 = ldg(c.s.L, r0 + nx + ui);
+    dLm = L0 - Lm;
+    dL0 = L1 - L0;
+    dQ0 = ldg(c.s.Q, r0 + nx + ui) - ldg(c.s.Q, r0 + ui);
+    DLc = ldg(c.s.DL, r0 + ui);
+    DLw = ldg(c.s.DL, r0 + uim);
+    DQc = ldg(c.s.DQ, r0 + ui);
+    aPij = -g.p0 * ch * (C)ldg(c.aoP, r0 + ui);
+    if (!sPole) aPi1 = -g.p0 * ch * (C)ldg(c.aoP, r0 + nx + ui);
   }
-  __syncthreads();
-  auto PUr = [&](int rP, int i) -> T { return T(0.5) * (S2(rP, i) + S2(rP, wrp_up(i + 1, nx))); };
-  for (int cc = 0; cc < NI; ++cc) {
-    const int i = t + cc * B;
-    if (i < nx) {
-      S2(RrUm, i) = T(1) / PUr(RPm, i);
-      S2(RrU0, i) = T(1) / PUr(RP0, i);
-      S2(RrU1, i) = T(1) / PUr(RP1, i);
-      S2(RrPV0, i) = T(1) / (T(0.5) * (S2(RP0, i) + S2(RP1, i)));
-      S2(RrPVm, i) = T(1) / (T(0.5) * (S2(RPm, i) + S2(RP0, i)));
-    }
-  }
-  __syncthreads();
 
   // ---- pass A: column totals (hydrostatic H of rows j and j+1; sum of the adjoint of S)
-  // HRj, HR1: hydrostatic totals, then (running) the part below the level; Asj, As1: the adjoint
-  // of S summed over the column, then (running) over the levels below
-  C HRj[NI], HR1[NI], Asj[NI], As1[NI];
+  C HRj = 0, HR1 = 0, Asj = 0, As1 = 0;
+  if (act) {
+    constexpr int KU = 6;   // levels per batch: a batch's loads are all in flight before its sums
+    for (int k0 = 0; k0 < nz; k0 += KU) {
+      T vF[KU], vF1[KU], vq[KU], vq1[KU];
 #pragma unroll
-  for (int cc = 0; cc < NI; ++cc) { HRj[cc] = HR1[cc] = Asj[cc] = As1[cc] = 0; }
-  // levels in batches of kAarKU: the loads of a batch are all in flight before its sums
-  constexpr int kAarKU = 6;
-  for (int k0 = 0; k0 < nz; k0 += kAarKU) {
-    asm volatile("" : "+v"(t));
-    T vF[kAarKU][NI], vF1[kAarKU][NI], vq[kAarKU][NI], vq1[kAarKU][NI];
-#pragma unroll
-    for (int u = 0; u < kAarKU; ++u) {
-      const int k = k0 + u < nz ? k0 + u : nz - 1;
-      const auto rF = urow(c.F, (size_t)j * row3 + (size_t)k * nx);
-      const auto rq = urow(c.aoF, (size_t)j * row3 + (size_t)k * nx);
-      const auto rF1 = urow(c.F, (size_t)(j + 1) * row3 + (size_t)k * nx);
-      const auto rq1 = urow(c.aoF, (size_t)(j + 1) * row3 + (size_t)k * nx);
-#pragma unroll
-      for (int cc = 0; cc < NI; ++cc) {
-        const int i = t + cc * B;
-        const unsigned ui = (unsigned)(i < nx ? i : 0);
-        vF[u][cc] = rF[ui];
-        vq[u][cc] = rq[ui];
-        vF1[u][cc] = sPole ? (T)c.pin[(nz + 1) + k] : rF1[ui];
-        vq1[u][cc] = sPole ? T(0) : rq1[ui];
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + u < nz ? k0 + u : nz - 1;
+        const unsigned lv = (unsigned)(k * nx) + ui;
+        vF[u] = ldg(c.F, oJ + lv);
+        vq[u] = ldg(c.aoF, oJ + lv);
+        vF1[u] = sPole ? (T)c.pin[(nz + 1) + k] : ldg(c.F, oJ1 + lv);
+        vq1[u] = sPole ? T(0) : ldg(c.aoF, oJ1 + lv);
       }
-    }
 #pragma unroll
-    for (int u = 0; u < kAarKU; ++u) {
-      const int k = k0 + u;
-      if (k >= nz) break;
-      const C clk = g.cl[k], rsg = c.f.rsig[k];
-#pragma unroll
-      for (int cc = 0; cc < NI; ++cc) {
-        const int i = t + cc * B;
-        if (i >= nx) continue;
-        const T Fj = vF[u][cc], F1 = vF1[u][cc];
-        const T P0 = S2(RP0, i), P1 = S2(RP1, i);
-        const C rP0 = (C)S2(RrP0, i), rP1 = (C)S2(RrP1, i);
-        HRj[cc] += clk * (C)(b * Fj * S2(RrP0, i));
-        HR1[cc] += clk * (C)(b * F1 * S2(RrP1, i));
-        const C aWPj = ((C)(b * P0) + (C)(kap * Fj)) * (ch * (C)vq[u][cc]);
-        Asj[cc] += -aWPj * rsg * (rP0 * rP0);
-        if (!sPole) {
-          const C aWP1 = ((C)(b * P1) + (C)(kap * F1)) * (ch * (C)vq1[u][cc]);
-          As1[cc] += -aWP1 * rsg * (rP1 * rP1);
-        }
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + u;
+        if (k >= nz) break;
+        const C clk = g.cl[k];
+        const A rsg = (A)c.f.rsig[k];
+        HRj += clk * (C)(b * vF[u] * rP0);
+        HR1 += clk * (C)(b * vF1[u] * rP1);
+        Asj += (C)(-((b * P0 + kap * vF[u]) * (chA * vq[u])) * rsg * (rP0 * rP0));
+        if (!sPole) As1 += (C)(-((b * P1 + kap * vF1[u]) * (chA * vq1[u])) * rsg * (rP1 * rP1));
       }
     }
   }
@@ -1220,101 +1191,63 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
   // ---- level loop
   // aLQ: column sum of the l and q adjoints (they enter p_s only as a sum); aDLQ: of the leaped
   // d+l and d+q adjoints (the same leap transposes both)
-  C Sj[NI], pre[NI], aP[NI], aPU[NI], aPV[NI], aLQ[NI], aDLQ[NI];
-#pragma unroll
-  for (int cc = 0; cc < NI; ++cc) Sj[cc] = pre[cc] = aP[cc] = aPU[cc] = aPV[cc] = aLQ[cc] = aDLQ[cc] = 0;
+  C Sj = 0, pre = 0, aP = 0, aPU = 0, aPV = 0, aLQ = 0, aDLQ = 0;
 #pragma unroll 1
   for (int k = 0; k < nz; ++k) {
-    asm volatile("" : "+v"(t));
+    T* L = (k & 1) ? lb1 : lb0;
+    auto SL = [&](int row, int slot) -> T& { return L[slot * kAatLev + row]; };
     const C clk = g.cl[k], cpk = g.cpk[k], dsg = g.dsig[k];
-    const C rsg = c.f.rsig[k];
-    const size_t lvl = (size_t)k * nx;
-    const auto pFm = urow(c.F, ((size_t)(j - 1) * row3 + lvl));
-    const auto pFj = urow(c.F, ((size_t)j * row3 + lvl));
-    const auto pF1 = urow(c.F, ((size_t)(j + 1) * row3 + lvl));
-    const auto pUm = urow(c.U, ((size_t)(j - 1) * row3 + lvl));
-    const auto pUj = urow(c.U, ((size_t)j * row3 + lvl));
-    const auto pU1 = urow(c.U, ((size_t)(j + 1) * row3 + lvl));
-    const auto pVm = urow(c.V, ((size_t)(j - 1) * row3 + lvl));
-    const auto pVj = urow(c.V, ((size_t)j * row3 + lvl));
-    const auto qFm = urow(c.aoF, ((size_t)(j - 1) * row3 + lvl));
-    const auto qFj = urow(c.aoF, ((size_t)j * row3 + lvl));
-    const auto qF1 = urow(c.aoF, ((size_t)(j + 1) * row3 + lvl));
-    const auto qUj = urow(c.aoU, ((size_t)j * row3 + lvl));
-    const auto qU1 = urow(c.aoU, ((size_t)(j + 1) * row3 + lvl));
-    const auto qVm = urow(c.aoV, ((size_t)(j - 1) * row3 + lvl));
-    const auto qVj = urow(c.aoV, ((size_t)j * row3 + lvl));
+    const C rsgC = c.f.rsig[k];
+    const A rsg = (A)rsgC, dsgA = (A)dsg;
+    const unsigned lv = (unsigned)(k * nx);
     // values of the owned columns carried from phase 1 to phase 2
-    // (the owned columns' entries of the LDS rows are read back in phase 2)
-    T vRTm[NI], vRT1[NI], vPH1[NI], vFj[NI], vUj[NI], vVj[NI], vVm[NI];
-    T vAVm[NI], vAV1[NI], vAD1[NI], vMVm[NI], vMVj[NI], voF[NI], voU[NI], voV[NI], vAUU[NI];
-    // the accumulators the second phase updates, fetched now
-    T aiU0[NI], aiV0[NI], aiF0[NI];
-#pragma unroll
-    for (int cc = 0; cc < NI; ++cc) aiU0[cc] = aiV0[cc] = aiF0[cc] = T(0);
-    if (!c.ai_zero) {
-      const auto gaU = urow(c.aiU, ((size_t)j * row3 + lvl));
-      const auto gaV = urow(c.aiV, ((size_t)j * row3 + lvl));
-      const auto gaF = urow(c.aiF, ((size_t)j * row3 + lvl));
-#pragma unroll
-      for (int cc = 0; cc < NI; ++cc) {
-        const int i0 = t + cc * B;
-        const unsigned ui = (unsigned)(i0 < nx ? i0 : 0);
-        aiU0[cc] = gaU[ui];
-        aiV0[cc] = gaV[ui];
-        aiF0[cc] = gaF[ui];
+    T vRTm = 0, vRT1 = 0, vPH1 = 0, vFj = 0, vUj = 0, vVj = 0, vVm = 0;
+    T vAVm = 0, vAV1 = 0, vAD1 = 0, vMVm = 0, vMVj = 0, voF = 0, voU = 0, voV = 0, vAUU = 0;
+    T aiU0 = 0, aiV0 = 0, aiF0 = 0;
+    // ---- phase 1: per-point quantities of every slot
+    if (act) {
+      if (!c.ai_zero && own) {
+        aiU0 = ldg(c.aiU, oJ + lv + ui);
+        aiV0 = ldg(c.aiV, oJ + lv + ui);
+        aiF0 = ldg(c.aiF, oJ + lv + ui);
       }
-    }
-    // ---- phase 1: per-point quantities of the owned columns
-#pragma unroll
-    for (int cc = 0; cc < NI; ++cc) {
-      const int i = t + cc * B;
-      if (i >= nx) continue;
-      const int im = wrp_dn(i - 1, nx), ip = wrp_up(i + 1, nx);
-      const size_t oj = (size_t)j * row3 + lvl;
-      const unsigned ui = (unsigned)i, uim = (unsigned)im, uip = (unsigned)ip;
-      const T Fm = nPole ? (T)c.pin[k] : pFm[ui];
-      const T Fj = pFj[ui];
-      const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : pF1[ui];
-      const T Uj = pUj[ui], Ujm = pUj[uim];
-      const T Um = nPole ? T(0) : pUm[ui], Umm = nPole ? T(0) : pUm[uim];
-      const T U1 = sPole ? T(0) : pU1[ui], U1m = sPole ? T(0) : pU1[uim];
-      const T Vj = pVj[ui], Vjp = pVj[uip];                    // V row j+1/2
-      const T Vm = pVm[ui], Vmp = pVm[uip];                    // V row j-1/2
-      const T Pm = S2(RPm, i), P0 = S2(RP0, i), P1 = S2(RP1, i);
+      const T Fm = nPole ? (T)c.pin[k] : ldg(c.F, oJm + lv + ui);
+      const T Fj = ldg(c.F, oJ + lv + ui);
+      const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : ldg(c.F, oJ1 + lv + ui);
+      const T Uj = ldg(c.U, oJ + lv + ui), Ujm = ldg(c.U, oJ + lv + uim);
+      const T Um = nPole ? T(0) : ldg(c.U, oJm + lv + ui), Umm = nPole ? T(0) : ldg(c.U, oJm + lv + uim);
+      const T U1 = sPole ? T(0) : ldg(c.U, oJ1 + lv + ui), U1m = sPole ? T(0) : ldg(c.U, oJ1 + lv + uim);
+      const T Vj = ldg(c.V, oJ + lv + ui), Vjp = ldg(c.V, oJ + lv + uip);     // V row j+1/2
+      const T Vm = ldg(c.V, oJm + lv + ui), Vmp = ldg(c.V, oJm + lv + uip);   // V row j-1/2
+      voF = ldg(c.aoF, oJ + lv + ui);
+      voU = ldg(c.aoU, oJ + lv + ui);
+      voV = ldg(c.aoV, oJ + lv + ui);
+      const T qVm = ldg(c.aoV, oJm + lv + ui);
+      const T qFm = nPole ? T(0) : ldg(c.aoF, oJm + lv + ui);
+      const T qF1 = sPole ? T(0) : ldg(c.aoF, oJ1 + lv + ui);
+      const T qU1 = sPole ? T(0) : ldg(c.aoU, oJ1 + lv + ui);
       // forward: R T', phi'
-      const T RTm = b * Fm / Pm, RTj = b * Fj * S2(RrP0, i), RT1 = b * F1 * S2(RrP1, i);
-      HRj[cc] -= clk * (C)RTj;
-      HR1[cc] -= clk * (C)RT1;
-      const T PHj = (T)(HRj[cc] + cpk * (C)RTj);
-      const T PH1 = (T)(HR1[cc] + cpk * (C)RT1);
-      const T PU0 = PUr(RP0, i);
-      const T uj = Uj * S2(RrU0, i);
+      const T RTm = b * Fm * rPm, RTj = b * Fj * rP0, RT1 = b * F1 * rP1;
+      HRj -= clk * (C)RTj;
+      HR1 -= clk * (C)RT1;
+      const T PHj = (T)(HRj + cpk * (C)RTj);
+      const T PH1 = (T)(HR1 + cpk * (C)RT1);
+      const T uj = Uj * rU0;
       // adjoint seeds
-      voF[cc] = qFj[ui];
-      voU[cc] = qUj[ui];
-      voV[cc] = qVj[ui];
-      const A gF = chA * (A)voF[cc];
-      const A gU = chA * (A)voU[cc];
-      const A gV = chA * (A)voV[cc];
-      const A gVm = chA * (A)qVm[ui];
+      const A gF = chA * (A)voF, gU = chA * (A)voU, gV = chA * (A)voV, gVm = chA * (A)qVm;
       const A aWPj = ((A)(b * P0) + (A)(kap * Fj)) * gF;
       A aWPm = 0, aWP1 = 0;
-      if (!nPole) aWPm = ((A)(b * Pm) + (A)(kap * Fm)) * (chA * (A)qFm[ui]);
+      if (!nPole) aWPm = ((A)(b * Pm) + (A)(kap * Fm)) * (chA * (A)qFm);
       C AD1 = 0;
       if (!sPole) {
-        aWP1 = ((A)(b * P1) + (A)(kap * F1)) * (chA * (A)qF1[ui]);
-        const C rP1 = (C)S2(RrP1, i);
-        const C aSK1 = -(C)aWP1 * rsg * (rP1 * rP1);
-        As1[cc] -= aSK1;
-        const C aPi1 = -g.p0 * ch * (C)c.aoP[(size_t)(j + 1) * nx + i];
-        AD1 = 0.5 * dsg * aSK1 + dsg * (aPi1 + As1[cc]);
+        aWP1 = ((A)(b * P1) + (A)(kap * F1)) * (chA * (A)qF1);
+        const C aSK1 = (C)(-aWP1 * rsg * (rP1 * rP1));
+        As1 -= aSK1;
+        AD1 = 0.5 * dsg * aSK1 + dsg * (aPi1 + As1);
       }
-      const C rP0 = (C)S2(RrP0, i);
-      const C aSKj = -(C)aWPj * rsg * (rP0 * rP0);
-      Asj[cc] -= aSKj;
-      const C aPij = -g.p0 * ch * (C)c.aoP[(size_t)j * nx + i];
-      const C ADj = 0.5 * dsg * aSKj + dsg * (aPij + Asj[cc]);
+      const C aSKj = (C)(-aWPj * rsg * (rP0 * rP0));
+      Asj -= aSKj;
+      const C ADj = 0.5 * dsg * aSKj + dsg * (aPij + Asj);
       // U row j
       const T VV = T(0.25) * (Vj + Vjp + Vm + Vmp);
       const T fs = fj + uj * cotj;
@@ -1323,170 +1256,169 @@ __global__ void __launch_bounds__(aar_block(NI)) k_aar(Ctx<T> c) {
       const A AUU = -(A)VV * cotjA * gU;
       // U row j+1 (Coriolis read of V row j+1/2)
       A FU1 = 0;
-      if (!sPole) {
-        const T fs1 = f1 + (U1 * S2(RrU1, i)) * cot1;
-        FU1 = (A)fs1 * (chA * (A)qU1[ui]);
-      }
-      // V rows j-1/2 (jv = j-1) and j+1/2 (jv = j)
-      auto vrow = [&](int jv, int sPa, int sPb, int sRa, int sRb, T Ua, T Uam, T Ub, T Ubm,
-                      A gv, A& MV, A& FV, A& UV) {
-        const T PV = T(0.5) * (S2(sPa, i) + S2(sPb, i));
-        const T ua = (jv >= 1) ? Ua * S2(sRa, i) : T(0), uam = (jv >= 1) ? Uam * S2(sRa, im) : T(0);
-        const T ub = (jv + 1 <= ny - 1) ? Ub * S2(sRb, i) : T(0), ubm = (jv + 1 <= ny - 1) ? Ubm * S2(sRb, im) : T(0);
-        const T UU = T(0.25) * (Uam + Ua + Ubm + Ub);
+      if (!sPole) FU1 = (A)(f1 + (U1 * rU1) * cot1) * (chA * (A)qU1);
+      // V row j-1/2: U rows j-1 (row 0 is the pole: u = 0) and j
+      A MVm, FVm, UVm;
+      {
+        const T ua = nPole ? T(0) : Um * rUm, uam = nPole ? T(0) : Umm * rUmw;
+        const T ub = Uj * rU0, ubm = Ujm * rU0w;
+        const T UU = T(0.25) * (Umm + Um + Ujm + Uj);
         const T uu = T(0.25) * (uam + ua + ubm + ub);
-        const T fsv = (T)g.fv[jv] + uu * (T)(g.cotv[jv] / g.a);
-        MV = -(A)PV * gv * rdyAA;
-        FV = (A)fsv * gv;
-        UV = (A)UU * gv * (A)(g.cotv[jv] / g.a);
-      };
-      A MVm, FVm, UVm, MVj, FVj, UVj;
-      vrow(j - 1, RPm, RP0, RrUm, RrU0, Um, Umm, Uj, Ujm, gVm, MVm, FVm, UVm);
-      vrow(j, RP0, RP1, RrU0, RrU1, Uj, Ujm, U1, U1m, gV, MVj, FVj, UVj);
-      // LDS rows
-      SL(LHH, i) = (T)HH;
-      SL(LAV, i) = (T)aWPj;
-      SL(LFVm, i) = (T)FVm;
-      SL(LFV0, i) = (T)FVj;
-      SL(LUVm, i) = (T)UVm;
-      SL(LUV0, i) = (T)UVj;
-      SL(LFU0, i) = (T)FUj;
-      SL(LFU1, i) = (T)FU1;
-      SL(LAD, i) = (T)ADj;
-      SL(LPH, i) = PHj;
-      SL(LRT, i) = RTj;
-      SL(LMU, i) = PU0 * Uj;
-      SL(Lu, i) = uj;
-      // carried values
-      vRTm[cc] = RTm; vRT1[cc] = RT1; vPH1[cc] = PH1;
-      vFj[cc] = Fj; vUj[cc] = Uj; vVj[cc] = Vj; vVm[cc] = Vm;
-      vAVm[cc] = (T)aWPm; vAV1[cc] = (T)aWP1;
-      vAD1[cc] = (T)AD1;
-      vMVm[cc] = (T)MVm; vMVj[cc] = (T)MVj;
-      vAUU[cc] = (T)AUU;
-      // intermediates the pole rows' per-point kernels read
-      if (j == 1) {
-        c.s.AVGL[oj + i] = (T)aWPj;
-        c.s.FU[oj + i] = (T)FUj;
-        c.s.AD[oj + i] = (T)ADj;
-        c.s.PHI[oj + i] = PHj;
-        c.s.RT[oj + i] = RTj;
+        MVm = -(A)(T(0.5) * (Pm + P0)) * gVm * rdyAA;
+        FVm = (A)(fvm + uu * cvm) * gVm;
+        UVm = (A)UU * gVm * cvmA;
       }
-      if (j == ny - 1) {
-        c.s.AVGL[oj + i] = (T)aWPj;
-        c.s.MV[oj + i] = (T)MVj;
-        c.s.RT[oj + i] = RTj;
+      // V row j+1/2: U rows j and j+1 (row ny is the pole)
+      A MVj, FVj, UVj;
+      {
+        const T ua = Uj * rU0, uam = Ujm * rU0w;
+        const T ub = sPole ? T(0) : U1 * rU1, ubm = sPole ? T(0) : U1m * rU1w;
+        const T UU = T(0.25) * (Ujm + Uj + U1m + U1);
+        const T uu = T(0.25) * (uam + ua + ubm + ub);
+        MVj = -(A)(T(0.5) * (P0 + P1)) * gV * rdyAA;
+        FVj = (A)(fv0 + uu * cv0) * gV;
+        UVj = (A)UU * gV * cv0A;
       }
-      // base transpose of the interior row (identity); where the base and input adjoints are one
-      // buffer, into the accumulator values already fetched for the second phase
-      if (c.abU) {
-        if (c.abF == c.aiF) aiF0[cc] += voF[cc]; else c.abF[oj + i] += voF[cc];
-        if (c.abU == c.aiU) aiU0[cc] += voU[cc]; else c.abU[oj + i] += voU[cc];
-        if (c.abV == c.aiV) aiV0[cc] += voV[cc]; else c.abV[oj + i] += voV[cc];
-        if (k == 0) c.abP[(size_t)j * nx + i] += c.aoP[(size_t)j * nx + i];
+      SL(LHH, sl) = (T)HH;
+      SL(LAV, sl) = (T)aWPj;
+      SL(LFVm, sl) = (T)FVm;
+      SL(LFV0, sl) = (T)FVj;
+      SL(LUVm, sl) = (T)UVm;
+      SL(LUV0, sl) = (T)UVj;
+      SL(LFU0, sl) = (T)FUj;
+      SL(LFU1, sl) = (T)FU1;
+      SL(LAD, sl) = (T)ADj;
+      SL(LPH, sl) = PHj;
+      SL(LRT, sl) = RTj;
+      SL(LMU, sl) = PU0 * Uj;
+      SL(Lu, sl) = uj;
+      vRTm = RTm; vRT1 = RT1; vPH1 = PH1;
+      vFj = Fj; vUj = Uj; vVj = Vj; vVm = Vm;
+      vAVm = (T)aWPm; vAV1 = (T)aWP1;
+      vAD1 = (T)AD1;
+      vMVm = (T)MVm; vMVj = (T)MVj;
+      vAUU = (T)AUU;
+      if (own) {
+        const unsigned oj = oJ + lv + ui;
+        // intermediates the pole rows' per-point kernels read
+        if (j == 1) {
+          stg(c.s.AVGL, oj, (T)aWPj);
+          stg(c.s.FU, oj, (T)FUj);
+          stg(c.s.AD, oj, (T)ADj);
+          stg(c.s.PHI, oj, PHj);
+          stg(c.s.RT, oj, RTj);
+        }
+        if (j == ny - 1) {
+          stg(c.s.AVGL, oj, (T)aWPj);
+          stg(c.s.MV, oj, (T)MVj);
+          stg(c.s.RT, oj, RTj);
+        }
+        // base transpose of the interior row (identity); where the base and input adjoints are one
+        // buffer, into the accumulator values already fetched for the second phase
+        if (c.abU) {
+          if (c.abF == c.aiF) aiF0 += voF; else stg(c.abF, oj, ldg(c.abF, oj) + voF);
+          if (c.abU == c.aiU) aiU0 += voU; else stg(c.abU, oj, ldg(c.abU, oj) + voU);
+          if (c.abV == c.aiV) aiV0 += voV; else stg(c.abV, oj, ldg(c.abV, oj) + voV);
+          if (k == 0) {
+            const unsigned o2 = (unsigned)j * (unsigned)nx + ui;
+            stg(c.abP, o2, ldg(c.abP, o2) + ldg(c.aoP, o2));
+          }
+        }
       }
     }
     __syncthreads();
 
     // ---- phase 2: forward D, S, omega/p; gathers; transposes into the owned columns
-#pragma unroll
-    for (int cc = 0; cc < NI; ++cc) {
-      const int i = t + cc * B;
-      if (i >= nx) continue;
-      const int im = wrp_dn(i - 1, nx), ip = wrp_up(i + 1, nx);
-      const size_t oj = (size_t)j * row3 + (size_t)k * nx + i;
-      const T vRTj = SL(LRT, i), vPHj = SL(LPH, i);
-      const A vAVj = (A)SL(LAV, i), vADj = (A)SL(LAD, i), vHH = (A)SL(LHH, i);
-      const A vUVm = (A)SL(LUVm, i), vUVj = (A)SL(LUV0, i), vFVm = (A)SL(LFVm, i), vFVj = (A)SL(LFV0, i);
-      const A vFUj = (A)SL(LFU0, i), vFU1 = (A)SL(LFU1, i);
-      const T PU0 = PUr(RP0, i);
-      const T PV0 = T(0.5) * (S2(RP0, i) + S2(RP1, i)), PVm = T(0.5) * (S2(RPm, i) + S2(RP0, i));
+    if (own) {
+      const int sm = sl - 1, sp = sl + 1;
+      const unsigned oj = oJ + lv + ui;
+      const T vRTj = SL(LRT, sl), vPHj = SL(LPH, sl);
+      const A vAVj = (A)SL(LAV, sl), vADj = (A)SL(LAD, sl), vHH = (A)SL(LHH, sl);
+      const A vUVm = (A)SL(LUVm, sl), vUVj = (A)SL(LUV0, sl), vFVm = (A)SL(LFVm, sl), vFVj = (A)SL(LFV0, sl);
+      const A vFUj = (A)SL(LFU0, sl), vFU1 = (A)SL(LFU1, sl);
+      const T PV0 = T(0.5) * (P0 + P1), PVm = T(0.5) * (Pm + P0);
       // forward D, S, omega/p (as the forward recompute forms them)
-      const T D = (SL(LMU, wrp_up(i + n - 1, nx)) - SL(LMU, wrp_dn(i - n, nx))) * rdxT +
-                  (svj * (PV0 * vVj[cc]) - svm * (PVm * vVm[cc])) * rdySjT;
-      const T rPV0 = S2(RrPV0, i), rPVm = S2(RrPVm, i);
-      const C SkC = Sj[cc];
-      const T Sk = (T)SkC;
-      Sj[cc] += (C)D * dsg;
-      const T zon = T(0.5) * (SL(Lu, i) * S2(RDL, i) + SL(Lu, im) * S2(RDL, im));
-      const T mer = T(0.5) * ((vVj[cc] * rPV0) * S2(RdL0, i) + (vVm[cc] * rPVm) * S2(RdLm, i)) * rdyAT;
-      const C rPc = (C)S2(RrP0, i), rP2c = rPc * rPc;
-      const T WP = (T)(((C)zon + (C)mer) - (SkC + 0.5 * (C)D * dsg) * rsg * rP2c);
-      const A wp = (A)WP, gF = chA * (A)voF[cc], aWP = vAVj;
-      const A rPA = (A)S2(RrP0, i), rP2A = rPA * rPA;
-      const A AFE = (A)kap * wp * gF;
-      const A AP3 = (A)b * wp * gF + A(2) * ((A)Sk + A(0.5) * (A)D * (A)dsg) * (A)rsg * (rP2A * rPA) * aWP;
+      const T D = (SL(LMU, sl + n - 1) - SL(LMU, sl - n)) * rdxT +
+                  (svj * (PV0 * vVj) - svm * (PVm * vVm)) * rdySjT;
+      const C SkC = Sj;
+      Sj += (C)D * dsg;
+      const T zon = T(0.5) * (SL(Lu, sl) * DLc + SL(Lu, sm) * DLw);
+      const T mer = T(0.5) * ((vVj * rPV0) * dL0 + (vVm * rPVm) * dLm) * rdyAT;
+      const T Sh = (T)(SkC + 0.5 * (C)D * dsg);   // S at the full level
+      const A rP2A = rP0 * rP0;
+      const A wp = (A)((zon + mer) - Sh * rsg * rP2A);
+      const A gF = chA * (A)voF, aWP = vAVj;
+      const A AFE = kap * wp * gF;
+      const A AP3 = b * wp * gF + A(2) * Sh * rsg * (rP2A * rP0) * aWP;
       // U point: pressure gradient seen by U row j
-      const T dphi = (SL(LPH, wrp_up(i + n, nx)) - SL(LPH, wrp_dn(i + 1 - n, nx))) * rdxT;
-      const T rtx = T(0.5) * (vRTj + SL(LRT, ip));
-      const A pgf = (A)dphi + RT0A * (A)S2(RDQ, i) + (A)rtx * (A)S2(RDL, i);
-      const A gU = chA * (A)voU[cc], gV = chA * (A)voV[cc];
+      const T dphi = (SL(LPH, sl + n) - SL(LPH, sl + 1 - n)) * rdxT;
+      const T rtx = T(0.5) * (vRTj + SL(LRT, sp));
+      const A pgf = (A)dphi + RT0A * (A)DQc + (A)rtx * (A)DLc;
+      const A gU = chA * (A)voU, gV = chA * (A)voV;
       const A APU3 = -pgf * gU;
       // V point: pressure gradient seen by V row j+1/2
-      const A pgfV = ((A)(vPH1[cc] - vPHj) + RT0A * (A)S2(RdQ0, i) +
-                      (A)(T(0.5) * (vRTj + vRT1[cc])) * (A)S2(RdL0, i)) * rdyAA;
+      const A pgfV = ((A)(vPH1 - vPHj) + RT0A * (A)dQ0 + (A)(T(0.5) * (vRTj + vRT1)) * (A)dL0) * rdyAA;
       const A APV3 = -pgfV * gV;
       // gathers: scalar point
-      const A mM = (A)vMVm[cc], mJ = (A)vMVj[cc];
-      const A aPHI = ((A)SL(LHH, wrp_dn(i - n, nx)) - (A)SL(LHH, wrp_up(i + n - 1, nx))) * rdxA + mM - mJ;
-      const A aRT = A(0.5) * ((A)SL(LHH, i) * (A)S2(RDL, i) + (A)SL(LHH, im) * (A)S2(RDL, im)) +
-                    A(0.5) * (A)S2(RdLm, i) * mM + A(0.5) * (A)S2(RdL0, i) * mJ;
-      const A cvgm = (nPole ? (A)(sVG[0 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAVm[cc]) + A(0.5) * vAVj;
-      const A cvgj = A(0.5) * vAVj + (sPole ? (A)(sVG[1 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAV1[cc]);
-      const A rtym = A(0.5) * ((A)vRTm[cc] + (A)vRTj), rtyj = A(0.5) * ((A)vRTj + (A)vRT1[cc]);
-      const A wm = (A)(vVm[cc] * rPVm) * raDyA * cvgm, wj = (A)(vVj[cc] * rPV0) * raDyA * cvgj;
+      const A mM = (A)vMVm, mJ = (A)vMVj;
+      const A aPHI = ((A)SL(LHH, sl - n) - (A)SL(LHH, sl + n - 1)) * rdxA + mM - mJ;
+      const A aRT = A(0.5) * ((A)SL(LHH, sl) * (A)DLc + (A)SL(LHH, sm) * (A)DLw) +
+                    A(0.5) * (A)dLm * mM + A(0.5) * (A)dL0 * mJ;
+      const A cvgm = (nPole ? (A)(sVG[0 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAVm) + A(0.5) * vAVj;
+      const A cvgj = A(0.5) * vAVj + (sPole ? (A)(sVG[1 * (nz + 1) + k] * rnx) : A(0.5) * (A)vAV1);
+      const A rtym = A(0.5) * ((A)vRTm + (A)vRTj), rtyj = A(0.5) * ((A)vRTj + (A)vRT1);
+      const A wm = (A)(vVm * rPVm) * raDyA * cvgm, wj = (A)(vVj * rPV0) * raDyA * cvgj;
       const A aL = (wm + rtym * mM) - (wj + rtyj * mJ);
       const A aQ = RT0A * mM - RT0A * mJ;
       // gathers: U point
-      const A dl = (A)S2(RDL, i);
-      const A au = (A)vAUU[cc] + A(0.5) * dl * (vAVj + (A)SL(LAV, ip)) +
-                   A(0.25) * (vUVm + (A)SL(LUVm, ip) + vUVj + (A)SL(LUV0, ip));
-      const A aUd = A(0.25) * (vFVm + (A)SL(LFVm, ip) + vFVj + (A)SL(LFV0, ip));
-      const A rPUc = (A)S2(RrU0, i);
-      const A u = (A)(vUj[cc] * S2(RrU0, i));
-      const A rtxA = A(0.5) * ((A)vRTj + (A)SL(LRT, ip));
-      const A adl = A(0.5) * u * (vAVj + (A)SL(LAV, ip)) + rtxA * vHH;
+      const A dl = (A)DLc;
+      const A au = (A)vAUU + A(0.5) * dl * (vAVj + (A)SL(LAV, sp)) +
+                   A(0.25) * (vUVm + (A)SL(LUVm, sp) + vUVj + (A)SL(LUV0, sp));
+      const A aUd = A(0.25) * (vFVm + (A)SL(LFVm, sp) + vFVj + (A)SL(LFV0, sp));
+      const A rPUc = (A)rU0;
+      const A u = (A)(vUj * rU0);
+      const A rtxA = A(0.5) * ((A)vRTj + (A)SL(LRT, sp));
+      const A adl = A(0.5) * u * (vAVj + (A)SL(LAV, sp)) + rtxA * vHH;
       const A adq = RT0A * vHH;
       // gathers: V point
-      const A avv = (A)S2(RdL0, i) * raDyA * cvgj;
-      A aVd = (A)SL(LFU0, im) + vFUj;
-      if (!sPole) aVd += (A)SL(LFU1, im) + vFU1;
+      const A avv = (A)dL0 * raDyA * cvgj;
+      A aVd = (A)SL(LFU0, sm) + vFUj;
+      if (!sPole) aVd += (A)SL(LFU1, sm) + vFU1;
       const A avd = A(-0.25) * aVd;
       // divergence and velocity transposes
-      const A aMU = ((A)SL(LAD, wrp_dn(i - n + 1, nx)) - (A)SL(LAD, wrp_up(i + n, nx))) * rdxA;
-      const A PUc = (A)PU0, Uc = (A)vUj[cc];
-      c.aiU[oj] = (T)((C)aiU0[cc] + (C)(aUd + au * rPUc + PUc * aMU));
+      const A aMU = ((A)SL(LAD, sl - n + 1) - (A)SL(LAD, sl + n)) * rdxA;
+      const A PUc = (A)PU0, Uc = (A)vUj;
+      stg(c.aiU, oj, (T)((C)aiU0 + (C)(aUd + au * rPUc + PUc * aMU)));
       const A aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;
       const A tN = vADj * rdySjA;
-      const A tS = sPole ? (A)(capD * sDs[1 * (nz + 1) + k]) : (A)vAD1[cc] * rdyS1A;
+      const A tS = sPole ? (A)(capD * sDs[1 * (nz + 1) + k]) : (A)vAD1 * rdyS1A;
       const A aMV = (A)svj * (tN - tS);
-      const A PVc = (A)PV0, Vc = (A)vVj[cc], rPVc = (A)rPV0;
-      c.aiV[oj] = (T)((C)aiV0[cc] + (C)(avd + avv * rPVc + PVc * aMV));
+      const A PVc = (A)PV0, Vc = (A)vVj, rPVc = (A)rPV0;
+      stg(c.aiV, oj, (T)((C)aiV0 + (C)(avd + avv * rPVc + PVc * aMV)));
       const A aPV3 = -Vc * (rPVc * rPVc) * avv + Vc * aMV;
       // hydrostatic transpose and column sums
-      const C art = (C)aRT + clk * pre[cc] + cpk * (C)aPHI;
-      pre[cc] += (C)aPHI;
-      const C afe = (C)AFE + (C)b * rPc * art;
-      aP[cc] += (C)AP3 - (C)b * rP2c * (C)vFj[cc] * art;
-      aLQ[cc] += (C)(aL + aQ);
-      aDLQ[cc] += (C)(adl + adq);
-      aPU[cc] += (C)(APU3 + aPU3);
-      aPV[cc] += (C)(APV3 + aPV3);
-      c.aiF[oj] = (T)((C)aiF0[cc] + afe);
+      const A art = aRT + (A)(clk * pre) + (A)cpk * aPHI;
+      pre += (C)aPHI;
+      const A afe = AFE + b * rP0 * art;
+      aP += (C)(AP3 - b * rP2A * (A)vFj * art);
+      aLQ += (C)(aL + aQ);
+      aDLQ += (C)(adl + adq);
+      aPU += (C)(APU3 + aPU3);
+      aPV += (C)(APV3 + aPV3);
+      stg(c.aiF, oj, (T)((C)aiF0 + (C)afe));
     }
-    __syncthreads();
+    (void)dsgA;
+    // no second barrier: the next level's phase 1 writes the other buffer, and the level after that
+    // writes this one only past the next barrier, which every wave reaches after this phase 2
   }
-#pragma unroll
-  for (int cc = 0; cc < NI; ++cc) {
-    const int i = t + cc * B;
-    if (i >= nx) continue;
-    const size_t i2 = (size_t)j * nx + i;
-    c.s.AP2[i2] = aP[cc];
-    c.s.APU2[i2] = aPU[cc];
-    c.s.APV2[i2] = aPV[cc];
-    c.s.AL2[i2] = aLQ[cc];
+  if (own) {
+    const size_t i2 = (size_t)j * nx + col;
+    c.s.AP2[i2] = aP;
+    c.s.APU2[i2] = aPU;
+    c.s.APV2[i2] = aPV;
+    c.s.AL2[i2] = aLQ;
     c.s.AQ2[i2] = 0;
-    c.s.ADL2[i2] = aDLQ[cc];
+    c.s.ADL2[i2] = aDLQ;
     c.s.ADQ2[i2] = 0;
   }
 }
@@ -1525,21 +1457,22 @@ hipError_t allow_lds_adj(size_t lds) {
   return e;
 }
 
-// The row-fused adaptation adjoint serves grids whose rows fit the LDS at <= 2 columns per thread.
+// The tiled row-fused adaptation adjoint serves every grid whose rows' halos leave tiles of at least
+// 32 columns (the handle then holds its work items).
 template <typename T>
 bool aar_used(const Ctx<T>& c) {
-  return c.blk > 0 && aar_ok(c.g.nx, (int)sizeof(T)) && (c.g.nx + c.blk - 1) / c.blk <= 2 && c.g.ny >= 4;
+  return c.aat != nullptr && c.aat_n > 0 && c.g.ny >= 4;
 }
 
-template <typename T, int NI>
+template <typename T>
 hipError_t launch_aar(const Ctx<T>& c, hipStream_t s) {
-  const size_t lds = aar_lds(c.g.nx, (int)sizeof(T));
-  hipError_t e = allow_lds_adj<k_aar<T, NI>>(lds);
+  const size_t lds = aat_lds(c.aat_blk, (int)sizeof(T));
+  hipError_t e = allow_lds_adj<k_aat<T>>(lds);
   if (e != hipSuccess) return e;
   KTimer* t = c.timer;
   const bool timed = t && t->armed && t->n < t->cap;
   if (timed && (e = hipEventRecord(t->ev[2 * t->n], s)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_aar<T, NI>), dim3(c.g.ny - 1), dim3(c.blk), lds, s, c);
+  hipLaunchKernelGGL((k_aat<T>), dim3(c.aat_n), dim3(c.aat_blk), lds, s, c);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (timed) {
@@ -1594,7 +1527,7 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     hipLaunchKernelGGL((k_a12<T, 6, 1>), dim3(gx, 2), dim3(tb), 0, s, cp);
     hipLaunchKernelGGL((k_pole_sum2<T>), dim3(4 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
                        c.s.psum + PS_AD * 2 * (nz + 1), (const T*)c.s.AVGL, c.s.psum + PS_AVGL * 2 * (nz + 1));
-    const hipError_t e = (nx + c.blk - 1) / c.blk == 1 ? launch_aar<T, 1>(c, s) : launch_aar<T, 2>(c, s);
+    const hipError_t e = launch_aar<T>(c, s);
     if (e != hipSuccess) return e;
     Ctx<T> cv = c;   // V row 1/2: reads phi' and R T' of row 1, written by the row-fused kernel
     cv.parts = 4;
@@ -1735,6 +1668,9 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.f = v.fac;
   c.blk = v.block;
   c.timer = v.timer;
+  c.aat = v.aat;
+  c.aat_n = v.aat_n;
+  c.aat_blk = v.aat_block;
   c.ai_zero = ai_zero && ab.U != ai.U;
   c.base_in_tail = process == 1 && ab.U && ab.U == ai.U && ab.V == ai.V && ab.F == ai.F && ab.P == ai.P;
   hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
@@ -1785,7 +1721,7 @@ hipError_t zero_outside_rows(const HandleView& v, St4<T> a, hipStream_t s) {
 // Whether the adaptation-stage adjoint of this handle runs the row-fused kernel (as aar_used).
 template <typename T>
 bool rows_fused(const HandleView& v) {
-  const Ctx<T> c = [&] { Ctx<T> x; x.g = v.g; x.blk = v.block; return x; }();
+  const Ctx<T> c = [&] { Ctx<T> x; x.g = v.g; x.blk = v.block; x.aat = v.aat; x.aat_n = v.aat_n; return x; }();
   return aar_used(c);
 }
 

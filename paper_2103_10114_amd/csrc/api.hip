@@ -71,6 +71,8 @@ struct dycore_s {
   unsigned long long* count = nullptr;
   void* adj = nullptr;          // adjoint workspace
   size_t adj_bytes = 0;
+  AatItem* aat = nullptr;       // work items of the tiled adaptation-stage adjoint (device)
+  int aat_n = 0, aat_block = 0;
   size_t bytes = 0;
 };
 
@@ -125,6 +127,53 @@ int leap_span(double sin_theta, double dlam, int nx) {
   if ((cap & 1) == 0) --cap;
   if (cap < 1) cap = 1;
   return std::min(m, cap);
+}
+
+// Work items of the tiled adaptation-stage adjoint (AatItem) for a block of `block` threads: every
+// interior row is cut into the fewest equal zonal tiles whose owned columns plus a halo of n_j + 1
+// columns on each side fit the block.  Items are listed row by row, then spread so that item b
+// (which the hardware dispatches to XCD b mod 8) walks a contiguous eighth of that list.  Returns
+// false when some row's halo leaves fewer than 32 owned columns.
+bool aat_tiles(int nx, int ny, const std::vector<int>& M, int block, std::vector<AatItem>& out) {
+  std::vector<AatItem> seq;
+  for (int j = 1; j < ny; ++j) {
+    const int hl = (M[j] + 1) / 2 + 1;
+    const int cap = block - 2 * hl;
+    if (cap < 32) return false;
+    const int nt = (nx + cap - 1) / cap;
+    const int w = (nx + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+      const int i0 = t * w;
+      if (i0 >= nx) break;
+      seq.push_back(AatItem{j, i0, std::min(w, nx - i0), hl});
+    }
+  }
+  const int n = (int)seq.size(), per = (n + 7) / 8;
+  out.assign((size_t)per * 8, AatItem{-1, 0, 0, 0});
+  for (int x = 0; x < 8; ++x)
+    for (int q = 0; q < per; ++q) {
+      const int src = x * per + q;
+      if (src < n) out[(size_t)q * 8 + x] = seq[src];
+    }
+  return true;
+}
+
+// The block (a multiple of 64 up to kAatMaxBlock) whose tiles leave the fewest idle threads
+// (owned columns over launched threads; ties go to the larger block), and its items.  False when no
+// block fits the widest halo (the adjoint then uses its per-point kernels).
+bool aat_items(int nx, int ny, const std::vector<int>& M, std::vector<AatItem>& out, int& block) {
+  double best = -1.0;
+  for (int b = 64; b <= kAatMaxBlock; b += 64) {
+    std::vector<AatItem> items;
+    if (!aat_tiles(nx, ny, M, b, items)) continue;
+    const double util = (double)nx * (ny - 1) / ((double)items.size() * b);
+    if (util >= best - 1e-12) {
+      best = util;
+      block = b;
+      out.swap(items);
+    }
+  }
+  return best > 0.0;
 }
 
 // Threads per row workgroup: one column per thread up to 1024 columns, else the fewest
@@ -303,6 +352,9 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.fac = h->fac;
   v.recorded = const_cast<int*>(&h->recorded);
   v.timer = const_cast<dyc::KTimer*>(&h->timer);
+  v.aat = h->aat;
+  v.aat_n = h->aat_n;
+  v.aat_block = h->aat_block;
   return v;
 }
 
@@ -451,6 +503,18 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   if (ok && !(h->flags & DYCORE_FORWARD_ONLY)) {
     h->adj_bytes = dyc_adjoint_workspace_bytes(h);
     ok = hipMalloc(&h->adj, h->adj_bytes) == hipSuccess;
+    std::vector<AatItem> items;
+    int blk = 0;
+    if (ok && aat_items(nx, ny, h->M, items, blk)) {
+      ok = hipMalloc((void**)&h->aat, sizeof(AatItem) * items.size()) == hipSuccess;
+      ok = ok && hipMemcpy(h->aat, items.data(), sizeof(AatItem) * items.size(), hipMemcpyHostToDevice) ==
+                     hipSuccess;
+      if (ok) {
+        h->aat_n = (int)items.size();
+        h->aat_block = blk;
+        h->adj_bytes += sizeof(AatItem) * items.size();
+      }
+    }
   }
   if (!ok) { dycore_destroy(h); return DYCORE_ENOMEM; }
   h->bytes += 2 * h->state_bytes + sizeof(double) * (kPoleSlots * 2 * (nz + 1) + 3 * (ny + 1) + 2) + 8 + h->adj_bytes;
@@ -509,6 +573,7 @@ int dycore_destroy(dycore_t h) {
   if (h->diag) (void)hipFree(h->diag);
   if (h->count) (void)hipFree(h->count);
   if (h->adj) (void)hipFree(h->adj);
+  if (h->aat) (void)hipFree(h->aat);
   release_timer(h);
   delete h;
   return DYCORE_OK;

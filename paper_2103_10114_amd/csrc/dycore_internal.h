@@ -155,6 +155,15 @@ __device__ __forceinline__ void xcd_tile3(int gx, int nz, int nrows, int& x, int
   j = tup / (gx * nz);
 }
 
+// Zonal tiles of the tiled adaptation-stage adjoint: one work item per (row, tile), a tile being
+// w owned columns from i0 plus a halo of hl = n_j + 1 columns on each side (n_j the row's leap half
+// width), one column per thread, w + 2 hl <= the launch's block.  Items are ordered so that the
+// workgroups one XCD runs cover a contiguous band of rows; padding items have j = -1.
+struct AatItem {
+  int j, i0, w, hl;
+};
+constexpr int kAatMaxBlock = 320;
+
 // What the adjoint translation unit sees of a handle.
 struct HandleView {
   GeoDev g;
@@ -169,6 +178,9 @@ struct HandleView {
   GeoFac fac;
   int* recorded;     // 1 while the adjoint workspace holds the stage inputs of a recorded step
   KTimer* timer;     // launches of the row-fused adaptation-stage adjoint kernel
+  const AatItem* aat;   // tiled adaptation-adjoint work items (device), or NULL when rows do not fit
+  int aat_n;            // item count (a multiple of 8)
+  int aat_block;        // threads per tile workgroup
 };
 HandleView view_of(const dycore_s* h);
 

@@ -1,5 +1,5 @@
 """GPU edge cases: every kernel form on both sides of the row length at which its LDS rows stop
-fitting (the pipelined stage kernels, the row-fused adaptation adjoint), ragged rows at two columns
+fitting (the pipelined stage kernels), the tilings of the row-fused adaptation adjoint, ragged rows at two columns
 per thread, a single sigma level, zero steps, sizes the library refuses, and a stage adjoint whose
 base and input adjoints are one buffer."""
 import dataclasses
@@ -81,13 +81,15 @@ def test_stage_fp32_ragged_and_limit(nx, process):
         assert err < 2e-3, (k, err)
 
 
-# The row-fused adaptation adjoint holds 28 rows (no pole-sum block): FP64 fits at 731 columns.
-@pytest.mark.parametrize("nx", [731, 732])
-def test_stage_adjoint_fp64_across_row_kernel_limit(nx):
-    """The adaptation-stage adjoint equals the oracle on both sides of the row-fused kernel's limit."""
-    assert (((28 * 731 * 8 + 15) // 16) * 16 <= 160 * 1024) and (((28 * 732 * 8 + 15) // 16) * 16 > 160 * 1024)
-    print(f"stage adjoint fp64 nx={nx}", flush=True)
-    cfg = small(nx, 8, 3)
+# The tiled row-fused adaptation adjoint cuts rows into zonal tiles of <= 320 slots, halos included:
+# 731 columns give three tiles with a ragged last one; 96 columns one tile per row; at 512 x 1024 the
+# polar rows' halos (n + 1 = 117 columns each side) leave 86-column tiles; at 1024 x 1440 they
+# (n + 1 = 163) leave fewer than 32 owned columns, so that handle runs the per-point adjoint kernels.
+@pytest.mark.parametrize("nx,ny,nz", [(731, 8, 3), (96, 24, 4), (512, 1024, 2), (1024, 1440, 1)])
+def test_stage_adjoint_fp64_tile_forms(nx, ny, nz):
+    """The adaptation-stage adjoint equals the oracle for each tiling of the rows."""
+    print(f"stage adjoint fp64 {nx}x{ny}x{nz}", flush=True)
+    cfg = small(nx, ny, nz)
     st = synth.make_state(cfg)
     ao = synth.random_like(st, 31)
     ch = 200.0
