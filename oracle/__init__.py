@@ -59,7 +59,7 @@ def _p(a):
 class Oracle:
     """One grid: nx longitudes, ny latitude intervals (ny+1 scalar rows incl. poles), nz levels."""
 
-    def __init__(self, nx, ny, nz, phis=None, sigma_half=None, consts=None):
+    def __init__(self, nx, ny, nz, phis=None, sigma_half=None, consts=None, filters=False):
         self.nx, self.ny, self.nz = nx, ny, nz
         L = _load()
         self._phis = None if phis is None else np.ascontiguousarray(phis, dtype=np.float64)
@@ -69,6 +69,7 @@ class Oracle:
         if not self.h:
             raise ValueError("bad grid")
         self.L = L
+        L.orc_set_filters(ctypes.c_void_p(self.h), 1 if filters else 0)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -136,6 +137,12 @@ class Oracle:
                          _p(s["U"]), _p(s["V"]), _p(s["Phi"]), _p(s["ps"]),
                          _p(o["U"]), _p(o["V"]), _p(o["Phi"]), _p(o["ps"]))
         return o
+
+    def filter(self, st):
+        """The low-latitude filters (Sec. III-B, Table IV rows 1-2) applied once to a copy of st."""
+        s = {k: np.array(v, dtype=np.float64, copy=True, order="C") for k, v in self._c(st).items()}
+        self.L.orc_filter(self._vh(), _p(s["U"]), _p(s["V"]), _p(s["Phi"]), _p(s["ps"]))
+        return s
 
     def substeps(self, dt):
         return int(self.L.orc_substeps(self._vh(), ctypes.c_double(dt)))

@@ -49,6 +49,7 @@ struct Geo {
   std::vector<int> M, n, Mv, nv;        // leap span (odd) and half width
   std::vector<double> sigh, sig, dsig, cl, cpk;
   std::vector<double> phis;             // (ny+1)*nx, pole rows replaced by their mean
+  int filters = 0;                      // low-latitude filters after each outer step (Table IV rows 1-2)
 };
 
 // eq. 7 with res = dlam and cos(90deg - theta) = sin(theta); the result is
@@ -492,12 +493,73 @@ void rk3(const Geo& g, St<T>& y, double h, int which) {
   y = y3;
 }
 
+// ---------------------------------------------------------------- low-latitude filters
+// The filters the leap format keeps equatorward of 70 degrees (Sec. III-B, Table IV rows 1-2),
+// one zonal row at a time, in the readings of the design notes:
+//   |lat| < 38 deg:        the simplified filter removes the 2-dlam wave, F_x -= (-1)^x A with
+//                          A = (1/I) sum_x' (-1)^x' F_x' (x from 0, I = nx even);
+//   38 <= |lat| <= 70 deg: the 3-point operator F_x + r (F_{x-1} - 2 F_x + F_{x+1}), with
+//                          r = (1 - cos(lat) / cos 38deg) / 4, so that the 2-dlam wave keeps the
+//                          fraction cos(lat) / cos 38deg of its amplitude (the ratio of the row's
+//                          zonal spacing to the spacing at 38 degrees);
+//   |lat| > 70 deg:        no filter (the leap takes its place).
+// The latitude of a row is 90 (ny - 2j) / ny degrees for scalar and U rows and 90 (ny - 2j - 1) / ny
+// for V row j; the band edges are decided on those integers exactly.
+// Returns 0 (no filter), 1 (simplified filter) or 2 (3-point operator, coefficient in *r).
+int filter_band(int num, int ny, double* r) {
+  const int m = num < 0 ? -num : num;   // |lat| = 90 m / ny degrees
+  *r = 0.0;
+  if (m * 90 < 38 * ny) return 1;
+  if (m * 90 <= 70 * ny) {
+    const double lat = (90.0 * m / ny) * M_PI / 180.0;
+    *r = 0.25 * (1.0 - std::cos(lat) / std::cos(38.0 * M_PI / 180.0));
+    return 2;
+  }
+  return 0;
+}
+
+template <typename T>
+void filter_row(T* F, int nx, int band, double r) {
+  if (band == 1) {
+    T A(0);
+    for (int x = 0; x < nx; ++x) A += (x % 2 == 0) ? F[x] : -F[x];
+    A /= double(nx);
+    for (int x = 0; x < nx; ++x) F[x] -= (x % 2 == 0) ? A : -A;
+  } else if (band == 2) {
+    std::vector<T> old(F, F + nx);
+    for (int x = 0; x < nx; ++x)
+      F[x] = old[x] + r * (old[wrap(x - 1, nx)] - 2.0 * old[x] + old[wrap(x + 1, nx)]);
+  }
+}
+
+// The filters on every interior row of U, V, Phi and p_s (the pole rows lie poleward of 70 deg).
+template <typename T>
+void filter_lowlat(const Geo& g, St<T>& y) {
+  const Sizes z(g);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  double r;
+  for (int j = 1; j < ny; ++j) {
+    const int band = filter_band(ny - 2 * j, ny, &r);
+    for (int k = 0; k < nz; ++k) {
+      filter_row(&y.U[z.i3(j, k, 0)], nx, band, r);
+      filter_row(&y.F[z.i3(j, k, 0)], nx, band, r);
+    }
+    filter_row(&y.ps[z.i2(j, 0)], nx, band, r);
+  }
+  for (int jv = 0; jv < ny; ++jv) {
+    const int band = filter_band(ny - 2 * jv - 1, ny, &r);
+    for (int k = 0; k < nz; ++k) filter_row(&y.V[z.i3(jv, k, 0)], nx, band, r);
+  }
+}
+
 // One outer step: msub RK3 sub-steps of the adaptation with dt/msub (3*msub calls),
-// then one RK3 step of the advection with dt (3 calls).
+// then one RK3 step of the advection with dt (3 calls), then (when enabled) the low-latitude
+// filters.
 template <typename T>
 void step(const Geo& g, St<T>& y, double dt, int msub) {
   for (int m = 0; m < msub; ++m) rk3(g, y, dt / msub, 0);
   rk3(g, y, dt, 1);
+  if (g.filters) filter_lowlat(g, y);
 }
 
 // ---------------------------------------------------------------- adjoint (reverse sweep)
@@ -1053,6 +1115,8 @@ void adj_rk3(const Geo& g, const St<double>& y, double h, int which, St<double>&
 
 // Transpose of step about its start state y0.
 void adj_step(const Geo& g, const St<double>& y0, double dt, int msub, St<double>& a) {
+  // the filters act last and each row operator is symmetric: their transpose is themselves
+  if (g.filters) filter_lowlat(g, a);
   std::vector<St<double>> starts;
   St<double> y = y0;
   for (int m = 0; m < msub; ++m) { starts.push_back(y); rk3(g, y, dt / msub, 0); }
@@ -1355,6 +1419,17 @@ void orc_diagnostics(void* h, const double* U, const double* V, const double* F,
   }
   *mass = m;
   *energy = g.p0 / (2.0 * g.g) * e + g.rd * g.t0 * g.p0 / (2.0 * g.g) * es;
+}
+
+// Low-latitude filters on (step) or off; the state filter alone, in place.
+void orc_set_filters(void* h, int on) { static_cast<Geo*>(h)->filters = on ? 1 : 0; }
+
+void orc_filter(void* h, double* U, double* V, double* F, double* ps) {
+  const Geo& g = *static_cast<Geo*>(h);
+  St<double> y;
+  load(g, y, U, V, F, ps);
+  filter_lowlat(g, y);
+  store(g, y, U, V, F, ps);
 }
 
 // Sub-step count from the CFL rule: ceil(omega_max dt / (0.8 sqrt 3)) with

@@ -623,3 +623,109 @@ def test_numpy_brute_force(nx, ny, nz, which):
     for k in ("U", "V", "Phi", "ps"):
         scale = max(np.abs(t[k]).max(), 1e-300)
         np.testing.assert_allclose(b[k], t[k], rtol=0, atol=1e-12 * scale, err_msg=f"{which} {k}")
+
+
+# ----------------------------------------------------------------------------- low-latitude filters
+def _lat(ny, j, vrow=False):
+    """Latitude in degrees of scalar/U row j or V row j (colatitude j dth or (j + 1/2) dth)."""
+    return 90.0 - (j + (0.5 if vrow else 0.0)) * 180.0 / ny
+
+
+def _filter_case(nx=64, ny=32, nz=2):
+    o = oracle.Oracle(nx, ny, nz)
+    lam = np.arange(nx) * 2 * math.pi / nx
+    alt = (-1.0) ** np.arange(nx)
+    st = o.zeros()
+    # every row: a constant, a smooth wave and the 2-dlam wave
+    row = 3.0 + 0.7 * np.cos(3 * lam) + 0.25 * alt
+    st["U"][1:ny] = row
+    st["V"][:] = row
+    st["Phi"][1:ny] = row
+    st["ps"][1:ny] = 1e5 + 10.0 * row
+    return o, st, lam, alt
+
+
+def test_filter_bands_and_simplified_filter():
+    """Sec. III-B, Table IV: rows equatorward of 38 deg lose exactly their 2-dlam wave (the simplified
+    filter) and keep every other zonal wave; rows poleward of 70 deg and the pole rows are untouched."""
+    nx, ny = 64, 32
+    o, st, lam, alt = _filter_case(nx, ny)
+    out = o.filter(st)
+    smooth = 3.0 + 0.7 * np.cos(3 * lam)
+    for key, rows, vrow in (("U", range(1, ny), False), ("V", range(ny), True), ("Phi", range(1, ny), False)):
+        for j in rows:
+            lat = abs(_lat(ny, j, vrow))
+            for k in range(2):
+                got = out[key][j, k]
+                if lat < 38:
+                    np.testing.assert_allclose(got, smooth, rtol=0, atol=1e-14)
+                elif lat > 70:
+                    assert np.array_equal(got, st[key][j, k])
+    for j in range(1, ny):
+        if abs(_lat(ny, j)) < 38:
+            np.testing.assert_allclose(out["ps"][j], 1e5 + 10 * smooth, rtol=0, atol=1e-9)
+    for key in ("Phi", "ps", "U"):
+        assert np.array_equal(out[key][0], st[key][0]) and np.array_equal(out[key][-1], st[key][-1])
+
+
+def test_filter_three_point_operator():
+    """Sec. III-B, Table IV: between 38 and 70 deg the filter is a symmetric 3-point operator
+    F + r (F_{x-1} - 2 F + F_{x+1}) (checked by its impulse response), which keeps constants and the
+    row sum, and which scales the 2-dlam wave by the ratio of the row's zonal spacing to the spacing at
+    38 deg, cos(lat) / cos(38 deg); every other wave m is then scaled by 1 - 4 r sin^2(m dlam / 2)."""
+    nx, ny = 64, 32
+    o = oracle.Oracle(nx, ny, 1)
+    lam = np.arange(nx) * 2 * math.pi / nx
+    seen = 0
+    for j in range(1, ny):
+        lat = abs(_lat(ny, j))
+        if not (38 <= lat <= 70):
+            continue
+        seen += 1
+        st = o.zeros()
+        st["Phi"][j, 0, 5] = 1.0                       # impulse
+        st["Phi"][j, 0, 40] = 1.0
+        imp = o.filter(st)["Phi"][j, 0]
+        r = imp[4]
+        assert imp[6] == r and imp[39] == r and imp[41] == r and abs(imp[5] - (1 - 2 * r)) < 1e-15
+        assert np.count_nonzero(imp) == 6
+        assert abs(imp.sum() - 2.0) < 1e-14
+        st = o.zeros()
+        st["Phi"][j, 0] = (-1.0) ** np.arange(nx)
+        fac = o.filter(st)["Phi"][j, 0] / st["Phi"][j, 0]
+        want = math.cos(math.radians(lat)) / math.cos(math.radians(38.0))
+        np.testing.assert_allclose(fac, want, rtol=0, atol=1e-14)
+        st["Phi"][j, 0] = 2.0 + np.cos(5 * lam)
+        got = o.filter(st)["Phi"][j, 0]
+        want5 = 2.0 + (1 - (1 - want) * math.sin(5 * math.pi / nx) ** 2) * np.cos(5 * lam)
+        np.testing.assert_allclose(got, want5, rtol=0, atol=1e-14)
+    assert seen >= 8
+
+
+def test_filters_conserve_mass_c1():
+    """Both filters keep each row's zonal sum, so the flux-form mass stays conserved: <= 1e-13 over
+    C1's 20 steps with the filters applied after every step (and they do act: the state differs)."""
+    cfg = synth.CONFIGS["c1"]
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"], filters=True)
+    m0, _ = o.diagnostics(st)
+    s = o.step(st, cfg.steps, cfg.dt)
+    m1, _ = o.diagnostics(s)
+    assert abs(m1 - m0) / m0 <= 1e-13
+    plain = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).step(st, 1, cfg.dt)
+    filt = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"], filters=True).step(st, 1, cfg.dt)
+    assert np.abs(plain["V"] - filt["V"]).max() > 1e-6
+
+
+def test_filters_adjoint_dot():
+    """With the filters on, the hand-written adjoint of the step passes the dot test against the
+    complex-step tangent-linear (each row filter is symmetric, so its transpose is itself)."""
+    cfg = small_cfg(32, 16, 3, degree=4)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(32, 16, 3, phis=st["phis"], filters=True)
+    x = synth.random_like(st, 81)
+    y = synth.random_like(st, 82)
+    jx = o.tl_step(st, x, cfg.dt)
+    jty = o.adj_step(st, y, cfg.dt)
+    lhs, rhs = oracle.dot(jx, y), oracle.dot(x, jty)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
