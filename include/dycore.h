@@ -47,7 +47,13 @@ typedef enum {
 typedef enum { DYCORE_FP32 = 0, DYCORE_FP64 = 1 } dycore_precision;
 
 enum {
-  DYCORE_FORWARD_ONLY = 1u  /* do not reserve adjoint workspace at create */
+  DYCORE_FORWARD_ONLY = 1u,   /* do not reserve adjoint workspace at create */
+  DYCORE_LOWLAT_FILTERS = 2u  /* close every outer step with the low-latitude filters the leap format
+                                 keeps (Sec. III-B, Table IV rows 1-2): below 38 degrees the
+                                 simplified filter removes the 2-dlam wave of each zonal row, from 38
+                                 to 70 degrees the 3-point operator F + r (F_{x-1} - 2F + F_{x+1})
+                                 with r = (1 - cos(lat)/cos 38deg)/4; on U, V, Phi and p_s, pole rows
+                                 untouched.  Needs an even nx (EINVAL otherwise). */
 };
 
 typedef struct {
@@ -62,7 +68,7 @@ typedef struct {
   const double* phis;      /* host, (ny+1)*nx surface geopotential (m^2/s^2), copied; NULL = flat */
   double a, omega, g, rd, cp, p0, t0;  /* constants; 0 selects 6.371e6, 7.292e-5, 9.80616,
                                           287.04, 1004.64, 1e5, 300 */
-  unsigned flags;          /* DYCORE_FORWARD_ONLY */
+  unsigned flags;          /* DYCORE_FORWARD_ONLY | DYCORE_LOWLAT_FILTERS */
   int block;               /* threads per row workgroup (64..1024, multiple of 64); 0 = tuned default */
 } dycore_config;
 

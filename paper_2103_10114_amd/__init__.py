@@ -19,6 +19,7 @@ _lib = None
 
 DYCORE_FP32, DYCORE_FP64 = 0, 1
 DYCORE_FORWARD_ONLY = 1
+DYCORE_LOWLAT_FILTERS = 2
 KEYS = ("U", "V", "Phi", "ps")
 
 
@@ -96,7 +97,7 @@ class Dycore:
     """One grid (nx longitudes, ny latitude intervals, nz levels) and time step dt."""
 
     def __init__(self, nx, ny, nz, dt, prec="fp32", phis=None, msub=0, block=0, forward_only=False,
-                 sigma_half=None):
+                 sigma_half=None, filters=False):
         import numpy as np
         import torch
         self.nx, self.ny, self.nz, self.dt = nx, ny, nz, float(dt)
@@ -111,7 +112,7 @@ class Dycore:
         dp = ctypes.POINTER(ctypes.c_double)
         c.phis = self._phis.ctypes.data_as(dp) if self._phis is not None else None
         c.sigma_half = self._sig.ctypes.data_as(dp) if self._sig is not None else None
-        c.flags = DYCORE_FORWARD_ONLY if forward_only else 0
+        c.flags = (DYCORE_FORWARD_ONLY if forward_only else 0) | (DYCORE_LOWLAT_FILTERS if filters else 0)
         c.block = int(block)
         h = ctypes.c_void_p()
         _check(lib().dycore_create(ctypes.byref(c), ctypes.byref(h)))

@@ -1777,6 +1777,8 @@ int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s)
       if (e == hipSuccess) e = launch_axpy_fill<double>(pole, pole + 3 * ps, ps, s);
     } else if (e == hipSuccess && out.U) {
       e = launch_stage<T>(mk(h, y2, out, pole + 2 * ps, pole + 3 * ps), v.block, s);
+      // the low-latitude filters close the step, as in dycore_step
+      if (e == hipSuccess) e = launch_lowlat<T>(v.g, v.filt, v.nfilt, out.U, out.V, out.F, out.P, s);
     }
     if (e != hipSuccess) return DYCORE_EHIP;
   }
@@ -1794,7 +1796,10 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
   St4<T> l2 = state_at<T>(v, base + L.lam_off + L.state);
   double* pole = reinterpret_cast<double*>(base + L.pole_off);
   const size_t ps = 2 * (v.g.nz + 1);
-  hipError_t e;
+  // the low-latitude filters act last in the step and each row operator is symmetric, so the sweep
+  // starts with the same filters applied to lam
+  hipError_t e = launch_lowlat<T>(v.g, v.filt, v.nfilt, lam.U, lam.V, lam.F, lam.P, s);
+  if (e != hipSuccess) return DYCORE_EHIP;
   // reverse sweep.  lam accumulates the adjoint of the RK step's input: every stage adds the base
   // transpose of its output adjoint to it; the last stage's share is lam itself with the base
   // transpose applied in place once that stage has read it.

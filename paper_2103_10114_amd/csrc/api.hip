@@ -73,6 +73,8 @@ struct dycore_s {
   size_t adj_bytes = 0;
   AatItem* aat = nullptr;       // work items of the tiled adaptation-stage adjoint (device)
   int aat_n = 0, aat_block = 0;
+  FiltItem* filt = nullptr;     // rows of the low-latitude filters (device), when enabled
+  int nfilt = 0;
   size_t bytes = 0;
 };
 
@@ -127,6 +129,34 @@ int leap_span(double sin_theta, double dlam, int nx) {
   if ((cap & 1) == 0) --cap;
   if (cap < 1) cap = 1;
   return std::min(m, cap);
+}
+
+// Rows the low-latitude filters act on (Sec. III-B, Table IV rows 1-2).  The latitude of scalar
+// and U row j is 90 (ny - 2j) / ny degrees, of V row j 90 (ny - 2j - 1) / ny; the band edges are
+// decided on those integers: below 38 degrees the simplified filter (r = -1), from 38 to 70 the
+// 3-point operator with r = (1 - cos(lat) / cos 38deg) / 4 (rows where it vanishes are skipped),
+// poleward of 70 nothing.
+std::vector<FiltItem> filter_items(int ny) {
+  auto coef = [&](int num) {
+    const int m = num < 0 ? -num : num;
+    if (m * 90 < 38 * ny) return -1.0;
+    if (m * 90 > 70 * ny) return 0.0;
+    const double lat = 90.0 * m / ny * (M_PI / 180.0);
+    return 0.25 * (1.0 - std::cos(lat) / std::cos(38.0 * M_PI / 180.0));
+  };
+  std::vector<FiltItem> out;
+  for (int j = 1; j < ny; ++j) {
+    const double r = coef(ny - 2 * j);
+    if (r == 0.0) continue;
+    out.push_back(FiltItem{0, j, r});
+    out.push_back(FiltItem{2, j, r});
+    out.push_back(FiltItem{3, j, r});
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double r = coef(ny - 2 * j - 1);
+    if (r != 0.0) out.push_back(FiltItem{1, j, r});
+  }
+  return out;
 }
 
 // Work items of the tiled adaptation-stage adjoint (AatItem) for a block of `block` threads: every
@@ -246,12 +276,16 @@ int step_impl(dycore_s* h, T* U, T* V, T* F, T* P, int nsteps, hipStream_t s) {
   hipError_t e = launch_pole_prep<T>(h->g, F, P, pole_slot(h, 0), s);
   if (e != hipSuccess) return DYCORE_EHIP;
   const int nrk = h->msub + 1;
-  for (int n = 0; n < nsteps; ++n)
+  for (int n = 0; n < nsteps; ++n) {
     for (int rk = 0; rk < nrk; ++rk)
       for (int r = 0; r < 3; ++r) {
         e = launch_stage<T>(step_stage_args<T>(h, rk, r, U, V, F, P), h->block, s);
         if (e != hipSuccess) return DYCORE_EHIP;
       }
+    // the low-latitude filters close the step (they leave the pole rows and their slot alone)
+    e = launch_lowlat<T>(h->g, h->filt, h->nfilt, U, V, F, P, s);
+    if (e != hipSuccess) return DYCORE_EHIP;
+  }
   return DYCORE_OK;
 }
 
@@ -325,6 +359,8 @@ int validate_cfg(const dycore_config* c) {
   // a given sub-step count must keep the adaptation sub-step within the CFL bound of the
   // gravity-wave speed: w_max dt / M <= 0.8 sqrt 3 (the count chosen when M = 0)
   if (c->n_adapt_substeps > 0 && cfl_substeps(c) > c->n_adapt_substeps) return DYCORE_EINVAL;
+  // the simplified filter removes the 2-dlam wave, which needs an even number of columns
+  if ((c->flags & DYCORE_LOWLAT_FILTERS) && (c->nx % 2) != 0) return DYCORE_EINVAL;
   if (c->sigma_half) {
     if (c->sigma_half[0] != 0.0 || c->sigma_half[c->nz] != 1.0) return DYCORE_EINVAL;
     for (int k = 0; k < c->nz; ++k)
@@ -355,6 +391,8 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.aat = h->aat;
   v.aat_n = h->aat_n;
   v.aat_block = h->aat_block;
+  v.filt = h->filt;
+  v.nfilt = h->nfilt;
   return v;
 }
 
@@ -516,6 +554,14 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       }
     }
   }
+  if (ok && (h->flags & DYCORE_LOWLAT_FILTERS)) {
+    const std::vector<FiltItem> fi = filter_items(ny);
+    if (!fi.empty()) {
+      ok = hipMalloc((void**)&h->filt, sizeof(FiltItem) * fi.size()) == hipSuccess;
+      ok = ok && hipMemcpy(h->filt, fi.data(), sizeof(FiltItem) * fi.size(), hipMemcpyHostToDevice) == hipSuccess;
+      if (ok) h->nfilt = (int)fi.size();
+    }
+  }
   if (!ok) { dycore_destroy(h); return DYCORE_ENOMEM; }
   h->bytes += 2 * h->state_bytes + sizeof(double) * (kPoleSlots * 2 * (nz + 1) + 3 * (ny + 1) + 2) + 8 + h->adj_bytes;
   *out = h;
@@ -574,6 +620,7 @@ int dycore_destroy(dycore_t h) {
   if (h->count) (void)hipFree(h->count);
   if (h->adj) (void)hipFree(h->adj);
   if (h->aat) (void)hipFree(h->aat);
+  if (h->filt) (void)hipFree(h->filt);
   release_timer(h);
   delete h;
   return DYCORE_OK;
@@ -780,12 +827,19 @@ int batch_step(dycore_batch_s* b, int nsteps, hipStream_t s) {
                      b->n);
   if (hipGetLastError() != hipSuccess) return DYCORE_EHIP;
   const StageArgs<T>* args = static_cast<const StageArgs<T>*>(b->d_args);
-  for (int n = 0; n < nsteps; ++n)
+  for (int n = 0; n < nsteps; ++n) {
     for (int sidx = 0; sidx < b->nstage_max; ++sidx) {
       hipError_t e = launch_stage_batch<T>(args + (size_t)sidx * b->n, b->d_items, b->nitems, b->grid, b->block,
                                            b->max_nx, b->lds, b->pipe, s);
       if (e != hipSuccess) return DYCORE_EHIP;
     }
+    for (int m = 0; m < b->n; ++m) {   // members with the low-latitude filters close their step
+      const dycore_s* h = b->hs[m];
+      if (launch_lowlat<T>(h->g, h->filt, h->nfilt, (T*)b->U[m], (T*)b->V[m], (T*)b->F[m], (T*)b->P[m], s) !=
+          hipSuccess)
+        return DYCORE_EHIP;
+    }
+  }
   return DYCORE_OK;
 }
 

@@ -84,6 +84,13 @@ struct AdjArgs {
   double* wpole;       // pole scratch, 64*(nz+1) doubles
 };
 
+// One zonal row the low-latitude filters act on: field 0 U, 1 V, 2 Phi, 3 p_s; row j; r < 0 for the
+// simplified filter (removes the 2-dlam wave), r > 0 for the 3-point operator's coefficient.
+struct FiltItem {
+  int field, j;
+  double r;
+};
+
 // Launch helpers implemented in the kernel translation units.
 template <typename T>
 hipError_t launch_pole_prep(const GeoDev& g, const T* F, const T* ps, double* pole, hipStream_t s);
@@ -101,6 +108,10 @@ hipError_t launch_diag(const GeoDev& g, const T* U, const T* V, const T* F, cons
                        double* partial, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_nonfinite(const T* x, size_t n, unsigned long long* count, hipStream_t s);
+// The low-latitude filters on the rows of `items` (every level of the 3D fields), in place.
+template <typename T>
+hipError_t launch_lowlat(const GeoDev& g, const FiltItem* items, int nitems, T* U, T* V, T* F, T* P,
+                         hipStream_t s);
 template <typename T>
 hipError_t launch_axpy_fill(T* dst, const T* src, size_t n, hipStream_t s);   // dst = src (copy) via kernel
 template <typename T>
@@ -181,6 +192,8 @@ struct HandleView {
   const AatItem* aat;   // tiled adaptation-adjoint work items (device), or NULL when rows do not fit
   int aat_n;            // item count (a multiple of 8)
   int aat_block;        // threads per tile workgroup
+  const FiltItem* filt; // rows of the low-latitude filters (device), NULL when they are off
+  int nfilt;
 };
 HandleView view_of(const dycore_s* h);
 

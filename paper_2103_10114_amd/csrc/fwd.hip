@@ -1524,6 +1524,40 @@ __global__ void __launch_bounds__(256) k_diag(GeoDev g, const T* U, const T* V, 
   }
 }
 
+// The low-latitude filters (Sec. III-B, Table IV rows 1-2), one zonal row of one level per block,
+// in place: the row is read into LDS in FP64, then either the 2-dlam wave is removed (the amplitude
+// (1/nx) sum_x (-1)^x F_x is summed in FP64 in a fixed order: strided per-thread sums, a butterfly
+// per wavefront, the wavefronts in order) or the 3-point operator F + r (F_{x-1} - 2 F + F_{x+1})
+// is applied; results are rounded once to the field precision.
+template <typename T>
+__global__ void __launch_bounds__(256) k_lowlat(int nx, int nz, const FiltItem* items, T* U, T* V, T* F, T* P) {
+  extern __shared__ double frow[];
+  __shared__ double red[4];
+  const FiltItem it = items[blockIdx.y];
+  const int k = blockIdx.x;
+  if (it.field == 3 && k > 0) return;
+  T* base = it.field == 0 ? U : (it.field == 1 ? V : (it.field == 2 ? F : P));
+  T* row = base + (it.field == 3 ? (size_t)it.j * nx : ((size_t)it.j * nz + k) * nx);
+  const int t = threadIdx.x;
+  for (int i = t; i < nx; i += 256) frow[i] = (double)row[i];
+  __syncthreads();
+  if (it.r < 0.0) {
+    double part = 0;
+    for (int i = t; i < nx; i += 256) part += (i & 1) ? -frow[i] : frow[i];
+    part = wave_sum(part);
+    if ((t & 63) == 0) red[t >> 6] = part;
+    __syncthreads();
+    const double A = (((red[0] + red[1]) + red[2]) + red[3]) / (double)nx;
+    for (int i = t; i < nx; i += 256) row[i] = (T)(frow[i] - ((i & 1) ? -A : A));
+  } else {
+    const double r = it.r;
+    for (int i = t; i < nx; i += 256) {
+      const double fm = frow[i == 0 ? nx - 1 : i - 1], fp = frow[i == nx - 1 ? 0 : i + 1];
+      row[i] = (T)(frow[i] + r * (fm - 2.0 * frow[i] + fp));
+    }
+  }
+}
+
 // Global sums of the per-row partials of k_diag, in a fixed order (each lane adds its rows in
 // ascending order, then a fixed butterfly; lane 0's result is written), so a result never depends
 // on timing.  out[0] = mass, out[1] = (p0/2g) sum w dsig (U^2 + V^2 + Phi^2) + (R T0 p0/2g) sum w q^2.
@@ -1666,6 +1700,15 @@ hipError_t launch_diag(const GeoDev& g, const T* U, const T* V, const T* F, cons
 }
 
 template <typename T>
+hipError_t launch_lowlat(const GeoDev& g, const FiltItem* items, int nitems, T* U, T* V, T* F, T* P,
+                         hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_lowlat<T>), dim3(g.nz, nitems), dim3(256), sizeof(double) * g.nx, s, g.nx, g.nz, items,
+                     U, V, F, P);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_nonfinite(const T* x, size_t n, unsigned long long* count, hipStream_t s) {
   hipLaunchKernelGGL((k_nonfinite<T>), dim3(1024), dim3(256), 0, s, x, n, count);
   return hipGetLastError();
@@ -1691,6 +1734,7 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s) {
   template hipError_t launch_diag<T>(const GeoDev&, const T*, const T*, const T*, const T*, double*, double*, \
                                      hipStream_t);                                                           \
   template hipError_t launch_nonfinite<T>(const T*, size_t, unsigned long long*, hipStream_t);               \
+  template hipError_t launch_lowlat<T>(const GeoDev&, const FiltItem*, int, T*, T*, T*, T*, hipStream_t);   \
   template hipError_t launch_axpy_fill<T>(T*, const T*, size_t, hipStream_t);                                \
   template hipError_t launch_zero<T>(T*, size_t, hipStream_t);
 DYC_INST(float)

@@ -85,3 +85,18 @@ def test_substeps_below_cfl_refused_without_gpu(msub, ok):
         assert rc != -1
         if rc == 0:
             L.dycore_destroy(h)
+
+
+def test_filters_need_even_nx_without_gpu():
+    """The simplified filter removes the 2-dlam wave, so DYCORE_LOWLAT_FILTERS with an odd nx is an
+    argument error, reported before any device call."""
+    if not os.path.exists(LIB):
+        pytest.skip("libdycore.so not built")
+    from paper_2103_10114_amd import _Config, DYCORE_LOWLAT_FILTERS
+    L = ctypes.CDLL(LIB)
+    cfg = _Config()
+    cfg.nx, cfg.ny, cfg.nz, cfg.dt, cfg.prec = 129, 64, 3, 600.0, 1
+    cfg.flags = DYCORE_LOWLAT_FILTERS
+    h = ctypes.c_void_p()
+    assert L.dycore_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert not h.value
