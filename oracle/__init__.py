@@ -59,7 +59,7 @@ def _p(a):
 class Oracle:
     """One grid: nx longitudes, ny latitude intervals (ny+1 scalar rows incl. poles), nz levels."""
 
-    def __init__(self, nx, ny, nz, phis=None, sigma_half=None, consts=None, filters=False):
+    def __init__(self, nx, ny, nz, phis=None, sigma_half=None, consts=None, filters=False, kstar=0.0):
         self.nx, self.ny, self.nz = nx, ny, nz
         L = _load()
         self._phis = None if phis is None else np.ascontiguousarray(phis, dtype=np.float64)
@@ -70,6 +70,7 @@ class Oracle:
             raise ValueError("bad grid")
         self.L = L
         L.orc_set_filters(ctypes.c_void_p(self.h), 1 if filters else 0)
+        L.orc_set_kstar(ctypes.c_void_p(self.h), ctypes.c_double(kstar))
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -50,6 +50,7 @@ struct Geo {
   std::vector<double> sigh, sig, dsig, cl, cpk;
   std::vector<double> phis;             // (ny+1)*nx, pole rows replaced by their mean
   int filters = 0;                      // low-latitude filters after each outer step (Table IV rows 1-2)
+  double kstar = 0.0;                   // p_s diffusion coefficient kappa* of eq. 1 (m^2/s)
 };
 
 // eq. 7 with res = dlam and cos(90deg - theta) = sin(theta); the result is
@@ -302,6 +303,34 @@ void tend_A(const Geo& g, const St<T>& y, const Work<T>& w, St<T>& t) {
   // p_s: -p0 * Pi
   for (int j = 0; j <= ny; ++j)
     for (int i = 0; i < nx; ++i) t.ps[z.i2(j, i)] = -g.p0 * w.S[z.ih(j, nz, i)];
+  // p_s diffusion kappa* D_sa (eq. 1, p_s line): the horizontal Laplacian of p_s in flux form on
+  // the C grid, zonally the leaped difference of the leaped difference, (F_{i+M} - 2 F_i + F_{i-M})
+  // / (M dx)^2; meridionally the divergence of the face gradients; at a pole the outward gradient
+  // flux through the cap edge over the cap area
+  if (g.kstar != 0.0) {
+    for (int j = 1; j < ny; ++j) {
+      const int M = g.M[j];
+      const double dx = M * a * g.s[j] * g.dlam;
+      const double dy2 = a * a * g.s[j] * g.dth * g.dth;
+      for (int i = 0; i < nx; ++i) {
+        const T zon = (w.pse[z.i2(j, i + M)] - 2.0 * w.pse[z.i2(j, i)] + w.pse[z.i2(j, i - M)]) / (dx * dx);
+        const T mer = (g.sv[j] * (w.pse[z.i2(j + 1, i)] - w.pse[z.i2(j, i)]) -
+                       g.sv[j - 1] * (w.pse[z.i2(j, i)] - w.pse[z.i2(j - 1, i)])) / dy2;
+        t.ps[z.i2(j, i)] += g.kstar * (zon + mer);
+      }
+    }
+    T fn(0), fs(0);
+    for (int i = 0; i < nx; ++i) {
+      fn += w.pse[z.i2(1, i)] - w.pse[z.i2(0, i)];
+      fs += w.pse[z.i2(ny - 1, i)] - w.pse[z.i2(ny, i)];
+    }
+    const T dn = g.sv[0] * g.dlam / (g.acap * g.dth) * fn;
+    const T ds = g.sv[ny - 1] * g.dlam / (g.acap * g.dth) * fs;
+    for (int i = 0; i < nx; ++i) {
+      t.ps[z.i2(0, i)] += g.kstar * dn;
+      t.ps[z.i2(ny, i)] += g.kstar * ds;
+    }
+  }
 
   // U: -P^U [d+ phi' + R T0 d+ q + <RT'>^x d+ l] - f* <<V>>, leap pattern (x+1,x) -> (x+N, x-N+1)
 #pragma omp parallel for
@@ -851,6 +880,35 @@ void adj_tend_A(const Geo& g, const St<double>& y, const Work<double>& w, const 
   // p_s tendency
   for (int j = 0; j <= ny; ++j)
     for (int i = 0; i < nx; ++i) b.S[z.ih(j, nz, i)] += -g.p0 * at.ps[z.i2(j, i)];
+  // p_s diffusion (transpose of the flux-form Laplacian, into the pole-read p_s)
+  if (g.kstar != 0.0) {
+    for (int j = 1; j < ny; ++j) {
+      const int M = g.M[j];
+      const double dx = M * a * g.s[j] * g.dlam;
+      const double dy2 = a * a * g.s[j] * g.dth * g.dth;
+      for (int i = 0; i < nx; ++i) {
+        const double c = g.kstar * at.ps[z.i2(j, i)];
+        b.pse[z.i2(j, i + M)] += c / (dx * dx);
+        b.pse[z.i2(j, i - M)] += c / (dx * dx);
+        b.pse[z.i2(j, i)] -= 2.0 * c / (dx * dx);
+        b.pse[z.i2(j + 1, i)] += c * g.sv[j] / dy2;
+        b.pse[z.i2(j, i)] -= c * (g.sv[j] + g.sv[j - 1]) / dy2;
+        b.pse[z.i2(j - 1, i)] += c * g.sv[j - 1] / dy2;
+      }
+    }
+    double an = 0, as = 0;
+    for (int i = 0; i < nx; ++i) {
+      an += g.kstar * at.ps[z.i2(0, i)];
+      as += g.kstar * at.ps[z.i2(ny, i)];
+    }
+    const double cn = g.sv[0] * g.dlam / (g.acap * g.dth), cs = g.sv[ny - 1] * g.dlam / (g.acap * g.dth);
+    for (int i = 0; i < nx; ++i) {
+      b.pse[z.i2(1, i)] += cn * an;
+      b.pse[z.i2(0, i)] -= cn * an;
+      b.pse[z.i2(ny - 1, i)] += cs * as;
+      b.pse[z.i2(ny, i)] -= cs * as;
+    }
+  }
   // Phi tendency
   for (int j = 0; j <= ny; ++j)
     for (int k = 0; k < nz; ++k)
@@ -1423,6 +1481,9 @@ void orc_diagnostics(void* h, const double* U, const double* V, const double* F,
 
 // Low-latitude filters on (step) or off; the state filter alone, in place.
 void orc_set_filters(void* h, int on) { static_cast<Geo*>(h)->filters = on ? 1 : 0; }
+
+// p_s diffusion coefficient kappa* of eq. 1 (m^2/s; 0 = off).
+void orc_set_kstar(void* h, double kstar) { static_cast<Geo*>(h)->kstar = kstar; }
 
 void orc_filter(void* h, double* U, double* V, double* F, double* ps) {
   const Geo& g = *static_cast<Geo*>(h);

@@ -729,3 +729,98 @@ def test_filters_adjoint_dot():
     jty = o.adj_step(st, y, cfg.dt)
     lhs, rhs = oracle.dot(jx, y), oracle.dot(x, jty)
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ----------------------------------------------------------------------------- p_s diffusion (kappa*)
+def _rest_ps(o, ps):
+    st = o.zeros()
+    st["ps"] = np.array(ps, dtype=np.float64)
+    return st
+
+
+def test_ps_diffusion_zonal_symbol():
+    """eq. 1's kappa* D_sa at rest (no winds, flat terrain, so -p0 Pi = 0): on a row whose span is M,
+    a zonal p_s wave cos(m lam) gives kappa* (-4 sin^2(m M dlam / 2) / (M dx)^2) cos(m lam) from the
+    leaped second difference, plus the meridional part of a zonally uniform row pattern (zero here)."""
+    nx, ny = 96, 48
+    o = oracle.Oracle(nx, ny, 2, kstar=3e5)
+    c = o.constants()
+    M = o.leap_table()[0]
+    lam = np.arange(nx) * 2 * math.pi / nx
+    for j, m in [(2, 3), (5, 4), (24, 7)]:
+        ps = np.full((ny + 1, nx), 1e5)
+        ps[j] += 50.0 * np.cos(m * lam)
+        t = o.tendency(_rest_ps(o, ps), "A")["ps"][j]
+        dx = M[j] * c["a"] * math.sin(j * math.pi / ny) * 2 * math.pi / nx
+        zon = -4 * math.sin(m * M[j] * math.pi / nx) ** 2 / dx ** 2 * 50.0 * np.cos(m * lam)
+        dy2 = c["a"] ** 2 * math.sin(j * math.pi / ny) * (math.pi / ny) ** 2
+        sv = [math.sin((jj + 0.5) * math.pi / ny) for jj in (j - 1, j)]
+        mer = -(sv[0] + sv[1]) / dy2 * 50.0 * np.cos(m * lam)   # the neighbours rows hold the mean
+        np.testing.assert_allclose(t, 3e5 * (zon + mer), rtol=0, atol=1e-12 * np.abs(3e5 * (zon + mer)).max())
+
+
+def test_ps_diffusion_converges_to_laplacian():
+    """The flux-form D_sa converges at order 2 to the spherical Laplacian: for p_s = p0 (1 + e Y) with
+    Y = sin(theta) cos(theta) cos(lam) = x z / r^2 (a degree-2 spherical harmonic, Laplacian -6/a^2 Y) on rows
+    within 60 degrees of the equator (the leap span of each row is fixed as the grid refines)."""
+    errs = []
+    for ny in (48, 96, 192):
+        nx = 2 * ny
+        o = oracle.Oracle(nx, ny, 1, kstar=1.0)
+        a = o.constants()["a"]
+        th = np.arange(ny + 1) * math.pi / ny
+        lam = np.arange(nx) * 2 * math.pi / nx
+        Y = (np.sin(th) * np.cos(th))[:, None] * np.cos(lam)[None, :]
+        ps = 1e5 * (1 + 1e-3 * Y)
+        t = o.tendency(_rest_ps(o, ps), "A")["ps"]
+        exact = -6.0 / a ** 2 * 1e5 * 1e-3 * Y
+        rows = np.abs(90 - np.degrees(th)) <= 60
+        errs.append(np.abs(t[rows] - exact[rows]).max() / np.abs(exact[rows]).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.8 < r < 2.3 for r in rates), (errs, rates)
+
+
+def test_ps_diffusion_conserves_mass():
+    """The flux form telescopes: the area-weighted sum of kappa* D_sa over the sphere (caps included)
+    vanishes, and the global mass stays conserved over C1's steps with kappa* = 2e5 m^2/s (which
+    changes the state)."""
+    cfg = synth.CONFIGS["c1"]
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"], kstar=2e5)
+    rest = dict(st)
+    rest["U"] = np.zeros_like(st["U"])
+    rest["V"] = np.zeros_like(st["V"])
+    t = o.tendency(rest, "A")["ps"]
+    c = o.constants()
+    ny, nx = cfg.ny, cfg.nx
+    th = np.arange(ny + 1) * math.pi / ny
+    w = c["a"] ** 2 * np.sin(th) * (math.pi / ny) * (2 * math.pi / nx)
+    tot = (w[1:ny, None] * t[1:ny]).sum() + c["acap"] * (t[0, 0] + t[ny, 0])
+    scale = (w[1:ny, None] * np.abs(t[1:ny])).sum()
+    assert abs(tot) < 1e-13 * scale and scale > 0
+    m0, _ = o.diagnostics(st)
+    s = o.step(st, 10, cfg.dt)
+    m1, _ = o.diagnostics(s)
+    assert abs(m1 - m0) / m0 <= 1e-13
+    s0 = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).step(st, 1, cfg.dt)
+    s1 = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"], kstar=2e5).step(st, 1, cfg.dt)
+    assert np.abs(s0["ps"] - s1["ps"]).max() > 1e-3
+
+
+def test_ps_diffusion_adjoint_dot():
+    """With kappa* on, the hand-written adjoint (tendency and whole step) passes the dot test against
+    the complex-step tangent-linear."""
+    cfg = small_cfg(32, 16, 3, degree=4)
+    st = synth.make_state(cfg)
+    o = oracle.Oracle(32, 16, 3, phis=st["phis"], kstar=2e5)
+    x = synth.random_like(st, 83)
+    y = synth.random_like(st, 84)
+    for which in "AL":
+        jx = o.tl_tendency(st, x, which)
+        jty = o.adj_tendency(st, y, which)
+        lhs, rhs = oracle.dot(jx, y), oracle.dot(x, jty)
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs), which
+    jx = o.tl_step(st, x, cfg.dt)
+    jty = o.adj_step(st, y, cfg.dt)
+    lhs, rhs = oracle.dot(jx, y), oracle.dot(x, jty)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
