@@ -70,6 +70,9 @@ typedef struct {
                                           287.04, 1004.64, 1e5, 300 */
   unsigned flags;          /* DYCORE_FORWARD_ONLY | DYCORE_LOWLAT_FILTERS */
   int block;               /* threads per row workgroup (64..1024, multiple of 64); 0 = tuned default */
+  double kappa_star;       /* kappa* of eq. 1's p_s line (m^2/s, >= 0; 0 = off): the adaptation's p_s
+                              tendency gains kappa* D_sa, D_sa the flux-form horizontal Laplacian of
+                              p_s (leaped second difference zonally, cap fluxes at the poles) */
 } dycore_config;
 
 /* Create a handle: validates the config, builds the leap table (eq. 7; span made

@@ -33,7 +33,7 @@ class _Config(ctypes.Structure):
                 ("sigma_half", ctypes.POINTER(ctypes.c_double)), ("phis", ctypes.POINTER(ctypes.c_double)),
                 ("a", ctypes.c_double), ("omega", ctypes.c_double), ("g", ctypes.c_double),
                 ("rd", ctypes.c_double), ("cp", ctypes.c_double), ("p0", ctypes.c_double), ("t0", ctypes.c_double),
-                ("flags", ctypes.c_uint), ("block", ctypes.c_int)]
+                ("flags", ctypes.c_uint), ("block", ctypes.c_int), ("kappa_star", ctypes.c_double)]
 
 
 def lib():
@@ -97,7 +97,7 @@ class Dycore:
     """One grid (nx longitudes, ny latitude intervals, nz levels) and time step dt."""
 
     def __init__(self, nx, ny, nz, dt, prec="fp32", phis=None, msub=0, block=0, forward_only=False,
-                 sigma_half=None, filters=False):
+                 sigma_half=None, filters=False, kappa_star=0.0):
         import numpy as np
         import torch
         self.nx, self.ny, self.nz, self.dt = nx, ny, nz, float(dt)
@@ -114,6 +114,7 @@ class Dycore:
         c.sigma_half = self._sig.ctypes.data_as(dp) if self._sig is not None else None
         c.flags = (DYCORE_FORWARD_ONLY if forward_only else 0) | (DYCORE_LOWLAT_FILTERS if filters else 0)
         c.block = int(block)
+        c.kappa_star = float(kappa_star)
         h = ctypes.c_void_p()
         _check(lib().dycore_create(ctypes.byref(c), ctypes.byref(h)))
         self.h = h

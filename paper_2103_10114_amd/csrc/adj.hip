@@ -1041,6 +1041,41 @@ __global__ void k_t3(Ctx<T> c) {
   else c.s.APSR[i2] = aps;
 }
 
+// Transpose of the p_s diffusion kappa* D_sa (eq. 1, p_s line) of an adaptation stage, FP64, added
+// after k_t3: interior entries gather ch kappa* (D_sa^T a_out) directly into the input adjoint; the
+// pole rows add their share to the pole-read sums (APSR) that k_t4 spreads.  The pole outputs enter
+// through the FP64 sums of their replicated rows (PS_AOF, level nz).
+template <typename T>
+__global__ void k_dsa_adj(Ctx<T> c) {
+  const GeoDev& g = c.g;
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nx) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const C kc = c.ch * g.kstar;
+  const double* sF = c.s.psum + PS_AOF * 2 * (nz + 1);
+  const C SAn = sF[0 * (nz + 1) + nz], SAs = sF[1 * (nz + 1) + nz];   // sums of a_out over the pole rows
+  auto ao = [&](int jr, int ii) -> C { return (C)c.aoP[(size_t)jr * nx + ii]; };
+  auto dy2 = [&](int jr) -> C { return g.a * g.a * g.s[jr] * g.dth * g.dth; };
+  const C capN = g.sv[0] * g.dlam / (g.acap * g.dth), capS = g.sv[ny - 1] * g.dlam / (g.acap * g.dth);
+  const size_t i2 = (size_t)j * nx + i;
+  if (j >= 1 && j < ny) {
+    const int M = g.M[j];
+    const C dx = (C)M * g.a * g.s[j] * g.dlam;
+    C a = (ao(j, wrp(i + M, nx)) - 2.0 * ao(j, i) + ao(j, wrp(i - M, nx))) / (dx * dx);
+    a -= ao(j, i) * (g.sv[j] + g.sv[j - 1]) / dy2(j);
+    if (j + 1 < ny) a += ao(j + 1, i) * g.sv[j] / dy2(j + 1);
+    else a += SAs * capS;                 // the south cap's flux reads row ny-1
+    if (j - 1 > 0) a += ao(j - 1, i) * g.sv[j - 1] / dy2(j - 1);
+    else a += SAn * capN;                 // the north cap's flux reads row 1
+    c.aiP[i2] = (T)((C)c.aiP[i2] + kc * a);
+  } else if (j == 0) {
+    c.s.APSR[i2] += kc * (ao(1, i) * g.sv[0] / dy2(1) - SAn * capN);
+  } else {
+    c.s.APSR[i2] += kc * (ao(ny - 1, i) * g.sv[ny - 1] / dy2(ny - 1) - SAs * capS);
+  }
+}
+
 // pole rows: spread the FP64 row sums of the pole-copy adjoints over the stored row
 template <typename T>
 __global__ void k_t4(Ctx<T> c) {
@@ -1543,6 +1578,7 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     hipLaunchKernelGGL((k_a4<T>), g2, dim3(tb), 0, s, c);
   }
   hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
+  if (g.kstar != 0.0) hipLaunchKernelGGL((k_dsa_adj<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
   return hipGetLastError();
 }

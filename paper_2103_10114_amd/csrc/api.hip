@@ -361,6 +361,7 @@ int validate_cfg(const dycore_config* c) {
   if (c->n_adapt_substeps > 0 && cfl_substeps(c) > c->n_adapt_substeps) return DYCORE_EINVAL;
   // the simplified filter removes the 2-dlam wave, which needs an even number of columns
   if ((c->flags & DYCORE_LOWLAT_FILTERS) && (c->nx % 2) != 0) return DYCORE_EINVAL;
+  if (!(c->kappa_star >= 0.0) || !std::isfinite(c->kappa_star)) return DYCORE_EINVAL;
   if (c->sigma_half) {
     if (c->sigma_half[0] != 0.0 || c->sigma_half[c->nz] != 1.0) return DYCORE_EINVAL;
     for (int k = 0; k < c->nz; ++k)
@@ -443,6 +444,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   g.dlam = 2.0 * M_PI / nx;
   g.dth = M_PI / ny;
   g.acap = 2.0 * M_PI * g.a * g.a * (1.0 - std::cos(0.5 * g.dth));
+  g.kstar = cfg->kappa_star;
 
   // host tables
   std::vector<double> s(ny + 1, 0.0), cot(ny + 1, 0.0), f(ny + 1, 0.0);

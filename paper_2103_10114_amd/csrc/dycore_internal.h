@@ -13,6 +13,7 @@ namespace dyc {
 struct GeoDev {
   int nx, ny, nz;
   double a, omega, g, rd, cp, p0, t0, kappa, b, dlam, dth, acap, RT0;
+  double kstar;         // p_s diffusion coefficient kappa* (m^2/s), 0 = off
   const double* s;      // sin(theta_j), rows 0..ny
   const double* cot;    // cot(theta_j)
   const double* f;      // 2 Omega cos(theta_j)

@@ -39,6 +39,47 @@ using C = double;
 
 }  // namespace
 
+// kappa* D_sa of eq. 1's p_s line at column i of interior row j, from the stage input's stored p_s
+// (pole values read from their slot), FP64: the flux-form horizontal Laplacian, zonally the leaped
+// second difference (F_{i+M} - 2 F_i + F_{i-M}) / (M dx)^2, meridionally the difference of the face
+// gradients times sin(theta) at the faces over a^2 sin(theta_j) dtheta^2.
+template <typename T>
+__device__ __forceinline__ C ps_diffusion(const StageArgs<T>& A, int j, int i) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  auto ps = [&](int jr, int ii) -> C {
+    if (jr == 0) return A.pin[nz];
+    if (jr == ny) return A.pin[(nz + 1) + nz];
+    return (C)A.inP[(size_t)jr * nx + ii];
+  };
+  const int M = g.M[j];
+  const C dx = (C)M * g.a * g.s[j] * g.dlam;
+  const C dy2 = g.a * g.a * g.s[j] * g.dth * g.dth;
+  const C p0 = ps(j, i);
+  const C zon = (ps(j, wrp(i + M, nx)) - 2.0 * p0 + ps(j, wrp(i - M, nx))) / (dx * dx);
+  const C mer = (g.sv[j] * (ps(j + 1, i) - p0) - g.sv[j - 1] * (p0 - ps(j - 1, i))) / dy2;
+  return g.kstar * (zon + mer);
+}
+
+// kappa* D_sa at a pole: the outward gradient flux through the cap edge over the cap area,
+// sin(theta_1/2) dlam / (A_cap dtheta) sum_i (p_s(adjacent row, i) - p_pole), summed in FP64 in a
+// fixed order by wavefront 0 and returned to every thread (a workgroup-wide barrier inside).
+template <typename T>
+__device__ C ps_diffusion_pole(const StageArgs<T>& A, int j, double* red) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ja = (j == 0) ? 1 : ny - 1, jv = (j == 0) ? 0 : ny - 1;
+  const C pp = A.pin[(j == 0 ? 0 : nz + 1) + nz];
+  if (threadIdx.x < 64) {
+    C s = 0;
+    for (int i = threadIdx.x; i < nx; i += 64) s += (C)A.inP[(size_t)ja * nx + i] - pp;
+    s = wave_sum(s);
+    if (threadIdx.x == 0) red[0] = s;
+  }
+  __syncthreads();
+  return g.kstar * (g.sv[jv] * g.dlam / (g.acap * g.dth)) * red[0];
+}
+
 // Largest workgroup per columns-per-thread: bounds the VGPR budget so that the FP64 column
 // sums and one level's loads of every owned column stay in registers (768 threads: 170 VGPRs).
 constexpr int max_block(int ni) { return ni <= 2 ? 768 : 512; }
@@ -326,11 +367,14 @@ __device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* sme
       const int i = t + c * B;
       if (i < nx) {
         const size_t idx = (size_t)j * nx + i;
-        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c]));
+        const C dsa = g.kstar != 0.0 ? ps_diffusion(A, j, i) : 0.0;
+        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c] + dsa));
       }
     }
   } else {
-    const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp));
+    // the cap sums' LDS is free again after the level loop's last barrier
+    const C dsa = g.kstar != 0.0 ? ps_diffusion_pole(A, j, sCap) : 0.0;
+    const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp + dsa));
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;
@@ -670,11 +714,14 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
       const int i = t + c * B;
       if (i < nx) {
         const size_t idx = (size_t)j * nx + i;
-        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c]));
+        const C dsa = g.kstar != 0.0 ? ps_diffusion(A, j, i) : 0.0;
+        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c] + dsa));
       }
     }
   } else {
-    const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp));
+    // the cap sums' LDS is free again after the level loop's last barrier
+    const C dsa = g.kstar != 0.0 ? ps_diffusion_pole(A, j, sCap) : 0.0;
+    const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp + dsa));
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
       const int i = t + c * B;

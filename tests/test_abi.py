@@ -100,3 +100,17 @@ def test_filters_need_even_nx_without_gpu():
     h = ctypes.c_void_p()
     assert L.dycore_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
     assert not h.value
+
+
+@pytest.mark.parametrize("kstar", [-1.0, float("nan"), float("inf")])
+def test_bad_kappa_star_refused_without_gpu(kstar):
+    """A negative or non-finite p_s diffusion coefficient is an argument error."""
+    if not os.path.exists(LIB):
+        pytest.skip("libdycore.so not built")
+    from paper_2103_10114_amd import _Config
+    L = ctypes.CDLL(LIB)
+    cfg = _Config()
+    cfg.nx, cfg.ny, cfg.nz, cfg.dt, cfg.prec = 64, 32, 3, 600.0, 1
+    cfg.kappa_star = kstar
+    h = ctypes.c_void_p()
+    assert L.dycore_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
