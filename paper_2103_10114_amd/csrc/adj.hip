@@ -1803,6 +1803,10 @@ int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s)
       a.ch = chh;
       a.process = proc;
       a.pad = 0;
+      a.tiles = v.ftiles;
+      a.cap = v.cap;
+      a.ntiles = v.nftiles;
+      a.tblock = v.ftblock;
       return a;
     };
     e = launch_stage<T>(mk(h / 3.0, y, y1, pole, pole + ps), v.block, s);

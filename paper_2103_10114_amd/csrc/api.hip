@@ -75,6 +75,9 @@ struct dycore_s {
   int aat_n = 0, aat_block = 0;
   FiltItem* filt = nullptr;     // rows of the low-latitude filters (device), when enabled
   int nfilt = 0;
+  AatItem* ftiles = nullptr;    // zonal tiles of the forward adaptation stage (device), rows 0..ny
+  int nftiles = 0, ftblock = 0;
+  double* cap = nullptr;        // cap sums of the forward adaptation stage: [2 poles][2][nz]
   size_t bytes = 0;
 };
 
@@ -86,8 +89,12 @@ struct dycore_batch_s {
   int pipe;     // stage kernel form: 1 all members pipelined, 0 none, 2 mixed
   std::vector<dycore_t> hs;
   void* d_args = nullptr;       // nstage_max x n StageArgs
-  int2* d_items = nullptr;
+  int2* d_items = nullptr;      // advection rows (member, row)
   int nitems = 0;
+  int2* d_titems = nullptr;     // adaptation tiles (member, index into the member's tile table)
+  int ntitems = 0;
+  AatItem* d_tiles = nullptr;   // every member's tile table for the batch's block
+  int max_nz = 0;
   void* d_prep = nullptr;       // per member prep descriptors
   std::vector<void*> U, V, F, P;
 };
@@ -164,9 +171,11 @@ std::vector<FiltItem> filter_items(int ny) {
 // columns on each side fit the block.  Items are listed row by row, then spread so that item b
 // (which the hardware dispatches to XCD b mod 8) walks a contiguous eighth of that list.  Returns
 // false when some row's halo leaves fewer than 32 owned columns.
-bool aat_tiles(int nx, int ny, const std::vector<int>& M, int block, std::vector<AatItem>& out) {
+bool aat_tiles(int nx, int ny, const std::vector<int>& M, int block, std::vector<AatItem>& out, int j0 = 1,
+               int j1 = -1) {
+  if (j1 < 0) j1 = ny - 1;
   std::vector<AatItem> seq;
-  for (int j = 1; j < ny; ++j) {
+  for (int j = j0; j <= j1; ++j) {
     const int hl = (M[j] + 1) / 2 + 1;
     const int cap = block - 2 * hl;
     if (cap < 32) return false;
@@ -191,12 +200,14 @@ bool aat_tiles(int nx, int ny, const std::vector<int>& M, int block, std::vector
 // The block (a multiple of 64 up to kAatMaxBlock) whose tiles leave the fewest idle threads
 // (owned columns over launched threads; ties go to the larger block), and its items.  False when no
 // block fits the widest halo (the adjoint then uses its per-point kernels).
-bool aat_items(int nx, int ny, const std::vector<int>& M, std::vector<AatItem>& out, int& block) {
+bool aat_items(int nx, int ny, const std::vector<int>& M, std::vector<AatItem>& out, int& block, int j0 = 1,
+               int j1 = -1, int max_block = kAatMaxBlock) {
+  if (j1 < 0) j1 = ny - 1;
   double best = -1.0;
-  for (int b = 64; b <= kAatMaxBlock; b += 64) {
+  for (int b = 64; b <= max_block; b += 64) {
     std::vector<AatItem> items;
-    if (!aat_tiles(nx, ny, M, b, items)) continue;
-    const double util = (double)nx * (ny - 1) / ((double)items.size() * b);
+    if (!aat_tiles(nx, ny, M, b, items, j0, j1)) continue;
+    const double util = (double)nx * (j1 - j0 + 1) / ((double)items.size() * b);
     if (util >= best - 1e-12) {
       best = util;
       block = b;
@@ -229,6 +240,10 @@ StageArgs<T> make_args(const dycore_s* h, int process, double ch, const T* inU, 
   a.ch = ch;
   a.process = process;
   a.pad = 0;
+  a.tiles = h->ftiles;
+  a.cap = h->cap;
+  a.ntiles = h->nftiles;
+  a.tblock = h->ftblock;
   return a;
 }
 
@@ -394,6 +409,10 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.aat_block = h->aat_block;
   v.filt = h->filt;
   v.nfilt = h->nfilt;
+  v.ftiles = h->ftiles;
+  v.nftiles = h->nftiles;
+  v.ftblock = h->ftblock;
+  v.cap = h->cap;
   return v;
 }
 
@@ -540,6 +559,26 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   ok = ok && hipMalloc((void**)&h->pole, sizeof(double) * kPoleSlots * 2 * (nz + 1)) == hipSuccess;
   ok = ok && hipMalloc((void**)&h->diag, sizeof(double) * (3 * (ny + 1) + 2)) == hipSuccess;
   ok = ok && hipMalloc((void**)&h->count, sizeof(unsigned long long)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&h->cap, sizeof(double) * 4 * nz) == hipSuccess;
+  if (ok) {
+    // the forward adaptation stage covers every scalar row, the poles (span 1) included
+    std::vector<AatItem> ft;
+    int fblk = 0;
+    // blocks of at most 256 threads leave room for several workgroups per CU; grids whose polar
+    // halos need more take up to 1024 threads (FP64: 704, for the LDS)
+    const int fmax = h->prec == DYCORE_FP32 ? kFwdTileMaxBlock : 704;
+    if (!aat_items(nx, ny, h->M, ft, fblk, 0, ny, 256) && !aat_items(nx, ny, h->M, ft, fblk, 0, ny, fmax)) {
+      dycore_destroy(h);
+      return DYCORE_EUNSUPPORTED;
+    }
+    ok = hipMalloc((void**)&h->ftiles, sizeof(AatItem) * ft.size()) == hipSuccess;
+    ok = ok && hipMemcpy(h->ftiles, ft.data(), sizeof(AatItem) * ft.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) {
+      h->nftiles = (int)ft.size();
+      h->ftblock = fblk;
+      h->bytes += sizeof(AatItem) * ft.size() + sizeof(double) * 4 * nz;
+    }
+  }
   if (ok && !(h->flags & DYCORE_FORWARD_ONLY)) {
     h->adj_bytes = dyc_adjoint_workspace_bytes(h);
     ok = hipMalloc(&h->adj, h->adj_bytes) == hipSuccess;
@@ -623,6 +662,8 @@ int dycore_destroy(dycore_t h) {
   if (h->adj) (void)hipFree(h->adj);
   if (h->aat) (void)hipFree(h->aat);
   if (h->filt) (void)hipFree(h->filt);
+  if (h->ftiles) (void)hipFree(h->ftiles);
+  if (h->cap) (void)hipFree(h->cap);
   release_timer(h);
   delete h;
   return DYCORE_OK;
@@ -767,6 +808,21 @@ __global__ void k_prep_batch(const PrepDesc* d, int n) {
 template <typename T>
 int batch_build(dycore_batch_s* b) {
   const int n = b->n;
+  // every member's adaptation tiles for the batch's block, one table after the other
+  std::vector<AatItem> tiles;
+  std::vector<size_t> toff(n);
+  std::vector<int> tcount(n);
+  for (int m = 0; m < n; ++m) {
+    const dycore_s* h = b->hs[m];
+    std::vector<AatItem> t;
+    if (!aat_tiles(h->nx, h->ny, h->M, b->block, t, 0, h->ny)) return DYCORE_EUNSUPPORTED;
+    toff[m] = tiles.size();
+    tcount[m] = (int)t.size();
+    tiles.insert(tiles.end(), t.begin(), t.end());
+  }
+  if (hipMalloc((void**)&b->d_tiles, sizeof(AatItem) * tiles.size()) != hipSuccess) return DYCORE_ENOMEM;
+  if (hipMemcpy(b->d_tiles, tiles.data(), sizeof(AatItem) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return DYCORE_EHIP;
   std::vector<StageArgs<T>> args((size_t)b->nstage_max * n);
   for (int m = 0; m < n; ++m) {
     dycore_s* h = b->hs[m];
@@ -779,6 +835,9 @@ int batch_build(dycore_batch_s* b) {
       } else {
         a = make_args<T>(h, -1, 0.0, U, V, F, P, U, V, F, P, U, V, F, P, nullptr, nullptr, nullptr);
       }
+      a.tiles = b->d_tiles + toff[m];
+      a.ntiles = tcount[m];
+      a.tblock = b->block;
     }
   }
   if (hipMalloc(&b->d_args, sizeof(StageArgs<T>) * args.size()) != hipSuccess) return DYCORE_ENOMEM;
@@ -808,6 +867,15 @@ int batch_build(dycore_batch_s* b) {
     }
   }
   b->nitems = (int)items.size();
+  // adaptation tiles in the same member order; each table is a multiple of 8 long and XCD-ordered, so
+  // item w still runs on XCD w mod 8 in the persistent launch (whose grid is a multiple of 8)
+  std::vector<int2> titems;
+  for (int m : order)
+    for (int q = 0; q < tcount[m]; ++q) titems.push_back(int2{m, q});
+  b->ntitems = (int)titems.size();
+  if (hipMalloc((void**)&b->d_titems, sizeof(int2) * titems.size()) != hipSuccess) return DYCORE_ENOMEM;
+  if (hipMemcpy(b->d_titems, titems.data(), sizeof(int2) * titems.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return DYCORE_EHIP;
   if (hipMalloc((void**)&b->d_items, sizeof(int2) * items.size()) != hipSuccess) return DYCORE_ENOMEM;
   if (hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
     return DYCORE_EHIP;
@@ -831,8 +899,8 @@ int batch_step(dycore_batch_s* b, int nsteps, hipStream_t s) {
   const StageArgs<T>* args = static_cast<const StageArgs<T>*>(b->d_args);
   for (int n = 0; n < nsteps; ++n) {
     for (int sidx = 0; sidx < b->nstage_max; ++sidx) {
-      hipError_t e = launch_stage_batch<T>(args + (size_t)sidx * b->n, b->d_items, b->nitems, b->grid, b->block,
-                                           b->max_nx, b->lds, b->pipe, s);
+      hipError_t e = launch_stage_batch<T>(args + (size_t)sidx * b->n, b->n, b->max_nz, b->d_titems, b->ntitems,
+                                           b->d_items, b->nitems, b->grid, b->block, b->max_nx, b->lds, b->pipe, s);
       if (e != hipSuccess) return DYCORE_EHIP;
     }
     for (int m = 0; m < b->n; ++m) {   // members with the low-latitude filters close their step
@@ -865,16 +933,20 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
     max_nx = std::max(max_nx, hs[m]->nx);
     nst = std::max(nst, 3 * (hs[m]->msub + 1));
     const int el = hs[m]->prec == DYCORE_FP32 ? 4 : 8;
-    lds = std::max(lds, std::max(stage_lds_bytes(0, hs[m]->nx, el), stage_lds_bytes(1, hs[m]->nx, el)));
+    lds = std::max(lds, stage_lds_bytes(1, hs[m]->nx, el));
     npipe += stage_pipelined(hs[m]->nx, el);
   }
   if (block == 0) block = 256;
   if (block < 64 || block > 1024 || block % 64) return DYCORE_EINVAL;
+  lds = std::max(lds, adapt_tile_lds_bytes(block, prec == DYCORE_FP32 ? 4 : 8));
+  int max_nz = 0;
+  for (int m = 0; m < n; ++m) max_nz = std::max(max_nz, hs[m]->nz);
   if (columns_per_thread(max_nx, block) > 8 || !max_block_for(max_nx, block)) return DYCORE_EUNSUPPORTED;
   if (lds > 160 * 1024) return DYCORE_EUNSUPPORTED;
   dycore_batch_s* b = new (std::nothrow) dycore_batch_s();
   if (!b) return DYCORE_ENOMEM;
   b->n = n; b->prec = prec; b->block = block; b->max_nx = max_nx; b->nstage_max = nst; b->lds = lds;
+  b->max_nz = max_nz;
   b->pipe = npipe == n ? 1 : (npipe == 0 ? 0 : 2);
   b->hs.assign(hs, hs + n);
   b->U.assign(U, U + n); b->V.assign(V, V + n); b->F.assign(Phi, Phi + n); b->P.assign(ps, ps + n);
@@ -906,6 +978,8 @@ int dycore_batch_destroy(dycore_batch_t b) {
   (void)hipDeviceSynchronize();
   if (b->d_args) (void)hipFree(b->d_args);
   if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_titems) (void)hipFree(b->d_titems);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_prep) (void)hipFree(b->d_prep);
   delete b;
   return DYCORE_OK;

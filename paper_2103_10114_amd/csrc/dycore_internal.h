@@ -52,6 +52,16 @@ struct KTimer {
 // Pole slot layout: double[2][nz+1]; [p][k] = Phi pole value at level k, [p][nz] = p_s pole value,
 // p = 0 north, 1 south.
 
+// Zonal tiles of the tiled adaptation stage and its adjoint: one work item per (row, tile), a tile
+// being w owned columns from i0 plus a halo of hl = n_j + 1 columns on each side (n_j the row's leap
+// half width), one column per thread, w + 2 hl <= the launch's block.  Items are ordered so that the
+// workgroups one XCD runs cover a contiguous band of rows; padding items have j = -1.
+struct AatItem {
+  int j, i0, w, hl;
+};
+constexpr int kAatMaxBlock = 320;       // adjoint tiles
+constexpr int kFwdTileMaxBlock = 1024;  // forward adaptation tiles
+
 // One stage out = base + ch * T(in) of one member.
 template <typename T>
 struct StageArgs {
@@ -65,6 +75,10 @@ struct StageArgs {
   double ch;
   int process;          // 0 adaptation, 1 advection, -1 idle
   int pad;
+  const AatItem* tiles;  // zonal tiles of the adaptation stage (rows 0..ny)
+  double* cap;          // [2 poles][2][nz] FP64 cap sums of the adaptation stage's input
+  int ntiles;           // tile count (a multiple of 8)
+  int tblock;           // threads per tile workgroup
 };
 
 // Adjoint of one stage about `in`.
@@ -97,9 +111,12 @@ template <typename T>
 hipError_t launch_pole_prep(const GeoDev& g, const T* F, const T* ps, double* pole, hipStream_t s);
 template <typename T>
 hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s);
+// One batched stage: the cap sums of the members at an adaptation stage, then one persistent launch
+// over the adaptation tiles (titems) and the advection rows (items) of every member.
 template <typename T>
-hipError_t launch_stage_batch(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid,
-                              int block, int max_nx, size_t lds, int pipe, hipStream_t s);
+hipError_t launch_stage_batch(const StageArgs<T>* d_args, int nargs, int max_nz, const int2* d_titems, int ntitems,
+                              const int2* d_items, int nitems, int grid, int block, int max_nx, size_t lds, int pipe,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_stage_adjoint(const AdjArgs<T>& a, int block, hipStream_t s);
 // FP64 mass and energy: per-row partials (3 (ny+1) doubles in `partial`), then their fixed-order
@@ -120,7 +137,8 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s);
 
 size_t stage_lds_bytes(int process, int nx, int elem);
 int columns_per_thread(int nx, int block);
-int stage_pipelined(int nx, int elem);   // 1 if the stage kernels for rows of nx columns are pipelined
+int stage_pipelined(int nx, int elem);   // 1 if the advection kernel for rows of nx columns is pipelined
+size_t adapt_tile_lds_bytes(int block, int elem);   // LDS of an adaptation tile workgroup
 int max_block_for(int nx, int block);   // 1 if `block` threads are allowed for rows of nx columns
 
 // A uniform row of a global array: the array base (the kernel argument's, one SGPR pair for every
@@ -167,14 +185,7 @@ __device__ __forceinline__ void xcd_tile3(int gx, int nz, int nrows, int& x, int
   j = tup / (gx * nz);
 }
 
-// Zonal tiles of the tiled adaptation-stage adjoint: one work item per (row, tile), a tile being
-// w owned columns from i0 plus a halo of hl = n_j + 1 columns on each side (n_j the row's leap half
-// width), one column per thread, w + 2 hl <= the launch's block.  Items are ordered so that the
-// workgroups one XCD runs cover a contiguous band of rows; padding items have j = -1.
-struct AatItem {
-  int j, i0, w, hl;
-};
-constexpr int kAatMaxBlock = 320;
+
 
 // What the adjoint translation unit sees of a handle.
 struct HandleView {
@@ -195,6 +206,9 @@ struct HandleView {
   int aat_block;        // threads per tile workgroup
   const FiltItem* filt; // rows of the low-latitude filters (device), NULL when they are off
   int nfilt;
+  const AatItem* ftiles; // zonal tiles of the forward adaptation stage (device)
+  int nftiles, ftblock;
+  double* cap;           // cap sums of the forward adaptation stage (device, 4 nz doubles)
 };
 HandleView view_of(const dycore_s* h);
 

@@ -37,6 +37,18 @@ __device__ __forceinline__ double wave_sum(double acc) {
 
 using C = double;
 
+// A global load or store at the array's base plus a 32-bit element offset (fields hold fewer than
+// 2^30 elements; create refuses larger grids).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, unsigned idx) {
+  return *(const __attribute__((address_space(1))) T*)(
+      (const __attribute__((address_space(1))) char*)p + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, unsigned idx, T v) {
+  *(__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)p + idx * (unsigned)sizeof(T)) = v;
+}
+
 }  // namespace
 
 // kappa* D_sa of eq. 1's p_s line at column i of interior row j, from the stage input's stored p_s
@@ -90,519 +102,167 @@ namespace {
 // ----------------------------------------------------------------------------------------------
 // Adaptation: out = base + ch * A(in)
 // ----------------------------------------------------------------------------------------------
-// LDS: 2D rows P, l (rows j-1, j, j+1), q (rows j, j+1), leaped d+l and d+q on the U points of
-// row j, and per level the leaped rows phi' and MU of row j.  Registers per owned column: the
-// FP64 column sums, the wrapped neighbour indices and the reciprocals of the P averages (so the
-// level loop divides only where a neighbour's P enters).
-template <typename T, int NI>
-__device__ void adapt_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
-  const GeoDev& g = A.g;
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int B = blockDim.x, t = threadIdx.x;
-  T* sPm = reinterpret_cast<T*>(smem);
-  T* sP0 = sPm + nx;
-  T* sP1 = sP0 + nx;
-  T* sLm = sP1 + nx;
-  T* sL0 = sLm + nx;
-  T* sL1 = sL0 + nx;
-  T* sQ0 = sL1 + nx;
-  T* sQ1 = sQ0 + nx;
-  T* sDl = sQ1 + nx;
-  T* sDq = sDl + nx;
-  T* sPhi = sDq + nx;
-  T* sMU = sPhi + nx;
-  double* sCap = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));  // [2][nz]
-
-  const bool isPole = (j == 0 || j == ny);
-  const bool hasV = (j < ny);
-  const int pidx = (j == 0) ? 0 : 1;
-  const T p0 = (T)g.p0, b = (T)g.b, RT0 = (T)g.RT0;
-  const C RT0c = g.RT0;
-  const size_t row3 = (size_t)nz * nx;
-
-  auto psA = [&](int jr, int i) -> T {
-    if (jr == 0) return (T)A.pin[nz];
-    if (jr == ny) return (T)A.pin[(nz + 1) + nz];
-    return A.inP[(size_t)jr * nx + i];
-  };
-
-  // ---- 2D rows
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    if (i < nx) {
-      const T ps0 = psA(j, i);
-      sP0[i] = tsqrt<T>(ps0 / p0);
-      sL0[i] = tlog<T>(ps0 / p0);
-      sQ0[i] = sL0[i] + (T)g.phis[(size_t)j * nx + i] / RT0;
-      if (j < ny) {
-        const T ps1 = psA(j + 1, i);
-        sP1[i] = tsqrt<T>(ps1 / p0);
-        sL1[i] = tlog<T>(ps1 / p0);
-        sQ1[i] = sL1[i] + (T)g.phis[(size_t)(j + 1) * nx + i] / RT0;
-      }
-      if (j > 0) {
-        const T psm = psA(j - 1, i);
-        sPm[i] = tsqrt<T>(psm / p0);
-        sLm[i] = tlog<T>(psm / p0);
-      }
-    }
-  }
-  __syncthreads();
-  const int Mj = isPole ? 1 : g.M[j];
-  const int nj = (Mj + 1) / 2;
-  const T rdx = isPole ? T(0) : (T)(1.0 / ((double)Mj * g.a * g.s[j] * g.dlam));
-  if (!isPole) {
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) {
-        sDl[i] = (sL0[wrp(i + nj, nx)] - sL0[wrp(i + 1 - nj, nx)]) * rdx;
-        sDq[i] = (sQ0[wrp(i + nj, nx)] - sQ0[wrp(i + 1 - nj, nx)]) * rdx;
-      }
-    }
-  }
-  // pole workgroups: cap divergence and zonal-mean v.grad(l) of every level, FP64, wavefront 0
-  if (isPole && t < 64) {
-    const int jva = (j == 0) ? 0 : ny - 1;
-    const T* sPa = (j == 0) ? sP1 : sPm;
-    const T* sLa = (j == 0) ? sL1 : sLm;
-    const T Pp = sP0[0], lp = sL0[0];
-    for (int k = 0; k < nz; ++k) {
-      const T* pV = A.inV + (size_t)jva * row3 + (size_t)k * nx;
-      C s1 = 0, s2 = 0;
-      for (int i = t; i < nx; i += 64) {
-        const T pv = T(0.5) * (Pp + sPa[i]);
-        const T vv = pV[i];
-        s1 += (C)(pv * vv);
-        s2 += (C)((vv / pv) * (j == 0 ? (sLa[i] - lp) : (lp - sLa[i])));
-      }
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
-    }
-  }
-  __syncthreads();
-
-  // per-column constants
-  T rPU0[NI], rPU1[NI], rPV0[NI], rPVm[NI], rP0[NI], rP1[NI];
-  C H0c[NI], H1c[NI], R0c[NI], R1c[NI], Sc[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    const int ii = i < nx ? i : 0;
-    const int ip = wrp(ii + 1, nx);
-    const T P0 = sP0[ii];
-    rP0[c] = T(1) / P0;
-    rPU0[c] = T(2) / (P0 + sP0[ip]);
-    rP1[c] = rPU1[c] = rPV0[c] = rPVm[c] = T(1);
-    if (hasV) {
-      rP1[c] = T(1) / sP1[ii];
-      rPU1[c] = T(2) / (sP1[ii] + sP1[ip]);
-      rPV0[c] = T(2) / (P0 + sP1[ii]);
-    }
-    if (j >= 1) rPVm[c] = T(2) / (sPm[ii] + P0);
-    H0c[c] = 0; H1c[c] = 0; R0c[c] = 0; R1c[c] = 0; Sc[c] = 0;
-  }
-
-  // ---- pass A: column totals H = sum_{l>=1} cl_l RT'_l (FP64) for phi' = H - R_k + cpk_k RT'_k
-  if (hasV) {
-#pragma unroll 1
-    for (int k = 0; k < nz; ++k) {
-      const C clk = g.cl[k];
-      const size_t lev = (size_t)k * nx;
-      const T* pF0 = isPole ? nullptr : A.inF + (size_t)j * row3 + lev;
-      const T* pF1 = (j + 1 < ny) ? A.inF + (size_t)(j + 1) * row3 + lev : nullptr;
-      const T F0p = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
-      const T F1p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i < nx) {
-          H0c[c] += clk * (C)(b * (pF0 ? pF0[i] : F0p) * rP0[c]);
-          H1c[c] += clk * (C)(b * (pF1 ? pF1[i] : F1p) * rP1[c]);
-        }
-      }
-    }
-  }
-
-  // ---- pass B: top to bottom
-  C Sp = 0;
-  const T rdyS = isPole ? T(0) : (T)(1.0 / (g.a * g.s[j] * g.dth));
-  const T rdyA = (T)(1.0 / (g.a * g.dth));
-  const C rdyAc = 1.0 / (C)(T)(g.a * g.dth);
-  for (int k = 0; k < nz; ++k) {
-    const C clk = g.cl[k], cpk = g.cpk[k];
-    const C dsg = g.dsig[k], rsg = 1.0 / g.sig[k];
-    const size_t lev = (size_t)k * nx;
-    const T* pF0 = isPole ? nullptr : A.inF + (size_t)j * row3 + lev;
-    const T* pF1 = (j + 1 < ny) ? A.inF + (size_t)(j + 1) * row3 + lev : nullptr;
-    const T F0p = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
-    const T F1p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
-    const T* pU0 = isPole ? nullptr : A.inU + (size_t)j * row3 + lev;
-    const T* pU1 = (j + 1 < ny) ? A.inU + (size_t)(j + 1) * row3 + lev : nullptr;
-    const T* pV0 = hasV ? A.inV + (size_t)j * row3 + lev : nullptr;
-    const T* pVm = (j >= 1) ? A.inV + (size_t)(j - 1) * row3 + lev : nullptr;
-    // phase 1: every global load of this level, phi' and MU into LDS
-    T Fj[NI], Fp[NI], RTj[NI], RTj1[NI], phij[NI], phij1[NI], Uj[NI], Ujm[NI], U1[NI], U1m[NI];
-    T Vn[NI], Vnp[NI], Vs[NI], Vsp[NI];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      Fj[c] = Fp[c] = RTj[c] = RTj1[c] = phij[c] = phij1[c] = Uj[c] = Ujm[c] = U1[c] = U1m[c] = T(0);
-      Vn[c] = Vnp[c] = Vs[c] = Vsp[c] = T(0);
-      if (i < nx) {
-        const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
-        Fj[c] = pF0 ? pF0[i] : F0p;
-        RTj[c] = b * Fj[c] * rP0[c];
-        if (hasV) {
-          R0c[c] += clk * (C)RTj[c];
-          phij[c] = (T)(H0c[c] - R0c[c] + cpk * (C)RTj[c]);
-          RTj1[c] = b * (pF1 ? pF1[i] : F1p) * rP1[c];
-          R1c[c] += clk * (C)RTj1[c];
-          phij1[c] = (T)(H1c[c] - R1c[c] + cpk * (C)RTj1[c]);
-          if (pU1) { U1[c] = pU1[i]; U1m[c] = pU1[im]; }
-        }
-        if (!isPole) {
-          Fp[c] = pF0[ip];
-          Uj[c] = pU0[i];
-          Ujm[c] = pU0[im];
-          Vn[c] = pV0[i];
-          Vnp[c] = pV0[ip];
-          Vs[c] = pVm[i];
-          Vsp[c] = pVm[ip];
-          sPhi[i] = phij[c];
-          sMU[i] = T(0.5) * (sP0[i] + sP0[ip]) * Uj[c];
-        }
-      }
-    }
-    __syncthreads();
-
-    if (!isPole) {
-      const T svj = (T)g.sv[j], svm = (T)g.sv[j - 1];
-      const T fj = (T)g.f[j], cota = (T)(g.cot[j] / g.a);
-      const T kap = (T)g.kappa;
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const size_t idx = (size_t)j * row3 + lev + i;
-        const int ip = wrp(i + 1, nx), im = wrp(i - 1, nx);
-        const T PV0 = T(0.5) * (sP0[i] + sP1[i]), PVm = T(0.5) * (sPm[i] + sP0[i]);
-        // divergence of the mass flux: leaped (x,x-1) -> (x+N-1, x-N) plus meridional
-        const T D = (sMU[wrp(i + nj - 1, nx)] - sMU[wrp(i - nj, nx)]) * rdx + (svj * (PV0 * Vn[c]) - svm * (PVm * Vs[c])) * rdyS;
-        const C Sk = Sc[c];
-        Sc[c] += (C)D * dsg;
-        // v . grad(l)
-        const T u_i = Uj[c] * rPU0[c];
-        const T u_m = Ujm[c] / (T(0.5) * (sP0[im] + sP0[i]));
-        const T zon = T(0.5) * (u_i * sDl[i] + u_m * sDl[im]);
-        const T mer = T(0.5) * ((Vn[c] * rPV0[c]) * (sL1[i] - sL0[i]) + (Vs[c] * rPVm[c]) * (sL0[i] - sLm[i])) * rdyA;
-        const C rp = (C)rP0[c];
-        const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) * rsg * (rp * rp);
-        const C TF = ((C)(b * sP0[i]) + (C)(kap * Fj[c])) * wp;
-        A.oF[idx] = (T)((C)A.bF[idx] + A.ch * TF);
-        // U at i+1/2: pressure gradient with leap (x+1,x) -> (x+N, x-N+1) and Coriolis
-        const T dphi = (sPhi[wrp(i + nj, nx)] - sPhi[wrp(i + 1 - nj, nx)]) * rdx;
-        const T RTp = b * Fp[c] / sP0[ip];
-        const T rtx = T(0.5) * (RTj[c] + RTp);
-        const C pgf = (C)dphi + RT0c * (C)sDq[i] + (C)rtx * (C)sDl[i];
-        const T VV = T(0.25) * (Vn[c] + Vnp[c] + Vs[c] + Vsp[c]);
-        const T fs = fj + u_i * cota;
-        const C TU = -(C)(T(0.5) * (sP0[i] + sP0[ip])) * pgf - (C)fs * (C)VV;
-        A.oU[idx] = (T)((C)A.bU[idx] + A.ch * TU);
-        __builtin_amdgcn_sched_barrier(0);   // one column at a time: bounds the live registers
-      }
-    } else {
-      // pole column from the precomputed cap sums
-      const int jva = (j == 0) ? 0 : ny - 1;
-      const T Pp = sP0[0];
-      const C sgn = (j == 0) ? 1.0 : -1.0;
-      const C Dp = sgn * g.a * g.dlam * g.sv[jva] * sCap[k] / g.acap;
-      const C vglp = sCap[nz + k] / ((double)nx * g.a * g.dth);
-      const C Sk = Sp;
-      Sp += Dp * dsg;
-      const C wp = vglp - (Sk + 0.5 * Dp * dsg) * rsg / ((C)Pp * (C)Pp);
-      const C TF = ((C)(b * Pp) + (C)((T)g.kappa * F0p)) * wp;
-      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i < nx) {
-          const size_t idx = (size_t)j * row3 + lev + i;
-          A.oF[idx] = val;
-          A.oU[idx] = T(0);
-        }
-      }
-      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
-    }
-
-    if (hasV) {
-      const T fvj = (T)g.fv[j], cotva = (T)(g.cotv[j] / g.a);
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const size_t idv = (size_t)j * row3 + lev + i;
-        const int im = wrp(i - 1, nx);
-        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)(sQ1[i] - sQ0[i]) +
-                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)(sL1[i] - sL0[i])) * rdyAc;
-        const T u0i = isPole ? T(0) : Uj[c] * rPU0[c];
-        const T u0m = isPole ? T(0) : Ujm[c] / (T(0.5) * (sP0[im] + sP0[i]));
-        const T u1i = pU1 ? U1[c] * rPU1[c] : T(0);
-        const T u1m = pU1 ? U1m[c] / (T(0.5) * (sP1[im] + sP1[i])) : T(0);
-        const T UU = T(0.25) * (Ujm[c] + Uj[c] + U1m[c] + U1[c]);
-        const T uu = T(0.25) * (u0m + u0i + u1m + u1i);
-        const T fs = fvj + uu * cotva;
-        const C TV = -(C)(T(0.5) * (sP0[i] + sP1[i])) * pgf + (C)fs * (C)UU;
-        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    __syncthreads();
-  }
-
-  // surface pressure: -p0 * Pi
-  if (!isPole) {
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) {
-        const size_t idx = (size_t)j * nx + i;
-        const C dsa = g.kstar != 0.0 ? ps_diffusion(A, j, i) : 0.0;
-        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c] + dsa));
-      }
-    }
-  } else {
-    // the cap sums' LDS is free again after the level loop's last barrier
-    const C dsa = g.kstar != 0.0 ? ps_diffusion_pole(A, j, sCap) : 0.0;
-    const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp + dsa));
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) A.oP[(size_t)j * nx + i] = val;
-    }
-    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
-  }
-}
-
-// Adaptation, software-pipelined (rows whose LDS rows fit in 160 KB: nx <= 1498 in FP32, 749 in FP64).  Every value the level loop reads at another
-// column sits in LDS: 13 2D rows (P, the reciprocals of P and of its U-point averages, the
-// leaped d+l and d+q, the V-point averages of P and the meridional l and q differences) and,
+// Per zonal slot, the LDS holds 13 2D rows (P, the reciprocals of P and of its U-point averages,
+// the leaped d+l and d+q, the V-point averages of P, the meridional l and q differences) and,
 // double-buffered, the 7 per-level rows (phi', MU, Phi, U of rows j and j+1, V of rows j+-1/2).
-// Level k+1 is fetched into registers while level k is computed and written to the other
-// buffer afterwards, so one barrier per level suffices and the fetch latency hides behind the
-// arithmetic.  The column totals of pass A are summed over unrolled groups of levels.
 constexpr int kAdaptPipeRows2D = 13, kAdaptPipeRowsLev = 7;
-__host__ __device__ constexpr size_t adapt_pipe_lds(int nx, int elem) {
-  return (((size_t)(kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev) * nx * elem + 15) & ~size_t(15)) +
-         2 * 128 * sizeof(double);
-}
-__host__ __device__ constexpr bool adapt_pipe_ok(int nx, int elem) { return adapt_pipe_lds(nx, elem) <= 160 * 1024; }
 
-template <typename T, int NI>
-__device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char* smem) {
+// Adaptation, tiled: one workgroup per work item (row j, a zonal tile of w owned columns from i0 and
+// a halo of hl = n_j + 1 columns on each side), one column per thread.  The stage's arithmetic is
+// that of the pipelined row form: every value a level reads at another column sits in LDS, per slot
+// 27 words (the 13 2D rows, then two buffers of the 7 level rows; an odd stride, no bank conflicts),
+// level k+1 is fetched into registers while level k is computed, one barrier per level.  The leap
+// and +-1 neighbours of the owned columns are halo slots, so LDS indices need no wrap, and a tile's
+// small LDS leaves room for several workgroups per CU.  Pole rows (j = 0, ny) take their cap sums from
+// k_capsum, which runs before the stage; their tiles write the replicated pole values of their own
+// columns.
+constexpr int kTileRS = kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev;   // 27 words per slot
+__host__ __device__ constexpr size_t adapt_tile_lds(int block, int elem) {
+  return (size_t)kTileRS * block * elem + 8 * sizeof(double);
+}
+
+template <typename T>
+__device__ void adapt_tile(const StageArgs<T>& A, const AatItem it, unsigned char* smem) {
   const GeoDev& g = A.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int B = blockDim.x, t = threadIdx.x;
-  // LDS cells column-major, 27 words per column: the 13 2D rows, then the two buffers of 7 level
-  // rows; one address per column index serves every row (the row is an immediate offset) and
-  // consecutive lanes stride 27 words (no bank conflicts)
-  constexpr int RS = kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev;
+  const int j = it.j, hl = it.hl, w = it.w;
+  const int NS = w + 2 * hl;
+  const int sl = threadIdx.x;
+  const bool act = sl < NS;
+  const bool own = sl >= hl && sl < hl + w;
+  int col = (it.i0 - hl + sl) % nx;
+  if (col < 0) col += nx;
+  const int colp = col == nx - 1 ? 0 : col + 1;
   T* r = reinterpret_cast<T*>(smem);
-  auto S2 = [&](int row, int col) -> T& { return r[col * RS + row]; };
-  auto SB = [&](int bsel, int row, int col) -> T& {
-    return r[col * RS + kAdaptPipeRows2D + bsel * kAdaptPipeRowsLev + row];
+  double* red = reinterpret_cast<double*>(smem + (size_t)kTileRS * blockDim.x * sizeof(T));
+  auto S2 = [&](int row, int slot) -> T& { return r[slot * kTileRS + row]; };
+  auto SB = [&](int bsel, int row, int slot) -> T& {
+    return r[slot * kTileRS + kAdaptPipeRows2D + bsel * kAdaptPipeRowsLev + row];
   };
   enum { RP0, RrP0, RrP1, RrU0, RrU1, RDl, RDq, RPV0, RPVm, RgN, RgS, RdL, RdQ };
   enum { BPhi, BMU, BF, BU0, BU1, BV0, BVm };
-  double* sCap = reinterpret_cast<double*>(smem + ((((size_t)kAdaptPipeRows2D + 2 * kAdaptPipeRowsLev) * nx * sizeof(T) + 15) & ~size_t(15)));
 
   const bool isPole = (j == 0 || j == ny);
   const bool hasV = (j < ny);
   const int pidx = (j == 0) ? 0 : 1;
   const T p0 = (T)g.p0, b = (T)g.b, RT0 = (T)g.RT0;
   const C RT0c = g.RT0;
-  const size_t row3 = (size_t)nz * nx;
+  const unsigned row3 = (unsigned)(nz * nx);
   auto psA = [&](int jr, int i) -> T {
     if (jr == 0) return (T)A.pin[nz];
     if (jr == ny) return (T)A.pin[(nz + 1) + nz];
     return A.inP[(size_t)jr * nx + i];
   };
 
-  // ---- 2D rows.  Temporaries (P, l, q of the neighbour rows) live in the level buffers.
-  // (tP1, tL0, tQ0 and, for pole rows, P and l of the adjacent row in rows 0..4 of buffer 0)
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    if (i < nx) {
-      const T ps0 = psA(j, i);
-      const T P0 = tsqrt<T>(ps0 / p0), L0 = tlog<T>(ps0 / p0);
-      const T Q0 = L0 + (T)g.phis[(size_t)j * nx + i] / RT0;
-      S2(RP0, i) = P0;
-      S2(RrP0, i) = T(1) / P0;
-      SB(0, 1, i) = L0;
-      SB(0, 2, i) = Q0;
-      T P1 = T(1), L1 = T(0);
-      if (hasV) {
-        const T ps1 = psA(j + 1, i);
-        P1 = tsqrt<T>(ps1 / p0);
-        L1 = tlog<T>(ps1 / p0);
-        const T Q1 = L1 + (T)g.phis[(size_t)(j + 1) * nx + i] / RT0;
-        SB(0, 0, i) = P1;
-        S2(RrP1, i) = T(1) / P1;
-        const T PV0 = T(0.5) * (P0 + P1);
-        S2(RPV0, i) = PV0;
-        S2(RgN, i) = (L1 - L0) / PV0;
-        S2(RdL, i) = L1 - L0;
-        S2(RdQ, i) = Q1 - Q0;
-      }
-      if (j >= 1) {
-        const T psm = psA(j - 1, i);
-        const T Pm = tsqrt<T>(psm / p0), Lm = tlog<T>(psm / p0);
-        const T PVm = T(0.5) * (Pm + P0);
-        S2(RPVm, i) = PVm;
-        S2(RgS, i) = (L0 - Lm) / PVm;
-        if (j == ny) { SB(0, 3, i) = Pm; SB(0, 4, i) = Lm; }
-      }
-      if (j == 0) { SB(0, 3, i) = P1; SB(0, 4, i) = L1; }
+  // ---- 2D rows of every slot (l and q of row j in buffer 0 until the leaped differences are formed)
+  if (act) {
+    const T ps0 = psA(j, col);
+    const T P0 = tsqrt<T>(ps0 / p0), L0 = tlog<T>(ps0 / p0);
+    const T Q0 = L0 + (T)g.phis[(size_t)j * nx + col] / RT0;
+    const T P0p = tsqrt<T>(psA(j, colp) / p0);
+    S2(RP0, sl) = P0;
+    S2(RrP0, sl) = T(1) / P0;
+    S2(RrU0, sl) = T(2) / (P0 + P0p);
+    SB(0, 1, sl) = L0;
+    SB(0, 2, sl) = Q0;
+    if (hasV) {
+      const T ps1 = psA(j + 1, col);
+      const T P1 = tsqrt<T>(ps1 / p0), L1 = tlog<T>(ps1 / p0);
+      const T Q1 = L1 + (T)g.phis[(size_t)(j + 1) * nx + col] / RT0;
+      const T P1p = tsqrt<T>(psA(j + 1, colp) / p0);
+      S2(RrP1, sl) = T(1) / P1;
+      S2(RrU1, sl) = T(2) / (P1 + P1p);
+      const T PV0 = T(0.5) * (P0 + P1);
+      S2(RPV0, sl) = PV0;
+      S2(RgN, sl) = (L1 - L0) / PV0;
+      S2(RdL, sl) = L1 - L0;
+      S2(RdQ, sl) = Q1 - Q0;
+    }
+    if (j >= 1) {
+      const T psm = psA(j - 1, col);
+      const T Pm = tsqrt<T>(psm / p0), Lm = tlog<T>(psm / p0);
+      const T PVm = T(0.5) * (Pm + P0);
+      S2(RPVm, sl) = PVm;
+      S2(RgS, sl) = (L0 - Lm) / PVm;
     }
   }
   __syncthreads();
   const int Mj = isPole ? 1 : g.M[j];
   const int nj = (Mj + 1) / 2;
   const T rdx = isPole ? T(0) : (T)(1.0 / ((double)Mj * g.a * g.s[j] * g.dlam));
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    if (i < nx) {
-      const int ip = wrp_up(i + 1, nx);
-      S2(RrU0, i) = T(2) / (S2(RP0, i) + S2(RP0, ip));
-      if (hasV) S2(RrU1, i) = T(2) / (SB(0, 0, i) + SB(0, 0, ip));
-      if (!isPole) {
-        S2(RDl, i) = (SB(0, 1, wrp_up(i + nj, nx)) - SB(0, 1, wrp_dn(i + 1 - nj, nx))) * rdx;
-        S2(RDq, i) = (SB(0, 2, wrp_up(i + nj, nx)) - SB(0, 2, wrp_dn(i + 1 - nj, nx))) * rdx;
-      }
-    }
-  }
-  if (isPole && t < 64) {
-    const int jva = (j == 0) ? 0 : ny - 1;
-    const T Pp = S2(RP0, 0), lp = SB(0, 1, 0);
-    for (int k = 0; k < nz; ++k) {
-      const T* pV = A.inV + (size_t)jva * row3 + (size_t)k * nx;
-      C s1 = 0, s2 = 0;
-      for (int i = t; i < nx; i += 64) {
-        const T pv = T(0.5) * (Pp + SB(0, 3, i));
-        const T vv = pV[i];
-        s1 += (C)(pv * vv);
-        s2 += (C)((vv / pv) * (j == 0 ? (SB(0, 4, i) - lp) : (lp - SB(0, 4, i))));
-      }
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
-    }
+  if (!isPole && sl >= nj - 1 && sl + nj < NS) {   // the slots whose leap neighbours are in the tile
+    S2(RDl, sl) = (SB(0, 1, sl + nj) - SB(0, 1, sl + 1 - nj)) * rdx;
+    S2(RDq, sl) = (SB(0, 2, sl + nj) - SB(0, 2, sl + 1 - nj)) * rdx;
   }
   __syncthreads();
 
   // ---- pass A: column totals of R T' (the hydrostatic suffix sums start from them)
-  C Q0c[NI], Q1c[NI], Sc[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) { Q0c[c] = 0; Q1c[c] = 0; Sc[c] = 0; }
-  if (hasV) {
-    T rp0[NI], rp1[NI];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      rp0[c] = (i < nx) ? b * S2(RrP0, i) : T(0);
-      rp1[c] = (i < nx) ? b * S2(RrP1, i) : T(0);
-    }
-    const T* pF0 = isPole ? nullptr : A.inF + (size_t)j * row3;
-    const T* pF1 = (j + 1 < ny) ? A.inF + (size_t)(j + 1) * row3 : nullptr;
+  C Q0c = 0, Q1c = 0, Sc = 0;
+  if (hasV && act) {
+    const T rp0 = b * S2(RrP0, sl), rp1 = b * S2(RrP1, sl);
     constexpr int KU = 6;
-    int k = 0;
-    for (; k + KU <= nz; k += KU) {
-      T f0[KU][NI], f1[KU][NI];
+    for (int k0 = 0; k0 < nz; k0 += KU) {
+      T f0[KU], f1[KU];
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
-#pragma unroll
-        for (int c = 0; c < NI; ++c) {
-          const int i = t + c * B;
-          const size_t o = (size_t)(k + u) * nx + (i < nx ? i : 0);
-          f0[u][c] = pF0 ? pF0[o] : (T)A.pin[k + u];
-          f1[u][c] = pF1 ? pF1[o] : (T)A.pin[(nz + 1) + k + u];
-        }
+        const int k = k0 + u < nz ? k0 + u : nz - 1;
+        const unsigned o = (unsigned)(k * nx + col);
+        f0[u] = isPole ? (T)A.pin[k] : ldg(A.inF, (unsigned)j * row3 + o);
+        f1[u] = (j + 1 < ny) ? ldg(A.inF, (unsigned)(j + 1) * row3 + o) : (T)A.pin[(nz + 1) + k];
       }
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
-        const C clk = g.cl[k + u];
-#pragma unroll
-        for (int c = 0; c < NI; ++c) {
-          Q0c[c] += clk * (C)(f0[u][c] * rp0[c]);
-          Q1c[c] += clk * (C)(f1[u][c] * rp1[c]);
-        }
-      }
-    }
-    for (; k < nz; ++k) {
-      const C clk = g.cl[k];
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        const size_t o = (size_t)k * nx + (i < nx ? i : 0);
-        const T f0 = pF0 ? pF0[o] : (T)A.pin[k];
-        const T f1 = pF1 ? pF1[o] : (T)A.pin[(nz + 1) + k];
-        Q0c[c] += clk * (C)(f0 * rp0[c]);
-        Q1c[c] += clk * (C)(f1 * rp1[c]);
+        if (k0 + u >= nz) break;
+        const C clk = g.cl[k0 + u];
+        Q0c += clk * (C)(f0[u] * rp0);
+        Q1c += clk * (C)(f1[u] * rp1);
       }
     }
   }
 
-  // ---- pass B, pipelined over levels
-  // raw values of one level for the owned columns
-  T nF0[NI], nF1[NI], nU0[NI], nU1[NI], nV0[NI], nVm[NI];
+  // ---- pass B, pipelined over levels: the next level's inputs and base values are fetched while
+  // the current level is computed
+  T nF0 = 0, nF1 = 0, nU0 = 0, nU1 = 0, nV0 = 0, nVm = 0;
+  T nbF = 0, nbU = 0, nbV = 0;
   auto fetch = [&](int k) {
-    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-    const T F0p = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
-    const T F1p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
-    const auto gF0 = urow(A.inF, lo);
-    const auto gU0 = urow(A.inU, lo);
-    const auto gF1 = urow(A.inF, lo + row3);
-    const auto gU1 = urow(A.inU, lo + row3);
-    const auto gV0 = urow(A.inV, lo);
-    const auto gVm = urow(A.inV, (lo - (j >= 1 ? row3 : 0)));
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      const unsigned ii = i < nx ? (unsigned)i : 0u;
-      nF0[c] = isPole ? F0p : gF0[ii];
-      nU0[c] = isPole ? T(0) : gU0[ii];
-      nF1[c] = (j + 1 < ny) ? gF1[ii] : F1p;
-      nU1[c] = (j + 1 < ny) ? gU1[ii] : T(0);
-      nV0[c] = hasV ? gV0[ii] : T(0);
-      nVm[c] = (j >= 1) ? gVm[ii] : T(0);
+    if (!act) return;
+    const unsigned lo = (unsigned)j * row3 + (unsigned)(k * nx + col);
+    if (own) {
+      if (!isPole) {
+        nbF = ldg(A.bF, lo);
+        nbU = ldg(A.bU, lo);
+      }
+      if (hasV) nbV = ldg(A.bV, lo);
     }
+    nF0 = isPole ? (T)A.pin[pidx * (nz + 1) + k] : ldg(A.inF, lo);
+    nU0 = isPole ? T(0) : ldg(A.inU, lo);
+    nF1 = (j + 1 < ny) ? ldg(A.inF, lo + row3) : (T)A.pin[(nz + 1) + k];
+    nU1 = (j + 1 < ny) ? ldg(A.inU, lo + row3) : T(0);
+    nV0 = hasV ? ldg(A.inV, lo) : T(0);
+    nVm = (j >= 1) ? ldg(A.inV, lo - row3) : T(0);
   };
   // R T' and phi' of rows j and j+1 at the current level (registers)
-  T RTj[NI], RTj1[NI], phij[NI], phij1[NI];
+  T RTj = 0, RTj1 = 0, phij = 0, phij1 = 0;
   auto commit = [&](int k, int bs) {
+    if (!act) return;
     const C clk = g.cl[k], cpk = g.cpk[k];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      RTj[c] = RTj1[c] = phij[c] = phij1[c] = T(0);
-      if (i < nx) {
-        RTj[c] = b * nF0[c] * S2(RrP0, i);
-        SB(bs, BF, i) = nF0[c];
-        SB(bs, BU0, i) = nU0[c];
-        SB(bs, BMU, i) = T(0.5) * (S2(RP0, i) + S2(RP0, wrp_up(i + 1, nx))) * nU0[c];
-        if (hasV) {
-          Q0c[c] -= clk * (C)RTj[c];
-          phij[c] = (T)(Q0c[c] + cpk * (C)RTj[c]);
-          RTj1[c] = b * nF1[c] * S2(RrP1, i);
-          Q1c[c] -= clk * (C)RTj1[c];
-          phij1[c] = (T)(Q1c[c] + cpk * (C)RTj1[c]);
-          SB(bs, BU1, i) = nU1[c];
-          SB(bs, BV0, i) = nV0[c];
-        }
-        SB(bs, BVm, i) = nVm[c];
-        SB(bs, BPhi, i) = phij[c];
-      }
+    RTj = b * nF0 * S2(RrP0, sl);
+    SB(bs, BF, sl) = nF0;
+    SB(bs, BU0, sl) = nU0;
+    // (the last slot's MU is never gathered; its eastern neighbour is out of the tile)
+    SB(bs, BMU, sl) = T(0.5) * (S2(RP0, sl) + S2(RP0, sl + 1 < NS ? sl + 1 : sl)) * nU0;
+    RTj1 = phij = phij1 = T(0);
+    if (hasV) {
+      Q0c -= clk * (C)RTj;
+      phij = (T)(Q0c + cpk * (C)RTj);
+      RTj1 = b * nF1 * S2(RrP1, sl);
+      Q1c -= clk * (C)RTj1;
+      phij1 = (T)(Q1c + cpk * (C)RTj1);
+      SB(bs, BU1, sl) = nU1;
+      SB(bs, BV0, sl) = nV0;
     }
+    SB(bs, BVm, sl) = nVm;
+    SB(bs, BPhi, sl) = phij;
   };
 
   fetch(0);
@@ -617,118 +277,130 @@ __device__ void adapt_row_pipe(const StageArgs<T>& A, const int j, unsigned char
   const T fj = (T)g.f[j], cota = (T)(g.cot[j] / g.a);
   const T kap = (T)g.kappa;
   const T fvj = hasV ? (T)g.fv[j] : T(0), cotva = hasV ? (T)(g.cotv[j] / g.a) : T(0);
+  const double* cap = A.cap + pidx * 2 * nz;
+  const unsigned oc = (unsigned)col;
 #pragma unroll 1
   for (int k = 0; k < nz; ++k) {
+    const T baseF = nbF, baseU = nbU, baseV = nbV;
     if (k + 1 < nz) fetch(k + 1);
     const int bs = k & 1;
-    const C clk = g.cl[k];
-    (void)clk;
     const C dsg = g.dsig[k], rsg = 1.0 / g.sig[k];
-    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-    const auto gbF = urow(A.bF, lo);
-    const auto gbU = urow(A.bU, lo);
-    const auto gbV = urow(A.bV, lo);
-    const auto goF = urow(A.oF, lo);
-    const auto goU = urow(A.oU, lo);
-    const auto goV = urow(A.oV, lo);
-
-    if (!isPole) {
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const unsigned idx = (unsigned)i;
-        const T baseF = gbF[idx], baseU = gbU[idx];
-        const int ip = wrp_up(i + 1, nx), im = wrp_dn(i - 1, nx);
-        const T Vn = SB(bs, BV0, i), Vs = SB(bs, BVm, i);
-        const T D = (SB(bs, BMU, wrp_up(i + nj - 1, nx)) - SB(bs, BMU, wrp_dn(i - nj, nx))) * rdx +
-                    (svj * (S2(RPV0, i) * Vn) - svm * (S2(RPVm, i) * Vs)) * rdyS;
-        const C Sk = Sc[c];
-        Sc[c] += (C)D * dsg;
-        const T u_i = SB(bs, BU0, i) * S2(RrU0, i);
-        const T u_m = SB(bs, BU0, im) * S2(RrU0, im);
-        const T zon = T(0.5) * (u_i * S2(RDl, i) + u_m * S2(RDl, im));
-        const T mer = T(0.5) * (Vn * S2(RgN, i) + Vs * S2(RgS, i)) * rdyA;
-        const C rp = (C)S2(RrP0, i);
+    const unsigned lo = (unsigned)j * row3 + (unsigned)(k * nx);
+    if (own) {
+      const int sp = sl + 1, sm = sl - 1;
+      if (!isPole) {
+        const T Vn = SB(bs, BV0, sl), Vs = SB(bs, BVm, sl);
+        const T D = (SB(bs, BMU, sl + nj - 1) - SB(bs, BMU, sl - nj)) * rdx +
+                    (svj * (S2(RPV0, sl) * Vn) - svm * (S2(RPVm, sl) * Vs)) * rdyS;
+        const C Sk = Sc;
+        Sc += (C)D * dsg;
+        const T u_i = SB(bs, BU0, sl) * S2(RrU0, sl);
+        const T u_m = SB(bs, BU0, sm) * S2(RrU0, sm);
+        const T zon = T(0.5) * (u_i * S2(RDl, sl) + u_m * S2(RDl, sm));
+        const T mer = T(0.5) * (Vn * S2(RgN, sl) + Vs * S2(RgS, sl)) * rdyA;
+        const C rp = (C)S2(RrP0, sl);
         const C wp = ((C)zon + (C)mer) - (Sk + 0.5 * (C)D * dsg) * rsg * (rp * rp);
-        const C TF = ((C)(b * S2(RP0, i)) + (C)(kap * SB(bs, BF, i))) * wp;
-        goF[idx] = (T)((C)baseF + A.ch * TF);
-        const T dphi = (SB(bs, BPhi, wrp_up(i + nj, nx)) - SB(bs, BPhi, wrp_dn(i + 1 - nj, nx))) * rdx;
-        const T rtx = T(0.5) * (RTj[c] + b * SB(bs, BF, ip) * S2(RrP0, ip));
-        const C pgf = (C)dphi + RT0c * (C)S2(RDq, i) + (C)rtx * (C)S2(RDl, i);
-        const T VV = T(0.25) * (Vn + SB(bs, BV0, ip) + Vs + SB(bs, BVm, ip));
+        const C TF = ((C)(b * S2(RP0, sl)) + (C)(kap * SB(bs, BF, sl))) * wp;
+        stg(A.oF, lo + oc, (T)((C)baseF + A.ch * TF));
+        const T dphi = (SB(bs, BPhi, sl + nj) - SB(bs, BPhi, sl + 1 - nj)) * rdx;
+        const T rtx = T(0.5) * (RTj + b * SB(bs, BF, sp) * S2(RrP0, sp));
+        const C pgf = (C)dphi + RT0c * (C)S2(RDq, sl) + (C)rtx * (C)S2(RDl, sl);
+        const T VV = T(0.25) * (Vn + SB(bs, BV0, sp) + Vs + SB(bs, BVm, sp));
         const T fs = fj + u_i * cota;
-        const C TU = -(C)(T(0.5) * (S2(RP0, i) + S2(RP0, ip))) * pgf - (C)fs * (C)VV;
-        goU[idx] = (T)((C)baseU + A.ch * TU);
+        const C TU = -(C)(T(0.5) * (S2(RP0, sl) + S2(RP0, sp))) * pgf - (C)fs * (C)VV;
+        stg(A.oU, lo + oc, (T)((C)baseU + A.ch * TU));
+      } else {
+        const T F0p = (T)A.pin[pidx * (nz + 1) + k];
+        const int jva = (j == 0) ? 0 : ny - 1;
+        const T Pp = S2(RP0, sl);
+        const C sgn = (j == 0) ? 1.0 : -1.0;
+        const C Dp = sgn * g.a * g.dlam * g.sv[jva] * cap[k] / g.acap;
+        const C vglp = cap[nz + k] / ((double)nx * g.a * g.dth);
+        const C Sk = Sp;
+        Sp += Dp * dsg;
+        const C wp = vglp - (Sk + 0.5 * Dp * dsg) * rsg / ((C)Pp * (C)Pp);
+        const C TF = ((C)(b * Pp) + (C)(kap * F0p)) * wp;
+        const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
+        stg(A.oF, lo + oc, val);
+        stg(A.oU, lo + oc, T(0));
+        if (col == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
       }
-    } else {
-      const T F0p = (T)A.pin[pidx * (nz + 1) + k];
-      const int jva = (j == 0) ? 0 : ny - 1;
-      const T Pp = S2(RP0, 0);
-      const C sgn = (j == 0) ? 1.0 : -1.0;
-      const C Dp = sgn * g.a * g.dlam * g.sv[jva] * sCap[k] / g.acap;
-      const C vglp = sCap[nz + k] / ((double)nx * g.a * g.dth);
-      const C Sk = Sp;
-      Sp += Dp * dsg;
-      const C wp = vglp - (Sk + 0.5 * Dp * dsg) * rsg / ((C)Pp * (C)Pp);
-      const C TF = ((C)(b * Pp) + (C)(kap * F0p)) * wp;
-      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i < nx) {
-          goF[i] = val;
-          goU[i] = T(0);
-        }
-      }
-      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
-    }
-
-    if (hasV) {
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const unsigned idv = (unsigned)i;
-        const T baseV = gbV[idv];
-        const int im = wrp_dn(i - 1, nx);
-        const C pgf = ((C)(phij1[c] - phij[c]) + RT0c * (C)S2(RdQ, i) +
-                       (C)(T(0.5) * (RTj[c] + RTj1[c])) * (C)S2(RdL, i)) * rdyAc;
-        const T U0i = SB(bs, BU0, i), U0m = SB(bs, BU0, im), U1i = SB(bs, BU1, i), U1m = SB(bs, BU1, im);
-        const T u0i = U0i * S2(RrU0, i), u0m = U0m * S2(RrU0, im);
-        const T u1i = U1i * S2(RrU1, i), u1m = U1m * S2(RrU1, im);
+      if (hasV) {
+        const C pgf = ((C)(phij1 - phij) + RT0c * (C)S2(RdQ, sl) +
+                       (C)(T(0.5) * (RTj + RTj1)) * (C)S2(RdL, sl)) * rdyAc;
+        const T U0i = SB(bs, BU0, sl), U0m = SB(bs, BU0, sm), U1i = SB(bs, BU1, sl), U1m = SB(bs, BU1, sm);
+        const T u0i = U0i * S2(RrU0, sl), u0m = U0m * S2(RrU0, sm);
+        const T u1i = U1i * S2(RrU1, sl), u1m = U1m * S2(RrU1, sm);
         const T UU = T(0.25) * (U0m + U0i + U1m + U1i);
         const T uu = T(0.25) * (u0m + u0i + u1m + u1i);
         const T fs = fvj + uu * cotva;
-        const C TV = -(C)S2(RPV0, i) * pgf + (C)fs * (C)UU;
-        goV[idv] = (T)((C)baseV + A.ch * TV);
+        const C TV = -(C)S2(RPV0, sl) * pgf + (C)fs * (C)UU;
+        stg(A.oV, lo + oc, (T)((C)baseV + A.ch * TV));
       }
     }
     if (k + 1 < nz) commit(k + 1, (k + 1) & 1);
     __syncthreads();
   }
 
+  // surface pressure: -p0 * Pi (plus kappa* D_sa)
   if (!isPole) {
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) {
-        const size_t idx = (size_t)j * nx + i;
-        const C dsa = g.kstar != 0.0 ? ps_diffusion(A, j, i) : 0.0;
-        A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc[c] + dsa));
-      }
+    if (own) {
+      const size_t idx = (size_t)j * nx + col;
+      const C dsa = g.kstar != 0.0 ? ps_diffusion(A, j, col) : 0.0;
+      A.oP[idx] = (T)((C)A.bP[idx] + A.ch * (-g.p0 * Sc + dsa));
     }
   } else {
-    // the cap sums' LDS is free again after the level loop's last barrier
-    const C dsa = g.kstar != 0.0 ? ps_diffusion_pole(A, j, sCap) : 0.0;
+    const C dsa = g.kstar != 0.0 ? ps_diffusion_pole(A, j, red) : 0.0;
     const T val = (T)(A.pbase[pidx * (nz + 1) + nz] + A.ch * (-g.p0 * Sp + dsa));
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) A.oP[(size_t)j * nx + i] = val;
+    if (own) {
+      A.oP[(size_t)j * nx + col] = val;
+      if (col == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
     }
-    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
   }
+}
+
+// FP64 cap sums of the adaptation stage's input, one block (a wavefront) per (level, pole): the
+// flux sum_i P^V V through the V row next to the pole and sum_i (V / P^V) (l_adj - l_pole), in a
+// fixed order (lane-strided partial sums, then a butterfly), for the pole rows of adapt_tile.
+template <typename T>
+__device__ void capsum_level(const StageArgs<T>& A, int k, int p) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const T p0 = (T)g.p0;
+  const int ja = (p == 0) ? 1 : ny - 1, jva = (p == 0) ? 0 : ny - 1;
+  const T pps = (T)A.pin[(p == 0 ? 0 : nz + 1) + nz];
+  const T Pp = tsqrt<T>(pps / p0), lp = tlog<T>(pps / p0);
+  const T* pV = A.inV + ((size_t)jva * nz + k) * nx;
+  C s1 = 0, s2 = 0;
+  for (int i = threadIdx.x; i < nx; i += 64) {
+    const T psa = A.inP[(size_t)ja * nx + i];
+    const T Pa = tsqrt<T>(psa / p0), La = tlog<T>(psa / p0);
+    const T pv = T(0.5) * (Pp + Pa);
+    const T vv = pV[i];
+    s1 += (C)(pv * vv);
+    s2 += (C)((vv / pv) * (p == 0 ? (La - lp) : (lp - La)));
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (threadIdx.x == 0) {
+    A.cap[p * 2 * nz + k] = s1;
+    A.cap[p * 2 * nz + nz + k] = s2;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_capsum(StageArgs<T> a) {
+  capsum_level<T>(a, blockIdx.x, blockIdx.y);
+}
+
+// The cap sums of every batched member whose stage is an adaptation stage.
+template <typename T>
+__global__ void __launch_bounds__(64) k_capsum_batch(const StageArgs<T>* __restrict__ args, int n) {
+  const int m = blockIdx.z;
+  if (m >= n) return;
+  const StageArgs<T> a = args[m];
+  if (a.process != 0 || (int)blockIdx.x >= a.g.nz) return;
+  capsum_level<T>(a, blockIdx.x, blockIdx.y);
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -1447,36 +1119,47 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
   }
 }
 
-// One launch per stage; the process is a template parameter so that the
-// adaptation and advection kernels are separate symbols in a profile.  PROC: 0 adaptation,
-// 1 advection, 2 and 3 their pipelined forms (rows whose 27 LDS rows fit in 160 KB).
+// One launch per advection stage; the form is a template parameter so that the row kernels are
+// separate symbols in a profile.  PROC: 1 advection, 3 its pipelined form (rows whose 27 LDS rows fit
+// in 160 KB).
 template <typename T, int NI, int PROC>
 __global__ void __launch_bounds__(max_block(NI)) k_stage(StageArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int j = xcd_row(blockIdx.x, a.g.ny + 1);
-  if constexpr (PROC == 0) adapt_row<T, NI>(a, j, smem);
-  else if constexpr (PROC == 2) adapt_row_pipe<T, NI>(a, j, smem);
-  else if constexpr (PROC == 3) advect_row_pipe<T, NI>(a, j, smem);
+  if constexpr (PROC == 3) advect_row_pipe<T, NI>(a, j, smem);
   else advect_row<T, NI>(a, j, smem);
 }
 
-// Persistent batched stage: work item w = (member, row); block b takes items b, b+G, ...
-// PIPE: 1 when every member's stages take the pipelined forms, 0 when none does, 2 mixed.
+// One launch per adaptation stage: one workgroup per zonal tile (the cap sums come from k_capsum).
+template <typename T>
+__global__ void __launch_bounds__(kFwdTileMaxBlock) k_stage_tile(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const AatItem it = a.tiles[blockIdx.x];
+  if (it.j < 0) return;
+  adapt_tile<T>(a, it, smem);
+}
+
+// Persistent batched stage.  Work items: first the adaptation tiles of every member (tile item =
+// (member, index into the member's tile table)), then the advection rows (row item = (member, row));
+// a workgroup takes items b, b+G, ... and skips those whose member is not at that process in this
+// stage.  PIPE: 1 when every member's advection takes the pipelined form, 0 when none does, 2 mixed.
 template <typename T, int NI, int PIPE>
 __global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T>* __restrict__ args,
-                                                     const int2* __restrict__ items, int nitems) {
+                                                               const int2* __restrict__ titems, int ntitems,
+                                                               const int2* __restrict__ items, int nitems) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const int2 it = items[w];
+  for (int w = blockIdx.x; w < ntitems + nitems; w += gridDim.x) {
+    const bool tile = w < ntitems;
+    const int2 it = tile ? titems[w] : items[w - ntitems];
     if (it.x < 0) continue;
     const StageArgs<T> a = args[it.x];
-    if (a.process == 0) {
-      if constexpr (PIPE == 1) adapt_row_pipe<T, NI>(a, it.y, smem);
-      else if constexpr (PIPE == 0) adapt_row<T, NI>(a, it.y, smem);
-      else if (adapt_pipe_ok(a.g.nx, sizeof(T))) adapt_row_pipe<T, NI>(a, it.y, smem);
-      else adapt_row<T, NI>(a, it.y, smem);
-    }
-    else if (a.process == 1) {
+    if (tile) {
+      if (a.process != 0) continue;
+      const AatItem ti = a.tiles[it.y];
+      if (ti.j < 0) continue;
+      adapt_tile<T>(a, ti, smem);
+    } else {
+      if (a.process != 1) continue;
       if constexpr (PIPE == 1) advect_row_pipe<T, NI>(a, it.y, smem);
       else if constexpr (PIPE == 0) advect_row<T, NI>(a, it.y, smem);
       else if (advect_pipe_ok(a.g.nx, sizeof(T))) advect_row_pipe<T, NI>(a, it.y, smem);
@@ -1652,15 +1335,7 @@ template <typename T, int NI>
 hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
   const size_t lds = stage_lds_bytes(a.process, a.g.nx, sizeof(T));
   hipError_t e;
-  if (a.process == 0 && adapt_pipe_ok(a.g.nx, sizeof(T))) {
-    e = allow_lds<k_stage<T, NI, 2>>(lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage<T, NI, 2>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
-  } else if (a.process == 0) {
-    e = allow_lds<k_stage<T, NI, 0>>(lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage<T, NI, 0>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
-  } else if (advect_pipe_ok(a.g.nx, sizeof(T))) {
+  if (advect_pipe_ok(a.g.nx, sizeof(T))) {
     e = allow_lds<k_stage<T, NI, 3>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage<T, NI, 3>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
@@ -1672,37 +1347,53 @@ hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
   return hipGetLastError();
 }
 
+// An adaptation stage: the cap sums of its input, then the tiles.
+template <typename T>
+hipError_t launch_adapt_tiles(const StageArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_capsum<T>), dim3(a.g.nz, 2), dim3(64), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = adapt_tile_lds(a.tblock, sizeof(T));
+  e = allow_lds<k_stage_tile<T>>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_stage_tile<T>), dim3(a.ntiles), dim3(a.tblock), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int NI, int PIPE>
-hipError_t launch_batch_pipe(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
-                             size_t lds, hipStream_t s) {
+hipError_t launch_batch_pipe(const StageArgs<T>* d_args, const int2* d_titems, int ntitems, const int2* d_items,
+                             int nitems, int grid, int block, size_t lds, hipStream_t s) {
   hipError_t e = allow_lds<k_stage_batch<T, NI, PIPE>>(lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stage_batch<T, NI, PIPE>), dim3(grid), dim3(block), lds, s, d_args, d_items, nitems);
+  hipLaunchKernelGGL((k_stage_batch<T, NI, PIPE>), dim3(grid), dim3(block), lds, s, d_args, d_titems, ntitems,
+                     d_items, nitems);
   return hipGetLastError();
 }
 
 template <typename T, int NI>
-hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
-                           size_t lds, int pipe, hipStream_t s) {
-  if (pipe == 1) return launch_batch_pipe<T, NI, 1>(d_args, d_items, nitems, grid, block, lds, s);
-  if (pipe == 2) return launch_batch_pipe<T, NI, 2>(d_args, d_items, nitems, grid, block, lds, s);
-  return launch_batch_pipe<T, NI, 0>(d_args, d_items, nitems, grid, block, lds, s);
+hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_titems, int ntitems, const int2* d_items,
+                           int nitems, int grid, int block, size_t lds, int pipe, hipStream_t s) {
+  if (pipe == 1) return launch_batch_pipe<T, NI, 1>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, s);
+  if (pipe == 2) return launch_batch_pipe<T, NI, 2>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, s);
+  return launch_batch_pipe<T, NI, 0>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, s);
 }
 
 }  // namespace
 
 size_t stage_lds_bytes(int process, int nx, int elem) {
-  if (process == 0 && adapt_pipe_ok(nx, elem)) return adapt_pipe_lds(nx, elem);
-  if (process == 1 && advect_pipe_ok(nx, elem)) return advect_pipe_lds(nx, elem);
+  if (process == 0) return adapt_tile_lds(elem == 4 ? kFwdTileMaxBlock : 704, elem);   // the largest tile block
+  if (advect_pipe_ok(nx, elem)) return advect_pipe_lds(nx, elem);
   const size_t rows = 12;
   return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 2 * 128 * sizeof(double);
 }
 
 int columns_per_thread(int nx, int block) { return (nx + block - 1) / block; }
-int stage_pipelined(int nx, int elem) { return adapt_pipe_ok(nx, elem) && advect_pipe_ok(nx, elem) ? 1 : 0; }
+size_t adapt_tile_lds_bytes(int block, int elem) { return adapt_tile_lds(block, elem); }
+int stage_pipelined(int nx, int elem) { return advect_pipe_ok(nx, elem) ? 1 : 0; }
 
 template <typename T>
 hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
+  if (a.process == 0) return launch_adapt_tiles<T>(a, s);
   switch (columns_per_thread(a.g.nx, block)) {
     case 1: return launch_stage_ni<T, 1>(a, block, s);
     case 2: return launch_stage_ni<T, 2>(a, block, s);
@@ -1717,17 +1408,21 @@ hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_stage_batch(const StageArgs<T>* d_args, const int2* d_items, int nitems, int grid, int block,
-                              int max_nx, size_t lds, int pipe, hipStream_t s) {
+hipError_t launch_stage_batch(const StageArgs<T>* d_args, int nargs, int max_nz, const int2* d_titems, int ntitems,
+                              const int2* d_items, int nitems, int grid, int block, int max_nx, size_t lds, int pipe,
+                              hipStream_t s) {
+  hipLaunchKernelGGL((k_capsum_batch<T>), dim3(max_nz, 2, nargs), dim3(64), 0, s, d_args, nargs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   switch (columns_per_thread(max_nx, block)) {
-    case 1: return launch_batch_ni<T, 1>(d_args, d_items, nitems, grid, block, lds, pipe, s);
-    case 2: return launch_batch_ni<T, 2>(d_args, d_items, nitems, grid, block, lds, pipe, s);
-    case 3: return launch_batch_ni<T, 3>(d_args, d_items, nitems, grid, block, lds, pipe, s);
-    case 4: return launch_batch_ni<T, 4>(d_args, d_items, nitems, grid, block, lds, pipe, s);
-    case 5: return launch_batch_ni<T, 5>(d_args, d_items, nitems, grid, block, lds, pipe, s);
-    case 6: return launch_batch_ni<T, 6>(d_args, d_items, nitems, grid, block, lds, pipe, s);
-    case 7: return launch_batch_ni<T, 7>(d_args, d_items, nitems, grid, block, lds, pipe, s);
-    case 8: return launch_batch_ni<T, 8>(d_args, d_items, nitems, grid, block, lds, pipe, s);
+    case 1: return launch_batch_ni<T, 1>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
+    case 2: return launch_batch_ni<T, 2>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
+    case 3: return launch_batch_ni<T, 3>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
+    case 4: return launch_batch_ni<T, 4>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
+    case 5: return launch_batch_ni<T, 5>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
+    case 6: return launch_batch_ni<T, 6>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
+    case 7: return launch_batch_ni<T, 7>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
+    case 8: return launch_batch_ni<T, 8>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1775,8 +1470,8 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s) {
 
 #define DYC_INST(T)                                                                                          \
   template hipError_t launch_stage<T>(const StageArgs<T>&, int, hipStream_t);                                \
-  template hipError_t launch_stage_batch<T>(const StageArgs<T>*, const int2*, int, int, int, int, size_t, int,  \
-                                            hipStream_t);                                                    \
+  template hipError_t launch_stage_batch<T>(const StageArgs<T>*, int, int, const int2*, int, const int2*, int,   \
+                                            int, int, int, size_t, int, hipStream_t);                        \
   template hipError_t launch_pole_prep<T>(const GeoDev&, const T*, const T*, double*, hipStream_t);          \
   template hipError_t launch_diag<T>(const GeoDev&, const T*, const T*, const T*, const T*, double*, double*, \
                                      hipStream_t);                                                           \
