@@ -800,10 +800,17 @@ __device__ __forceinline__ void l1_point(const Ctx<T>& c, int j, int k, int i) {
   if (tr(k >= 1)) stg(c.s.ASD, ihu(g, j, k, i), (T)oSD);
 }
 
+// Largest divisor of nz up to 8: the level blocks of the advection transposes' launch order.
+__host__ __device__ constexpr int level_block(int nz) {
+  for (int d = 8; d > 1; --d)
+    if (nz % d == 0) return d;
+  return 1;
+}
+
 template <typename T>
 __global__ void k_l1(Ctx<T> c) {
   int tx, k, j;
-  xcd_tile3((int)gridDim.x, c.g.nz, c.g.ny + 1, tx, k, j);
+  xcd_tile3_kb((int)gridDim.x, c.g.nz, c.g.ny + 1, level_block(c.g.nz), tx, k, j);
   const int i = tx * blockDim.x + threadIdx.x;
   if (i >= c.g.nx) return;
   if (j >= 2 && j <= c.g.ny - 2 && k >= 1 && k + 1 < c.g.nz) l1_point<T, true>(c, j, k, i);

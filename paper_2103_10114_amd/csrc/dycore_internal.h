@@ -187,6 +187,24 @@ __device__ __forceinline__ void xcd_tile3(int gx, int nz, int nrows, int& x, int
 
 
 
+// As xcd_tile3, with the levels in blocks of KB (KB divides nz): the tuples run (level block, row,
+// level in the block, tile), tile fastest, so that a point's neighbours at rows j+-1 and levels k+-1
+// were read a few dozen workgroups earlier on the same XCD, and the working set of the rows in
+// flight (every field a point reads, KB levels deep) stays well inside an XCD's L2.
+__device__ __forceinline__ void xcd_tile3_kb(int gx, int nz, int nrows, int KB, int& x, int& k, int& j) {
+  const int b = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+  const int total = gx * nz * nrows;
+  const int xc = b & 7, slot = b >> 3;
+  const int q = total >> 3, rem = total & 7;
+  const int tup = xc * q + (xc < rem ? xc : rem) + slot;
+  const int per_block = nrows * KB * gx;
+  const int kb = tup / per_block, r = tup - kb * per_block;
+  j = r / (KB * gx);
+  const int r2 = r - j * (KB * gx);
+  k = kb * KB + r2 / gx;
+  x = r2 % gx;
+}
+
 // What the adjoint translation unit sees of a handle.
 struct HandleView {
   GeoDev g;
