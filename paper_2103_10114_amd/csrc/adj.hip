@@ -70,13 +70,19 @@ struct Ctx {
   double ch;
   Scr<T> s;
   GeoFac f;                        // difference factors of the forward stages
-  int jr0 = 0, jrs = 1;            // rows a launch covers: jr0 + jrs * (grid row index)
+  int jr0 = 0, jrs = 1;            // rows a launch covers: jr0 + jrs * (grid row index), or with
+  int rsplit = 0;                  // rsplit > 0: grid rows r < rsplit are rows r, the rest the last
+                                   // rows (ny - (grid rows - 1 - r))
   int blk = 0;                     // workgroup size of the row-fused kernel (the handle's)
   int parts = 7;                   // first adaptation transposes: 1 scalar point (+ suffix), 2 U, 4 V
   KTimer* timer = nullptr;         // host side: times the row-fused kernel's launches when armed
   const AatItem* aat = nullptr;    // work items of the tiled row-fused adaptation adjoint (NULL: per point)
   int aat_n = 0;                   // item count
   int aat_blk = 0;                 // threads per tile workgroup
+  const AatItem* adt = nullptr;    // work items of the tiled row-fused advection adjoint (NULL: per point)
+  int adt_n = 0, adt_blk = 0;      // their count and workgroup size (rows with halos up to 112 columns)
+  int pp_n = 0, pp_s = 0;          // with it: rows 1..pp_n and ny-pp_s..ny-1 (halos too wide for its
+                                   // tiles) run the per-point kernels with the pole rows
   int fwd_all = 1;                 // forward recompute of R T', phi', omega/p too (0: D, S, sigma-dot only)
   int ai_zero = 0;                 // the input adjoint starts at zero and, in its interior rows, only the
                                    // row-fused kernel adds to it: those rows are stored without a read
@@ -84,6 +90,13 @@ struct Ctx {
   int base_in_tail = 0;            // advection with one base and input adjoint: the interior base transpose
                                    // is added by the column tail (k_l3, k_t3) instead of k_base
 };
+
+// The row of grid row r of a launch over nrows rows (Ctx::jr0, jrs, rsplit).
+template <typename T>
+__device__ __forceinline__ int row_of(const Ctx<T>& c, int r, int nrows) {
+  if (c.rsplit > 0) return r < c.rsplit ? r : c.g.ny - (nrows - 1 - r);
+  return c.jr0 + c.jrs * r;
+}
 
 template <typename T>
 __device__ __forceinline__ size_t i3(const GeoDev& g, int j, int k, int i) {
@@ -211,12 +224,46 @@ __global__ void k_f1(Ctx<T> c) {
   // advection: u at the U point and v sin(theta) on V row j, as k_uv forms them (rows 1..ny-1)
   const T rPU2 = all ? T(0) : T(2) / (P0 + P2(c, j, wrp(i + 1, nx)));
   const T rPVs = all ? T(0) : T(1) / (T(0.5) * (P2(c, j, i) + P2(c, j + 1, i)));
-  stg(c.s.S, ihu(g, j, 0, i), T(0));
+  // advection with the row-fused tail: the sigma-dot transposes of the column are formed here too
+  // (the adjoint of sigma-dot at each half level, then aPi, the adjoint of the divergence and the
+  // column's P share), from the output adjoints and the state at this column and its western
+  // neighbour, with the same arithmetic as the per-point form.  u and v sin(theta) are then stored
+  // only for the rows that the per-point kernels of the polar rows read (the row-fused kernel forms
+  // them itself), and S not at all.
+  const bool asdm = !all && c.adt != nullptr;
+  const bool keep_uv = !all && (!asdm || j <= c.pp_n + 1 || j >= g.ny - c.pp_s - 1);
+  using A = T;
+  const A chA = (A)c.ch;
+  A qF = 0, xF = 0, qU = 0, xU = 0, qUw = 0, xUw = 0, qVm = 0, xVm = 0, qV = 0, xV = 0;   // level k-1
+  const C rP2c = 1.0 / ((C)P0 * (C)P0);
+  C aPi = 0, aSt = 0;   // aPi and the column sum of aS_h = -asd_h / P^2
+  if (!asdm) stg(c.s.S, ihu(g, j, 0, i), T(0));
   for (int k = 0; k < nz; ++k) {
     const unsigned id = i3u(g, j, k, i);
-    if (!all) {
+    if (keep_uv) {
       stg(c.s.UA, id, ldg(c.U, id) * rPU2);
       stg(c.s.VT, id, ldg(c.V, id) * rPVs * (T)g.sv[j]);
+    }
+    if (asdm) {
+      const unsigned idw = i3u(g, j, k, im1), idm = i3u(g, j - 1, k, i);
+      const A aF = -chA * (A)ldg(c.aoF, id), vF = ldg(c.F, id);
+      const A aU = -chA * (A)ldg(c.aoU, id), vU = ldg(c.U, id);
+      const A aUw = -chA * (A)ldg(c.aoU, idw), vUw = ldg(c.U, idw);
+      const A aVm = -chA * (A)ldg(c.aoV, idm), vVm = ldg(c.V, idm);
+      const A aV = -chA * (A)ldg(c.aoV, id), vV = ldg(c.V, id);
+      if (k >= 1) {
+        const A r0 = (A)c.f.r2d[k - 1], r1 = (A)c.f.r2d[k];
+        A a = 0;
+        a += qF * vF * r0 - aF * xF * r1;
+        const A su = qU * vU * r0 - aU * xU * r1, sw = qUw * vUw * r0 - aUw * xUw * r1;
+        a += A(0.5) * (su + sw);
+        a += A(0.5) * (qVm * vVm * r0 - aVm * xVm * r1);
+        a += A(0.5) * (qV * vV * r0 - aV * xV * r1);
+        stg(c.s.ASD, ihu(g, j, k, i), (T)a);
+        aPi += g.sigh[k] * (C)(T)a * rP2c;
+        aSt += -(C)(T)a * rP2c;
+      }
+      qF = aF; xF = vF; qU = aU; xU = vU; qUw = aUw; xUw = vUw; qVm = aVm; xVm = vVm; qV = aV; xV = vV;
     }
     if (all) {
       const T RT = b * Fe(c, j, k, i) / P0;
@@ -227,7 +274,7 @@ __global__ void k_f1(Ctx<T> c) {
                 ((T)g.sv[j] * (PV0 * Ve(c, j, k, i)) - (T)g.sv[j - 1] * (PVm * Ve(c, j - 1, k, i))) / dyS;
     stg(c.s.D, id, D);
     S += (C)D * g.dsig[k];
-    stg(c.s.S, ihu(g, j, k + 1, i), (T)S);
+    if (!asdm) stg(c.s.S, ihu(g, j, k + 1, i), (T)S);
   }
   const C Pi = S;
   C R = 0, Sk = 0;
@@ -237,6 +284,10 @@ __global__ void k_f1(Ctx<T> c) {
     l0 = c.s.L[(size_t)j * nx + i]; l1 = c.s.L[(size_t)(j + 1) * nx + i]; lm = c.s.L[(size_t)(j - 1) * nx + i];
     dl0 = c.s.DL[(size_t)j * nx + i]; dlm = c.s.DL[(size_t)j * nx + im1];
   }
+  // sigma-dot transposes, top-down: aD_l = dsig_l (aPi + sum_{h>l} aS_h), the suffix sum being the
+  // column sum less the levels above; the P share sums -2 (sigma_h Pi - S_h) asd_h / P^3
+  const C Pt = (C)(T)Pi, rP3 = rP2c / (C)P0;
+  C pre = 0, aP = 0;
   stg(c.s.SD, ihu(g, j, 0, i), T(0));
   for (int k = 0; k < nz; ++k) {
     const unsigned id = i3u(g, j, k, i);
@@ -249,9 +300,18 @@ __global__ void k_f1(Ctx<T> c) {
       const T mer = T(0.5) * ((Ve(c, j, k, i) / PV0) * (l1 - l0) + (Ve(c, j - 1, k, i) / PVm) * (l0 - lm)) / dyA;
       stg(c.s.WP, id, (T)(((C)zon + (C)mer) - (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s)));
     }
+    if (asdm) {
+      if (k >= 1) {
+        const C a = (C)ldg((const T*)c.s.ASD, ihu(g, j, k, i));
+        pre += -a * rP2c;
+        aP += -2.0 * (g.sigh[k] * Pt - (C)(T)Sk) * rP3 * a;
+      }
+      stg(c.s.AD, id, (T)(g.dsig[k] * (aPi + (aSt - pre))));
+    }
     Sk += D * g.dsig[k];
     stg(c.s.SD, ihu(g, j, k + 1, i), (k + 1 < nz) ? (T)((g.sigh[k + 1] * Pi - Sk) / P0s) : T(0));
   }
+  if (asdm) c.s.AP2[(size_t)j * nx + i] = aP;
 }
 
 // pole columns, step 1: per (pole, level) cap divergence and zonal-mean v.grad(l) (FP64, one block each)
@@ -809,8 +869,9 @@ __host__ __device__ constexpr int level_block(int nz) {
 
 template <typename T>
 __global__ void k_l1(Ctx<T> c) {
-  int tx, k, j;
-  xcd_tile3_kb((int)gridDim.x, c.g.nz, c.g.ny + 1, level_block(c.g.nz), tx, k, j);
+  int tx, k, jy;
+  xcd_tile3_kb((int)gridDim.x, c.g.nz, (int)gridDim.z, level_block(c.g.nz), tx, k, jy);
+  const int j = row_of(c, jy, (int)gridDim.z);
   const int i = tx * blockDim.x + threadIdx.x;
   if (i >= c.g.nx) return;
   if (j >= 2 && j <= c.g.ny - 2 && k >= 1 && k + 1 < c.g.nz) l1_point<T, true>(c, j, k, i);
@@ -821,7 +882,7 @@ __global__ void k_l1(Ctx<T> c) {
 template <typename T>
 __global__ void k_l2(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.y;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nz = g.nz;
@@ -951,8 +1012,9 @@ __global__ void k_a4(Ctx<T> c) {
 template <typename T>
 __global__ void k_l3(Ctx<T> c) {
   const GeoDev& g = c.g;
-  int tx, k0, j;
-  xcd_tile3((int)gridDim.x, 1, (int)gridDim.y, tx, k0, j);
+  int tx, k0, jy;
+  xcd_tile3((int)gridDim.x, 1, (int)gridDim.y, tx, k0, jy);
+  const int j = row_of(c, jy, (int)gridDim.y);
   int i = tx * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -1102,6 +1164,278 @@ __global__ void k_t4(Ctx<T> c) {
   for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
     if (k < g.nz) c.aiF[i3<T>(g, j, k, i)] += add;
     else c.aiP[(size_t)j * g.nx + i] += add;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Advection-stage adjoint, row-fused and tiled (interior rows whose halos fit 256 threads with 32
+// owned columns; the few next to the poles on fine grids go with the pole rows through the per-point
+// kernels).  The forward recompute has formed sigma-dot and, per column, the sigma-dot transposes
+// down to the adjoint of the divergence (AD).  One workgroup per work item (row j, a zonal tile of w
+// owned columns and a halo of hl = max(M_j, Mv_j, nv_{j-1}) columns on each side: the reach of the
+// leaped advection transposes, whose centred differences span 2 M; one column per thread) walks the
+// levels top to bottom.  Per level every slot stages the output adjoints of Phi, U and V rows j-1/2,
+// j+1/2 (times -ch), the state they multiply, u of U rows j and j+1 (formed here from U and P, as
+// the per-point kernels store it) and AD of row j in LDS; the owned columns then
+// gather the transposes of every advection term that reads their Phi, U and V points (zonal leap
+// offsets from LDS, the meridional and vertical neighbours from global memory, with the per-point
+// form's arithmetic and order), and apply the divergence and velocity transposes into U and V with
+// the column sums of the staggered-P adjoints, as the per-point column tail does.  Level rows are
+// double-buffered (one barrier per level); the next level's slot values are fetched while the
+// current one is computed.
+// ------------------------------------------------------------------------------------------------
+constexpr int kAdtLev = 11;   // per-level LDS rows (odd: consecutive slots stride an odd word count)
+__host__ __device__ constexpr size_t adt_lds(int block, int elem) { return (size_t)2 * kAdtLev * block * elem; }
+
+template <typename T>
+struct AdtLev { T aF, F, aU, U, aVm, Vm, aV, V, U1, AD; };
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adt(Ctx<T> c) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const AatItem it = c.adt[blockIdx.x];
+  if (it.j < 0) return;
+  const GeoDev& g = c.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int j = it.j, hl = it.hl, w = it.w;
+  const int NS = w + 2 * hl;                 // slots of the tile, halo included
+  const int sl = threadIdx.x;                // this thread's slot
+  const bool act = sl < NS;                  // slots past NS only meet the barriers
+  const bool own = sl >= hl && sl < hl + w;  // owned column: the gathers and every global write
+  int col = (it.i0 - hl + sl) % nx;
+  if (col < 0) col += nx;
+  const unsigned ui = (unsigned)col, uim = (unsigned)(col == 0 ? nx - 1 : col - 1);
+  const unsigned uip = (unsigned)(col == nx - 1 ? 0 : col + 1);
+  T* lb0 = reinterpret_cast<T*>(smem);
+  T* lb1 = lb0 + kAdtLev * blockDim.x;
+  enum { LaF, LF, LaU, LU, LaVm, LVm, LaV, LV, LuA, LuA1, LAD };
+  using A = T;
+  const bool nIn = j >= 2;            // scalar/U row j-1 is interior
+  const bool sIn = j + 1 <= ny - 1;   // scalar/U row j+1 is interior
+  const bool sPole = j + 1 == ny;
+  const A ch = (A)c.ch;
+  const int M = g.M[j], n = (M + 1) / 2;
+  const int Mv = g.Mv[j], nv = (Mv + 1) / 2;
+  const int nvm = (g.Mv[j - 1] + 1) / 2;
+  // the forward's difference factors (rounded to the field precision)
+  const A rdx2j = (A)(0.5 * c.f.rdx[j]), rdy2j = (A)(0.5 * c.f.rdy[j]);
+  const A rdy2m = nIn ? (A)(0.5 * c.f.rdy[j - 1]) : A(0), rdy2p = sIn ? (A)(0.5 * c.f.rdy[j + 1]) : A(0);
+  const A rdxv2m = (A)c.f.rdxv2[j - 1], rdxv2j = (A)c.f.rdxv2[j];
+  const A rdyv2m = (A)c.f.rdyv2[j - 1], rdyv2j = (A)c.f.rdyv2[j], rdyv2p = sIn ? (A)c.f.rdyv2[j + 1] : A(0);
+  const A cc = (A)(g.a * g.dlam / (2.0 * g.acap));
+  const A svA = (A)g.sv[j];
+  const double* sF = c.s.psum + PS_AOF * 2 * (nz + 1);
+  const double* sD = c.s.psum + PS_AD * 2 * (nz + 1);
+  // column tail constants (FP64; reciprocals: the level loop only multiplies)
+  const C rdxU = 1.0 / (C)(T)((double)M * g.a * g.s[j] * g.dlam);
+  const C rdyN = 1.0 / (C)(T)(g.a * g.s[j] * g.dth);
+  const C rdyS = sIn ? 1.0 / (C)(T)(g.a * g.s[j + 1] * g.dth) : 1.0;
+  const C capD = g.a * g.dlam / g.acap;
+  const C svj = (C)(T)g.sv[j];
+  const unsigned row3 = (unsigned)(nz * nx), rowh = (unsigned)((nz + 1) * nx);
+  const unsigned oJ = (unsigned)j * row3, oJm = oJ - row3, oJ1 = oJ + row3;
+  const unsigned ohJ = (unsigned)j * rowh, ohJ1 = ohJ + rowh;
+  // 2D factors: 1 / P^U of U rows j and j+1 at this slot (u = U / P^U, as the per-point kernels store
+  // it); for the owned columns 1 / P^V of V rows j-1/2 .. j+3/2 here and east (v sin(theta)) and the
+  // tail's P^U, P^V
+  T ruj = 0, ru1 = 0;
+  T rvm = 0, rvmE = 0, rv0 = 0, rv0E = 0, rv1 = 0;
+  C PU = 1, rPU = 1, PV = 1, rPV = 1;
+  if (act) {
+    const unsigned r0 = (unsigned)j * (unsigned)nx;
+    const T P0 = ldg(c.s.P, r0 + ui), P0p = ldg(c.s.P, r0 + uip);
+    const T P1 = ldg(c.s.P, r0 + nx + ui), P1p = ldg(c.s.P, r0 + nx + uip);
+    ruj = T(2) / (P0 + P0p);
+    if (!sPole) ru1 = T(2) / (P1 + P1p);
+    if (own) {
+      const T Pm = ldg(c.s.P, r0 - nx + ui), Pmp = ldg(c.s.P, r0 - nx + uip);
+      rvm = T(1) / (T(0.5) * (Pm + P0));
+      rvmE = T(1) / (T(0.5) * (Pmp + P0p));
+      rv0 = T(1) / (T(0.5) * (P0 + P1));
+      rv0E = T(1) / (T(0.5) * (P0p + P1p));
+      if (sIn) rv1 = T(1) / (T(0.5) * (P1 + ldg(c.s.P, r0 + 2 * nx + ui)));
+      PU = (C)(T(0.5) * (P0 + P0p));
+      rPU = 1.0 / PU;
+      PV = (C)(T(0.5) * (P0 + P1));
+      rPV = 1.0 / PV;
+    }
+  }
+  const T svm = (T)g.sv[j - 1], sv0 = (T)g.sv[j], sv1 = sIn ? (T)g.sv[j + 1] : T(0);
+  auto load_lev = [&](int k, AdtLev<T>& v) {
+    const unsigned lv = (unsigned)(k * nx) + ui;
+    v.aF = ldg(c.aoF, oJ + lv);
+    v.F = ldg(c.F, oJ + lv);
+    v.aU = ldg(c.aoU, oJ + lv);
+    v.U = ldg(c.U, oJ + lv);
+    v.aVm = ldg(c.aoV, oJm + lv);
+    v.Vm = ldg(c.V, oJm + lv);
+    v.aV = ldg(c.aoV, oJ + lv);
+    v.V = ldg(c.V, oJ + lv);
+    v.U1 = sPole ? T(0) : ldg(c.U, oJ1 + lv);
+    v.AD = ldg(c.s.AD, oJ + lv);
+  };
+  AdtLev<T> cur{}, nxt{};
+  if (act) load_lev(0, cur);
+  A pF = 0, pU = 0, pV = 0;        // owned column: -ch a_out of Phi, U, V (row j) at level k-1
+  T sdk = 0, sdkp = 0, sd1k = 0;   // sigma-dot at half level k: this column, its east neighbour, row j+1
+  C aPU = 0, aPV = 0;
+#pragma unroll 1
+  for (int k = 0; k < nz; ++k) {
+    T* L = (k & 1) ? lb1 : lb0;
+    const unsigned lv = (unsigned)(k * nx);
+    if (act && k + 1 < nz) load_lev(k + 1, nxt);
+    // owned column: the meridional neighbours, sigma-dot at half level k+1, the accumulators
+    T aFm = 0, aUm = 0, aFp = 0, Fp = 0, aUp = 0, aUpw = 0, Up = 0, Upw = 0, aVp = 0, Vp = 0;
+    T ADp = 0, sdn = 0, sdnp = 0, sd1n = 0;
+    T aiU0 = 0, aiV0 = 0, aiF0 = 0;
+    if (own) {
+      const unsigned o = oJ + lv + ui, ow = oJ + lv + uim, op = oJ + lv + uip;
+      if (nIn) {
+        aFm = ldg(c.aoF, o - row3);
+        aUm = ldg(c.aoU, o - row3);
+      }
+      Fp = sPole ? (T)c.pin[(nz + 1) + k] : ldg(c.F, o + row3);
+      if (sIn) {
+        aFp = ldg(c.aoF, o + row3);
+        aUp = ldg(c.aoU, o + row3);
+        aUpw = ldg(c.aoU, ow + row3);
+        Up = ldg(c.U, o + row3);
+        Upw = ldg(c.U, ow + row3);
+        aVp = ldg(c.aoV, o + row3);
+        Vp = ldg(c.V, o + row3);
+        ADp = ldg(c.s.AD, o + row3);
+      }
+      (void)op;
+      if (k + 1 < nz) {
+        const unsigned h = (unsigned)((k + 1) * nx);
+        sdn = ldg(c.s.SD, ohJ + h + ui);
+        sdnp = ldg(c.s.SD, ohJ + h + uip);
+        sd1n = ldg(c.s.SD, ohJ1 + h + ui);
+      }
+      if (!c.ai_zero) {
+        aiU0 = ldg(c.aiU, o);
+        aiV0 = ldg(c.aiV, o);
+        aiF0 = ldg(c.aiF, o);
+      }
+    }
+    if (act) {
+      T* q = L + sl * kAdtLev;
+      q[LaF] = -ch * (A)cur.aF;
+      q[LF] = cur.F;
+      q[LaU] = -ch * (A)cur.aU;
+      q[LU] = cur.U;
+      q[LaVm] = -ch * (A)cur.aVm;
+      q[LVm] = cur.Vm;
+      q[LaV] = -ch * (A)cur.aV;
+      q[LV] = cur.V;
+      q[LuA] = cur.U * ruj;
+      q[LuA1] = cur.U1 * ru1;
+      q[LAD] = cur.AD;
+    }
+    __syncthreads();
+    if (own) {
+      auto R = [&](int row, int s) -> A { return (A)L[s * kAdtLev + row]; };
+      const int s = sl;
+      const A aF0 = R(LaF, s), aU0 = R(LaU, s), aVm0 = R(LaVm, s), aV0 = R(LaV, s);
+      const A F0 = cur.F, U0 = cur.U, Vm0 = cur.Vm, V0 = cur.V;
+      // v sin(theta) on V rows j-1/2 (here and east), j+1/2 (here and east), j+3/2
+      const T vAm = cur.Vm * rvm * svm, vAmp = L[(s + 1) * kAdtLev + LVm] * rvmE * svm;
+      const T vA0 = cur.V * rv0 * sv0, vA0p = L[(s + 1) * kAdtLev + LV] * rv0E * sv0;
+      const T vAp = Vp * rv1 * sv1;
+      const bool up = k >= 1, dn = k + 1 < nz;
+      const A nF = dn ? -ch * (A)nxt.aF : A(0), nU = dn ? -ch * (A)nxt.aU : A(0), nV = dn ? -ch * (A)nxt.aV : A(0);
+      const A r2m = up ? (A)c.f.r2d[k - 1] : A(0), r2p = dn ? (A)c.f.r2d[k + 1] : A(0);
+      const A AN = (A)(-c.ch * sF[0 * (nz + 1) + k]), AS = (A)(-c.ch * sF[1 * (nz + 1) + k]);
+      // ---- scalar point: adjoint of Phi
+      A aFE = (R(LaF, s - M) * R(LuA, s - n) - R(LaF, s + M) * R(LuA, s + n - 1)) * rdx2j;
+      if (nIn) aFE += (-ch * (A)aFm) * (A)vAm * rdy2m;
+      if (sIn) aFE -= (-ch * (A)aFp) * (A)vA0 * rdy2p;
+      if (j == 1) aFE += cc * (A)vAm * AN;
+      if (j == ny - 1) aFE -= cc * (A)vA0 * AS;
+      if (up) aFE += pF * (A)sdk * r2m;
+      if (dn) aFE -= nF * (A)sdn * r2p;
+      // ---- U point: adjoint of u
+      A au = (R(LaF, s - n + 1) * R(LF, s + n) - R(LaF, s + n) * R(LF, s - n + 1)) * rdx2j;
+      {
+        auto aub = [&](int q) -> A {
+          return (R(LaU, q - n) * R(LU, q + n - 1) - R(LaU, q + n - 1) * R(LU, q - n)) * rdx2j;
+        };
+        au += A(0.5) * (aub(s) + aub(s + 1));
+        const A auvm = (R(LaVm, s - nvm + 1) * R(LVm, s + nvm) - R(LaVm, s + nvm) * R(LVm, s - nvm + 1)) * rdxv2m;
+        au += A(0.5) * auvm;
+        const A auvj = (R(LaV, s - nv + 1) * R(LV, s + nv) - R(LaV, s + nv) * R(LV, s - nv + 1)) * rdxv2j;
+        au += A(0.5) * auvj;
+      }
+      // direct adjoint of U
+      A aUd;
+      {
+        auto ub = [&](int q) -> A { return A(0.5) * (R(LuA, q - 1) + R(LuA, q)); };
+        aUd = (R(LaU, s - M) * ub(s - n + 1) - R(LaU, s + M) * ub(s + n)) * rdx2j;
+        if (nIn) aUd += (-ch * (A)aUm) * (A(0.5) * ((A)vAm + (A)vAmp)) * rdy2m;
+        if (sIn) aUd -= (-ch * (A)aUp) * (A(0.5) * ((A)vA0 + (A)vA0p)) * rdy2p;
+        if (up) aUd += pU * (A(0.5) * ((A)sdk + (A)sdkp)) * r2m;
+        if (dn) aUd -= nU * (A(0.5) * ((A)sdn + (A)sdnp)) * r2p;
+      }
+      // ---- V point (row j+1/2): direct adjoint of V
+      A aVd;
+      {
+        auto uv = [&](int q) -> A { return A(0.5) * (R(LuA, q) + R(LuA1, q)); };
+        aVd = (R(LaV, s - Mv) * uv(s - nv) - R(LaV, s + Mv) * uv(s + nv - 1)) * rdxv2j;
+        aVd += aVm0 * (A(0.5) * ((A)vAm + (A)vA0)) * rdyv2m;
+        if (sIn) aVd -= (-ch * (A)aVp) * (A(0.5) * ((A)vA0 + (A)vAp)) * rdyv2p;
+        if (up) aVd += pV * (A(0.5) * ((A)sdk + (A)sd1k)) * r2m;
+        if (dn) aVd -= nV * (A(0.5) * ((A)sdn + (A)sd1n)) * r2p;
+      }
+      // adjoint of v sin(theta) on this V row
+      A avt = aF0 * (A)Fp * rdy2j;
+      if (sIn) avt -= (-ch * (A)aFp) * F0 * rdy2p;
+      if (j == ny - 1) avt -= cc * F0 * AS;
+      {
+        auto avtu = [&](A aUj, A Uj, A aUn, A Un) -> A {
+          A r = 0;
+          r += aUj * Un * rdy2j;
+          if (sIn) r -= aUn * Uj * rdy2p;
+          return r;
+        };
+        avt += A(0.5) * (avtu(aU0, U0, -ch * (A)aUp, (A)Up) + avtu(R(LaU, s - 1), R(LU, s - 1), -ch * (A)aUpw, (A)Upw));
+        const A avs0 = aVm0 * V0 * rdyv2m - aV0 * Vm0 * rdyv2j;
+        const A avs1 = sIn ? aV0 * (A)Vp * rdyv2j - (-ch * (A)aVp) * V0 * rdyv2p : A(0);
+        avt += A(0.5) * (avs0 + avs1);
+      }
+      const A aVV = avt * svA;
+      // ---- divergence and velocity transposes into U and V, column sums (the per-point tail)
+      const unsigned o = oJ + lv + ui;
+      const bool bt = c.base_in_tail;
+      const C aMU = ((C)R(LAD, s - n + 1) - (C)R(LAD, s + n)) * rdxU;
+      const C Uc = (C)U0;
+      stg(c.aiU, o, (T)((C)aiU0 + (bt ? (C)cur.aU : 0.0) + (C)aUd + (C)au * rPU + PU * aMU));
+      aPU += -Uc * (rPU * rPU) * (C)au + Uc * aMU;
+      const C tN = (C)cur.AD * rdyN;
+      const C tS = sIn ? (C)ADp * rdyS : capD * sD[1 * (nz + 1) + k];
+      const C aMV = svj * (tN - tS);
+      const C Vc = (C)V0;
+      stg(c.aiV, o, (T)((C)aiV0 + (bt ? (C)cur.aV : 0.0) + (C)aVd + (C)aVV * rPV + PV * aMV));
+      aPV += -Vc * (rPV * rPV) * (C)aVV + Vc * aMV;
+      stg(c.aiF, o, (T)((C)aiF0 + (bt ? (C)cur.aF : 0.0) + (C)aFE));
+      pF = aF0;
+      pU = aU0;
+      pV = aV0;
+    }
+    sdk = sdn;
+    sdkp = sdnp;
+    sd1k = sd1n;
+    cur = nxt;
+    // no second barrier: the next level's slot rows go to the other buffer, and the level after that
+    // writes this one only past the next barrier, which every wave reaches after these gathers
+  }
+  if (own) {
+    const size_t i2 = (size_t)j * nx + col;
+    c.s.APU2[i2] = aPU;
+    c.s.APV2[i2] = aPV;
+    c.s.AL2[i2] = 0;
+    c.s.AQ2[i2] = 0;
+    c.s.ADL2[i2] = 0;
+    c.s.ADQ2[i2] = 0;
   }
 }
 
@@ -1524,6 +1858,20 @@ hipError_t launch_aar(const Ctx<T>& c, hipStream_t s) {
   return hipSuccess;
 }
 
+// The tiled row-fused advection adjoint serves every grid whose rows' halos fit (the handle then
+// holds its work items).
+template <typename T>
+bool adt_used(const Ctx<T>& c) {
+  return c.adt != nullptr && c.adt_n > 0;
+}
+
+template <typename T>
+hipError_t launch_adt(const Ctx<T>& c, hipStream_t s) {
+  const size_t lds = adt_lds(c.adt_blk, (int)sizeof(T));
+  hipLaunchKernelGGL((k_adt<T>), dim3(c.adt_n), dim3(c.adt_blk), lds, s, c);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   const GeoDev& g = c.g;
@@ -1597,18 +1945,32 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
-  {
-    // u and v sin(theta) of rows 1..ny-1 come from the forward recompute (k_f1); here the pole rows
-    Ctx<T> cu = c;
-    cu.jr0 = 0;
-    cu.jrs = ny;
-    hipLaunchKernelGGL((k_uv<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cu);
+  // u and v sin(theta) of rows 1..ny-1 come from the forward recompute (k_f1); here the pole rows
+  Ctx<T> cp = c;
+  cp.jr0 = 0;
+  cp.jrs = ny;
+  hipLaunchKernelGGL((k_uv<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
+  if (adt_used(c)) {
+    // the pole rows and the rows next to them whose halos do not fit the tiles (rows 0..pp_n and
+    // ny-pp_s..ny) through the per-point kernels; the interior rows' sigma-dot transposes came with
+    // the forward recompute (k_l2 serves the pole rows), the other rows are row-fused
+    Ctx<T> cw = c;
+    cw.rsplit = c.pp_n + 1;
+    const int nw = c.pp_n + c.pp_s + 2;
+    hipLaunchKernelGGL((k_l1<T>), dim3(gx, nz, nw), dim3(tb), 0, s, cw);
+    hipLaunchKernelGGL((k_l2<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
+                       (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
+    const hipError_t e = launch_adt<T>(c, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_l3<T>), dim3(gx, nw), dim3(tb), 0, s, cw);
+  } else {
+    hipLaunchKernelGGL((k_l1<T>), g3, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_l2<T>), g2, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
+                       (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
+    hipLaunchKernelGGL((k_l3<T>), g2, dim3(tb), 0, s, c);
   }
-  hipLaunchKernelGGL((k_l1<T>), g3, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_l2<T>), g2, dim3(tb), 0, s, c);
-  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD, (const T*)nullptr,
-                     c.s.psum + PS_AD * 2 * (nz + 1));
-  hipLaunchKernelGGL((k_l3<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
   return hipGetLastError();
@@ -1714,6 +2076,11 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.aat = v.aat;
   c.aat_n = v.aat_n;
   c.aat_blk = v.aat_block;
+  c.adt = v.adt;
+  c.adt_n = v.adt_n;
+  c.adt_blk = v.adt_block;
+  c.pp_n = v.adt_pp_n;
+  c.pp_s = v.adt_pp_s;
   c.ai_zero = ai_zero && ab.U != ai.U;
   c.base_in_tail = process == 1 && ab.U && ab.U == ai.U && ab.V == ai.V && ab.F == ai.F && ab.P == ai.P;
   hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
@@ -1732,15 +2099,16 @@ hipError_t zero_state(const HandleView& v, St4<T> a, hipStream_t s) {
   return e;
 }
 
-// Zeroes only what kernels other than the row-fused adaptation adjoint add to: pole rows of U and
-// Phi, V row 1/2 and p_s.  The row-fused kernel stores the interior rows of an input adjoint the
-// caller marks as zeroed (Ctx::ai_zero).
-// The six segments cleared in one launch: blockIdx.y picks the segment, the blocks along x stride
+// Zeroes only what kernels other than the row-fused stage adjoints add to: the rows those leave to
+// the per-point kernels (pole rows of U and Phi, V row 1/2, with the advection also rows 1..pp_n and
+// ny-pp_s..ny-1 of U, V, Phi) and p_s.  The row-fused kernels store the other rows of an input
+// adjoint the caller marks as zeroed (Ctx::ai_zero).
+// The seven segments cleared in one launch: blockIdx.y picks the segment, the blocks along x stride
 // over it (vector stores).
 template <typename T>
 struct ZeroSegs {
-  T* p[6];
-  unsigned n[6];
+  T* p[7];
+  unsigned n[7];
 };
 
 template <typename T>
@@ -1751,21 +2119,30 @@ __global__ void __launch_bounds__(256) k_zero_segs(ZeroSegs<T> z) {
 }
 
 template <typename T>
-hipError_t zero_outside_rows(const HandleView& v, St4<T> a, hipStream_t s) {
-  const size_t row = (size_t)v.g.nz * v.g.nx;
-  const ZeroSegs<T> z{{a.U, a.U + (size_t)v.g.ny * row, a.F, a.F + (size_t)v.g.ny * row, a.V, a.P},
-                      {(unsigned)row, (unsigned)row, (unsigned)row, (unsigned)row, (unsigned)row, (unsigned)v.nP}};
-  const size_t most = std::max(row, v.nP);
+hipError_t zero_outside_rows(const HandleView& v, St4<T> a, hipStream_t s, int pn, int ps) {
+  const size_t row = (size_t)v.g.nz * v.g.nx, ny = (size_t)v.g.ny;
+  const size_t nn = (size_t)(pn + 1) * row, ns = (size_t)(ps + 1) * row;   // rows 0..pn, ny-ps..ny
+  const ZeroSegs<T> z{{a.U, a.U + (ny - ps) * row, a.F, a.F + (ny - ps) * row, a.V, a.V + (ny - ps) * row, a.P},
+                      {(unsigned)nn, (unsigned)ns, (unsigned)nn, (unsigned)ns, (unsigned)nn,
+                       (unsigned)(ns - row), (unsigned)v.nP}};
+  const size_t most = std::max(std::max(nn, ns), v.nP);
   const unsigned gx = (unsigned)std::min<size_t>((most + 255) / 256, 1024);
-  hipLaunchKernelGGL((k_zero_segs<T>), dim3(gx, 6), dim3(256), 0, s, z);
+  hipLaunchKernelGGL((k_zero_segs<T>), dim3(gx, 7), dim3(256), 0, s, z);
   return hipGetLastError();
 }
 
-// Whether the adaptation-stage adjoint of this handle runs the row-fused kernel (as aar_used).
+// Whether a stage adjoint of this handle runs a row-fused kernel (as aar_used and adt_used): then the
+// input adjoint's interior rows are stored without a read.
 template <typename T>
-bool rows_fused(const HandleView& v) {
-  const Ctx<T> c = [&] { Ctx<T> x; x.g = v.g; x.blk = v.block; x.aat = v.aat; x.aat_n = v.aat_n; return x; }();
-  return aar_used(c);
+bool rows_fused(const HandleView& v, int process) {
+  Ctx<T> c;
+  c.g = v.g;
+  c.blk = v.block;
+  c.aat = v.aat;
+  c.aat_n = v.aat_n;
+  c.adt = v.adt;
+  c.adt_n = v.adt_n;
+  return process == 0 ? aar_used(c) : adt_used(c);
 }
 
 template <typename T>
@@ -1858,9 +2235,10 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
     St4<T> y = traj(3 * rk), y1 = traj(3 * rk + 1), y2 = traj(3 * rk + 2);
     // l2 and l1 start at zero: where the row-fused kernel stores their interior rows, only the
     // rest is cleared
-    const bool fused = proc == 0 && rows_fused<T>(v);
-    e = fused ? zero_outside_rows<T>(v, l1, s) : zero_state<T>(v, l1, s);
-    if (e == hipSuccess) e = fused ? zero_outside_rows<T>(v, l2, s) : zero_state<T>(v, l2, s);
+    const bool fused = rows_fused<T>(v, proc);
+    const int pn = proc == 0 ? 0 : v.adt_pp_n, psn = proc == 0 ? 0 : v.adt_pp_s;
+    e = fused ? zero_outside_rows<T>(v, l1, s, pn, psn) : zero_state<T>(v, l1, s);
+    if (e == hipSuccess) e = fused ? zero_outside_rows<T>(v, l2, s, pn, psn) : zero_state<T>(v, l2, s);
     if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, pin, s, true);
     if (e == hipSuccess) {
       hipLaunchKernelGGL((k_base_inplace<T>), dim3(v.g.nz + 1, 2), dim3(256), 0, s, v.g, lam.U, lam.F, lam.P);

@@ -73,6 +73,9 @@ struct dycore_s {
   size_t adj_bytes = 0;
   AatItem* aat = nullptr;       // work items of the tiled adaptation-stage adjoint (device)
   int aat_n = 0, aat_block = 0;
+  AatItem* adt = nullptr;       // work items of the tiled advection-stage adjoint (device)
+  int adt_n = 0, adt_block = 0;
+  int adt_pp_n = 0, adt_pp_s = 0;   // interior rows at each end that run the per-point kernels
   FiltItem* filt = nullptr;     // rows of the low-latitude filters (device), when enabled
   int nfilt = 0;
   AatItem* ftiles = nullptr;    // zonal tiles of the forward adaptation stage (device), rows 0..ny
@@ -166,25 +169,23 @@ std::vector<FiltItem> filter_items(int ny) {
   return out;
 }
 
-// Work items of the tiled adaptation-stage adjoint (AatItem) for a block of `block` threads: every
-// interior row is cut into the fewest equal zonal tiles whose owned columns plus a halo of n_j + 1
-// columns on each side fit the block.  Items are listed row by row, then spread so that item b
-// (which the hardware dispatches to XCD b mod 8) walks a contiguous eighth of that list.  Returns
-// false when some row's halo leaves fewer than 32 owned columns.
-bool aat_tiles(int nx, int ny, const std::vector<int>& M, int block, std::vector<AatItem>& out, int j0 = 1,
-               int j1 = -1) {
-  if (j1 < 0) j1 = ny - 1;
+// Zonal tiles of the listed rows for a block of `block` threads: every row is cut into the fewest
+// equal tiles whose owned columns plus a halo of hl[j] columns on each side fit the block.  Items are
+// listed row by row, then spread so that item b (which the hardware dispatches to XCD b mod 8) walks
+// a contiguous eighth of that list.  Returns false when some row's halo leaves fewer than 32 owned
+// columns.
+bool zonal_tiles(int nx, const std::vector<int>& rows, const std::vector<int>& hl, int block,
+                 std::vector<AatItem>& out) {
   std::vector<AatItem> seq;
-  for (int j = j0; j <= j1; ++j) {
-    const int hl = (M[j] + 1) / 2 + 1;
-    const int cap = block - 2 * hl;
+  for (const int j : rows) {
+    const int cap = block - 2 * hl[j];
     if (cap < 32) return false;
     const int nt = (nx + cap - 1) / cap;
     const int w = (nx + nt - 1) / nt;
     for (int t = 0; t < nt; ++t) {
       const int i0 = t * w;
       if (i0 >= nx) break;
-      seq.push_back(AatItem{j, i0, std::min(w, nx - i0), hl});
+      seq.push_back(AatItem{j, i0, std::min(w, nx - i0), hl[j]});
     }
   }
   const int n = (int)seq.size(), per = (n + 7) / 8;
@@ -197,17 +198,16 @@ bool aat_tiles(int nx, int ny, const std::vector<int>& M, int block, std::vector
   return true;
 }
 
-// The block (a multiple of 64 up to kAatMaxBlock) whose tiles leave the fewest idle threads
-// (owned columns over launched threads; ties go to the larger block), and its items.  False when no
-// block fits the widest halo (the adjoint then uses its per-point kernels).
-bool aat_items(int nx, int ny, const std::vector<int>& M, std::vector<AatItem>& out, int& block, int j0 = 1,
-               int j1 = -1, int max_block = kAatMaxBlock) {
-  if (j1 < 0) j1 = ny - 1;
+// The block (a multiple of 64 up to max_block) whose tiles of the listed rows leave the fewest idle
+// threads (owned columns over launched threads; ties go to the larger block), and its items.  False
+// when no block fits the widest halo.
+bool best_tiles(int nx, const std::vector<int>& rows, const std::vector<int>& hl, int max_block,
+                std::vector<AatItem>& out, int& block) {
   double best = -1.0;
   for (int b = 64; b <= max_block; b += 64) {
     std::vector<AatItem> items;
-    if (!aat_tiles(nx, ny, M, b, items, j0, j1)) continue;
-    const double util = (double)nx * (j1 - j0 + 1) / ((double)items.size() * b);
+    if (!zonal_tiles(nx, rows, hl, b, items)) continue;
+    const double util = (double)nx * rows.size() / ((double)items.size() * b);
     if (util >= best - 1e-12) {
       best = util;
       block = b;
@@ -215,6 +215,55 @@ bool aat_items(int nx, int ny, const std::vector<int>& M, std::vector<AatItem>& 
     }
   }
   return best > 0.0;
+}
+
+// Rows j0..j1 (j1 < 0: ny - 1) and the halo n_j + 1 of the adaptation stage and its adjoint, whose
+// leaped differences reach n_j columns and whose U-V averages one more.
+std::vector<int> row_range(int j0, int j1) {
+  std::vector<int> r;
+  for (int j = j0; j <= j1; ++j) r.push_back(j);
+  return r;
+}
+std::vector<int> adapt_halos(const std::vector<int>& M) {
+  std::vector<int> hl(M.size());
+  for (size_t j = 0; j < M.size(); ++j) hl[j] = (M[j] + 1) / 2 + 1;
+  return hl;
+}
+
+// Work items of the tiled adaptation stage and its adjoint for a block of `block` threads.
+bool aat_tiles(int nx, int ny, const std::vector<int>& M, int block, std::vector<AatItem>& out, int j0 = 1,
+               int j1 = -1) {
+  return zonal_tiles(nx, row_range(j0, j1 < 0 ? ny - 1 : j1), adapt_halos(M), block, out);
+}
+
+// The best block up to max_block for those tiles (false when no block fits the widest halo: the
+// adjoint then uses its per-point kernels).
+bool aat_items(int nx, int ny, const std::vector<int>& M, std::vector<AatItem>& out, int& block, int j0 = 1,
+               int j1 = -1, int max_block = kAatMaxBlock) {
+  return best_tiles(nx, row_range(j0, j1 < 0 ? ny - 1 : j1), adapt_halos(M), max_block, out, block);
+}
+
+// Work items of the tiled advection-stage adjoint.  Its centred leaped differences span 2 M, so a
+// row's halo is the largest leap of the row and its V rows: max(M_j, Mv_j, nv_{j-1}).  Rows whose
+// halo leaves 32 owned columns in 256 threads are tiled; the others must be the first pp_n and the
+// last pp_s interior rows (next to the poles, where the leaps grow), which run the per-point
+// kernels with the pole rows.  False when no row is tiled or the others are not at the ends.
+bool adt_items(int nx, int ny, const std::vector<int>& M, const std::vector<int>& Mv, std::vector<AatItem>& out,
+               int& block, int& pp_n, int& pp_s) {
+  std::vector<int> hl(ny + 1, 0), rows;
+  std::vector<char> fits(ny + 1, 0);
+  for (int j = 1; j <= ny - 1; ++j) {
+    hl[j] = std::max(std::max(M[j], Mv[j]), (Mv[j - 1] + 1) / 2);
+    fits[j] = 256 - 2 * hl[j] >= 32;
+    if (fits[j]) rows.push_back(j);
+  }
+  out.clear();
+  block = pp_n = pp_s = 0;
+  if (rows.empty()) return false;
+  pp_n = rows.front() - 1;
+  pp_s = ny - 1 - rows.back();
+  if ((int)rows.size() != rows.back() - rows.front() + 1) return false;
+  return best_tiles(nx, rows, hl, 256, out, block);
 }
 
 // Threads per row workgroup: one column per thread up to 1024 columns, else the fewest
@@ -407,6 +456,11 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.aat = h->aat;
   v.aat_n = h->aat_n;
   v.aat_block = h->aat_block;
+  v.adt = h->adt;
+  v.adt_n = h->adt_n;
+  v.adt_block = h->adt_block;
+  v.adt_pp_n = h->adt_pp_n;
+  v.adt_pp_s = h->adt_pp_s;
   v.filt = h->filt;
   v.nfilt = h->nfilt;
   v.ftiles = h->ftiles;
@@ -594,6 +648,19 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
         h->adj_bytes += sizeof(AatItem) * items.size();
       }
     }
+    std::vector<AatItem> at;
+    int ab = 0, pn = 0, psn = 0;
+    if (ok && adt_items(nx, ny, h->M, h->Mv, at, ab, pn, psn)) {
+      ok = hipMalloc((void**)&h->adt, sizeof(AatItem) * at.size()) == hipSuccess;
+      ok = ok && hipMemcpy(h->adt, at.data(), sizeof(AatItem) * at.size(), hipMemcpyHostToDevice) == hipSuccess;
+      if (ok) {
+        h->adt_n = (int)at.size();
+        h->adt_block = ab;
+        h->adt_pp_n = pn;
+        h->adt_pp_s = psn;
+        h->adj_bytes += sizeof(AatItem) * at.size();
+      }
+    }
   }
   if (ok && (h->flags & DYCORE_LOWLAT_FILTERS)) {
     const std::vector<FiltItem> fi = filter_items(ny);
@@ -661,6 +728,7 @@ int dycore_destroy(dycore_t h) {
   if (h->count) (void)hipFree(h->count);
   if (h->adj) (void)hipFree(h->adj);
   if (h->aat) (void)hipFree(h->aat);
+  if (h->adt) (void)hipFree(h->adt);
   if (h->filt) (void)hipFree(h->filt);
   if (h->ftiles) (void)hipFree(h->ftiles);
   if (h->cap) (void)hipFree(h->cap);

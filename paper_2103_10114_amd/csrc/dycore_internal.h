@@ -222,6 +222,9 @@ struct HandleView {
   const AatItem* aat;   // tiled adaptation-adjoint work items (device), or NULL when rows do not fit
   int aat_n;            // item count (a multiple of 8)
   int aat_block;        // threads per tile workgroup
+  const AatItem* adt;   // tiled advection-adjoint work items (device), or NULL: per-point kernels
+  int adt_n, adt_block; // their count (a multiple of 8) and workgroup size (up to 256)
+  int adt_pp_n, adt_pp_s; // rows 1..pp_n and ny-pp_s..ny-1 go with the pole rows (per point)
   const FiltItem* filt; // rows of the low-latitude filters (device), NULL when they are off
   int nfilt;
   const AatItem* ftiles; // zonal tiles of the forward adaptation stage (device)

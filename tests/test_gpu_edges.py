@@ -82,24 +82,28 @@ def test_stage_fp32_ragged_and_limit(nx, process):
 
 
 # The tiled row-fused adaptation adjoint cuts rows into zonal tiles of <= 320 slots, halos included:
-# 731 columns give three tiles with a ragged last one; 96 columns one tile per row; at 512 x 1024 the
-# polar rows' halos (n + 1 = 117 columns each side) leave 86-column tiles; at 1024 x 1440 they
-# (n + 1 = 163) leave fewer than 32 owned columns, so that handle runs the per-point adjoint kernels.
+# Adaptation (halo n + 1): 731 columns give three tiles with a ragged last one; 96 columns one tile
+# per row; at 512 x 1024 the polar rows' halos (117 columns each side) leave 86-column tiles; at
+# 1024 x 1440 they (163) leave fewer than 32 owned columns, so that handle runs the per-point
+# adjoint kernels.  Advection (halo max(M, Mv, nv of the row to the north)): 731 x 8 and 96 x 24 fit
+# 256 threads in every row; at 512 x 1024 four rows next to the poles (halos up to 255) and at
+# 1024 x 1440 five (up to 511) go with the pole rows through the per-point kernels.
 @pytest.mark.parametrize("nx,ny,nz", [(731, 8, 3), (96, 24, 4), (512, 1024, 2), (1024, 1440, 1)])
-def test_stage_adjoint_fp64_tile_forms(nx, ny, nz):
-    """The adaptation-stage adjoint equals the oracle for each tiling of the rows."""
-    print(f"stage adjoint fp64 {nx}x{ny}x{nz}", flush=True)
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_stage_adjoint_fp64_tile_forms(nx, ny, nz, process):
+    """The stage adjoint equals the oracle for each tiling of the rows."""
+    print(f"stage adjoint fp64 {process} {nx}x{ny}x{nz}", flush=True)
     cfg = small(nx, ny, nz)
     st = synth.make_state(cfg)
     ao = synth.random_like(st, 31)
     ch = 200.0
-    wb, wi = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).adj_stage(st, ao, ch, "A")
+    wb, wi = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).adj_stage(st, ao, ch, process)
     core = _core(cfg, st, "fp64")
     d = core.to_device(st)
     a = core.to_device(ao)
     ab = {k: torch.zeros_like(v) for k, v in d.items()}
     ai = {k: torch.zeros_like(v) for k, v in d.items()}
-    core.stage_adjoint("A", ch, d, a, ab, ai)
+    core.stage_adjoint(process, ch, d, a, ab, ai)
     gb, gi = _host(ab), _host(ai)
     for k in ("U", "V", "Phi", "ps"):
         assert _rel(gb[k], wb[k]) < 1e-12, ("base", k)
