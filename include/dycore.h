@@ -69,7 +69,8 @@ typedef struct {
   double a, omega, g, rd, cp, p0, t0;  /* constants; 0 selects 6.371e6, 7.292e-5, 9.80616,
                                           287.04, 1004.64, 1e5, 300 */
   unsigned flags;          /* DYCORE_FORWARD_ONLY | DYCORE_LOWLAT_FILTERS */
-  int block;               /* threads per row workgroup (64..1024, multiple of 64); 0 = tuned default */
+  int block;               /* threads per workgroup of the tiled advection stage (64..1024, multiple of
+                              64; sizes above 256 run as 256); 0 = 256.  Results do not depend on it. */
   double kappa_star;       /* kappa* of eq. 1's p_s line (m^2/s, >= 0; 0 = off): the adaptation's p_s
                               tendency gains kappa* D_sa, D_sa the flux-form horizontal Laplacian of
                               p_s (leaped second difference zonally, cap fluxes at the poles) */
@@ -179,15 +180,16 @@ int dycore_kernel_timer_stop(dycore_t h, double* total_ms, int* launches);
 
 /* Batches of ensemble members (any grids, one precision) advanced together:
  * one persistent launch per global stage, each workgroup pulling (member,
- * row) work items, so the launch sequence of a step is fixed and can be
+ * zonal tile) work items, so the launch sequence of a step is fixed and can be
  * captured once in a hipGraph and replayed.
  *
  * dycore_batch_create binds member m's fields (U[m], V[m], Phi[m], ps[m],
  * device pointers of its handle's grid) and uploads the stage descriptors; it
  * allocates and synchronises.  Each member needs its own handle (the handle's
- * scratch is used).  block = threads per workgroup (0: 256), grid = persistent
- * workgroups (0: fill every CU).  dycore_batch_step only enqueues kernels and
- * gives results equal bit for bit to dycore_step on each member. */
+ * scratch is used).  block = threads per workgroup (0: 256; above 512:
+ * DYCORE_EUNSUPPORTED), grid = persistent workgroups (0: fill every CU).
+ * dycore_batch_step only enqueues kernels and gives results equal bit for bit
+ * to dycore_step on each member. */
 typedef struct dycore_batch_s* dycore_batch_t;
 int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* V, void* const* Phi,
                         void* const* ps, int block, int grid, dycore_batch_t* out);

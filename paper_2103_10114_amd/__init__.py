@@ -258,10 +258,10 @@ class Batch:
         _check(lib().dycore_batch_step(self.b, int(nsteps), _stream()))
 
     @classmethod
-    def autotune(cls, cores, states, blocks=(256, 384, 512, 768, 1024), steps=2):
+    def autotune(cls, cores, states, blocks=(128, 256, 384, 512), steps=2):
         """Time the batched step at each workgroup size in `blocks` (on copies of the states, so the
         members are not advanced) and return (Batch at the fastest size, {block: ms per step}).
-        Sizes the grid cannot use (too many columns per thread, too large for the register budget)
+        Sizes the batch cannot use (tiles that do not fit, above the register budget's 512 threads)
         are skipped.  Results do not depend on the workgroup size, so tuning changes speed only."""
         import torch
         copies = [_clone(st) for st in states]

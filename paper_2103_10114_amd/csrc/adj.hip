@@ -2191,16 +2191,19 @@ int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s)
       a.cap = v.cap;
       a.ntiles = v.nftiles;
       a.tblock = v.ftblock;
+      a.atiles = v.atiles;
+      a.natiles = v.natiles;
+      a.ablock = v.ablock;
       return a;
     };
-    e = launch_stage<T>(mk(h / 3.0, y, y1, pole, pole + ps), v.block, s);
-    if (e == hipSuccess) e = launch_stage<T>(mk(h / 2.0, y1, y2, pole + ps, pole + 2 * ps), v.block, s);
+    e = launch_stage<T>(mk(h / 3.0, y, y1, pole, pole + ps), s);
+    if (e == hipSuccess) e = launch_stage<T>(mk(h / 2.0, y1, y2, pole + ps, pole + 2 * ps), s);
     if (e == hipSuccess && rk + 1 < nrk) {
       St4<T> yn = traj(3 * (rk + 1));
-      e = launch_stage<T>(mk(h, y2, yn, pole + 2 * ps, pole + 3 * ps), v.block, s);
+      e = launch_stage<T>(mk(h, y2, yn, pole + 2 * ps, pole + 3 * ps), s);
       if (e == hipSuccess) e = launch_axpy_fill<double>(pole, pole + 3 * ps, ps, s);
     } else if (e == hipSuccess && out.U) {
-      e = launch_stage<T>(mk(h, y2, out, pole + 2 * ps, pole + 3 * ps), v.block, s);
+      e = launch_stage<T>(mk(h, y2, out, pole + 2 * ps, pole + 3 * ps), s);
       // the low-latitude filters close the step, as in dycore_step
       if (e == hipSuccess) e = launch_lowlat<T>(v.g, v.filt, v.nfilt, out.U, out.V, out.F, out.P, s);
     }

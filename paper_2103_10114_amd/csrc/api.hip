@@ -80,6 +80,8 @@ struct dycore_s {
   int nfilt = 0;
   AatItem* ftiles = nullptr;    // zonal tiles of the forward adaptation stage (device), rows 0..ny
   int nftiles = 0, ftblock = 0;
+  AatItem* atiles = nullptr;    // zonal tiles of the forward advection stage (device), rows 0..ny
+  int natiles = 0;              // (workgroups of `block` threads)
   double* cap = nullptr;        // cap sums of the forward adaptation stage: [2 poles][2][nz]
   size_t bytes = 0;
 };
@@ -89,14 +91,13 @@ size_t dyc_adjoint_workspace_bytes(const dycore_s* h);
 struct dycore_batch_s {
   int n, prec, block, grid, max_nx, nstage_max;
   size_t lds;   // dynamic LDS of the batched stage kernel: the largest need of any member
-  int pipe;     // stage kernel form: 1 all members pipelined, 0 none, 2 mixed
   std::vector<dycore_t> hs;
   void* d_args = nullptr;       // nstage_max x n StageArgs
-  int2* d_items = nullptr;      // advection rows (member, row)
+  int2* d_items = nullptr;      // advection tiles (member, index into the member's advection tile table)
   int nitems = 0;
   int2* d_titems = nullptr;     // adaptation tiles (member, index into the member's tile table)
   int ntitems = 0;
-  AatItem* d_tiles = nullptr;   // every member's tile table for the batch's block
+  AatItem* d_tiles = nullptr;   // every member's adaptation and advection tile tables for the batch's block
   int max_nz = 0;
   void* d_prep = nullptr;       // per member prep descriptors
   std::vector<void*> U, V, F, P;
@@ -266,14 +267,35 @@ bool adt_items(int nx, int ny, const std::vector<int>& M, const std::vector<int>
   return best_tiles(nx, rows, hl, 256, out, block);
 }
 
-// Threads per row workgroup: one column per thread up to 1024 columns, else the fewest
-// columns per thread (each thread keeps its columns' FP64 sums in registers).
-int default_block(int nx, int prec) {
-  (void)prec;
-  if (nx <= 768) return std::max(64, (nx + 63) / 64 * 64);
-  if (nx <= 1536) return ((nx + 1) / 2 + 63) / 64 * 64;
-  const int ni = (nx + 511) / 512;
-  return ((nx + ni - 1) / ni + 63) / 64 * 64;
+// Work items of the tiled advection stage for a block of `block` threads (rows 0..ny).  A row's halo
+// is the reach of its leaped centred differences, max(M_j, Mv_j, 1) (the pole rows have no zonal
+// Phi and U terms); rows whose halo leaves 32 owned columns take band tiles, the others wide tiles
+// (a halo of one column, hl = -1 in the item) that read their leap operands from global memory.
+// Wide items lead the list, so that they start first.
+void advect_tiles(int nx, int ny, const std::vector<int>& M, const std::vector<int>& Mv, int block,
+                  std::vector<AatItem>& out) {
+  std::vector<AatItem> wide, band;
+  for (int j = 0; j <= ny; ++j) {
+    const int hl = std::max((j == 0 || j == ny) ? 1 : M[j], j < ny ? Mv[j] : 1);
+    const bool fits = block - 2 * hl >= 32;
+    const int cap = fits ? block - 2 * hl : block - 2;
+    const int nt = (nx + cap - 1) / cap;
+    const int w = (nx + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+      const int i0 = t * w;
+      if (i0 >= nx) break;
+      (fits ? band : wide).push_back(AatItem{j, i0, std::min(w, nx - i0), fits ? hl : -1});
+    }
+  }
+  std::vector<AatItem> seq(wide);
+  seq.insert(seq.end(), band.begin(), band.end());
+  const int n = (int)seq.size(), per = (n + 7) / 8;
+  out.assign((size_t)per * 8, AatItem{-1, 0, 0, 0});
+  for (int x = 0; x < 8; ++x)
+    for (int q = 0; q < per; ++q) {
+      const int src = x * per + q;
+      if (src < n) out[(size_t)q * 8 + x] = seq[src];
+    }
 }
 
 template <typename T>
@@ -293,6 +315,9 @@ StageArgs<T> make_args(const dycore_s* h, int process, double ch, const T* inU, 
   a.cap = h->cap;
   a.ntiles = h->nftiles;
   a.tblock = h->ftblock;
+  a.atiles = h->atiles;
+  a.natiles = h->natiles;
+  a.ablock = h->block;
   return a;
 }
 
@@ -343,7 +368,7 @@ int step_impl(dycore_s* h, T* U, T* V, T* F, T* P, int nsteps, hipStream_t s) {
   for (int n = 0; n < nsteps; ++n) {
     for (int rk = 0; rk < nrk; ++rk)
       for (int r = 0; r < 3; ++r) {
-        e = launch_stage<T>(step_stage_args<T>(h, rk, r, U, V, F, P), h->block, s);
+        e = launch_stage<T>(step_stage_args<T>(h, rk, r, U, V, F, P), s);
         if (e != hipSuccess) return DYCORE_EHIP;
       }
     // the low-latitude filters close the step (they leave the pole rows and their slot alone)
@@ -366,13 +391,13 @@ int process_run_impl(dycore_s* h, int process, int n_rk, double hstep, T* U, T* 
   for (int n = 0; n < n_rk; ++n) {
     const int nb = (b == 0) ? 3 : 0;
     e = launch_stage<T>(make_args<T>(h, process, hstep / 3.0, U, V, F, P, U, V, F, P, y1.U, y1.V, y1.F, y1.P,
-                                     pole_slot(h, b), pole_slot(h, b), pole_slot(h, 1)), h->block, s);
+                                     pole_slot(h, b), pole_slot(h, b), pole_slot(h, 1)), s);
     if (e == hipSuccess)
       e = launch_stage<T>(make_args<T>(h, process, hstep / 2.0, y1.U, y1.V, y1.F, y1.P, U, V, F, P, y2.U, y2.V,
-                                       y2.F, y2.P, pole_slot(h, 1), pole_slot(h, b), pole_slot(h, 2)), h->block, s);
+                                       y2.F, y2.P, pole_slot(h, 1), pole_slot(h, b), pole_slot(h, 2)), s);
     if (e == hipSuccess)
       e = launch_stage<T>(make_args<T>(h, process, hstep, y2.U, y2.V, y2.F, y2.P, U, V, F, P, U, V, F, P,
-                                       pole_slot(h, 2), pole_slot(h, b), pole_slot(h, nb)), h->block, s);
+                                       pole_slot(h, 2), pole_slot(h, b), pole_slot(h, nb)), s);
     if (e != hipSuccess) return DYCORE_EHIP;
     b = nb;
   }
@@ -386,7 +411,7 @@ int stage_impl(dycore_s* h, int process, double ch, const T* bU, const T* bV, co
   if (e == hipSuccess) e = launch_pole_prep<T>(h->g, bF, bP, pole_slot(h, 1), s);
   if (e == hipSuccess)
     e = launch_stage<T>(make_args<T>(h, process, ch, U, V, F, P, bU, bV, bF, bP, oU, oV, oF, oP, pole_slot(h, 0),
-                                     pole_slot(h, 1), pole_slot(h, 2)), h->block, s);
+                                     pole_slot(h, 1), pole_slot(h, 2)), s);
   return hip_status(e);
 }
 
@@ -466,6 +491,9 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.ftiles = h->ftiles;
   v.nftiles = h->nftiles;
   v.ftblock = h->ftblock;
+  v.atiles = h->atiles;
+  v.natiles = h->natiles;
+  v.ablock = h->block;
   v.cap = h->cap;
   return v;
 }
@@ -493,13 +521,8 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   if (!h) return DYCORE_ENOMEM;
   h->nx = cfg->nx; h->ny = cfg->ny; h->nz = cfg->nz; h->prec = cfg->prec; h->dt = cfg->dt; h->flags = cfg->flags;
   h->elem = (h->prec == DYCORE_FP32) ? 4 : 8;
-  h->block = cfg->block ? cfg->block : default_block(h->nx, h->prec);
-  if (columns_per_thread(h->nx, h->block) > 8 || !max_block_for(h->nx, h->block)) {
-    delete h;
-    return DYCORE_EUNSUPPORTED;
-  }
-  const size_t lds = std::max(stage_lds_bytes(0, h->nx, (int)h->elem), stage_lds_bytes(1, h->nx, (int)h->elem));
-  if (lds > 160 * 1024) { delete h; return DYCORE_EUNSUPPORTED; }
+  // the tiled advection stage's workgroup (its kernel's register budget is set for 256 threads)
+  h->block = cfg->block ? std::min(cfg->block, 256) : 256;
   (void)hipGetDevice(&h->device);
   if ((st = resolve_scratch(h->device)) != DYCORE_OK) { delete h; return st; }
 
@@ -632,6 +655,14 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       h->ftblock = fblk;
       h->bytes += sizeof(AatItem) * ft.size() + sizeof(double) * 4 * nz;
     }
+    std::vector<AatItem> at;
+    advect_tiles(nx, ny, h->M, h->Mv, h->block, at);
+    ok = ok && hipMalloc((void**)&h->atiles, sizeof(AatItem) * at.size()) == hipSuccess;
+    ok = ok && hipMemcpy(h->atiles, at.data(), sizeof(AatItem) * at.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) {
+      h->natiles = (int)at.size();
+      h->bytes += sizeof(AatItem) * at.size();
+    }
   }
   if (ok && !(h->flags & DYCORE_FORWARD_ONLY)) {
     h->adj_bytes = dyc_adjoint_workspace_bytes(h);
@@ -731,6 +762,7 @@ int dycore_destroy(dycore_t h) {
   if (h->adt) (void)hipFree(h->adt);
   if (h->filt) (void)hipFree(h->filt);
   if (h->ftiles) (void)hipFree(h->ftiles);
+  if (h->atiles) (void)hipFree(h->atiles);
   if (h->cap) (void)hipFree(h->cap);
   release_timer(h);
   delete h;
@@ -878,15 +910,19 @@ int batch_build(dycore_batch_s* b) {
   const int n = b->n;
   // every member's adaptation tiles for the batch's block, one table after the other
   std::vector<AatItem> tiles;
-  std::vector<size_t> toff(n);
-  std::vector<int> tcount(n);
+  std::vector<size_t> toff(n), aoff(n);
+  std::vector<int> tcount(n), acount(n);
   for (int m = 0; m < n; ++m) {
     const dycore_s* h = b->hs[m];
-    std::vector<AatItem> t;
+    std::vector<AatItem> t, at;
     if (!aat_tiles(h->nx, h->ny, h->M, b->block, t, 0, h->ny)) return DYCORE_EUNSUPPORTED;
+    advect_tiles(h->nx, h->ny, h->M, h->Mv, b->block, at);
     toff[m] = tiles.size();
     tcount[m] = (int)t.size();
     tiles.insert(tiles.end(), t.begin(), t.end());
+    aoff[m] = tiles.size();
+    acount[m] = (int)at.size();
+    tiles.insert(tiles.end(), at.begin(), at.end());
   }
   if (hipMalloc((void**)&b->d_tiles, sizeof(AatItem) * tiles.size()) != hipSuccess) return DYCORE_ENOMEM;
   if (hipMemcpy(b->d_tiles, tiles.data(), sizeof(AatItem) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
@@ -906,6 +942,9 @@ int batch_build(dycore_batch_s* b) {
       a.tiles = b->d_tiles + toff[m];
       a.ntiles = tcount[m];
       a.tblock = b->block;
+      a.atiles = b->d_tiles + aoff[m];
+      a.natiles = acount[m];
+      a.ablock = b->block;
     }
   }
   if (hipMalloc(&b->d_args, sizeof(StageArgs<T>) * args.size()) != hipSuccess) return DYCORE_ENOMEM;
@@ -918,26 +957,12 @@ int batch_build(dycore_batch_s* b) {
     const dycore_s* a = b->hs[x]; const dycore_s* c = b->hs[y];
     return (size_t)a->nx * a->nz > (size_t)c->nx * c->nz;
   });
-  std::vector<int2> items;
-  for (int m : order) {
-    const int R = b->hs[m]->ny + 1;
-    const int Rp = (R + 7) / 8 * 8;
-    for (int p = 0; p < Rp; ++p) {
-      int2 it;
-      if (p < R) {
-        const int x = p & 7, slot = p >> 3, q = R >> 3, rem = R & 7;
-        it.x = m;
-        it.y = x * q + std::min(x, rem) + slot;
-      } else {
-        it.x = -1; it.y = 0;
-      }
-      items.push_back(it);
-    }
-  }
+  // tiles in member order; each table is a multiple of 8 long and XCD-ordered, so item w still runs
+  // on XCD w mod 8 in the persistent launch (whose grid is a multiple of 8)
+  std::vector<int2> items, titems;
+  for (int m : order)
+    for (int q = 0; q < acount[m]; ++q) items.push_back(int2{m, q});
   b->nitems = (int)items.size();
-  // adaptation tiles in the same member order; each table is a multiple of 8 long and XCD-ordered, so
-  // item w still runs on XCD w mod 8 in the persistent launch (whose grid is a multiple of 8)
-  std::vector<int2> titems;
   for (int m : order)
     for (int q = 0; q < tcount[m]; ++q) titems.push_back(int2{m, q});
   b->ntitems = (int)titems.size();
@@ -968,7 +993,7 @@ int batch_step(dycore_batch_s* b, int nsteps, hipStream_t s) {
   for (int n = 0; n < nsteps; ++n) {
     for (int sidx = 0; sidx < b->nstage_max; ++sidx) {
       hipError_t e = launch_stage_batch<T>(args + (size_t)sidx * b->n, b->n, b->max_nz, b->d_titems, b->ntitems,
-                                           b->d_items, b->nitems, b->grid, b->block, b->max_nx, b->lds, b->pipe, s);
+                                           b->d_items, b->nitems, b->grid, b->block, b->lds, s);
       if (e != hipSuccess) return DYCORE_EHIP;
     }
     for (int m = 0; m < b->n; ++m) {   // members with the low-latitude filters close their step
@@ -991,8 +1016,6 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
   *out = nullptr;
   const int prec = hs[0] ? hs[0]->prec : -1;
   int max_nx = 0, nst = 0;
-  size_t lds = 0;
-  int npipe = 0;
   for (int m = 0; m < n; ++m) {
     if (!hs[m] || hs[m]->prec != prec || !U[m] || !V[m] || !Phi[m] || !ps[m]) return DYCORE_EINVAL;
     if (!aligned16(U[m]) || !aligned16(V[m]) || !aligned16(Phi[m]) || !aligned16(ps[m])) return DYCORE_EINVAL;
@@ -1000,22 +1023,19 @@ int dycore_batch_create(int n, const dycore_t* hs, void* const* U, void* const* 
       if (hs[q] == hs[m]) return DYCORE_EINVAL;   // each member needs its own scratch
     max_nx = std::max(max_nx, hs[m]->nx);
     nst = std::max(nst, 3 * (hs[m]->msub + 1));
-    const int el = hs[m]->prec == DYCORE_FP32 ? 4 : 8;
-    lds = std::max(lds, stage_lds_bytes(1, hs[m]->nx, el));
-    npipe += stage_pipelined(hs[m]->nx, el);
   }
   if (block == 0) block = 256;
   if (block < 64 || block > 1024 || block % 64) return DYCORE_EINVAL;
-  lds = std::max(lds, adapt_tile_lds_bytes(block, prec == DYCORE_FP32 ? 4 : 8));
+  if (block > kBatchMaxBlock) return DYCORE_EUNSUPPORTED;
+  const int el = prec == DYCORE_FP32 ? 4 : 8;
+  const size_t lds = std::max(adapt_tile_lds_bytes(block, el), advect_tile_lds_bytes(block, el));
   int max_nz = 0;
   for (int m = 0; m < n; ++m) max_nz = std::max(max_nz, hs[m]->nz);
-  if (columns_per_thread(max_nx, block) > 8 || !max_block_for(max_nx, block)) return DYCORE_EUNSUPPORTED;
   if (lds > 160 * 1024) return DYCORE_EUNSUPPORTED;
   dycore_batch_s* b = new (std::nothrow) dycore_batch_s();
   if (!b) return DYCORE_ENOMEM;
   b->n = n; b->prec = prec; b->block = block; b->max_nx = max_nx; b->nstage_max = nst; b->lds = lds;
   b->max_nz = max_nz;
-  b->pipe = npipe == n ? 1 : (npipe == 0 ? 0 : 2);
   b->hs.assign(hs, hs + n);
   b->U.assign(U, U + n); b->V.assign(V, V + n); b->F.assign(Phi, Phi + n); b->P.assign(ps, ps + n);
   const int st = prec == DYCORE_FP32 ? batch_build<float>(b) : batch_build<double>(b);

@@ -61,6 +61,7 @@ struct AatItem {
 };
 constexpr int kAatMaxBlock = 320;       // adjoint tiles
 constexpr int kFwdTileMaxBlock = 1024;  // forward adaptation tiles
+constexpr int kBatchMaxBlock = 512;     // the persistent batched stage (its VGPR budget: 256)
 
 // One stage out = base + ch * T(in) of one member.
 template <typename T>
@@ -76,9 +77,12 @@ struct StageArgs {
   int process;          // 0 adaptation, 1 advection, -1 idle
   int pad;
   const AatItem* tiles;  // zonal tiles of the adaptation stage (rows 0..ny)
-  double* cap;          // [2 poles][2][nz] FP64 cap sums of the adaptation stage's input
+  double* cap;          // [2 poles][2][nz] FP64 cap sums of the stage's input (either process)
   int ntiles;           // tile count (a multiple of 8)
   int tblock;           // threads per tile workgroup
+  const AatItem* atiles; // zonal tiles of the advection stage (rows 0..ny; hl < 0: wide form)
+  int natiles;          // their count (a multiple of 8)
+  int ablock;           // threads per advection tile workgroup
 };
 
 // Adjoint of one stage about `in`.
@@ -109,14 +113,14 @@ struct FiltItem {
 // Launch helpers implemented in the kernel translation units.
 template <typename T>
 hipError_t launch_pole_prep(const GeoDev& g, const T* F, const T* ps, double* pole, hipStream_t s);
+// One stage out = base + ch T(in): the pole cap sums of `in`, then the process's zonal tiles.
 template <typename T>
-hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s);
-// One batched stage: the cap sums of the members at an adaptation stage, then one persistent launch
-// over the adaptation tiles (titems) and the advection rows (items) of every member.
+hipError_t launch_stage(const StageArgs<T>& a, hipStream_t s);
+// One batched stage: the cap sums of every member, then a persistent launch over the adaptation
+// tiles (titems) and one over the advection tiles (items) of every member.
 template <typename T>
 hipError_t launch_stage_batch(const StageArgs<T>* d_args, int nargs, int max_nz, const int2* d_titems, int ntitems,
-                              const int2* d_items, int nitems, int grid, int block, int max_nx, size_t lds, int pipe,
-                              hipStream_t s);
+                              const int2* d_items, int nitems, int grid, int block, size_t lds, hipStream_t s);
 template <typename T>
 hipError_t launch_stage_adjoint(const AdjArgs<T>& a, int block, hipStream_t s);
 // FP64 mass and energy: per-row partials (3 (ny+1) doubles in `partial`), then their fixed-order
@@ -135,11 +139,8 @@ hipError_t launch_axpy_fill(T* dst, const T* src, size_t n, hipStream_t s);   //
 template <typename T>
 hipError_t launch_zero(T* dst, size_t n, hipStream_t s);
 
-size_t stage_lds_bytes(int process, int nx, int elem);
-int columns_per_thread(int nx, int block);
-int stage_pipelined(int nx, int elem);   // 1 if the advection kernel for rows of nx columns is pipelined
-size_t adapt_tile_lds_bytes(int block, int elem);   // LDS of an adaptation tile workgroup
-int max_block_for(int nx, int block);   // 1 if `block` threads are allowed for rows of nx columns
+size_t adapt_tile_lds_bytes(int block, int elem);    // LDS of an adaptation tile workgroup
+size_t advect_tile_lds_bytes(int block, int elem);   // LDS of an advection tile workgroup
 
 // A uniform row of a global array: the array base (the kernel argument's, one SGPR pair for every
 // row) plus a uniform 32-bit element offset made opaque with readfirstlane (one SGPR per row; loop
@@ -229,6 +230,8 @@ struct HandleView {
   int nfilt;
   const AatItem* ftiles; // zonal tiles of the forward adaptation stage (device)
   int nftiles, ftblock;
+  const AatItem* atiles; // zonal tiles of the forward advection stage (device)
+  int natiles, ablock;
   double* cap;           // cap sums of the forward adaptation stage (device, 4 nz doubles)
 };
 HandleView view_of(const dycore_s* h);

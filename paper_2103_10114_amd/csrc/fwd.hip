@@ -92,10 +92,6 @@ __device__ C ps_diffusion_pole(const StageArgs<T>& A, int j, double* red) {
   return g.kstar * (g.sv[jv] * g.dlam / (g.acap * g.dth)) * red[0];
 }
 
-// Largest workgroup per columns-per-thread: bounds the VGPR budget so that the FP64 column
-// sums and one level's loads of every owned column stay in registers (768 threads: 170 VGPRs).
-constexpr int max_block(int ni) { return ni <= 2 ? 768 : 512; }
-int max_block_for(int nx, int block) { return block <= max_block(columns_per_thread(nx, block)) ? 1 : 0; }
 
 namespace {
 
@@ -393,436 +389,55 @@ __global__ void __launch_bounds__(64) k_capsum(StageArgs<T> a) {
   capsum_level<T>(a, blockIdx.x, blockIdx.y);
 }
 
-// The cap sums of every batched member whose stage is an adaptation stage.
-template <typename T>
-__global__ void __launch_bounds__(64) k_capsum_batch(const StageArgs<T>* __restrict__ args, int n) {
-  const int m = blockIdx.z;
-  if (m >= n) return;
-  const StageArgs<T> a = args[m];
-  if (a.process != 0 || (int)blockIdx.x >= a.g.nz) return;
-  capsum_level<T>(a, blockIdx.x, blockIdx.y);
-}
 
 // ----------------------------------------------------------------------------------------------
-// Advection: out = base - ch * L(in), L in the IAP skew form, zonal part leaped
+// Advection, tiled: one workgroup per work item (row j, a zonal tile of w owned columns from i0,
+// one column per thread).  Band tiles carry a halo of hl = max(M_j, Mv_j, 1) columns on each side,
+// the reach of the leaped centred differences (2 M wide), and gather every level value from LDS.
+// Wide tiles (rows whose halo would leave fewer than 32 owned columns in 256 threads: next to the
+// poles on fine grids; marked hl < 0) keep a halo of one column and read their leap operands from
+// global memory, forming u = U / P^U and the V-row mean of u there as the LDS rows hold them, so both
+// forms give the same values.  Per slot the LDS holds, double-buffered, 7 level rows (Phi, U, u of
+// row j, V, u on the V row, v sin(theta) on V rows j+-1/2) and a 3-slot sigma-dot ring: 17 words, an
+// odd stride.  sigma-dot of row j comes from every slot's column total Pi (pass A, the leap
+// neighbours of U from global memory) and running S; that of row j+1 is formed at the owned columns
+// only.  The pole rows' cap sums come from k_capsum_adv.
 // ----------------------------------------------------------------------------------------------
-// LDS: P rows j and j+1; per level the rows MU(j+1), u(j), u on the V row, Phi(j), U(j), V(j+1/2),
-// v sin(theta) on V rows j-1/2 and j+1/2, and sigma-dot of row j at two half levels.  The first
-// pass (column totals Pi) reads leap neighbours straight from global memory, without barriers.
-template <typename T, int NI>
-__device__ void advect_row(const StageArgs<T>& A, const int j, unsigned char* smem) {
+constexpr int kAdvTileRows = 7;
+constexpr int kAdvTileRS = 2 * kAdvTileRows + 3;   // 17 words per slot
+__host__ __device__ constexpr size_t advect_tile_lds(int block, int elem) { return (size_t)kAdvTileRS * block * elem; }
+
+template <typename T, bool WIDE>
+__device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned char* smem) {
   const GeoDev& g = A.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int B = blockDim.x, t = threadIdx.x;
-  T* sP0 = reinterpret_cast<T*>(smem);    // P row j
-  T* sP1 = sP0 + nx;                       // P row j+1 (south pole WG: row ny-1)
-  T* sMU1 = sP1 + nx;                      // MU row j+1 at level k
-  T* su0 = sMU1 + nx;                      // u row j
-  T* suv = su0 + nx;                       // u averaged to V row j+1/2
-  T* sF = suv + nx;                        // Phi row j
-  T* sU = sF + nx;                         // U row j
-  T* sV = sU + nx;                         // V row j
-  T* svtm = sV + nx;                       // v sin(theta) on V row j-1
-  T* svt0 = svtm + nx;                     // v sin(theta) on V row j
-  T* sSd = svt0 + nx;                      // sigma-dot row j at two half levels [2][nx]
-  double* sCap = reinterpret_cast<double*>(smem + ((12 * nx * sizeof(T) + 15) & ~size_t(15)));  // [2][nz]
-
-  const bool isPole = (j == 0 || j == ny);
-  const bool hasV = (j < ny);
-  const bool j1Pole = (j + 1 == ny);
-  const bool j1Int = (j + 1 >= 1 && j + 1 <= ny - 1);
-  const int pidx = (j == 0) ? 0 : 1;
-  const T p0 = (T)g.p0;
-  const size_t row3 = (size_t)nz * nx;
-
-  auto psA = [&](int jr, int i) -> T {
-    if (jr == 0) return (T)A.pin[nz];
-    if (jr == ny) return (T)A.pin[(nz + 1) + nz];
-    return A.inP[(size_t)jr * nx + i];
-  };
-  auto FA = [&](int jr, int k, int i) -> T {
-    if (jr == 0) return (T)A.pin[k];
-    if (jr == ny) return (T)A.pin[(nz + 1) + k];
-    return A.inF[(size_t)jr * row3 + (size_t)k * nx + i];
-  };
-
-  const int ja = (j == 0) ? 1 : ny - 1;   // row next to a pole
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    if (i < nx) {
-      sP0[i] = tsqrt<T>(psA(j, i) / p0);
-      sP1[i] = tsqrt<T>(psA(hasV ? j + 1 : ja, i) / p0);
-      sSd[i] = T(0);
-      sSd[nx + i] = T(0);
-    }
-  }
-  __syncthreads();
-
-  // pole caps of every level (FP64, wavefront 0): cap divergence of the pole row (j pole) or of
-  // the south pole seen from row ny-1, and the cap flux of Phi for a pole row
-  if ((isPole || (hasV && j1Pole)) && t < 64) {
-    const int jv = (j == 0) ? 0 : ny - 1;
-    for (int k = 0; k < nz; ++k) {
-      const T* pV = A.inV + (size_t)jv * row3 + (size_t)k * nx;
-      C s1 = 0, s2 = 0;
-      for (int i = t; i < nx; i += 64) {
-        const T pv = T(0.5) * (sP0[i] + sP1[i]);
-        const T vv = pV[i];
-        s1 += (C)(pv * vv);
-        if (isPole) s2 += (C)(vv / pv * (T)g.sv[jv] * FA(ja, k, i));
-      }
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
-    }
-  }
-  __syncthreads();
-
-  const int Mj = isPole ? 1 : g.M[j], nj = (Mj + 1) / 2;
-  const int Mj1 = j1Int ? g.M[j + 1] : 1, nj1 = (Mj1 + 1) / 2;
-  const T rdx = isPole ? T(0) : (T)(1.0 / ((double)Mj * g.a * g.s[j] * g.dlam));
-  const T rdx1 = j1Int ? (T)(1.0 / ((double)Mj1 * g.a * g.s[j + 1] * g.dlam)) : T(0);
-  const T rdyS = isPole ? T(0) : (T)(1.0 / (g.a * g.s[j] * g.dth));
-  const T rdyS1 = j1Int ? (T)(1.0 / (g.a * g.s[j + 1] * g.dth)) : T(0);
-  const T svj = hasV ? (T)g.sv[j] : T(0), svm = (j >= 1) ? (T)g.sv[j - 1] : T(0);
-  const T sv1 = (j + 1 < ny) ? (T)g.sv[j + 1] : T(0);
-  const C capD0 = isPole ? ((j == 0) ? 1.0 : -1.0) * g.a * g.dlam * g.sv[(j == 0) ? 0 : ny - 1] / g.acap : 0.0;
-  const C capD1 = (hasV && j1Pole) ? -g.a * g.dlam * g.sv[ny - 1] / g.acap : 0.0;
-
-  // per-column constants
-  int ip1[NI], ic[NI], id[NI], ic1[NI], id1[NI];
-  T PUc[NI], PUd[NI], rPU0[NI], rPU1[NI], PVm[NI], PV0[NI], PV1[NI], rPVm[NI], rPV0[NI], rPV1[NI];
-  C rP0sq[NI], rP1sq[NI], Pi0[NI], Pi1[NI], S0[NI], S1[NI], sd0c[NI], sd1c[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    const int ii = i < nx ? i : 0;
-    ip1[c] = wrp(ii + 1, nx);
-    ic[c] = wrp(ii + nj - 1, nx); id[c] = wrp(ii - nj, nx);
-    ic1[c] = wrp(ii + nj1 - 1, nx); id1[c] = wrp(ii - nj1, nx);
-    const T P0 = sP0[ii], P1 = sP1[ii];
-    rP0sq[c] = 1.0 / ((C)P0 * (C)P0);
-    rP1sq[c] = hasV ? 1.0 / ((C)P1 * (C)P1) : 0.0;
-    PUc[c] = T(0.5) * (sP0[ic[c]] + sP0[wrp(ic[c] + 1, nx)]);
-    PUd[c] = T(0.5) * (sP0[id[c]] + sP0[wrp(id[c] + 1, nx)]);
-    rPU0[c] = isPole ? T(0) : T(2) / (P0 + sP0[ip1[c]]);
-    rPU1[c] = j1Int ? T(2) / (P1 + sP1[ip1[c]]) : T(0);
-    PVm[c] = PV0[c] = PV1[c] = rPVm[c] = rPV0[c] = rPV1[c] = T(1);
-    if (hasV) { PV0[c] = T(0.5) * (P0 + P1); rPV0[c] = T(1) / PV0[c]; }
-    if (j >= 1) { PVm[c] = T(0.5) * (tsqrt<T>(psA(j - 1, ii) / p0) + P0); rPVm[c] = T(1) / PVm[c]; }
-    if (j + 2 <= ny) { PV1[c] = T(0.5) * (P1 + tsqrt<T>(psA(j + 2, ii) / p0)); rPV1[c] = T(1) / PV1[c]; }
-    Pi0[c] = Pi1[c] = S0[c] = S1[c] = sd0c[c] = sd1c[c] = 0;
-  }
-  // MU of row j+1 at leap positions comes from LDS in pass B; in pass A from global
-  T PU1c[NI], PU1d[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) {
-    PU1c[c] = j1Int ? T(0.5) * (sP1[ic1[c]] + sP1[wrp(ic1[c] + 1, nx)]) : T(0);
-    PU1d[c] = j1Int ? T(0.5) * (sP1[id1[c]] + sP1[wrp(id1[c] + 1, nx)]) : T(0);
-  }
-
-  // ---- pass A: column totals Pi for rows j and j+1 (no LDS, no barriers)
-#pragma unroll 1
-  for (int k = 0; k < nz; ++k) {
-    const size_t lev = (size_t)k * nx;
-    const T* pU0 = isPole ? nullptr : A.inU + (size_t)j * row3 + lev;
-    const T* pU1 = j1Int ? A.inU + (size_t)(j + 1) * row3 + lev : nullptr;
-    const T* pV0 = hasV ? A.inV + (size_t)j * row3 + lev : nullptr;
-    const T* pVm = (j >= 1) ? A.inV + (size_t)(j - 1) * row3 + lev : nullptr;
-    const T* pV1 = (j + 1 < ny) ? A.inV + (size_t)(j + 1) * row3 + lev : nullptr;
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i >= nx) continue;
-      const T Vj = pV0 ? pV0[i] : T(0);
-      C D0, D1 = 0;
-      if (isPole) {
-        D0 = capD0 * sCap[k];
-      } else {
-        D0 = (C)((PUc[c] * pU0[ic[c]] - PUd[c] * pU0[id[c]]) * rdx +
-                 (svj * (PV0[c] * Vj) - svm * (PVm[c] * pVm[i])) * rdyS);
-      }
-      if (hasV) {
-        if (j1Pole) D1 = capD1 * sCap[k];
-        else
-          D1 = (C)((PU1c[c] * pU1[ic1[c]] - PU1d[c] * pU1[id1[c]]) * rdx1 +
-                   (sv1 * (PV1[c] * pV1[i]) - svj * (PV0[c] * Vj)) * rdyS1);
-      }
-      Pi0[c] += D0 * g.dsig[k];
-      Pi1[c] += D1 * g.dsig[k];
-    }
-  }
-
-  // ---- pass B
-  const C cc = g.a * g.dlam / (2.0 * g.acap);
-  const T rdx2 = T(0.5) * rdx;
-  const T rdy2 = T(0.5) * rdyS;
-  const int Mv = hasV ? g.Mv[j] : 1, nv = (Mv + 1) / 2;
-  const T rdxv2 = hasV ? (T)(1.0 / (2.0 * (double)Mv * g.a * g.sv[j] * g.dlam)) : T(0);
-  const T rdyv2 = hasV ? (T)(1.0 / (2.0 * g.a * g.sv[j] * g.dth)) : T(0);
-  for (int k = 0; k < nz; ++k) {
-    const C dsg = g.dsig[k], r2d = 1.0 / (2.0 * dsg);
-    const int par = k & 1, parn = (k + 1) & 1;
-    const size_t lev = (size_t)k * nx;
-    const T* pU0 = isPole ? nullptr : A.inU + (size_t)j * row3 + lev;
-    const T* pU1 = j1Int ? A.inU + (size_t)(j + 1) * row3 + lev : nullptr;
-    const T* pV0 = hasV ? A.inV + (size_t)j * row3 + lev : nullptr;
-    const T* pVm = (j >= 1) ? A.inV + (size_t)(j - 1) * row3 + lev : nullptr;
-    const T* pV1 = (j + 1 < ny) ? A.inV + (size_t)(j + 1) * row3 + lev : nullptr;
-    // phase 1: loads of this level; LDS rows
-    T Vj[NI], Vm[NI], V1[NI], Fn[NI], Fs[NI], Un[NI], Us[NI];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      Vj[c] = Vm[c] = V1[c] = Fn[c] = Fs[c] = Un[c] = Us[c] = T(0);
-      if (i < nx) {
-        const T Fj = FA(j, k, i);
-        const T Uj = pU0 ? pU0[i] : T(0);
-        sF[i] = Fj;
-        sU[i] = Uj;
-        const T u0 = Uj * rPU0[c];
-        su0[i] = u0;
-        const T U1 = pU1 ? pU1[i] : T(0);
-        if (j1Int) sMU1[i] = T(0.5) * (sP1[i] + sP1[ip1[c]]) * U1;
-        if (hasV) {
-          Vj[c] = pV0[i];
-          sV[i] = Vj[c];
-          svt0[i] = Vj[c] * rPV0[c] * svj;
-          suv[i] = T(0.5) * (u0 + U1 * rPU1[c]);
-        }
-        if (j >= 1) {
-          Vm[c] = pVm[i];
-          svtm[i] = Vm[c] * rPVm[c] * svm;
-        }
-        if (pV1) V1[c] = pV1[i];
-        if (!isPole) {
-          Fn[c] = FA(j + 1, k, i);
-          Fs[c] = FA(j - 1, k, i);
-          Un[c] = U1;
-          Us[c] = (j - 1 >= 1) ? A.inU[(size_t)(j - 1) * row3 + lev + i] : T(0);
-        }
-      }
-    }
-    __syncthreads();
-    C sd0n[NI], sd1n[NI];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      C D0 = 0, D1 = 0;
-      if (i < nx) {
-        if (isPole) {
-          D0 = capD0 * sCap[k];
-        } else {
-          D0 = (C)((PUc[c] * sU[ic[c]] - PUd[c] * sU[id[c]]) * rdx +
-                   (svj * (PV0[c] * Vj[c]) - svm * (PVm[c] * Vm[c])) * rdyS);
-        }
-        if (hasV) {
-          if (j1Pole) D1 = capD1 * sCap[k];
-          else
-            D1 = (C)((sMU1[ic1[c]] - sMU1[id1[c]]) * rdx1 + (sv1 * (PV1[c] * V1[c]) - svj * (PV0[c] * Vj[c])) * rdyS1);
-        }
-      }
-      S0[c] += D0 * dsg;
-      S1[c] += D1 * dsg;
-      sd0n[c] = 0; sd1n[c] = 0;
-      if (k + 1 < nz && i < nx) {
-        const C sh = g.sigh[k + 1];
-        sd0n[c] = (sh * Pi0[c] - S0[c]) * rP0sq[c];
-        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) * rP1sq[c];
-      }
-      if (i < nx) sSd[parn * nx + i] = (T)sd0n[c];
-    }
-    __syncthreads();
-
-    if (!isPole) {
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const size_t idx = (size_t)j * row3 + lev + i;
-        const int pM = wrp(i + Mj, nx), mM = wrp(i - Mj, nx);
-        // Phi: zonal (x+1,x-1) -> (x+2N-1, x-2N+1), u at the midpoints
-        const T L1 = (su0[ic[c]] * sF[pM] - su0[id[c]] * sF[mM]) * rdx2;
-        const T L2 = (svt0[i] * Fn[c] - svtm[i] * Fs[c]) * rdy2;
-        C L3 = 0;
-        if (k + 1 < nz) L3 += sd0n[c] * (C)A.inF[idx + nx];
-        if (k > 0) L3 -= sd0c[c] * (C)A.inF[idx - nx];
-        const C TF = -((C)L1 + (C)L2 + L3 * r2d);
-        A.oF[idx] = (T)((C)A.bF[idx] + A.ch * TF);
-        // U: same leap on U points with u averaged to the integer points i+n and i+1-n
-        const int pA = wrp(i + nj, nx), pB = wrp(i + 1 - nj, nx);
-        const T ubA = T(0.5) * (su0[ic[c]] + su0[pA]);
-        const T ubB = T(0.5) * (su0[id[c]] + su0[pB]);
-        const T U1v = (ubA * sU[pM] - ubB * sU[mM]) * rdx2;
-        const int ip = ip1[c];
-        const T vtn = T(0.5) * (svt0[i] + svt0[ip]);
-        const T vts = T(0.5) * (svtm[i] + svtm[ip]);
-        const T U2v = (vtn * Un[c] - vts * Us[c]) * rdy2;
-        C U3 = 0;
-        if (k + 1 < nz) U3 += (C)(T(0.5) * (sSd[parn * nx + i] + sSd[parn * nx + ip])) * (C)A.inU[idx + nx];
-        if (k > 0) U3 -= (C)(T(0.5) * (sSd[par * nx + i] + sSd[par * nx + ip])) * (C)A.inU[idx - nx];
-        const C TU = -((C)U1v + (C)U2v + U3 * r2d);
-        A.oU[idx] = (T)((C)A.bU[idx] + A.ch * TU);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    } else {
-      const C sgn = (j == 0) ? 1.0 : -1.0;
-      const C L2 = sgn * cc * sCap[nz + k];
-      C L3 = 0;
-      if (k + 1 < nz) L3 += sd0n[0] * (C)FA(j, k + 1, 0);
-      if (k > 0) L3 -= sd0c[0] * (C)FA(j, k - 1, 0);
-      const C TF = -(L2 + L3 * r2d);
-      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i < nx) {
-          const size_t idx = (size_t)j * row3 + lev + i;
-          A.oF[idx] = val;
-          A.oU[idx] = T(0);
-        }
-      }
-      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
-    }
-
-    if (hasV) {
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const size_t idv = (size_t)j * row3 + lev + i;
-        const T L1 = (suv[wrp(i + nv - 1, nx)] * sV[wrp(i + Mv, nx)] - suv[wrp(i - nv, nx)] * sV[wrp(i - Mv, nx)]) * rdxv2;
-        T L2 = T(0);
-        if (j + 1 < ny) L2 += T(0.5) * (svt0[i] + V1[c] * rPV1[c] * sv1) * V1[c];
-        if (j > 0) L2 -= T(0.5) * (svtm[i] + svt0[i]) * Vm[c];
-        L2 = L2 * rdyv2;
-        C L3 = 0;
-        if (k + 1 < nz) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)A.inV[idv + nx];
-        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)A.inV[idv - nx];
-        const C TV = -((C)L1 + (C)L2 + L3 * r2d);
-        A.oV[idv] = (T)((C)A.bV[idv] + A.ch * TV);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NI; ++c) { sd0c[c] = sd0n[c]; sd1c[c] = sd1n[c]; }
-    __syncthreads();
-  }
-
-  // p_s is not advected
-  if (!isPole) {
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) A.oP[(size_t)j * nx + i] = A.bP[(size_t)j * nx + i];
-    }
-  } else {
-    const T val = (T)A.pbase[pidx * (nz + 1) + nz];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) A.oP[(size_t)j * nx + i] = val;
-    }
-    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
-  }
-}
-
-// Advection, software-pipelined (the same LDS limit as the adaptation).  LDS: the P rows j and j+1, the reciprocal
-// U-point averages of P on rows j and j+1, the V-point averages of P (and their reciprocals) on
-// V rows j-1/2, j+1/2, j+3/2, the per-level rows (Phi, U, u of row j, V, the u average on the V
-// row, v sin(theta) on V rows j+-1/2) double-buffered, and sigma-dot of row j in a ring of three
-// half levels.  Level k+1 (own columns, the leap gathers of U that its divergence needs, and the
-// base values) is fetched while level k is computed; the vertical neighbours come from a rolling
-// register window, so each level is read from memory once.  One barrier per level.
-constexpr int kAdvectPipeRows2D = 10, kAdvectPipeRowsLev = 7;
-__host__ __device__ constexpr size_t advect_pipe_lds(int nx, int elem) {
-  return (((size_t)(kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3) * nx * elem + 15) & ~size_t(15)) +
-         2 * 128 * sizeof(double);
-}
-__host__ __device__ constexpr bool advect_pipe_ok(int nx, int elem) { return advect_pipe_lds(nx, elem) <= 160 * 1024; }
-
-template <typename T, int NI>
-__device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned char* smem) {
-  const GeoDev& g = A.g;
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int B = blockDim.x;
-  int t = threadIdx.x;   // re-made opaque every level: column indices are recomputed, not held
-  // LDS cells column-major, 27 words per column: the 10 2D rows, the two buffers of 7 level rows
-  // and the 3-slot sigma-dot ring; one address per column index serves every row (the row is an
-  // immediate offset) and consecutive lanes stride 27 words (no bank conflicts)
-  constexpr int RS = kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3;
+  const int j = it.j, w = it.w, hl = WIDE ? 1 : it.hl;
+  const int NS = w + 2 * hl;
+  const int sl = threadIdx.x;
+  const bool act = sl < NS;                  // slots past NS only meet the barriers
+  const bool own = sl >= hl && sl < hl + w;  // owned column: the tendencies and every global write
+  int col = (it.i0 - hl + sl) % nx;
+  if (col < 0) col += nx;
   T* r = reinterpret_cast<T*>(smem);
-  auto S2 = [&](int row, int col) -> T& { return r[col * RS + row]; };
-  auto SB = [&](int bsel, int row, int col) -> T& {
-    return r[col * RS + kAdvectPipeRows2D + bsel * kAdvectPipeRowsLev + row];
-  };
-  auto SD = [&](int slot, int col) -> T& { return r[col * RS + kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + slot]; };
-  enum { RP0, RP1, RrPU0, RrPU1, RPV0, RPVm, RPV1, RrPV0, RrPVm, RrPV1 };
+  auto SB = [&](int bsel, int row, int slot) -> T& { return r[slot * kAdvTileRS + bsel * kAdvTileRows + row]; };
+  auto SD = [&](int ring, int slot) -> T& { return r[slot * kAdvTileRS + 2 * kAdvTileRows + ring]; };
   enum { BF, BU, Bu0, BV, Buv, Bvt0, Bvtm };
-  double* sCap = reinterpret_cast<double*>(
-      smem + ((((size_t)kAdvectPipeRows2D + 2 * kAdvectPipeRowsLev + 3) * nx * sizeof(T) + 15) & ~size_t(15)));
 
   const bool isPole = (j == 0 || j == ny);
   const bool hasV = (j < ny);
   const bool j1Pole = (j + 1 == ny);
   const bool j1Int = (j + 1 >= 1 && j + 1 <= ny - 1);
   const int pidx = (j == 0) ? 0 : 1;
+  const int ja = (j == 0) ? 1 : ny - 1;
   const T p0 = (T)g.p0;
-  const size_t row3 = (size_t)nz * nx;
+  const unsigned row3 = (unsigned)(nz * nx);
   auto psA = [&](int jr, int i) -> T {
     if (jr == 0) return (T)A.pin[nz];
     if (jr == ny) return (T)A.pin[(nz + 1) + nz];
     return A.inP[(size_t)jr * nx + i];
   };
-  auto FA = [&](int jr, int k, int i) -> T {
-    if (jr == 0) return (T)A.pin[k];
-    if (jr == ny) return (T)A.pin[(nz + 1) + k];
-    return A.inF[(size_t)jr * row3 + (size_t)k * nx + i];
-  };
-
-  // ---- 2D rows
-  const int ja = (j == 0) ? 1 : ny - 1;   // row next to a pole
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    if (i < nx) {
-      const T P0 = tsqrt<T>(psA(j, i) / p0);
-      const T P1 = tsqrt<T>(psA(hasV ? j + 1 : ja, i) / p0);
-      S2(RP0, i) = P0;
-      S2(RP1, i) = P1;
-      T PV0 = T(1), PVm = T(1), PV1 = T(1);
-      if (hasV) PV0 = T(0.5) * (P0 + P1);
-      if (j >= 1) PVm = T(0.5) * (tsqrt<T>(psA(j - 1, i) / p0) + P0);
-      if (j + 2 <= ny) PV1 = T(0.5) * (P1 + tsqrt<T>(psA(j + 2, i) / p0));
-      S2(RPV0, i) = PV0; S2(RPVm, i) = PVm; S2(RPV1, i) = PV1;
-      S2(RrPV0, i) = T(1) / PV0; S2(RrPVm, i) = T(1) / PVm; S2(RrPV1, i) = T(1) / PV1;
-      SD(0, i) = T(0);   // half level 0
-    }
-  }
-  __syncthreads();
-  if ((isPole || (hasV && j1Pole)) && t < 64) {
-    const int jv = (j == 0) ? 0 : ny - 1;
-    for (int k = 0; k < nz; ++k) {
-      const T* pV = A.inV + (size_t)jv * row3 + (size_t)k * nx;
-      C s1 = 0, s2 = 0;
-      for (int i = t; i < nx; i += 64) {
-        const T pv = T(0.5) * (S2(RP0, i) + S2(RP1, i));
-        const T vv = pV[i];
-        s1 += (C)(pv * vv);
-        if (isPole) s2 += (C)(vv / pv * (T)g.sv[jv] * FA(ja, k, i));
-      }
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      if (t == 0) { sCap[k] = s1; sCap[nz + k] = s2; }
-    }
-  }
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    if (i < nx) {
-      const int ip = wrp_up(i + 1, nx);
-      S2(RrPU0, i) = isPole ? T(0) : T(2) / (S2(RP0, i) + S2(RP0, ip));
-      S2(RrPU1, i) = j1Int ? T(2) / (S2(RP1, i) + S2(RP1, ip)) : T(0);
-    }
-  }
+  auto Prow = [&](int jr, int i) -> T { return tsqrt<T>(psA(jr, i) / p0); };
+  auto up1 = [&](int i) { return i == nx - 1 ? 0 : i + 1; };
 
   const int Mj = isPole ? 1 : g.M[j], nj = (Mj + 1) / 2;
   const int Mj1 = j1Int ? g.M[j + 1] : 1, nj1 = (Mj1 + 1) / 2;
@@ -834,168 +449,143 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
   const T sv1 = (j + 1 < ny) ? (T)g.sv[j + 1] : T(0);
   const C capD0 = isPole ? ((j == 0) ? 1.0 : -1.0) * g.a * g.dlam * g.sv[(j == 0) ? 0 : ny - 1] / g.acap : 0.0;
   const C capD1 = (hasV && j1Pole) ? -g.a * g.dlam * g.sv[ny - 1] / g.acap : 0.0;
+  const double* cap0 = A.cap + pidx * 2 * nz;   // this pole row's sums (pole rows)
+  const double* cap1 = A.cap + 1 * 2 * nz;      // the south pole's (row ny-1)
 
-  // per-column constants: 1 / P^2 (FP64)
-  C rP0sq[NI], rP1sq[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) {
-    const int i = t + c * B;
-    const int ii = i < nx ? i : 0;
-    rP0sq[c] = 1.0 / ((C)S2(RP0, ii) * (C)S2(RP0, ii));
-    rP1sq[c] = hasV ? 1.0 / ((C)S2(RP1, ii) * (C)S2(RP1, ii)) : 0.0;
+  // sigma-dot of row j: the owned columns and their eastern neighbour (the U points read both)
+  const bool sdr = act && sl >= hl && sl <= hl + w;
+  // ---- 2D values of this slot's column: P of rows j and j+1 (here and east), the U-point and
+  // V-point factors, the P averages at the leap neighbours that the divergence reads
+  const int ic = (col + nj - 1) % nx, id = (col - nj + nx) % nx;
+  const int ic1 = (col + nj1 - 1) % nx, id1 = (col - nj1 + nx) % nx;
+  T rPU0 = 0, rPU1 = 0, PV0 = 1, PVm = 1, PV1 = 1, rPV0 = 1, rPVm = 1, rPV1 = 1;
+  T PUc = 0, PUd = 0, PU1c = 0, PU1d = 0;
+  C rP0sq = 0, rP1sq = 0;
+  if (act) {
+    const T P0 = Prow(j, col), P1 = Prow(hasV ? j + 1 : ja, col);
+    if (!isPole) rPU0 = T(2) / (P0 + Prow(j, up1(col)));
+    if (j1Int) rPU1 = T(2) / (P1 + Prow(j + 1, up1(col)));
+    if (hasV) PV0 = T(0.5) * (P0 + P1);
+    if (j >= 1) PVm = T(0.5) * (Prow(j - 1, col) + P0);
+    if (j + 2 <= ny) PV1 = T(0.5) * (P1 + Prow(j + 2, col));
+    rPV0 = T(1) / PV0;
+    rPVm = T(1) / PVm;
+    rPV1 = T(1) / PV1;
+    rP0sq = 1.0 / ((C)P0 * (C)P0);
+    rP1sq = hasV ? 1.0 / ((C)P1 * (C)P1) : 0.0;
+    if (sdr && !isPole) {
+      PUc = T(0.5) * (Prow(j, ic) + Prow(j, up1(ic)));
+      PUd = T(0.5) * (Prow(j, id) + Prow(j, up1(id)));
+    }
+    if (j1Int && own) {
+      PU1c = T(0.5) * (Prow(j + 1, ic1) + Prow(j + 1, up1(ic1)));
+      PU1d = T(0.5) * (Prow(j + 1, id1) + Prow(j + 1, up1(id1)));
+    }
   }
-  __syncthreads();
-
-  // divergence of rows j and j+1 at level k from the owned column's values and leap gathers
-  auto div0 = [&](int k, int c, T Uic, T Uid, T Vj, T Vm) -> C {
-    if (isPole) return capD0 * sCap[k];
-    const int i = t + c * B;
-    const int ii = i < nx ? i : 0;
-    const int ic = wrp_up(ii + nj - 1, nx), id = wrp_dn(ii - nj, nx);
-    const T PUc = T(0.5) * (S2(RP0, ic) + S2(RP0, wrp_up(ic + 1, nx)));
-    const T PUd = T(0.5) * (S2(RP0, id) + S2(RP0, wrp_up(id + 1, nx)));
-    return (C)((PUc * Uic - PUd * Uid) * rdx + (svj * (S2(RPV0, ii) * Vj) - svm * (S2(RPVm, ii) * Vm)) * rdyS);
+  const bool d1 = own && hasV;   // sigma-dot of row j+1: owned columns only
+  // divergence of rows j and j+1 at level k
+  auto div0 = [&](int k, T Uic, T Uid, T Vj, T Vm) -> C {
+    if (isPole) return capD0 * cap0[k];
+    return (C)((PUc * Uic - PUd * Uid) * rdx + (svj * (PV0 * Vj) - svm * (PVm * Vm)) * rdyS);
   };
-  auto div1 = [&](int k, int c, T U1ic, T U1id, T Vj, T V1) -> C {
+  auto div1 = [&](int k, T U1ic, T U1id, T Vj, T V1) -> C {
     if (!hasV) return 0.0;
-    if (j1Pole) return capD1 * sCap[k];
-    const int i = t + c * B;
-    const int ii = i < nx ? i : 0;
-    const int ic1 = wrp_up(ii + nj1 - 1, nx), id1 = wrp_dn(ii - nj1, nx);
-    const T PU1c = T(0.5) * (S2(RP1, ic1) + S2(RP1, wrp_up(ic1 + 1, nx)));
-    const T PU1d = T(0.5) * (S2(RP1, id1) + S2(RP1, wrp_up(id1 + 1, nx)));
-    return (C)((PU1c * U1ic - PU1d * U1id) * rdx1 + (sv1 * (S2(RPV1, ii) * V1) - svj * (S2(RPV0, ii) * Vj)) * rdyS1);
+    if (j1Pole) return capD1 * cap1[k];
+    return (C)((PU1c * U1ic - PU1d * U1id) * rdx1 + (sv1 * (PV1 * V1) - svj * (PV0 * Vj)) * rdyS1);
   };
+  auto gU = [&](int jr, int k, int i) -> T { return ldg(A.inU, (unsigned)jr * row3 + (unsigned)(k * nx + i)); };
+  auto gV = [&](int jr, int k, int i) -> T { return ldg(A.inV, (unsigned)jr * row3 + (unsigned)(k * nx + i)); };
+  auto gF = [&](int jr, int k, int i) -> T { return ldg(A.inF, (unsigned)jr * row3 + (unsigned)(k * nx + i)); };
 
   // ---- pass A: column totals Pi of rows j and j+1
-  C Pi0[NI], Pi1[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) { Pi0[c] = 0; Pi1[c] = 0; }
-  {
+  C Pi0 = 0, Pi1 = 0;
+  if (sdr) {
     constexpr int KU = 3;
     for (int k0 = 0; k0 < nz; k0 += KU) {
-      T a0[KU][NI], a1[KU][NI], a2[KU][NI], a3[KU][NI], a4[KU][NI], a5[KU][NI], a6[KU][NI];
+      T a0[KU], a1[KU], a2[KU], a3[KU], a4[KU], a5[KU], a6[KU];
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
         const int k = k0 + u < nz ? k0 + u : nz - 1;
-        const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-        const auto gU0 = urow(A.inU, lo);
-        const auto gU1 = urow(A.inU, lo + row3);
-        const auto gV0 = urow(A.inV, lo);
-        const auto gVm = urow(A.inV, (lo - (j >= 1 ? row3 : 0)));
-        const auto gV1 = urow(A.inV, lo + row3);
-#pragma unroll
-        for (int c = 0; c < NI; ++c) {
-          const int i = t + c * B;
-          const int ii = i < nx ? i : 0;
-          a0[u][c] = isPole ? T(0) : gU0[(unsigned)wrp_up(ii + nj - 1, nx)];
-          a1[u][c] = isPole ? T(0) : gU0[(unsigned)wrp_dn(ii - nj, nx)];
-          a2[u][c] = j1Int ? gU1[(unsigned)wrp_up(ii + nj1 - 1, nx)] : T(0);
-          a3[u][c] = j1Int ? gU1[(unsigned)wrp_dn(ii - nj1, nx)] : T(0);
-          a4[u][c] = hasV ? gV0[(unsigned)ii] : T(0);
-          a5[u][c] = (j >= 1) ? gVm[(unsigned)ii] : T(0);
-          a6[u][c] = (j + 1 < ny) ? gV1[(unsigned)ii] : T(0);
-        }
+        a0[u] = isPole ? T(0) : gU(j, k, ic);
+        a1[u] = isPole ? T(0) : gU(j, k, id);
+        a2[u] = (d1 && j1Int) ? gU(j + 1, k, ic1) : T(0);
+        a3[u] = (d1 && j1Int) ? gU(j + 1, k, id1) : T(0);
+        a4[u] = hasV ? gV(j, k, col) : T(0);
+        a5[u] = (j >= 1) ? gV(j - 1, k, col) : T(0);
+        a6[u] = (d1 && j + 1 < ny) ? gV(j + 1, k, col) : T(0);
       }
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
         const int k = k0 + u;
         if (k < nz) {
           const C dsg = g.dsig[k];
-#pragma unroll
-          for (int c = 0; c < NI; ++c) {
-            Pi0[c] += div0(k, c, a0[u][c], a1[u][c], a4[u][c], a5[u][c]) * dsg;
-            Pi1[c] += div1(k, c, a2[u][c], a3[u][c], a4[u][c], a6[u][c]) * dsg;
-          }
+          Pi0 += div0(k, a0[u], a1[u], a4[u], a5[u]) * dsg;
+          if (d1) Pi1 += div1(k, a2[u], a3[u], a4[u], a6[u]) * dsg;
         }
       }
     }
   }
 
-  // ---- pass B, pipelined over levels
-  // next level (fetched one level ahead)
-  T nF[NI], nU[NI], nV[NI], nVm[NI], nU1[NI], nV1[NI], nFn[NI], nFs[NI], nUs[NI];
-  T nUic[NI], nUid[NI], nU1ic[NI], nU1id[NI];
-  // current level (the level above is read back from the other LDS buffer)
-  T cVm[NI], cU1[NI], cV1[NI], cFn[NI], cFs[NI], cUs[NI];
-  C S0[NI], S1[NI], sd0c[NI], sd0n[NI], sd1c[NI], sd1n[NI];
-#pragma unroll
-  for (int c = 0; c < NI; ++c) S0[c] = S1[c] = sd0c[c] = sd0n[c] = sd1c[c] = sd1n[c] = 0;
-
+  // ---- pass B, pipelined over levels: level k+1 is fetched while level k is computed
+  T nF = 0, nU = 0, nV = 0, nVm = 0, nU1 = 0, nV1 = 0, nFn = 0, nFs = 0, nUs = 0;
+  T nUic = 0, nUid = 0, nU1ic = 0, nU1id = 0;
+  T cVm = 0, cU1 = 0, cV1 = 0, cFn = 0, cFs = 0, cUs = 0;   // the owned column's values at level k
+  C S0 = 0, S1 = 0, sd0c = 0, sd0n = 0, sd1c = 0, sd1n = 0;
   auto fetch = [&](int k) {
-    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-    const auto gF0 = urow(A.inF, lo);
-    const auto gU0 = urow(A.inU, lo);
-    const auto gV0 = urow(A.inV, lo);
-    const auto gVm = urow(A.inV, (lo - (j >= 1 ? row3 : 0)));
-    const auto gU1 = urow(A.inU, lo + row3);
-    const auto gV1 = urow(A.inV, lo + row3);
-    const auto gF1 = urow(A.inF, lo + row3);
-    const auto gFs = urow(A.inF, (lo - (j >= 1 ? row3 : 0)));
-    const auto gUs = urow(A.inU, (lo - (j >= 1 ? row3 : 0)));
-    const T Fp0 = isPole ? (T)A.pin[pidx * (nz + 1) + k] : T(0);
-    const T Fn_p = (j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0);
-    const T Fs_p = (j - 1 == 0) ? (T)A.pin[k] : T(0);
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      const unsigned ii = i < nx ? (unsigned)i : 0u;
-      nF[c] = isPole ? Fp0 : gF0[ii];
-      nU[c] = isPole ? T(0) : gU0[ii];
-      nV[c] = hasV ? gV0[ii] : T(0);
-      nVm[c] = (j >= 1) ? gVm[ii] : T(0);
-      nU1[c] = j1Int ? gU1[ii] : T(0);
-      nV1[c] = (j + 1 < ny) ? gV1[ii] : T(0);
-      nFn[c] = (!isPole && j + 1 < ny) ? gF1[ii] : Fn_p;
-      nFs[c] = (!isPole && j - 1 >= 1) ? gFs[ii] : Fs_p;
-      nUs[c] = (!isPole && j - 1 >= 1) ? gUs[ii] : T(0);
-      nUic[c] = isPole ? T(0) : gU0[(unsigned)wrp_up((int)ii + nj - 1, nx)];
-      nUid[c] = isPole ? T(0) : gU0[(unsigned)wrp_dn((int)ii - nj, nx)];
-      nU1ic[c] = j1Int ? gU1[(unsigned)wrp_up((int)ii + nj1 - 1, nx)] : T(0);
-      nU1id[c] = j1Int ? gU1[(unsigned)wrp_dn((int)ii - nj1, nx)] : T(0);
+    if (!act) return;
+    nF = isPole ? (T)A.pin[pidx * (nz + 1) + k] : gF(j, k, col);
+    nU = isPole ? T(0) : gU(j, k, col);
+    nV = hasV ? gV(j, k, col) : T(0);
+    nVm = (j >= 1) ? gV(j - 1, k, col) : T(0);
+    nU1 = j1Int ? gU(j + 1, k, col) : T(0);
+    if (sdr && !isPole) {
+      nUic = gU(j, k, ic);
+      nUid = gU(j, k, id);
+    }
+    if (own) {
+      nV1 = (j + 1 < ny) ? gV(j + 1, k, col) : T(0);
+      nFn = (!isPole && j + 1 < ny) ? gF(j + 1, k, col) : ((j + 1 == ny) ? (T)A.pin[(nz + 1) + k] : T(0));
+      nFs = (!isPole && j - 1 >= 1) ? gF(j - 1, k, col) : ((j - 1 == 0) ? (T)A.pin[k] : T(0));
+      nUs = (!isPole && j - 1 >= 1) ? gU(j - 1, k, col) : T(0);
+      nU1ic = j1Int ? gU(j + 1, k, ic1) : T(0);
+      nU1id = j1Int ? gU(j + 1, k, id1) : T(0);
     }
   };
-  // level k into LDS buffer k & 1; sigma-dot of its lower half level into slot (k + 1) % 3;
-  // then the window moves down one level
+  // level k into LDS buffer k & 1, sigma-dot of its lower half level into ring slot (k + 1) % 3
   auto commit = [&](int k) {
+    if (!act) return;
     const int bs = k & 1, sn = (k + 1) % 3;
     const C dsg = g.dsig[k];
     const C sh = (k + 1 < nz) ? g.sigh[k + 1] : 0.0;
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      const C D0 = div0(k, c, nUic[c], nUid[c], nV[c], nVm[c]);
-      const C D1 = div1(k, c, nU1ic[c], nU1id[c], nV[c], nV1[c]);
-      S0[c] += D0 * dsg;
-      S1[c] += D1 * dsg;
-      sd0c[c] = sd0n[c];
-      sd1c[c] = sd1n[c];
-      sd0n[c] = 0;
-      sd1n[c] = 0;
+    if (sdr) {
+      S0 += div0(k, nUic, nUid, nV, nVm) * dsg;
+      if (d1) S1 += div1(k, nU1ic, nU1id, nV, nV1) * dsg;
+      sd0c = sd0n;
+      sd1c = sd1n;
+      sd0n = 0;
+      sd1n = 0;
       if (k + 1 < nz) {
-        sd0n[c] = (sh * Pi0[c] - S0[c]) * rP0sq[c];
-        if (hasV) sd1n[c] = (sh * Pi1[c] - S1[c]) * rP1sq[c];
+        sd0n = (sh * Pi0 - S0) * rP0sq;
+        if (d1) sd1n = (sh * Pi1 - S1) * rP1sq;
       }
-      if (i < nx) {
-        SB(bs, BF, i) = nF[c];
-        SB(bs, BU, i) = nU[c];
-        const T u0 = nU[c] * S2(RrPU0, i);
-        SB(bs, Bu0, i) = u0;
-        if (hasV) {
-          SB(bs, BV, i) = nV[c];
-          SB(bs, Bvt0, i) = nV[c] * S2(RrPV0, i) * svj;
-          SB(bs, Buv, i) = T(0.5) * (u0 + nU1[c] * S2(RrPU1, i));
-        }
-        if (j >= 1) SB(bs, Bvtm, i) = nVm[c] * S2(RrPVm, i) * svm;
-        SD(sn, i) = (T)sd0n[c];
-      }
-      cVm[c] = nVm[c]; cU1[c] = nU1[c]; cV1[c] = nV1[c];
-      cFn[c] = nFn[c]; cFs[c] = nFs[c]; cUs[c] = nUs[c];
     }
+    SB(bs, BF, sl) = nF;
+    SB(bs, BU, sl) = nU;
+    const T u0 = nU * rPU0;
+    SB(bs, Bu0, sl) = u0;
+    if (hasV) {
+      SB(bs, BV, sl) = nV;
+      SB(bs, Bvt0, sl) = nV * rPV0 * svj;
+      SB(bs, Buv, sl) = T(0.5) * (u0 + nU1 * rPU1);
+    }
+    if (j >= 1) SB(bs, Bvtm, sl) = nVm * rPVm * svm;
+    SD(sn, sl) = (T)sd0n;
+    cVm = nVm; cU1 = nU1; cV1 = nV1; cFn = nFn; cFs = nFs; cUs = nUs;
   };
 
   fetch(0);
   commit(0);
+  if (act) SD(0, sl) = T(0);   // half level 0
   __syncthreads();
 
   const C cc = g.a * g.dlam / (2.0 * g.acap);
@@ -1004,130 +594,166 @@ __device__ void advect_row_pipe(const StageArgs<T>& A, const int j, unsigned cha
   const int Mv = hasV ? g.Mv[j] : 1, nv = (Mv + 1) / 2;
   const T rdxv2 = hasV ? (T)(1.0 / (2.0 * (double)Mv * g.a * g.sv[j] * g.dlam)) : T(0);
   const T rdyv2 = hasV ? (T)(1.0 / (2.0 * g.a * g.sv[j] * g.dth)) : T(0);
+  T pF = 0, pU = 0, pV = 0;   // the owned column's level k-1 values
+  const unsigned oc = (unsigned)col;
 #pragma unroll 1
   for (int k = 0; k < nz; ++k) {
-    asm volatile("" : "+v"(t));
     const bool more = k + 1 < nz;
+    const T cF = nF, cU = nU, cV = nV;   // level k (the fetch below moves to level k+1)
+    T baseF = 0, baseU = 0, baseV = 0;
+    const unsigned lo = (unsigned)j * row3 + (unsigned)(k * nx);
+    if (own) {
+      if (!isPole) {
+        baseF = ldg(A.bF, lo + oc);
+        baseU = ldg(A.bU, lo + oc);
+      }
+      if (hasV) baseV = ldg(A.bV, lo + oc);
+    }
     if (more) fetch(k + 1);
     const C dsg = g.dsig[k], r2d = 1.0 / (2.0 * dsg);
-    // buffer of level k, the other buffer (level k-1, own columns only), sigma-dot slots above and below
-    const int bs = k & 1, ob = (k + 1) & 1, st = k % 3, sb = (k + 1) % 3;
-    const size_t lo = (size_t)j * row3 + (size_t)k * nx;
-    const auto goF = urow(A.oF, lo);
-    const auto goU = urow(A.oU, lo);
-    const auto goV = urow(A.oV, lo);
-    const auto gbF = urow(A.bF, lo);
-    const auto gbU = urow(A.bU, lo);
-    const auto gbV = urow(A.bV, lo);
-    T cbF[NI], cbU[NI], cbV[NI];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      const unsigned ii = i < nx ? (unsigned)i : 0u;
-      cbF[c] = isPole ? T(0) : gbF[ii];
-      cbU[c] = isPole ? T(0) : gbU[ii];
-      cbV[c] = hasV ? gbV[ii] : T(0);
-    }
-
-    if (!isPole) {
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const int ic = wrp_up(i + nj - 1, nx), id = wrp_dn(i - nj, nx);
-        const int pM = wrp_up(i + Mj, nx), mM = wrp_dn(i - Mj, nx);
-        // Phi: zonal (x+1, x-1) -> (x+2N-1, x-2N+1) with u at the midpoints
-        const T L1 = (SB(bs, Bu0, ic) * SB(bs, BF, pM) - SB(bs, Bu0, id) * SB(bs, BF, mM)) * rdx2;
-        const T L2 = (SB(bs, Bvt0, i) * cFn[c] - SB(bs, Bvtm, i) * cFs[c]) * rdy2;
+    const int bs = k & 1, st = k % 3, sb = (k + 1) % 3;
+    // level-k values at offset o from the owned column: LDS (band) or formed from global memory (wide)
+    // (the wide forms repeat commit's statements, so that both forms round and contract alike)
+    auto cw = [&](int o) { return ((col + o) % nx + nx) % nx; };
+    auto vF = [&](int o) -> T { return WIDE ? gF(j, k, cw(o)) : SB(bs, BF, sl + o); };
+    auto vU = [&](int o) -> T { return WIDE ? gU(j, k, cw(o)) : SB(bs, BU, sl + o); };
+    auto vV = [&](int o) -> T { return WIDE ? gV(j, k, cw(o)) : SB(bs, BV, sl + o); };
+    auto wu0 = [&](int c) -> T {
+      const T Uc = isPole ? T(0) : gU(j, k, c);
+      const T rp = isPole ? T(0) : T(2) / (Prow(j, c) + Prow(j, up1(c)));
+      const T u0 = Uc * rp;
+      return u0;
+    };
+    auto vu0 = [&](int o) -> T { return WIDE ? wu0(cw(o)) : SB(bs, Bu0, sl + o); };
+    auto vuv = [&](int o) -> T {
+      if (!WIDE) return SB(bs, Buv, sl + o);
+      const int c = cw(o);
+      const T u0 = wu0(c);
+      const T U1c = j1Int ? gU(j + 1, k, c) : T(0);
+      const T rp1 = j1Int ? T(2) / (Prow(j + 1, c) + Prow(j + 1, up1(c))) : T(0);
+      return T(0.5) * (u0 + U1c * rp1);
+    };
+    if (own) {
+      const int sp = sl + 1;
+      if (!isPole) {
+        // Phi: the leaped centred difference of u Phi, u at the midpoints
+        const T L1 = (vu0(nj - 1) * vF(Mj) - vu0(-nj) * vF(-Mj)) * rdx2;
+        const T L2 = (SB(bs, Bvt0, sl) * cFn - SB(bs, Bvtm, sl) * cFs) * rdy2;
         C L3 = 0;
-        if (more) L3 += sd0n[c] * (C)nF[c];
-        if (k > 0) L3 -= sd0c[c] * (C)SB(ob, BF, i);
+        if (more) L3 += sd0n * (C)nF;
+        if (k > 0) L3 -= sd0c * (C)pF;
         const C TF = -((C)L1 + (C)L2 + L3 * r2d);
-        goF[i] = (T)((C)cbF[c] + A.ch * TF);
+        stg(A.oF, lo + oc, (T)((C)baseF + A.ch * TF));
         // U: the same leap on U points, u averaged to the integer points i+n and i+1-n
-        const int pA = wrp_up(i + nj, nx), pB = wrp_dn(i + 1 - nj, nx);
-        const T ubA = T(0.5) * (SB(bs, Bu0, ic) + SB(bs, Bu0, pA));
-        const T ubB = T(0.5) * (SB(bs, Bu0, id) + SB(bs, Bu0, pB));
-        const T U1v = (ubA * SB(bs, BU, pM) - ubB * SB(bs, BU, mM)) * rdx2;
-        const int ip = wrp_up(i + 1, nx);
-        const T vtn = T(0.5) * (SB(bs, Bvt0, i) + SB(bs, Bvt0, ip));
-        const T vts = T(0.5) * (SB(bs, Bvtm, i) + SB(bs, Bvtm, ip));
-        const T U2v = (vtn * cU1[c] - vts * cUs[c]) * rdy2;
+        const T ubA = T(0.5) * (vu0(nj - 1) + vu0(nj));
+        const T ubB = T(0.5) * (vu0(-nj) + vu0(1 - nj));
+        const T U1v = (ubA * vU(Mj) - ubB * vU(-Mj)) * rdx2;
+        const T vtn = T(0.5) * (SB(bs, Bvt0, sl) + SB(bs, Bvt0, sp));
+        const T vts = T(0.5) * (SB(bs, Bvtm, sl) + SB(bs, Bvtm, sp));
+        const T U2v = (vtn * cU1 - vts * cUs) * rdy2;
         C U3 = 0;
-        if (more) U3 += (C)(T(0.5) * (SD(sb, i) + SD(sb, ip))) * (C)nU[c];
-        if (k > 0) U3 -= (C)(T(0.5) * (SD(st, i) + SD(st, ip))) * (C)SB(ob, BU, i);
+        if (more) U3 += (C)(T(0.5) * (SD(sb, sl) + SD(sb, sp))) * (C)nU;
+        if (k > 0) U3 -= (C)(T(0.5) * (SD(st, sl) + SD(st, sp))) * (C)pU;
         const C TU = -((C)U1v + (C)U2v + U3 * r2d);
-        goU[i] = (T)((C)cbU[c] + A.ch * TU);
-        __builtin_amdgcn_sched_barrier(0);
+        stg(A.oU, lo + oc, (T)((C)baseU + A.ch * TU));
+      } else {
+        const C sgn = (j == 0) ? 1.0 : -1.0;
+        const C L2 = sgn * cc * cap0[nz + k];
+        C L3 = 0;
+        if (more) L3 += sd0n * (C)(T)A.pin[pidx * (nz + 1) + k + 1];
+        if (k > 0) L3 -= sd0c * (C)(T)A.pin[pidx * (nz + 1) + k - 1];
+        const C TF = -(L2 + L3 * r2d);
+        const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
+        stg(A.oF, lo + oc, val);
+        stg(A.oU, lo + oc, T(0));
+        if (col == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
       }
-    } else {
-      const C sgn = (j == 0) ? 1.0 : -1.0;
-      const C L2 = sgn * cc * sCap[nz + k];
-      C L3 = 0;
-      if (more) L3 += sd0n[0] * (C)FA(j, k + 1, 0);
-      if (k > 0) L3 -= sd0c[0] * (C)FA(j, k - 1, 0);
-      const C TF = -(L2 + L3 * r2d);
-      const T val = (T)(A.pbase[pidx * (nz + 1) + k] + A.ch * TF);
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i < nx) {
-          goF[i] = val;
-          goU[i] = T(0);
-        }
-      }
-      if (t == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
-    }
-
-    if (hasV) {
-#pragma unroll
-      for (int c = 0; c < NI; ++c) {
-        const int i = t + c * B;
-        if (i >= nx) continue;
-        const T L1 = (SB(bs, Buv, wrp_up(i + nv - 1, nx)) * SB(bs, BV, wrp_up(i + Mv, nx)) - SB(bs, Buv, wrp_dn(i - nv, nx)) * SB(bs, BV, wrp_dn(i - Mv, nx))) * rdxv2;
+      if (hasV) {
+        const T L1 = (vuv(nv - 1) * vV(Mv) - vuv(-nv) * vV(-Mv)) * rdxv2;
         T L2 = T(0);
-        if (j + 1 < ny) L2 += T(0.5) * (SB(bs, Bvt0, i) + cV1[c] * S2(RrPV1, i) * sv1) * cV1[c];
-        if (j > 0) L2 -= T(0.5) * (SB(bs, Bvtm, i) + SB(bs, Bvt0, i)) * cVm[c];
+        if (j + 1 < ny) L2 += T(0.5) * (SB(bs, Bvt0, sl) + cV1 * rPV1 * sv1) * cV1;
+        if (j > 0) L2 -= T(0.5) * (SB(bs, Bvtm, sl) + SB(bs, Bvt0, sl)) * cVm;
         L2 = L2 * rdyv2;
         C L3 = 0;
-        if (more) L3 += 0.5 * (sd0n[c] + sd1n[c]) * (C)nV[c];
-        if (k > 0) L3 -= 0.5 * (sd0c[c] + sd1c[c]) * (C)SB(ob, BV, i);
+        if (more) L3 += 0.5 * (sd0n + sd1n) * (C)nV;
+        if (k > 0) L3 -= 0.5 * (sd0c + sd1c) * (C)pV;
         const C TV = -((C)L1 + (C)L2 + L3 * r2d);
-        goV[i] = (T)((C)cbV[c] + A.ch * TV);
-        __builtin_amdgcn_sched_barrier(0);
+        stg(A.oV, lo + oc, (T)((C)baseV + A.ch * TV));
       }
     }
+    pF = cF;
+    pU = cU;
+    pV = cV;
     if (more) commit(k + 1);
     __syncthreads();
   }
 
   // p_s is not advected
-  if (!isPole) {
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) A.oP[(size_t)j * nx + i] = A.bP[(size_t)j * nx + i];
+  if (own) {
+    const size_t i2 = (size_t)j * nx + col;
+    if (!isPole) {
+      A.oP[i2] = A.bP[i2];
+    } else {
+      const T val = (T)A.pbase[pidx * (nz + 1) + nz];
+      A.oP[i2] = val;
+      if (col == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
     }
-  } else {
-    const T val = (T)A.pbase[pidx * (nz + 1) + nz];
-#pragma unroll
-    for (int c = 0; c < NI; ++c) {
-      const int i = t + c * B;
-      if (i < nx) A.oP[(size_t)j * nx + i] = val;
-    }
-    if (t == 0) A.pout[pidx * (nz + 1) + nz] = (double)val;
   }
 }
 
-// One launch per advection stage; the form is a template parameter so that the row kernels are
-// separate symbols in a profile.  PROC: 1 advection, 3 its pipelined form (rows whose 27 LDS rows fit
-// in 160 KB).
-template <typename T, int NI, int PROC>
-__global__ void __launch_bounds__(max_block(NI)) k_stage(StageArgs<T> a) {
+// FP64 cap sums of the advection stage's input, one wavefront per (level, pole), in the fixed order
+// of the lane-strided partial sums and a butterfly: the flux sum_i P^V V through the V row next to
+// the pole and sum_i (V / P^V) sin(theta) Phi of the row next to the pole.
+template <typename T>
+__device__ void capsum_adv_level(const StageArgs<T>& A, int k, int p) {
+  const GeoDev& g = A.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const T p0 = (T)g.p0;
+  const int ja = (p == 0) ? 1 : ny - 1, jv = (p == 0) ? 0 : ny - 1;
+  const T Pp = tsqrt<T>((T)A.pin[(p == 0 ? 0 : nz + 1) + nz] / p0);
+  const T* pV = A.inV + ((size_t)jv * nz + k) * nx;
+  const T* pF = A.inF + ((size_t)ja * nz + k) * nx;
+  const T svv = (T)g.sv[jv];
+  C s1 = 0, s2 = 0;
+  for (int i = threadIdx.x; i < nx; i += 64) {
+    const T pv = T(0.5) * (Pp + tsqrt<T>(A.inP[(size_t)ja * nx + i] / p0));
+    const T vv = pV[i];
+    s1 += (C)(pv * vv);
+    s2 += (C)(vv / pv * svv * pF[i]);
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (threadIdx.x == 0) {
+    A.cap[p * 2 * nz + k] = s1;
+    A.cap[p * 2 * nz + nz + k] = s2;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_capsum_adv(StageArgs<T> a) {
+  capsum_adv_level<T>(a, blockIdx.x, blockIdx.y);
+}
+
+// The cap sums of every batched member, for the process of its stage.
+template <typename T>
+__global__ void __launch_bounds__(64) k_capsum_batch(const StageArgs<T>* __restrict__ args, int n) {
+  const int m = blockIdx.z;
+  if (m >= n) return;
+  const StageArgs<T> a = args[m];
+  if ((int)blockIdx.x >= a.g.nz) return;
+  if (a.process == 0) capsum_level<T>(a, blockIdx.x, blockIdx.y);
+  else if (a.process == 1) capsum_adv_level<T>(a, blockIdx.x, blockIdx.y);
+}
+
+// One launch per advection stage (after k_capsum_adv): one workgroup per zonal tile, the wide tiles
+// first in the list so that they start early.
+template <typename T>
+__global__ void __launch_bounds__(256) k_stage_atile(StageArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int j = xcd_row(blockIdx.x, a.g.ny + 1);
-  if constexpr (PROC == 3) advect_row_pipe<T, NI>(a, j, smem);
-  else advect_row<T, NI>(a, j, smem);
+  const AatItem it = a.atiles[blockIdx.x];
+  if (it.j < 0) return;
+  if (it.hl < 0) advect_tile<T, true>(a, it, smem);
+  else advect_tile<T, false>(a, it, smem);
 }
 
 // One launch per adaptation stage: one workgroup per zonal tile (the cap sums come from k_capsum).
@@ -1139,32 +765,25 @@ __global__ void __launch_bounds__(kFwdTileMaxBlock) k_stage_tile(StageArgs<T> a)
   adapt_tile<T>(a, it, smem);
 }
 
-// Persistent batched stage.  Work items: first the adaptation tiles of every member (tile item =
-// (member, index into the member's tile table)), then the advection rows (row item = (member, row));
-// a workgroup takes items b, b+G, ... and skips those whose member is not at that process in this
-// stage.  PIPE: 1 when every member's advection takes the pipelined form, 0 when none does, 2 mixed.
-template <typename T, int NI, int PIPE>
-__global__ void __launch_bounds__(max_block(NI)) k_stage_batch(const StageArgs<T>* __restrict__ args,
-                                                               const int2* __restrict__ titems, int ntitems,
-                                                               const int2* __restrict__ items, int nitems) {
+// Persistent batched stage of one process (one launch each, so that each has its own register
+// budget).  Work items: the tiles of every member (item = (member, index into the member's tile table
+// of that process)); a workgroup takes items b, b+G, ... and skips those whose member is not at that
+// process in this stage.  Every column's arithmetic is that of the single-member launches whatever
+// the tiling, so members equal their own steps bit for bit.
+template <typename T, int PROC>
+__global__ void __launch_bounds__(kBatchMaxBlock) k_stage_batch(const StageArgs<T>* __restrict__ args,
+                                                                const int2* __restrict__ items, int nitems) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int w = blockIdx.x; w < ntitems + nitems; w += gridDim.x) {
-    const bool tile = w < ntitems;
-    const int2 it = tile ? titems[w] : items[w - ntitems];
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const int2 it = items[w];
     if (it.x < 0) continue;
     const StageArgs<T> a = args[it.x];
-    if (tile) {
-      if (a.process != 0) continue;
-      const AatItem ti = a.tiles[it.y];
-      if (ti.j < 0) continue;
-      adapt_tile<T>(a, ti, smem);
-    } else {
-      if (a.process != 1) continue;
-      if constexpr (PIPE == 1) advect_row_pipe<T, NI>(a, it.y, smem);
-      else if constexpr (PIPE == 0) advect_row<T, NI>(a, it.y, smem);
-      else if (advect_pipe_ok(a.g.nx, sizeof(T))) advect_row_pipe<T, NI>(a, it.y, smem);
-      else advect_row<T, NI>(a, it.y, smem);
-    }
+    if (a.process != PROC) continue;
+    const AatItem ti = PROC == 0 ? a.tiles[it.y] : a.atiles[it.y];
+    if (ti.j < 0) continue;
+    if constexpr (PROC == 0) adapt_tile<T>(a, ti, smem);
+    else if (ti.hl < 0) advect_tile<T, true>(a, ti, smem);
+    else advect_tile<T, false>(a, ti, smem);
     __syncthreads();
   }
 }
@@ -1331,22 +950,6 @@ hipError_t allow_lds(size_t lds) {
   return e;
 }
 
-template <typename T, int NI>
-hipError_t launch_stage_ni(const StageArgs<T>& a, int block, hipStream_t s) {
-  const size_t lds = stage_lds_bytes(a.process, a.g.nx, sizeof(T));
-  hipError_t e;
-  if (advect_pipe_ok(a.g.nx, sizeof(T))) {
-    e = allow_lds<k_stage<T, NI, 3>>(lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage<T, NI, 3>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
-  } else {
-    e = allow_lds<k_stage<T, NI, 1>>(lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage<T, NI, 1>), dim3(a.g.ny + 1), dim3(block), lds, s, a);
-  }
-  return hipGetLastError();
-}
-
 // An adaptation stage: the cap sums of its input, then the tiles.
 template <typename T>
 hipError_t launch_adapt_tiles(const StageArgs<T>& a, hipStream_t s) {
@@ -1360,71 +963,43 @@ hipError_t launch_adapt_tiles(const StageArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int NI, int PIPE>
-hipError_t launch_batch_pipe(const StageArgs<T>* d_args, const int2* d_titems, int ntitems, const int2* d_items,
-                             int nitems, int grid, int block, size_t lds, hipStream_t s) {
-  hipError_t e = allow_lds<k_stage_batch<T, NI, PIPE>>(lds);
+// An advection stage: the pole cap sums of its input, then the tiles.
+template <typename T>
+hipError_t launch_advect_tiles(const StageArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_capsum_adv<T>), dim3(a.g.nz, 2), dim3(64), 0, s, a);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stage_batch<T, NI, PIPE>), dim3(grid), dim3(block), lds, s, d_args, d_titems, ntitems,
-                     d_items, nitems);
+  hipLaunchKernelGGL((k_stage_atile<T>), dim3(a.natiles), dim3(a.ablock), advect_tile_lds(a.ablock, sizeof(T)), s, a);
   return hipGetLastError();
-}
-
-template <typename T, int NI>
-hipError_t launch_batch_ni(const StageArgs<T>* d_args, const int2* d_titems, int ntitems, const int2* d_items,
-                           int nitems, int grid, int block, size_t lds, int pipe, hipStream_t s) {
-  if (pipe == 1) return launch_batch_pipe<T, NI, 1>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, s);
-  if (pipe == 2) return launch_batch_pipe<T, NI, 2>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, s);
-  return launch_batch_pipe<T, NI, 0>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, s);
 }
 
 }  // namespace
 
-size_t stage_lds_bytes(int process, int nx, int elem) {
-  if (process == 0) return adapt_tile_lds(elem == 4 ? kFwdTileMaxBlock : 704, elem);   // the largest tile block
-  if (advect_pipe_ok(nx, elem)) return advect_pipe_lds(nx, elem);
-  const size_t rows = 12;
-  return ((rows * (size_t)nx * elem + 15) & ~size_t(15)) + 2 * 128 * sizeof(double);
-}
-
-int columns_per_thread(int nx, int block) { return (nx + block - 1) / block; }
 size_t adapt_tile_lds_bytes(int block, int elem) { return adapt_tile_lds(block, elem); }
-int stage_pipelined(int nx, int elem) { return advect_pipe_ok(nx, elem) ? 1 : 0; }
+size_t advect_tile_lds_bytes(int block, int elem) { return advect_tile_lds(block, elem); }
 
 template <typename T>
-hipError_t launch_stage(const StageArgs<T>& a, int block, hipStream_t s) {
-  if (a.process == 0) return launch_adapt_tiles<T>(a, s);
-  switch (columns_per_thread(a.g.nx, block)) {
-    case 1: return launch_stage_ni<T, 1>(a, block, s);
-    case 2: return launch_stage_ni<T, 2>(a, block, s);
-    case 3: return launch_stage_ni<T, 3>(a, block, s);
-    case 4: return launch_stage_ni<T, 4>(a, block, s);
-    case 5: return launch_stage_ni<T, 5>(a, block, s);
-    case 6: return launch_stage_ni<T, 6>(a, block, s);
-    case 7: return launch_stage_ni<T, 7>(a, block, s);
-    case 8: return launch_stage_ni<T, 8>(a, block, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_stage(const StageArgs<T>& a, hipStream_t s) {
+  return a.process == 0 ? launch_adapt_tiles<T>(a, s) : launch_advect_tiles<T>(a, s);
 }
 
 template <typename T>
 hipError_t launch_stage_batch(const StageArgs<T>* d_args, int nargs, int max_nz, const int2* d_titems, int ntitems,
-                              const int2* d_items, int nitems, int grid, int block, int max_nx, size_t lds, int pipe,
-                              hipStream_t s) {
+                              const int2* d_items, int nitems, int grid, int block, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((k_capsum_batch<T>), dim3(max_nz, 2, nargs), dim3(64), 0, s, d_args, nargs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  switch (columns_per_thread(max_nx, block)) {
-    case 1: return launch_batch_ni<T, 1>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    case 2: return launch_batch_ni<T, 2>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    case 3: return launch_batch_ni<T, 3>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    case 4: return launch_batch_ni<T, 4>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    case 5: return launch_batch_ni<T, 5>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    case 6: return launch_batch_ni<T, 6>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    case 7: return launch_batch_ni<T, 7>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    case 8: return launch_batch_ni<T, 8>(d_args, d_titems, ntitems, d_items, nitems, grid, block, lds, pipe, s);
-    default: return hipErrorInvalidValue;
+  if (ntitems > 0) {
+    if ((e = allow_lds<k_stage_batch<T, 0>>(lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage_batch<T, 0>), dim3(grid), dim3(block), lds, s, d_args, d_titems, ntitems);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  if (nitems > 0) {
+    if ((e = allow_lds<k_stage_batch<T, 1>>(lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage_batch<T, 1>), dim3(grid), dim3(block), lds, s, d_args, d_items, nitems);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 template <typename T>
@@ -1469,9 +1044,9 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s) {
 }
 
 #define DYC_INST(T)                                                                                          \
-  template hipError_t launch_stage<T>(const StageArgs<T>&, int, hipStream_t);                                \
+  template hipError_t launch_stage<T>(const StageArgs<T>&, hipStream_t);                                     \
   template hipError_t launch_stage_batch<T>(const StageArgs<T>*, int, int, const int2*, int, const int2*, int,   \
-                                            int, int, int, size_t, int, hipStream_t);                        \
+                                            int, int, size_t, hipStream_t);                                  \
   template hipError_t launch_pole_prep<T>(const GeoDev&, const T*, const T*, double*, hipStream_t);          \
   template hipError_t launch_diag<T>(const GeoDev&, const T*, const T*, const T*, const T*, double*, double*, \
                                      hipStream_t);                                                           \

@@ -1,7 +1,7 @@
 """GPU parity at the 0.25-degree workload (1440 x 720 x 30, dt 120 s, M = 4), in the launch
-configuration the benchmark times: the default workgroup of 768 threads with two columns per thread,
-the pipelined FP32 stage kernels and the row-fused FP32 adaptation-stage adjoint at the full leap
-spans (163 on U rows, 325 on V rows).  Every case starts from the FP32-rounded state, so FP32 and FP64
+configuration the benchmark times: the tiled FP32 stage kernels (256-thread advection tiles, the rows
+next to the poles in the wide form) and the row-fused FP32 stage adjoints at the full leap spans (163
+on U rows, 325 on V rows).  Every case starts from the FP32-rounded state, so FP32 and FP64
 modes are compared with one set of FP64 oracle results.
 
 FP32 bounds: 5x the errors measured on MI355X (stated per process and field; the measured values are
@@ -72,9 +72,9 @@ def _host(d):
 
 
 def test_c4_launch_configuration():
-    """The handle the benchmark uses: 768 threads per row, so 2 columns per thread at 1440 columns."""
+    """The handle the benchmark uses: advection tiles of 256 threads, M = 4, the full leap spans."""
     core = _core("fp32")
-    assert core.block == 768 and core.substeps == 4
+    assert core.block == 256 and core.substeps == 4
     m, mv = core.leap_table()
     assert m.max() == 163 and mv.max() == 325
 

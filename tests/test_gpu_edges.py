@@ -1,7 +1,7 @@
-"""GPU edge cases: every kernel form on both sides of the row length at which its LDS rows stop
-fitting (the pipelined stage kernels), the tilings of the row-fused adaptation adjoint, ragged rows at two columns
-per thread, a single sigma level, zero steps, sizes the library refuses, and a stage adjoint whose
-base and input adjoints are one buffer."""
+"""GPU edge cases: row lengths around the former whole-row LDS limits and the longest rows accepted
+(every stage now runs in zonal tiles), the tilings of the row-fused stage adjoints, ragged tiles, a
+single sigma level, zero steps, sizes the library refuses, and a stage adjoint whose base and input
+adjoints are one buffer."""
 import dataclasses
 
 import numpy as np
@@ -32,20 +32,12 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def _lds_fits(rows, nx, elem):
-    """Whether `rows` LDS rows of nx values (16-byte aligned) plus 2 KiB of pole sums fit 160 KiB."""
-    return ((rows * nx * elem + 15) // 16) * 16 + 2048 <= 160 * 1024
-
-
-# The pipelined stage kernels hold 27 rows: FP64 rows of 749 columns fit, 750 do not.
-assert _lds_fits(27, 749, 8) and not _lds_fits(27, 750, 8)
-assert _lds_fits(27, 1498, 4) and not _lds_fits(27, 1499, 4)
-
-
+# Row lengths at which whole-row kernels with 27 LDS rows would stop fitting 160 KiB (749/750 columns
+# in FP64, 1498/1499 in FP32): the zonal tiles do not depend on them, and these cases check so.
 @pytest.mark.parametrize("nx", [749, 750])
 @pytest.mark.parametrize("process", ["A", "L"])
 def test_tendency_fp64_across_pipeline_limit(nx, process):
-    """Both stage-kernel forms (pipelined at 749 columns, per-level barriers at 750) equal the oracle."""
+    """Stage tendencies on rows of 749 and 750 columns (ragged last tiles) equal the oracle."""
     print(f"tendency fp64 nx={nx} {process}", flush=True)
     cfg = small(nx, 8, 3)
     st = synth.make_state(cfg)
@@ -62,8 +54,8 @@ def test_tendency_fp64_across_pipeline_limit(nx, process):
 @pytest.mark.parametrize("nx", [1000, 1498, 1499])
 @pytest.mark.parametrize("process", ["A", "L"])
 def test_stage_fp32_ragged_and_limit(nx, process):
-    """FP32 stages at two columns per thread with a ragged second column (1000), at the last row
-    length the pipelined kernels take (1498) and the first they do not (1499)."""
+    """FP32 stages on rows of 1000, 1498 and 1499 columns (ragged last tiles) within 2e-3 of the
+    increment scale of the oracle's."""
     print(f"stage fp32 nx={nx} {process}", flush=True)
     cfg = small(nx, 10, 3)
     st = synth.make_state(cfg)
@@ -162,12 +154,32 @@ def test_zero_steps_is_identity():
         assert torch.equal(d[k], ref[k]), k
 
 
+@pytest.mark.parametrize("process", ["A", "L"])
+def test_longest_rows_fp32(process):
+    """Rows of 4096 columns (the largest accepted) run in zonal tiles like any other and equal the
+    oracle's stage."""
+    cfg = small(4096, 8, 2)
+    st = synth.make_state(cfg)
+    st32 = {k: st[k].astype(np.float32).astype(np.float64) for k in ("U", "V", "Phi", "ps")}
+    ch = 60.0
+    want = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"]).stage(st32, st32, ch, process)
+    core = _core(cfg, st, "fp32", forward_only=True)
+    d = core.to_device(st32)
+    out = {k: torch.empty_like(v) for k, v in d.items()}
+    got = _host(core.stage(process, ch, d, d, out))
+    for k in ("U", "V", "Phi", "ps"):
+        inc = want[k] - st32[k]
+        scale = max(np.abs(inc).max(), np.abs(want[k]).max() * 1e-7)
+        err = np.abs(got[k] - want[k]).max() / scale
+        assert err < 2e-3, (k, err)
+
+
 def test_refused_sizes():
-    """Rows too long for any kernel form's LDS are refused at create (not at the first step);
-    grids below the minimum and too many levels are argument errors."""
+    """Rows above 4096 columns, grids below the minimum and too many levels are argument errors,
+    reported at create (not at the first step)."""
     from paper_2103_10114_amd import Dycore, DycoreError
     with pytest.raises(DycoreError):
-        Dycore(4096, 8, 3, 60.0, prec="fp32", forward_only=True)
+        Dycore(4097, 8, 3, 60.0, prec="fp32", forward_only=True)
     with pytest.raises(DycoreError):
         Dycore(7, 8, 3, 60.0, prec="fp64", forward_only=True)
     with pytest.raises(DycoreError):

@@ -52,7 +52,8 @@ def test_tendency_fp64(cfg, process):
 
 @pytest.mark.parametrize("block", [64, 128, 256])
 def test_tendency_fp64_blocks(block):
-    """Results do not depend on the workgroup size (columns per thread 1..3)."""
+    """Results do not depend on the advection tiles' workgroup size (64 and 128 threads turn the
+    rows next to the poles into wide tiles)."""
     cfg = small(150, 32, 4)
     st = synth.make_state(cfg)
     o = oracle.Oracle(cfg.nx, cfg.ny, cfg.nz, phis=st["phis"])
