@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(256) k_f1p(Ctx<T> c) {
 template <typename T>
 __global__ void k_base(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = c.jr0 + c.jrs * (int)blockIdx.z, k = blockIdx.y;
+  const int j = row_of(c, (int)blockIdx.z, (int)gridDim.z), k = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const size_t id = i3<T>(g, j, k, i);
@@ -962,121 +962,160 @@ __global__ void k_a3t1(Ctx<T> c) {
   if (j < g.ny) c.s.APV3[id] = (T)((C)c.s.APV3[id] + aPV3);
 }
 
-// Adaptation, per column, top to bottom: hydrostatic transpose phi' -> R T' -> (Phi, P) and the
-// column sums of the 2D adjoints.
-template <typename T>
-__global__ void k_a4(Ctx<T> c) {
-  const GeoDev& g = c.g;
-  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nx) return;
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const T b = (T)g.b;
-  const C P = (C)P2(c, j, i);
-  const C bP = (C)b / P, bP2 = (C)b / (P * P);
-  const bool intr = (j >= 1 && j < ny);
-  C aP = 0, aPU = 0, aPV = 0, aL = 0, aQ = 0, aDL = 0, aDQ = 0, pre = 0;
-  for (int k = 0; k < nz; ++k) {
-    asm volatile("" : "+v"(i));
-    const size_t id = i3<T>(g, j, k, i);
-    const C aphi = (C)c.s.APHI[id];
-    const C art = (C)c.s.ART[id] + g.cl[k] * pre + g.cpk[k] * aphi;
-    pre += aphi;
-    const C afe = (C)c.s.AFE[id] + bP * art;
-    aP += (C)c.s.AP3[id] - bP2 * (C)Fe(c, j, k, i) * art;
-    aL += (C)c.s.AL3[id];
-    aQ += (C)c.s.AQ3[id];
-    if (intr) {
-      aDL += (C)c.s.ADL3[id];
-      aDQ += (C)c.s.ADQ3[id];
-      aPU += (C)c.s.APU3[id];
-      c.aiF[id] = (T)((C)c.aiF[id] + afe);
-    } else {
-      c.s.AFE[id] = (T)afe;     // pole copies: aggregated later
+// The column kernels below run a column as kLG level groups of contiguous levels (block 64 x kLG:
+// 64 columns, one group per y index), so that a column's latency is that of its group's levels;
+// partial FP64 sums meet in LDS and are added in group order.
+constexpr int kLG = 4;
+
+template <int N>
+__device__ __forceinline__ void group_sums(double (&v)[N], double (*red)[kLG][64]) {
+  const int c = threadIdx.x, q = threadIdx.y;
+#pragma unroll
+  for (int n = 0; n < N; ++n) red[n][q][c] = v[n];
+  __syncthreads();
+  if (q == 0) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      double t = red[n][0][c];
+      for (int r = 1; r < kLG; ++r) t += red[n][r][c];
+      v[n] = t;
     }
-    if (j < ny) aPV += (C)c.s.APV3[id];
   }
-  const size_t i2 = (size_t)j * nx + i;
-  c.s.AP2[i2] = aP;
-  c.s.APU2[i2] = aPU;
-  c.s.APV2[i2] = aPV;
-  c.s.AL2[i2] = aL;
-  c.s.AQ2[i2] = aQ;
-  c.s.ADL2[i2] = aDL;
-  c.s.ADQ2[i2] = aDQ;
 }
 
-// Advection, per column, top to bottom: the divergence and velocity transposes into U and V (the
-// adjoints of u, U, v, V at each point come from the advection transposes) and the column sums of
-// the staggered-P adjoints.
+// Adaptation, per column: hydrostatic transpose phi' -> R T' -> (Phi, P) and the column sums of the
+// 2D adjoints.  The transpose's running sum of the phi' adjoints from the top starts each level
+// group at the sum over the groups above it.
 template <typename T>
-__global__ void k_l3(Ctx<T> c) {
+__global__ void __launch_bounds__(64 * kLG) k_a4(Ctx<T> c) {
+  __shared__ double red[7][kLG][64];
   const GeoDev& g = c.g;
-  int tx, k0, jy;
-  xcd_tile3((int)gridDim.x, 1, (int)gridDim.y, tx, k0, jy);
-  const int j = row_of(c, jy, (int)gridDim.y);
-  int i = tx * blockDim.x + threadIdx.x;
-  if (i >= g.nx) return;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
+  const int i = blockIdx.x * 64 + threadIdx.x, q = threadIdx.y;
+  const bool live = i < g.nx;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int L = (nz + kLG - 1) / kLG, k0 = min(nz, q * L), k1 = min(nz, k0 + L);
+  const T b = (T)g.b;
+  const bool intr = (j >= 1 && j < ny);
+  // the groups' sums of the phi' adjoints, then this group's start
+  C own = 0;
+  if (live)
+    for (int k = k0; k < k1; ++k) own += (C)c.s.APHI[i3<T>(g, j, k, i)];
+  red[0][q][threadIdx.x] = own;
+  __syncthreads();
+  C pre = 0;
+  for (int r = 0; r < q; ++r) pre += red[0][r][threadIdx.x];
+  __syncthreads();
+  C v[7] = {0, 0, 0, 0, 0, 0, 0};   // aP, aPU, aPV, aL, aQ, aDL, aDQ
+  if (live) {
+    const C P = (C)P2(c, j, i);
+    const C bP = (C)b / P, bP2 = (C)b / (P * P);
+    for (int k = k0; k < k1; ++k) {
+      const size_t id = i3<T>(g, j, k, i);
+      const C aphi = (C)c.s.APHI[id];
+      const C art = (C)c.s.ART[id] + g.cl[k] * pre + g.cpk[k] * aphi;
+      pre += aphi;
+      const C afe = (C)c.s.AFE[id] + bP * art;
+      v[0] += (C)c.s.AP3[id] - bP2 * (C)Fe(c, j, k, i) * art;
+      v[3] += (C)c.s.AL3[id];
+      v[4] += (C)c.s.AQ3[id];
+      if (intr) {
+        v[5] += (C)c.s.ADL3[id];
+        v[6] += (C)c.s.ADQ3[id];
+        v[1] += (C)c.s.APU3[id];
+        c.aiF[id] = (T)((C)c.aiF[id] + afe);
+      } else {
+        c.s.AFE[id] = (T)afe;     // pole copies: aggregated later
+      }
+      if (j < ny) v[2] += (C)c.s.APV3[id];
+    }
+  }
+  group_sums<7>(v, red);
+  if (live && q == 0) {
+    const size_t i2 = (size_t)j * nx + i;
+    c.s.AP2[i2] = v[0];
+    c.s.APU2[i2] = v[1];
+    c.s.APV2[i2] = v[2];
+    c.s.AL2[i2] = v[3];
+    c.s.AQ2[i2] = v[4];
+    c.s.ADL2[i2] = v[5];
+    c.s.ADQ2[i2] = v[6];
+  }
+}
+
+// Advection, per column: the divergence and velocity transposes into U and V (the adjoints of u, U,
+// v, V at each point come from the advection transposes) and the column sums of the staggered-P
+// adjoints.
+template <typename T>
+__global__ void __launch_bounds__(64 * kLG) k_l3(Ctx<T> c) {
+  __shared__ double red[2][kLG][64];
+  const GeoDev& g = c.g;
+  const int j = row_of(c, (int)blockIdx.y, (int)gridDim.y);
+  const int i = blockIdx.x * 64 + threadIdx.x, q = threadIdx.y;
+  const bool live = i < g.nx;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int L = (nz + kLG - 1) / kLG, k0 = min(nz, q * L), k1 = min(nz, k0 + L);
   const double* sD = c.s.psum + PS_AD * 2 * (nz + 1);
   const bool intr = (j >= 1 && j < ny);
-  const size_t i2 = (size_t)j * nx + i;
-  // U-point constants (as reciprocals: the level loop only multiplies)
-  int n = 1;
-  C rdxU = 1, PU = 1, rPU = 1;
-  if (intr) {
-    const int M = g.M[j];
-    n = (M + 1) / 2;
-    rdxU = 1.0 / (C)(T)((double)M * g.a * g.s[j] * g.dlam);
-    PU = (C)PUe(c, j, i);
-    rPU = 1.0 / PU;
-  }
-  // V-point constants
-  C PV = 1, rPV = 1, rdyN = 1, rdyS = 1, capD = g.a * g.dlam / g.acap;
-  if (j < ny) {
-    PV = (C)PVe(c, j, i);
-    rPV = 1.0 / PV;
-    if (j >= 1) rdyN = 1.0 / (C)(T)(g.a * g.s[j] * g.dth);
-    if (j + 1 <= ny - 1) rdyS = 1.0 / (C)(T)(g.a * g.s[j + 1] * g.dth);
-  }
-  const C svj = j < ny ? (C)(T)g.sv[j] : 0.0;
-  const int ia = wrp(i - n + 1, nx), ib = wrp(i + n, nx);
-  C aP = c.s.AP2[i2];
-  C aPU = 0, aPV = 0;
-  for (int k = 0; k < nz; ++k) {
-    asm volatile("" : "+v"(i));
-    const unsigned id = i3u(g, j, k, i);
-    A3Out o{};
-    if (intr) { o.au = (C)ldg(c.s.AUU, id); o.aud = (C)ldg(c.s.AUD, id); }
-    if (j < ny) { o.avv = (C)ldg(c.s.AVV, id); o.avd = (C)ldg(c.s.AVD, id); }
+  C v[2] = {0, 0};   // aPU, aPV
+  if (live) {
+    // U-point constants (as reciprocals: the level loop only multiplies)
+    int n = 1;
+    C rdxU = 1, PU = 1, rPU = 1;
     if (intr) {
-      const C aMU = ((C)ldg(c.s.AD, i3u(g, j, k, ia)) - (C)ldg(c.s.AD, i3u(g, j, k, ib))) * rdxU;
-      const C U = (C)ldg(c.U, id);
-      const C bU = c.base_in_tail ? (C)ldg(c.aoU, id) : 0.0;
-      stg(c.aiU, id, (T)((C)ldg((const T*)c.aiU, id) + bU + o.aud + o.au * rPU + PU * aMU));
-      aPU += -U * (rPU * rPU) * o.au + U * aMU;
+      const int M = g.M[j];
+      n = (M + 1) / 2;
+      rdxU = 1.0 / (C)(T)((double)M * g.a * g.s[j] * g.dlam);
+      PU = (C)PUe(c, j, i);
+      rPU = 1.0 / PU;
     }
+    // V-point constants
+    C PV = 1, rPV = 1, rdyN = 1, rdyS = 1, capD = g.a * g.dlam / g.acap;
     if (j < ny) {
-      const int jv = j;
-      const C tN = (jv >= 1) ? (C)ldg(c.s.AD, i3u(g, jv, k, i)) * rdyN : capD * sD[0 * (nz + 1) + k];
-      const C tS = (jv + 1 <= ny - 1) ? (C)ldg(c.s.AD, i3u(g, jv + 1, k, i)) * rdyS : capD * sD[1 * (nz + 1) + k];
-      const C aMV = svj * (tN - tS);
-      const C V = (C)ldg(c.V, id);
-      const C bV = c.base_in_tail ? (C)ldg(c.aoV, id) : 0.0;
-      stg(c.aiV, id, (T)((C)ldg((const T*)c.aiV, id) + bV + o.avd + o.avv * rPV + PV * aMV));
-      aPV += -V * (rPV * rPV) * o.avv + V * aMV;
+      PV = (C)PVe(c, j, i);
+      rPV = 1.0 / PV;
+      if (j >= 1) rdyN = 1.0 / (C)(T)(g.a * g.s[j] * g.dth);
+      if (j + 1 <= ny - 1) rdyS = 1.0 / (C)(T)(g.a * g.s[j + 1] * g.dth);
     }
-    const C afe = (C)ldg(c.s.AFE, id);
-    if (intr) stg(c.aiF, id, (T)((C)ldg((const T*)c.aiF, id) + (c.base_in_tail ? (C)ldg(c.aoF, id) : 0.0) + afe));
-    else stg(c.s.AFE, id, (T)afe);     // pole copies: aggregated later
+    const C svj = j < ny ? (C)(T)g.sv[j] : 0.0;
+    const int ia = wrp(i - n + 1, nx), ib = wrp(i + n, nx);
+    for (int k = k0; k < k1; ++k) {
+      const unsigned id = i3u(g, j, k, i);
+      A3Out o{};
+      if (intr) { o.au = (C)ldg(c.s.AUU, id); o.aud = (C)ldg(c.s.AUD, id); }
+      if (j < ny) { o.avv = (C)ldg(c.s.AVV, id); o.avd = (C)ldg(c.s.AVD, id); }
+      if (intr) {
+        const C aMU = ((C)ldg(c.s.AD, i3u(g, j, k, ia)) - (C)ldg(c.s.AD, i3u(g, j, k, ib))) * rdxU;
+        const C U = (C)ldg(c.U, id);
+        const C bU = c.base_in_tail ? (C)ldg(c.aoU, id) : 0.0;
+        stg(c.aiU, id, (T)((C)ldg((const T*)c.aiU, id) + bU + o.aud + o.au * rPU + PU * aMU));
+        v[0] += -U * (rPU * rPU) * o.au + U * aMU;
+      }
+      if (j < ny) {
+        const int jv = j;
+        const C tN = (jv >= 1) ? (C)ldg(c.s.AD, i3u(g, jv, k, i)) * rdyN : capD * sD[0 * (nz + 1) + k];
+        const C tS = (jv + 1 <= ny - 1) ? (C)ldg(c.s.AD, i3u(g, jv + 1, k, i)) * rdyS : capD * sD[1 * (nz + 1) + k];
+        const C aMV = svj * (tN - tS);
+        const C V = (C)ldg(c.V, id);
+        const C bV = c.base_in_tail ? (C)ldg(c.aoV, id) : 0.0;
+        stg(c.aiV, id, (T)((C)ldg((const T*)c.aiV, id) + bV + o.avd + o.avv * rPV + PV * aMV));
+        v[1] += -V * (rPV * rPV) * o.avv + V * aMV;
+      }
+      if (intr) stg(c.aiF, id, (T)((C)ldg((const T*)c.aiF, id) + (c.base_in_tail ? (C)ldg(c.aoF, id) : 0.0) +
+                                   (C)ldg(c.s.AFE, id)));
+      // (pole rows: the pole-copy adjoints stay in AFE, aggregated later)
+    }
   }
-  c.s.AP2[i2] = aP;
-  c.s.APU2[i2] = aPU;
-  c.s.APV2[i2] = aPV;
-  c.s.AL2[i2] = 0;
-  c.s.AQ2[i2] = 0;
-  c.s.ADL2[i2] = 0;
-  c.s.ADQ2[i2] = 0;
+  group_sums<2>(v, red);
+  if (live && q == 0) {
+    const size_t i2 = (size_t)j * nx + i;
+    c.s.APU2[i2] = v[0];
+    c.s.APV2[i2] = v[1];
+    c.s.AL2[i2] = 0;
+    c.s.AQ2[i2] = 0;
+    c.s.ADL2[i2] = 0;
+    c.s.ADQ2[i2] = 0;
+  }
 }
 
 // 2D: staggered P, the leaped d+ transposes for l and q, then p_s
@@ -1276,6 +1315,7 @@ __global__ void __launch_bounds__(256) k_adt(Ctx<T> c) {
   };
   AdtLev<T> cur{}, nxt{};
   if (act) load_lev(0, cur);
+  const bool bsep = c.abU != nullptr && !c.base_in_tail;   // a separate base accumulator
   A pF = 0, pU = 0, pV = 0;        // owned column: -ch a_out of Phi, U, V (row j) at level k-1
   T sdk = 0, sdkp = 0, sd1k = 0;   // sigma-dot at half level k: this column, its east neighbour, row j+1
   C aPU = 0, aPV = 0;
@@ -1287,7 +1327,7 @@ __global__ void __launch_bounds__(256) k_adt(Ctx<T> c) {
     // owned column: the meridional neighbours, sigma-dot at half level k+1, the accumulators
     T aFm = 0, aUm = 0, aFp = 0, Fp = 0, aUp = 0, aUpw = 0, Up = 0, Upw = 0, aVp = 0, Vp = 0;
     T ADp = 0, sdn = 0, sdnp = 0, sd1n = 0;
-    T aiU0 = 0, aiV0 = 0, aiF0 = 0;
+    T aiU0 = 0, aiV0 = 0, aiF0 = 0, abU0 = 0, abV0 = 0, abF0 = 0;
     if (own) {
       const unsigned o = oJ + lv + ui, ow = oJ + lv + uim, op = oJ + lv + uip;
       if (nIn) {
@@ -1316,6 +1356,11 @@ __global__ void __launch_bounds__(256) k_adt(Ctx<T> c) {
         aiU0 = ldg(c.aiU, o);
         aiV0 = ldg(c.aiV, o);
         aiF0 = ldg(c.aiF, o);
+      }
+      if (bsep) {
+        abU0 = ldg((const T*)c.abU, o);
+        abV0 = ldg((const T*)c.abV, o);
+        abF0 = ldg((const T*)c.abF, o);
       }
     }
     if (act) {
@@ -1417,6 +1462,15 @@ __global__ void __launch_bounds__(256) k_adt(Ctx<T> c) {
       stg(c.aiV, o, (T)((C)aiV0 + (bt ? (C)cur.aV : 0.0) + (C)aVd + (C)aVV * rPV + PV * aMV));
       aPV += -Vc * (rPV * rPV) * (C)aVV + Vc * aMV;
       stg(c.aiF, o, (T)((C)aiF0 + (bt ? (C)cur.aF : 0.0) + (C)aFE));
+      if (bsep) {   // the base transpose (identity) into a separate accumulator
+        stg(c.abU, o, abU0 + cur.aU);
+        stg(c.abV, o, abV0 + cur.aV);
+        stg(c.abF, o, abF0 + cur.aF);
+        if (k == 0) {
+          const unsigned o2 = (unsigned)j * (unsigned)nx + ui;
+          stg(c.abP, o2, ldg((const T*)c.abP, o2) + ldg(c.aoP, o2));
+        }
+      }
       pF = aF0;
       pU = aU0;
       pV = aV0;
@@ -1890,9 +1944,18 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, s, c);
   if (c.abU && !c.base_in_tail) {
-    // interior rows' base transpose is folded into the row-fused kernel (adaptation) or the column
-    // tail (advection with one accumulator); V row 1/2 stays here for the row-fused case
-    hipLaunchKernelGGL((k_base<T>), rows ? dim3(gx, nz, 1) : g3, dim3(tb), 0, s, c);
+    // interior rows' base transpose is folded into the row-fused kernels (the adaptation's and the
+    // advection's, for their rows) or the column tail (advection with one accumulator); V row 1/2
+    // stays here for the row-fused adaptation, the per-point rows for the row-fused advection
+    if (rows) {
+      hipLaunchKernelGGL((k_base<T>), dim3(gx, nz, 1), dim3(tb), 0, s, c);
+    } else if (!adapt && adt_used(c)) {
+      Ctx<T> cw = c;
+      cw.rsplit = c.pp_n + 1;
+      hipLaunchKernelGGL((k_base<T>), dim3(gx, nz, c.pp_n + c.pp_s + 2), dim3(tb), 0, s, cw);
+    } else {
+      hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
+    }
   }
   hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
                      c.s.psum + PS_AOF * 2 * (nz + 1));
@@ -1907,6 +1970,7 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
+  const int gx64 = (nx + 63) / 64;   // column kernels: 64 columns x kLG level groups
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
   if (aar_used(c)) {
     // pole rows through the per-point kernels, interior rows row-fused
@@ -1924,13 +1988,13 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     hipLaunchKernelGGL((k_a1lev<T>), dim3(gx, nz, 1), dim3(tb), 0, s, cv);
     cp.parts = 7;
     hipLaunchKernelGGL((k_a3t1<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
-    hipLaunchKernelGGL((k_a4<T>), dim3(gx, 2), dim3(tb), 0, s, cp);
+    hipLaunchKernelGGL((k_a4<T>), dim3(gx64, 2), dim3(64, kLG), 0, s, cp);
   } else {
     hipLaunchKernelGGL((k_a12<T, 1, 0>), g2, dim3(tb), 0, s, c);
     hipLaunchKernelGGL((k_pole_sum2<T>), dim3(4 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
                        c.s.psum + PS_AD * 2 * (nz + 1), (const T*)c.s.AVGL, c.s.psum + PS_AVGL * 2 * (nz + 1));
     hipLaunchKernelGGL((k_a3t1<T>), g3, dim3(tb), 0, s, c);
-    hipLaunchKernelGGL((k_a4<T>), g2, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_a4<T>), dim3(gx64, ny + 1), dim3(64, kLG), 0, s, c);
   }
   hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
   if (g.kstar != 0.0) hipLaunchKernelGGL((k_dsa_adj<T>), g2, dim3(tb), 0, s, c);
@@ -1944,6 +2008,7 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int tb = 256;
   const int gx = (nx + tb - 1) / tb;
+  const int gx64 = (nx + 63) / 64;   // column kernels: 64 columns x kLG level groups
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
   // u and v sin(theta) of rows 1..ny-1 come from the forward recompute (k_f1); here the pole rows
   Ctx<T> cp = c;
@@ -1963,13 +2028,13 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
                        (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
     const hipError_t e = launch_adt<T>(c, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_l3<T>), dim3(gx, nw), dim3(tb), 0, s, cw);
+    hipLaunchKernelGGL((k_l3<T>), dim3(gx64, nw), dim3(64, kLG), 0, s, cw);
   } else {
     hipLaunchKernelGGL((k_l1<T>), g3, dim3(tb), 0, s, c);
     hipLaunchKernelGGL((k_l2<T>), g2, dim3(tb), 0, s, c);
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
                        (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
-    hipLaunchKernelGGL((k_l3<T>), g2, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_l3<T>), dim3(gx64, ny + 1), dim3(64, kLG), 0, s, c);
   }
   hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
   hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
@@ -1993,7 +2058,7 @@ constexpr int kN2D = 8;   // 2D FP64 fields
 
 struct Layout {
   size_t n3, nh, n2, state;
-  size_t traj_off, lam_off, f3_off, fh_off, f2t_off, f2d_off, psum_off, pole_off, total;
+  size_t traj_off, lam_off, f3_off, fh_off, f2t_off, f2d_off, psum_off, pole_off, tpole_off, total;
 };
 
 Layout layout(const HandleView& v) {
@@ -2013,6 +2078,7 @@ Layout layout(const HandleView& v) {
   L.f2d_off = o; o += kN2D * a256(L.n2 * 8);
   L.psum_off = o; o += a256(8 * 2 * (g.nz + 1) * 8);
   L.pole_off = o; o += a256(4 * 2 * (g.nz + 1) * 8);
+  L.tpole_off = o; o += a256((size_t)(nst + 1) * 2 * (g.nz + 1) * 8);   // pole values of each traj state
   L.total = o;
   return L;
 }
@@ -2058,9 +2124,11 @@ St4<T> state_at(const HandleView& v, void* base) {
   return s;
 }
 
+// pin: pole values of y, formed here from y's pole rows unless pin_ready (the recorded forward's)
 template <typename T>
 hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<const T> y, St4<const T> ao,
-                              St4<T> ab, St4<T> ai, double* pin, hipStream_t s, bool ai_zero = false) {
+                              St4<T> ab, St4<T> ai, double* pin, hipStream_t s, bool ai_zero = false,
+                              bool pin_ready = false) {
   Ctx<T> c;
   c.g = v.g;
   c.U = y.U; c.V = y.V; c.F = y.F; c.P = y.P;
@@ -2083,7 +2151,7 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.pp_s = v.adt_pp_s;
   c.ai_zero = ai_zero && ab.U != ai.U;
   c.base_in_tail = process == 1 && ab.U && ab.U == ai.U && ab.V == ai.V && ab.F == ai.F && ab.P == ai.P;
-  hipError_t e = launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
+  hipError_t e = pin_ready ? hipSuccess : launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
   if (e != hipSuccess) return e;
   e = run_stage_adjoint<T>(c, s, process == 0);
   if (e != hipSuccess) return e;
@@ -2158,20 +2226,23 @@ template <typename T>
 St4<const T> cst(St4<T> a) { return St4<const T>{a.U, a.V, a.F, a.P}; }
 
 // Forward pass of one outer step that keeps every stage input in the workspace: traj[3 rk] = y_rk,
-// traj[3 rk + 1] = y1, traj[3 rk + 2] = y2.  With `out` set, the last stage of the last RK step is
-// run too and writes the step's result there (out may be y0's buffers: y0 is copied first).
+// traj[3 rk + 1] = y1, traj[3 rk + 2] = y2, with their pole values (tpole[q]: those of y0 from its
+// pole rows, the others as the stage that wrote the state formed them), which the reverse sweep
+// linearises about.  With `out` set, the last stage of the last RK step is run too and writes the
+// step's result there (out may be y0's buffers: y0 is copied first).
 template <typename T>
 int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s) {
   const Layout L = layout(v);
   char* base = static_cast<char*>(v.adj);
   const int nrk = v.msub + 1;
   auto traj = [&](int q) { return state_at<T>(v, base + L.traj_off + (size_t)q * L.state); };
-  double* pole = reinterpret_cast<double*>(base + L.pole_off);   // [4][2][nz+1]
   const size_t ps = 2 * (v.g.nz + 1);
+  double* tp = reinterpret_cast<double*>(base + L.tpole_off);   // [3 nrk + 1][2][nz+1]
+  auto tpole = [&](int q) { return tp + (size_t)q * ps; };
   hipError_t e;
   e = copy_state<T>(v, traj(0), y0, s);
   if (e != hipSuccess) return DYCORE_EHIP;
-  e = launch_pole_prep<T>(v.g, traj(0).F, traj(0).P, pole, s);
+  e = launch_pole_prep<T>(v.g, traj(0).F, traj(0).P, tpole(0), s);
   if (e != hipSuccess) return DYCORE_EHIP;
   for (int rk = 0; rk < nrk; ++rk) {
     const int proc = rk < v.msub ? 0 : 1;
@@ -2183,7 +2254,7 @@ int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s)
       a.inU = in.U; a.inV = in.V; a.inF = in.F; a.inP = in.P;
       a.bU = y.U; a.bV = y.V; a.bF = y.F; a.bP = y.P;
       a.oU = out.U; a.oV = out.V; a.oF = out.F; a.oP = out.P;
-      a.pin = pin; a.pbase = pole; a.pout = pout;
+      a.pin = pin; a.pbase = tpole(3 * rk); a.pout = pout;
       a.ch = chh;
       a.process = proc;
       a.pad = 0;
@@ -2196,14 +2267,14 @@ int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s)
       a.ablock = v.ablock;
       return a;
     };
-    e = launch_stage<T>(mk(h / 3.0, y, y1, pole, pole + ps), s);
-    if (e == hipSuccess) e = launch_stage<T>(mk(h / 2.0, y1, y2, pole + ps, pole + 2 * ps), s);
+    const int q = 3 * rk;
+    e = launch_stage<T>(mk(h / 3.0, y, y1, tpole(q), tpole(q + 1)), s);
+    if (e == hipSuccess) e = launch_stage<T>(mk(h / 2.0, y1, y2, tpole(q + 1), tpole(q + 2)), s);
     if (e == hipSuccess && rk + 1 < nrk) {
-      St4<T> yn = traj(3 * (rk + 1));
-      e = launch_stage<T>(mk(h, y2, yn, pole + 2 * ps, pole + 3 * ps), s);
-      if (e == hipSuccess) e = launch_axpy_fill<double>(pole, pole + 3 * ps, ps, s);
+      e = launch_stage<T>(mk(h, y2, traj(q + 3), tpole(q + 2), tpole(q + 3)), s);
     } else if (e == hipSuccess && out.U) {
-      e = launch_stage<T>(mk(h, y2, out, pole + 2 * ps, pole + 3 * ps), s);
+      // (the step result's pole values go to the spare last slot)
+      e = launch_stage<T>(mk(h, y2, out, tpole(q + 2), tpole(q + 3)), s);
       // the low-latitude filters close the step, as in dycore_step
       if (e == hipSuccess) e = launch_lowlat<T>(v.g, v.filt, v.nfilt, out.U, out.V, out.F, out.P, s);
     }
@@ -2221,8 +2292,9 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
   auto traj = [&](int q) { return state_at<T>(v, base + L.traj_off + (size_t)q * L.state); };
   St4<T> l1 = state_at<T>(v, base + L.lam_off);
   St4<T> l2 = state_at<T>(v, base + L.lam_off + L.state);
-  double* pole = reinterpret_cast<double*>(base + L.pole_off);
   const size_t ps = 2 * (v.g.nz + 1);
+  double* tp = reinterpret_cast<double*>(base + L.tpole_off);   // the recorded stage inputs' pole values
+  auto tpole = [&](int q) { return tp + (size_t)q * ps; };
   // the low-latitude filters act last in the step and each row operator is symmetric, so the sweep
   // starts with the same filters applied to lam
   hipError_t e = launch_lowlat<T>(v.g, v.filt, v.nfilt, lam.U, lam.V, lam.F, lam.P, s);
@@ -2230,7 +2302,6 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
   // reverse sweep.  lam accumulates the adjoint of the RK step's input: every stage adds the base
   // transpose of its output adjoint to it; the last stage's share is lam itself with the base
   // transpose applied in place once that stage has read it.
-  double* pin = pole + 3 * ps;
   const St4<T> none{nullptr, nullptr, nullptr, nullptr};
   for (int rk = nrk - 1; rk >= 0; --rk) {
     const int proc = rk < v.msub ? 0 : 1;
@@ -2242,13 +2313,15 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
     const int pn = proc == 0 ? 0 : v.adt_pp_n, psn = proc == 0 ? 0 : v.adt_pp_s;
     e = fused ? zero_outside_rows<T>(v, l1, s, pn, psn) : zero_state<T>(v, l1, s);
     if (e == hipSuccess) e = fused ? zero_outside_rows<T>(v, l2, s, pn, psn) : zero_state<T>(v, l2, s);
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, pin, s, true);
+    const int q = 3 * rk;
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, tpole(q + 2), s, true, true);
     if (e == hipSuccess) {
       hipLaunchKernelGGL((k_base_inplace<T>), dim3(v.g.nz + 1, 2), dim3(256), 0, s, v.g, lam.U, lam.F, lam.P);
       e = hipGetLastError();
     }
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lam, l1, pin, s, true);
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lam, lam, pin, s);
+    if (e == hipSuccess)
+      e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lam, l1, tpole(q + 1), s, true, true);
+    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lam, lam, tpole(q), s, false, true);
     if (e != hipSuccess) return DYCORE_EHIP;
   }
   return DYCORE_OK;
