@@ -62,11 +62,6 @@ def time_gpu(fn, reps):
     return e0.elapsed_time(e1) / 1e3
 
 
-def adapt_pipelined(nx):
-    """The FP32 adaptation stage runs in its pipelined form when its 27 LDS rows fit in 160 KB."""
-    return ((27 * nx * 4 + 15) // 16) * 16 + 2 * 128 * 8 <= 160 * 1024
-
-
 def run_prec(cfg, st, prec, steps, warmup, adjoint, seed_lam=7):
     import torch
     from paper_2103_10114_amd import Dycore, synth
@@ -99,8 +94,9 @@ def run_prec(cfg, st, prec, steps, warmup, adjoint, seed_lam=7):
 
 
 def roofline(core, d, cfg, elem, reps=10):
-    """Average launch duration of the adaptation and advection stage kernels, timed with HIP
-    events on the launch stream over reps RK3 steps of each process alone."""
+    """Average duration of an adaptation and of an advection stage (the tile kernel and its pole
+    cap-sum pre-kernel), timed with HIP events on the launch stream over reps RK3 steps of each
+    process alone."""
     ms = {}
     for proc in ("A", "L"):
         h = cfg.dt / core.substeps if proc == "A" else cfg.dt
@@ -131,13 +127,25 @@ def traffic_from_profiles(kernel_hash, key):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(msub):
     """The FP64 oracle as it stands, on the host, on a bounded sample of the 0.25-degree workload:
     one adaptation stage and one advection stage, each forward and adjoint, on the full
-    1440x720x30 grid with all OpenMP threads.  The rate of a whole bench step (one forward outer
-    step + one adjoint outer step, whose forward recompute repeats the forward stages) is scaled
-    from these four timings: 2 (3M t_A + 3 t_L) + 3M t_A' + 3 t_L'.  Also: one forward outer step
-    of the 128x64x9 grid at 1 thread and at all threads."""
+    1440x720x30 grid with all OpenMP threads (the forward stages run their rows in parallel, the
+    adjoint sweep is serial).  The rate of a whole bench step (one forward outer step + one adjoint
+    outer step, whose forward recompute repeats the forward stages) is scaled from these four
+    timings: 2 (3M t_A + 3 t_L) + 3M t_A' + 3 t_L'.  Also: the adaptation stage forward at 1 thread
+    on the same grid, and one forward outer step of the 128x64x9 grid at 1 thread and at all
+    threads."""
     import oracle
     from paper_2103_10114_amd import synth
     cfg = synth.CONFIGS["c4"]
@@ -154,6 +162,11 @@ def cpu_baseline(msub):
         o.adj_stage(st, lam, ch, which)
         t2 = time.perf_counter()
         t[which] = (t1 - t0, t2 - t1)
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    o.stage(st, st, h, "A")
+    t_a1 = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
     del o, st, lam
     fwd = 3 * msub * t["A"][0] + 3 * t["L"][0]
     step = 2 * fwd + 3 * msub * t["A"][1] + 3 * t["L"][1]
@@ -175,21 +188,23 @@ def cpu_baseline(msub):
                        f"{t['L'][1]:.2f} s ({threads} OpenMP threads over rows for the forward; the "
                        f"adjoint sweep is serial); scaled to one forward + one adjoint outer step "
                        f"(M {msub}: {3 * msub} + 3 stages each way, forward stages twice)"),
-            "forward_updates_per_s": pts / fwd,
+            "forward_updates_per_s": pts / fwd, "adjoint_sweep": "serial", "cpu_model": cpu_model(),
+            "c4_adaptation_stage_s": {"threads_1": t_a1, f"threads_{threads}": t["A"][0]},
             "c1_forward_updates_per_s": {"threads_1": rates[1], f"threads_{threads}": rates[threads]}}
 
 
 def ensemble_c5(steps):
     """The 24-member mixed ensemble (8 each of 128x64x9, 256x128x30, 720x360x30): one persistent
     launch per stage at the autotuned workgroup size, the batched step captured once in a hipGraph
-    and replayed."""
+    and replayed; then the one-step adjoint of every member (dycore_step_adjoint, member after
+    member, from its state after the replays, with a seeded output adjoint)."""
     import torch
     from paper_2103_10114_amd import Batch, Dycore, synth
     cfgs = [synth.ensemble_member(m) for m in range(24)]
     cores, states = [], []
     for cfg in cfgs:
         st = synth.make_state(cfg)
-        c = Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec="fp32", phis=st["phis"], forward_only=True)
+        c = Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec="fp32", phis=st["phis"])
         cores.append(c)
         states.append(c.to_device(st))
     b, table = Batch.autotune(cores, states)
@@ -208,9 +223,21 @@ def ensemble_c5(steps):
     el = time.perf_counter() - t0
     pts = sum(c.nx * c.ny * c.nz for c in cfgs)
     bad = sum(core.count_nonfinite(st) for core, st in zip(cores, states))
+    lams = [core.to_device(synth.random_like(st, 900 + m)) for m, (core, st) in enumerate(zip(cores, states))]
+    for core, st, lam in zip(cores, states, lams):     # warm
+        core.step_adjoint(st, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for core, st, lam in zip(cores, states, lams):
+        core.step_adjoint(st, lam)
+    torch.cuda.synchronize()
+    ela = time.perf_counter() - t0
+    bad_adj = sum(core.count_nonfinite(lam) for core, lam in zip(cores, lams))
     return {"value": pts * steps / el, "unit": "grid-pt updates/s", "members": len(cfgs), "points_per_step": pts,
             "steps": steps, "ms_per_step": el / steps * 1e3, "graph_replay": True, "nonfinite_after": bad,
-            "block": min(table, key=table.get), "autotune_ms_per_step": {str(k): v for k, v in table.items()}}
+            "block": min(table, key=table.get), "autotune_ms_per_step": {str(k): v for k, v in table.items()},
+            "adjoint_one_step": {"ms_all_members": ela * 1e3, "updates_per_s": pts / ela,
+                                 "nonfinite_after": bad_adj}}
 
 
 def window_adjoint(core, d, lam, nsteps, ckpt):
@@ -314,13 +341,21 @@ def main():
         print("[bench] roofline timing", file=sys.stderr, flush=True)
         kh = kernel_source_hash()
         sb = state_bytes(cfg.nx, cfg.ny, cfg.nz, 4)
-        ni = -(-cfg.nx // core.block)
         ms, alg, ach = roofline(core, d, cfg, 4)
-        stage_name = f"k_stage<float,{ni},{2 if adapt_pipelined(cfg.nx) else 0}>"
+        stage_name = "k_stage_tile<float>"
         fwd = {"kernel": stage_name + " (adaptation stage)", "avg_launch_ms": ms["A"],
                "alg_bytes_per_launch": alg, "achieved": ach, "frac": ach / HBM_PEAK_GBS,
                "traffic": traffic_from_profiles(kh, stage_name),
-               "advection_launch_ms": ms["L"]}
+               "advection": {"kernel": "k_stage_atile<float>", "avg_launch_ms": ms["L"],
+                             "achieved": alg / (ms["L"] * 1e-3) / 1e9,
+                             "frac": alg / (ms["L"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "traffic": traffic_from_profiles(kh, "k_stage_atile<float>")}}
+        # the whole bench step: every forward stage moves 8/3 states, every stage adjoint 4
+        nst = 3 * (msub + 1) if adjoint else 0
+        step_states = 3 * (msub + 1) * 8.0 / 3.0 + 4.0 * nst
+        step_ach = step_states * sb / (el / args.steps) / 1e9
+        out["whole_step"] = {"alg_states": step_states, "alg_bytes": step_states * sb, "achieved": step_ach,
+                             "unit": "GB/s", "frac": step_ach / HBM_PEAK_GBS}
         tot, n = core.kernel_timing
         if n > 0:
             # the dominant kernel of the bench step: over the three stages of an RK step the

@@ -1818,13 +1818,14 @@ __global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat(Ct
       // divergence and velocity transposes
       const A aMU = ((A)SL(LAD, sl - n + 1) - (A)SL(LAD, sl + n)) * rdxA;
       const A PUc = (A)PU0, Uc = (A)vUj;
-      stg(c.aiU, oj, (T)((C)aiU0 + (C)(aUd + au * rPUc + PUc * aMU)));
+      // (an FP32 sum rounded once equals the FP64 sum rounded to FP32: 53 >= 2 * 24 + 2 bits)
+      stg(c.aiU, oj, (T)(aiU0 + (aUd + au * rPUc + PUc * aMU)));
       const A aPU3 = -Uc * (rPUc * rPUc) * au + Uc * aMU;
       const A tN = vADj * rdySjA;
       const A tS = sPole ? (A)(capD * sDs[1 * (nz + 1) + k]) : (A)vAD1 * rdyS1A;
       const A aMV = (A)svj * (tN - tS);
       const A PVc = (A)PV0, Vc = (A)vVj, rPVc = (A)rPV0;
-      stg(c.aiV, oj, (T)((C)aiV0 + (C)(avd + avv * rPVc + PVc * aMV)));
+      stg(c.aiV, oj, (T)(aiV0 + (avd + avv * rPVc + PVc * aMV)));
       const A aPV3 = -Vc * (rPVc * rPVc) * avv + Vc * aMV;
       // hydrostatic transpose and column sums
       const A art = aRT + (A)(clk * pre) + (A)cpk * aPHI;
@@ -1835,7 +1836,7 @@ __global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat(Ct
       aDLQ += (C)(adl + adq);
       aPU += (C)(APU3 + aPU3);
       aPV += (C)(APV3 + aPV3);
-      stg(c.aiF, oj, (T)((C)aiF0 + (C)afe));
+      stg(c.aiF, oj, (T)(aiF0 + afe));
     }
     (void)dsgA;
     // no second barrier: the next level's phase 1 writes the other buffer, and the level after that
