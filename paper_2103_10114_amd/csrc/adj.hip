@@ -2266,16 +2266,20 @@ int record_impl(const HandleView& v, St4<const T> y0, St4<T> out, hipStream_t s)
       a.atiles = v.atiles;
       a.natiles = v.natiles;
       a.ablock = v.ablock;
+      a.awide = v.awide;
+      a.ptiles = v.ptiles;
+      a.nptiles = v.nptiles;
+      a.pblock = v.pblock;
       return a;
     };
     const int q = 3 * rk;
-    e = launch_stage<T>(mk(h / 3.0, y, y1, tpole(q), tpole(q + 1)), s);
-    if (e == hipSuccess) e = launch_stage<T>(mk(h / 2.0, y1, y2, tpole(q + 1), tpole(q + 2)), s);
+    e = launch_stage<T>(mk(h / 3.0, y, y1, tpole(q), tpole(q + 1)), s, v.side);
+    if (e == hipSuccess) e = launch_stage<T>(mk(h / 2.0, y1, y2, tpole(q + 1), tpole(q + 2)), s, v.side);
     if (e == hipSuccess && rk + 1 < nrk) {
-      e = launch_stage<T>(mk(h, y2, traj(q + 3), tpole(q + 2), tpole(q + 3)), s);
+      e = launch_stage<T>(mk(h, y2, traj(q + 3), tpole(q + 2), tpole(q + 3)), s, v.side);
     } else if (e == hipSuccess && out.U) {
       // (the step result's pole values go to the spare last slot)
-      e = launch_stage<T>(mk(h, y2, out, tpole(q + 2), tpole(q + 3)), s);
+      e = launch_stage<T>(mk(h, y2, out, tpole(q + 2), tpole(q + 3)), s, v.side);
       // the low-latitude filters close the step, as in dycore_step
       if (e == hipSuccess) e = launch_lowlat<T>(v.g, v.filt, v.nfilt, out.U, out.V, out.F, out.P, s);
     }

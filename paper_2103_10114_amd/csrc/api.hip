@@ -80,8 +80,10 @@ struct dycore_s {
   int nfilt = 0;
   AatItem* ftiles = nullptr;    // zonal tiles of the forward adaptation stage (device), rows 0..ny
   int nftiles = 0, ftblock = 0;
-  AatItem* atiles = nullptr;    // zonal tiles of the forward advection stage (device), rows 0..ny
-  int natiles = 0;              // (workgroups of `block` threads)
+  AatItem* atiles = nullptr;    // zonal tiles of the forward advection stage (device): the main
+  int natiles = 0, awide = 0;   // launch's (workgroups of `block` threads; awide: it has wide tiles),
+  int nptiles = 0, pblock = 0;  // then the polar launch's (wide tiles) at atiles + natiles
+  dyc::SideLaunch side{nullptr, nullptr, nullptr};   // the polar launch's stream and events
   double* cap = nullptr;        // cap sums of the forward adaptation stage: [2 poles][2][nz]
   size_t bytes = 0;
 };
@@ -267,6 +269,43 @@ bool adt_items(int nx, int ny, const std::vector<int>& M, const std::vector<int>
   return best_tiles(nx, rows, hl, 256, out, block);
 }
 
+// Work items of the tiled advection stage of one member, for a main launch and a polar launch, both
+// of `block` threads: a row takes band tiles in the main launch when its halo (as below) leaves 32
+// owned columns, else wide tiles (halo 1, leap operands from global memory) in the polar launch,
+// which runs beside the main one.  Both lists are XCD-spread as zonal_tiles.
+void advect_tiles_split(int nx, int ny, const std::vector<int>& M, const std::vector<int>& Mv, int block,
+                        std::vector<AatItem>& main, std::vector<AatItem>& polar) {
+  std::vector<AatItem> wide, band, pol;
+  auto cut = [&](int j, int hl, int cap, int hmark, std::vector<AatItem>& to) {
+    const int nt = (nx + cap - 1) / cap;
+    const int w = (nx + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+      const int i0 = t * w;
+      if (i0 >= nx) break;
+      to.push_back(AatItem{j, i0, std::min(w, nx - i0), hmark});
+    }
+    (void)hl;
+  };
+  for (int j = 0; j <= ny; ++j) {
+    const int hl = std::max((j == 0 || j == ny) ? 1 : M[j], j < ny ? Mv[j] : 1);
+    if (block - 2 * hl >= 32) cut(j, hl, block - 2 * hl, hl, band);
+    else cut(j, hl, block - 2, -1, pol);
+  }
+  auto spread = [](const std::vector<AatItem>& seq, std::vector<AatItem>& out) {
+    const int n = (int)seq.size(), per = (n + 7) / 8;
+    out.assign((size_t)per * 8, AatItem{-1, 0, 0, 0});
+    for (int x = 0; x < 8; ++x)
+      for (int q = 0; q < per; ++q) {
+        const int src = x * per + q;
+        if (src < n) out[(size_t)q * 8 + x] = seq[src];
+      }
+  };
+  (void)wide;
+  spread(band, main);
+  polar.clear();
+  if (!pol.empty()) spread(pol, polar);
+}
+
 // Work items of the tiled advection stage for a block of `block` threads (rows 0..ny).  A row's halo
 // is the reach of its leaped centred differences, max(M_j, Mv_j, 1) (the pole rows have no zonal
 // Phi and U terms); rows whose halo leaves 32 owned columns take band tiles, the others wide tiles
@@ -298,6 +337,9 @@ void advect_tiles(int nx, int ny, const std::vector<int>& M, const std::vector<i
     }
 }
 
+// The polar advection tiles' stream of a handle (NULL when it has none).
+const dyc::SideLaunch* side_of(const dycore_s* h) { return h->side.s ? &h->side : nullptr; }
+
 template <typename T>
 StageArgs<T> make_args(const dycore_s* h, int process, double ch, const T* inU, const T* inV, const T* inF,
                        const T* inP, const T* bU, const T* bV, const T* bF, const T* bP, T* oU, T* oV, T* oF,
@@ -318,6 +360,10 @@ StageArgs<T> make_args(const dycore_s* h, int process, double ch, const T* inU, 
   a.atiles = h->atiles;
   a.natiles = h->natiles;
   a.ablock = h->block;
+  a.awide = h->awide;
+  a.ptiles = h->nptiles > 0 ? h->atiles + h->natiles : nullptr;
+  a.nptiles = h->nptiles;
+  a.pblock = h->pblock;
   return a;
 }
 
@@ -368,7 +414,7 @@ int step_impl(dycore_s* h, T* U, T* V, T* F, T* P, int nsteps, hipStream_t s) {
   for (int n = 0; n < nsteps; ++n) {
     for (int rk = 0; rk < nrk; ++rk)
       for (int r = 0; r < 3; ++r) {
-        e = launch_stage<T>(step_stage_args<T>(h, rk, r, U, V, F, P), s);
+        e = launch_stage<T>(step_stage_args<T>(h, rk, r, U, V, F, P), s, side_of(h));
         if (e != hipSuccess) return DYCORE_EHIP;
       }
     // the low-latitude filters close the step (they leave the pole rows and their slot alone)
@@ -391,13 +437,13 @@ int process_run_impl(dycore_s* h, int process, int n_rk, double hstep, T* U, T* 
   for (int n = 0; n < n_rk; ++n) {
     const int nb = (b == 0) ? 3 : 0;
     e = launch_stage<T>(make_args<T>(h, process, hstep / 3.0, U, V, F, P, U, V, F, P, y1.U, y1.V, y1.F, y1.P,
-                                     pole_slot(h, b), pole_slot(h, b), pole_slot(h, 1)), s);
+                                     pole_slot(h, b), pole_slot(h, b), pole_slot(h, 1)), s, side_of(h));
     if (e == hipSuccess)
       e = launch_stage<T>(make_args<T>(h, process, hstep / 2.0, y1.U, y1.V, y1.F, y1.P, U, V, F, P, y2.U, y2.V,
-                                       y2.F, y2.P, pole_slot(h, 1), pole_slot(h, b), pole_slot(h, 2)), s);
+                                       y2.F, y2.P, pole_slot(h, 1), pole_slot(h, b), pole_slot(h, 2)), s, side_of(h));
     if (e == hipSuccess)
       e = launch_stage<T>(make_args<T>(h, process, hstep, y2.U, y2.V, y2.F, y2.P, U, V, F, P, U, V, F, P,
-                                       pole_slot(h, 2), pole_slot(h, b), pole_slot(h, nb)), s);
+                                       pole_slot(h, 2), pole_slot(h, b), pole_slot(h, nb)), s, side_of(h));
     if (e != hipSuccess) return DYCORE_EHIP;
     b = nb;
   }
@@ -411,7 +457,7 @@ int stage_impl(dycore_s* h, int process, double ch, const T* bU, const T* bV, co
   if (e == hipSuccess) e = launch_pole_prep<T>(h->g, bF, bP, pole_slot(h, 1), s);
   if (e == hipSuccess)
     e = launch_stage<T>(make_args<T>(h, process, ch, U, V, F, P, bU, bV, bF, bP, oU, oV, oF, oP, pole_slot(h, 0),
-                                     pole_slot(h, 1), pole_slot(h, 2)), s);
+                                     pole_slot(h, 1), pole_slot(h, 2)), s, side_of(h));
   return hip_status(e);
 }
 
@@ -494,6 +540,11 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.atiles = h->atiles;
   v.natiles = h->natiles;
   v.ablock = h->block;
+  v.awide = h->awide;
+  v.ptiles = h->nptiles > 0 ? h->atiles + h->natiles : nullptr;
+  v.nptiles = h->nptiles;
+  v.pblock = h->pblock;
+  v.side = h->side.s ? &h->side : nullptr;
   v.cap = h->cap;
   return v;
 }
@@ -655,13 +706,27 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       h->ftblock = fblk;
       h->bytes += sizeof(AatItem) * ft.size() + sizeof(double) * 4 * nz;
     }
-    std::vector<AatItem> at;
-    advect_tiles(nx, ny, h->M, h->Mv, h->block, at);
-    ok = ok && hipMalloc((void**)&h->atiles, sizeof(AatItem) * at.size()) == hipSuccess;
+    std::vector<AatItem> at, pt;
+    const int pblock = h->block;
+    advect_tiles_split(nx, ny, h->M, h->Mv, h->block, at, pt);
+    h->awide = 0;
+    const size_t nall = at.size() + pt.size();
+    ok = ok && hipMalloc((void**)&h->atiles, sizeof(AatItem) * nall) == hipSuccess;
     ok = ok && hipMemcpy(h->atiles, at.data(), sizeof(AatItem) * at.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && !pt.empty())
+      ok = hipMemcpy(h->atiles + at.size(), pt.data(), sizeof(AatItem) * pt.size(), hipMemcpyHostToDevice) ==
+           hipSuccess;
     if (ok) {
       h->natiles = (int)at.size();
-      h->bytes += sizeof(AatItem) * at.size();
+      h->nptiles = (int)pt.size();
+      h->pblock = pblock;
+      h->bytes += sizeof(AatItem) * nall;
+    }
+    // the polar tiles run beside the main launch on a stream of their own (default priority)
+    if (ok && h->nptiles > 0) {
+      ok = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming) == hipSuccess;
     }
   }
   if (ok && !(h->flags & DYCORE_FORWARD_ONLY)) {
@@ -763,6 +828,9 @@ int dycore_destroy(dycore_t h) {
   if (h->filt) (void)hipFree(h->filt);
   if (h->ftiles) (void)hipFree(h->ftiles);
   if (h->atiles) (void)hipFree(h->atiles);
+  if (h->side.fork) (void)hipEventDestroy(h->side.fork);
+  if (h->side.join) (void)hipEventDestroy(h->side.join);
+  if (h->side.s) (void)hipStreamDestroy(h->side.s);
   if (h->cap) (void)hipFree(h->cap);
   release_timer(h);
   delete h;
@@ -945,6 +1013,9 @@ int batch_build(dycore_batch_s* b) {
       a.atiles = b->d_tiles + aoff[m];
       a.natiles = acount[m];
       a.ablock = b->block;
+      a.awide = 1;
+      a.ptiles = nullptr;
+      a.nptiles = 0;
     }
   }
   if (hipMalloc(&b->d_args, sizeof(StageArgs<T>) * args.size()) != hipSuccess) return DYCORE_ENOMEM;

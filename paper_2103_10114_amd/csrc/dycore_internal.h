@@ -83,6 +83,17 @@ struct StageArgs {
   const AatItem* atiles; // zonal tiles of the advection stage (rows 0..ny; hl < 0: wide form)
   int natiles;          // their count (a multiple of 8)
   int ablock;           // threads per advection tile workgroup
+  int awide;            // 1 if atiles holds wide-form items
+  const AatItem* ptiles; // single-member launches: wide tiles of the rows whose halos do not fit
+  int nptiles;          // the workgroup (next to the poles), a second launch of pblock threads
+  int pblock;
+};
+
+// A second stream for work that overlaps the main launch of a stage (the advection's polar tiles):
+// the main stream forks to it and joins it again through the two events (default priority).
+struct SideLaunch {
+  hipStream_t s;
+  hipEvent_t fork, join;
 };
 
 // Adjoint of one stage about `in`.
@@ -115,7 +126,7 @@ template <typename T>
 hipError_t launch_pole_prep(const GeoDev& g, const T* F, const T* ps, double* pole, hipStream_t s);
 // One stage out = base + ch T(in): the pole cap sums of `in`, then the process's zonal tiles.
 template <typename T>
-hipError_t launch_stage(const StageArgs<T>& a, hipStream_t s);
+hipError_t launch_stage(const StageArgs<T>& a, hipStream_t s, const SideLaunch* side = nullptr);
 // One batched stage: the cap sums of every member, then a persistent launch over the adaptation
 // tiles (titems) and one over the advection tiles (items) of every member.
 template <typename T>
@@ -231,7 +242,10 @@ struct HandleView {
   const AatItem* ftiles; // zonal tiles of the forward adaptation stage (device)
   int nftiles, ftblock;
   const AatItem* atiles; // zonal tiles of the forward advection stage (device)
-  int natiles, ablock;
+  int natiles, ablock, awide;
+  const AatItem* ptiles; // its polar tiles (larger workgroups), NULL when none
+  int nptiles, pblock;
+  const SideLaunch* side; // the stream they run on beside the main launch
   double* cap;           // cap sums of the forward adaptation stage (device, 4 nz doubles)
 };
 HandleView view_of(const dycore_s* h);

@@ -594,6 +594,24 @@ __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned ch
   const int Mv = hasV ? g.Mv[j] : 1, nv = (Mv + 1) / 2;
   const T rdxv2 = hasV ? (T)(1.0 / (2.0 * (double)Mv * g.a * g.sv[j] * g.dlam)) : T(0);
   const T rdyv2 = hasV ? (T)(1.0 / (2.0 * g.a * g.sv[j] * g.dth)) : T(0);
+  // wide tiles: the owned column's leap neighbours (i+n-1, i-n, i+n, i+1-n, i+-M, and on the V row
+  // i+nv-1, i-nv, i+-Mv) and the level-invariant 1/P^U factors that form u there
+  int wcol[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T wfac[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if constexpr (WIDE) {
+    if (own) {
+      auto cwr = [&](int o) { return ((col + o) % nx + nx) % nx; };
+      auto rp0 = [&](int c) -> T { return isPole ? T(0) : T(2) / (Prow(j, c) + Prow(j, up1(c))); };
+      auto rp1 = [&](int c) -> T { return j1Int ? T(2) / (Prow(j + 1, c) + Prow(j + 1, up1(c))) : T(0); };
+      const int offs[10] = {nj - 1, -nj, nj, 1 - nj, Mj, -Mj, nv - 1, -nv, Mv, -Mv};
+      for (int q = 0; q < 10; ++q) wcol[q] = cwr(offs[q]);
+      for (int q = 0; q < 4; ++q) wfac[q] = rp0(wcol[q]);
+      wfac[4] = rp0(wcol[6]);
+      wfac[5] = rp1(wcol[6]);
+      wfac[6] = rp0(wcol[7]);
+      wfac[7] = rp1(wcol[7]);
+    }
+  }
   T pF = 0, pU = 0, pV = 0;   // the owned column's level k-1 values
   const unsigned oc = (unsigned)col;
 #pragma unroll 1
@@ -612,32 +630,63 @@ __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned ch
     if (more) fetch(k + 1);
     const C dsg = g.dsig[k], r2d = 1.0 / (2.0 * dsg);
     const int bs = k & 1, st = k % 3, sb = (k + 1) % 3;
-    // level-k values at offset o from the owned column: LDS (band) or formed from global memory (wide)
-    // (the wide forms repeat commit's statements, so that both forms round and contract alike)
-    auto cw = [&](int o) { return ((col + o) % nx + nx) % nx; };
-    auto vF = [&](int o) -> T { return WIDE ? gF(j, k, cw(o)) : SB(bs, BF, sl + o); };
-    auto vU = [&](int o) -> T { return WIDE ? gU(j, k, cw(o)) : SB(bs, BU, sl + o); };
-    auto vV = [&](int o) -> T { return WIDE ? gV(j, k, cw(o)) : SB(bs, BV, sl + o); };
-    auto wu0 = [&](int c) -> T {
-      const T Uc = isPole ? T(0) : gU(j, k, c);
-      const T rp = isPole ? T(0) : T(2) / (Prow(j, c) + Prow(j, up1(c)));
-      const T u0 = Uc * rp;
-      return u0;
-    };
-    auto vu0 = [&](int o) -> T { return WIDE ? wu0(cw(o)) : SB(bs, Bu0, sl + o); };
-    auto vuv = [&](int o) -> T {
-      if (!WIDE) return SB(bs, Buv, sl + o);
-      const int c = cw(o);
-      const T u0 = wu0(c);
-      const T U1c = j1Int ? gU(j + 1, k, c) : T(0);
-      const T rp1 = j1Int ? T(2) / (Prow(j + 1, c) + Prow(j + 1, up1(c))) : T(0);
-      return T(0.5) * (u0 + U1c * rp1);
-    };
+    // the level-k values at the owned column's leap neighbours: LDS slots (band tiles), or formed from
+    // global memory with the level-invariant factors taken before the loop (wide tiles; the same
+    // statements as commit's, so that both forms round and contract alike)
+    T u0IC = 0, u0ID = 0, u0PA = 0, u0PB = 0, FPM = 0, FMM = 0, UPM = 0, UMM = 0;
+    T uvQA = 0, uvQB = 0, VVP = 0, VVM = 0;
+    if (own) {
+      if constexpr (WIDE) {
+        auto wu0 = [&](int c, T rp) -> T {
+          const T Uc = isPole ? T(0) : gU(j, k, c);
+          const T u0 = Uc * rp;
+          return u0;
+        };
+        auto wuv = [&](int c, T rp0, T rp1) -> T {
+          const T u0 = wu0(c, rp0);
+          const T U1c = j1Int ? gU(j + 1, k, c) : T(0);
+          return T(0.5) * (u0 + U1c * rp1);
+        };
+        if (!isPole) {
+          u0IC = wu0(wcol[0], wfac[0]);
+          u0ID = wu0(wcol[1], wfac[1]);
+          u0PA = wu0(wcol[2], wfac[2]);
+          u0PB = wu0(wcol[3], wfac[3]);
+          FPM = gF(j, k, wcol[4]);
+          FMM = gF(j, k, wcol[5]);
+          UPM = gU(j, k, wcol[4]);
+          UMM = gU(j, k, wcol[5]);
+        }
+        if (hasV) {
+          uvQA = wuv(wcol[6], wfac[4], wfac[5]);
+          uvQB = wuv(wcol[7], wfac[6], wfac[7]);
+          VVP = gV(j, k, wcol[8]);
+          VVM = gV(j, k, wcol[9]);
+        }
+      } else {
+        if (!isPole) {
+          u0IC = SB(bs, Bu0, sl + nj - 1);
+          u0ID = SB(bs, Bu0, sl - nj);
+          u0PA = SB(bs, Bu0, sl + nj);
+          u0PB = SB(bs, Bu0, sl + 1 - nj);
+          FPM = SB(bs, BF, sl + Mj);
+          FMM = SB(bs, BF, sl - Mj);
+          UPM = SB(bs, BU, sl + Mj);
+          UMM = SB(bs, BU, sl - Mj);
+        }
+        if (hasV) {
+          uvQA = SB(bs, Buv, sl + nv - 1);
+          uvQB = SB(bs, Buv, sl - nv);
+          VVP = SB(bs, BV, sl + Mv);
+          VVM = SB(bs, BV, sl - Mv);
+        }
+      }
+    }
     if (own) {
       const int sp = sl + 1;
       if (!isPole) {
         // Phi: the leaped centred difference of u Phi, u at the midpoints
-        const T L1 = (vu0(nj - 1) * vF(Mj) - vu0(-nj) * vF(-Mj)) * rdx2;
+        const T L1 = (u0IC * FPM - u0ID * FMM) * rdx2;
         const T L2 = (SB(bs, Bvt0, sl) * cFn - SB(bs, Bvtm, sl) * cFs) * rdy2;
         C L3 = 0;
         if (more) L3 += sd0n * (C)nF;
@@ -645,9 +694,9 @@ __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned ch
         const C TF = -((C)L1 + (C)L2 + L3 * r2d);
         stg(A.oF, lo + oc, (T)((C)baseF + A.ch * TF));
         // U: the same leap on U points, u averaged to the integer points i+n and i+1-n
-        const T ubA = T(0.5) * (vu0(nj - 1) + vu0(nj));
-        const T ubB = T(0.5) * (vu0(-nj) + vu0(1 - nj));
-        const T U1v = (ubA * vU(Mj) - ubB * vU(-Mj)) * rdx2;
+        const T ubA = T(0.5) * (u0IC + u0PA);
+        const T ubB = T(0.5) * (u0ID + u0PB);
+        const T U1v = (ubA * UPM - ubB * UMM) * rdx2;
         const T vtn = T(0.5) * (SB(bs, Bvt0, sl) + SB(bs, Bvt0, sp));
         const T vts = T(0.5) * (SB(bs, Bvtm, sl) + SB(bs, Bvtm, sp));
         const T U2v = (vtn * cU1 - vts * cUs) * rdy2;
@@ -669,7 +718,7 @@ __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned ch
         if (col == 0) A.pout[pidx * (nz + 1) + k] = (double)val;
       }
       if (hasV) {
-        const T L1 = (vuv(nv - 1) * vV(Mv) - vuv(-nv) * vV(-Mv)) * rdxv2;
+        const T L1 = (uvQA * VVP - uvQB * VVM) * rdxv2;
         T L2 = T(0);
         if (j + 1 < ny) L2 += T(0.5) * (SB(bs, Bvt0, sl) + cV1 * rPV1 * sv1) * cV1;
         if (j > 0) L2 -= T(0.5) * (SB(bs, Bvtm, sl) + SB(bs, Bvt0, sl)) * cVm;
@@ -745,15 +794,22 @@ __global__ void __launch_bounds__(64) k_capsum_batch(const StageArgs<T>* __restr
   else if (a.process == 1) capsum_adv_level<T>(a, blockIdx.x, blockIdx.y);
 }
 
-// One launch per advection stage (after k_capsum_adv): one workgroup per zonal tile, the wide tiles
-// first in the list so that they start early.
-template <typename T>
-__global__ void __launch_bounds__(256) k_stage_atile(StageArgs<T> a) {
+// Advection stage tiles (after k_capsum_adv): one workgroup per zonal tile.  The main launch takes
+// the rows whose halos fit its workgroup as band tiles; the rows next to the poles run as wide tiles
+// in a second launch (WIDE), beside it on a second stream, so that their larger register need does not
+// lower the main launch's occupancy (band tiles alone stay within 128 VGPRs: four waves per SIMD).
+template <typename T, int MAXB, bool WIDE>
+__global__ void __launch_bounds__(MAXB) k_stage_atile(StageArgs<T> a, const AatItem* items) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const AatItem it = a.atiles[blockIdx.x];
+  const AatItem it = items[blockIdx.x];
   if (it.j < 0) return;
-  if (it.hl < 0) advect_tile<T, true>(a, it, smem);
-  else advect_tile<T, false>(a, it, smem);
+  if constexpr (WIDE) {
+    if (it.hl < 0) {
+      advect_tile<T, true>(a, it, smem);
+      return;
+    }
+  }
+  advect_tile<T, false>(a, it, smem);
 }
 
 // One launch per adaptation stage: one workgroup per zonal tile (the cap sums come from k_capsum).
@@ -963,14 +1019,32 @@ hipError_t launch_adapt_tiles(const StageArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// An advection stage: the pole cap sums of its input, then the tiles.
+// An advection stage: the pole cap sums of its input, then the tiles: the polar ones on the side
+// stream (or, without one, before the others on the same stream).
 template <typename T>
-hipError_t launch_advect_tiles(const StageArgs<T>& a, hipStream_t s) {
+hipError_t launch_advect_tiles(const StageArgs<T>& a, hipStream_t s, const SideLaunch* side) {
   hipLaunchKernelGGL((k_capsum_adv<T>), dim3(a.g.nz, 2), dim3(64), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stage_atile<T>), dim3(a.natiles), dim3(a.ablock), advect_tile_lds(a.ablock, sizeof(T)), s, a);
-  return hipGetLastError();
+  const bool fork = a.nptiles > 0 && side != nullptr;
+  if (a.nptiles > 0) {
+    const size_t plds = advect_tile_lds(a.pblock, sizeof(T));
+    hipStream_t ps = s;
+    if (fork) {
+      if ((e = hipEventRecord(side->fork, s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(side->s, side->fork, 0)) != hipSuccess) return e;
+      ps = side->s;
+    }
+    hipLaunchKernelGGL((k_stage_atile<T, 256, true>), dim3(a.nptiles), dim3(a.pblock), plds, ps, a, a.ptiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (fork && (e = hipEventRecord(side->join, side->s)) != hipSuccess) return e;
+  }
+  const size_t lds = advect_tile_lds(a.ablock, sizeof(T));
+  if (a.awide) hipLaunchKernelGGL((k_stage_atile<T, 256, true>), dim3(a.natiles), dim3(a.ablock), lds, s, a, a.atiles);
+  else hipLaunchKernelGGL((k_stage_atile<T, 256, false>), dim3(a.natiles), dim3(a.ablock), lds, s, a, a.atiles);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (fork) e = hipStreamWaitEvent(s, side->join, 0);
+  return e;
 }
 
 }  // namespace
@@ -979,8 +1053,8 @@ size_t adapt_tile_lds_bytes(int block, int elem) { return adapt_tile_lds(block, 
 size_t advect_tile_lds_bytes(int block, int elem) { return advect_tile_lds(block, elem); }
 
 template <typename T>
-hipError_t launch_stage(const StageArgs<T>& a, hipStream_t s) {
-  return a.process == 0 ? launch_adapt_tiles<T>(a, s) : launch_advect_tiles<T>(a, s);
+hipError_t launch_stage(const StageArgs<T>& a, hipStream_t s, const SideLaunch* side) {
+  return a.process == 0 ? launch_adapt_tiles<T>(a, s) : launch_advect_tiles<T>(a, s, side);
 }
 
 template <typename T>
@@ -1044,7 +1118,7 @@ hipError_t launch_zero(T* dst, size_t n, hipStream_t s) {
 }
 
 #define DYC_INST(T)                                                                                          \
-  template hipError_t launch_stage<T>(const StageArgs<T>&, hipStream_t);                                     \
+  template hipError_t launch_stage<T>(const StageArgs<T>&, hipStream_t, const SideLaunch*);                 \
   template hipError_t launch_stage_batch<T>(const StageArgs<T>*, int, int, const int2*, int, const int2*, int,   \
                                             int, int, size_t, hipStream_t);                                  \
   template hipError_t launch_pole_prep<T>(const GeoDev&, const T*, const T*, double*, hipStream_t);          \
