@@ -115,6 +115,31 @@ def test_batch_autotune_bitwise():
             assert torch.equal(s[k], r[k]), k
 
 
+def test_step_graph_replay_with_polar_launch():
+    """dycore_step captured in a hipGraph on a grid whose advection runs wide polar tiles on the
+    handle's second stream (749 x 374: the last row's halo is 169 columns): each replay, with eager
+    steps between, equals the eager step bit for bit."""
+    from paper_2103_10114_amd import Dycore
+    cfg = dataclasses.replace(synth.CONFIGS["c1"], nx=749, ny=374, nz=3, degree=5, seed=31, dt=120.0)
+    st = synth.make_state(cfg)
+    core = Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec="fp32", phis=st["phis"], forward_only=True)
+    work = core.to_device(st)
+    ref = core.to_device(st)
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        core.step(work, 1)
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        core.step(ref, 1)
+        torch.cuda.synchronize()
+        for k in ("U", "V", "Phi", "ps"):
+            assert torch.equal(work[k], ref[k]), (rep, k)
+    assert core.count_nonfinite(work) == 0
+
+
 def test_ensemble_c5_bitwise_and_graph_replay():
     """The 24-member mixed ensemble (8 each of 128x64x9, 256x128x30, 720x360x30, seeds 500+m, 0.5 m/s
     wind noise): one persistent launch per stage, captured in a hipGraph and replayed; after each
