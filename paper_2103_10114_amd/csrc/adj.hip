@@ -33,6 +33,23 @@ __device__ __forceinline__ double wave_sum(double acc) {
   return acc;
 }
 
+// One lane's FP64 partial sum of a row of n values: the lane's elements (lane, lane + 64, ...) added
+// in index order, the loads of eight of them issued before their additions.
+template <typename T>
+__device__ __forceinline__ double lane_row_sum(const T* p, int n, int lane) {
+  constexpr int CH = 8;
+  double s = 0;
+  for (int i0 = lane; i0 < n; i0 += 64 * CH) {
+    T v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) v[u] = p[i0 + 64 * u < n ? i0 + 64 * u : i0];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (i0 + 64 * u < n) s += (double)v[u];
+  }
+  return s;
+}
+
 template <typename T> __device__ __forceinline__ T tsqrt(T x);
 template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 template <> __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
@@ -358,8 +375,15 @@ __global__ void __launch_bounds__(256) k_f1p(Ctx<T> c) {
   const int nx = g.nx, nz = g.nz, t = threadIdx.x;
   const T b = (T)g.b;
   const T Pp = P2(c, j, 0);
-  auto RTl = [&](int kk) -> T { return b * (T)c.pin[p * (nz + 1) + kk] / Pp; };
-  auto Dl = [&](int kk) -> C { return (C)c.s.D[i3<T>(g, j, kk, 0)]; };
+  __shared__ T sRT[kMaxLevels];
+  __shared__ double sD[kMaxLevels];
+  for (int kk = t; kk < nz; kk += blockDim.x) {
+    sRT[kk] = b * (T)c.pin[p * (nz + 1) + kk] / Pp;
+    sD[kk] = (C)c.s.D[i3<T>(g, j, kk, 0)];
+  }
+  __syncthreads();
+  auto RTl = [&](int kk) -> T { return sRT[kk]; };
+  auto Dl = [&](int kk) -> C { return sD[kk]; };
   C H = 0, Pi = 0;
   for (int kk = 0; kk < nz; ++kk) {
     H += g.cl[kk] * (C)RTl(kk);
@@ -420,10 +444,9 @@ __global__ void __launch_bounds__(64) k_pole_sum(GeoDev g, const T* f3, const T*
   const int j = p == 0 ? 0 : g.ny;
   C s = 0;
   if (k < g.nz) {
-    if (f3)
-      for (int i = threadIdx.x; i < g.nx; i += 64) s += (C)f3[((size_t)j * g.nz + k) * g.nx + i];
+    if (f3) s = lane_row_sum(f3 + ((size_t)j * g.nz + k) * g.nx, g.nx, threadIdx.x);
   } else if (f2) {
-    for (int i = threadIdx.x; i < g.nx; i += 64) s += (C)f2[(size_t)j * g.nx + i];
+    s = lane_row_sum(f2 + (size_t)j * g.nx, g.nx, threadIdx.x);
   }
   s = wave_sum(s);
   if (threadIdx.x == 0) out[p * (g.nz + 1) + k] = s;
@@ -441,23 +464,33 @@ __global__ void __launch_bounds__(64) k_pole_sum2(GeoDev g, const T* fa, double*
   const int p = v / (g.nz + 1), k = v % (g.nz + 1);
   const int j = p == 0 ? 0 : g.ny;
   C s = 0;
-  if (k < g.nz)
-    for (int i = threadIdx.x; i < g.nx; i += 64) s += (C)f3[((size_t)j * g.nz + k) * g.nx + i];
+  if (k < g.nz) s = lane_row_sum(f3 + ((size_t)j * g.nz + k) * g.nx, g.nx, threadIdx.x);
   s = wave_sum(s);
   if (threadIdx.x == 0) out[p * (g.nz + 1) + k] = s;
 }
 
+// The pole sums of the output adjoints of Phi (per level) and p_s (slot nz) into PS_AOF, the first
+// wavefront of each block summing its row as k_pole_sum does, then the base part of the pole rows'
+// transpose: the block adds its sum / nx to every stored copy of its row of the base adjoint.
 template <typename T>
-__global__ void k_base_pole(Ctx<T> c) {
+__global__ void __launch_bounds__(256) k_pole_sum_base(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int p = blockIdx.y, k = blockIdx.x;   // k in 0..nz (nz = p_s)
+  const int v = blockIdx.x;   // 0 .. 2*(nz+1)-1
+  const int p = v / (g.nz + 1), k = v % (g.nz + 1);
   const int j = p == 0 ? 0 : g.ny;
-  const double* sf = c.s.psum + PS_AOF * 2 * (g.nz + 1);
-  const T add = (T)(sf[p * (g.nz + 1) + k] / g.nx);
-  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
-    if (k < g.nz) c.abF[i3<T>(g, j, k, i)] += add;
-    else c.abP[(size_t)j * g.nx + i] += add;
+  __shared__ double tot;
+  if (threadIdx.x < 64) {
+    const T* row = k < g.nz ? c.aoF + ((size_t)j * g.nz + k) * g.nx : c.aoP + (size_t)j * g.nx;
+    const C s = wave_sum(lane_row_sum(row, g.nx, threadIdx.x));
+    if (threadIdx.x == 0) {
+      c.s.psum[PS_AOF * 2 * (g.nz + 1) + p * (g.nz + 1) + k] = s;
+      tot = s;
+    }
   }
+  __syncthreads();
+  const T add = (T)(tot / g.nx);
+  T* dst = k < g.nz ? c.abF + ((size_t)j * g.nz + k) * g.nx : c.abP + (size_t)j * g.nx;
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) dst[i] += add;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1958,9 +1991,11 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
       hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
     }
   }
-  hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
-                     c.s.psum + PS_AOF * 2 * (nz + 1));
-  if (c.abU) hipLaunchKernelGGL((k_base_pole<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
+  if (c.abU)
+    hipLaunchKernelGGL((k_pole_sum_base<T>), dim3(2 * (nz + 1)), dim3(256), 0, s, c);
+  else
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
+                       c.s.psum + PS_AOF * 2 * (nz + 1));
   // (process-specific part is launched by the caller between these two groups)
   return hipGetLastError();
 }

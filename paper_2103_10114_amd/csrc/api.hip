@@ -83,7 +83,7 @@ struct dycore_s {
   AatItem* atiles = nullptr;    // zonal tiles of the forward advection stage (device): the main
   int natiles = 0, awide = 0;   // launch's (workgroups of `block` threads; awide: it has wide tiles),
   int nptiles = 0, pblock = 0;  // then the polar launch's (wide tiles) at atiles + natiles
-  dyc::SideLaunch side{nullptr, nullptr, nullptr};   // the polar launch's stream and events
+  dyc::SideLaunch side{nullptr, nullptr, nullptr};   // second stream and events: band beside polar tiles
   double* cap = nullptr;        // cap sums of the forward adaptation stage: [2 poles][2][nz]
   size_t bytes = 0;
 };
@@ -482,7 +482,7 @@ int cfl_substeps(const dycore_config* c) {
 
 int validate_cfg(const dycore_config* c) {
   if (!c) return DYCORE_EINVAL;
-  if (c->nx < 8 || c->nx > 4096 || c->ny < 4 || c->ny > 8192 || c->nz < 1 || c->nz > 128) return DYCORE_EINVAL;
+  if (c->nx < 8 || c->nx > 4096 || c->ny < 4 || c->ny > 8192 || c->nz < 1 || c->nz > kMaxLevels) return DYCORE_EINVAL;
   if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return DYCORE_EINVAL;
   if (c->n_adapt_substeps < 0) return DYCORE_EINVAL;
   if (c->prec != DYCORE_FP32 && c->prec != DYCORE_FP64) return DYCORE_EINVAL;
@@ -722,7 +722,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       h->pblock = pblock;
       h->bytes += sizeof(AatItem) * nall;
     }
-    // the polar tiles run beside the main launch on a stream of their own (default priority)
+    // the band tiles run beside the polar launch on a second stream (default priority)
     if (ok && h->nptiles > 0) {
       ok = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking) == hipSuccess;
       ok = ok && hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming) == hipSuccess;

@@ -59,6 +59,7 @@ struct KTimer {
 struct AatItem {
   int j, i0, w, hl;
 };
+constexpr int kMaxLevels = 128;         // most model levels a handle takes
 constexpr int kAatMaxBlock = 320;       // adjoint tiles
 constexpr int kFwdTileMaxBlock = 1024;  // forward adaptation tiles
 constexpr int kBatchMaxBlock = 512;     // the persistent batched stage (its VGPR budget: 256)
@@ -89,8 +90,9 @@ struct StageArgs {
   int pblock;
 };
 
-// A second stream for work that overlaps the main launch of a stage (the advection's polar tiles):
-// the main stream forks to it and joins it again through the two events (default priority).
+// A second stream for a launch that overlaps another of the same stage (the advection's band tiles
+// run there beside its polar tiles): the stage's stream forks to it and joins it again through the
+// two events (default priority).
 struct SideLaunch {
   hipStream_t s;
   hipEvent_t fork, join;
@@ -245,7 +247,7 @@ struct HandleView {
   int natiles, ablock, awide;
   const AatItem* ptiles; // its polar tiles (larger workgroups), NULL when none
   int nptiles, pblock;
-  const SideLaunch* side; // the stream they run on beside the main launch
+  const SideLaunch* side; // the second stream: the band tiles run there beside the polar launch
   double* cap;           // cap sums of the forward adaptation stage (device, 4 nz doubles)
 };
 HandleView view_of(const dycore_s* h);

@@ -355,9 +355,37 @@ __device__ void adapt_tile(const StageArgs<T>& A, const AatItem it, unsigned cha
   }
 }
 
-// FP64 cap sums of the adaptation stage's input, one block (a wavefront) per (level, pole): the
-// flux sum_i P^V V through the V row next to the pole and sum_i (V / P^V) (l_adj - l_pole), in a
-// fixed order (lane-strided partial sums, then a butterfly), for the pole rows of adapt_tile.
+// FP64 cap sums of the adaptation stage's input, one block per (level, pole): the flux
+// sum_i P^V V through the V row next to the pole and sum_i (V / P^V) (l_adj - l_pole), in a fixed
+// order (thread-strided partial sums, a butterfly per wavefront, the wavefronts in order), for the
+// pole rows of adapt_tile.
+constexpr int kCapChunk = 8;   // columns per thread whose loads go out together
+constexpr int kCapBlock = 256;  // threads of a cap-sum block
+
+// The block's two cap sums of one (level, pole): each wavefront's butterfly, then the wavefronts'
+// sums added in wavefront order.
+template <typename T>
+__device__ __forceinline__ void cap_store(const StageArgs<T>& A, int k, int p, double s1, double s2) {
+  __shared__ double red[2][kCapBlock / 64];
+  const int nz = A.g.nz;
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s1;
+    red[1][threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t1 = 0, t2 = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      t1 += red[0][w];
+      t2 += red[1][w];
+    }
+    A.cap[p * 2 * nz + k] = t1;
+    A.cap[p * 2 * nz + nz + k] = t2;
+  }
+}
+
 template <typename T>
 __device__ void capsum_level(const StageArgs<T>& A, int k, int p) {
   const GeoDev& g = A.g;
@@ -367,25 +395,34 @@ __device__ void capsum_level(const StageArgs<T>& A, int k, int p) {
   const T pps = (T)A.pin[(p == 0 ? 0 : nz + 1) + nz];
   const T Pp = tsqrt<T>(pps / p0), lp = tlog<T>(pps / p0);
   const T* pV = A.inV + ((size_t)jva * nz + k) * nx;
+  const T* pP = A.inP + (size_t)ja * nx;
   C s1 = 0, s2 = 0;
-  for (int i = threadIdx.x; i < nx; i += 64) {
-    const T psa = A.inP[(size_t)ja * nx + i];
-    const T Pa = tsqrt<T>(psa / p0), La = tlog<T>(psa / p0);
-    const T pv = T(0.5) * (Pp + Pa);
-    const T vv = pV[i];
-    s1 += (C)(pv * vv);
-    s2 += (C)((vv / pv) * (p == 0 ? (La - lp) : (lp - La)));
+  // the thread's columns in index order, the loads of kCapChunk of them ahead of their additions
+  const int nt = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < nx; i0 += nt * kCapChunk) {
+    T psv[kCapChunk], vvv[kCapChunk];
+#pragma unroll
+    for (int u = 0; u < kCapChunk; ++u) {
+      const int i = i0 + nt * u < nx ? i0 + nt * u : i0;
+      psv[u] = pP[i];
+      vvv[u] = pV[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCapChunk; ++u) {
+      if (i0 + nt * u >= nx) break;
+      const T psa = psv[u];
+      const T Pa = tsqrt<T>(psa / p0), La = tlog<T>(psa / p0);
+      const T pv = T(0.5) * (Pp + Pa);
+      const T vv = vvv[u];
+      s1 += (C)(pv * vv);
+      s2 += (C)((vv / pv) * (p == 0 ? (La - lp) : (lp - La)));
+    }
   }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (threadIdx.x == 0) {
-    A.cap[p * 2 * nz + k] = s1;
-    A.cap[p * 2 * nz + nz + k] = s2;
-  }
+  cap_store(A, k, p, s1, s2);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_capsum(StageArgs<T> a) {
+__global__ void __launch_bounds__(kCapBlock) k_capsum(StageArgs<T> a) {
   capsum_level<T>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -407,8 +444,11 @@ constexpr int kAdvTileRows = 7;
 constexpr int kAdvTileRS = 2 * kAdvTileRows + 3;   // 17 words per slot
 __host__ __device__ constexpr size_t advect_tile_lds(int block, int elem) { return (size_t)kAdvTileRS * block * elem; }
 
-template <typename T, bool WIDE>
+// WPF (wide tiles only): the leap operands and base values of level k+1 are fetched while level k is
+// computed; without it a wide tile loads them at their level (the batched kernel's register budget)
+template <typename T, bool WIDE, bool WPF = WIDE>
 __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned char* smem) {
+  static_assert(WIDE || !WPF, "the prefetch serves wide tiles");
   const GeoDev& g = A.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int j = it.j, w = it.w, hl = WIDE ? 1 : it.hl;
@@ -614,13 +654,52 @@ __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned ch
   }
   T pF = 0, pU = 0, pV = 0;   // the owned column's level k-1 values
   const unsigned oc = (unsigned)col;
+  // wide tiles: the owned column's leap operands and base values of a level (with WPF those of the
+  // next level, fetched while the current one is computed: a wide launch's few workgroups cannot
+  // hide a load's latency)
+  T wU0 = 0, wU1 = 0, wU2 = 0, wU3 = 0, wF4 = 0, wF5 = 0, wU4 = 0, wU5 = 0;
+  T wUa6 = 0, wUa7 = 0, wUb6 = 0, wUb7 = 0, wV8 = 0, wV9 = 0, wbF = 0, wbU = 0, wbV = 0;
+  auto wfetch = [&](int k) {
+    if (!own) return;
+    const unsigned lo = (unsigned)j * row3 + (unsigned)(k * nx);
+    if (!isPole) {
+      wU0 = gU(j, k, wcol[0]);
+      wU1 = gU(j, k, wcol[1]);
+      wU2 = gU(j, k, wcol[2]);
+      wU3 = gU(j, k, wcol[3]);
+      wF4 = gF(j, k, wcol[4]);
+      wF5 = gF(j, k, wcol[5]);
+      wU4 = gU(j, k, wcol[4]);
+      wU5 = gU(j, k, wcol[5]);
+      wbF = ldg(A.bF, lo + oc);
+      wbU = ldg(A.bU, lo + oc);
+    }
+    if (hasV) {
+      wUa6 = isPole ? T(0) : gU(j, k, wcol[6]);
+      wUa7 = isPole ? T(0) : gU(j, k, wcol[7]);
+      wUb6 = j1Int ? gU(j + 1, k, wcol[6]) : T(0);
+      wUb7 = j1Int ? gU(j + 1, k, wcol[7]) : T(0);
+      wV8 = gV(j, k, wcol[8]);
+      wV9 = gV(j, k, wcol[9]);
+      wbV = ldg(A.bV, lo + oc);
+    }
+  };
+  if constexpr (WPF) wfetch(0);
 #pragma unroll 1
   for (int k = 0; k < nz; ++k) {
     const bool more = k + 1 < nz;
     const T cF = nF, cU = nU, cV = nV;   // level k (the fetch below moves to level k+1)
     T baseF = 0, baseU = 0, baseV = 0;
     const unsigned lo = (unsigned)j * row3 + (unsigned)(k * nx);
-    if (own) {
+    // wide tiles with WPF: this level's prefetched operands (the fetch below moves to level k+1)
+    const T xU0 = wU0, xU1 = wU1, xU2 = wU2, xU3 = wU3, xF4 = wF4, xF5 = wF5, xU4 = wU4, xU5 = wU5;
+    const T xUa6 = wUa6, xUa7 = wUa7, xUb6 = wUb6, xUb7 = wUb7, xV8 = wV8, xV9 = wV9;
+    if constexpr (WPF) {
+      baseF = wbF;
+      baseU = wbU;
+      baseV = wbV;
+      if (more) wfetch(k + 1);
+    } else if (own) {
       if (!isPole) {
         baseF = ldg(A.bF, lo + oc);
         baseU = ldg(A.bU, lo + oc);
@@ -636,7 +715,28 @@ __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned ch
     T u0IC = 0, u0ID = 0, u0PA = 0, u0PB = 0, FPM = 0, FMM = 0, UPM = 0, UMM = 0;
     T uvQA = 0, uvQB = 0, VVP = 0, VVM = 0;
     if (own) {
-      if constexpr (WIDE) {
+      if constexpr (WPF) {
+        auto wuv = [&](T Uc, T U1c, T rp0, T rp1) -> T {
+          const T u0 = Uc * rp0;
+          return T(0.5) * (u0 + U1c * rp1);
+        };
+        if (!isPole) {
+          u0IC = xU0 * wfac[0];
+          u0ID = xU1 * wfac[1];
+          u0PA = xU2 * wfac[2];
+          u0PB = xU3 * wfac[3];
+          FPM = xF4;
+          FMM = xF5;
+          UPM = xU4;
+          UMM = xU5;
+        }
+        if (hasV) {
+          uvQA = wuv(xUa6, xUb6, wfac[4], wfac[5]);
+          uvQB = wuv(xUa7, xUb7, wfac[6], wfac[7]);
+          VVP = xV8;
+          VVM = xV9;
+        }
+      } else if constexpr (WIDE) {
         auto wu0 = [&](int c, T rp) -> T {
           const T Uc = isPole ? T(0) : gU(j, k, c);
           const T u0 = Uc * rp;
@@ -750,9 +850,9 @@ __device__ void advect_tile(const StageArgs<T>& A, const AatItem it, unsigned ch
   }
 }
 
-// FP64 cap sums of the advection stage's input, one wavefront per (level, pole), in the fixed order
-// of the lane-strided partial sums and a butterfly: the flux sum_i P^V V through the V row next to
-// the pole and sum_i (V / P^V) sin(theta) Phi of the row next to the pole.
+// FP64 cap sums of the advection stage's input, one block per (level, pole), in the fixed order of
+// capsum_level: the flux sum_i P^V V through the V row next to the pole and
+// sum_i (V / P^V) sin(theta) Phi of the row next to the pole.
 template <typename T>
 __device__ void capsum_adv_level(const StageArgs<T>& A, int k, int p) {
   const GeoDev& g = A.g;
@@ -763,29 +863,38 @@ __device__ void capsum_adv_level(const StageArgs<T>& A, int k, int p) {
   const T* pV = A.inV + ((size_t)jv * nz + k) * nx;
   const T* pF = A.inF + ((size_t)ja * nz + k) * nx;
   const T svv = (T)g.sv[jv];
+  const T* pP = A.inP + (size_t)ja * nx;
   C s1 = 0, s2 = 0;
-  for (int i = threadIdx.x; i < nx; i += 64) {
-    const T pv = T(0.5) * (Pp + tsqrt<T>(A.inP[(size_t)ja * nx + i] / p0));
-    const T vv = pV[i];
-    s1 += (C)(pv * vv);
-    s2 += (C)(vv / pv * svv * pF[i]);
+  const int nt = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < nx; i0 += nt * kCapChunk) {
+    T psv[kCapChunk], vvv[kCapChunk], fv[kCapChunk];
+#pragma unroll
+    for (int u = 0; u < kCapChunk; ++u) {
+      const int i = i0 + nt * u < nx ? i0 + nt * u : i0;
+      psv[u] = pP[i];
+      vvv[u] = pV[i];
+      fv[u] = pF[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCapChunk; ++u) {
+      if (i0 + nt * u >= nx) break;
+      const T pv = T(0.5) * (Pp + tsqrt<T>(psv[u] / p0));
+      const T vv = vvv[u];
+      s1 += (C)(pv * vv);
+      s2 += (C)(vv / pv * svv * fv[u]);
+    }
   }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (threadIdx.x == 0) {
-    A.cap[p * 2 * nz + k] = s1;
-    A.cap[p * 2 * nz + nz + k] = s2;
-  }
+  cap_store(A, k, p, s1, s2);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_capsum_adv(StageArgs<T> a) {
+__global__ void __launch_bounds__(kCapBlock) k_capsum_adv(StageArgs<T> a) {
   capsum_adv_level<T>(a, blockIdx.x, blockIdx.y);
 }
 
 // The cap sums of every batched member, for the process of its stage.
 template <typename T>
-__global__ void __launch_bounds__(64) k_capsum_batch(const StageArgs<T>* __restrict__ args, int n) {
+__global__ void __launch_bounds__(kCapBlock) k_capsum_batch(const StageArgs<T>* __restrict__ args, int n) {
   const int m = blockIdx.z;
   if (m >= n) return;
   const StageArgs<T> a = args[m];
@@ -796,8 +905,9 @@ __global__ void __launch_bounds__(64) k_capsum_batch(const StageArgs<T>* __restr
 
 // Advection stage tiles (after k_capsum_adv): one workgroup per zonal tile.  The main launch takes
 // the rows whose halos fit its workgroup as band tiles; the rows next to the poles run as wide tiles
-// in a second launch (WIDE), beside it on a second stream, so that their larger register need does not
-// lower the main launch's occupancy (band tiles alone stay within 128 VGPRs: four waves per SIMD).
+// in a second launch (WIDE) that runs beside it, the two on different streams, so that their larger
+// register need does not lower the main launch's occupancy (band tiles alone stay within 128 VGPRs:
+// four waves per SIMD).
 template <typename T, int MAXB, bool WIDE>
 __global__ void __launch_bounds__(MAXB) k_stage_atile(StageArgs<T> a, const AatItem* items) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -838,7 +948,7 @@ __global__ void __launch_bounds__(kBatchMaxBlock) k_stage_batch(const StageArgs<
     const AatItem ti = PROC == 0 ? a.tiles[it.y] : a.atiles[it.y];
     if (ti.j < 0) continue;
     if constexpr (PROC == 0) adapt_tile<T>(a, ti, smem);
-    else if (ti.hl < 0) advect_tile<T, true>(a, ti, smem);
+    else if (ti.hl < 0) advect_tile<T, true, false>(a, ti, smem);
     else advect_tile<T, false>(a, ti, smem);
     __syncthreads();
   }
@@ -1009,7 +1119,7 @@ hipError_t allow_lds(size_t lds) {
 // An adaptation stage: the cap sums of its input, then the tiles.
 template <typename T>
 hipError_t launch_adapt_tiles(const StageArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_capsum<T>), dim3(a.g.nz, 2), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((k_capsum<T>), dim3(a.g.nz, 2), dim3(kCapBlock), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = adapt_tile_lds(a.tblock, sizeof(T));
@@ -1019,31 +1129,37 @@ hipError_t launch_adapt_tiles(const StageArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// An advection stage: the pole cap sums of its input, then the tiles: the polar ones on the side
-// stream (or, without one, before the others on the same stream).
+// An advection stage: the pole cap sums of its input, then the tiles: the polar ones first on the
+// stage's stream, the band tiles beside them on the side stream (without one, after them on the same
+// stream).
 template <typename T>
 hipError_t launch_advect_tiles(const StageArgs<T>& a, hipStream_t s, const SideLaunch* side) {
-  hipLaunchKernelGGL((k_capsum_adv<T>), dim3(a.g.nz, 2), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((k_capsum_adv<T>), dim3(a.g.nz, 2), dim3(kCapBlock), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const bool fork = a.nptiles > 0 && side != nullptr;
+  hipStream_t ms = s;   // the stream of the main launch
   if (a.nptiles > 0) {
+    // the polar tiles go out first, on the stage's stream, the band tiles beside them on the second
+    // stream: a polar workgroup needs more registers per wave than a finished band workgroup frees,
+    // so queued behind a full band launch it would start only at that launch's tail
     const size_t plds = advect_tile_lds(a.pblock, sizeof(T));
-    hipStream_t ps = s;
     if (fork) {
       if ((e = hipEventRecord(side->fork, s)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(side->s, side->fork, 0)) != hipSuccess) return e;
-      ps = side->s;
+      ms = side->s;
     }
-    hipLaunchKernelGGL((k_stage_atile<T, 256, true>), dim3(a.nptiles), dim3(a.pblock), plds, ps, a, a.ptiles);
+    hipLaunchKernelGGL((k_stage_atile<T, 256, true>), dim3(a.nptiles), dim3(a.pblock), plds, s, a, a.ptiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (fork && (e = hipEventRecord(side->join, side->s)) != hipSuccess) return e;
   }
   const size_t lds = advect_tile_lds(a.ablock, sizeof(T));
-  if (a.awide) hipLaunchKernelGGL((k_stage_atile<T, 256, true>), dim3(a.natiles), dim3(a.ablock), lds, s, a, a.atiles);
-  else hipLaunchKernelGGL((k_stage_atile<T, 256, false>), dim3(a.natiles), dim3(a.ablock), lds, s, a, a.atiles);
+  if (a.awide) hipLaunchKernelGGL((k_stage_atile<T, 256, true>), dim3(a.natiles), dim3(a.ablock), lds, ms, a, a.atiles);
+  else hipLaunchKernelGGL((k_stage_atile<T, 256, false>), dim3(a.natiles), dim3(a.ablock), lds, ms, a, a.atiles);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (fork) e = hipStreamWaitEvent(s, side->join, 0);
+  if (fork) {
+    if ((e = hipEventRecord(side->join, side->s)) != hipSuccess) return e;
+    e = hipStreamWaitEvent(s, side->join, 0);
+  }
   return e;
 }
 
@@ -1060,7 +1176,7 @@ hipError_t launch_stage(const StageArgs<T>& a, hipStream_t s, const SideLaunch* 
 template <typename T>
 hipError_t launch_stage_batch(const StageArgs<T>* d_args, int nargs, int max_nz, const int2* d_titems, int ntitems,
                               const int2* d_items, int nitems, int grid, int block, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_capsum_batch<T>), dim3(max_nz, 2, nargs), dim3(64), 0, s, d_args, nargs);
+  hipLaunchKernelGGL((k_capsum_batch<T>), dim3(max_nz, 2, nargs), dim3(kCapBlock), 0, s, d_args, nargs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ntitems > 0) {

@@ -116,9 +116,9 @@ def test_batch_autotune_bitwise():
 
 
 def test_step_graph_replay_with_polar_launch():
-    """dycore_step captured in a hipGraph on a grid whose advection runs wide polar tiles on the
-    handle's second stream (749 x 374: the last row's halo is 169 columns): each replay, with eager
-    steps between, equals the eager step bit for bit."""
+    """dycore_step captured in a hipGraph on a grid whose advection runs wide polar tiles beside its
+    band tiles, the two launches on two streams (749 x 374: the last row's halo is 169 columns): each
+    replay, with eager steps between, equals the eager step bit for bit."""
     from paper_2103_10114_amd import Dycore
     cfg = dataclasses.replace(synth.CONFIGS["c1"], nx=749, ny=374, nz=3, degree=5, seed=31, dt=120.0)
     st = synth.make_state(cfg)
