@@ -220,7 +220,7 @@ __global__ void k_f2d(Ctx<T> c) {
 
 // interior columns: RT', D, S, phi', sigma-dot, omega/p
 template <typename T>
-__global__ void k_f1(Ctx<T> c) {
+__global__ void __launch_bounds__(256) k_f1(Ctx<T> c) {
   const GeoDev& g = c.g;
   int tx, k0, jy;
   xcd_tile3((int)gridDim.x, 1, (int)gridDim.y, tx, k0, jy);
@@ -255,19 +255,43 @@ __global__ void k_f1(Ctx<T> c) {
   const C rP2c = 1.0 / ((C)P0 * (C)P0);
   C aPi = 0, aSt = 0;   // aPi and the column sum of aS_h = -asd_h / P^2
   if (!asdm) stg(c.s.S, ihu(g, j, 0, i), T(0));
+  // the level's loads, issued one level ahead of their use
+  struct L1 { T F, U, V, Uw, Vm, aF, aU, aUw, aVm, aV, Ua, Ub; };
+  auto load1 = [&](int k) {
+    L1 l{};
+    const unsigned id = i3u(g, j, k, i), idm = i3u(g, j - 1, k, i);
+    if (asdm || all) l.F = ldg(c.F, id);
+    if (asdm || keep_uv) l.U = ldg(c.U, id);
+    l.V = ldg(c.V, id);
+    l.Vm = ldg(c.V, idm);
+    if (asdm) {
+      const unsigned idw = i3u(g, j, k, im1);
+      l.Uw = ldg(c.U, idw);
+      l.aF = ldg(c.aoF, id);
+      l.aU = ldg(c.aoU, id);
+      l.aUw = ldg(c.aoU, idw);
+      l.aVm = ldg(c.aoV, idm);
+      l.aV = ldg(c.aoV, id);
+    }
+    l.Ua = ldg(c.U, i3u(g, j, k, pa));
+    l.Ub = ldg(c.U, i3u(g, j, k, pb));
+    return l;
+  };
+  L1 nx1 = load1(0);
   for (int k = 0; k < nz; ++k) {
     const unsigned id = i3u(g, j, k, i);
+    const L1 l = nx1;
+    if (k + 1 < nz) nx1 = load1(k + 1);
     if (keep_uv) {
-      stg(c.s.UA, id, ldg(c.U, id) * rPU2);
-      stg(c.s.VT, id, ldg(c.V, id) * rPVs * (T)g.sv[j]);
+      stg(c.s.UA, id, l.U * rPU2);
+      stg(c.s.VT, id, l.V * rPVs * (T)g.sv[j]);
     }
     if (asdm) {
-      const unsigned idw = i3u(g, j, k, im1), idm = i3u(g, j - 1, k, i);
-      const A aF = -chA * (A)ldg(c.aoF, id), vF = ldg(c.F, id);
-      const A aU = -chA * (A)ldg(c.aoU, id), vU = ldg(c.U, id);
-      const A aUw = -chA * (A)ldg(c.aoU, idw), vUw = ldg(c.U, idw);
-      const A aVm = -chA * (A)ldg(c.aoV, idm), vVm = ldg(c.V, idm);
-      const A aV = -chA * (A)ldg(c.aoV, id), vV = ldg(c.V, id);
+      const A aF = -chA * (A)l.aF, vF = l.F;
+      const A aU = -chA * (A)l.aU, vU = l.U;
+      const A aUw = -chA * (A)l.aUw, vUw = l.Uw;
+      const A aVm = -chA * (A)l.aVm, vVm = l.Vm;
+      const A aV = -chA * (A)l.aV, vV = l.V;
       if (k >= 1) {
         const A r0 = (A)c.f.r2d[k - 1], r1 = (A)c.f.r2d[k];
         A a = 0;
@@ -283,12 +307,11 @@ __global__ void k_f1(Ctx<T> c) {
       qF = aF; xF = vF; qU = aU; xU = vU; qUw = aUw; xUw = vUw; qVm = aVm; xVm = vVm; qV = aV; xV = vV;
     }
     if (all) {
-      const T RT = b * Fe(c, j, k, i) / P0;
+      const T RT = b * l.F / P0;
       stg(c.s.RT, id, RT);
       H += g.cl[k] * (C)RT;
     }
-    const T D = (PUa * Ue(c, j, k, pa) - PUb * Ue(c, j, k, pb)) / dx +
-                ((T)g.sv[j] * (PV0 * Ve(c, j, k, i)) - (T)g.sv[j - 1] * (PVm * Ve(c, j - 1, k, i))) / dyS;
+    const T D = (PUa * l.Ua - PUb * l.Ub) / dx + ((T)g.sv[j] * (PV0 * l.V) - (T)g.sv[j - 1] * (PVm * l.Vm)) / dyS;
     stg(c.s.D, id, D);
     S += (C)D * g.dsig[k];
     if (!asdm) stg(c.s.S, ihu(g, j, k + 1, i), (T)S);
@@ -306,20 +329,40 @@ __global__ void k_f1(Ctx<T> c) {
   const C Pt = (C)(T)Pi, rP3 = rP2c / (C)P0;
   C pre = 0, aP = 0;
   stg(c.s.SD, ihu(g, j, 0, i), T(0));
+  // the second pass's loads, one level ahead (D, R T' and the sigma-dot adjoints are this thread's
+  // own stores of the first pass)
+  struct L2 { T D, RT, U, Uw, V, Vm, asd; };
+  auto load2 = [&](int k) {
+    L2 l{};
+    const unsigned id = i3u(g, j, k, i);
+    l.D = ldg((const T*)c.s.D, id);
+    if (all) {
+      l.RT = ldg((const T*)c.s.RT, id);
+      l.U = ldg(c.U, id);
+      l.Uw = ldg(c.U, i3u(g, j, k, im1));
+      l.V = ldg(c.V, id);
+      l.Vm = ldg(c.V, i3u(g, j - 1, k, i));
+    }
+    if (asdm && k >= 1) l.asd = ldg((const T*)c.s.ASD, ihu(g, j, k, i));
+    return l;
+  };
+  L2 nx2 = load2(0);
   for (int k = 0; k < nz; ++k) {
     const unsigned id = i3u(g, j, k, i);
-    const C D = (C)ldg(c.s.D, id);
+    const L2 l = nx2;
+    if (k + 1 < nz) nx2 = load2(k + 1);
+    const C D = (C)l.D;
     if (all) {
-      const T RT = ldg(c.s.RT, id);
+      const T RT = l.RT;
       R += g.cl[k] * (C)RT;
       stg(c.s.PHI, id, (T)(H - R + g.cpk[k] * (C)RT));
-      const T zon = T(0.5) * ((Ue(c, j, k, i) / PU0) * dl0 + (Ue(c, j, k, im1) / PUm) * dlm);
-      const T mer = T(0.5) * ((Ve(c, j, k, i) / PV0) * (l1 - l0) + (Ve(c, j - 1, k, i) / PVm) * (l0 - lm)) / dyA;
+      const T zon = T(0.5) * ((l.U / PU0) * dl0 + (l.Uw / PUm) * dlm);
+      const T mer = T(0.5) * ((l.V / PV0) * (l1 - l0) + (l.Vm / PVm) * (l0 - lm)) / dyA;
       stg(c.s.WP, id, (T)(((C)zon + (C)mer) - (Sk + 0.5 * D * g.dsig[k]) / (g.sig[k] * P0s)));
     }
     if (asdm) {
       if (k >= 1) {
-        const C a = (C)ldg((const T*)c.s.ASD, ihu(g, j, k, i));
+        const C a = (C)l.asd;
         pre += -a * rP2c;
         aP += -2.0 * (g.sigh[k] * Pt - (C)(T)Sk) * rP3 * a;
       }
