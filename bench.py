@@ -110,11 +110,14 @@ def roofline(core, d, cfg, elem, reps=10):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c4_fp32.json")
+# the two launches of a forward advection stage: band tiles and, beside them, the polar tiles
+ADVECTION_LAUNCHES = ("k_stage_atile<float,256,false>", "k_stage_atile<float,256,true>")
 
 
 def traffic_from_profiles(kernel_hash, key):
-    """HBM bytes per launch of kernel `key` from the committed PMC summary, while it was taken
-    from the kernels built now (same source hash); None otherwise."""
+    """HBM bytes per launch of kernel `key` (a name, or a tuple of the launches that together make
+    one stage, summed) from the committed PMC summary, while it was taken from the kernels built now
+    (same source hash); None otherwise."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
@@ -123,8 +126,11 @@ def traffic_from_profiles(kernel_hash, key):
         return None
     if t.get("kernel_hash") != kernel_hash:
         return None
-    k = t.get("kernels", {}).get(key)
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    ks = t.get("kernels", {})
+    keys = key if isinstance(key, tuple) else (key,)
+    if any(k not in ks for k in keys):
+        return None
+    return sum(ks[k]["fetch_bytes"] + ks[k]["write_bytes"] for k in keys)
 
 
 def cpu_model():
@@ -346,10 +352,11 @@ def main():
         fwd = {"kernel": stage_name + " (adaptation stage)", "avg_launch_ms": ms["A"],
                "alg_bytes_per_launch": alg, "achieved": ach, "frac": ach / HBM_PEAK_GBS,
                "traffic": traffic_from_profiles(kh, stage_name),
-               "advection": {"kernel": "k_stage_atile<float>", "avg_launch_ms": ms["L"],
+               "advection": {"kernel": "k_stage_atile<float,256,false> (band tiles) beside "
+                                       "k_stage_atile<float,256,true> (polar tiles)", "avg_launch_ms": ms["L"],
                              "achieved": alg / (ms["L"] * 1e-3) / 1e9,
                              "frac": alg / (ms["L"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                             "traffic": traffic_from_profiles(kh, "k_stage_atile<float>")}}
+                             "traffic": traffic_from_profiles(kh, ADVECTION_LAUNCHES)}}
         # the whole bench step: every forward stage moves 8/3 states, every stage adjoint 4
         nst = 3 * (msub + 1) if adjoint else 0
         step_states = 3 * (msub + 1) * 8.0 / 3.0 + 4.0 * nst
