@@ -96,6 +96,9 @@ struct Ctx {
   const AatItem* aat = nullptr;    // work items of the tiled row-fused adaptation adjoint (NULL: per point)
   int aat_n = 0;                   // item count
   int aat_blk = 0;                 // threads per tile workgroup
+  int aat_edge_n = 0;              // > 0: aat holds rows 2..ny-2, then this many items of rows 1 and
+                                   // ny-1 (which read the pole rows' sums) for a launch of their own
+  const SideLaunch* side = nullptr;   // second stream: the pole rows' chain runs there beside k_aat
   const AatItem* adt = nullptr;    // work items of the tiled row-fused advection adjoint (NULL: per point)
   int adt_n = 0, adt_blk = 0;      // their count and workgroup size (rows with halos up to 112 columns)
   int pp_n = 0, pp_s = 0;          // with it: rows 1..pp_n and ny-pp_s..ny-1 (halos too wide for its
@@ -1587,7 +1590,7 @@ constexpr int kAatLev = 13;   // per-level LDS rows (odd: consecutive slots stri
 __host__ __device__ constexpr size_t aat_lds(int block, int elem) { return (size_t)2 * kAatLev * block * elem; }
 
 template <typename T>
-__global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat(Ctx<T> c) {
+__device__ __forceinline__ void aat_tile(const Ctx<T>& c) {
   extern __shared__ __align__(16) unsigned char smem[];
   const AatItem it = c.aat[blockIdx.x];
   if (it.j < 0) return;
@@ -1930,6 +1933,18 @@ __global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat(Ct
   }
 }
 
+// The tiles of the interior rows (all of them, or rows 2..ny-2 when rows 1 and ny-1 run apart).
+template <typename T>
+__global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat(Ctx<T> c) {
+  aat_tile<T>(c);
+}
+
+// The tiles of rows 1 and ny-1, launched after the pole rows' sums that they read.
+template <typename T>
+__global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat_edge(Ctx<T> c) {
+  aat_tile<T>(c);
+}
+
 // The base transpose of a stage applied in place: pole rows of Phi and p_s become the spread of
 // their row mean (FP64 sum), pole rows of U become 0; interior rows and V are left as they are.
 template <typename T>
@@ -1969,6 +1984,24 @@ hipError_t allow_lds_adj(size_t lds) {
 template <typename T>
 bool aar_used(const Ctx<T>& c) {
   return c.aat != nullptr && c.aat_n > 0 && c.g.ny >= 4;
+}
+
+// rows 1 and ny-1 in a launch of their own (on the side stream when the handle has one)
+template <typename T>
+bool aar_split(const Ctx<T>& c) {
+  return aar_used(c) && c.aat_edge_n > 0;
+}
+
+template <typename T>
+hipError_t launch_aar_edge(const Ctx<T>& c, hipStream_t s) {
+  const size_t lds = aat_lds(c.aat_blk, (int)sizeof(T));
+  hipError_t e = allow_lds_adj<k_aat_edge<T>>(lds);
+  if (e != hipSuccess) return e;
+  Ctx<T> ce = c;
+  ce.aat = c.aat + c.aat_n;
+  ce.aat_n = c.aat_edge_n;
+  hipLaunchKernelGGL((k_aat_edge<T>), dim3(ce.aat_n), dim3(ce.aat_blk), lds, s, ce);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -2011,6 +2044,9 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1), gcol_int(gx, ny - 1);
   const bool rows = adapt && aar_used(c);
+  // the row-fused adaptation with a second stream: the pole columns' recompute opens the pole rows'
+  // chain there (forked below, after the base transpose and the output adjoint's pole sums)
+  const bool fork = rows && aar_split(c) && c.side != nullptr;
   hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
   Ctx<T> cf = c;
   cf.jr0 = 1;
@@ -2018,8 +2054,10 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   cf.fwd_all = adapt ? 1 : 0;
   // the row-fused kernel recomputes its rows itself (and writes what the pole rows read)
   if (!rows) hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, cf);
-  hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
-  hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, s, c);
+  if (!fork) {
+    hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
+    hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, s, c);
+  }
   if (c.abU && !c.base_in_tail) {
     // interior rows' base transpose is folded into the row-fused kernels (the adaptation's and the
     // advection's, for their rows) or the column tail (advection with one accumulator); V row 1/2
@@ -2039,6 +2077,13 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   else
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
                        c.s.psum + PS_AOF * 2 * (nz + 1));
+  if (fork) {
+    hipError_t e = hipEventRecord(c.side->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c.side->s, c.side->fork, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, c.side->s, c);
+    hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, c.side->s, c);
+  }
   // (process-specific part is launched by the caller between these two groups)
   return hipGetLastError();
 }
@@ -2052,22 +2097,35 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
   const int gx64 = (nx + 63) / 64;   // column kernels: 64 columns x kLG level groups
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1);
   if (aar_used(c)) {
-    // pole rows through the per-point kernels, interior rows row-fused
+    // pole rows through the per-point kernels, interior rows row-fused.  With the rows split and a
+    // second stream, the pole rows' chain (with rows 1 and ny-1, which read the pole rows' sums and
+    // write what the pole rows' gathers read) runs there beside the other rows' launch: the two touch
+    // disjoint rows of every output and scratch field, and every read-modify-write of a pole row
+    // (base spread, input adjoint) is on the chain or came before the fork.
+    const bool split = aar_split(c);
+    const bool fork = split && c.side != nullptr;
+    const hipStream_t ps = fork ? c.side->s : s;
+    hipError_t e = hipSuccess;
+    if (fork && (e = launch_aar<T>(c, s)) != hipSuccess) return e;
     Ctx<T> cp = c;
     cp.jr0 = 0;
     cp.jrs = ny;
     cp.parts = 1;   // scalar points of the pole rows (their sums feed the interior rows)
-    hipLaunchKernelGGL((k_a12<T, 6, 1>), dim3(gx, 2), dim3(tb), 0, s, cp);
-    hipLaunchKernelGGL((k_pole_sum2<T>), dim3(4 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
+    hipLaunchKernelGGL((k_a12<T, 6, 1>), dim3(gx, 2), dim3(tb), 0, ps, cp);
+    hipLaunchKernelGGL((k_pole_sum2<T>), dim3(4 * (nz + 1)), dim3(64), 0, ps, g, (const T*)c.s.AD,
                        c.s.psum + PS_AD * 2 * (nz + 1), (const T*)c.s.AVGL, c.s.psum + PS_AVGL * 2 * (nz + 1));
-    const hipError_t e = launch_aar<T>(c, s);
-    if (e != hipSuccess) return e;
+    if (!fork && (e = launch_aar<T>(c, s)) != hipSuccess) return e;
+    if (split && (e = launch_aar_edge<T>(c, ps)) != hipSuccess) return e;
     Ctx<T> cv = c;   // V row 1/2: reads phi' and R T' of row 1, written by the row-fused kernel
     cv.parts = 4;
-    hipLaunchKernelGGL((k_a1lev<T>), dim3(gx, nz, 1), dim3(tb), 0, s, cv);
+    hipLaunchKernelGGL((k_a1lev<T>), dim3(gx, nz, 1), dim3(tb), 0, ps, cv);
     cp.parts = 7;
-    hipLaunchKernelGGL((k_a3t1<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
-    hipLaunchKernelGGL((k_a4<T>), dim3(gx64, 2), dim3(64, kLG), 0, s, cp);
+    hipLaunchKernelGGL((k_a3t1<T>), dim3(gx, nz, 2), dim3(tb), 0, ps, cp);
+    hipLaunchKernelGGL((k_a4<T>), dim3(gx64, 2), dim3(64, kLG), 0, ps, cp);
+    if (fork) {
+      if ((e = hipEventRecord(c.side->join, ps)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, c.side->join, 0)) != hipSuccess) return e;
+    }
   } else {
     hipLaunchKernelGGL((k_a12<T, 1, 0>), g2, dim3(tb), 0, s, c);
     hipLaunchKernelGGL((k_pole_sum2<T>), dim3(4 * (nz + 1)), dim3(64), 0, s, g, (const T*)c.s.AD,
@@ -2223,6 +2281,8 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.aat = v.aat;
   c.aat_n = v.aat_n;
   c.aat_blk = v.aat_block;
+  c.aat_edge_n = v.aat_edge_n;
+  c.side = v.side;
   c.adt = v.adt;
   c.adt_n = v.adt_n;
   c.adt_blk = v.adt_block;

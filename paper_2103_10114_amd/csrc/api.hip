@@ -72,7 +72,7 @@ struct dycore_s {
   void* adj = nullptr;          // adjoint workspace
   size_t adj_bytes = 0;
   AatItem* aat = nullptr;       // work items of the tiled adaptation-stage adjoint (device)
-  int aat_n = 0, aat_block = 0;
+  int aat_n = 0, aat_block = 0, aat_edge_n = 0;   // aat_edge_n: rows 1 and ny-1 after the others
   AatItem* adt = nullptr;       // work items of the tiled advection-stage adjoint (device)
   int adt_n = 0, adt_block = 0;
   int adt_pp_n = 0, adt_pp_s = 0;   // interior rows at each end that run the per-point kernels
@@ -527,6 +527,7 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.aat = h->aat;
   v.aat_n = h->aat_n;
   v.aat_block = h->aat_block;
+  v.aat_edge_n = h->aat_edge_n;
   v.adt = h->adt;
   v.adt_n = h->adt_n;
   v.adt_block = h->adt_block;
@@ -722,12 +723,6 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       h->pblock = pblock;
       h->bytes += sizeof(AatItem) * nall;
     }
-    // the band tiles run beside the polar launch on a second stream (default priority)
-    if (ok && h->nptiles > 0) {
-      ok = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking) == hipSuccess;
-      ok = ok && hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming) == hipSuccess;
-      ok = ok && hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming) == hipSuccess;
-    }
   }
   if (ok && !(h->flags & DYCORE_FORWARD_ONLY)) {
     h->adj_bytes = dyc_adjoint_workspace_bytes(h);
@@ -735,11 +730,23 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
     std::vector<AatItem> items;
     int blk = 0;
     if (ok && aat_items(nx, ny, h->M, items, blk)) {
+      // rows 2..ny-2, then rows 1 and ny-1 (at the same block), which read the pole rows' sums and
+      // so launch after them: the pole rows' chain then runs beside the others' launch
+      std::vector<AatItem> mi, ei;
+      const std::vector<int> hl = adapt_halos(h->M);
+      int nmain = (int)items.size(), nedge = 0;
+      if (zonal_tiles(nx, row_range(2, ny - 2), hl, blk, mi) && zonal_tiles(nx, {1, ny - 1}, hl, blk, ei)) {
+        nmain = (int)mi.size();
+        nedge = (int)ei.size();
+        items = mi;
+        items.insert(items.end(), ei.begin(), ei.end());
+      }
       ok = hipMalloc((void**)&h->aat, sizeof(AatItem) * items.size()) == hipSuccess;
       ok = ok && hipMemcpy(h->aat, items.data(), sizeof(AatItem) * items.size(), hipMemcpyHostToDevice) ==
                      hipSuccess;
       if (ok) {
-        h->aat_n = (int)items.size();
+        h->aat_n = nmain;
+        h->aat_edge_n = nedge;
         h->aat_block = blk;
         h->adj_bytes += sizeof(AatItem) * items.size();
       }
@@ -757,6 +764,13 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
         h->adj_bytes += sizeof(AatItem) * at.size();
       }
     }
+  }
+  // a second stream (default priority): the forward advection's band tiles run there beside its
+  // polar tiles, the adaptation adjoint's pole-row chain beside its row-fused launch
+  if (ok && (h->nptiles > 0 || h->aat_edge_n > 0)) {
+    ok = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming) == hipSuccess;
   }
   if (ok && (h->flags & DYCORE_LOWLAT_FILTERS)) {
     const std::vector<FiltItem> fi = filter_items(ny);

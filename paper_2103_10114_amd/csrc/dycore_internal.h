@@ -90,9 +90,10 @@ struct StageArgs {
   int pblock;
 };
 
-// A second stream for a launch that overlaps another of the same stage (the advection's band tiles
-// run there beside its polar tiles): the stage's stream forks to it and joins it again through the
-// two events (default priority).
+// A second stream for launches that overlap another of the same stage (the advection's band tiles
+// run there beside its polar tiles; the adaptation adjoint's pole-row chain beside its row-fused
+// launch): the stage's stream forks to it and joins it again through the two events (default
+// priority).
 struct SideLaunch {
   hipStream_t s;
   hipEvent_t fork, join;
@@ -236,6 +237,7 @@ struct HandleView {
   const AatItem* aat;   // tiled adaptation-adjoint work items (device), or NULL when rows do not fit
   int aat_n;            // item count (a multiple of 8)
   int aat_block;        // threads per tile workgroup
+  int aat_edge_n;       // > 0: aat holds rows 2..ny-2, then this many items of rows 1 and ny-1
   const AatItem* adt;   // tiled advection-adjoint work items (device), or NULL: per-point kernels
   int adt_n, adt_block; // their count (a multiple of 8) and workgroup size (up to 256)
   int adt_pp_n, adt_pp_s; // rows 1..pp_n and ny-pp_s..ny-1 go with the pole rows (per point)
@@ -247,7 +249,7 @@ struct HandleView {
   int natiles, ablock, awide;
   const AatItem* ptiles; // its polar tiles (larger workgroups), NULL when none
   int nptiles, pblock;
-  const SideLaunch* side; // the second stream: the band tiles run there beside the polar launch
+  const SideLaunch* side; // second stream: the advection's band tiles, the adaptation adjoint's pole chain
   double* cap;           // cap sums of the forward adaptation stage (device, 4 nz doubles)
 };
 HandleView view_of(const dycore_s* h);
