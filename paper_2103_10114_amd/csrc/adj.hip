@@ -2029,6 +2029,14 @@ bool adt_used(const Ctx<T>& c) {
   return c.adt != nullptr && c.adt_n > 0;
 }
 
+// With the rows next to the poles in the per-point set (pp_n, pp_s >= 1) the tiles read nothing of
+// the pole rows' chain but the output adjoint's pole sums, so that chain can run on the second stream
+// beside them.
+template <typename T>
+bool adt_fork(const Ctx<T>& c) {
+  return adt_used(c) && c.side != nullptr && c.pp_n >= 1 && c.pp_s >= 1;
+}
+
 template <typename T>
 hipError_t launch_adt(const Ctx<T>& c, hipStream_t s) {
   const size_t lds = adt_lds(c.adt_blk, (int)sizeof(T));
@@ -2044,9 +2052,9 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1), gcol_int(gx, ny - 1);
   const bool rows = adapt && aar_used(c);
-  // the row-fused adaptation with a second stream: the pole columns' recompute opens the pole rows'
-  // chain there (forked below, after the base transpose and the output adjoint's pole sums)
-  const bool fork = rows && aar_split(c) && c.side != nullptr;
+  // the row-fused stage adjoints with a second stream: the pole columns' recompute opens the pole
+  // rows' chain there (forked below, after the base transpose and the output adjoint's pole sums)
+  const bool fork = adapt ? rows && aar_split(c) && c.side != nullptr : adt_fork(c);
   hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
   Ctx<T> cf = c;
   cf.jr0 = 1;
@@ -2151,6 +2159,28 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
   Ctx<T> cp = c;
   cp.jr0 = 0;
   cp.jrs = ny;
+  if (adt_fork(c)) {
+    // the tiles on the stage's stream; beside them on the second stream (forked with the pole
+    // columns' recompute) the pole rows and the rows next to them through the per-point kernels: the
+    // two touch disjoint rows of every output and scratch field
+    const hipStream_t ps = c.side->s;
+    Ctx<T> cw = c;
+    cw.rsplit = c.pp_n + 1;
+    const int nw = c.pp_n + c.pp_s + 2;
+    hipError_t e = launch_adt<T>(c, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_uv<T>), dim3(gx, nz, 2), dim3(tb), 0, ps, cp);
+    hipLaunchKernelGGL((k_l1<T>), dim3(gx, nz, nw), dim3(tb), 0, ps, cw);
+    hipLaunchKernelGGL((k_l2<T>), dim3(gx, 2), dim3(tb), 0, ps, cp);
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, ps, g, (const T*)c.s.AD,
+                       (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
+    hipLaunchKernelGGL((k_l3<T>), dim3(gx64, nw), dim3(64, kLG), 0, ps, cw);
+    if ((e = hipEventRecord(c.side->join, ps)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, c.side->join, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
+    hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_uv<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
   if (adt_used(c)) {
     // the pole rows and the rows next to them whose halos do not fit the tiles (rows 0..pp_n and
