@@ -766,11 +766,14 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
     }
   }
   // a second stream (default priority): the forward advection's band tiles run there beside its
-  // polar tiles, the adaptation adjoint's pole-row chain beside its row-fused launch
+  // polar tiles, the adaptation adjoint's pole-row chain beside its row-fused launch.  The fork and
+  // join events order work of one device: they need no system-scope fence (the host never waits on
+  // them), which would write back and invalidate the caches at every fork and join.
   if (ok && (h->nptiles > 0 || h->aat_edge_n > 0)) {
+    const unsigned ef = hipEventDisableTiming | hipEventDisableSystemFence;
     ok = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->side.fork, ef) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->side.join, ef) == hipSuccess;
   }
   if (ok && (h->flags & DYCORE_LOWLAT_FILTERS)) {
     const std::vector<FiltItem> fi = filter_items(ny);
