@@ -2052,8 +2052,10 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   const int gx = (nx + tb - 1) / tb;
   const dim3 g3(gx, nz, ny + 1), g2(gx, ny + 1), gcol_int(gx, ny - 1);
   const bool rows = adapt && aar_used(c);
-  // the row-fused stage adjoints with a second stream: the pole columns' recompute opens the pole
-  // rows' chain there (forked below, after the base transpose and the output adjoint's pole sums)
+  // the row-fused stage adjoints with a second stream: the work on the pole rows and the per-point
+  // rows (pole-column recompute, their base transpose, the output adjoint's pole sums) opens the pole
+  // rows' chain there, forked once the full-grid recompute is done; the row-fused launch that follows
+  // on this stream reads none of it
   const bool fork = adapt ? rows && aar_split(c) && c.side != nullptr : adt_fork(c);
   hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
   Ctx<T> cf = c;
@@ -2062,36 +2064,34 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   cf.fwd_all = adapt ? 1 : 0;
   // the row-fused kernel recomputes its rows itself (and writes what the pole rows read)
   if (!rows) hipLaunchKernelGGL((k_f1<T>), gcol_int, dim3(tb), 0, s, cf);
-  if (!fork) {
-    hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, s, c);
-    hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, s, c);
+  hipStream_t es = s;
+  if (fork) {
+    hipError_t e = hipEventRecord(c.side->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c.side->s, c.side->fork, 0);
+    if (e != hipSuccess) return e;
+    es = c.side->s;
   }
+  hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, es, c);
+  hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, es, c);
   if (c.abU && !c.base_in_tail) {
     // interior rows' base transpose is folded into the row-fused kernels (the adaptation's and the
     // advection's, for their rows) or the column tail (advection with one accumulator); V row 1/2
     // stays here for the row-fused adaptation, the per-point rows for the row-fused advection
     if (rows) {
-      hipLaunchKernelGGL((k_base<T>), dim3(gx, nz, 1), dim3(tb), 0, s, c);
+      hipLaunchKernelGGL((k_base<T>), dim3(gx, nz, 1), dim3(tb), 0, es, c);
     } else if (!adapt && adt_used(c)) {
       Ctx<T> cw = c;
       cw.rsplit = c.pp_n + 1;
-      hipLaunchKernelGGL((k_base<T>), dim3(gx, nz, c.pp_n + c.pp_s + 2), dim3(tb), 0, s, cw);
+      hipLaunchKernelGGL((k_base<T>), dim3(gx, nz, c.pp_n + c.pp_s + 2), dim3(tb), 0, es, cw);
     } else {
-      hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, s, c);
+      hipLaunchKernelGGL((k_base<T>), g3, dim3(tb), 0, es, c);
     }
   }
   if (c.abU)
-    hipLaunchKernelGGL((k_pole_sum_base<T>), dim3(2 * (nz + 1)), dim3(256), 0, s, c);
+    hipLaunchKernelGGL((k_pole_sum_base<T>), dim3(2 * (nz + 1)), dim3(256), 0, es, c);
   else
-    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, s, g, c.aoF, c.aoP,
+    hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, es, g, c.aoF, c.aoP,
                        c.s.psum + PS_AOF * 2 * (nz + 1));
-  if (fork) {
-    hipError_t e = hipEventRecord(c.side->fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(c.side->s, c.side->fork, 0);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_f1p_red<T>), dim3(nz, 2), dim3(256), 0, c.side->s, c);
-    hipLaunchKernelGGL((k_f1p<T>), dim3(nz, 2), dim3(256), 0, c.side->s, c);
-  }
   // (process-specific part is launched by the caller between these two groups)
   return hipGetLastError();
 }
