@@ -1197,11 +1197,11 @@ __global__ void __launch_bounds__(64 * kLG) k_l3(Ctx<T> c) {
   }
 }
 
-// 2D: staggered P, the leaped d+ transposes for l and q, then p_s
+// 2D: staggered P, the leaped d+ transposes for l and q, then p_s (rows jr0 + jrs * blockIdx.y)
 template <typename T>
 __global__ void k_t3(Ctx<T> c) {
   const GeoDev& g = c.g;
-  const int j = blockIdx.y;
+  const int j = c.jr0 + c.jrs * (int)blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nx) return;
   const int nx = g.nx, ny = g.ny;
@@ -2131,8 +2131,21 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
     hipLaunchKernelGGL((k_a3t1<T>), dim3(gx, nz, 2), dim3(tb), 0, ps, cp);
     hipLaunchKernelGGL((k_a4<T>), dim3(gx64, 2), dim3(64, kLG), 0, ps, cp);
     if (fork) {
+      // without D_sa the pole rows' p_s transpose and the spread of the pole-copy sums read only the
+      // chain's results: they close it, and this stream takes rows 1..ny-1 of k_t3 after the join
+      if (g.kstar == 0.0) {
+        hipLaunchKernelGGL((k_t3<T>), dim3(gx, 2), dim3(tb), 0, ps, cp);   // rows 0 and ny
+        hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, ps, c);
+      }
       if ((e = hipEventRecord(c.side->join, ps)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(s, c.side->join, 0)) != hipSuccess) return e;
+      if (g.kstar == 0.0) {
+        Ctx<T> ci = c;
+        ci.jr0 = 1;
+        ci.jrs = 1;
+        hipLaunchKernelGGL((k_t3<T>), dim3(gx, ny - 1), dim3(tb), 0, s, ci);
+        return hipGetLastError();
+      }
     }
   } else {
     hipLaunchKernelGGL((k_a12<T, 1, 0>), g2, dim3(tb), 0, s, c);
@@ -2175,10 +2188,15 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
     hipLaunchKernelGGL((k_pole_sum<T>), dim3(2 * (nz + 1)), dim3(64), 0, ps, g, (const T*)c.s.AD,
                        (const T*)nullptr, c.s.psum + PS_AD * 2 * (nz + 1));
     hipLaunchKernelGGL((k_l3<T>), dim3(gx64, nw), dim3(64, kLG), 0, ps, cw);
+    // the pole rows' p_s transpose and the spread of the pole-copy sums read only the chain's results
+    hipLaunchKernelGGL((k_t3<T>), dim3(gx, 2), dim3(tb), 0, ps, cp);
+    hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, ps, c);
     if ((e = hipEventRecord(c.side->join, ps)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s, c.side->join, 0)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_t3<T>), g2, dim3(tb), 0, s, c);
-    hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, s, c);
+    Ctx<T> ci = c;
+    ci.jr0 = 1;
+    ci.jrs = 1;
+    hipLaunchKernelGGL((k_t3<T>), dim3(gx, ny - 1), dim3(tb), 0, s, ci);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_uv<T>), dim3(gx, nz, 2), dim3(tb), 0, s, cp);
