@@ -2330,7 +2330,7 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.aat_n = v.aat_n;
   c.aat_blk = v.aat_block;
   c.aat_edge_n = v.aat_edge_n;
-  c.side = v.side;
+  c.side = v.adj_side;
   c.adt = v.adt;
   c.adt_n = v.adt_n;
   c.adt_blk = v.adt_block;

@@ -546,6 +546,8 @@ dyc::HandleView dyc::view_of(const dycore_s* h) {
   v.nptiles = h->nptiles;
   v.pblock = h->pblock;
   v.side = h->side.s ? &h->side : nullptr;
+  v.adj_side = h->side.s && !(h->flags & DYCORE_FORWARD_ONLY) &&
+                       (size_t)h->nx * h->ny * h->nz >= kAdjOverlapPoints ? &h->side : nullptr;
   v.cap = h->cap;
   return v;
 }
@@ -735,7 +737,9 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       std::vector<AatItem> mi, ei;
       const std::vector<int> hl = adapt_halos(h->M);
       int nmain = (int)items.size(), nedge = 0;
-      if (zonal_tiles(nx, row_range(2, ny - 2), hl, blk, mi) && zonal_tiles(nx, {1, ny - 1}, hl, blk, ei)) {
+      const bool overlap = (size_t)nx * ny * nz >= kAdjOverlapPoints;
+      if (overlap && zonal_tiles(nx, row_range(2, ny - 2), hl, blk, mi) &&
+          zonal_tiles(nx, {1, ny - 1}, hl, blk, ei)) {
         nmain = (int)mi.size();
         nedge = (int)ei.size();
         items = mi;
@@ -769,7 +773,8 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   // polar tiles, the adaptation adjoint's pole-row chain beside its row-fused launch.  The fork and
   // join events order work of one device: they need no system-scope fence (the host never waits on
   // them), which would write back and invalidate the caches at every fork and join.
-  if (ok && (h->nptiles > 0 || h->aat_edge_n > 0)) {
+  if (ok && (h->nptiles > 0 || h->aat_edge_n > 0 ||
+             (!(h->flags & DYCORE_FORWARD_ONLY) && (size_t)nx * ny * nz >= kAdjOverlapPoints))) {
     const unsigned ef = hipEventDisableTiming | hipEventDisableSystemFence;
     ok = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&h->side.fork, ef) == hipSuccess;

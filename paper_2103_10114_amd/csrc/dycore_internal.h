@@ -60,6 +60,9 @@ struct AatItem {
   int j, i0, w, hl;
 };
 constexpr int kMaxLevels = 128;         // most model levels a handle takes
+// Grids of at least this many points run the stage adjoints' pole-row chains beside their row-fused
+// launches (on smaller grids a fork and join cost more than the chain they would hide).
+constexpr size_t kAdjOverlapPoints = size_t(1) << 24;
 constexpr int kAatMaxBlock = 320;       // adjoint tiles
 constexpr int kFwdTileMaxBlock = 1024;  // forward adaptation tiles
 constexpr int kBatchMaxBlock = 512;     // the persistent batched stage (its VGPR budget: 256)
@@ -249,7 +252,8 @@ struct HandleView {
   int natiles, ablock, awide;
   const AatItem* ptiles; // its polar tiles (larger workgroups), NULL when none
   int nptiles, pblock;
-  const SideLaunch* side; // second stream: the advection's band tiles, the adaptation adjoint's pole chain
+  const SideLaunch* side; // second stream: the forward advection's band tiles beside its polar tiles
+  const SideLaunch* adj_side; // the same stream for the stage adjoints' pole-row chains (NULL: serial)
   double* cap;           // cap sums of the forward adaptation stage (device, 4 nz doubles)
 };
 HandleView view_of(const dycore_s* h);
