@@ -48,12 +48,16 @@ typedef enum { DYCORE_FP32 = 0, DYCORE_FP64 = 1 } dycore_precision;
 
 enum {
   DYCORE_FORWARD_ONLY = 1u,   /* do not reserve adjoint workspace at create */
-  DYCORE_LOWLAT_FILTERS = 2u  /* close every outer step with the low-latitude filters the leap format
+  DYCORE_LOWLAT_FILTERS = 2u, /* close every outer step with the low-latitude filters the leap format
                                  keeps (Sec. III-B, Table IV rows 1-2): below 38 degrees the
                                  simplified filter removes the 2-dlam wave of each zonal row, from 38
                                  to 70 degrees the 3-point operator F + r (F_{x-1} - 2F + F_{x+1})
                                  with r = (1 - cos(lat)/cos 38deg)/4; on U, V, Phi and p_s, pole rows
                                  untouched.  Needs an even nx (EINVAL otherwise). */
+  DYCORE_SINGLE_STREAM = 4u   /* run every launch on the caller's stream: no second stream, so the
+                                 advection's polar tiles and the stage adjoints' pole-row chains run
+                                 before and after the other tiles instead of beside them.  Results are
+                                 bitwise the same; only the schedule differs. */
 };
 
 typedef struct {
@@ -68,7 +72,7 @@ typedef struct {
   const double* phis;      /* host, (ny+1)*nx surface geopotential (m^2/s^2), copied; NULL = flat */
   double a, omega, g, rd, cp, p0, t0;  /* constants; 0 selects 6.371e6, 7.292e-5, 9.80616,
                                           287.04, 1004.64, 1e5, 300 */
-  unsigned flags;          /* DYCORE_FORWARD_ONLY | DYCORE_LOWLAT_FILTERS */
+  unsigned flags;          /* DYCORE_FORWARD_ONLY | DYCORE_LOWLAT_FILTERS | DYCORE_SINGLE_STREAM */
   int block;               /* threads per workgroup of the tiled advection stage (64..1024, multiple of
                               64; sizes above 256 run as 256); 0 = 256.  Results do not depend on it. */
   double kappa_star;       /* kappa* of eq. 1's p_s line (m^2/s, >= 0; 0 = off): the adaptation's p_s

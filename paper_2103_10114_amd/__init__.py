@@ -20,6 +20,7 @@ _lib = None
 DYCORE_FP32, DYCORE_FP64 = 0, 1
 DYCORE_FORWARD_ONLY = 1
 DYCORE_LOWLAT_FILTERS = 2
+DYCORE_SINGLE_STREAM = 4
 KEYS = ("U", "V", "Phi", "ps")
 
 
@@ -97,7 +98,7 @@ class Dycore:
     """One grid (nx longitudes, ny latitude intervals, nz levels) and time step dt."""
 
     def __init__(self, nx, ny, nz, dt, prec="fp32", phis=None, msub=0, block=0, forward_only=False,
-                 sigma_half=None, filters=False, kappa_star=0.0):
+                 sigma_half=None, filters=False, kappa_star=0.0, single_stream=False):
         import numpy as np
         import torch
         self.nx, self.ny, self.nz, self.dt = nx, ny, nz, float(dt)
@@ -112,7 +113,8 @@ class Dycore:
         dp = ctypes.POINTER(ctypes.c_double)
         c.phis = self._phis.ctypes.data_as(dp) if self._phis is not None else None
         c.sigma_half = self._sig.ctypes.data_as(dp) if self._sig is not None else None
-        c.flags = (DYCORE_FORWARD_ONLY if forward_only else 0) | (DYCORE_LOWLAT_FILTERS if filters else 0)
+        c.flags = ((DYCORE_FORWARD_ONLY if forward_only else 0) | (DYCORE_LOWLAT_FILTERS if filters else 0) |
+                   (DYCORE_SINGLE_STREAM if single_stream else 0))
         c.block = int(block)
         c.kappa_star = float(kappa_star)
         h = ctypes.c_void_p()

@@ -737,7 +737,7 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
       std::vector<AatItem> mi, ei;
       const std::vector<int> hl = adapt_halos(h->M);
       int nmain = (int)items.size(), nedge = 0;
-      const bool overlap = (size_t)nx * ny * nz >= kAdjOverlapPoints;
+      const bool overlap = !(h->flags & DYCORE_SINGLE_STREAM) && (size_t)nx * ny * nz >= kAdjOverlapPoints;
       if (overlap && zonal_tiles(nx, row_range(2, ny - 2), hl, blk, mi) &&
           zonal_tiles(nx, {1, ny - 1}, hl, blk, ei)) {
         nmain = (int)mi.size();
@@ -773,8 +773,8 @@ int dycore_create(const dycore_config* cfg, dycore_t* out) {
   // polar tiles, the adaptation adjoint's pole-row chain beside its row-fused launch.  The fork and
   // join events order work of one device: they need no system-scope fence (the host never waits on
   // them), which would write back and invalidate the caches at every fork and join.
-  if (ok && (h->nptiles > 0 || h->aat_edge_n > 0 ||
-             (!(h->flags & DYCORE_FORWARD_ONLY) && (size_t)nx * ny * nz >= kAdjOverlapPoints))) {
+  if (ok && !(h->flags & DYCORE_SINGLE_STREAM) &&
+      (h->nptiles > 0 || (!(h->flags & DYCORE_FORWARD_ONLY) && (size_t)nx * ny * nz >= kAdjOverlapPoints))) {
     const unsigned ef = hipEventDisableTiming | hipEventDisableSystemFence;
     ok = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&h->side.fork, ef) == hipSuccess;

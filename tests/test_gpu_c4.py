@@ -164,3 +164,43 @@ def test_c4_recorded_step_fp32():
     for k in KEYS:
         assert torch.isfinite(l1[k]).all(), k
         assert torch.equal(l1[k], l2_[k]), k
+
+
+def test_c4_single_stream_bitwise():
+    """At C4 the advection's polar tiles and the stage adjoints' pole-row chains run on a second
+    stream beside the other tiles; a DYCORE_SINGLE_STREAM handle runs the same launches one after
+    another on the caller's stream.  The recorded forward step, its adjoint and one stage adjoint of
+    each process agree bit for bit between the two schedules."""
+    from paper_2103_10114_amd import Dycore
+    c = _case()
+    cfg = c["cfg"]
+    core = _core("fp32")
+    one = Dycore(cfg.nx, cfg.ny, cfg.nz, cfg.dt, prec="fp32", phis=c["st"]["phis"], single_stream=True)
+    try:
+        print("C4 fp32: two streams vs one stream", flush=True)
+        outs = []
+        for h in (core, one):
+            d = h.to_device(c["st32"])
+            h.step_record(d)
+            lam = h.to_device(c["ao32"])
+            h.step_adjoint_recorded(lam)
+            st_adj = {}
+            for process in ("A", "L"):
+                s = h.to_device(c["st32"])
+                a = h.to_device(c["ao32"])
+                ab = {k: torch.zeros_like(v) for k, v in s.items()}
+                ai = {k: torch.zeros_like(v) for k, v in s.items()}
+                h.stage_adjoint(process, c["ch"][process], s, a, ab, ai)
+                st_adj[process] = (ab, ai)
+            torch.cuda.synchronize()
+            outs.append((d, lam, st_adj))
+        (d0, l0, s0), (d1, l1, s1) = outs
+        for k in KEYS:
+            assert torch.equal(d0[k], d1[k]), ("forward", k)
+            assert torch.isfinite(l0[k]).all(), k
+            assert torch.equal(l0[k], l1[k]), ("step adjoint", k)
+            for process in ("A", "L"):
+                for part in (0, 1):
+                    assert torch.equal(s0[process][part][k], s1[process][part][k]), (process, part, k)
+    finally:
+        one.close()
