@@ -204,3 +204,37 @@ def test_c4_single_stream_bitwise():
                     assert torch.equal(s0[process][part][k], s1[process][part][k]), (process, part, k)
     finally:
         one.close()
+
+
+def test_c4_step_adjoint_graph_replay():
+    """The step adjoint at C4 (its stage adjoints fork the pole rows' chains to the handle's second
+    stream and join them) captured in a hipGraph: two replays, with an eager adjoint between them,
+    equal the eager adjoint bit for bit."""
+    c = _case()
+    core = _core("fp32")
+    y0 = core.to_device(c["st32"])
+    lam0 = core.to_device(c["ao32"])
+    ref = {k: v.clone() for k, v in lam0.items()}
+    core.step_adjoint(y0, ref)
+    torch.cuda.synchronize()
+    lam = {k: v.clone() for k, v in lam0.items()}
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    print("C4 fp32 step adjoint: capture", flush=True)
+    with torch.cuda.graph(graph, stream=stream):
+        core.step_adjoint(y0, lam)
+    for rep in range(2):
+        for k in KEYS:
+            lam[k].copy_(lam0[k])
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        print(f"  replay {rep}", flush=True)
+        for k in KEYS:
+            assert torch.equal(lam[k], ref[k]), (rep, k)
+        eager = {k: v.clone() for k, v in lam0.items()}
+        core.step_adjoint(y0, eager)
+        torch.cuda.synchronize()
+        for k in KEYS:
+            assert torch.equal(eager[k], ref[k]), (rep, "eager", k)
+    del graph
