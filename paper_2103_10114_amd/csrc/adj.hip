@@ -99,6 +99,10 @@ struct Ctx {
   int aat_edge_n = 0;              // > 0: aat holds rows 2..ny-2, then this many items of rows 1 and
                                    // ny-1 (which read the pole rows' sums) for a launch of their own
   const SideLaunch* side = nullptr;   // second stream: the pole rows' chain runs there beside k_aat
+  int f2d_ready = 0;               // s.P, L, Q, DL, DQ already hold this stage's 2D recompute
+  const T* next_ps = nullptr;      // non-NULL: the chain ends with the next stage's 2D recompute (p_s
+  const double* next_pin = nullptr;   // and pole values of its input) into the other set, next2d
+  T* next2d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   const AatItem* adt = nullptr;    // work items of the tiled row-fused advection adjoint (NULL: per point)
   int adt_n = 0, adt_blk = 0;      // their count and workgroup size (rows with halos up to 112 columns)
   int pp_n = 0, pp_s = 0;          // with it: rows 1..pp_n and ny-pp_s..ny-1 (halos too wide for its
@@ -2037,6 +2041,20 @@ bool adt_fork(const Ctx<T>& c) {
   return adt_used(c) && c.side != nullptr && c.pp_n >= 1 && c.pp_s >= 1;
 }
 
+// The next stage's 2D recompute (P, l, q and the leaped d+l, d+q of its input) into the other set of
+// 2D fields, launched at the end of this stage's pole-row chain: it reads only the recorded input,
+// and the set it writes is free (this stage reads the other one).
+template <typename T>
+void launch_f2d_next(const Ctx<T>& c, hipStream_t s) {
+  if (!c.next_ps) return;
+  Ctx<T> cn = c;
+  cn.P = c.next_ps;
+  cn.pin = c.next_pin;
+  cn.s.P = c.next2d[0]; cn.s.L = c.next2d[1]; cn.s.Q = c.next2d[2]; cn.s.DL = c.next2d[3]; cn.s.DQ = c.next2d[4];
+  const int gx = (c.g.nx + 255) / 256;
+  hipLaunchKernelGGL((k_f2d<T>), dim3(gx, c.g.ny + 1), dim3(256), 0, s, cn);
+}
+
 template <typename T>
 hipError_t launch_adt(const Ctx<T>& c, hipStream_t s) {
   const size_t lds = adt_lds(c.adt_blk, (int)sizeof(T));
@@ -2057,7 +2075,7 @@ hipError_t run_stage_adjoint(const Ctx<T>& c, hipStream_t s, bool adapt) {
   // rows' chain there, forked once the full-grid recompute is done; the row-fused launch that follows
   // on this stream reads none of it
   const bool fork = adapt ? rows && aar_split(c) && c.side != nullptr : adt_fork(c);
-  hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
+  if (!c.f2d_ready) hipLaunchKernelGGL((k_f2d<T>), g2, dim3(tb), 0, s, c);
   Ctx<T> cf = c;
   cf.jr0 = 1;
   cf.jrs = 1;
@@ -2137,6 +2155,7 @@ hipError_t run_adapt(const Ctx<T>& c, hipStream_t s) {
         hipLaunchKernelGGL((k_t3<T>), dim3(gx, 2), dim3(tb), 0, ps, cp);   // rows 0 and ny
         hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, ps, c);
       }
+      launch_f2d_next<T>(c, ps);
       if ((e = hipEventRecord(c.side->join, ps)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(s, c.side->join, 0)) != hipSuccess) return e;
       if (g.kstar == 0.0) {
@@ -2191,6 +2210,7 @@ hipError_t run_advect(const Ctx<T>& c, hipStream_t s) {
     // the pole rows' p_s transpose and the spread of the pole-copy sums read only the chain's results
     hipLaunchKernelGGL((k_t3<T>), dim3(gx, 2), dim3(tb), 0, ps, cp);
     hipLaunchKernelGGL((k_t4<T>), dim3(nz + 1, 2), dim3(256), 0, ps, c);
+    launch_f2d_next<T>(c, ps);
     if ((e = hipEventRecord(c.side->join, ps)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s, c.side->join, 0)) != hipSuccess) return e;
     Ctx<T> ci = c;
@@ -2238,7 +2258,7 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
 constexpr int kN3 = 27;   // 3D scalar-size scratch fields (4 forward + 23 adjoint)
 constexpr int kNH = 3;    // half-level fields
-constexpr int kN2T = 5;   // 2D T fields
+constexpr int kN2T = 10;  // 2D T fields: two sets of P, l, q, d+l, d+q (a stage's and the next one's)
 constexpr int kN2D = 8;   // 2D FP64 fields
 
 struct Layout {
@@ -2269,7 +2289,7 @@ Layout layout(const HandleView& v) {
 }
 
 template <typename T>
-Scr<T> scratch_of(const HandleView& v) {
+Scr<T> scratch_of(const HandleView& v, int set = 0) {
   const Layout L = layout(v);
   char* base = static_cast<char*>(v.adj);
   Scr<T> s;
@@ -2286,7 +2306,8 @@ Scr<T> scratch_of(const HandleView& v) {
   s.S = fh[0]; s.SD = fh[1]; s.ASD = fh[2];
   T* f2[kN2T];
   for (int q = 0; q < kN2T; ++q) f2[q] = reinterpret_cast<T*>(base + L.f2t_off + q * a256(L.n2 * v.elem));
-  s.P = f2[0]; s.L = f2[1]; s.Q = f2[2]; s.DL = f2[3]; s.DQ = f2[4];
+  T** f2s = f2 + 5 * (set & 1);
+  s.P = f2s[0]; s.L = f2s[1]; s.Q = f2s[2]; s.DL = f2s[3]; s.DQ = f2s[4];
   double* d2[kN2D];
   for (int q = 0; q < kN2D; ++q) d2[q] = reinterpret_cast<double*>(base + L.f2d_off + q * a256(L.n2 * 8));
   s.AP2 = d2[0]; s.APU2 = d2[1]; s.APV2 = d2[2]; s.AL2 = d2[3]; s.AQ2 = d2[4]; s.ADL2 = d2[5]; s.ADQ2 = d2[6];
@@ -2311,9 +2332,14 @@ St4<T> state_at(const HandleView& v, void* base) {
 
 // pin: pole values of y, formed here from y's pole rows unless pin_ready (the recorded forward's)
 template <typename T>
+// set: the set of 2D recompute fields the stage uses (f2d_ready: they hold its input's already);
+// next_ps, next_pin: the next stage's input p_s and pole values, whose 2D recompute goes into the
+// other set at the end of the pole-row chain when the stage forks one (*prefetched tells)
 hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<const T> y, St4<const T> ao,
                               St4<T> ab, St4<T> ai, double* pin, hipStream_t s, bool ai_zero = false,
-                              bool pin_ready = false) {
+                              bool pin_ready = false, int set = 0, bool f2d_ready = false,
+                              const T* next_ps = nullptr, const double* next_pin = nullptr,
+                              bool* prefetched = nullptr) {
   Ctx<T> c;
   c.g = v.g;
   c.U = y.U; c.V = y.V; c.F = y.F; c.P = y.P;
@@ -2322,7 +2348,7 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.aiU = ai.U; c.aiV = ai.V; c.aiF = ai.F; c.aiP = ai.P;
   c.pin = pin;
   c.ch = ch;
-  c.s = scratch_of<T>(v);
+  c.s = scratch_of<T>(v, set);
   c.f = v.fac;
   c.blk = v.block;
   c.timer = v.timer;
@@ -2338,6 +2364,15 @@ hipError_t stage_adjoint_impl(const HandleView& v, int process, double ch, St4<c
   c.pp_s = v.adt_pp_s;
   c.ai_zero = ai_zero && ab.U != ai.U;
   c.base_in_tail = process == 1 && ab.U && ab.U == ai.U && ab.V == ai.V && ab.F == ai.F && ab.P == ai.P;
+  c.f2d_ready = f2d_ready;
+  const bool forks = process == 0 ? aar_split(c) && c.side != nullptr : adt_fork(c);
+  if (forks && next_ps) {
+    const Scr<T> o = scratch_of<T>(v, set + 1);
+    c.next_ps = next_ps;
+    c.next_pin = next_pin;
+    c.next2d[0] = o.P; c.next2d[1] = o.L; c.next2d[2] = o.Q; c.next2d[3] = o.DL; c.next2d[4] = o.DQ;
+  }
+  if (prefetched) *prefetched = c.next_ps != nullptr;
   hipError_t e = pin_ready ? hipSuccess : launch_pole_prep<T>(v.g, y.F, y.P, pin, s);
   if (e != hipSuccess) return e;
   e = run_stage_adjoint<T>(c, s, process == 0);
@@ -2494,6 +2529,10 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
   // transpose of its output adjoint to it; the last stage's share is lam itself with the base
   // transpose applied in place once that stage has read it.
   const St4<T> none{nullptr, nullptr, nullptr, nullptr};
+  // the 2D recompute of each stage's input alternates between two sets; a stage that forks a pole-row
+  // chain computes the next stage's at its end, and the next stage then skips it
+  int set = 0;
+  bool ready = false;
   for (int rk = nrk - 1; rk >= 0; --rk) {
     const int proc = rk < v.msub ? 0 : 1;
     const double h = proc == 0 ? v.dt / v.msub : v.dt;
@@ -2505,14 +2544,29 @@ int reverse_impl(const HandleView& v, St4<T> lam, hipStream_t s) {
     e = fused ? zero_outside_rows<T>(v, l1, s, pn, psn) : zero_state<T>(v, l1, s);
     if (e == hipSuccess) e = fused ? zero_outside_rows<T>(v, l2, s, pn, psn) : zero_state<T>(v, l2, s);
     const int q = 3 * rk;
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, tpole(q + 2), s, true, true);
+    // the input that the stage after the third one reads: the next RK step's third stage input
+    const T* nps = rk > 0 ? traj(3 * (rk - 1) + 2).P : nullptr;
+    const double* npin = rk > 0 ? tpole(3 * (rk - 1) + 2) : nullptr;
+    bool pre = false;
+    if (e == hipSuccess)
+      e = stage_adjoint_impl<T>(v, proc, h, cst(y2), cst(lam), none, l2, tpole(q + 2), s, true, true, set, ready,
+                                y1.P, tpole(q + 1), &pre);
+    set ^= 1;
+    ready = pre;
     if (e == hipSuccess) {
       hipLaunchKernelGGL((k_base_inplace<T>), dim3(v.g.nz + 1, 2), dim3(256), 0, s, v.g, lam.U, lam.F, lam.P);
       e = hipGetLastError();
     }
     if (e == hipSuccess)
-      e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lam, l1, tpole(q + 1), s, true, true);
-    if (e == hipSuccess) e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lam, lam, tpole(q), s, false, true);
+      e = stage_adjoint_impl<T>(v, proc, h / 2.0, cst(y1), cst(l2), lam, l1, tpole(q + 1), s, true, true, set, ready,
+                                y.P, tpole(q), &pre);
+    set ^= 1;
+    ready = pre;
+    if (e == hipSuccess)
+      e = stage_adjoint_impl<T>(v, proc, h / 3.0, cst(y), cst(l1), lam, lam, tpole(q), s, false, true, set, ready,
+                                nps, npin, &pre);
+    set ^= 1;
+    ready = pre;
     if (e != hipSuccess) return DYCORE_EHIP;
   }
   return DYCORE_OK;
