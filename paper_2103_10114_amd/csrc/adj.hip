@@ -1584,11 +1584,13 @@ __global__ void __launch_bounds__(256) k_adt(Ctx<T> c) {
 // the first transposes of every output that reads row j's inputs (U row j, V rows j-1/2 and j+1/2,
 // scalar rows j-1..j+1) are formed per level for every slot of the tile and staged in LDS, so that
 // the owned columns' gathers at the leap offsets (+-n_j) and at +-1 are LDS reads of slots that the
-// halo covers: no modular index in LDS, and the tile's LDS and registers leave room for two
-// workgroups per CU.  The level rows are double-buffered (one barrier per level).  Suffix sums (the
-// adjoint of S, the hydrostatic totals) run top-down from column totals taken in a first pass.  The
-// pole rows' share goes through the per-point kernels (restricted to the pole rows); this kernel
-// writes the few row-1 and row-(ny-1) intermediates those read.
+// halo covers: no modular index in LDS, and the tile's LDS and registers (161 VGPRs in FP32) leave
+// room for three 256-thread workgroups per CU.  The level rows are double-buffered (one barrier per
+// level).  Suffix sums (the adjoint of S, the hydrostatic totals) run top-down from column totals
+// taken in a first pass.  The pole rows' share goes through the per-point kernels (restricted to the
+// pole rows); this kernel writes the few row-1 and row-(ny-1) intermediates those read.  On large
+// grids rows 1 and ny-1, which read the pole rows' sums, run as a launch of their own (k_aat_edge)
+// after them, so that the pole rows' chain can run beside the launch of the other rows.
 // ------------------------------------------------------------------------------------------------
 constexpr int kAatLev = 13;   // per-level LDS rows (odd: consecutive slots stride an odd word count)
 __host__ __device__ constexpr size_t aat_lds(int block, int elem) { return (size_t)2 * kAatLev * block * elem; }
