@@ -1595,9 +1595,17 @@ __global__ void __launch_bounds__(256) k_adt(Ctx<T> c) {
 constexpr int kAatLev = 13;   // per-level LDS rows (odd: consecutive slots stride an odd word count)
 __host__ __device__ constexpr size_t aat_lds(int block, int elem) { return (size_t)2 * kAatLev * block * elem; }
 
-template <typename T>
+// STAGE (FP32, workgroups of at most kAatStageMax threads): a level's global inputs of phase 1 are
+// copied straight into LDS (global_load_lds, no registers) while the previous level's phase 2 runs,
+// one field-major row per input; each thread reads back only its own column's values, so the copies
+// need no barrier, and they go out after a level's barrier and are read before the next one.
+constexpr int kAatStg = 23;          // staged inputs per column
+constexpr int kAatStageMax = 256;    // widest staged workgroup
+
+template <typename T, bool STAGE>
 __device__ __forceinline__ void aat_tile(const Ctx<T>& c) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float gin[STAGE ? kAatStg : 1][STAGE ? kAatStageMax : 1];   // staged inputs
   const AatItem it = c.aat[blockIdx.x];
   if (it.j < 0) return;
   const GeoDev& g = c.g;
@@ -1707,6 +1715,52 @@ __device__ __forceinline__ void aat_tile(const Ctx<T>& c) {
   // aLQ: column sum of the l and q adjoints (they enter p_s only as a sum); aDLQ: of the leaped
   // d+l and d+q adjoints (the same leap transposes both)
   C Sj = 0, pre = 0, aP = 0, aPU = 0, aPV = 0, aLQ = 0, aDLQ = 0;
+  enum { GaiU, GaiV, GaiF, GFm, GFj, GF1, GUj, GUjm, GUm, GUmm, GU1, GU1m, GVj, GVjp, GVm, GVmp,
+         GoF, GoU, GoV, GqVm, GqFm, GqF1, GqU1 };
+  // the copies of level k's inputs into the staging rows (lane l of a wavefront lands at slot w + l)
+  auto issue = [&](int k) {
+    if constexpr (STAGE) {
+      if (!act) return;
+      const unsigned lv = (unsigned)(k * nx);
+      const int wb = sl & ~63;
+      auto cp = [&](int f, const T* g, unsigned o) {
+        __builtin_amdgcn_global_load_lds(g + o, &gin[f][wb], 4, 0, 0);
+      };
+      if (!c.ai_zero && own) {
+        cp(GaiU, c.aiU, oJ + lv + ui);
+        cp(GaiV, c.aiV, oJ + lv + ui);
+        cp(GaiF, c.aiF, oJ + lv + ui);
+      }
+      if (!nPole) cp(GFm, c.F, oJm + lv + ui);
+      cp(GFj, c.F, oJ + lv + ui);
+      if (!sPole) cp(GF1, c.F, oJ1 + lv + ui);
+      cp(GUj, c.U, oJ + lv + ui);
+      cp(GUjm, c.U, oJ + lv + uim);
+      if (!nPole) {
+        cp(GUm, c.U, oJm + lv + ui);
+        cp(GUmm, c.U, oJm + lv + uim);
+      }
+      if (!sPole) {
+        cp(GU1, c.U, oJ1 + lv + ui);
+        cp(GU1m, c.U, oJ1 + lv + uim);
+      }
+      cp(GVj, c.V, oJ + lv + ui);
+      cp(GVjp, c.V, oJ + lv + uip);
+      cp(GVm, c.V, oJm + lv + ui);
+      cp(GVmp, c.V, oJm + lv + uip);
+      cp(GoF, c.aoF, oJ + lv + ui);
+      cp(GoU, c.aoU, oJ + lv + ui);
+      cp(GoV, c.aoV, oJ + lv + ui);
+      cp(GqVm, c.aoV, oJm + lv + ui);
+      if (!nPole) cp(GqFm, c.aoF, oJm + lv + ui);
+      if (!sPole) {
+        cp(GqF1, c.aoF, oJ1 + lv + ui);
+        cp(GqU1, c.aoU, oJ1 + lv + ui);
+      }
+    }
+  };
+  auto S = [&](int f) -> T { return (T)gin[f][sl]; };
+  issue(0);
 #pragma unroll 1
   for (int k = 0; k < nz; ++k) {
     T* L = (k & 1) ? lb1 : lb0;
@@ -1721,26 +1775,31 @@ __device__ __forceinline__ void aat_tile(const Ctx<T>& c) {
     T aiU0 = 0, aiV0 = 0, aiF0 = 0;
     // ---- phase 1: per-point quantities of every slot
     if (act) {
+      // the level's inputs (staged: copied into LDS during the previous level's phase 2)
+      auto G = [&](int f, const T* g, unsigned o) -> T {
+        if constexpr (STAGE) return S(f);
+        else return ldg(g, o);
+      };
       if (!c.ai_zero && own) {
-        aiU0 = ldg(c.aiU, oJ + lv + ui);
-        aiV0 = ldg(c.aiV, oJ + lv + ui);
-        aiF0 = ldg(c.aiF, oJ + lv + ui);
+        aiU0 = G(GaiU, c.aiU, oJ + lv + ui);
+        aiV0 = G(GaiV, c.aiV, oJ + lv + ui);
+        aiF0 = G(GaiF, c.aiF, oJ + lv + ui);
       }
-      const T Fm = nPole ? (T)c.pin[k] : ldg(c.F, oJm + lv + ui);
-      const T Fj = ldg(c.F, oJ + lv + ui);
-      const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : ldg(c.F, oJ1 + lv + ui);
-      const T Uj = ldg(c.U, oJ + lv + ui), Ujm = ldg(c.U, oJ + lv + uim);
-      const T Um = nPole ? T(0) : ldg(c.U, oJm + lv + ui), Umm = nPole ? T(0) : ldg(c.U, oJm + lv + uim);
-      const T U1 = sPole ? T(0) : ldg(c.U, oJ1 + lv + ui), U1m = sPole ? T(0) : ldg(c.U, oJ1 + lv + uim);
-      const T Vj = ldg(c.V, oJ + lv + ui), Vjp = ldg(c.V, oJ + lv + uip);     // V row j+1/2
-      const T Vm = ldg(c.V, oJm + lv + ui), Vmp = ldg(c.V, oJm + lv + uip);   // V row j-1/2
-      voF = ldg(c.aoF, oJ + lv + ui);
-      voU = ldg(c.aoU, oJ + lv + ui);
-      voV = ldg(c.aoV, oJ + lv + ui);
-      const T qVm = ldg(c.aoV, oJm + lv + ui);
-      const T qFm = nPole ? T(0) : ldg(c.aoF, oJm + lv + ui);
-      const T qF1 = sPole ? T(0) : ldg(c.aoF, oJ1 + lv + ui);
-      const T qU1 = sPole ? T(0) : ldg(c.aoU, oJ1 + lv + ui);
+      const T Fm = nPole ? (T)c.pin[k] : G(GFm, c.F, oJm + lv + ui);
+      const T Fj = G(GFj, c.F, oJ + lv + ui);
+      const T F1 = sPole ? (T)c.pin[(nz + 1) + k] : G(GF1, c.F, oJ1 + lv + ui);
+      const T Uj = G(GUj, c.U, oJ + lv + ui), Ujm = G(GUjm, c.U, oJ + lv + uim);
+      const T Um = nPole ? T(0) : G(GUm, c.U, oJm + lv + ui), Umm = nPole ? T(0) : G(GUmm, c.U, oJm + lv + uim);
+      const T U1 = sPole ? T(0) : G(GU1, c.U, oJ1 + lv + ui), U1m = sPole ? T(0) : G(GU1m, c.U, oJ1 + lv + uim);
+      const T Vj = G(GVj, c.V, oJ + lv + ui), Vjp = G(GVjp, c.V, oJ + lv + uip);     // V row j+1/2
+      const T Vm = G(GVm, c.V, oJm + lv + ui), Vmp = G(GVmp, c.V, oJm + lv + uip);   // V row j-1/2
+      voF = G(GoF, c.aoF, oJ + lv + ui);
+      voU = G(GoU, c.aoU, oJ + lv + ui);
+      voV = G(GoV, c.aoV, oJ + lv + ui);
+      const T qVm = G(GqVm, c.aoV, oJm + lv + ui);
+      const T qFm = nPole ? T(0) : G(GqFm, c.aoF, oJm + lv + ui);
+      const T qF1 = sPole ? T(0) : G(GqF1, c.aoF, oJ1 + lv + ui);
+      const T qU1 = sPole ? T(0) : G(GqU1, c.aoU, oJ1 + lv + ui);
       // forward: R T', phi'
       const T RTm = b * Fm * rPm, RTj = b * Fj * rP0, RT1 = b * F1 * rP1;
       HRj -= clk * (C)RTj;
@@ -1842,6 +1901,7 @@ __device__ __forceinline__ void aat_tile(const Ctx<T>& c) {
       }
     }
     __syncthreads();
+    if (k + 1 < nz) issue(k + 1);
 
     // ---- phase 2: forward D, S, omega/p; gathers; transposes into the owned columns
     if (own) {
@@ -1942,13 +2002,19 @@ __device__ __forceinline__ void aat_tile(const Ctx<T>& c) {
 // The tiles of the interior rows (all of them, or rows 2..ny-2 when rows 1 and ny-1 run apart).
 template <typename T>
 __global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat(Ctx<T> c) {
-  aat_tile<T>(c);
+  aat_tile<T, sizeof(T) == 4>(c);
 }
 
 // The tiles of rows 1 and ny-1, launched after the pole rows' sums that they read.
 template <typename T>
 __global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat_edge(Ctx<T> c) {
-  aat_tile<T>(c);
+  aat_tile<T, sizeof(T) == 4>(c);
+}
+
+// Workgroups wider than the staging rows: the inputs are loaded at their level.
+template <typename T>
+__global__ void __launch_bounds__(kAatMaxBlock, sizeof(T) == 4 ? 3 : 2) k_aat_wide(Ctx<T> c) {
+  aat_tile<T, false>(c);
 }
 
 // The base transpose of a stage applied in place: pole rows of Phi and p_s become the spread of
@@ -1998,27 +2064,37 @@ bool aar_split(const Ctx<T>& c) {
   return aar_used(c) && c.aat_edge_n > 0;
 }
 
+// the staged form serves FP32 workgroups up to the staging rows' width
+template <typename T>
+bool aat_staged(const Ctx<T>& c) {
+  return sizeof(T) == 4 && c.aat_blk <= kAatStageMax;
+}
+
 template <typename T>
 hipError_t launch_aar_edge(const Ctx<T>& c, hipStream_t s) {
   const size_t lds = aat_lds(c.aat_blk, (int)sizeof(T));
-  hipError_t e = allow_lds_adj<k_aat_edge<T>>(lds);
+  const bool st = aat_staged(c);
+  hipError_t e = st ? allow_lds_adj<k_aat_edge<T>>(lds) : allow_lds_adj<k_aat_wide<T>>(lds);
   if (e != hipSuccess) return e;
   Ctx<T> ce = c;
   ce.aat = c.aat + c.aat_n;
   ce.aat_n = c.aat_edge_n;
-  hipLaunchKernelGGL((k_aat_edge<T>), dim3(ce.aat_n), dim3(ce.aat_blk), lds, s, ce);
+  if (st) hipLaunchKernelGGL((k_aat_edge<T>), dim3(ce.aat_n), dim3(ce.aat_blk), lds, s, ce);
+  else hipLaunchKernelGGL((k_aat_wide<T>), dim3(ce.aat_n), dim3(ce.aat_blk), lds, s, ce);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_aar(const Ctx<T>& c, hipStream_t s) {
   const size_t lds = aat_lds(c.aat_blk, (int)sizeof(T));
-  hipError_t e = allow_lds_adj<k_aat<T>>(lds);
+  const bool st = aat_staged(c);
+  hipError_t e = st ? allow_lds_adj<k_aat<T>>(lds) : allow_lds_adj<k_aat_wide<T>>(lds);
   if (e != hipSuccess) return e;
   KTimer* t = c.timer;
   const bool timed = t && t->armed && t->n < t->cap;
   if (timed && (e = hipEventRecord(t->ev[2 * t->n], s)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_aat<T>), dim3(c.aat_n), dim3(c.aat_blk), lds, s, c);
+  if (st) hipLaunchKernelGGL((k_aat<T>), dim3(c.aat_n), dim3(c.aat_blk), lds, s, c);
+  else hipLaunchKernelGGL((k_aat_wide<T>), dim3(c.aat_n), dim3(c.aat_blk), lds, s, c);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (timed) {
