@@ -1724,7 +1724,9 @@ __device__ __forceinline__ void aat_tile(const Ctx<T>& c) {
       const unsigned lv = (unsigned)(k * nx);
       const int wb = sl & ~63;
       auto cp = [&](int f, const T* g, unsigned o) {
-        __builtin_amdgcn_global_load_lds(g + o, &gin[f][wb], 4, 0, 0);
+        // a global-space base and a 32-bit byte offset, as ldg forms its addresses
+        using GP = const __attribute__((address_space(1))) char*;
+        __builtin_amdgcn_global_load_lds((GP)g + o * (unsigned)sizeof(T), &gin[f][wb], 4, 0, 0);
       };
       if (!c.ai_zero && own) {
         cp(GaiU, c.aiU, oJ + lv + ui);
